@@ -1,0 +1,199 @@
+/*
+ * hdm.h -- C ABI of the MI355X hierarchical diffusion-maps library (libhdm.so).
+ *
+ * The library computes the leading eigenpairs of the diffusion-maps operator of
+ * a point cloud (Sec. 2.1, Alg. 1 with alpha = 1) by Lanczos iteration (Sec. 2.2)
+ * over a hierarchical approximation K~ = D + S + UV of the Gaussian kernel matrix
+ * (Eq. (2), Eq. (3)), compressed once and applied once per iteration (Sec. 1.2).
+ *
+ * Conventions for every entry point:
+ *  - The return value is an hdm_status; HDM_OK is 0.  On any other value the
+ *    outputs are left untouched and hdm_last_error() describes the failure.
+ *  - No C++ exception crosses this boundary.
+ *  - Vectors at the boundary are float64, in the caller's original point order,
+ *    column-major with leading dimension n when several right-hand sides are
+ *    passed.  The tree permutation is internal.
+ *  - "device" pointers are HIP device memory of the context's GPU; "host"
+ *    pointers are ordinary host memory.  The caller owns every buffer it passes.
+ *  - stream: a hipStream_t (NULL = the default stream).  Calls that return
+ *    results in host memory synchronise that stream before returning.
+ *  - One hdm_ctx and the operators made from it are used by one thread at a
+ *    time.  The server calls are thread-safe.
+ */
+#ifndef HDM_H
+#define HDM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HDM_OK = 0,
+    HDM_EINVAL = 1,      /* bad argument, size or parameter; NaN/Inf in the points */
+    HDM_ENOMEM = 2,      /* device or host allocation failed, or over the context budget */
+    HDM_EDEVICE = 3,     /* a HIP call failed */
+    HDM_ENOCONV = 4,     /* Lanczos stopped at max_basis before the tolerance was met */
+    HDM_EBUSY = 5,       /* request still pending (hdm_poll) */
+    HDM_ECANCELLED = 6,  /* request cancelled */
+    HDM_EINTERNAL = 7,   /* internal invariant violated */
+    HDM_ENUMERIC = 8     /* non-positive degree in the normalisation */
+} hdm_status;
+
+typedef enum { HDM_F64 = 0, HDM_F32 = 1, HDM_BF16 = 2, HDM_F16 = 3, HDM_U8 = 4 } hdm_dtype;
+
+typedef struct hdm_ctx_s *hdm_ctx;
+typedef struct hdm_op_s *hdm_op;
+typedef struct hdm_server_s *hdm_server;
+
+/* Problem statement: points X and bandwidth eps (Eq. (2), eps = sigma^2), the
+ * density parameter alpha (Alg. 1; only 1 is supported), and the compression
+ * parameters of Sec. 4.2.3: leaf size m, maximal off-diagonal rank s,
+ * tolerance tau, neighbour count k. */
+typedef struct {
+    int64_t n;          /* number of points, >= 2 */
+    int32_t dim;        /* coordinates per point, >= 1 */
+    int32_t x_dtype;    /* HDM_F64 (n x dim row-major doubles) or HDM_U8 (codes k meaning k/255) */
+    double eps;         /* > 0 */
+    double alpha;       /* must be 1 */
+    int32_t leaf_m;     /* leaf size bound: depth = min d with ceil(n / 2^d) <= m; every leaf must hold > knn_k points */
+    int32_t max_rank_s; /* >= 1 */
+    double tau;         /* >= 0, relative pivot threshold of the interpolative decomposition */
+    int32_t knn_k;      /* neighbours per point, 1..64 */
+    int32_t knn_iters;  /* random trees for the neighbour search, >= 1 (10) */
+    double budget;      /* fraction of leaves added to each near list, in [0, 1] (0.05) */
+    int32_t near_prec;  /* HDM_F64, HDM_F32, HDM_BF16 or HDM_F16: near-field tiles */
+    int32_t far_prec;   /* HDM_F64, HDM_F32, HDM_BF16 or HDM_F16: skeleton tiles */
+    uint64_t seed;      /* all random choices are Philox4x32-10 draws keyed by this seed */
+} hdm_params;
+
+/* Fills p with the defaults (alpha 1, knn_iters 10, budget 0.05, f32 tiles). */
+void hdm_params_default(hdm_params *p);
+
+typedef struct {
+    int64_t n;
+    int32_t dim, depth, leaves, knn_k;
+    int32_t max_rank, min_leaf_rank;
+    double mean_leaf_rank;
+    int64_t near_pairs, far_pairs;
+    int64_t bytes_near, bytes_far, bytes_p, bytes_total;  /* resident operator bytes in HBM */
+    int64_t algo_bytes_matvec;   /* bytes one single-vector product must move (tiles once + vectors) */
+    int64_t flops_matvec;        /* 2 x multiply-adds of one single-vector product */
+    double seconds_compress;     /* wall time of hdm_compress */
+} hdm_op_stats_t;
+
+typedef struct {
+    int32_t iters;        /* Lanczos steps (block steps when block > 1) */
+    int32_t matvecs;      /* operator applications (vectors) */
+    int32_t converged;    /* 1 when every requested pair met the tolerance */
+    double max_rel_resid; /* max_i |beta_j y_{j,i}| / |theta_i| at exit */
+    double seconds;
+} hdm_eig_info_t;
+
+/* ---- context -------------------------------------------------------------- */
+/* device: HIP ordinal.  hbm_budget_bytes: cap on operator memory (0 = no cap). */
+hdm_status hdm_ctx_create(int device, size_t hbm_budget_bytes, hdm_ctx *out);
+hdm_status hdm_ctx_destroy(hdm_ctx ctx);
+/* Message of the last failure on the calling thread (valid until its next call). */
+const char *hdm_last_error(void);
+/* Version string of the library. */
+const char *hdm_version(void);
+
+/* ---- compression (Sec. 1.2 "compressed once"; Eq. (3)) ---------------------
+ * Builds the kernel-space ball tree, the randomized-tree neighbour lists, the
+ * near and far interaction lists, the nested skeletons with their interpolation
+ * matrices, the near and skeleton kernel tiles, and the alpha = 1 degrees of K~
+ * (two float64 products), all on the GPU.  X: n x dim, row-major, host or device
+ * memory (x_on_device).  X is copied; the caller may free it on return. */
+hdm_status hdm_compress(hdm_ctx ctx, const void *X, int x_on_device, const hdm_params *params, void *stream,
+                        hdm_op *out);
+hdm_status hdm_op_destroy(hdm_op op);
+hdm_status hdm_op_stats(hdm_op op, hdm_op_stats_t *out);
+
+/* ---- inspection (host outputs) -------------------------------------------- */
+/* perm[t] = original index of the point at tree position t (n entries). */
+hdm_status hdm_op_perm(hdm_op op, int32_t *perm);
+/* Neighbour lists in original order: idx n x k, d2 n x k (squared distances),
+ * each row ascending by (d2, index).  Either pointer may be NULL. */
+hdm_status hdm_op_knn(hdm_op op, int32_t *idx, double *d2);
+/* Interaction lists.  Near: CSR over leaves 0..L-1 (near_off L+1 entries).
+ * Far: CSR over heap ids 0..2L-1 (far_off 2L+1 entries; root 1, children 2h, 2h+1).
+ * Call with NULL arrays to get the sizes in *near_nnz / *far_nnz. */
+hdm_status hdm_op_lists(hdm_op op, int32_t *near_off, int32_t *near_idx, int64_t *near_nnz, int32_t *far_off,
+                        int32_t *far_idx, int64_t *far_nnz);
+/* Per heap id (2L entries): rank, candidate count and sampled-row count. */
+hdm_status hdm_op_ranks(hdm_op op, int32_t *rank, int32_t *ncand, int32_t *nrows);
+/* Skeleton of heap node h (rank original indices), its sampled rows (nrows
+ * original indices) and its interpolation matrix P (rank x ncand row-major,
+ * float64).  Any pointer may be NULL. */
+hdm_status hdm_op_node(hdm_op op, int64_t h, int32_t *skel, int32_t *rows, double *P);
+/* Degrees of the alpha = 1 normalisation in original order (host, n each):
+ * q = K~ 1, d = Q^-1 K~ Q^-1 1, c = 1 / (q sqrt(d)).  Any pointer may be NULL. */
+hdm_status hdm_op_degrees(hdm_op op, double *q, double *d, double *c);
+
+/* ---- evaluation (Eq. (3); called once per Lanczos step) --------------------
+ * y = K~ x (normalised = 0) or y = S~ x = c * K~ (c * x) (normalised = 1), the
+ * symmetric conjugate of the Markov matrix of Alg. 1.  x, y: device float64,
+ * n x nrhs column-major (ld = n), 1 <= nrhs <= 64, x and y must not overlap.
+ * Tiles are applied in the operator's near/far precision with float32
+ * accumulation (float64 when the tiles are float64). */
+hdm_status hdm_matvec(hdm_op op, int normalised, const double *x, double *y, int32_t nrhs, void *stream);
+
+/* ---- eigensolver (Alg. 1 eigendecomposition; Sec. 2.2 Lanczos) --------------
+ * Leading r eigenpairs (largest algebraic) of S~ by Lanczos with full float64
+ * reorthogonalisation.  block = 1: single-vector Lanczos; block > 1: block
+ * Lanczos with that many start vectors.  Stops when every pair i < r has
+ * |beta_j y_{j,i}| <= rel_resid_tol |theta_i| or when the basis reaches
+ * max_basis vectors (then HDM_ENOCONV with evals/info filled).
+ * evals: host, r entries, descending.  evecs: device float64 n x r (column-major,
+ * phi: unit 2-norm, largest-magnitude entry positive) or NULL. */
+hdm_status hdm_eigs(hdm_op op, int32_t r, double rel_resid_tol, int32_t block, int32_t max_basis, uint64_t seed,
+                    double *evals, double *evecs, hdm_eig_info_t *info, void *stream);
+
+/* ---- serving --------------------------------------------------------------- */
+typedef struct {
+    int32_t max_slots;          /* requests on the GPU at once */
+    size_t mem_budget_bytes;    /* admission limit on the sum of resident footprints */
+} hdm_server_cfg_t;
+
+typedef struct {
+    const void *X;          /* host points; borrowed until the request is admitted */
+    hdm_params params;
+    int32_t r;              /* eigenpairs */
+    double rel_resid_tol;
+    int32_t max_basis;
+    double arrival_s;       /* caller's arrival timestamp (seconds, any epoch; latency = done - arrival) */
+} hdm_request_t;
+
+typedef struct {
+    int32_t status;         /* hdm_status of the solve */
+    int32_t r;
+    double evals[64];       /* leading eigenvalues, descending (first r valid) */
+    double latency_s;       /* completion - arrival on the caller's clock */
+    double service_s;       /* admission -> completion */
+    int32_t iters;
+    int32_t x_released;     /* 1 once the library no longer reads X */
+} hdm_result_t;
+
+typedef struct {
+    int64_t submitted, admitted, completed, rejected, cancelled;
+    double solves_per_s, p50_latency_s, p99_latency_s;
+    int64_t peak_resident_bytes;
+    int64_t shared_launches;  /* launches that served more than one request */
+} hdm_server_stats_t;
+
+hdm_status hdm_server_create(hdm_ctx ctx, const hdm_server_cfg_t *cfg, hdm_server *out);
+hdm_status hdm_submit(hdm_server srv, const hdm_request_t *req, uint64_t *ticket);
+/* HDM_EBUSY while the request is queued or running; its result otherwise. */
+hdm_status hdm_poll(hdm_server srv, uint64_t ticket, hdm_result_t *out);
+hdm_status hdm_cancel(hdm_server srv, uint64_t ticket);
+hdm_status hdm_server_stats(hdm_server srv, hdm_server_stats_t *out);
+/* Waits for running requests, cancels queued ones, frees everything. */
+hdm_status hdm_server_destroy(hdm_server srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HDM_H */

@@ -1,0 +1,1039 @@
+// Geometry-oblivious compression on the GPU: kernel-space ball tree,
+// randomized-tree neighbours, near/far interaction lists, nested skeletons by a
+// sampled-row interpolative decomposition, and the kernel tiles of Eq. (3).
+//
+// Every decision (argmin, median cut, neighbour order, pivot) is taken in
+// float64 with a total order (value, index); this file is compiled with
+// -ffp-contract=off so each product and sum is one IEEE operation in the order
+// written, which keeps the tree and the neighbour lists reproducible.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "op.hpp"
+
+namespace hdm {
+
+namespace {
+
+constexpr int kSample = 64;     // points sampled per node for the centroid
+constexpr int kBlock = 256;
+
+struct Pts {
+    const double* xf;
+    const uint8_t* xu;
+    int dim;
+    int is_u8;
+    double eps;
+};
+
+// ||x_i - x_j||^2 summed over coordinates in increasing order
+__device__ inline double sqd(const Pts& P, int64_t i, int64_t j) {
+    if (P.is_u8) {
+        const uint8_t* a = P.xu + i * P.dim;
+        const uint8_t* b = P.xu + j * P.dim;
+        int acc = 0;
+        for (int d = 0; d < P.dim; ++d) {
+            const int t = static_cast<int>(a[d]) - static_cast<int>(b[d]);
+            acc += t * t;
+        }
+        return static_cast<double>(acc) / 65025.0;
+    }
+    const double* a = P.xf + i * P.dim;
+    const double* b = P.xf + j * P.dim;
+    double acc = 0.0;
+    for (int d = 0; d < P.dim; ++d) {
+        const double t = a[d] - b[d];
+        acc = acc + t * t;
+    }
+    return acc;
+}
+
+// Eq. (2): exp(-||x_i - x_j||^2 / eps)
+__device__ inline double kval(const Pts& P, int64_t i, int64_t j) { return exp(-(sqd(P, i, j) / P.eps)); }
+
+// heap id of the level-lvl node holding tree position pos
+__device__ inline int64_t node_of(int64_t pos, int lvl, const int64_t* start) {
+    int64_t h = 1;
+    for (int l = 0; l < lvl; ++l) h = (pos < start[2 * h + 1]) ? 2 * h : 2 * h + 1;
+    return h;
+}
+
+// ---------------------------------------------------------------------------
+// tree construction
+// ---------------------------------------------------------------------------
+__global__ void k_iota(int32_t* p, int64_t n) {
+    const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    if (i < n) p[i] = static_cast<int32_t>(i);
+}
+
+// Floyd's sampling of min(n, 64) distinct positions of each node, ascending.
+__global__ void k_tree_sample(int lvl, const int64_t* start, const int64_t* size, uint64_t seed, int32_t* samp,
+                              int32_t* nsamp) {
+    const int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    const int64_t nodes = int64_t(1) << lvl;
+    if (t >= nodes) return;
+    const int64_t h = nodes + t;
+    const int64_t n = size[h];
+    int32_t* out = samp + t * kSample;
+    if (n <= kSample) {
+        for (int q = 0; q < n; ++q) out[q] = static_cast<int32_t>(start[h] + q);
+        nsamp[t] = static_cast<int32_t>(n);
+        return;
+    }
+    int cnt = 0;
+    for (int64_t j = n - kSample; j < n; ++j) {
+        const int64_t r = below(philox_draw(seed, kTreeSample, static_cast<uint32_t>(h), 0, static_cast<uint32_t>(j)),
+                                static_cast<uint32_t>(j + 1));
+        bool present = false;
+        for (int q = 0; q < cnt; ++q) present = present || (out[q] == r);
+        out[cnt++] = static_cast<int32_t>(present ? j : r);
+    }
+    for (int a = 1; a < cnt; ++a) {
+        const int32_t v = out[a];
+        int b = a - 1;
+        while (b >= 0 && out[b] > v) { out[b + 1] = out[b]; --b; }
+        out[b + 1] = v;
+    }
+    for (int q = 0; q < cnt; ++q) out[q] = static_cast<int32_t>(start[h] + out[q]);
+    nsamp[t] = cnt;
+}
+
+// sum over the node's sample of K(x_i, x_j), in ascending sample position
+__global__ void k_tree_sumk(int lvl, int64_t n, const int64_t* start, const int32_t* perm, const int32_t* samp,
+                            const int32_t* nsamp, Pts P, double* sumk) {
+    const int64_t pos = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    if (pos >= n) return;
+    const int64_t t = node_of(pos, lvl, start) - (int64_t(1) << lvl);
+    const int32_t i = perm[pos];
+    double acc = 0.0;
+    const int ns = nsamp[t];
+    for (int q = 0; q < ns; ++q) acc = acc + kval(P, i, perm[samp[t * kSample + q]]);
+    sumk[pos] = acc;
+}
+
+// lexicographic block reduction helpers: (value, position), smaller wins / larger wins
+__device__ inline void block_argbest(double& v, int64_t& p, bool want_min, double* sv, int64_t* sp) {
+    const int tid = threadIdx.x;
+    sv[tid] = v;
+    sp[tid] = p;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if (tid < w) {
+            const double ov = sv[tid + w];
+            const int64_t op = sp[tid + w];
+            const bool better = want_min ? (ov < sv[tid] || (ov == sv[tid] && op < sp[tid]))
+                                         : (ov > sv[tid] || (ov == sv[tid] && op < sp[tid]));
+            if (better) { sv[tid] = ov; sp[tid] = op; }
+        }
+        __syncthreads();
+    }
+    v = sv[0];
+    p = sp[0];
+    __syncthreads();
+}
+
+// p = argmin sumk (the point farthest from the sample centroid in feature space),
+// q = argmax ||x - x_p||^2; ties go to the lower position
+__global__ void k_tree_pq(int lvl, const int64_t* start, const int64_t* size, const int32_t* perm,
+                          const double* sumk, Pts P, int32_t* pq) {
+    __shared__ double sv[kBlock];
+    __shared__ int64_t sp[kBlock];
+    const int64_t t = blockIdx.x;
+    const int64_t h = (int64_t(1) << lvl) + t;
+    const int64_t s0 = start[h], n = size[h];
+    double best = INFINITY;
+    int64_t bpos = INT64_MAX;
+    for (int64_t pos = s0 + threadIdx.x; pos < s0 + n; pos += blockDim.x) {
+        const double v = sumk[pos];
+        if (v < best || (v == best && pos < bpos)) { best = v; bpos = pos; }
+    }
+    block_argbest(best, bpos, true, sv, sp);
+    if (bpos < s0 || bpos >= s0 + n) bpos = s0;   // only reachable with non-finite sums
+    const int32_t ip = perm[bpos];
+    double far = -1.0;
+    int64_t fpos = INT64_MAX;
+    for (int64_t pos = s0 + threadIdx.x; pos < s0 + n; pos += blockDim.x) {
+        const double d = sqd(P, perm[pos], ip);
+        if (d > far || (d == far && pos < fpos)) { far = d; fpos = pos; }
+    }
+    block_argbest(far, fpos, false, sv, sp);
+    if (fpos < s0 || fpos >= s0 + n) fpos = s0;
+    if (threadIdx.x == 0) {
+        pq[2 * t] = ip;
+        pq[2 * t + 1] = perm[fpos];
+    }
+}
+
+// random pivots p != q of each node of a neighbour-search tree
+__global__ void k_knn_pq(int lvl, const int64_t* start, const int64_t* size, const int32_t* perm, uint64_t seed,
+                         int it, int32_t* pq) {
+    const int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    const int64_t nodes = int64_t(1) << lvl;
+    if (t >= nodes) return;
+    const int64_t h = nodes + t;
+    const uint32_t n = static_cast<uint32_t>(size[h]);
+    const uint32_t a = below(philox_draw(seed, kKnnPivot, static_cast<uint32_t>(h), static_cast<uint32_t>(it), 0), n);
+    uint32_t b = below(philox_draw(seed, kKnnPivot, static_cast<uint32_t>(h), static_cast<uint32_t>(it), 1), n - 1);
+    if (b >= a) ++b;
+    pq[2 * t] = perm[start[h] + a];
+    pq[2 * t + 1] = perm[start[h] + b];
+}
+
+// split key: mode 0 (ball tree) K(x,q) - K(x,p); mode 1 (neighbour trees) |x-p|^2 - |x-q|^2
+__global__ void k_tree_key(int lvl, int64_t n, const int64_t* start, const int32_t* perm, const int32_t* pq, Pts P,
+                           int mode, double* key) {
+    const int64_t pos = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    if (pos >= n) return;
+    const int64_t t = node_of(pos, lvl, start) - (int64_t(1) << lvl);
+    const int32_t i = perm[pos], p = pq[2 * t], q = pq[2 * t + 1];
+    key[pos] = mode == 0 ? kval(P, i, q) - kval(P, i, p) : sqd(P, i, p) - sqd(P, i, q);
+}
+
+// left[pos] = 1 when fewer than floor(n/2) members of the node precede it in (key, index) order
+__global__ void k_tree_rank(int lvl, int64_t n, const int64_t* start, const int64_t* size, const int32_t* perm,
+                            const double* key, uint8_t* left) {
+    __shared__ double sk[kBlock];
+    __shared__ int32_t si[kBlock];
+    const int64_t first = blockIdx.x * static_cast<int64_t>(kBlock);
+    const int64_t last = min(n, first + kBlock) - 1;
+    const int64_t hlo = node_of(first, lvl, start), hhi = node_of(last, lvl, start);
+    const int64_t blo = start[hlo], bhi = start[hhi] + size[hhi];
+    const int64_t pos = first + threadIdx.x;
+    const bool valid = pos <= last;
+    int64_t lo = 0, hi = 0, half = 0;
+    double ki = 0.0;
+    int32_t ii = 0;
+    if (valid) {
+        const int64_t h = node_of(pos, lvl, start);
+        lo = start[h];
+        hi = lo + size[h];
+        half = size[h] / 2;
+        ki = key[pos];
+        ii = perm[pos];
+    }
+    int64_t cnt = 0;
+    for (int64_t j0 = blo; j0 < bhi; j0 += kBlock) {
+        const int64_t jj = j0 + threadIdx.x;
+        if (jj < bhi) { sk[threadIdx.x] = key[jj]; si[threadIdx.x] = perm[jj]; }
+        __syncthreads();
+        const int64_t m = min<int64_t>(kBlock, bhi - j0);
+        if (valid) {
+            const int64_t u0 = max<int64_t>(0, lo - j0), u1 = min<int64_t>(m, hi - j0);
+            for (int64_t u = u0; u < u1; ++u) {
+                const double kj = sk[u];
+                cnt += (kj < ki) || (kj == ki && si[u] < ii);
+            }
+        }
+        __syncthreads();
+    }
+    if (valid) left[pos] = cnt < half ? 1 : 0;
+}
+
+// inclusive block scan of 0/1 flags (Hillis-Steele in shared memory)
+__device__ inline int block_scan(int v, int* buf) {
+    const int tid = threadIdx.x;
+    buf[tid] = v;
+    __syncthreads();
+    for (int off = 1; off < static_cast<int>(blockDim.x); off <<= 1) {
+        const int a = tid >= off ? buf[tid - off] : 0;
+        __syncthreads();
+        buf[tid] += a;
+        __syncthreads();
+    }
+    const int r = buf[tid];
+    __syncthreads();
+    return r;
+}
+
+// stable partition of every node: left members first, both halves keep their order
+__global__ void k_tree_partition(int lvl, const int64_t* start, const int64_t* size, const int32_t* perm,
+                                 const uint8_t* left, int32_t* out) {
+    __shared__ int buf[kBlock];
+    __shared__ int tot;
+    const int64_t h = (int64_t(1) << lvl) + blockIdx.x;
+    const int64_t s0 = start[h], n = size[h], nl = n / 2;
+    int64_t run_l = 0, run_r = 0;
+    for (int64_t base = 0; base < n; base += kBlock) {
+        const int64_t a = base + threadIdx.x;
+        const bool valid = a < n;
+        const int f = valid ? left[s0 + a] : 0;
+        const int incl = block_scan(f, buf);
+        if (threadIdx.x == blockDim.x - 1) tot = incl;
+        __syncthreads();
+        if (valid) {
+            const int lf = incl - f;
+            const int64_t np = f ? s0 + run_l + lf : s0 + nl + run_r + (threadIdx.x - lf);
+            out[np] = perm[s0 + a];
+        }
+        const int64_t cvalid = min<int64_t>(kBlock, n - base);
+        run_l += tot;
+        run_r += cvalid - tot;
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// neighbours
+// ---------------------------------------------------------------------------
+__global__ void k_knn_init(int32_t* idx, double* d2, int64_t cnt) {
+    const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    if (i < cnt) { idx[i] = -1; d2[i] = INFINITY; }
+}
+
+__device__ inline void knn_insert(double* ld, int32_t* li, int k, double d, int32_t j) {
+    const double dl = ld[k - 1];
+    const int32_t il = li[k - 1];
+    if (d > dl || (d == dl && il >= 0 && j >= il)) return;
+    for (int t = 0; t < k; ++t)
+        if (li[t] == j) return;
+    int pos = k - 1;
+    while (pos > 0) {
+        const double dp = ld[pos - 1];
+        const int32_t ip = li[pos - 1];
+        if (!(dp > d || (dp == d && (ip > j || ip < 0)))) break;
+        ld[pos] = dp;
+        li[pos] = ip;
+        --pos;
+    }
+    ld[pos] = d;
+    li[pos] = j;
+}
+
+// all pairs inside every leaf, merged into each point's running list
+__global__ void k_knn_leaf(int depth, const int64_t* start, const int64_t* size, const int32_t* perm, Pts P, int k,
+                           int32_t* kidx, double* kd2) {
+    extern __shared__ char smem[];
+    double* ld = reinterpret_cast<double*>(smem) + static_cast<int64_t>(threadIdx.x) * k;
+    int32_t* li = reinterpret_cast<int32_t*>(smem + sizeof(double) * blockDim.x * k) + static_cast<int64_t>(threadIdx.x) * k;
+    const int64_t h = (int64_t(1) << depth) + blockIdx.x;
+    const int64_t s0 = start[h], n = size[h];
+    for (int64_t a = threadIdx.x; a < n; a += blockDim.x) {
+        const int32_t i = perm[s0 + a];
+        for (int t = 0; t < k; ++t) { ld[t] = kd2[static_cast<int64_t>(i) * k + t]; li[t] = kidx[static_cast<int64_t>(i) * k + t]; }
+        for (int64_t b = 0; b < n; ++b) {
+            if (b == a) continue;
+            const int32_t j = perm[s0 + b];
+            knn_insert(ld, li, k, sqd(P, i, j), j);
+        }
+        for (int t = 0; t < k; ++t) { kd2[static_cast<int64_t>(i) * k + t] = ld[t]; kidx[static_cast<int64_t>(i) * k + t] = li[t]; }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// interaction lists
+// ---------------------------------------------------------------------------
+__global__ void k_inverse_perm(const int32_t* perm, int32_t* iperm, int64_t n) {
+    const int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    if (t < n) iperm[perm[t]] = static_cast<int32_t>(t);
+}
+
+// votes[a][b] = number of (point in leaf a, neighbour in leaf b) pairs
+__global__ void k_votes(int64_t n, int depth, const int64_t* start, const int32_t* perm, const int32_t* iperm,
+                        const int32_t* kidx, int k, int32_t* votes) {
+    const int64_t pos = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    if (pos >= n) return;
+    const int64_t L = int64_t(1) << depth;
+    const int64_t a = node_of(pos, depth, start) - L;
+    const int32_t i = perm[pos];
+    for (int t = 0; t < k; ++t) {
+        const int32_t j = kidx[static_cast<int64_t>(i) * k + t];
+        if (j < 0) continue;
+        const int64_t b = node_of(iperm[j], depth, start) - L;
+        atomicAdd(&votes[a * L + b], 1);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// skeletonisation
+// ---------------------------------------------------------------------------
+struct LevelArgs {
+    int lvl, depth;
+    int64_t n;
+    int k, s, cmax, rmax;
+    uint64_t seed;
+    double tau;
+    const int64_t* start;
+    const int64_t* size;
+    const int32_t* perm;
+    const int32_t* iperm;
+    const int32_t* kidx;
+    const int32_t* skel;        // compact skeletons of the level below
+    const int64_t* skoff;       // per heap id
+    const int32_t* rank;        // per heap id (level below filled)
+    int32_t* cand;              // per node cmax
+    int32_t* ncand;             // per node
+    int32_t* cnt;               // per node n
+    uint32_t* bits;             // per node ceil(n/32)
+    int32_t* uniq;              // per node cmax*k: unique outside neighbours, ascending
+    int32_t* rows;              // per node rmax
+    int32_t* nrows;             // per node
+    double* B;                  // per node rmax x cmax
+    int32_t* cp;                // per node cmax
+    double* Pws;                // per node s x cmax
+    int32_t* rk;                // per node
+    int32_t* status;            // per node: 0 ok, 1 row fill failed
+};
+
+__global__ void k_cand(LevelArgs A) {
+    const int64_t t = blockIdx.x;
+    const int64_t h = (int64_t(1) << A.lvl) + t;
+    int32_t* c = A.cand + t * A.cmax;
+    if (A.lvl == A.depth) {
+        const int64_t n = A.size[h];
+        for (int64_t u = threadIdx.x; u < n; u += blockDim.x) c[u] = A.perm[A.start[h] + u];
+        if (threadIdx.x == 0) A.ncand[t] = static_cast<int32_t>(n);
+    } else {
+        const int rl = A.rank[2 * h], rr = A.rank[2 * h + 1];
+        for (int u = threadIdx.x; u < rl + rr; u += blockDim.x)
+            c[u] = u < rl ? A.skel[A.skoff[2 * h] + u] : A.skel[A.skoff[2 * h + 1] + (u - rl)];
+        if (threadIdx.x == 0) A.ncand[t] = rl + rr;
+    }
+}
+
+// neighbour votes of the candidates, for points outside the node
+__global__ void k_row_count(LevelArgs A) {
+    const int64_t t = blockIdx.y;
+    const int64_t h = (int64_t(1) << A.lvl) + t;
+    const int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    const int nc = A.ncand[t];
+    if (e >= static_cast<int64_t>(nc) * A.k) return;
+    const int32_t j = A.cand[t * A.cmax + e / A.k];
+    const int32_t i = A.kidx[static_cast<int64_t>(j) * A.k + e % A.k];
+    if (i < 0) return;
+    const int64_t pi = A.iperm[i];
+    if (pi >= A.start[h] && pi < A.start[h] + A.size[h]) return;
+    atomicAdd(&A.cnt[t * A.n + i], 1);
+}
+
+// up to half of the rows: most-voted outside neighbours (ties: lower index);
+// the rest: uniform draws from outside the node (or every outside point when
+// that is all there is)
+__global__ void k_row_select(LevelArgs A) {
+    __shared__ int buf[kBlock];
+    __shared__ int tot;
+    const int64_t t = blockIdx.x;
+    const int64_t h = (int64_t(1) << A.lvl) + t;
+    const int64_t lo = A.start[h], hi = A.start[h] + A.size[h];
+    const int32_t* cnt = A.cnt + t * A.n;
+    int32_t* uq = A.uniq + t * static_cast<int64_t>(A.cmax) * A.k;
+    int32_t* rows = A.rows + t * A.rmax;
+    uint32_t* bits = A.bits + t * ((A.n + 31) / 32);
+    int64_t want = A.n - A.size[h];
+    if (want > 2 * static_cast<int64_t>(A.s)) want = 2 * static_cast<int64_t>(A.s);
+    const int64_t want_nb = want / 2;
+    // compaction of {i : cnt[i] > 0} in index order
+    int64_t nu = 0;
+    for (int64_t base = 0; base < A.n; base += kBlock) {
+        const int64_t i = base + threadIdx.x;
+        const int f = (i < A.n && cnt[i] > 0) ? 1 : 0;
+        const int incl = block_scan(f, buf);
+        if (threadIdx.x == blockDim.x - 1) tot = incl;
+        __syncthreads();
+        if (f) uq[nu + incl - 1] = static_cast<int32_t>(i);
+        nu += tot;
+        __syncthreads();
+    }
+    // rank by (votes desc, index asc); keep the first want_nb
+    for (int64_t u = threadIdx.x; u < nu; u += blockDim.x) {
+        const int32_t iu = uq[u];
+        const int32_t cu = cnt[iu];
+        int64_t r = 0;
+        for (int64_t v = 0; v < nu; ++v) {
+            const int32_t cv = cnt[uq[v]];
+            r += (cv > cu) || (cv == cu && v < u);
+        }
+        if (r < want_nb) {
+            rows[r] = iu;
+            atomicOr(&bits[iu >> 5], 1u << (iu & 31));
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t nr = nu < want_nb ? nu : want_nb;
+        int32_t st = 0;
+        if (nr < want) {
+            if (want == A.n - A.size[h]) {
+                for (int64_t i = 0; i < A.n && nr < want; ++i) {
+                    const int64_t pi = A.iperm[i];
+                    if (pi >= lo && pi < hi) continue;
+                    if (bits[i >> 5] & (1u << (i & 31))) continue;
+                    rows[nr++] = static_cast<int32_t>(i);
+                    bits[i >> 5] |= 1u << (i & 31);
+                }
+            } else {
+                const uint64_t cap = 64ull * static_cast<uint64_t>(A.n) + 1024ull;
+                uint32_t d = 0;
+                while (nr < want) {
+                    if (static_cast<uint64_t>(d) > cap) { st = 1; break; }
+                    const int32_t i = static_cast<int32_t>(
+                        below(philox_draw(A.seed, kRowFill, static_cast<uint32_t>(h), 0, d), static_cast<uint32_t>(A.n)));
+                    ++d;
+                    const int64_t pi = A.iperm[i];
+                    if (pi >= lo && pi < hi) continue;
+                    if (bits[i >> 5] & (1u << (i & 31))) continue;
+                    rows[nr++] = i;
+                    bits[i >> 5] |= 1u << (i & 31);
+                }
+            }
+        }
+        A.nrows[t] = static_cast<int32_t>(nr);
+        A.status[t] = st;
+    }
+}
+
+// B = K(rows, cand), row-major with leading dimension ncand
+__global__ void k_block(LevelArgs A, Pts P) {
+    const int64_t t = blockIdx.y;
+    const int nc = A.ncand[t], nr = A.nrows[t];
+    const int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    if (e >= static_cast<int64_t>(nr) * nc) return;
+    const int r = static_cast<int>(e / nc), c = static_cast<int>(e % nc);
+    A.B[t * static_cast<int64_t>(A.rmax) * A.cmax + e] = kval(P, A.rows[t * A.rmax + r], A.cand[t * A.cmax + c]);
+}
+
+// Householder QR with column pivoting of B (nr x nc) and the interpolation
+// matrix P = [I, R11^-1 R12] in candidate order.  One workgroup per node, one
+// thread per column; every column norm and dot product is a sequential sum
+// over rows.
+__global__ void __launch_bounds__(kBlock) k_pivoted_id(LevelArgs A) {
+    __shared__ double sv[kBlock];
+    __shared__ int64_t sp[kBlock];
+    __shared__ double hv[1024];   // Householder vector (rows <= 1024)
+    __shared__ double s_vtv, s_alpha, s_r11;
+    __shared__ int s_stop;
+    const int64_t t = blockIdx.x;
+    const int nc = A.ncand[t], nr = A.nrows[t];
+    double* B = A.B + t * static_cast<int64_t>(A.rmax) * A.cmax;
+    int32_t* cp = A.cp + t * A.cmax;
+    double* Pm = A.Pws + t * static_cast<int64_t>(A.s) * A.cmax;
+    for (int c = threadIdx.x; c < nc; c += blockDim.x) cp[c] = c;
+    int kmax = nr < nc ? nr : nc;
+    if (kmax > A.s) kmax = A.s;
+    int rank = 0;
+    __syncthreads();
+    for (int j = 0; j < kmax; ++j) {
+        // pivot: largest remaining column norm (ties: lowest column)
+        double best = -1.0;
+        int64_t bc = INT64_MAX;
+        for (int c = j + threadIdx.x; c < nc; c += blockDim.x) {
+            double acc = 0.0;
+            for (int i = j; i < nr; ++i) {
+                const double x = B[static_cast<int64_t>(i) * nc + c];
+                acc = acc + x * x;
+            }
+            const double nrm = sqrt(acc);
+            if (nrm > best || (nrm == best && c < bc)) { best = nrm; bc = c; }
+        }
+        block_argbest(best, bc, false, sv, sp);
+        const int piv = (bc >= j && bc < nc) ? static_cast<int>(bc) : j;
+        if (piv != j) {
+            for (int i = threadIdx.x; i < nr; i += blockDim.x) {
+                const double x = B[static_cast<int64_t>(i) * nc + j];
+                B[static_cast<int64_t>(i) * nc + j] = B[static_cast<int64_t>(i) * nc + piv];
+                B[static_cast<int64_t>(i) * nc + piv] = x;
+            }
+            if (threadIdx.x == 0) { const int32_t x = cp[j]; cp[j] = cp[piv]; cp[piv] = x; }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            if (j == 0) s_r11 = best;
+            s_stop = !(best > A.tau * s_r11);
+        }
+        __syncthreads();
+        if (s_stop) break;
+        for (int i = j + threadIdx.x; i < nr; i += blockDim.x) hv[i] = B[static_cast<int64_t>(i) * nc + j];
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const double x0 = hv[j];
+            const double alpha = x0 >= 0.0 ? -best : best;
+            hv[j] = x0 - alpha;
+            double vtv = 0.0;
+            for (int i = j; i < nr; ++i) vtv = vtv + hv[i] * hv[i];
+            s_vtv = vtv;
+            s_alpha = alpha;
+        }
+        __syncthreads();
+        const double vtv = s_vtv;
+        for (int c = j + 1 + threadIdx.x; c < nc; c += blockDim.x) {
+            double dot = 0.0;
+            for (int i = j; i < nr; ++i) dot = dot + hv[i] * B[static_cast<int64_t>(i) * nc + c];
+            const double f = (2.0 * dot) / vtv;
+            for (int i = j; i < nr; ++i) B[static_cast<int64_t>(i) * nc + c] = B[static_cast<int64_t>(i) * nc + c] - f * hv[i];
+        }
+        __syncthreads();
+        for (int i = j + threadIdx.x; i < nr; i += blockDim.x) B[static_cast<int64_t>(i) * nc + j] = (i == j) ? s_alpha : 0.0;
+        rank = j + 1;
+        __syncthreads();
+    }
+    // P[:, cp[j]] = e_j for j < rank; P[:, cp[c]] = R11^-1 R12[:, c] (back substitution)
+    for (int64_t e = threadIdx.x; e < static_cast<int64_t>(rank) * nc; e += blockDim.x) Pm[e] = 0.0;
+    __syncthreads();
+    for (int j = threadIdx.x; j < rank; j += blockDim.x) Pm[static_cast<int64_t>(j) * nc + cp[j]] = 1.0;
+    for (int c = rank + threadIdx.x; c < nc; c += blockDim.x) {
+        const int pc = cp[c];
+        for (int i = rank - 1; i >= 0; --i) {
+            double acc = B[static_cast<int64_t>(i) * nc + c];
+            for (int q = i + 1; q < rank; ++q) acc = acc - B[static_cast<int64_t>(i) * nc + q] * Pm[static_cast<int64_t>(q) * nc + pc];
+            Pm[static_cast<int64_t>(i) * nc + pc] = acc / B[static_cast<int64_t>(i) * nc + i];
+        }
+    }
+    if (threadIdx.x == 0) A.rk[t] = rank;
+}
+
+// move this level's skeletons, P and rows into the compact operator arrays
+__global__ void k_compact(LevelArgs A, const int64_t* skoff, const int64_t* poff, const int64_t* rowoff,
+                          int32_t* skel_out, double* P_out, int32_t* rows_out) {
+    const int64_t t = blockIdx.x;
+    const int64_t h = (int64_t(1) << A.lvl) + t;
+    const int rk = A.rk[t], nc = A.ncand[t], nr = A.nrows[t];
+    for (int u = threadIdx.x; u < rk; u += blockDim.x) skel_out[skoff[h] + u] = A.cand[t * A.cmax + A.cp[t * A.cmax + u]];
+    for (int64_t e = threadIdx.x; e < static_cast<int64_t>(rk) * nc; e += blockDim.x)
+        P_out[poff[h] + e] = A.Pws[t * static_cast<int64_t>(A.s) * A.cmax + e];
+    for (int u = threadIdx.x; u < nr; u += blockDim.x) rows_out[rowoff[h] + u] = A.rows[t * A.rmax + u];
+}
+
+// ---------------------------------------------------------------------------
+// kernel tiles
+// ---------------------------------------------------------------------------
+struct NearPair {
+    int64_t off;       // element offset of the tile (column-major, leading dim ld)
+    int32_t ld, a0, na, b0, nb, pad;   // a0/b0: tree positions of row 0 / column 0
+};
+
+__global__ void k_near_tiles(const NearPair* pairs, const int32_t* perm, Pts P, double* out) {
+    const NearPair pr = pairs[blockIdx.y];
+    const int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    if (e >= static_cast<int64_t>(pr.ld) * pr.nb) return;
+    const int i = static_cast<int>(e % pr.ld), j = static_cast<int>(e / pr.ld);
+    out[pr.off + e] = i < pr.na ? kval(P, perm[pr.a0 + i], perm[pr.b0 + j]) : 0.0;
+}
+
+struct FarBlock {
+    int64_t off;       // element offset (row-major rank x cols)
+    int64_t col0;      // first column in the global column map
+    int32_t rows, cols;
+    int64_t sk0;       // skeleton offset of the row node
+};
+
+__global__ void k_far_tiles(const FarBlock* blocks, const int32_t* colmap, const int32_t* skel, Pts P, double* out) {
+    const FarBlock fb = blocks[blockIdx.y];
+    const int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    if (e >= static_cast<int64_t>(fb.rows) * fb.cols) return;
+    const int i = static_cast<int>(e / fb.cols), c = static_cast<int>(e % fb.cols);
+    out[fb.off + e] = kval(P, skel[fb.sk0 + i], skel[colmap[fb.col0 + c]]);
+}
+
+__global__ void k_check_points(const double* x, int64_t cnt, int* bad) {
+    const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    if (i < cnt && !isfinite(x[i])) atomicOr(bad, 1);
+}
+
+template <typename T>
+T* ptr(DevBuf<T>& b) { return b.get(); }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// host orchestration
+// ---------------------------------------------------------------------------
+static void tree_ranges(int64_t n, int depth, std::vector<int64_t>& start, std::vector<int64_t>& size) {
+    const int64_t nn = int64_t(1) << (depth + 1);
+    start.assign(nn, 0);
+    size.assign(nn, 0);
+    size[1] = n;
+    for (int64_t h = 1; h < (int64_t(1) << depth); ++h) {
+        const int64_t nl = size[h] / 2;
+        start[2 * h] = start[h];
+        size[2 * h] = nl;
+        start[2 * h + 1] = start[h] + nl;
+        size[2 * h + 1] = size[h] - nl;
+    }
+}
+
+// one perfect tree of the given depth: ball tree (mode 0) or random-pivot tree (mode 1)
+static void build_tree(Op& op, int mode, int it, DevBuf<int32_t>& perm, DevBuf<int32_t>& tmp, Pts P, hipStream_t s,
+                       DevBuf<int32_t>& samp, DevBuf<int32_t>& nsamp, DevBuf<int32_t>& pq, DevBuf<double>& sumk,
+                       DevBuf<double>& key, DevBuf<uint8_t>& left) {
+    const int64_t n = op.n;
+    const int gN = ceil_div(n, kBlock);
+    hipLaunchKernelGGL(k_iota, dim3(gN), dim3(kBlock), 0, s, perm.get(), n);
+    for (int lvl = 0; lvl < op.depth; ++lvl) {
+        const int nodes = 1 << lvl;
+        if (mode == 0) {
+            hipLaunchKernelGGL(k_tree_sample, dim3(ceil_div(nodes, 64)), dim3(64), 0, s, lvl, op.d_start.get(),
+                               op.d_size.get(), op.prm.seed, samp.get(), nsamp.get());
+            hipLaunchKernelGGL(k_tree_sumk, dim3(gN), dim3(kBlock), 0, s, lvl, n, op.d_start.get(), perm.get(),
+                               samp.get(), nsamp.get(), P, sumk.get());
+            hipLaunchKernelGGL(k_tree_pq, dim3(nodes), dim3(kBlock), 0, s, lvl, op.d_start.get(), op.d_size.get(),
+                               perm.get(), sumk.get(), P, pq.get());
+        } else {
+            hipLaunchKernelGGL(k_knn_pq, dim3(ceil_div(nodes, 64)), dim3(64), 0, s, lvl, op.d_start.get(),
+                               op.d_size.get(), perm.get(), op.prm.seed, it, pq.get());
+        }
+        hipLaunchKernelGGL(k_tree_key, dim3(gN), dim3(kBlock), 0, s, lvl, n, op.d_start.get(), perm.get(), pq.get(),
+                           P, mode, key.get());
+        hipLaunchKernelGGL(k_tree_rank, dim3(gN), dim3(kBlock), 0, s, lvl, n, op.d_start.get(), op.d_size.get(),
+                           perm.get(), key.get(), left.get());
+        hipLaunchKernelGGL(k_tree_partition, dim3(nodes), dim3(kBlock), 0, s, lvl, op.d_start.get(), op.d_size.get(),
+                           perm.get(), left.get(), tmp.get());
+        check_launch("tree level");
+        std::swap(perm, tmp);
+    }
+}
+
+// near lists: self plus ceil(budget * L) other leaves by (votes desc, id asc), symmetrised
+static void build_near_lists(Op& op, const std::vector<int32_t>& votes) {
+    const int64_t L = op.L;
+    std::vector<uint8_t> rel(static_cast<size_t>(L * L), 0);
+    const int64_t extra = static_cast<int64_t>(std::ceil(op.prm.budget * static_cast<double>(L)));
+    std::vector<int32_t> order(L);
+    for (int64_t a = 0; a < L; ++a) {
+        rel[a * L + a] = 1;
+        int cnt = 0;
+        for (int64_t b = 0; b < L; ++b)
+            if (b != a) order[cnt++] = static_cast<int32_t>(b);
+        std::stable_sort(order.begin(), order.begin() + cnt, [&](int32_t x, int32_t y) {
+            const int32_t vx = votes[a * L + x], vy = votes[a * L + y];
+            return vx != vy ? vx > vy : x < y;
+        });
+        for (int64_t t = 0; t < extra && t < cnt; ++t) rel[a * L + order[t]] = 1;
+    }
+    for (int64_t a = 0; a < L; ++a)
+        for (int64_t b = 0; b < L; ++b)
+            if (rel[a * L + b]) rel[b * L + a] = 1;
+    op.near_off.assign(L + 1, 0);
+    op.near_idx.clear();
+    for (int64_t a = 0; a < L; ++a) {
+        op.near_off[a] = static_cast<int32_t>(op.near_idx.size());
+        for (int64_t b = 0; b < L; ++b)
+            if (rel[a * L + b]) op.near_idx.push_back(static_cast<int32_t>(b));
+    }
+    op.near_off[L] = static_cast<int32_t>(op.near_idx.size());
+}
+
+// far lists: dual traversal from (root, root); a same-level pair without any
+// near leaf pair beneath it is far, otherwise its four child pairs are visited
+static void build_far_lists(Op& op) {
+    const int64_t L = op.L;
+    const int depth = op.depth;
+    // near leaf relation as bit rows for quick subtree queries
+    std::vector<uint8_t> rel(static_cast<size_t>(L * L), 0);
+    for (int64_t a = 0; a < L; ++a)
+        for (int32_t t = op.near_off[a]; t < op.near_off[a + 1]; ++t) rel[a * L + op.near_idx[t]] = 1;
+    // prefix sums over the relation matrix for O(1) rectangle queries
+    std::vector<int64_t> ps(static_cast<size_t>((L + 1) * (L + 1)), 0);
+    for (int64_t a = 0; a < L; ++a)
+        for (int64_t b = 0; b < L; ++b)
+            ps[(a + 1) * (L + 1) + (b + 1)] = rel[a * L + b] + ps[a * (L + 1) + (b + 1)] + ps[(a + 1) * (L + 1) + b] -
+                                              ps[a * (L + 1) + b];
+    auto related = [&](int64_t x, int64_t y, int lvl) {
+        const int sh = depth - lvl;
+        const int64_t x0 = (x << sh) - L, x1 = x0 + (int64_t(1) << sh);
+        const int64_t y0 = (y << sh) - L, y1 = y0 + (int64_t(1) << sh);
+        return ps[x1 * (L + 1) + y1] - ps[x0 * (L + 1) + y1] - ps[x1 * (L + 1) + y0] + ps[x0 * (L + 1) + y0] > 0;
+    };
+    std::vector<std::vector<int32_t>> far(static_cast<size_t>(op.nnodes));
+    struct Item { int64_t x, y; int lvl; };
+    std::vector<Item> stack{{1, 1, 0}};
+    while (!stack.empty()) {
+        const Item it = stack.back();
+        stack.pop_back();
+        if (!related(it.x, it.y, it.lvl)) { far[it.x].push_back(static_cast<int32_t>(it.y)); continue; }
+        if (it.lvl == depth) continue;
+        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 2; ++j) stack.push_back({2 * it.x + i, 2 * it.y + j, it.lvl + 1});
+    }
+    op.far_off.assign(op.nnodes + 1, 0);
+    op.far_idx.clear();
+    for (int64_t h = 0; h < op.nnodes; ++h) {
+        std::sort(far[h].begin(), far[h].end());
+        op.far_off[h] = static_cast<int32_t>(op.far_idx.size());
+        op.far_idx.insert(op.far_idx.end(), far[h].begin(), far[h].end());
+    }
+    op.far_off[op.nnodes] = static_cast<int32_t>(op.far_idx.size());
+}
+
+static void skeletonize(Op& op, Pts P, hipStream_t s) {
+    const int64_t n = op.n;
+    const int k = op.prm.knn_k, smax = op.prm.max_rank_s;
+    op.rank.assign(op.nnodes, 0);
+    op.ncand.assign(op.nnodes, 0);
+    op.nrows.assign(op.nnodes, 0);
+    op.skoff.assign(op.nnodes, 0);
+    op.poff.assign(op.nnodes, 0);
+    op.rowoff.assign(op.nnodes, 0);
+    int64_t leafmax = 0;
+    for (int64_t h = op.L; h < 2 * int64_t(op.L); ++h) leafmax = std::max(leafmax, op.size[h]);
+    const int cmax = static_cast<int>(std::max<int64_t>(leafmax, 2 * static_cast<int64_t>(smax)));
+    const int rmax = 2 * smax;
+    HDM_CHECK(rmax <= 1024, HDM_EINVAL, "max_rank_s must be <= 512");
+    // per-level outputs collected on the host side as offsets; data in growing device arrays
+    const int64_t maxnodes = op.L;        // widest level
+    DevBuf<int32_t> cand(maxnodes * cmax), ncand(maxnodes), rows(maxnodes * rmax), nrows(maxnodes), cp(maxnodes * cmax),
+        rk(maxnodes), status(maxnodes);
+    DevBuf<int32_t> uniq(static_cast<size_t>(maxnodes) * cmax * k);
+    DevBuf<double> B(static_cast<size_t>(maxnodes) * rmax * cmax), Pws(static_cast<size_t>(maxnodes) * smax * cmax);
+    // count and bitmap workspaces are per node of the widest level
+    DevBuf<int32_t> cnt(static_cast<size_t>(maxnodes) * n);
+    DevBuf<uint32_t> bits(static_cast<size_t>(maxnodes) * ((n + 31) / 32));
+    // compact outputs: upper bounds on skeletons/rows; P sized per level and concatenated
+    DevBuf<int32_t> skel_buf(static_cast<size_t>(op.nnodes) * smax + 1);
+    DevBuf<int32_t> rows_buf(static_cast<size_t>(op.nnodes) * rmax + 1);
+    std::vector<DevBuf<double>> Plevel(op.depth + 1);
+    std::vector<int64_t> Plevel_base(op.depth + 1, 0);
+    DevBuf<int32_t> d_rank(op.nnodes);
+    DevBuf<int64_t> d_skoff(op.nnodes), d_poff(op.nnodes), d_rowoff(op.nnodes);
+    HDM_HIP(hipMemsetAsync(d_rank.get(), 0, d_rank.bytes(), s));
+    int64_t sk_next = 0, row_next = 0, p_next = 0;
+    std::vector<int32_t> h_rk(maxnodes), h_nc(maxnodes), h_nr(maxnodes), h_st(maxnodes);
+    for (int lvl = op.depth; lvl >= 1; --lvl) {
+        const int nodes = 1 << lvl;
+        HDM_HIP(hipMemsetAsync(cnt.get(), 0, sizeof(int32_t) * static_cast<size_t>(nodes) * n, s));
+        HDM_HIP(hipMemsetAsync(bits.get(), 0, sizeof(uint32_t) * static_cast<size_t>(nodes) * ((n + 31) / 32), s));
+        LevelArgs A{};
+        A.lvl = lvl;
+        A.depth = op.depth;
+        A.n = n;
+        A.k = k;
+        A.s = smax;
+        A.cmax = cmax;
+        A.rmax = rmax;
+        A.seed = op.prm.seed;
+        A.tau = op.prm.tau;
+        A.start = op.d_start.get();
+        A.size = op.d_size.get();
+        A.perm = op.perm.get();
+        A.iperm = op.iperm.get();
+        A.kidx = op.knn_idx.get();
+        A.skel = skel_buf.get();
+        A.skoff = d_skoff.get();
+        A.rank = d_rank.get();
+        A.cand = cand.get();
+        A.ncand = ncand.get();
+        A.cnt = cnt.get();
+        A.bits = bits.get();
+        A.uniq = uniq.get();
+        A.rows = rows.get();
+        A.nrows = nrows.get();
+        A.B = B.get();
+        A.cp = cp.get();
+        A.Pws = Pws.get();
+        A.rk = rk.get();
+        A.status = status.get();
+        hipLaunchKernelGGL(k_cand, dim3(nodes), dim3(kBlock), 0, s, A);
+        hipLaunchKernelGGL(k_row_count, dim3(ceil_div(static_cast<int64_t>(cmax) * k, kBlock), nodes), dim3(kBlock), 0, s,
+                           A);
+        hipLaunchKernelGGL(k_row_select, dim3(nodes), dim3(kBlock), 0, s, A);
+        hipLaunchKernelGGL(k_block, dim3(ceil_div(static_cast<int64_t>(rmax) * cmax, kBlock), nodes), dim3(kBlock), 0,
+                           s, A, P);
+        hipLaunchKernelGGL(k_pivoted_id, dim3(nodes), dim3(kBlock), 0, s, A);
+        check_launch("skeletonisation");
+        rk.download(h_rk.data(), nodes, s);
+        ncand.download(h_nc.data(), nodes, s);
+        nrows.download(h_nr.data(), nodes, s);
+        status.download(h_st.data(), nodes, s);
+        HDM_HIP(hipStreamSynchronize(s));
+        int64_t plev = 0;
+        for (int t = 0; t < nodes; ++t) {
+            HDM_CHECK(h_st[t] == 0, HDM_EINTERNAL, "row sampling did not terminate");
+            const int64_t h = nodes + t;
+            op.rank[h] = h_rk[t];
+            op.ncand[h] = h_nc[t];
+            op.nrows[h] = h_nr[t];
+            op.skoff[h] = sk_next;
+            sk_next += h_rk[t];
+            op.rowoff[h] = row_next;
+            row_next += h_nr[t];
+            op.poff[h] = p_next + plev;
+            plev += static_cast<int64_t>(h_rk[t]) * h_nc[t];
+        }
+        Plevel[lvl].alloc(plev > 0 ? plev : 1);
+        Plevel_base[lvl] = p_next;
+        // level-local P offsets for the compaction kernel
+        std::vector<int64_t> poff_local(op.nnodes, 0);
+        for (int t = 0; t < nodes; ++t) poff_local[nodes + t] = op.poff[nodes + t] - p_next;
+        p_next += plev;
+        d_rank.upload(op.rank.data(), op.nnodes, s);
+        d_skoff.upload(op.skoff.data(), op.nnodes, s);
+        DevBuf<int64_t> d_plocal = to_device(poff_local, s);
+        d_rowoff.upload(op.rowoff.data(), op.nnodes, s);
+        hipLaunchKernelGGL(k_compact, dim3(nodes), dim3(kBlock), 0, s, A, d_skoff.get(), d_plocal.get(), d_rowoff.get(),
+                           skel_buf.get(), Plevel[lvl].get(), rows_buf.get());
+        check_launch("compact");
+        HDM_HIP(hipStreamSynchronize(s));
+    }
+    op.nskel = sk_next;
+    op.skel = std::move(skel_buf);
+    op.rows = std::move(rows_buf);
+    op.np = p_next;
+    op.P64.alloc(p_next > 0 ? p_next : 1);
+    for (int lvl = 1; lvl <= op.depth; ++lvl) {
+        if (Plevel[lvl].n == 0) continue;
+        int64_t cntp = 0;
+        for (int64_t h = int64_t(1) << lvl; h < (int64_t(1) << (lvl + 1)); ++h)
+            cntp += static_cast<int64_t>(op.rank[h]) * op.ncand[h];
+        if (cntp)
+            HDM_HIP(hipMemcpyAsync(op.P64.get() + Plevel_base[lvl], Plevel[lvl].get(), sizeof(double) * cntp,
+                                   hipMemcpyDeviceToDevice, s));
+    }
+    HDM_HIP(hipStreamSynchronize(s));
+}
+
+static void build_tiles(Op& op, Pts P, hipStream_t s) {
+    const int64_t L = op.L;
+    // near blocks: per leaf, column-major ld x (sum of near leaf sizes), ld = rows rounded up to 8
+    op.near_block_off.assign(L, 0);
+    op.near_ld.assign(L, 0);
+    op.near_tile_off.assign(op.near_idx.size(), 0);
+    std::vector<NearPair> pairs;
+    int64_t off = 0;
+    for (int64_t a = 0; a < L; ++a) {
+        const int64_t ha = L + a;
+        const int32_t ld = static_cast<int32_t>((op.size[ha] + 7) / 8 * 8);
+        op.near_ld[a] = ld;
+        op.near_block_off[a] = off;
+        for (int32_t t = op.near_off[a]; t < op.near_off[a + 1]; ++t) {
+            const int64_t hb = L + op.near_idx[t];
+            op.near_tile_off[t] = off;
+            pairs.push_back(NearPair{off, ld, static_cast<int32_t>(op.start[ha]), static_cast<int32_t>(op.size[ha]),
+                                     static_cast<int32_t>(op.start[hb]), static_cast<int32_t>(op.size[hb]), 0});
+            off += static_cast<int64_t>(ld) * op.size[hb];
+        }
+    }
+    op.near_elems = off;
+    op.near64.alloc(off);
+    {
+        DevBuf<NearPair> dp = to_device(pairs, s);
+        int64_t maxe = 0;
+        for (auto& p : pairs) maxe = std::max<int64_t>(maxe, static_cast<int64_t>(p.ld) * p.nb);
+        for (size_t base = 0; base < pairs.size(); base += 65535) {
+            const int cnt = static_cast<int>(std::min<size_t>(65535, pairs.size() - base));
+            hipLaunchKernelGGL(k_near_tiles, dim3(ceil_div(maxe, kBlock), cnt), dim3(kBlock), 0, s, dp.get() + base,
+                               op.perm.get(), P, op.near64.get());
+        }
+        check_launch("near tiles");
+        HDM_HIP(hipStreamSynchronize(s));
+    }
+    // far blocks: per node, row-major rank x (sum of far ranks)
+    op.far_block_off.assign(op.nnodes, 0);
+    op.far_cols.assign(op.nnodes, 0);
+    op.far_colbase.assign(op.nnodes, 0);
+    std::vector<FarBlock> blocks;
+    std::vector<int32_t> colmap;
+    int64_t foff = 0;
+    for (int64_t h = 2; h < op.nnodes; ++h) {
+        int32_t cols = 0;
+        op.far_colbase[h] = static_cast<int64_t>(colmap.size());
+        for (int32_t t = op.far_off[h]; t < op.far_off[h + 1]; ++t) {
+            const int32_t g = op.far_idx[t];
+            for (int32_t j = 0; j < op.rank[g]; ++j) colmap.push_back(static_cast<int32_t>(op.skoff[g] + j));
+            cols += op.rank[g];
+        }
+        op.far_cols[h] = cols;
+        op.far_block_off[h] = foff;
+        if (cols > 0 && op.rank[h] > 0)
+            blocks.push_back(FarBlock{foff, static_cast<int64_t>(colmap.size()) - cols, op.rank[h], cols, op.skoff[h]});
+        foff += static_cast<int64_t>(op.rank[h]) * cols;
+    }
+    op.far_elems = foff;
+    op.far64.alloc(foff > 0 ? foff : 1);
+    op.far_colmap = to_device(colmap, s);
+    if (!blocks.empty()) {
+        DevBuf<FarBlock> db = to_device(blocks, s);
+        int64_t maxe = 0;
+        for (auto& b : blocks) maxe = std::max<int64_t>(maxe, static_cast<int64_t>(b.rows) * b.cols);
+        for (size_t base = 0; base < blocks.size(); base += 65535) {
+            const int cnt = static_cast<int>(std::min<size_t>(65535, blocks.size() - base));
+            hipLaunchKernelGGL(k_far_tiles, dim3(ceil_div(maxe, kBlock), cnt), dim3(kBlock), 0, s, db.get() + base,
+                               op.far_colmap.get(), op.skel.get(), P, op.far64.get());
+        }
+        check_launch("far tiles");
+    }
+    HDM_HIP(hipStreamSynchronize(s));
+}
+
+void compress_operator(Op& op, const void* X, int x_on_device, hipStream_t s) {
+    const auto t0 = std::chrono::steady_clock::now();
+    const hdm_params& p = op.prm;
+    op.n = p.n;
+    op.dim = p.dim;
+    int depth = 0;
+    while ((op.n + (int64_t(1) << depth) - 1) / (int64_t(1) << depth) > p.leaf_m) ++depth;
+    op.depth = depth;
+    op.L = 1 << depth;
+    op.nnodes = int64_t(2) * op.L;
+    HDM_CHECK((op.n >> depth) > p.knn_k, HDM_EINVAL, "every leaf must hold more than knn_k points");
+    tree_ranges(op.n, depth, op.start, op.size);
+    op.d_start = to_device(op.start, s);
+    op.d_size = to_device(op.size, s);
+    // points
+    const size_t xb = static_cast<size_t>(op.n) * op.dim * dtype_size(p.x_dtype);
+    const hipMemcpyKind kind = x_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    Pts P{};
+    P.dim = op.dim;
+    P.eps = p.eps;
+    if (p.x_dtype == HDM_U8) {
+        op.xu.alloc(xb);
+        HDM_HIP(hipMemcpyAsync(op.xu.get(), X, xb, kind, s));
+        P.xu = op.xu.get();
+        P.is_u8 = 1;
+    } else {
+        op.xf.alloc(static_cast<size_t>(op.n) * op.dim);
+        HDM_HIP(hipMemcpyAsync(op.xf.get(), X, xb, kind, s));
+        P.xf = op.xf.get();
+        P.is_u8 = 0;
+        DevBuf<int> bad(1);
+        HDM_HIP(hipMemsetAsync(bad.get(), 0, sizeof(int), s));
+        hipLaunchKernelGGL(k_check_points, dim3(ceil_div(static_cast<int64_t>(op.n) * op.dim, kBlock)), dim3(kBlock), 0, s,
+                           op.xf.get(), static_cast<int64_t>(op.n) * op.dim, bad.get());
+        int hb = 0;
+        bad.download(&hb, 1, s);
+        HDM_HIP(hipStreamSynchronize(s));
+        HDM_CHECK(hb == 0, HDM_EINVAL, "points contain NaN or Inf");
+    }
+    // trees
+    const int64_t n = op.n;
+    DevBuf<int32_t> perm(n), tmp(n), samp(static_cast<size_t>(op.L) * kSample), nsamp(op.L), pq(2 * op.L);
+    DevBuf<double> sumk(n), key(n);
+    DevBuf<uint8_t> left(n);
+    build_tree(op, 0, 0, perm, tmp, P, s, samp, nsamp, pq, sumk, key, left);
+    op.perm = std::move(perm);
+    op.iperm.alloc(n);
+    hipLaunchKernelGGL(k_inverse_perm, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, s, op.perm.get(), op.iperm.get(), n);
+    // neighbours: random-pivot trees, all pairs inside leaves
+    const int k = p.knn_k;
+    op.knn_idx.alloc(static_cast<size_t>(n) * k);
+    op.knn_d2.alloc(static_cast<size_t>(n) * k);
+    hipLaunchKernelGGL(k_knn_init, dim3(ceil_div(n * k, kBlock)), dim3(kBlock), 0, s, op.knn_idx.get(), op.knn_d2.get(),
+                       n * k);
+    DevBuf<int32_t> kperm(n);
+    int threads = kBlock;
+    while (threads > 64 && static_cast<size_t>(threads) * k * 12 > 64 * 1024) threads /= 2;
+    for (int it = 0; it < p.knn_iters; ++it) {
+        build_tree(op, 1, it, kperm, tmp, P, s, samp, nsamp, pq, sumk, key, left);
+        hipLaunchKernelGGL(k_knn_leaf, dim3(op.L), dim3(threads), static_cast<size_t>(threads) * k * 12, s, op.depth,
+                           op.d_start.get(), op.d_size.get(), kperm.get(), P, k, op.knn_idx.get(), op.knn_d2.get());
+        check_launch("knn leaf");
+    }
+    // lists
+    {
+        DevBuf<int32_t> votes(static_cast<size_t>(op.L) * op.L);
+        HDM_HIP(hipMemsetAsync(votes.get(), 0, votes.bytes(), s));
+        hipLaunchKernelGGL(k_votes, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, s, n, op.depth, op.d_start.get(),
+                           op.perm.get(), op.iperm.get(), op.knn_idx.get(), k, votes.get());
+        check_launch("votes");
+        std::vector<int32_t> hv(static_cast<size_t>(op.L) * op.L);
+        votes.download(hv.data(), hv.size(), s);
+        HDM_HIP(hipStreamSynchronize(s));
+        build_near_lists(op, hv);
+        build_far_lists(op);
+    }
+    skeletonize(op, P, s);
+    build_tiles(op, P, s);
+    op.seconds_compress = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace hdm

@@ -1,0 +1,123 @@
+// The compressed operator resident in HBM, and the launch plans that apply it.
+#pragma once
+
+#include <memory>
+
+#include "common.hpp"
+
+namespace hdm {
+
+struct Ctx {
+    int device = 0;
+    size_t budget = 0;      // bytes, 0 = unlimited
+    size_t resident = 0;    // bytes held by live operators of this context
+};
+
+// One streaming work item of the near-field product: ncols consecutive
+// columns (one near tile) times the rows [row0, row0 + nrows) of leaf a's near
+// block.  Column c of the item multiplies w at tree position col_pos + c.
+struct NearItem {
+    int64_t tile_off;   // element offset of the item's first column, row 0, in the near buffer
+    int64_t part_off;   // offset of the item's partial sums (nrows_ld values)
+    int32_t ld;         // leading dimension (padded rows) of the leaf's near block
+    int32_t row0;       // first row of the item (multiple of the row group)
+    int32_t ncols;
+    int32_t col_pos;    // tree position of the first column's point
+    int32_t tile;       // index of the near tile (for its scale)
+    int32_t nrows;      // rows of the item: [row0, min(ld, row0 + nrows))
+};
+
+// Per leaf: where its partial sums live and how many items feed each row group.
+struct LeafPlan {
+    int64_t part_off;   // first partial of the leaf
+    int32_t nitems;     // items per row group of this leaf (same for each group)
+    int32_t ld;
+    int32_t start;      // tree position of row 0
+    int32_t rows;       // points in the leaf
+    int32_t heap;       // heap id
+    int32_t ngroups;    // row groups
+};
+
+struct NodeLevel {       // nodes of one tree level with their skeleton work
+    int level;
+    std::vector<int32_t> heap;  // heap ids with rank > 0
+};
+
+struct Op {
+    Ctx* ctx = nullptr;
+    hdm_params prm{};
+    int64_t n = 0;
+    int dim = 0, depth = 0, L = 0;
+    int64_t nnodes = 0;                  // 2L heap slots (slot 0 unused)
+    std::vector<int64_t> start, size;    // per heap id
+    DevBuf<int64_t> d_start, d_size;
+    DevBuf<double> xf;                   // points, original order (float64)
+    DevBuf<uint8_t> xu;                  // points, original order (u8 codes)
+    DevBuf<int32_t> perm, iperm;         // tree position -> original index, and back
+    DevBuf<int32_t> knn_idx;             // n x k (original order)
+    DevBuf<double> knn_d2;
+    // interaction lists (host copies are the source of truth for planning)
+    std::vector<int32_t> near_off, near_idx, far_off, far_idx;
+    // skeletons
+    std::vector<int32_t> rank, ncand, nrows;   // per heap id
+    std::vector<int64_t> skoff;                // per heap id: offset into skeleton arrays (children adjacent)
+    int64_t nskel = 0;
+    DevBuf<int32_t> skel;                      // original indices, by skoff
+    std::vector<int64_t> poff;                 // per heap id: offset of P (rank x ncand, row-major)
+    int64_t np = 0;
+    DevBuf<double> P64;
+    DevBuf<float> P32;
+    std::vector<int64_t> rowoff;               // per heap id: offset of sampled rows
+    DevBuf<int32_t> rows;
+    // near field: per leaf a column-major block ld x (sum of near leaf sizes)
+    std::vector<int64_t> near_block_off;       // per leaf (elements)
+    std::vector<int32_t> near_ld;              // per leaf
+    std::vector<int64_t> near_tile_off;        // per near pair (elements; same order as near_idx)
+    int64_t near_elems = 0;
+    DevBuf<double> near64;
+    DevBuf<char> nearT;                        // eval precision copy (near_prec)
+    DevBuf<float> near_scale;                  // per near pair
+    // far field: per node a row-major block rank x (sum of far ranks)
+    std::vector<int64_t> far_block_off;        // per heap id
+    std::vector<int32_t> far_cols;             // per heap id
+    int64_t far_elems = 0;
+    DevBuf<double> far64;
+    DevBuf<char> farT;
+    DevBuf<float> far_scale;                   // per heap id (one scale per block)
+    DevBuf<int32_t> far_colmap;                // per block column: skeleton slot of the weight it multiplies
+    std::vector<int64_t> far_colbase;          // per heap id: first column of its block in far_colmap
+    DevBuf<int64_t> d_far_colbase;
+    // plans
+    std::vector<NearItem> items;
+    DevBuf<NearItem> d_items;
+    std::vector<LeafPlan> leaves;
+    DevBuf<LeafPlan> d_leaves;
+    int64_t part_elems = 0;
+    int near_rows_per_group = 256;
+    std::vector<NodeLevel> levels;             // index = level
+    DevBuf<int32_t> d_heaps;                   // heap ids per level, concatenated
+    std::vector<int64_t> heaps_off;            // per level
+    DevBuf<int32_t> d_rank, d_ncand;
+    DevBuf<int64_t> d_skoff, d_poff, d_far_block_off;
+    DevBuf<int32_t> d_far_cols;
+    // normalisation (tree order)
+    DevBuf<double> q, d, c;
+    // workspaces of the product
+    int ws_nrhs = 0;
+    DevBuf<char> w_tree, u_tree, skw, sku, part;
+    double seconds_compress = 0.0;
+    size_t footprint() const;
+};
+
+// compression (compress.hip)
+void compress_operator(Op& op, const void* X, int x_on_device, hipStream_t s);
+// evaluation (evaluate.hip)
+void build_eval_plan(Op& op, hipStream_t s);
+void normalise_degrees(Op& op, hipStream_t s);
+void convert_eval_precision(Op& op, hipStream_t s);
+void apply(Op& op, int normalised, bool exact64, const double* x, double* y, int nrhs, hipStream_t s);
+// eigensolver (lanczos.hip)
+hdm_status lanczos_eigs(Op& op, int r, double tol, int block, int max_basis, uint64_t seed, double* evals,
+                        double* evecs, hdm_eig_info_t* info, hipStream_t s);
+
+}  // namespace hdm

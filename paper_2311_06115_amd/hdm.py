@@ -1,0 +1,287 @@
+"""ctypes binding of libhdm (include/hdm.h): argument marshalling only.
+
+Every step of the computation runs in the HIP library; torch supplies device
+memory and the current stream.  Loading fails loudly when libhdm.so has not been
+built: there is no other code path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhdm.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "hdm.h")
+
+F64, F32, BF16, F16, U8 = 0, 1, 2, 3, 4
+PREC = {"f64": F64, "f32": F32, "bf16": BF16, "f16": F16}
+STATUS = {0: "HDM_OK", 1: "HDM_EINVAL", 2: "HDM_ENOMEM", 3: "HDM_EDEVICE", 4: "HDM_ENOCONV", 5: "HDM_EBUSY",
+          6: "HDM_ECANCELLED", 7: "HDM_EINTERNAL", 8: "HDM_ENUMERIC"}
+
+
+class HdmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Params(C.Structure):
+    _fields_ = [("n", C.c_int64), ("dim", C.c_int32), ("x_dtype", C.c_int32), ("eps", C.c_double),
+                ("alpha", C.c_double), ("leaf_m", C.c_int32), ("max_rank_s", C.c_int32), ("tau", C.c_double),
+                ("knn_k", C.c_int32), ("knn_iters", C.c_int32), ("budget", C.c_double), ("near_prec", C.c_int32),
+                ("far_prec", C.c_int32), ("seed", C.c_uint64)]
+
+
+class OpStats(C.Structure):
+    _fields_ = [("n", C.c_int64), ("dim", C.c_int32), ("depth", C.c_int32), ("leaves", C.c_int32),
+                ("knn_k", C.c_int32), ("max_rank", C.c_int32), ("min_leaf_rank", C.c_int32),
+                ("mean_leaf_rank", C.c_double), ("near_pairs", C.c_int64), ("far_pairs", C.c_int64),
+                ("bytes_near", C.c_int64), ("bytes_far", C.c_int64), ("bytes_p", C.c_int64),
+                ("bytes_total", C.c_int64), ("algo_bytes_matvec", C.c_int64), ("flops_matvec", C.c_int64),
+                ("seconds_compress", C.c_double)]
+
+
+class EigInfo(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("matvecs", C.c_int32), ("converged", C.c_int32),
+                ("max_rel_resid", C.c_double), ("seconds", C.c_double)]
+
+
+class ServerCfg(C.Structure):
+    _fields_ = [("max_slots", C.c_int32), ("mem_budget_bytes", C.c_size_t)]
+
+
+class Request(C.Structure):
+    _fields_ = [("X", C.c_void_p), ("params", Params), ("r", C.c_int32), ("rel_resid_tol", C.c_double),
+                ("max_basis", C.c_int32), ("arrival_s", C.c_double)]
+
+
+class Result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("r", C.c_int32), ("evals", C.c_double * 64), ("latency_s", C.c_double),
+                ("service_s", C.c_double), ("iters", C.c_int32), ("x_released", C.c_int32)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("admitted", C.c_int64), ("completed", C.c_int64),
+                ("rejected", C.c_int64), ("cancelled", C.c_int64), ("solves_per_s", C.c_double),
+                ("p50_latency_s", C.c_double), ("p99_latency_s", C.c_double), ("peak_resident_bytes", C.c_int64),
+                ("shared_launches", C.c_int64)]
+
+
+_lib = None
+
+
+def declared_symbols():
+    """Entry points declared in include/hdm.h."""
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(hdm_[a-z_0-9]+)\s*\(", text)))
+
+
+def lib():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built: run paper_2311_06115_amd.build.build()")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, f64, st = C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_int
+    sig = {
+        "hdm_last_error": (C.c_char_p, []),
+        "hdm_version": (C.c_char_p, []),
+        "hdm_params_default": (None, [C.POINTER(Params)]),
+        "hdm_ctx_create": (st, [C.c_int, C.c_size_t, C.POINTER(vp)]),
+        "hdm_ctx_destroy": (st, [vp]),
+        "hdm_compress": (st, [vp, vp, C.c_int, C.POINTER(Params), vp, C.POINTER(vp)]),
+        "hdm_op_destroy": (st, [vp]),
+        "hdm_op_stats": (st, [vp, C.POINTER(OpStats)]),
+        "hdm_op_perm": (st, [vp, vp]),
+        "hdm_op_knn": (st, [vp, vp, vp]),
+        "hdm_op_lists": (st, [vp, vp, vp, C.POINTER(i64), vp, vp, C.POINTER(i64)]),
+        "hdm_op_ranks": (st, [vp, vp, vp, vp]),
+        "hdm_op_node": (st, [vp, i64, vp, vp, vp]),
+        "hdm_op_degrees": (st, [vp, vp, vp, vp]),
+        "hdm_matvec": (st, [vp, C.c_int, vp, vp, i32, vp]),
+        "hdm_eigs": (st, [vp, i32, f64, i32, i32, C.c_uint64, vp, vp, C.POINTER(EigInfo), vp]),
+        "hdm_server_create": (st, [vp, C.POINTER(ServerCfg), C.POINTER(vp)]),
+        "hdm_submit": (st, [vp, C.POINTER(Request), C.POINTER(C.c_uint64)]),
+        "hdm_poll": (st, [vp, C.c_uint64, C.POINTER(Result)]),
+        "hdm_cancel": (st, [vp, C.c_uint64]),
+        "hdm_server_stats": (st, [vp, C.POINTER(ServerStats)]),
+        "hdm_server_destroy": (st, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def check(status):
+    if status != 0:
+        raise HdmError(status, lib().hdm_last_error().decode())
+    return status
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _stream(torch):
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def default_params() -> Params:
+    p = Params()
+    lib().hdm_params_default(C.byref(p))
+    return p
+
+
+class Context:
+    def __init__(self, device: int = 0, budget_bytes: int = 0):
+        self.h = C.c_void_p()
+        check(lib().hdm_ctx_create(device, budget_bytes, C.byref(self.h)))
+        self.device = device
+
+    def close(self):
+        if self.h:
+            lib().hdm_ctx_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_default_ctx = {}
+
+
+def context(device: int = 0) -> Context:
+    if device not in _default_ctx:
+        _default_ctx[device] = Context(device)
+    return _default_ctx[device]
+
+
+def make_params(X, eps, m, s, tau, k, seed, near_prec="f32", far_prec=None, budget=0.05, knn_iters=10) -> Params:
+    p = default_params()
+    p.n, p.dim = int(X.shape[0]), int(X.shape[1])
+    p.x_dtype = U8 if X.dtype == np.uint8 else F64
+    p.eps, p.leaf_m, p.max_rank_s, p.tau, p.knn_k = float(eps), int(m), int(s), float(tau), int(k)
+    p.knn_iters, p.budget, p.seed = int(knn_iters), float(budget), int(seed)
+    p.near_prec = PREC[near_prec]
+    p.far_prec = PREC[far_prec or near_prec]
+    return p
+
+
+class Operator:
+    """Compressed diffusion-maps operator resident in HBM (hdm_op)."""
+
+    def __init__(self, X, eps, m, s, tau, k, seed, near_prec="f32", far_prec=None, budget=0.05, knn_iters=10,
+                 ctx: Context | None = None):
+        import torch
+        self.torch = torch
+        self.ctx = ctx or context(0)
+        if isinstance(X, torch.Tensor):
+            Xh = X.detach().cpu().numpy()
+        else:
+            Xh = np.asarray(X)
+        Xh = np.ascontiguousarray(Xh if Xh.dtype == np.uint8 else Xh.astype(np.float64))
+        self.params = make_params(Xh, eps, m, s, tau, k, seed, near_prec, far_prec, budget, knn_iters)
+        self.n, self.dim, self.k = Xh.shape[0], Xh.shape[1], int(k)
+        self.h = C.c_void_p()
+        check(lib().hdm_compress(self.ctx.h, _ptr(Xh), 0, C.byref(self.params), _stream(torch), C.byref(self.h)))
+        st = self.stats()
+        self.depth, self.L = st.depth, st.leaves
+        self.nnodes = 2 * self.L
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().hdm_op_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- inspection ------------------------------------------------------
+    def stats(self) -> OpStats:
+        st = OpStats()
+        check(lib().hdm_op_stats(self.h, C.byref(st)))
+        return st
+
+    def perm(self):
+        p = np.zeros(self.n, np.int32)
+        check(lib().hdm_op_perm(self.h, _ptr(p)))
+        return p
+
+    def knn(self):
+        idx = np.zeros((self.n, self.k), np.int32)
+        d2 = np.zeros((self.n, self.k), np.float64)
+        check(lib().hdm_op_knn(self.h, _ptr(idx), _ptr(d2)))
+        return idx, d2
+
+    def near(self):
+        nn, fn = C.c_int64(), C.c_int64()
+        check(lib().hdm_op_lists(self.h, None, None, C.byref(nn), None, None, C.byref(fn)))
+        off = np.zeros(self.L + 1, np.int32)
+        idx = np.zeros(max(nn.value, 1), np.int32)
+        check(lib().hdm_op_lists(self.h, _ptr(off), _ptr(idx), C.byref(nn), None, None, C.byref(fn)))
+        return off, idx[:nn.value]
+
+    def far(self):
+        nn, fn = C.c_int64(), C.c_int64()
+        check(lib().hdm_op_lists(self.h, None, None, C.byref(nn), None, None, C.byref(fn)))
+        off = np.zeros(self.nnodes + 1, np.int32)
+        idx = np.zeros(max(fn.value, 1), np.int32)
+        check(lib().hdm_op_lists(self.h, None, None, C.byref(nn), _ptr(off), _ptr(idx), C.byref(fn)))
+        return off, idx[:fn.value]
+
+    def ranks(self):
+        r = np.zeros(self.nnodes, np.int32)
+        c = np.zeros(self.nnodes, np.int32)
+        nr = np.zeros(self.nnodes, np.int32)
+        check(lib().hdm_op_ranks(self.h, _ptr(r), _ptr(c), _ptr(nr)))
+        return r, c, nr
+
+    def node(self, h):
+        r, c, nr = self.ranks()
+        skel = np.zeros(max(r[h], 1), np.int32)
+        rows = np.zeros(max(nr[h], 1), np.int32)
+        P = np.zeros(max(r[h] * c[h], 1), np.float64)
+        check(lib().hdm_op_node(self.h, int(h), _ptr(skel), _ptr(rows), _ptr(P)))
+        return skel[:r[h]], rows[:nr[h]], P[:r[h] * c[h]].reshape(r[h], c[h])
+
+    def degrees(self):
+        q, d, c = (np.zeros(self.n) for _ in range(3))
+        check(lib().hdm_op_degrees(self.h, _ptr(q), _ptr(d), _ptr(c)))
+        return q, d, c
+
+    # ---- products and eigenpairs -------------------------------------------
+    def matvec(self, x, normalised: bool = False):
+        """y = K~ x (or S~ x); x: float64 cuda tensor (n,) or (n, nrhs)."""
+        torch = self.torch
+        x = x.to(dtype=torch.float64)
+        vec = x.dim() == 1
+        X = x.reshape(self.n, -1).t().contiguous()   # column-major n x nrhs
+        Y = torch.empty_like(X)
+        check(lib().hdm_matvec(self.h, int(normalised), C.c_void_p(X.data_ptr()), C.c_void_p(Y.data_ptr()),
+                               X.shape[0], _stream(torch)))
+        Y = Y.t()
+        return Y[:, 0] if vec else Y
+
+    def eigs(self, r, tol=1e-10, block=1, max_basis=0, seed=0, vectors=True):
+        torch = self.torch
+        evals = np.zeros(r)
+        info = EigInfo()
+        vecs = torch.empty((r, self.n), dtype=torch.float64, device=f"cuda:{self.ctx.device}") if vectors else None
+        st = lib().hdm_eigs(self.h, int(r), float(tol), int(block), int(max_basis), int(seed), _ptr(evals),
+                            C.c_void_p(vecs.data_ptr()) if vectors else None, C.byref(info), _stream(torch))
+        if st not in (0, 4):
+            check(st)
+        return evals, (vecs.t() if vectors else None), info, st

@@ -1,0 +1,210 @@
+"""Parity of the HIP path (through the C ABI) with the oracle on the same seeded inputs.
+
+* tree permutation, neighbour lists, interaction lists, ranks and skeletons:
+  bit-exact against the oracle's CPU build of the same algorithm;
+* interpolation matrices and float64 products: relative 1e-10 / 1e-12;
+* reduced-precision products: within the rounding bound of the tile format;
+* eigenvalues: against the oracle's Lanczos on the same compressed operator,
+  and reported against the dense float64 operator.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import dense as D
+from oracle import diffusion as DF
+from oracle import hmatrix as HM
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _hdm():
+    from paper_2311_06115_amd import hdm
+    return hdm
+
+
+CASES = {
+    # name: (points, eps, m, s, tau, k, seed, budget)
+    "scurve-2k": None,
+    "scurve-ragged-1537": "ragged",
+    "mnist-2k": "mnist",
+    "gauss6-3k": "gauss6",
+}
+
+
+def _case(name):
+    if name == "scurve-2k":
+        cfg = synth.get_config("scurve-2k")
+        X, eps = synth.configs.make_inputs(cfg)
+        return X, eps, cfg["m"], cfg["s"], cfg["tau"], cfg["k"], cfg["seed"], 0.05
+    if name == "scurve-ragged-1537":
+        X, _ = synth.s_curve(1537, 9)
+        return X, synth.median_sq_dist_eps(X, 9), 100, 40, 1e-5, 16, 9, 0.05
+    if name == "mnist-2k":
+        X, _ = synth.mnist_shaped(2048, 2)
+        return X, synth.median_sq_dist_eps(X, 2), 128, 64, 1e-4, 16, 2, 0.05
+    if name == "gauss6-3k":
+        X = synth.gaussian_cloud(3000, 5)
+        return X, synth.median_sq_dist_eps(X, 5), 200, 100, 1e-3, 24, 5, 0.1
+    raise KeyError(name)
+
+
+_cache = {}
+
+
+def build_pair(name, prec="f64"):
+    key = (name, prec)
+    if key not in _cache:
+        X, eps, m, s, tau, k, seed, budget = _case(name)
+        print(f"[gpu] compress {name} prec={prec} n={X.shape[0]}", flush=True)
+        op = _hdm().Operator(X, eps, m, s, tau, k, seed, near_prec=prec, budget=budget)
+        if (name, "oracle") not in _cache:
+            _cache[(name, "oracle")] = HM.HMatrix(X, eps, m, s, tau, k, seed, budget=budget)
+        _cache[key] = (X, eps, op, _cache[(name, "oracle")])
+    return _cache[key]
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_tree_and_neighbours_bit_exact(name):
+    X, eps, op, H = build_pair(name)
+    assert np.array_equal(op.perm(), H.perm())
+    gi, gd = op.knn()
+    oi, od = H.knn()
+    assert np.array_equal(gi, oi)
+    assert np.array_equal(gd, od)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_lists_ranks_skeletons_exact(name):
+    X, eps, op, H = build_pair(name)
+    for a, b in zip(op.near(), H.near()):
+        assert np.array_equal(a, b)
+    for a, b in zip(op.far(), H.far()):
+        assert np.array_equal(a, b)
+    for a, b in zip(op.ranks(), H.ranks()):
+        assert np.array_equal(a[2:], b[2:])
+    r, c, nr = H.ranks()
+    for h in range(2, H.nnodes):
+        gs, grows, gP = op.node(h)
+        os_, orows, oP = H.node(h)
+        assert np.array_equal(grows, orows), h
+        assert np.array_equal(gs, os_), h
+        if oP.size:
+            assert np.max(np.abs(gP - oP)) <= 1e-10 * max(1.0, np.max(np.abs(oP))), h
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_float64_product_matches_oracle(name):
+    X, eps, op, H = build_pair(name)
+    rng = np.random.default_rng(11)
+    W = rng.standard_normal((X.shape[0], 3))
+    U = op.matvec(torch.from_numpy(W).cuda()).cpu().numpy()
+    R = H.matvec(W)
+    for c in range(3):
+        assert np.linalg.norm(U[:, c] - R[:, c]) <= 1e-12 * np.linalg.norm(R[:, c])
+
+
+@pytest.mark.parametrize("name", ["scurve-2k", "mnist-2k"])
+def test_degrees_and_normalised_product(name):
+    X, eps, op, H = build_pair(name)
+    q, d, c = op.degrees()
+    oq, od, oc = DF.degrees(H.matvec, X.shape[0])
+    np.testing.assert_allclose(q, oq, rtol=1e-12)
+    np.testing.assert_allclose(d, od, rtol=1e-12)
+    np.testing.assert_allclose(c, oc, rtol=1e-12)
+    w = np.random.default_rng(12).standard_normal(X.shape[0])
+    u = op.matvec(torch.from_numpy(w).cuda(), normalised=True).cpu().numpy()
+    ref = oc * H.matvec(oc * w)
+    assert np.linalg.norm(u - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+# tile-format bounds on the relative error of one product: unit roundoff of the
+# tile format (values in (0, 1]) plus float32 rounding of the vectors and sums
+PREC_TOL = {"f32": 2e-6, "f16": 2e-3, "bf16": 1.5e-2}
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("name", ["scurve-2k", "mnist-2k", "scurve-ragged-1537"])
+def test_reduced_precision_product(name, prec):
+    X, eps, op, H = build_pair(name, prec)
+    rng = np.random.default_rng(13)
+    w = rng.standard_normal(X.shape[0])
+    u = op.matvec(torch.from_numpy(w).cuda()).cpu().numpy()
+    ref = H.matvec(w)
+    assert np.linalg.norm(u - ref) / np.linalg.norm(ref) <= PREC_TOL[prec]
+    # the structure does not depend on the tile precision
+    assert np.array_equal(op.perm(), H.perm())
+
+
+def test_compression_error_against_dense_within_ten_tau():
+    X, eps, op, H = build_pair("scurve-2k")
+    W = D.kernel_matrix(X, eps)
+    rng = np.random.default_rng(14)
+    for _ in range(3):
+        w = rng.standard_normal(X.shape[0])
+        u = op.matvec(torch.from_numpy(w).cuda()).cpu().numpy()
+        ref = W @ w
+        assert np.linalg.norm(u - ref) / np.linalg.norm(ref) <= 10 * 1e-5
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-10), ("f32", 1e-6)])
+def test_eigenvalues_match_oracle(prec, tol):
+    X, eps, op, H = build_pair("scurve-2k", prec)
+    ev, vecs, info, st = op.eigs(10, tol=1e-10)
+    assert st == 0 and info.converged
+    th, ph, _ = DF.eigs(H.matvec, X.shape[0], 10, tol=1e-12)
+    rel = np.abs(ev - th) / np.abs(th)
+    print(f"[gpu] {prec} eig rel err vs oracle K~: {rel.max():.2e}; steps {info.iters}")
+    assert rel.max() <= tol
+    V = vecs.cpu().numpy()
+    for c in range(6):
+        assert abs(abs(V[:, c] @ ph[:, c]) - 1.0) <= 1e-6
+    gold = json.load(open(os.path.join(HERE, "golden", "eigs_scurve-2k.json")))
+    dense = np.array(gold["dense_eigenvalues"])
+    print(f"[gpu] {prec} eig rel err vs dense: {np.max(np.abs(ev - dense) / dense):.2e}")
+
+
+def test_top_eigenpair_closed_form_on_gpu():
+    X, eps, op, H = build_pair("mnist-2k", "f64")
+    ev, vecs, info, st = op.eigs(3, tol=1e-11)
+    q, d, c = op.degrees()
+    assert abs(ev[0] - 1.0) < 1e-10
+    want = np.sqrt(d) / np.linalg.norm(np.sqrt(d))
+    assert np.linalg.norm(vecs[:, 0].cpu().numpy() - want) < 1e-7
+
+
+def test_repeat_runs_are_bit_identical():
+    X, eps, op, H = build_pair("scurve-2k", "f32")
+    w = torch.from_numpy(np.random.default_rng(15).standard_normal(X.shape[0])).cuda()
+    a = op.matvec(w).cpu().numpy()
+    b = op.matvec(w).cpu().numpy()
+    assert np.array_equal(a, b)
+    X2, eps2, m, s, tau, k, seed, budget = _case("scurve-2k")
+    op2 = _hdm().Operator(X2, eps2, m, s, tau, k, seed, near_prec="f32", budget=budget)
+    assert np.array_equal(op2.perm(), op.perm())
+    assert np.array_equal(op2.matvec(w).cpu().numpy(), a)
+
+
+def test_invalid_inputs_are_rejected():
+    hdm = _hdm()
+    X, _ = synth.s_curve(600, 1)
+    bad = X.copy()
+    bad[5, 1] = np.nan
+    with pytest.raises(hdm.HdmError) as e:
+        hdm.Operator(bad, 1.0, 64, 16, 1e-5, 8, 0)
+    assert e.value.status == 1
+    for kw in [dict(eps=0.0), dict(eps=-1.0), dict(k=80), dict(s=0), dict(m=1)]:
+        args = dict(X=X, eps=1.0, m=64, s=16, tau=1e-5, k=8, seed=0)
+        args.update(kw)
+        with pytest.raises(hdm.HdmError) as e:
+            hdm.Operator(**args)
+        assert e.value.status == 1
+    # leaves must hold more than k points
+    with pytest.raises(hdm.HdmError):
+        hdm.Operator(X, 1.0, 20, 16, 1e-5, 32, 0)
