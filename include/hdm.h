@@ -80,6 +80,7 @@ typedef struct {
     int64_t near_pairs, far_pairs;
     int64_t bytes_near, bytes_far, bytes_p, bytes_total;  /* resident operator bytes in HBM */
     int64_t algo_bytes_matvec;   /* bytes one single-vector product must move (tiles once + vectors) */
+    int64_t algo_bytes_near;     /* of which the near field: unpadded near tiles + its input and output vectors */
     int64_t flops_matvec;        /* 2 x multiply-adds of one single-vector product */
     double seconds_compress;     /* wall time of hdm_compress */
 } hdm_op_stats_t;
@@ -92,6 +93,25 @@ typedef struct {
     double seconds;
 } hdm_eig_info_t;
 
+/* Phases timed by the context profiler (hdm_ctx_profile). */
+typedef enum {
+    HDM_PHASE_PREP = 0,      /* gather + scale of the input vector into tree order */
+    HDM_PHASE_N2S = 1,       /* upward pass: skeleton weights */
+    HDM_PHASE_S2S = 2,       /* far field between skeletons */
+    HDM_PHASE_S2N = 3,       /* downward pass over inner levels */
+    HDM_PHASE_L2L = 4,       /* near field: streams the near tiles */
+    HDM_PHASE_COMBINE = 5,   /* near partial sums + leaf downward pass + scatter */
+    HDM_PHASE_ORTHO = 6,     /* Lanczos reorthogonalisation and norms */
+    HDM_PHASE_TRIDIAG = 7,   /* tridiagonal eigensolve */
+    HDM_PHASE_COMPRESS = 8,  /* whole compression (one interval per hdm_compress) */
+    HDM_PHASE_COUNT = 9
+} hdm_phase;
+
+typedef struct {
+    int64_t launches[HDM_PHASE_COUNT];  /* intervals recorded per phase */
+    double ms[HDM_PHASE_COUNT];         /* summed GPU time per phase (HIP events on the launch stream) */
+} hdm_phase_times_t;
+
 /* ---- context -------------------------------------------------------------- */
 /* device: HIP ordinal.  hbm_budget_bytes: cap on operator memory (0 = no cap). */
 hdm_status hdm_ctx_create(int device, size_t hbm_budget_bytes, hdm_ctx *out);
@@ -100,6 +120,12 @@ hdm_status hdm_ctx_destroy(hdm_ctx ctx);
 const char *hdm_last_error(void);
 /* Version string of the library. */
 const char *hdm_version(void);
+/* enable = 1 clears the per-phase totals and starts recording a pair of HIP
+ * events around every phase launched through this context; enable = 0 stops. */
+hdm_status hdm_ctx_profile(hdm_ctx ctx, int enable);
+/* Synchronises the recorded events and returns the per-phase totals since the
+ * last hdm_ctx_profile(ctx, 1). */
+hdm_status hdm_ctx_phase_times(hdm_ctx ctx, hdm_phase_times_t *out);
 
 /* ---- compression (Sec. 1.2 "compressed once"; Eq. (3)) ---------------------
  * Builds the kernel-space ball tree, the randomized-tree neighbour lists, the

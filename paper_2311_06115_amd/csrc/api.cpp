@@ -7,6 +7,52 @@
 
 #include "op.hpp"
 
+namespace hdm {
+
+hipEvent_t Profiler::take() {
+    if (used == pool.size()) {
+        hipEvent_t e;
+        HDM_HIP(hipEventCreate(&e));
+        pool.push_back(e);
+    }
+    return pool[used++];
+}
+
+void Profiler::begin(int phase, hipStream_t s, size_t& slot) {
+    const size_t a = used;
+    HDM_HIP(hipEventRecord(take(), s));
+    marks.push_back(Mark{phase, a, SIZE_MAX});
+    slot = marks.size() - 1;
+}
+
+void Profiler::end(size_t slot, hipStream_t s) noexcept {
+    if (used == pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return;
+        pool.push_back(e);
+    }
+    const size_t b = used++;
+    if (hipEventRecord(pool[b], s) == hipSuccess) marks[slot].b = b;
+}
+
+void Profiler::totals(int64_t* launches, double* ms) {
+    for (int p = 0; p < HDM_PHASE_COUNT; ++p) { launches[p] = 0; ms[p] = 0.0; }
+    for (const Mark& m : marks) {
+        if (m.b == SIZE_MAX || m.phase < 0 || m.phase >= HDM_PHASE_COUNT) continue;
+        HDM_HIP(hipEventSynchronize(pool[m.b]));
+        float t = 0.0f;
+        HDM_HIP(hipEventElapsedTime(&t, pool[m.a], pool[m.b]));
+        launches[m.phase] += 1;
+        ms[m.phase] += t;
+    }
+}
+
+Profiler::~Profiler() {
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+}
+
+}  // namespace hdm
+
 struct hdm_ctx_s : hdm::Ctx {};
 struct hdm_op_s : hdm::Op {};
 
@@ -59,7 +105,7 @@ void validate(const hdm_params& p) {
     while ((p.n + (int64_t(1) << depth) - 1) / (int64_t(1) << depth) > p.leaf_m) ++depth;
     if (depth > 16) fail(HDM_EINVAL, "tree deeper than 16 levels: raise leaf_m");
     if ((p.n >> depth) <= p.knn_k) fail(HDM_EINVAL, "every leaf must hold more than knn_k points");
-    if (((p.n + (int64_t(1) << depth) - 1) >> depth) > 4096) fail(HDM_EINVAL, "leaf_m must be <= 4096");
+    if (((p.n + (int64_t(1) << depth) - 1) >> depth) > 2048) fail(HDM_EINVAL, "leaves must hold <= 2048 points");
 }
 
 void set_device(int dev) { HDM_HIP(hipSetDevice(dev)); }
@@ -109,6 +155,28 @@ hdm_status hdm_ctx_destroy(hdm_ctx ctx) {
     });
 }
 
+hdm_status hdm_ctx_profile(hdm_ctx ctx, int enable) {
+    return guarded([&] {
+        HDM_CHECK(ctx, HDM_EINVAL, "NULL context");
+        set_device(ctx->device);
+        if (enable) {
+            HDM_HIP(hipDeviceSynchronize());
+            ctx->prof.reset();
+        }
+        ctx->prof.on = enable != 0;
+        return HDM_OK;
+    });
+}
+
+hdm_status hdm_ctx_phase_times(hdm_ctx ctx, hdm_phase_times_t* out) {
+    return guarded([&] {
+        HDM_CHECK(ctx && out, HDM_EINVAL, "NULL argument");
+        set_device(ctx->device);
+        ctx->prof.totals(out->launches, out->ms);
+        return HDM_OK;
+    });
+}
+
 hdm_status hdm_compress(hdm_ctx ctx, const void* X, int x_on_device, const hdm_params* params, void* stream,
                         hdm_op* out) {
     return guarded([&] {
@@ -125,10 +193,13 @@ hdm_status hdm_compress(hdm_ctx ctx, const void* X, int x_on_device, const hdm_p
             for (int64_t i = 0; i < cnt; ++i)
                 HDM_CHECK(std::isfinite(x[i]), HDM_EINVAL, "points contain NaN or Inf");
         }
-        hdm::compress_operator(*op, X, x_on_device, s);
-        hdm::build_eval_plan(*op, s);
-        hdm::normalise_degrees(*op, s);
-        hdm::convert_eval_precision(*op, s);
+        {
+            hdm::PhaseScope ph(ctx, HDM_PHASE_COMPRESS, s);
+            hdm::compress_operator(*op, X, x_on_device, s);
+            hdm::build_eval_plan(*op, s);
+            hdm::normalise_degrees(*op, s);
+            hdm::convert_eval_precision(*op, s);
+        }
         HDM_HIP(hipStreamSynchronize(s));
         const size_t fp = op->footprint();
         HDM_CHECK(ctx->budget == 0 || ctx->resident + fp <= ctx->budget, HDM_ENOMEM,
@@ -187,6 +258,7 @@ hdm_status hdm_op_stats(hdm_op op, hdm_op_stats_t* out) {
         const size_t ev = op->prm.near_prec == HDM_F64 ? 8 : 4;
         st.algo_bytes_matvec = static_cast<int64_t>(near_alg * en + op->far_elems * ef + 2 * op->np * ep +
                                                      2 * op->n * 8 + 4 * op->nskel * ev);
+        st.algo_bytes_near = static_cast<int64_t>(near_alg * en + 2 * op->n * ev);
         st.flops_matvec = 2 * (near_alg + op->far_elems + 2 * op->np);
         st.seconds_compress = op->seconds_compress;
         *out = st;

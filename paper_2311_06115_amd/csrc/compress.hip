@@ -70,35 +70,34 @@ __global__ void k_iota(int32_t* p, int64_t n) {
 }
 
 // Floyd's sampling of min(n, 64) distinct positions of each node, ascending.
-__global__ void k_tree_sample(int lvl, const int64_t* start, const int64_t* size, uint64_t seed, int32_t* samp,
-                              int32_t* nsamp) {
-    const int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-    const int64_t nodes = int64_t(1) << lvl;
-    if (t >= nodes) return;
-    const int64_t h = nodes + t;
+// One wave per node: draws stay sequential (Floyd's rule depends on earlier
+// picks); lane q holds pick q, membership is a ballot, and the final order is
+// each pick's rank among the 64.
+__global__ void __launch_bounds__(64) k_tree_sample(int lvl, const int64_t* start, const int64_t* size, uint64_t seed,
+                                                    int32_t* samp, int32_t* nsamp) {
+    const int64_t t = blockIdx.x;
+    const int64_t h = (int64_t(1) << lvl) + t;
     const int64_t n = size[h];
+    const int lane = threadIdx.x;
     int32_t* out = samp + t * kSample;
     if (n <= kSample) {
-        for (int q = 0; q < n; ++q) out[q] = static_cast<int32_t>(start[h] + q);
-        nsamp[t] = static_cast<int32_t>(n);
+        if (lane < n) out[lane] = static_cast<int32_t>(start[h] + lane);
+        if (lane == 0) nsamp[t] = static_cast<int32_t>(n);
         return;
     }
-    int cnt = 0;
-    for (int64_t j = n - kSample; j < n; ++j) {
-        const int64_t r = below(philox_draw(seed, kTreeSample, static_cast<uint32_t>(h), 0, static_cast<uint32_t>(j)),
-                                static_cast<uint32_t>(j + 1));
-        bool present = false;
-        for (int q = 0; q < cnt; ++q) present = present || (out[q] == r);
-        out[cnt++] = static_cast<int32_t>(present ? j : r);
+    int32_t mine = -1;   // pick number `lane`
+    for (int q = 0; q < kSample; ++q) {
+        const int64_t j = n - kSample + q;
+        const int32_t r = static_cast<int32_t>(
+            below(philox_draw(seed, kTreeSample, static_cast<uint32_t>(h), 0, static_cast<uint32_t>(j)),
+                  static_cast<uint32_t>(j + 1)));
+        const bool present = __ballot(lane < q && mine == r) != 0;
+        if (lane == q) mine = present ? static_cast<int32_t>(j) : r;
     }
-    for (int a = 1; a < cnt; ++a) {
-        const int32_t v = out[a];
-        int b = a - 1;
-        while (b >= 0 && out[b] > v) { out[b + 1] = out[b]; --b; }
-        out[b + 1] = v;
-    }
-    for (int q = 0; q < cnt; ++q) out[q] = static_cast<int32_t>(start[h] + out[q]);
-    nsamp[t] = cnt;
+    int rank = 0;
+    for (int q = 0; q < kSample; ++q) rank += __shfl(mine, q, 64) < mine;
+    out[rank] = static_cast<int32_t>(start[h] + mine);
+    if (lane == 0) nsamp[t] = kSample;
 }
 
 // sum over the node's sample of K(x_i, x_j), in ascending sample position
@@ -192,86 +191,105 @@ __global__ void k_tree_key(int lvl, int64_t n, const int64_t* start, const int32
     key[pos] = mode == 0 ? kval(P, i, q) - kval(P, i, p) : sqd(P, i, p) - sqd(P, i, q);
 }
 
-// left[pos] = 1 when fewer than floor(n/2) members of the node precede it in (key, index) order
-__global__ void k_tree_rank(int lvl, int64_t n, const int64_t* start, const int64_t* size, const int32_t* perm,
-                            const double* key, uint8_t* left) {
-    __shared__ double sk[kBlock];
-    __shared__ int32_t si[kBlock];
-    const int64_t first = blockIdx.x * static_cast<int64_t>(kBlock);
-    const int64_t last = min(n, first + kBlock) - 1;
-    const int64_t hlo = node_of(first, lvl, start), hhi = node_of(last, lvl, start);
-    const int64_t blo = start[hlo], bhi = start[hhi] + size[hhi];
-    const int64_t pos = first + threadIdx.x;
-    const bool valid = pos <= last;
-    int64_t lo = 0, hi = 0, half = 0;
-    double ki = 0.0;
-    int32_t ii = 0;
-    if (valid) {
-        const int64_t h = node_of(pos, lvl, start);
-        lo = start[h];
-        hi = lo + size[h];
-        half = size[h] / 2;
-        ki = key[pos];
-        ii = perm[pos];
+// Exclusive prefix count of a 0/1 flag over the workgroup in thread order
+// (wave ballots + one shared-memory pass); *total receives the workgroup's count.
+__device__ inline int wg_flag_scan(bool f, int* wsum, int* total) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const uint64_t bal = __ballot(f);
+    const int in_wave = __popcll(bal & ((1ull << lane) - 1ull));
+    if (lane == 0) wsum[wv] = __popcll(bal);
+    __syncthreads();
+    int before = 0, tot = 0;
+    for (int w = 0; w < nw; ++w) {
+        const int c = wsum[w];
+        before += w < wv ? c : 0;
+        tot += c;
     }
-    int64_t cnt = 0;
-    for (int64_t j0 = blo; j0 < bhi; j0 += kBlock) {
-        const int64_t jj = j0 + threadIdx.x;
-        if (jj < bhi) { sk[threadIdx.x] = key[jj]; si[threadIdx.x] = perm[jj]; }
+    __syncthreads();
+    *total = tot;
+    return before + in_wave;
+}
+
+// order-preserving image of a float64 key as an unsigned integer (+0 for zero)
+__device__ inline uint64_t orderable(double x) {
+    if (x == 0.0) x = 0.0;
+    const uint64_t u = static_cast<uint64_t>(__double_as_longlong(x));
+    return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
+}
+
+// Median cut of every node, one workgroup per node.  The floor(n/2) members
+// with the smallest (key, position) go left; positions follow ascending
+// original index, so this is the (key, index) order.  The threshold is found by
+// radix selection (eight 8-bit digits of the key image, ties by position), then
+// the node is partitioned stably: both halves keep ascending original index.
+constexpr int kSplitBlock = 1024;
+__global__ void __launch_bounds__(kSplitBlock) k_tree_split(int lvl, const int64_t* start, const int64_t* size,
+                                                            const int32_t* perm, const double* key, int32_t* out) {
+    __shared__ int hist[256];
+    __shared__ int wsum[kSplitBlock / 64];
+    __shared__ uint64_t s_prefix;
+    __shared__ int s_k;
+    const int64_t h = (int64_t(1) << lvl) + blockIdx.x;
+    const int64_t s0 = start[h];
+    const int n = static_cast<int>(size[h]);
+    const int nl = n / 2;
+    if (threadIdx.x == 0) { s_prefix = 0; s_k = nl; }
+    uint64_t mask = 0;
+    for (int shift = 56; shift >= 0; shift -= 8) {
+        for (int b = threadIdx.x; b < 256; b += blockDim.x) hist[b] = 0;
         __syncthreads();
-        const int64_t m = min<int64_t>(kBlock, bhi - j0);
-        if (valid) {
-            const int64_t u0 = max<int64_t>(0, lo - j0), u1 = min<int64_t>(m, hi - j0);
-            for (int64_t u = u0; u < u1; ++u) {
-                const double kj = sk[u];
-                cnt += (kj < ki) || (kj == ki && si[u] < ii);
+        const uint64_t prefix = s_prefix;
+        for (int a = threadIdx.x; a < n; a += blockDim.x) {
+            const uint64_t u = orderable(key[s0 + a]);
+            if ((u & mask) == prefix) atomicAdd(&hist[(u >> shift) & 255u], 1);
+        }
+        __syncthreads();
+        if (threadIdx.x < 64) {
+            // lane l owns bins 4l..4l+3; an inclusive scan of their sums locates the bin of rank k
+            const int lane = threadIdx.x;
+            const int h0 = hist[4 * lane], h1 = hist[4 * lane + 1], h2 = hist[4 * lane + 2], h3 = hist[4 * lane + 3];
+            const int mine = h0 + h1 + h2 + h3;
+            int incl = mine;
+            for (int off = 1; off < 64; off <<= 1) {
+                const int o = __shfl_up(incl, off, 64);
+                if (lane >= off) incl += o;
+            }
+            const int excl = incl - mine;
+            const int k = s_k;
+            if (excl <= k && k < incl) {
+                int kk = k - excl, b = 4 * lane;
+                if (kk >= h0) { kk -= h0; ++b;
+                    if (kk >= h1) { kk -= h1; ++b;
+                        if (kk >= h2) { kk -= h2; ++b; } } }
+                s_k = kk;
+                s_prefix = prefix | (static_cast<uint64_t>(b) << shift);
             }
         }
+        mask |= 0xFFull << shift;
         __syncthreads();
     }
-    if (valid) left[pos] = cnt < half ? 1 : 0;
-}
-
-// inclusive block scan of 0/1 flags (Hillis-Steele in shared memory)
-__device__ inline int block_scan(int v, int* buf) {
-    const int tid = threadIdx.x;
-    buf[tid] = v;
-    __syncthreads();
-    for (int off = 1; off < static_cast<int>(blockDim.x); off <<= 1) {
-        const int a = tid >= off ? buf[tid - off] : 0;
-        __syncthreads();
-        buf[tid] += a;
-        __syncthreads();
-    }
-    const int r = buf[tid];
-    __syncthreads();
-    return r;
-}
-
-// stable partition of every node: left members first, both halves keep their order
-__global__ void k_tree_partition(int lvl, const int64_t* start, const int64_t* size, const int32_t* perm,
-                                 const uint8_t* left, int32_t* out) {
-    __shared__ int buf[kBlock];
-    __shared__ int tot;
-    const int64_t h = (int64_t(1) << lvl) + blockIdx.x;
-    const int64_t s0 = start[h], n = size[h], nl = n / 2;
-    int64_t run_l = 0, run_r = 0;
-    for (int64_t base = 0; base < n; base += kBlock) {
-        const int64_t a = base + threadIdx.x;
+    // the threshold is the (s_k)-th member (position order) whose key image equals s_prefix
+    const uint64_t ustar = s_prefix;
+    const int kstar = s_k;
+    int run_eq = 0, run_l = 0, run_r = 0;
+    for (int base = 0; base < n; base += blockDim.x) {
+        const int a = base + threadIdx.x;
         const bool valid = a < n;
-        const int f = valid ? left[s0 + a] : 0;
-        const int incl = block_scan(f, buf);
-        if (threadIdx.x == blockDim.x - 1) tot = incl;
-        __syncthreads();
+        const uint64_t u = valid ? orderable(key[s0 + a]) : 0;
+        const bool eq = valid && u == ustar;
+        int tot_eq = 0, tot_l = 0;
+        const int eqrank = run_eq + wg_flag_scan(eq, wsum, &tot_eq);
+        const bool left = valid && (u < ustar || (eq && eqrank < kstar));
+        const int lpre = wg_flag_scan(left, wsum, &tot_l);
         if (valid) {
-            const int lf = incl - f;
-            const int64_t np = f ? s0 + run_l + lf : s0 + nl + run_r + (threadIdx.x - lf);
+            const int rpre = threadIdx.x - lpre;
+            const int64_t np = left ? s0 + run_l + lpre : s0 + nl + run_r + rpre;
             out[np] = perm[s0 + a];
         }
-        const int64_t cvalid = min<int64_t>(kBlock, n - base);
-        run_l += tot;
-        run_r += cvalid - tot;
-        __syncthreads();
+        const int cvalid = min(static_cast<int>(blockDim.x), n - base);
+        run_eq += tot_eq;
+        run_l += tot_l;
+        run_r += cvalid - tot_l;
     }
 }
 
@@ -283,42 +301,87 @@ __global__ void k_knn_init(int32_t* idx, double* d2, int64_t cnt) {
     if (i < cnt) { idx[i] = -1; d2[i] = INFINITY; }
 }
 
-__device__ inline void knn_insert(double* ld, int32_t* li, int k, double d, int32_t j) {
-    const double dl = ld[k - 1];
-    const int32_t il = li[k - 1];
-    if (d > dl || (d == dl && il >= 0 && j >= il)) return;
-    for (int t = 0; t < k; ++t)
-        if (li[t] == j) return;
-    int pos = k - 1;
-    while (pos > 0) {
-        const double dp = ld[pos - 1];
-        const int32_t ip = li[pos - 1];
-        if (!(dp > d || (dp == d && (ip > j || ip < 0)))) break;
-        ld[pos] = dp;
-        li[pos] = ip;
-        --pos;
-    }
-    ld[pos] = d;
-    li[pos] = j;
+
+// All pairs inside every leaf, merged into each point's running list of the k
+// smallest (d2, index).  One wave per point: the list lives across lanes 0..k-1
+// (ascending), each lane evaluates a share of the leaf's candidates, and the
+// candidates that beat the current k-th entry are inserted one at a time
+// (duplicate check and insert position by ballot, shift by one lane).  The
+// result is the unique k smallest entries, whatever the insertion order.
+constexpr int kLeafStageDim = 8;
+constexpr int kLeafStageMax = 2048;
+constexpr int kKnnBlock = 1024;
+__device__ inline bool knn_less(double da, int32_t ia, double db, int32_t ib) {
+    // empty slots (index < 0) compare greater than every candidate
+    if (ib < 0) return ia >= 0;
+    if (ia < 0) return false;
+    return da < db || (da == db && ia < ib);
 }
 
-// all pairs inside every leaf, merged into each point's running list
-__global__ void k_knn_leaf(int depth, const int64_t* start, const int64_t* size, const int32_t* perm, Pts P, int k,
-                           int32_t* kidx, double* kd2) {
-    extern __shared__ char smem[];
-    double* ld = reinterpret_cast<double*>(smem) + static_cast<int64_t>(threadIdx.x) * k;
-    int32_t* li = reinterpret_cast<int32_t*>(smem + sizeof(double) * blockDim.x * k) + static_cast<int64_t>(threadIdx.x) * k;
-    const int64_t h = (int64_t(1) << depth) + blockIdx.x;
+__global__ void __launch_bounds__(kKnnBlock) k_knn_leaf(int depth, const int64_t* start, const int64_t* size,
+                                                        const int32_t* perm, Pts P, int k, int stage, int splits,
+                                                        int32_t* kidx, double* kd2) {
+    extern __shared__ double xs[];          // staged coordinates (n x dim) when stage != 0
+    __shared__ int32_t ids[kLeafStageMax];  // staged original indices
+    const int64_t h = (int64_t(1) << depth) + blockIdx.x / splits;
+    const int part = blockIdx.x % splits;
     const int64_t s0 = start[h], n = size[h];
-    for (int64_t a = threadIdx.x; a < n; a += blockDim.x) {
-        const int32_t i = perm[s0 + a];
-        for (int t = 0; t < k; ++t) { ld[t] = kd2[static_cast<int64_t>(i) * k + t]; li[t] = kidx[static_cast<int64_t>(i) * k + t]; }
-        for (int64_t b = 0; b < n; ++b) {
-            if (b == a) continue;
-            const int32_t j = perm[s0 + b];
-            knn_insert(ld, li, k, sqd(P, i, j), j);
+    for (int64_t e = threadIdx.x; e < n && e < kLeafStageMax; e += blockDim.x) ids[e] = perm[s0 + e];
+    if (stage)
+        for (int64_t e = threadIdx.x; e < n * P.dim; e += blockDim.x)
+            xs[e] = P.xf[static_cast<int64_t>(perm[s0 + e / P.dim]) * P.dim + e % P.dim];
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int64_t a = static_cast<int64_t>(part) * nw + wv; a < n; a += static_cast<int64_t>(splits) * nw) {
+        const int32_t i = n <= kLeafStageMax ? ids[a] : perm[s0 + a];
+        double ld = INFINITY;
+        int32_t li = -1;
+        if (lane < k) {
+            ld = kd2[static_cast<int64_t>(i) * k + lane];
+            li = kidx[static_cast<int64_t>(i) * k + lane];
         }
-        for (int t = 0; t < k; ++t) { kd2[static_cast<int64_t>(i) * k + t] = ld[t]; kidx[static_cast<int64_t>(i) * k + t] = li[t]; }
+        for (int64_t b0 = 0; b0 < n; b0 += 64) {
+            const int64_t b = b0 + lane;
+            double d = INFINITY;
+            int32_t j = -1;
+            if (b < n && b != a) {
+                j = n <= kLeafStageMax ? ids[b] : perm[s0 + b];
+                if (stage) {
+                    const double* xa = xs + a * P.dim;
+                    const double* xb = xs + b * P.dim;
+                    double acc = 0.0;
+                    for (int q = 0; q < P.dim; ++q) {
+                        const double tq = xa[q] - xb[q];
+                        acc = acc + tq * tq;
+                    }
+                    d = acc;
+                } else {
+                    d = sqd(P, i, j);
+                }
+            }
+            // candidates that beat the current k-th entry
+            const double dk = __shfl(ld, k - 1, 64);
+            const int32_t ik = __shfl(li, k - 1, 64);
+            uint64_t pend = __ballot(j >= 0 && knn_less(d, j, dk, ik));
+            while (pend) {
+                const int src = __ffsll(static_cast<long long>(pend)) - 1;
+                pend &= pend - 1;
+                const double dc = __shfl(d, src, 64);
+                const int32_t jc = __shfl(j, src, 64);
+                const bool dup = __ballot(lane < k && li == jc) != 0;
+                if (dup) continue;
+                const int pos = __popcll(__ballot(lane < k && knn_less(ld, li, dc, jc)));
+                if (pos >= k) continue;
+                const double up_d = __shfl_up(ld, 1, 64);
+                const int32_t up_i = __shfl_up(li, 1, 64);
+                if (lane == pos) { ld = dc; li = jc; }
+                else if (lane > pos && lane < k) { ld = up_d; li = up_i; }
+            }
+        }
+        if (lane < k) {
+            kd2[static_cast<int64_t>(i) * k + lane] = ld;
+            kidx[static_cast<int64_t>(i) * k + lane] = li;
+        }
     }
 }
 
@@ -410,10 +473,11 @@ __global__ void k_row_count(LevelArgs A) {
 
 // up to half of the rows: most-voted outside neighbours (ties: lower index);
 // the rest: uniform draws from outside the node (or every outside point when
-// that is all there is)
+// that is all there is).  The draws are taken 64 at a time by one wave and
+// accepted in draw order, exactly as a sequential rejection loop would.
 __global__ void k_row_select(LevelArgs A) {
-    __shared__ int buf[kBlock];
-    __shared__ int tot;
+    __shared__ int wsum[kBlock / 64];
+    __shared__ int32_t batch[64];
     const int64_t t = blockIdx.x;
     const int64_t h = (int64_t(1) << A.lvl) + t;
     const int64_t lo = A.start[h], hi = A.start[h] + A.size[h];
@@ -426,15 +490,13 @@ __global__ void k_row_select(LevelArgs A) {
     const int64_t want_nb = want / 2;
     // compaction of {i : cnt[i] > 0} in index order
     int64_t nu = 0;
-    for (int64_t base = 0; base < A.n; base += kBlock) {
+    for (int64_t base = 0; base < A.n; base += blockDim.x) {
         const int64_t i = base + threadIdx.x;
-        const int f = (i < A.n && cnt[i] > 0) ? 1 : 0;
-        const int incl = block_scan(f, buf);
-        if (threadIdx.x == blockDim.x - 1) tot = incl;
-        __syncthreads();
-        if (f) uq[nu + incl - 1] = static_cast<int32_t>(i);
+        const bool f = i < A.n && cnt[i] > 0;
+        int tot = 0;
+        const int pre = wg_flag_scan(f, wsum, &tot);
+        if (f) uq[nu + pre] = static_cast<int32_t>(i);
         nu += tot;
-        __syncthreads();
     }
     // rank by (votes desc, index asc); keep the first want_nb
     for (int64_t u = threadIdx.x; u < nu; u += blockDim.x) {
@@ -451,34 +513,50 @@ __global__ void k_row_select(LevelArgs A) {
         }
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        int64_t nr = nu < want_nb ? nu : want_nb;
-        int32_t st = 0;
-        if (nr < want) {
-            if (want == A.n - A.size[h]) {
-                for (int64_t i = 0; i < A.n && nr < want; ++i) {
-                    const int64_t pi = A.iperm[i];
-                    if (pi >= lo && pi < hi) continue;
-                    if (bits[i >> 5] & (1u << (i & 31))) continue;
-                    rows[nr++] = static_cast<int32_t>(i);
-                    bits[i >> 5] |= 1u << (i & 31);
-                }
-            } else {
-                const uint64_t cap = 64ull * static_cast<uint64_t>(A.n) + 1024ull;
-                uint32_t d = 0;
-                while (nr < want) {
-                    if (static_cast<uint64_t>(d) > cap) { st = 1; break; }
-                    const int32_t i = static_cast<int32_t>(
-                        below(philox_draw(A.seed, kRowFill, static_cast<uint32_t>(h), 0, d), static_cast<uint32_t>(A.n)));
-                    ++d;
-                    const int64_t pi = A.iperm[i];
-                    if (pi >= lo && pi < hi) continue;
-                    if (bits[i >> 5] & (1u << (i & 31))) continue;
-                    rows[nr++] = i;
-                    bits[i >> 5] |= 1u << (i & 31);
-                }
+    int64_t nr = nu < want_nb ? nu : want_nb;
+    int32_t st = 0;
+    if (nr < want && want == A.n - A.size[h]) {
+        // every outside point not chosen yet, ascending index
+        for (int64_t base = 0; base < A.n; base += blockDim.x) {
+            const int64_t i = base + threadIdx.x;
+            bool f = false;
+            if (i < A.n) {
+                const int64_t pi = A.iperm[i];
+                f = !(pi >= lo && pi < hi) && !(bits[i >> 5] & (1u << (i & 31)));
             }
+            int tot = 0;
+            const int pre = wg_flag_scan(f, wsum, &tot);
+            if (f && nr + pre < want) rows[nr + pre] = static_cast<int32_t>(i);
+            nr = min<int64_t>(want, nr + tot);
         }
+    } else if (nr < want && threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        const uint64_t cap = 64ull * static_cast<uint64_t>(A.n) + 1024ull;
+        uint64_t d = 0;
+        while (nr < want) {
+            if (d > cap) { st = 1; break; }
+            const int32_t c = static_cast<int32_t>(below(
+                philox_draw(A.seed, kRowFill, static_cast<uint32_t>(h), 0, static_cast<uint32_t>(d + lane)),
+                static_cast<uint32_t>(A.n)));
+            const int64_t pc = A.iperm[c];
+            const bool valid = !(pc >= lo && pc < hi) && !(bits[c >> 5] & (1u << (c & 31)));
+            batch[lane] = valid ? c : -1;
+            __builtin_amdgcn_wave_barrier();
+            bool dup = false;
+            for (int l = 0; l < lane; ++l) dup = dup || (batch[l] == c);
+            const bool acc = valid && !dup;
+            const uint64_t bal = __ballot(acc);
+            const int pre = __popcll(bal & ((1ull << lane) - 1ull));
+            if (acc && nr + pre < want) {
+                rows[nr + pre] = c;
+                atomicOr(&bits[c >> 5], 1u << (c & 31));
+            }
+            nr = min<int64_t>(want, nr + __popcll(bal));
+            d += 64;
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+    if (threadIdx.x == 0) {
         A.nrows[t] = static_cast<int32_t>(nr);
         A.status[t] = st;
     }
@@ -494,14 +572,36 @@ __global__ void k_block(LevelArgs A, Pts P) {
     A.B[t * static_cast<int64_t>(A.rmax) * A.cmax + e] = kval(P, A.rows[t * A.rmax + r], A.cand[t * A.cmax + c]);
 }
 
+// sum_{i in [i0, i1)} x_i^2 of column c, sequential in i; loads are issued in
+// batches so the chain of additions does not wait on each load
+__device__ inline double col_sumsq(const double* B, int nc, int c, int i0, int i1) {
+    double acc = 0.0;
+    int i = i0;
+    for (; i + 8 <= i1; i += 8) {
+        double x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) x[u] = B[static_cast<int64_t>(i + u) * nc + c];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc = acc + x[u] * x[u];
+    }
+    for (; i < i1; ++i) {
+        const double x = B[static_cast<int64_t>(i) * nc + c];
+        acc = acc + x * x;
+    }
+    return acc;
+}
+
 // Householder QR with column pivoting of B (nr x nc) and the interpolation
 // matrix P = [I, R11^-1 R12] in candidate order.  One workgroup per node, one
 // thread per column; every column norm and dot product is a sequential sum
-// over rows.
+// over rows.  The squared norms that choose the next pivot are accumulated
+// while the reflector is applied (same values, same order as a separate pass).
+constexpr int kMaxCand = 2048;
 __global__ void __launch_bounds__(kBlock) k_pivoted_id(LevelArgs A) {
     __shared__ double sv[kBlock];
     __shared__ int64_t sp[kBlock];
-    __shared__ double hv[1024];   // Householder vector (rows <= 1024)
+    __shared__ double hv[1024];        // Householder vector (rows <= 1024)
+    __shared__ double nsq[kMaxCand];   // remaining squared column norms
     __shared__ double s_vtv, s_alpha, s_r11;
     __shared__ int s_stop;
     const int64_t t = blockIdx.x;
@@ -509,7 +609,10 @@ __global__ void __launch_bounds__(kBlock) k_pivoted_id(LevelArgs A) {
     double* B = A.B + t * static_cast<int64_t>(A.rmax) * A.cmax;
     int32_t* cp = A.cp + t * A.cmax;
     double* Pm = A.Pws + t * static_cast<int64_t>(A.s) * A.cmax;
-    for (int c = threadIdx.x; c < nc; c += blockDim.x) cp[c] = c;
+    for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+        cp[c] = c;
+        nsq[c] = col_sumsq(B, nc, c, 0, nr);
+    }
     int kmax = nr < nc ? nr : nc;
     if (kmax > A.s) kmax = A.s;
     int rank = 0;
@@ -519,12 +622,7 @@ __global__ void __launch_bounds__(kBlock) k_pivoted_id(LevelArgs A) {
         double best = -1.0;
         int64_t bc = INT64_MAX;
         for (int c = j + threadIdx.x; c < nc; c += blockDim.x) {
-            double acc = 0.0;
-            for (int i = j; i < nr; ++i) {
-                const double x = B[static_cast<int64_t>(i) * nc + c];
-                acc = acc + x * x;
-            }
-            const double nrm = sqrt(acc);
+            const double nrm = sqrt(nsq[c]);
             if (nrm > best || (nrm == best && c < bc)) { best = nrm; bc = c; }
         }
         block_argbest(best, bc, false, sv, sp);
@@ -535,7 +633,10 @@ __global__ void __launch_bounds__(kBlock) k_pivoted_id(LevelArgs A) {
                 B[static_cast<int64_t>(i) * nc + j] = B[static_cast<int64_t>(i) * nc + piv];
                 B[static_cast<int64_t>(i) * nc + piv] = x;
             }
-            if (threadIdx.x == 0) { const int32_t x = cp[j]; cp[j] = cp[piv]; cp[piv] = x; }
+            if (threadIdx.x == 0) {
+                const int32_t x = cp[j]; cp[j] = cp[piv]; cp[piv] = x;
+                const double y = nsq[j]; nsq[j] = nsq[piv]; nsq[piv] = y;
+            }
         }
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -559,9 +660,39 @@ __global__ void __launch_bounds__(kBlock) k_pivoted_id(LevelArgs A) {
         const double vtv = s_vtv;
         for (int c = j + 1 + threadIdx.x; c < nc; c += blockDim.x) {
             double dot = 0.0;
-            for (int i = j; i < nr; ++i) dot = dot + hv[i] * B[static_cast<int64_t>(i) * nc + c];
+            int i = j;
+            for (; i + 8 <= nr; i += 8) {
+                double x[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) x[u] = B[static_cast<int64_t>(i + u) * nc + c];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) dot = dot + hv[i + u] * x[u];
+            }
+            for (; i < nr; ++i) dot = dot + hv[i] * B[static_cast<int64_t>(i) * nc + c];
             const double f = (2.0 * dot) / vtv;
-            for (int i = j; i < nr; ++i) B[static_cast<int64_t>(i) * nc + c] = B[static_cast<int64_t>(i) * nc + c] - f * hv[i];
+            {   // the pivot row first (its square is not part of the next norm), then batches
+                const int64_t e = static_cast<int64_t>(j) * nc + c;
+                B[e] = B[e] - f * hv[j];
+            }
+            double acc = 0.0;
+            for (i = j + 1; i + 8 <= nr; i += 8) {
+                double x[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) x[u] = B[static_cast<int64_t>(i + u) * nc + c];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    x[u] = x[u] - f * hv[i + u];
+                    B[static_cast<int64_t>(i + u) * nc + c] = x[u];
+                    acc = acc + x[u] * x[u];
+                }
+            }
+            for (; i < nr; ++i) {
+                const int64_t e = static_cast<int64_t>(i) * nc + c;
+                const double x = B[e] - f * hv[i];
+                B[e] = x;
+                acc = acc + x * x;
+            }
+            nsq[c] = acc;
         }
         __syncthreads();
         for (int i = j + threadIdx.x; i < nr; i += blockDim.x) B[static_cast<int64_t>(i) * nc + j] = (i == j) ? s_alpha : 0.0;
@@ -656,15 +787,15 @@ static void tree_ranges(int64_t n, int depth, std::vector<int64_t>& start, std::
 // one perfect tree of the given depth: ball tree (mode 0) or random-pivot tree (mode 1)
 static void build_tree(Op& op, int mode, int it, DevBuf<int32_t>& perm, DevBuf<int32_t>& tmp, Pts P, hipStream_t s,
                        DevBuf<int32_t>& samp, DevBuf<int32_t>& nsamp, DevBuf<int32_t>& pq, DevBuf<double>& sumk,
-                       DevBuf<double>& key, DevBuf<uint8_t>& left) {
+                       DevBuf<double>& key) {
     const int64_t n = op.n;
     const int gN = ceil_div(n, kBlock);
     hipLaunchKernelGGL(k_iota, dim3(gN), dim3(kBlock), 0, s, perm.get(), n);
     for (int lvl = 0; lvl < op.depth; ++lvl) {
         const int nodes = 1 << lvl;
         if (mode == 0) {
-            hipLaunchKernelGGL(k_tree_sample, dim3(ceil_div(nodes, 64)), dim3(64), 0, s, lvl, op.d_start.get(),
-                               op.d_size.get(), op.prm.seed, samp.get(), nsamp.get());
+            hipLaunchKernelGGL(k_tree_sample, dim3(nodes), dim3(64), 0, s, lvl, op.d_start.get(), op.d_size.get(),
+                               op.prm.seed, samp.get(), nsamp.get());
             hipLaunchKernelGGL(k_tree_sumk, dim3(gN), dim3(kBlock), 0, s, lvl, n, op.d_start.get(), perm.get(),
                                samp.get(), nsamp.get(), P, sumk.get());
             hipLaunchKernelGGL(k_tree_pq, dim3(nodes), dim3(kBlock), 0, s, lvl, op.d_start.get(), op.d_size.get(),
@@ -675,10 +806,8 @@ static void build_tree(Op& op, int mode, int it, DevBuf<int32_t>& perm, DevBuf<i
         }
         hipLaunchKernelGGL(k_tree_key, dim3(gN), dim3(kBlock), 0, s, lvl, n, op.d_start.get(), perm.get(), pq.get(),
                            P, mode, key.get());
-        hipLaunchKernelGGL(k_tree_rank, dim3(gN), dim3(kBlock), 0, s, lvl, n, op.d_start.get(), op.d_size.get(),
-                           perm.get(), key.get(), left.get());
-        hipLaunchKernelGGL(k_tree_partition, dim3(nodes), dim3(kBlock), 0, s, lvl, op.d_start.get(), op.d_size.get(),
-                           perm.get(), left.get(), tmp.get());
+        hipLaunchKernelGGL(k_tree_split, dim3(nodes), dim3(kSplitBlock), 0, s, lvl, op.d_start.get(), op.d_size.get(),
+                           perm.get(), key.get(), tmp.get());
         check_launch("tree level");
         std::swap(perm, tmp);
     }
@@ -768,6 +897,7 @@ static void skeletonize(Op& op, Pts P, hipStream_t s) {
     int64_t leafmax = 0;
     for (int64_t h = op.L; h < 2 * int64_t(op.L); ++h) leafmax = std::max(leafmax, op.size[h]);
     const int cmax = static_cast<int>(std::max<int64_t>(leafmax, 2 * static_cast<int64_t>(smax)));
+    HDM_CHECK(cmax <= kMaxCand, HDM_EINVAL, "leaf size and 2 * max_rank_s must be <= 2048");
     const int rmax = 2 * smax;
     HDM_CHECK(rmax <= 1024, HDM_EINVAL, "max_rank_s must be <= 512");
     // per-level outputs collected on the host side as offsets; data in growing device arrays
@@ -998,8 +1128,7 @@ void compress_operator(Op& op, const void* X, int x_on_device, hipStream_t s) {
     const int64_t n = op.n;
     DevBuf<int32_t> perm(n), tmp(n), samp(static_cast<size_t>(op.L) * kSample), nsamp(op.L), pq(2 * op.L);
     DevBuf<double> sumk(n), key(n);
-    DevBuf<uint8_t> left(n);
-    build_tree(op, 0, 0, perm, tmp, P, s, samp, nsamp, pq, sumk, key, left);
+    build_tree(op, 0, 0, perm, tmp, P, s, samp, nsamp, pq, sumk, key);
     op.perm = std::move(perm);
     op.iperm.alloc(n);
     hipLaunchKernelGGL(k_inverse_perm, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, s, op.perm.get(), op.iperm.get(), n);
@@ -1010,12 +1139,16 @@ void compress_operator(Op& op, const void* X, int x_on_device, hipStream_t s) {
     hipLaunchKernelGGL(k_knn_init, dim3(ceil_div(n * k, kBlock)), dim3(kBlock), 0, s, op.knn_idx.get(), op.knn_d2.get(),
                        n * k);
     DevBuf<int32_t> kperm(n);
-    int threads = kBlock;
-    while (threads > 64 && static_cast<size_t>(threads) * k * 12 > 64 * 1024) threads /= 2;
+    int64_t leafmax = 0;
+    for (int64_t h = op.L; h < 2 * int64_t(op.L); ++h) leafmax = std::max(leafmax, op.size[h]);
+    const int stage = (!P.is_u8 && P.dim <= kLeafStageDim && leafmax * P.dim * 8 <= 48 * 1024) ? 1 : 0;
+    const size_t shm = stage ? sizeof(double) * leafmax * P.dim : 0;
+    // enough workgroups to cover the device: split each leaf's points over several
+    const int splits = std::max(1, std::min(static_cast<int>((leafmax + 15) / 16), 2048 / op.L));
     for (int it = 0; it < p.knn_iters; ++it) {
-        build_tree(op, 1, it, kperm, tmp, P, s, samp, nsamp, pq, sumk, key, left);
-        hipLaunchKernelGGL(k_knn_leaf, dim3(op.L), dim3(threads), static_cast<size_t>(threads) * k * 12, s, op.depth,
-                           op.d_start.get(), op.d_size.get(), kperm.get(), P, k, op.knn_idx.get(), op.knn_d2.get());
+        build_tree(op, 1, it, kperm, tmp, P, s, samp, nsamp, pq, sumk, key);
+        hipLaunchKernelGGL(k_knn_leaf, dim3(op.L * splits), dim3(kKnnBlock), shm, s, op.depth, op.d_start.get(),
+                           op.d_size.get(), kperm.get(), P, k, stage, splits, op.knn_idx.get(), op.knn_d2.get());
         check_launch("knn leaf");
     }
     // lists

@@ -70,63 +70,58 @@ __global__ void k_prep(int64_t n, int nrhs, const double* x, const int32_t* perm
     for (int c = 0; c < nrhs; ++c) w[c * n + pos] = static_cast<V>(sc * x[c * n + i]);
 }
 
-// ---- N2S: skeleton weights, one workgroup per node --------------------------
+// ---- dot products of one row per wave (lanes stride the columns) -------------
+template <typename V, typename TM, typename GX>
+__device__ inline V row_dot(const TM* row, int nc, GX x) {
+    const int lane = threadIdx.x % kWave;
+    V acc = 0;
+    int j = lane;
+    for (; j + 3 * kWave < nc; j += 4 * kWave) {
+        const TM p0 = row[j], p1 = row[j + kWave], p2 = row[j + 2 * kWave], p3 = row[j + 3 * kWave];
+        const V x0 = x(j), x1 = x(j + kWave), x2 = x(j + 2 * kWave), x3 = x(j + 3 * kWave);
+        acc += val<V>(p0) * x0;
+        acc += val<V>(p1) * x1;
+        acc += val<V>(p2) * x2;
+        acc += val<V>(p3) * x3;
+    }
+    for (; j < nc; j += kWave) acc += val<V>(row[j]) * x(j);
+    return wave_sum(acc);
+}
+
+// ---- N2S: one level of skeleton weights, one wave per (node, row) -------------
+//   leaf:  w~_h = P_h w_h;   inner: w~_h = P_h [w~_left; w~_right]
 template <typename V, typename TP>
-__global__ void k_n2s(int lvl, int depth, const int32_t* heaps, const int64_t* start, const int32_t* rank,
-                      const int32_t* ncand, const int64_t* skoff, const int64_t* poff, const TP* P, const V* w,
-                      int64_t ldw, V* skw, int64_t ldsk, int nrhs) {
-    const int64_t h = heaps[blockIdx.x];
-    const int r = rank[h], nc = ncand[h];
-    const V* in = lvl == depth ? w + start[h] : skw + skoff[2 * h];
-    const int64_t ldin = lvl == depth ? ldw : ldsk;
-    const TP* Pm = P + poff[h];
-    const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave, nw = blockDim.x / kWave;
+__global__ void k_n2s(const RowTask* tasks, int64_t ntask, int leaf, const int64_t* start, const int32_t* ncand,
+                      const int64_t* skoff, const int64_t* poff, const TP* P, const V* w, int64_t ldw, V* skw,
+                      int64_t ldsk, int nrhs) {
+    const int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x / kWave) + threadIdx.x / kWave;
+    if (t >= ntask) return;
+    const RowTask T = tasks[t];
+    const int nc = ncand[T.h];
+    const TP* row = P + poff[T.h] + static_cast<int64_t>(T.i) * nc;
     for (int c = 0; c < nrhs; ++c) {
-        for (int i = wv; i < r; i += nw) {
-            V acc = 0;
-            for (int j = lane; j < nc; j += kWave) acc += static_cast<V>(Pm[static_cast<int64_t>(i) * nc + j]) * in[c * ldin + j];
-            acc = wave_sum(acc);
-            if (lane == 0) skw[c * ldsk + skoff[h] + i] = acc;
-        }
+        const V* in = leaf ? w + c * ldw + start[T.h] : skw + c * ldsk + skoff[2 * T.h];
+        const V acc = row_dot<V>(row, nc, [&](int j) { return in[j]; });
+        if (threadIdx.x % kWave == 0) skw[c * ldsk + skoff[T.h] + T.i] = acc;
     }
 }
 
-// ---- S2S: far field between skeletons, one workgroup per node ------------------
+// ---- S2S: far field between skeletons, one wave per (node, row) -----------------
 template <typename V, typename TF>
-__global__ void k_s2s(const int32_t* heaps, const int32_t* rank, const int64_t* skoff, const int64_t* boff,
+__global__ void k_s2s(const RowTask* tasks, int64_t ntask, const int64_t* skoff, const int64_t* boff,
                       const int32_t* cols, const int64_t* colbase, const int32_t* colmap, const TF* far,
                       const float* fscale, const V* skw, V* sku, int64_t ldsk, int nrhs) {
-    const int64_t h = heaps[blockIdx.x];
-    const int r = rank[h], nc = cols[h];
-    const TF* F = far + boff[h];
-    const int32_t* cm = colmap + colbase[h];
-    const V sc = fscale ? static_cast<V>(fscale[h]) : V(1);
-    const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave, nw = blockDim.x / kWave;
+    const int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x / kWave) + threadIdx.x / kWave;
+    if (t >= ntask) return;
+    const RowTask T = tasks[t];
+    const int nc = cols[T.h];
+    const TF* row = far + boff[T.h] + static_cast<int64_t>(T.i) * nc;
+    const int32_t* cm = colmap + colbase[T.h];
+    const V sc = fscale ? static_cast<V>(fscale[T.h]) : V(1);
     for (int c = 0; c < nrhs; ++c) {
-        for (int i = wv; i < r; i += nw) {
-            V acc = 0;
-            for (int j = lane; j < nc; j += kWave) acc += val<V>(F[static_cast<int64_t>(i) * nc + j]) * skw[c * ldsk + cm[j]];
-            acc = wave_sum(acc);
-            if (lane == 0) sku[c * ldsk + skoff[h] + i] = acc * sc;
-        }
-    }
-}
-
-// ---- S2N for inner nodes: children's potentials += P^T u~ --------------------
-template <typename V, typename TP>
-__global__ void k_s2n(const int32_t* heaps, const int32_t* rank, const int32_t* ncand, const int64_t* skoff,
-                      const int64_t* poff, const TP* P, V* sku, int64_t ldsk, int nrhs) {
-    const int64_t h = heaps[blockIdx.x];
-    const int r = rank[h], nc = ncand[h];
-    const TP* Pm = P + poff[h];
-    for (int c = 0; c < nrhs; ++c) {
-        const V* uh = sku + c * ldsk + skoff[h];
-        V* out = sku + c * ldsk + skoff[2 * h];
-        for (int j = threadIdx.x; j < nc; j += blockDim.x) {
-            V acc = 0;
-            for (int i = 0; i < r; ++i) acc += static_cast<V>(Pm[static_cast<int64_t>(i) * nc + j]) * uh[i];
-            out[j] += acc;
-        }
+        const V* x = skw + c * ldsk;
+        const V acc = row_dot<V>(row, nc, [&](int j) { return x[cm[j]]; });
+        if (threadIdx.x % kWave == 0) sku[c * ldsk + skoff[T.h] + T.i] = acc * sc;
     }
 }
 
@@ -184,25 +179,78 @@ __global__ void __launch_bounds__(kBlock) k_l2l(const NearItem* items, int64_t n
     }
 }
 
-// ---- combine: near partials + leaf S2N, scale, scatter to original order -------
+// ---- combine: downward pass, near partial sums, scale, scatter ---------------
+// One workgroup per leaf.  It walks the leaf's ancestors top-down,
+//   u~_child = S2S(child) + (P_parent^T u~_parent)[child's columns],
+// (the S2N pass restricted to one path), applies P_leaf^T, adds the near-field
+// partial sums of the leaf's rows and writes the scaled result in original order.
+constexpr int kMaxRank = 512;
 template <typename V, typename TP>
-__global__ void k_combine(const LeafPlan* leaves, const V* part, int64_t ldp, const int32_t* rank,
-                          const int64_t* skoff, const int64_t* poff, const TP* P, const V* sku, int64_t ldsk,
-                          const int32_t* perm, const double* scale, int64_t n, double* y, int nrhs) {
+__global__ void __launch_bounds__(kBlock) k_combine(const LeafPlan* leaves, const V* part, int64_t ldp, int depth,
+                                                    const int32_t* rank, const int32_t* ncand, const int64_t* skoff,
+                                                    const int64_t* poff, const TP* P, const V* sku, int64_t ldsk,
+                                                    const int32_t* perm, const double* scale, int64_t n, double* y,
+                                                    int nrhs) {
+    __shared__ V tot[2][kMaxRank];
     const LeafPlan lp = leaves[blockIdx.x];
-    const int r = rank[lp.heap];
-    const TP* Pm = P + poff[lp.heap];
     for (int c = 0; c < nrhs; ++c) {
-        const V* uh = sku + c * ldsk + skoff[lp.heap];
+        int cur = 0;
+        int rleaf = 0;
+        if (depth >= 1) {
+            const int64_t a1 = lp.heap >> (depth - 1);
+            for (int i = threadIdx.x; i < rank[a1]; i += blockDim.x) tot[0][i] = sku[c * ldsk + skoff[a1] + i];
+            __syncthreads();
+            for (int lvl = 2; lvl <= depth; ++lvl) {
+                const int64_t node = lp.heap >> (depth - lvl), par = node >> 1;
+                const int rp = rank[par], ncp = ncand[par], rn = rank[node];
+                const int off = (node & 1) ? rank[2 * par] : 0;
+                const TP* Pm = P + poff[par] + off;
+                for (int j = threadIdx.x; j < rn; j += blockDim.x) {
+                    V acc = 0;
+                    int i = 0;
+                    for (; i + 8 <= rp; i += 8) {
+                        TP pv[8];
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) pv[u] = Pm[static_cast<int64_t>(i + u) * ncp + j];
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) acc += static_cast<V>(pv[u]) * tot[cur][i + u];
+                    }
+                    for (; i < rp; ++i) acc += static_cast<V>(Pm[static_cast<int64_t>(i) * ncp + j]) * tot[cur][i];
+                    tot[cur ^ 1][j] = sku[c * ldsk + skoff[node] + j] + acc;
+                }
+                __syncthreads();
+                cur ^= 1;
+            }
+            rleaf = rank[lp.heap];
+        }
+        const TP* Pl = P + poff[lp.heap];
+        const V* pc = part + c * ldp + lp.part_off;
         for (int j = threadIdx.x; j < lp.rows; j += blockDim.x) {
-            V acc = 0;
-            for (int q = 0; q < lp.nitems; ++q) acc += part[c * ldp + lp.part_off + static_cast<int64_t>(q) * lp.ld + j];
+            V near = 0;
+            int q = 0;
+            for (; q + 8 <= lp.nitems; q += 8) {
+                V x[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) x[u] = pc[static_cast<int64_t>(q + u) * lp.ld + j];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) near += x[u];
+            }
+            for (; q < lp.nitems; ++q) near += pc[static_cast<int64_t>(q) * lp.ld + j];
             V f = 0;
-            for (int i = 0; i < r; ++i) f += static_cast<V>(Pm[static_cast<int64_t>(i) * lp.rows + j]) * uh[i];
+            int i = 0;
+            for (; i + 8 <= rleaf; i += 8) {
+                TP pv[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) pv[u] = Pl[static_cast<int64_t>(i + u) * lp.rows + j];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) f += static_cast<V>(pv[u]) * tot[cur][i + u];
+            }
+            for (; i < rleaf; ++i) f += static_cast<V>(Pl[static_cast<int64_t>(i) * lp.rows + j]) * tot[cur][i];
             const int64_t pos = lp.start + j;
             const double sc = scale ? scale[pos] : 1.0;
-            y[c * n + perm[pos]] = sc * static_cast<double>(acc + f);
+            y[c * n + perm[pos]] = sc * static_cast<double>(near + f);
         }
+        __syncthreads();
     }
 }
 
@@ -352,6 +400,30 @@ void build_eval_plan(Op& op, hipStream_t s) {
     op.part_elems = part;
     op.d_items = to_device(op.items, s);
     op.d_leaves = to_device(op.leaves, s);
+    // one row task per skeleton row, grouped by level from the leaves up; the
+    // same list, taken whole, gives the far-field (S2S) rows
+    std::vector<RowTask> tasks;
+    op.row_begin.assign(op.depth + 1, 0);
+    op.row_count.assign(op.depth + 1, 0);
+    for (int lvl = op.depth; lvl >= 1; --lvl) {
+        op.row_begin[lvl] = static_cast<int64_t>(tasks.size());
+        for (int64_t h = int64_t(1) << lvl; h < (int64_t(1) << (lvl + 1)); ++h)
+            for (int32_t i = 0; i < op.rank[h]; ++i) tasks.push_back(RowTask{static_cast<int32_t>(h), i});
+        op.row_count[lvl] = static_cast<int64_t>(tasks.size()) - op.row_begin[lvl];
+    }
+    op.row_total = static_cast<int64_t>(tasks.size());
+    op.d_row_tasks = to_device(tasks, s);
+    if (!op.side) HDM_HIP(hipStreamCreateWithFlags(&op.side, hipStreamNonBlocking));
+    if (!op.ev_fork) HDM_HIP(hipEventCreateWithFlags(&op.ev_fork, hipEventDisableTiming));
+    if (!op.ev_join) HDM_HIP(hipEventCreateWithFlags(&op.ev_join, hipEventDisableTiming));
+    HDM_HIP(hipStreamSynchronize(s));
+}
+
+Op::~Op() {
+    if (side) (void)hipStreamSynchronize(side);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    if (side) (void)hipStreamDestroy(side);
 }
 
 static void ensure_ws(Op& op, int nrhs, size_t vbytes) {
@@ -375,41 +447,57 @@ static void apply_t(Op& op, bool normalised, const TN* near, const float* nscale
     const int64_t ldsk = std::max<int64_t>(op.nskel, 1);
     const int64_t ldp = std::max<int64_t>(op.part_elems, 1);
     const double* scale = normalised ? op.c.get() : nullptr;
-    hipLaunchKernelGGL((k_prep<V>), dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, s, n, nrhs, x, op.perm.get(), scale, w);
-    // N2S, bottom-up
-    for (int lvl = op.depth; lvl >= 1; --lvl) {
-        const int nodes = static_cast<int>(op.heaps_off[lvl + 1] - op.heaps_off[lvl]);
-        hipLaunchKernelGGL((k_n2s<V, TP>), dim3(nodes), dim3(kBlock), 0, s, lvl, op.depth,
-                           op.d_heaps.get() + op.heaps_off[lvl], op.d_start.get(), op.d_rank.get(), op.d_ncand.get(),
-                           op.d_skoff.get(), op.d_poff.get(), P, w, n, skw, ldsk, nrhs);
+    Ctx* cx = op.ctx;
+    {
+        PhaseScope ph(cx, HDM_PHASE_PREP, s);
+        hipLaunchKernelGGL((k_prep<V>), dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, s, n, nrhs, x, op.perm.get(), scale, w);
     }
-    // S2S, every node at once
-    const int all = static_cast<int>(op.heaps_off[op.depth + 1] - op.heaps_off[1]);
-    if (op.nskel > 0) {
-        hipLaunchKernelGGL((k_s2s<V, TF>), dim3(all), dim3(kBlock), 0, s, op.d_heaps.get() + op.heaps_off[1],
-                           op.d_rank.get(), op.d_skoff.get(), op.d_far_block_off.get(), op.d_far_cols.get(),
-                           op.d_far_colbase.get(), op.far_colmap.get(), far, fscale, skw, sku, ldsk, nrhs);
-        // S2N, top-down over inner levels
-        for (int lvl = 1; lvl < op.depth; ++lvl) {
-            const int nodes = static_cast<int>(op.heaps_off[lvl + 1] - op.heaps_off[lvl]);
-            hipLaunchKernelGGL((k_s2n<V, TP>), dim3(nodes), dim3(kBlock), 0, s, op.d_heaps.get() + op.heaps_off[lvl],
-                               op.d_rank.get(), op.d_ncand.get(), op.d_skoff.get(), op.d_poff.get(), P, sku, ldsk, nrhs);
-        }
-    }
-    // L2L
-    const int64_t nit = static_cast<int64_t>(op.items.size());
+    // the upward pass and the far field run on a side stream while the near field streams its tiles
+    const bool tree = op.nskel > 0;
     const int wpb = kBlock / kWave;
-    hipLaunchKernelGGL((k_l2l<V, TN>), dim3(ceil_div(nit, wpb)), dim3(kBlock), 0, s, op.d_items.get(), nit, near, nscale,
-                       w, n, part, ldp, nrhs);
-    hipLaunchKernelGGL((k_combine<V, TP>), dim3(op.L), dim3(kBlock), 0, s, op.d_leaves.get(), part, ldp,
-                       op.d_rank.get(), op.d_skoff.get(), op.d_poff.get(), P, sku, ldsk, op.perm.get(), scale, n, y,
-                       nrhs);
+    if (tree) {
+        HDM_HIP(hipEventRecord(op.ev_fork, s));
+        HDM_HIP(hipStreamWaitEvent(op.side, op.ev_fork, 0));
+        {
+            PhaseScope ph(cx, HDM_PHASE_N2S, op.side);
+            for (int lvl = op.depth; lvl >= 1; --lvl) {
+                const int64_t t0 = op.row_begin[lvl], nt = op.row_count[lvl];
+                if (nt == 0) continue;
+                hipLaunchKernelGGL((k_n2s<V, TP>), dim3(ceil_div(nt, wpb)), dim3(kBlock), 0, op.side,
+                                   op.d_row_tasks.get() + t0, nt, lvl == op.depth ? 1 : 0, op.d_start.get(),
+                                   op.d_ncand.get(), op.d_skoff.get(), op.d_poff.get(), P, w, n, skw, ldsk, nrhs);
+            }
+        }
+        {
+            PhaseScope ph(cx, HDM_PHASE_S2S, op.side);
+            const int64_t nt = op.row_total;
+            hipLaunchKernelGGL((k_s2s<V, TF>), dim3(ceil_div(nt, wpb)), dim3(kBlock), 0, op.side,
+                               op.d_row_tasks.get(), nt, op.d_skoff.get(), op.d_far_block_off.get(),
+                               op.d_far_cols.get(), op.d_far_colbase.get(), op.far_colmap.get(), far, fscale, skw, sku,
+                               ldsk, nrhs);
+        }
+        HDM_HIP(hipEventRecord(op.ev_join, op.side));
+    }
+    {
+        PhaseScope ph(cx, HDM_PHASE_L2L, s);
+        const int64_t nit = static_cast<int64_t>(op.items.size());
+        hipLaunchKernelGGL((k_l2l<V, TN>), dim3(ceil_div(nit, wpb)), dim3(kBlock), 0, s, op.d_items.get(), nit, near,
+                           nscale, w, n, part, ldp, nrhs);
+    }
+    if (tree) HDM_HIP(hipStreamWaitEvent(s, op.ev_join, 0));
+    {
+        PhaseScope ph(cx, HDM_PHASE_COMBINE, s);
+        hipLaunchKernelGGL((k_combine<V, TP>), dim3(op.L), dim3(kBlock), 0, s, op.d_leaves.get(), part, ldp,
+                           tree ? op.depth : 0, op.d_rank.get(), op.d_ncand.get(), op.d_skoff.get(), op.d_poff.get(),
+                           P, sku, ldsk, op.perm.get(), scale, n, y, nrhs);
+    }
     check_launch("apply");
 }
 
 void apply(Op& op, int normalised, bool exact64, const double* x, double* y, int nrhs, hipStream_t s) {
     if (exact64 || (op.prm.near_prec == HDM_F64 && op.prm.far_prec == HDM_F64)) {
         HDM_CHECK(op.near64.n > 0 || op.near_elems == 0, HDM_EINTERNAL, "float64 tiles are not resident");
+    HDM_CHECK(op.prm.max_rank_s <= kMaxRank, HDM_EINTERNAL, "rank above the combine kernel's limit");
         apply_t<double, double, double, double>(op, normalised, op.near64.get(), nullptr, op.far64.get(), nullptr,
                                                 op.P64.get(), x, y, nrhs, s);
         return;

@@ -342,20 +342,26 @@ hdm_status lanczos_eigs(Op& op, int r, double tol, int block, int max_basis, uin
         apply(op, 1, false, vj, y.get(), 1, s);
         ++matvecs;
         const int nc = j + 1;
-        hipLaunchKernelGGL(k_gemvt, dim3(nb), dim3(kBlock), 0, s, V.get(), n, nc, y.get(), n, part.get(), ldp);
-        hipLaunchKernelGGL(k_reduce_cols, dim3(ceil_div(nc, 64)), dim3(64), 0, s, part.get(), nb, ldp, nc, h1.get());
-        hipLaunchKernelGGL(k_gemvn, dim3(nb), dim3(kBlock), 0, s, V.get(), n, nc, h1.get(), y.get(), n, nullptr);
-        hipLaunchKernelGGL(k_gemvt, dim3(nb), dim3(kBlock), 0, s, V.get(), n, nc, y.get(), n, part.get(), ldp);
-        hipLaunchKernelGGL(k_reduce_cols, dim3(ceil_div(nc, 64)), dim3(64), 0, s, part.get(), nb, ldp, nc, h2.get());
-        hipLaunchKernelGGL(k_gemvn, dim3(nb), dim3(kBlock), 0, s, V.get(), n, nc, h2.get(), y.get(), n, np.get());
-        hipLaunchKernelGGL(k_alpha_beta, dim3(1), dim3(1), 0, s, h1.get(), h2.get(), j, np.get(), nb, alpha.get(),
-                           beta.get());
+        {   // CGS2 against the whole basis, alpha_j, beta_j
+            PhaseScope ph(op.ctx, HDM_PHASE_ORTHO, s);
+            hipLaunchKernelGGL(k_gemvt, dim3(nb), dim3(kBlock), 0, s, V.get(), n, nc, y.get(), n, part.get(), ldp);
+            hipLaunchKernelGGL(k_reduce_cols, dim3(ceil_div(nc, 64)), dim3(64), 0, s, part.get(), nb, ldp, nc, h1.get());
+            hipLaunchKernelGGL(k_gemvn, dim3(nb), dim3(kBlock), 0, s, V.get(), n, nc, h1.get(), y.get(), n, nullptr);
+            hipLaunchKernelGGL(k_gemvt, dim3(nb), dim3(kBlock), 0, s, V.get(), n, nc, y.get(), n, part.get(), ldp);
+            hipLaunchKernelGGL(k_reduce_cols, dim3(ceil_div(nc, 64)), dim3(64), 0, s, part.get(), nb, ldp, nc, h2.get());
+            hipLaunchKernelGGL(k_gemvn, dim3(nb), dim3(kBlock), 0, s, V.get(), n, nc, h2.get(), y.get(), n, np.get());
+            hipLaunchKernelGGL(k_alpha_beta, dim3(1), dim3(1), 0, s, h1.get(), h2.get(), j, np.get(), nb, alpha.get(),
+                               beta.get());
+        }
         check_launch("lanczos step");
         m = j + 1;
         const bool last = (j == max_basis - 1);
         if (m >= r && ((m % check_every) == 0 || last)) {
-            hipLaunchKernelGGL(k_tridiag, dim3(ceil_div(r, 4)), dim3(kBlock), 0, s, alpha.get(), beta.get(), m, r,
-                               theta.get(), Y.get(), bound.get(), work.get());
+            {
+                PhaseScope pt(op.ctx, HDM_PHASE_TRIDIAG, s);
+                hipLaunchKernelGGL(k_tridiag, dim3(ceil_div(r, 4)), dim3(kBlock), 0, s, alpha.get(), beta.get(), m, r,
+                                   theta.get(), Y.get(), bound.get(), work.get());
+            }
             check_launch("tridiagonal eigensolve");
             theta.download(h_theta.data(), r, s);
             bound.download(h_bound.data(), r, s);

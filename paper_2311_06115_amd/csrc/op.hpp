@@ -7,10 +7,39 @@
 
 namespace hdm {
 
+// HIP-event pairs around phase launches, accumulated per phase.
+struct Profiler {
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    struct Mark { int phase; size_t a, b; };
+    std::vector<Mark> marks;   // phase with the pool indices of its start and end events
+    hipEvent_t take();
+    void begin(int phase, hipStream_t s, size_t& slot);
+    void end(size_t slot, hipStream_t s) noexcept;
+    void totals(int64_t* launches, double* ms);
+    void reset() { used = 0; marks.clear(); }
+    ~Profiler();
+};
+
 struct Ctx {
     int device = 0;
     size_t budget = 0;      // bytes, 0 = unlimited
     size_t resident = 0;    // bytes held by live operators of this context
+    Profiler prof;
+};
+
+// scoped phase interval on a stream (no-op unless the context profiles)
+struct PhaseScope {
+    Profiler* p;
+    hipStream_t s;
+    size_t slot = 0;
+    PhaseScope(Ctx* c, int phase, hipStream_t st) : p(c && c->prof.on ? &c->prof : nullptr), s(st) {
+        if (p) p->begin(phase, s, slot);
+    }
+    ~PhaseScope() {
+        if (p) p->end(slot, s);
+    }
 };
 
 // One streaming work item of the near-field product: ncols consecutive
@@ -36,6 +65,11 @@ struct LeafPlan {
     int32_t rows;       // points in the leaf
     int32_t heap;       // heap id
     int32_t ngroups;    // row groups
+};
+
+// one skeleton row: heap id and row index
+struct RowTask {
+    int32_t h, i;
 };
 
 struct NodeLevel {       // nodes of one tree level with their skeleton work
@@ -100,6 +134,11 @@ struct Op {
     DevBuf<int32_t> d_rank, d_ncand;
     DevBuf<int64_t> d_skoff, d_poff, d_far_block_off;
     DevBuf<int32_t> d_far_cols;
+    std::vector<int64_t> row_begin, row_count; // per level: skeleton-row tasks of the upward pass
+    int64_t row_total = 0;
+    DevBuf<RowTask> d_row_tasks;
+    hipStream_t side = nullptr;                // upward pass + far field run here, concurrent with the near field
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     // normalisation (tree order)
     DevBuf<double> q, d, c;
     // workspaces of the product
@@ -107,6 +146,10 @@ struct Op {
     DevBuf<char> w_tree, u_tree, skw, sku, part;
     double seconds_compress = 0.0;
     size_t footprint() const;
+    Op() = default;
+    Op(const Op&) = delete;
+    Op& operator=(const Op&) = delete;
+    ~Op();
 };
 
 // compression (compress.hip)

@@ -40,8 +40,16 @@ class OpStats(C.Structure):
                 ("knn_k", C.c_int32), ("max_rank", C.c_int32), ("min_leaf_rank", C.c_int32),
                 ("mean_leaf_rank", C.c_double), ("near_pairs", C.c_int64), ("far_pairs", C.c_int64),
                 ("bytes_near", C.c_int64), ("bytes_far", C.c_int64), ("bytes_p", C.c_int64),
-                ("bytes_total", C.c_int64), ("algo_bytes_matvec", C.c_int64), ("flops_matvec", C.c_int64),
+                ("bytes_total", C.c_int64), ("algo_bytes_matvec", C.c_int64), ("algo_bytes_near", C.c_int64),
+                ("flops_matvec", C.c_int64),
                 ("seconds_compress", C.c_double)]
+
+
+PHASES = ["prep", "n2s", "s2s", "s2n", "l2l", "combine", "ortho", "tridiag", "compress"]
+
+
+class PhaseTimes(C.Structure):
+    _fields_ = [("launches", C.c_int64 * len(PHASES)), ("ms", C.c_double * len(PHASES))]
 
 
 class EigInfo(C.Structure):
@@ -93,6 +101,8 @@ def lib():
         "hdm_params_default": (None, [C.POINTER(Params)]),
         "hdm_ctx_create": (st, [C.c_int, C.c_size_t, C.POINTER(vp)]),
         "hdm_ctx_destroy": (st, [vp]),
+        "hdm_ctx_profile": (st, [vp, C.c_int]),
+        "hdm_ctx_phase_times": (st, [vp, C.POINTER(PhaseTimes)]),
         "hdm_compress": (st, [vp, vp, C.c_int, C.POINTER(Params), vp, C.POINTER(vp)]),
         "hdm_op_destroy": (st, [vp]),
         "hdm_op_stats": (st, [vp, C.POINTER(OpStats)]),
@@ -145,6 +155,15 @@ class Context:
         check(lib().hdm_ctx_create(device, budget_bytes, C.byref(self.h)))
         self.device = device
 
+    def profile(self, enable: bool):
+        check(lib().hdm_ctx_profile(self.h, int(enable)))
+
+    def phase_times(self):
+        """{phase: (launches, milliseconds)} recorded since profile(True)."""
+        pt = PhaseTimes()
+        check(lib().hdm_ctx_phase_times(self.h, C.byref(pt)))
+        return {name: (pt.launches[i], pt.ms[i]) for i, name in enumerate(PHASES)}
+
     def close(self):
         if self.h:
             lib().hdm_ctx_destroy(self.h)
@@ -185,15 +204,22 @@ class Operator:
         import torch
         self.torch = torch
         self.ctx = ctx or context(0)
-        if isinstance(X, torch.Tensor):
-            Xh = X.detach().cpu().numpy()
+        on_device = isinstance(X, torch.Tensor) and X.is_cuda
+        if on_device:
+            if X.dtype not in (torch.uint8, torch.float64) or not X.is_contiguous():
+                raise ValueError("device points must be contiguous float64 or uint8")
+            shape_src = np.empty((X.shape[0], X.shape[1]), np.uint8 if X.dtype == torch.uint8 else np.float64)
+            xptr = C.c_void_p(X.data_ptr())
         else:
-            Xh = np.asarray(X)
-        Xh = np.ascontiguousarray(Xh if Xh.dtype == np.uint8 else Xh.astype(np.float64))
-        self.params = make_params(Xh, eps, m, s, tau, k, seed, near_prec, far_prec, budget, knn_iters)
-        self.n, self.dim, self.k = Xh.shape[0], Xh.shape[1], int(k)
+            Xh = X.detach().cpu().numpy() if isinstance(X, torch.Tensor) else np.asarray(X)
+            Xh = np.ascontiguousarray(Xh if Xh.dtype == np.uint8 else Xh.astype(np.float64))
+            shape_src = Xh
+            xptr = _ptr(Xh)
+        self.params = make_params(shape_src, eps, m, s, tau, k, seed, near_prec, far_prec, budget, knn_iters)
+        self.n, self.dim, self.k = shape_src.shape[0], shape_src.shape[1], int(k)
         self.h = C.c_void_p()
-        check(lib().hdm_compress(self.ctx.h, _ptr(Xh), 0, C.byref(self.params), _stream(torch), C.byref(self.h)))
+        check(lib().hdm_compress(self.ctx.h, xptr, int(on_device), C.byref(self.params), _stream(torch),
+                                 C.byref(self.h)))
         st = self.stats()
         self.depth, self.L = st.depth, st.leaves
         self.nnodes = 2 * self.L
