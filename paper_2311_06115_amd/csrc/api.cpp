@@ -35,6 +35,14 @@ void Profiler::end(size_t slot, hipStream_t s) noexcept {
     if (hipEventRecord(pool[b], s) == hipSuccess) marks[slot].b = b;
 }
 
+void Profiler::kernel_events(int phase, hipEvent_t& start, hipEvent_t& stop) {
+    const size_t a = used;
+    start = take();
+    const size_t b = used;
+    stop = take();
+    marks.push_back(Mark{phase, a, b});
+}
+
 void Profiler::totals(int64_t* launches, double* ms) {
     for (int p = 0; p < HDM_PHASE_COUNT; ++p) { launches[p] = 0; ms[p] = 0.0; }
     for (const Mark& m : marks) {

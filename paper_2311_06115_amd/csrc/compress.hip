@@ -210,6 +210,28 @@ __device__ inline int wg_flag_scan(bool f, int* wsum, int* total) {
     return before + in_wave;
 }
 
+// Exclusive prefix sum of an int over the workgroup in thread order (wave
+// shuffles + one shared-memory pass); *total receives the workgroup's sum.
+__device__ inline int wg_scan_excl(int v, int* wsum, int* total) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    int incl = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        const int o = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += o;
+    }
+    if (lane == 63) wsum[wv] = incl;
+    __syncthreads();
+    int before = 0, tot = 0;
+    for (int w = 0; w < nw; ++w) {
+        const int c = wsum[w];
+        before += w < wv ? c : 0;
+        tot += c;
+    }
+    __syncthreads();
+    *total = tot;
+    return before + incl - v;
+}
+
 // order-preserving image of a float64 key as an unsigned integer (+0 for zero)
 __device__ inline uint64_t orderable(double x) {
     if (x == 0.0) x = 0.0;
@@ -268,28 +290,33 @@ __global__ void __launch_bounds__(kSplitBlock) k_tree_split(int lvl, const int64
         mask |= 0xFFull << shift;
         __syncthreads();
     }
-    // the threshold is the (s_k)-th member (position order) whose key image equals s_prefix
+    // the threshold is the (s_k)-th member (position order) whose key image
+    // equals s_prefix.  Each thread owns a contiguous run of positions, so two
+    // workgroup scans of per-thread counts give every member its place.
     const uint64_t ustar = s_prefix;
     const int kstar = s_k;
-    int run_eq = 0, run_l = 0, run_r = 0;
-    for (int base = 0; base < n; base += blockDim.x) {
-        const int a = base + threadIdx.x;
-        const bool valid = a < n;
-        const uint64_t u = valid ? orderable(key[s0 + a]) : 0;
-        const bool eq = valid && u == ustar;
-        int tot_eq = 0, tot_l = 0;
-        const int eqrank = run_eq + wg_flag_scan(eq, wsum, &tot_eq);
-        const bool left = valid && (u < ustar || (eq && eqrank < kstar));
-        const int lpre = wg_flag_scan(left, wsum, &tot_l);
-        if (valid) {
-            const int rpre = threadIdx.x - lpre;
-            const int64_t np = left ? s0 + run_l + lpre : s0 + nl + run_r + rpre;
-            out[np] = perm[s0 + a];
-        }
-        const int cvalid = min(static_cast<int>(blockDim.x), n - base);
-        run_eq += tot_eq;
-        run_l += tot_l;
-        run_r += cvalid - tot_l;
+    const int per = (n + static_cast<int>(blockDim.x) - 1) / static_cast<int>(blockDim.x);
+    const int a0 = min(n, static_cast<int>(threadIdx.x) * per), a1 = min(n, a0 + per);
+    int neq = 0;
+    for (int a = a0; a < a1; ++a) neq += orderable(key[s0 + a]) == ustar;
+    int tot = 0;
+    const int eq_base = wg_scan_excl(neq, wsum, &tot);
+    int nleft = 0, e = eq_base;
+    for (int a = a0; a < a1; ++a) {
+        const uint64_t u = orderable(key[s0 + a]);
+        const bool eq = u == ustar;
+        nleft += u < ustar || (eq && e < kstar);
+        e += eq;
+    }
+    const int l_base = wg_scan_excl(nleft, wsum, &tot);
+    int li = l_base, ri = a0 - l_base;
+    e = eq_base;
+    for (int a = a0; a < a1; ++a) {
+        const uint64_t u = orderable(key[s0 + a]);
+        const bool eq = u == ustar;
+        const bool left = u < ustar || (eq && e < kstar);
+        e += eq;
+        out[left ? s0 + li++ : s0 + nl + ri++] = perm[s0 + a];
     }
 }
 
@@ -475,8 +502,10 @@ __global__ void k_row_count(LevelArgs A) {
 // the rest: uniform draws from outside the node (or every outside point when
 // that is all there is).  The draws are taken 64 at a time by one wave and
 // accepted in draw order, exactly as a sequential rejection loop would.
+constexpr int kRowStage = 8192;
 __global__ void k_row_select(LevelArgs A) {
     __shared__ int wsum[kBlock / 64];
+    __shared__ int32_t cnt_s[kRowStage];
     __shared__ int32_t batch[64];
     const int64_t t = blockIdx.x;
     const int64_t h = (int64_t(1) << A.lvl) + t;
@@ -499,12 +528,16 @@ __global__ void k_row_select(LevelArgs A) {
         nu += tot;
     }
     // rank by (votes desc, index asc); keep the first want_nb
+    const bool staged = nu <= kRowStage;
+    if (staged)
+        for (int64_t u = threadIdx.x; u < nu; u += blockDim.x) cnt_s[u] = cnt[uq[u]];
+    __syncthreads();
     for (int64_t u = threadIdx.x; u < nu; u += blockDim.x) {
         const int32_t iu = uq[u];
         const int32_t cu = cnt[iu];
         int64_t r = 0;
         for (int64_t v = 0; v < nu; ++v) {
-            const int32_t cv = cnt[uq[v]];
+            const int32_t cv = staged ? cnt_s[v] : cnt[uq[v]];
             r += (cv > cu) || (cv == cu && v < u);
         }
         if (r < want_nb) {
@@ -574,15 +607,16 @@ __global__ void k_block(LevelArgs A, Pts P) {
 
 // sum_{i in [i0, i1)} x_i^2 of column c, sequential in i; loads are issued in
 // batches so the chain of additions does not wait on each load
+constexpr int kQrBatch = 16;
 __device__ inline double col_sumsq(const double* B, int nc, int c, int i0, int i1) {
     double acc = 0.0;
     int i = i0;
-    for (; i + 8 <= i1; i += 8) {
-        double x[8];
+    for (; i + kQrBatch <= i1; i += kQrBatch) {
+        double x[kQrBatch];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) x[u] = B[static_cast<int64_t>(i + u) * nc + c];
+        for (int u = 0; u < kQrBatch; ++u) x[u] = B[static_cast<int64_t>(i + u) * nc + c];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) acc = acc + x[u] * x[u];
+        for (int u = 0; u < kQrBatch; ++u) acc = acc + x[u] * x[u];
     }
     for (; i < i1; ++i) {
         const double x = B[static_cast<int64_t>(i) * nc + c];
@@ -650,9 +684,18 @@ __global__ void __launch_bounds__(kBlock) k_pivoted_id(LevelArgs A) {
         if (threadIdx.x == 0) {
             const double x0 = hv[j];
             const double alpha = x0 >= 0.0 ? -best : best;
-            hv[j] = x0 - alpha;
-            double vtv = 0.0;
-            for (int i = j; i < nr; ++i) vtv = vtv + hv[i] * hv[i];
+            const double v0 = x0 - alpha;
+            hv[j] = v0;
+            double vtv = v0 * v0;
+            int i = j + 1;
+            for (; i + 8 <= nr; i += 8) {
+                double x[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) x[u] = hv[i + u];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) vtv = vtv + x[u] * x[u];
+            }
+            for (; i < nr; ++i) vtv = vtv + hv[i] * hv[i];
             s_vtv = vtv;
             s_alpha = alpha;
         }
@@ -661,12 +704,12 @@ __global__ void __launch_bounds__(kBlock) k_pivoted_id(LevelArgs A) {
         for (int c = j + 1 + threadIdx.x; c < nc; c += blockDim.x) {
             double dot = 0.0;
             int i = j;
-            for (; i + 8 <= nr; i += 8) {
-                double x[8];
+            for (; i + kQrBatch <= nr; i += kQrBatch) {
+                double x[kQrBatch];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) x[u] = B[static_cast<int64_t>(i + u) * nc + c];
+                for (int u = 0; u < kQrBatch; ++u) x[u] = B[static_cast<int64_t>(i + u) * nc + c];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) dot = dot + hv[i + u] * x[u];
+                for (int u = 0; u < kQrBatch; ++u) dot = dot + hv[i + u] * x[u];
             }
             for (; i < nr; ++i) dot = dot + hv[i] * B[static_cast<int64_t>(i) * nc + c];
             const double f = (2.0 * dot) / vtv;
@@ -675,12 +718,12 @@ __global__ void __launch_bounds__(kBlock) k_pivoted_id(LevelArgs A) {
                 B[e] = B[e] - f * hv[j];
             }
             double acc = 0.0;
-            for (i = j + 1; i + 8 <= nr; i += 8) {
-                double x[8];
+            for (i = j + 1; i + kQrBatch <= nr; i += kQrBatch) {
+                double x[kQrBatch];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) x[u] = B[static_cast<int64_t>(i + u) * nc + c];
+                for (int u = 0; u < kQrBatch; ++u) x[u] = B[static_cast<int64_t>(i + u) * nc + c];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
+                for (int u = 0; u < kQrBatch; ++u) {
                     x[u] = x[u] - f * hv[i + u];
                     B[static_cast<int64_t>(i + u) * nc + c] = x[u];
                     acc = acc + x[u] * x[u];

@@ -449,8 +449,9 @@ static void apply_t(Op& op, bool normalised, const TN* near, const float* nscale
     const double* scale = normalised ? op.c.get() : nullptr;
     Ctx* cx = op.ctx;
     {
-        PhaseScope ph(cx, HDM_PHASE_PREP, s);
-        hipLaunchKernelGGL((k_prep<V>), dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, s, n, nrhs, x, op.perm.get(), scale, w);
+        KernelEvents ev(cx, HDM_PHASE_PREP);
+        hipExtLaunchKernelGGL((k_prep<V>), dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, s, ev.start, ev.stop, 0, n, nrhs,
+                              x, op.perm.get(), scale, w);
     }
     // the upward pass and the far field run on a side stream while the near field streams its tiles
     const bool tree = op.nskel > 0;
@@ -469,25 +470,26 @@ static void apply_t(Op& op, bool normalised, const TN* near, const float* nscale
             }
         }
         {
-            PhaseScope ph(cx, HDM_PHASE_S2S, op.side);
+            KernelEvents ev(cx, HDM_PHASE_S2S);
             const int64_t nt = op.row_total;
-            hipLaunchKernelGGL((k_s2s<V, TF>), dim3(ceil_div(nt, wpb)), dim3(kBlock), 0, op.side,
-                               op.d_row_tasks.get(), nt, op.d_skoff.get(), op.d_far_block_off.get(),
+            hipExtLaunchKernelGGL((k_s2s<V, TF>), dim3(ceil_div(nt, wpb)), dim3(kBlock), 0, op.side, ev.start, ev.stop,
+                                  0, op.d_row_tasks.get(), nt, op.d_skoff.get(), op.d_far_block_off.get(),
                                op.d_far_cols.get(), op.d_far_colbase.get(), op.far_colmap.get(), far, fscale, skw, sku,
                                ldsk, nrhs);
         }
         HDM_HIP(hipEventRecord(op.ev_join, op.side));
     }
     {
-        PhaseScope ph(cx, HDM_PHASE_L2L, s);
+        KernelEvents ev(cx, HDM_PHASE_L2L);
         const int64_t nit = static_cast<int64_t>(op.items.size());
-        hipLaunchKernelGGL((k_l2l<V, TN>), dim3(ceil_div(nit, wpb)), dim3(kBlock), 0, s, op.d_items.get(), nit, near,
-                           nscale, w, n, part, ldp, nrhs);
+        hipExtLaunchKernelGGL((k_l2l<V, TN>), dim3(ceil_div(nit, wpb)), dim3(kBlock), 0, s, ev.start, ev.stop, 0,
+                              op.d_items.get(), nit, near, nscale, w, n, part, ldp, nrhs);
     }
     if (tree) HDM_HIP(hipStreamWaitEvent(s, op.ev_join, 0));
     {
-        PhaseScope ph(cx, HDM_PHASE_COMBINE, s);
-        hipLaunchKernelGGL((k_combine<V, TP>), dim3(op.L), dim3(kBlock), 0, s, op.d_leaves.get(), part, ldp,
+        KernelEvents ev(cx, HDM_PHASE_COMBINE);
+        hipExtLaunchKernelGGL((k_combine<V, TP>), dim3(op.L), dim3(kBlock), 0, s, ev.start, ev.stop, 0,
+                              op.d_leaves.get(), part, ldp,
                            tree ? op.depth : 0, op.d_rank.get(), op.d_ncand.get(), op.d_skoff.get(), op.d_poff.get(),
                            P, sku, ldsk, op.perm.get(), scale, n, y, nrhs);
     }

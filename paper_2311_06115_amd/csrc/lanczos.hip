@@ -358,9 +358,9 @@ hdm_status lanczos_eigs(Op& op, int r, double tol, int block, int max_basis, uin
         const bool last = (j == max_basis - 1);
         if (m >= r && ((m % check_every) == 0 || last)) {
             {
-                PhaseScope pt(op.ctx, HDM_PHASE_TRIDIAG, s);
-                hipLaunchKernelGGL(k_tridiag, dim3(ceil_div(r, 4)), dim3(kBlock), 0, s, alpha.get(), beta.get(), m, r,
-                                   theta.get(), Y.get(), bound.get(), work.get());
+                KernelEvents ev(op.ctx, HDM_PHASE_TRIDIAG);
+                hipExtLaunchKernelGGL(k_tridiag, dim3(ceil_div(r, 4)), dim3(kBlock), 0, s, ev.start, ev.stop, 0,
+                                      alpha.get(), beta.get(), m, r, theta.get(), Y.get(), bound.get(), work.get());
             }
             check_launch("tridiagonal eigensolve");
             theta.download(h_theta.data(), r, s);

@@ -3,6 +3,8 @@
 
 #include <memory>
 
+#include <hip/hip_ext.h>
+
 #include "common.hpp"
 
 namespace hdm {
@@ -17,6 +19,8 @@ struct Profiler {
     hipEvent_t take();
     void begin(int phase, hipStream_t s, size_t& slot);
     void end(size_t slot, hipStream_t s) noexcept;
+    // events for hipExtLaunchKernelGGL: they take the kernel's own start and end times
+    void kernel_events(int phase, hipEvent_t& start, hipEvent_t& stop);
     void totals(int64_t* launches, double* ms);
     void reset() { used = 0; marks.clear(); }
     ~Profiler();
@@ -27,6 +31,14 @@ struct Ctx {
     size_t budget = 0;      // bytes, 0 = unlimited
     size_t resident = 0;    // bytes held by live operators of this context
     Profiler prof;
+};
+
+// start/stop events of one profiled kernel launch (both null unless the context profiles)
+struct KernelEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
+    KernelEvents(Ctx* c, int phase) {
+        if (c && c->prof.on) c->prof.kernel_events(phase, start, stop);
+    }
 };
 
 // scoped phase interval on a stream (no-op unless the context profiles)
