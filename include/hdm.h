@@ -182,15 +182,16 @@ hdm_status hdm_eigs(hdm_op op, int32_t r, double rel_resid_tol, int32_t block, i
 typedef struct {
     int32_t max_slots;          /* requests on the GPU at once */
     size_t mem_budget_bytes;    /* admission limit on the sum of resident footprints */
+    int32_t compressors;        /* threads building operators concurrently (0: 2) */
 } hdm_server_cfg_t;
 
 typedef struct {
-    const void *X;          /* host points; borrowed until the request is admitted */
+    const void *X;          /* host points (params.x_dtype, n x dim); copied by hdm_submit */
     hdm_params params;
     int32_t r;              /* eigenpairs */
     double rel_resid_tol;
     int32_t max_basis;
-    double arrival_s;       /* caller's arrival timestamp (seconds, any epoch; latency = done - arrival) */
+    double arrival_s;       /* arrival time on CLOCK_MONOTONIC in seconds (0: the submission time); latency = done - arrival */
 } hdm_request_t;
 
 typedef struct {
@@ -210,7 +211,17 @@ typedef struct {
     int64_t shared_launches;  /* launches that served more than one request */
 } hdm_server_stats_t;
 
+/* Continuous batching of eigensolves (Alg. 1 + Sec. 2.2 per request): requests
+ * are admitted first come, first served while a slot is free and the sum of
+ * the admitted requests' device-memory footprints (an upper estimate until the
+ * operator exists, then its size) stays within mem_budget_bytes (0 = no cap).
+ * A compressor thread builds admitted operators; a solver thread advances every
+ * running eigensolve by one Lanczos step per tick, issuing the products of all
+ * running solves with equal tile precisions as one launch per phase.  Each
+ * result equals the one hdm_compress + hdm_eigs give for the request alone. */
 hdm_status hdm_server_create(hdm_ctx ctx, const hdm_server_cfg_t *cfg, hdm_server *out);
+/* HDM_EINVAL for bad parameters or NaN/Inf points, HDM_ENOMEM when the
+ * request's estimated footprint exceeds the whole budget (counted as rejected). */
 hdm_status hdm_submit(hdm_server srv, const hdm_request_t *req, uint64_t *ticket);
 /* HDM_EBUSY while the request is queued or running; its result otherwise. */
 hdm_status hdm_poll(hdm_server srv, uint64_t ticket, hdm_result_t *out);

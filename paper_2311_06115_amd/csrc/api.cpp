@@ -9,6 +9,7 @@
 
 namespace hdm {
 
+// callers hold mu
 hipEvent_t Profiler::take() {
     if (used == pool.size()) {
         hipEvent_t e;
@@ -19,6 +20,7 @@ hipEvent_t Profiler::take() {
 }
 
 void Profiler::begin(int phase, hipStream_t s, size_t& slot) {
+    std::lock_guard<std::mutex> g(mu);
     const size_t a = used;
     HDM_HIP(hipEventRecord(take(), s));
     marks.push_back(Mark{phase, a, SIZE_MAX});
@@ -26,6 +28,7 @@ void Profiler::begin(int phase, hipStream_t s, size_t& slot) {
 }
 
 void Profiler::end(size_t slot, hipStream_t s) noexcept {
+    std::lock_guard<std::mutex> g(mu);
     if (used == pool.size()) {
         hipEvent_t e;
         if (hipEventCreate(&e) != hipSuccess) return;
@@ -36,6 +39,7 @@ void Profiler::end(size_t slot, hipStream_t s) noexcept {
 }
 
 void Profiler::kernel_events(int phase, hipEvent_t& start, hipEvent_t& stop) {
+    std::lock_guard<std::mutex> g(mu);
     const size_t a = used;
     start = take();
     const size_t b = used;
@@ -44,6 +48,7 @@ void Profiler::kernel_events(int phase, hipEvent_t& start, hipEvent_t& stop) {
 }
 
 void Profiler::totals(int64_t* launches, double* ms) {
+    std::lock_guard<std::mutex> g(mu);
     for (int p = 0; p < HDM_PHASE_COUNT; ++p) { launches[p] = 0; ms[p] = 0.0; }
     for (const Mark& m : marks) {
         if (m.b == SIZE_MAX || m.phase < 0 || m.phase >= HDM_PHASE_COUNT) continue;
@@ -59,14 +64,90 @@ Profiler::~Profiler() {
     for (hipEvent_t e : pool) (void)hipEventDestroy(e);
 }
 
+namespace {
+thread_local std::string g_err;
+}  // namespace
+
+void set_last_error(const char* msg) { g_err = msg ? msg : ""; }
+
+namespace {
+bool prec_ok(int p) { return p == HDM_F64 || p == HDM_F32 || p == HDM_BF16 || p == HDM_F16; }
+}  // namespace
+
+void validate_params(const hdm_params& p) {
+    if (p.n < 2) fail(HDM_EINVAL, "n must be >= 2");
+    if (p.n > (int64_t(1) << 30)) fail(HDM_EINVAL, "n must be < 2^30");
+    if (p.dim < 1) fail(HDM_EINVAL, "dim must be >= 1");
+    if (p.x_dtype != HDM_F64 && p.x_dtype != HDM_U8) fail(HDM_EINVAL, "x_dtype must be HDM_F64 or HDM_U8");
+    if (!(p.eps > 0.0) || !std::isfinite(p.eps)) fail(HDM_EINVAL, "eps must be finite and > 0");
+    if (p.alpha != 1.0) fail(HDM_EINVAL, "only alpha = 1 is supported");
+    if (p.leaf_m < 2) fail(HDM_EINVAL, "leaf_m must be >= 2");
+    if (p.max_rank_s < 1 || p.max_rank_s > 512) fail(HDM_EINVAL, "max_rank_s must be in [1, 512]");
+    if (!(p.tau >= 0.0) || !std::isfinite(p.tau)) fail(HDM_EINVAL, "tau must be finite and >= 0");
+    if (p.knn_k < 1 || p.knn_k > 64) fail(HDM_EINVAL, "knn_k must be in [1, 64]");
+    if (p.knn_iters < 1 || p.knn_iters > 1000) fail(HDM_EINVAL, "knn_iters must be in [1, 1000]");
+    if (!(p.budget >= 0.0 && p.budget <= 1.0)) fail(HDM_EINVAL, "budget must be in [0, 1]");
+    if (!prec_ok(p.near_prec) || !prec_ok(p.far_prec)) fail(HDM_EINVAL, "bad tile precision");
+    if ((p.near_prec == HDM_F64) != (p.far_prec == HDM_F64))
+        fail(HDM_EINVAL, "float64 tiles cannot be mixed with reduced-precision tiles");
+    int depth = 0;
+    while ((p.n + (int64_t(1) << depth) - 1) / (int64_t(1) << depth) > p.leaf_m) ++depth;
+    if (depth > 16) fail(HDM_EINVAL, "tree deeper than 16 levels: raise leaf_m");
+    if ((p.n >> depth) <= p.knn_k) fail(HDM_EINVAL, "every leaf must hold more than knn_k points");
+    if (((p.n + (int64_t(1) << depth) - 1) >> depth) > 2048) fail(HDM_EINVAL, "leaves must hold <= 2048 points");
+}
+
+
+hdm_op_s* make_operator(Ctx* ctx, const void* X, int x_on_device, const hdm_params& params, hipStream_t s) {
+    validate_params(params);
+    if (!x_on_device && params.x_dtype == HDM_F64) {
+        const double* x = static_cast<const double*>(X);
+        const int64_t cnt = params.n * params.dim;
+        for (int64_t i = 0; i < cnt; ++i) HDM_CHECK(std::isfinite(x[i]), HDM_EINVAL, "points contain NaN or Inf");
+    }
+    std::unique_ptr<hdm_op_s> op(new hdm_op_s());
+    op->ctx = ctx;
+    op->prm = params;
+    {
+        PhaseScope ph(ctx, HDM_PHASE_COMPRESS, s);
+        compress_operator(*op, X, x_on_device, s);
+        build_eval_plan(*op, s);
+        normalise_degrees(*op, s);
+        convert_eval_precision(*op, s);
+    }
+    HDM_HIP(hipStreamSynchronize(s));
+    return op.release();
+}
+
+size_t footprint_estimate(const hdm_params& p, int max_basis) {
+    int depth = 0;
+    while ((p.n + (int64_t(1) << depth) - 1) / (int64_t(1) << depth) > p.leaf_m) ++depth;
+    const int64_t L = int64_t(1) << depth;
+    const int64_t leaf = (p.n + L - 1) / L;
+    const int64_t extra = static_cast<int64_t>(std::ceil(p.budget * static_cast<double>(L)));
+    const int64_t near_per_leaf = std::min<int64_t>(L, 2 * extra + 1);
+    const int64_t ld = (leaf + 7) / 8 * 8;
+    const int64_t near_elems = L * ld * leaf * near_per_leaf;
+    const size_t e_near = dtype_size(p.near_prec);
+    const int64_t s2 = 2 * static_cast<int64_t>(p.max_rank_s);
+    const int64_t cmax = std::max(leaf, s2);
+    size_t b = 0;
+    b += static_cast<size_t>(near_elems) * (8 + e_near);                 // float64 tiles for the degrees + eval copy
+    b += static_cast<size_t>(p.n) * p.dim * dtype_size(p.x_dtype);       // points
+    b += static_cast<size_t>(p.n) * p.knn_k * 12;                          // neighbour lists
+    b += static_cast<size_t>(L) * p.n * 4 + static_cast<size_t>(L) * s2 * cmax * 8 * 2;   // skeletonisation workspaces
+    b += static_cast<size_t>(2 * L) * p.max_rank_s * cmax * 12;           // interpolation matrices and far tiles
+    b += static_cast<size_t>(p.n) * (max_basis + 8) * 8;                  // Lanczos basis and vectors
+    return b;
+}
+
+
 }  // namespace hdm
 
-struct hdm_ctx_s : hdm::Ctx {};
-struct hdm_op_s : hdm::Op {};
 
 namespace {
 
-thread_local std::string g_err;
+using hdm::g_err;
 
 template <typename F>
 hdm_status guarded(F&& f) {
@@ -91,30 +172,6 @@ hdm_status guarded(F&& f) {
 inline hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
 
 bool prec_ok(int p) { return p == HDM_F64 || p == HDM_F32 || p == HDM_BF16 || p == HDM_F16; }
-
-void validate(const hdm_params& p) {
-    using hdm::fail;
-    if (p.n < 2) fail(HDM_EINVAL, "n must be >= 2");
-    if (p.n > (int64_t(1) << 30)) fail(HDM_EINVAL, "n must be < 2^30");
-    if (p.dim < 1) fail(HDM_EINVAL, "dim must be >= 1");
-    if (p.x_dtype != HDM_F64 && p.x_dtype != HDM_U8) fail(HDM_EINVAL, "x_dtype must be HDM_F64 or HDM_U8");
-    if (!(p.eps > 0.0) || !std::isfinite(p.eps)) fail(HDM_EINVAL, "eps must be finite and > 0");
-    if (p.alpha != 1.0) fail(HDM_EINVAL, "only alpha = 1 is supported");
-    if (p.leaf_m < 2) fail(HDM_EINVAL, "leaf_m must be >= 2");
-    if (p.max_rank_s < 1 || p.max_rank_s > 512) fail(HDM_EINVAL, "max_rank_s must be in [1, 512]");
-    if (!(p.tau >= 0.0) || !std::isfinite(p.tau)) fail(HDM_EINVAL, "tau must be finite and >= 0");
-    if (p.knn_k < 1 || p.knn_k > 64) fail(HDM_EINVAL, "knn_k must be in [1, 64]");
-    if (p.knn_iters < 1 || p.knn_iters > 1000) fail(HDM_EINVAL, "knn_iters must be in [1, 1000]");
-    if (!(p.budget >= 0.0 && p.budget <= 1.0)) fail(HDM_EINVAL, "budget must be in [0, 1]");
-    if (!prec_ok(p.near_prec) || !prec_ok(p.far_prec)) fail(HDM_EINVAL, "bad tile precision");
-    if ((p.near_prec == HDM_F64) != (p.far_prec == HDM_F64))
-        fail(HDM_EINVAL, "float64 tiles cannot be mixed with reduced-precision tiles");
-    int depth = 0;
-    while ((p.n + (int64_t(1) << depth) - 1) / (int64_t(1) << depth) > p.leaf_m) ++depth;
-    if (depth > 16) fail(HDM_EINVAL, "tree deeper than 16 levels: raise leaf_m");
-    if ((p.n >> depth) <= p.knn_k) fail(HDM_EINVAL, "every leaf must hold more than knn_k points");
-    if (((p.n + (int64_t(1) << depth) - 1) >> depth) > 2048) fail(HDM_EINVAL, "leaves must hold <= 2048 points");
-}
 
 void set_device(int dev) { HDM_HIP(hipSetDevice(dev)); }
 
@@ -189,26 +246,9 @@ hdm_status hdm_compress(hdm_ctx ctx, const void* X, int x_on_device, const hdm_p
                         hdm_op* out) {
     return guarded([&] {
         HDM_CHECK(ctx && X && params && out, HDM_EINVAL, "NULL argument");
-        validate(*params);
+        hdm::validate_params(*params);
         set_device(ctx->device);
-        hipStream_t s = as_stream(stream);
-        std::unique_ptr<hdm_op_s> op(new hdm_op_s());
-        op->ctx = ctx;
-        op->prm = *params;
-        if (!x_on_device && params->x_dtype == HDM_F64) {
-            const double* x = static_cast<const double*>(X);
-            const int64_t cnt = params->n * params->dim;
-            for (int64_t i = 0; i < cnt; ++i)
-                HDM_CHECK(std::isfinite(x[i]), HDM_EINVAL, "points contain NaN or Inf");
-        }
-        {
-            hdm::PhaseScope ph(ctx, HDM_PHASE_COMPRESS, s);
-            hdm::compress_operator(*op, X, x_on_device, s);
-            hdm::build_eval_plan(*op, s);
-            hdm::normalise_degrees(*op, s);
-            hdm::convert_eval_precision(*op, s);
-        }
-        HDM_HIP(hipStreamSynchronize(s));
+        std::unique_ptr<hdm_op_s> op(hdm::make_operator(ctx, X, x_on_device, *params, as_stream(stream)));
         const size_t fp = op->footprint();
         HDM_CHECK(ctx->budget == 0 || ctx->resident + fp <= ctx->budget, HDM_ENOMEM,
                   "operator exceeds the context's memory budget");

@@ -60,14 +60,37 @@ __device__ inline A wave_sum(A v) {
     return v;
 }
 
-// ---- vector staging ------------------------------------------------------
+// ---- batches ----------------------------------------------------------------
+// Per-launch arguments of a batched product, passed by value: the operators'
+// descriptors, the prefix of work units over the operators, and each
+// operator's vectors.
+struct Batch {
+    int nops, nrhs;
+    const OpDev* op[kMaxBatch];
+    int64_t pre[kMaxBatch + 1];
+    int32_t arg[kMaxBatch];       // per operator: tree level (N2S) or normalised flag (prep, combine)
+    const double* x[kMaxBatch];
+    double* y[kMaxBatch];
+};
+
+__device__ inline int batch_op(const Batch& b, int64_t unit) {
+    int o = 0;
+    while (o + 1 < b.nops && unit >= b.pre[o + 1]) ++o;
+    return o;
+}
+
+// ---- vector staging: w = c * x in tree order ------------------------------------
 template <typename V>
-__global__ void k_prep(int64_t n, int nrhs, const double* x, const int32_t* perm, const double* scale, V* w) {
-    const int64_t pos = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-    if (pos >= n) return;
-    const int32_t i = perm[pos];
-    const double sc = scale ? scale[pos] : 1.0;
-    for (int c = 0; c < nrhs; ++c) w[c * n + pos] = static_cast<V>(sc * x[c * n + i]);
+__global__ void k_prep(Batch b) {
+    const int64_t u = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    if (u >= b.pre[b.nops]) return;
+    const int o = batch_op(b, u);
+    const OpDev& D = *b.op[o];
+    const int64_t pos = u - b.pre[o];
+    const int32_t i = D.perm[pos];
+    const double sc = b.arg[o] ? D.c[pos] : 1.0;
+    V* w = static_cast<V*>(D.w);
+    for (int c = 0; c < b.nrhs; ++c) w[c * D.n + pos] = static_cast<V>(sc * b.x[o][c * D.n + i]);
 }
 
 // ---- dot products of one row per wave (lanes stride the columns) -------------
@@ -88,40 +111,45 @@ __device__ inline V row_dot(const TM* row, int nc, GX x) {
     return wave_sum(acc);
 }
 
-// ---- N2S: one level of skeleton weights, one wave per (node, row) -------------
+// ---- N2S: one tree level per operator (arg = level), one wave per skeleton row --
 //   leaf:  w~_h = P_h w_h;   inner: w~_h = P_h [w~_left; w~_right]
 template <typename V, typename TP>
-__global__ void k_n2s(const RowTask* tasks, int64_t ntask, int leaf, const int64_t* start, const int32_t* ncand,
-                      const int64_t* skoff, const int64_t* poff, const TP* P, const V* w, int64_t ldw, V* skw,
-                      int64_t ldsk, int nrhs) {
-    const int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x / kWave) + threadIdx.x / kWave;
-    if (t >= ntask) return;
-    const RowTask T = tasks[t];
-    const int nc = ncand[T.h];
-    const TP* row = P + poff[T.h] + static_cast<int64_t>(T.i) * nc;
-    for (int c = 0; c < nrhs; ++c) {
-        const V* in = leaf ? w + c * ldw + start[T.h] : skw + c * ldsk + skoff[2 * T.h];
+__global__ void k_n2s(Batch b) {
+    const int64_t u = blockIdx.x * static_cast<int64_t>(blockDim.x / kWave) + threadIdx.x / kWave;
+    if (u >= b.pre[b.nops]) return;
+    const int o = batch_op(b, u);
+    const OpDev& D = *b.op[o];
+    const int lvl = b.arg[o];
+    const RowTask T = D.rows[D.row_begin[lvl] + (u - b.pre[o])];
+    const int nc = D.ncand[T.h];
+    const TP* row = static_cast<const TP*>(D.P) + D.poff[T.h] + static_cast<int64_t>(T.i) * nc;
+    V* skw = static_cast<V*>(D.skw);
+    for (int c = 0; c < b.nrhs; ++c) {
+        const V* in = lvl == D.depth ? static_cast<const V*>(D.w) + c * D.n + D.start[T.h]
+                                     : skw + c * D.ldsk + D.skoff[2 * T.h];
         const V acc = row_dot<V>(row, nc, [&](int j) { return in[j]; });
-        if (threadIdx.x % kWave == 0) skw[c * ldsk + skoff[T.h] + T.i] = acc;
+        if (threadIdx.x % kWave == 0) skw[c * D.ldsk + D.skoff[T.h] + T.i] = acc;
     }
 }
 
-// ---- S2S: far field between skeletons, one wave per (node, row) -----------------
+// ---- S2S: far field between skeletons, one wave per skeleton row ----------------
 template <typename V, typename TF>
-__global__ void k_s2s(const RowTask* tasks, int64_t ntask, const int64_t* skoff, const int64_t* boff,
-                      const int32_t* cols, const int64_t* colbase, const int32_t* colmap, const TF* far,
-                      const float* fscale, const V* skw, V* sku, int64_t ldsk, int nrhs) {
-    const int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x / kWave) + threadIdx.x / kWave;
-    if (t >= ntask) return;
-    const RowTask T = tasks[t];
-    const int nc = cols[T.h];
-    const TF* row = far + boff[T.h] + static_cast<int64_t>(T.i) * nc;
-    const int32_t* cm = colmap + colbase[T.h];
-    const V sc = fscale ? static_cast<V>(fscale[T.h]) : V(1);
-    for (int c = 0; c < nrhs; ++c) {
-        const V* x = skw + c * ldsk;
+__global__ void k_s2s(Batch b) {
+    const int64_t u = blockIdx.x * static_cast<int64_t>(blockDim.x / kWave) + threadIdx.x / kWave;
+    if (u >= b.pre[b.nops]) return;
+    const int o = batch_op(b, u);
+    const OpDev& D = *b.op[o];
+    const RowTask T = D.rows[u - b.pre[o]];
+    const int nc = D.far_cols[T.h];
+    const TF* row = static_cast<const TF*>(D.far) + D.far_off[T.h] + static_cast<int64_t>(T.i) * nc;
+    const int32_t* cm = D.far_colmap + D.far_colbase[T.h];
+    const V sc = D.fscale ? static_cast<V>(D.fscale[T.h]) : V(1);
+    const V* skw = static_cast<const V*>(D.skw);
+    V* sku = static_cast<V*>(D.sku);
+    for (int c = 0; c < b.nrhs; ++c) {
+        const V* x = skw + c * D.ldsk;
         const V acc = row_dot<V>(row, nc, [&](int j) { return x[cm[j]]; });
-        if (threadIdx.x % kWave == 0) sku[c * ldsk + skoff[T.h] + T.i] = acc * sc;
+        if (threadIdx.x % kWave == 0) sku[c * D.ldsk + D.skoff[T.h] + T.i] = acc * sc;
     }
 }
 
@@ -130,18 +158,19 @@ __global__ void k_s2s(const RowTask* tasks, int64_t ntask, const int64_t* skoff,
 // each 64*RPL-row pass over the item's rows; the item's columns are consecutive
 // tree positions, so w is read as a wave-uniform value.
 template <typename V, typename TN>
-__global__ void __launch_bounds__(kBlock) k_l2l(const NearItem* items, int64_t nitems, const TN* tiles,
-                                                const float* tscale, const V* w, int64_t ldw, V* part,
-                                                int64_t ldp, int nrhs) {
+__global__ void __launch_bounds__(kBlock) k_l2l(Batch b) {
     constexpr int RPL = 16 / sizeof(TN);
-    const int64_t it = blockIdx.x * static_cast<int64_t>(blockDim.x / kWave) + threadIdx.x / kWave;
-    if (it >= nitems) return;
-    const NearItem I = items[it];
+    const int64_t u = blockIdx.x * static_cast<int64_t>(blockDim.x / kWave) + threadIdx.x / kWave;
+    if (u >= b.pre[b.nops]) return;
+    const int o = batch_op(b, u);
+    const OpDev& D = *b.op[o];
+    const NearItem I = D.items[u - b.pre[o]];
     const int lane = threadIdx.x % kWave;
     const int rend = min(I.ld, I.row0 + I.nrows);
-    const V sc = tscale ? static_cast<V>(tscale[I.tile]) : V(1);
-    for (int c = 0; c < nrhs; ++c) {
-        const V* wc = w + c * ldw + I.col_pos;
+    const V sc = D.nscale ? static_cast<V>(D.nscale[I.tile]) : V(1);
+    const TN* tiles = static_cast<const TN*>(D.near);
+    for (int c = 0; c < b.nrhs; ++c) {
+        const V* wc = static_cast<const V*>(D.w) + c * D.n + I.col_pos;
         for (int r0 = I.row0; r0 < rend; r0 += kWave * RPL) {
             const int row = r0 + lane * RPL;
             if (row >= rend) continue;
@@ -172,7 +201,7 @@ __global__ void __launch_bounds__(kBlock) k_l2l(const NearItem* items, int64_t n
 #pragma unroll
                 for (int r = 0; r < RPL; ++r) acc[r] += val<V>(v0[r]) * w0;
             }
-            V* out = part + c * ldp + I.part_off + row;
+            V* out = static_cast<V*>(D.part) + c * D.ldp + I.part_off + row;
 #pragma unroll
             for (int r = 0; r < RPL; ++r) out[r] = acc[r];
         }
@@ -186,54 +215,56 @@ __global__ void __launch_bounds__(kBlock) k_l2l(const NearItem* items, int64_t n
 // partial sums of the leaf's rows and writes the scaled result in original order.
 constexpr int kMaxRank = 512;
 template <typename V, typename TP>
-__global__ void __launch_bounds__(kBlock) k_combine(const LeafPlan* leaves, const V* part, int64_t ldp, int depth,
-                                                    const int32_t* rank, const int32_t* ncand, const int64_t* skoff,
-                                                    const int64_t* poff, const TP* P, const V* sku, int64_t ldsk,
-                                                    const int32_t* perm, const double* scale, int64_t n, double* y,
-                                                    int nrhs) {
+__global__ void __launch_bounds__(kBlock) k_combine(Batch b) {
     __shared__ V tot[2][kMaxRank];
-    const LeafPlan lp = leaves[blockIdx.x];
-    for (int c = 0; c < nrhs; ++c) {
+    const int64_t u = blockIdx.x;
+    const int o = batch_op(b, u);
+    const OpDev& D = *b.op[o];
+    const LeafPlan lp = D.leaves[u - b.pre[o]];
+    const TP* P = static_cast<const TP*>(D.P);
+    const V* sku = static_cast<const V*>(D.sku);
+    const int depth = D.row_total > 0 ? D.depth : 0;
+    for (int c = 0; c < b.nrhs; ++c) {
         int cur = 0;
         int rleaf = 0;
         if (depth >= 1) {
             const int64_t a1 = lp.heap >> (depth - 1);
-            for (int i = threadIdx.x; i < rank[a1]; i += blockDim.x) tot[0][i] = sku[c * ldsk + skoff[a1] + i];
+            for (int i = threadIdx.x; i < D.rank[a1]; i += blockDim.x) tot[0][i] = sku[c * D.ldsk + D.skoff[a1] + i];
             __syncthreads();
             for (int lvl = 2; lvl <= depth; ++lvl) {
                 const int64_t node = lp.heap >> (depth - lvl), par = node >> 1;
-                const int rp = rank[par], ncp = ncand[par], rn = rank[node];
-                const int off = (node & 1) ? rank[2 * par] : 0;
-                const TP* Pm = P + poff[par] + off;
+                const int rp = D.rank[par], ncp = D.ncand[par], rn = D.rank[node];
+                const int off = (node & 1) ? D.rank[2 * par] : 0;
+                const TP* Pm = P + D.poff[par] + off;
                 for (int j = threadIdx.x; j < rn; j += blockDim.x) {
                     V acc = 0;
                     int i = 0;
                     for (; i + 8 <= rp; i += 8) {
                         TP pv[8];
 #pragma unroll
-                        for (int u = 0; u < 8; ++u) pv[u] = Pm[static_cast<int64_t>(i + u) * ncp + j];
+                        for (int q = 0; q < 8; ++q) pv[q] = Pm[static_cast<int64_t>(i + q) * ncp + j];
 #pragma unroll
-                        for (int u = 0; u < 8; ++u) acc += static_cast<V>(pv[u]) * tot[cur][i + u];
+                        for (int q = 0; q < 8; ++q) acc += static_cast<V>(pv[q]) * tot[cur][i + q];
                     }
                     for (; i < rp; ++i) acc += static_cast<V>(Pm[static_cast<int64_t>(i) * ncp + j]) * tot[cur][i];
-                    tot[cur ^ 1][j] = sku[c * ldsk + skoff[node] + j] + acc;
+                    tot[cur ^ 1][j] = sku[c * D.ldsk + D.skoff[node] + j] + acc;
                 }
                 __syncthreads();
                 cur ^= 1;
             }
-            rleaf = rank[lp.heap];
+            rleaf = D.rank[lp.heap];
         }
-        const TP* Pl = P + poff[lp.heap];
-        const V* pc = part + c * ldp + lp.part_off;
+        const TP* Pl = P + D.poff[lp.heap];
+        const V* pc = static_cast<const V*>(D.part) + c * D.ldp + lp.part_off;
         for (int j = threadIdx.x; j < lp.rows; j += blockDim.x) {
             V near = 0;
             int q = 0;
             for (; q + 8 <= lp.nitems; q += 8) {
                 V x[8];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) x[u] = pc[static_cast<int64_t>(q + u) * lp.ld + j];
+                for (int t = 0; t < 8; ++t) x[t] = pc[static_cast<int64_t>(q + t) * lp.ld + j];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) near += x[u];
+                for (int t = 0; t < 8; ++t) near += x[t];
             }
             for (; q < lp.nitems; ++q) near += pc[static_cast<int64_t>(q) * lp.ld + j];
             V f = 0;
@@ -241,14 +272,14 @@ __global__ void __launch_bounds__(kBlock) k_combine(const LeafPlan* leaves, cons
             for (; i + 8 <= rleaf; i += 8) {
                 TP pv[8];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) pv[u] = Pl[static_cast<int64_t>(i + u) * lp.rows + j];
+                for (int t = 0; t < 8; ++t) pv[t] = Pl[static_cast<int64_t>(i + t) * lp.rows + j];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) f += static_cast<V>(pv[u]) * tot[cur][i + u];
+                for (int t = 0; t < 8; ++t) f += static_cast<V>(pv[t]) * tot[cur][i + t];
             }
             for (; i < rleaf; ++i) f += static_cast<V>(Pl[static_cast<int64_t>(i) * lp.rows + j]) * tot[cur][i];
             const int64_t pos = lp.start + j;
-            const double sc = scale ? scale[pos] : 1.0;
-            y[c * n + perm[pos]] = sc * static_cast<double>(near + f);
+            const double sc = b.arg[o] ? D.c[pos] : 1.0;
+            b.y[o][c * D.n + D.perm[pos]] = sc * static_cast<double>(near + f);
         }
         __syncthreads();
     }
@@ -322,29 +353,85 @@ size_t Op::footprint() const {
     return xf.bytes() + xu.bytes() + perm.bytes() + iperm.bytes() + knn_idx.bytes() + knn_d2.bytes() + skel.bytes() +
            P64.bytes() + P32.bytes() + rows.bytes() + near64.bytes() + nearT.bytes() + near_scale.bytes() +
            far64.bytes() + farT.bytes() + far_scale.bytes() + far_colmap.bytes() + d_items.bytes() +
-           d_leaves.bytes() + q.bytes() + d.bytes() + c.bytes() + w_tree.bytes() + u_tree.bytes() + skw.bytes() +
-           sku.bytes() + part.bytes();
+           d_leaves.bytes() + q.bytes() + d.bytes() + c.bytes() + w_tree.bytes() + skw.bytes() + sku.bytes() +
+           part.bytes() + d_row_tasks.bytes();
+}
+
+void Lane::init() {
+    if (!side) HDM_HIP(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
+    if (!fork) HDM_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+    if (!join) HDM_HIP(hipEventCreateWithFlags(&join, hipEventDisableTiming));
+}
+
+Lane::~Lane() {
+    if (side) (void)hipStreamSynchronize(side);
+    if (fork) (void)hipEventDestroy(fork);
+    if (join) (void)hipEventDestroy(join);
+    if (side) (void)hipStreamDestroy(side);
 }
 
 static int rows_per_lane(int dt) { return 16 / static_cast<int>(dtype_size(dt)); }
 
+// workspaces of the product for up to nrhs right-hand sides (8-byte elements
+// so that either vector type fits)
+static void ensure_ws(Op& op, int nrhs) {
+    if (op.ws_nrhs >= nrhs) return;
+    op.w_tree.alloc(static_cast<size_t>(op.n) * nrhs * 8);
+    op.skw.alloc(static_cast<size_t>(std::max<int64_t>(op.nskel, 1)) * nrhs * 8);
+    op.sku.alloc(static_cast<size_t>(std::max<int64_t>(op.nskel, 1)) * nrhs * 8);
+    op.part.alloc(static_cast<size_t>(std::max<int64_t>(op.part_elems, 1)) * nrhs * 8);
+    op.ws_nrhs = nrhs;
+}
+
+// (re)writes both descriptors of the operator into device memory
+static void publish_descriptors(Op& op, hipStream_t s) {
+    auto fill = [&](OpDev& D, bool f64) {
+        D.n = op.n;
+        D.depth = op.depth;
+        D.L = op.L;
+        D.perm = op.perm.get();
+        D.c = op.c.get();
+        D.start = op.d_start.get();
+        D.rank = op.d_rank.get();
+        D.ncand = op.d_ncand.get();
+        D.skoff = op.d_skoff.get();
+        D.poff = op.d_poff.get();
+        D.P = f64 ? static_cast<const void*>(op.P64.get()) : static_cast<const void*>(op.P32.get());
+        D.rows = op.d_row_tasks.get();
+        for (int l = 0; l < kMaxLevels; ++l) {
+            D.row_begin[l] = l < static_cast<int>(op.row_begin.size()) ? op.row_begin[l] : 0;
+            D.row_count[l] = l < static_cast<int>(op.row_count.size()) ? op.row_count[l] : 0;
+        }
+        D.row_total = op.row_total;
+        D.far_off = op.d_far_block_off.get();
+        D.far_cols = op.d_far_cols.get();
+        D.far_colbase = op.d_far_colbase.get();
+        D.far_colmap = op.far_colmap.get();
+        D.far = f64 ? static_cast<const void*>(op.far64.get()) : static_cast<const void*>(op.farT.get());
+        D.fscale = (!f64 && op.far_scale.n) ? op.far_scale.get() : nullptr;
+        D.items = op.d_items.get();
+        D.nitems = static_cast<int64_t>(op.items.size());
+        D.near = f64 ? static_cast<const void*>(op.near64.get()) : static_cast<const void*>(op.nearT.get());
+        D.nscale = (!f64 && op.near_scale.n) ? op.near_scale.get() : nullptr;
+        D.leaves = op.d_leaves.get();
+        D.w = op.w_tree.get();
+        D.skw = op.skw.get();
+        D.sku = op.sku.get();
+        D.part = op.part.get();
+        D.ldsk = std::max<int64_t>(op.nskel, 1);
+        D.ldp = std::max<int64_t>(op.part_elems, 1);
+    };
+    fill(op.host64, true);
+    fill(op.hostT, false);
+    if (!op.dev64.n) op.dev64.alloc(1);
+    if (!op.devT.n) op.devT.alloc(1);
+    op.dev64.upload(&op.host64, 1, s);
+    op.devT.upload(&op.hostT, 1, s);
+    HDM_HIP(hipStreamSynchronize(s));
+}
+
 void build_eval_plan(Op& op, hipStream_t s) {
     const int64_t L = op.L;
-    op.levels.assign(op.depth + 1, NodeLevel{});
-    std::vector<int32_t> heaps;
-    op.heaps_off.assign(op.depth + 2, 0);
-    for (int lvl = 0; lvl <= op.depth; ++lvl) {
-        op.heaps_off[lvl] = static_cast<int64_t>(heaps.size());
-        op.levels[lvl].level = lvl;
-        for (int64_t h = int64_t(1) << lvl; h < (int64_t(1) << (lvl + 1)); ++h) {
-            if (lvl >= 1) {
-                op.levels[lvl].heap.push_back(static_cast<int32_t>(h));
-                heaps.push_back(static_cast<int32_t>(h));
-            }
-        }
-    }
-    op.heaps_off[op.depth + 1] = static_cast<int64_t>(heaps.size());
-    op.d_heaps = to_device(heaps, s);
     op.d_rank = to_device(op.rank, s);
     op.d_ncand = to_device(op.ncand, s);
     op.d_skoff = to_device(op.skoff, s);
@@ -353,8 +440,7 @@ void build_eval_plan(Op& op, hipStream_t s) {
     op.d_far_cols = to_device(op.far_cols, s);
     op.d_far_colbase = to_device(op.far_colbase, s);
     // near-field items: per leaf, per row group, per near tile, per column chunk
-    const int rpl = rows_per_lane(op.prm.near_prec);
-    const int rg = kWave * rpl;
+    const int rg = kWave * rows_per_lane(op.prm.near_prec);
     op.near_rows_per_group = rg;
     op.items.clear();
     op.leaves.clear();
@@ -403,8 +489,8 @@ void build_eval_plan(Op& op, hipStream_t s) {
     // one row task per skeleton row, grouped by level from the leaves up; the
     // same list, taken whole, gives the far-field (S2S) rows
     std::vector<RowTask> tasks;
-    op.row_begin.assign(op.depth + 1, 0);
-    op.row_count.assign(op.depth + 1, 0);
+    op.row_begin.assign(kMaxLevels, 0);
+    op.row_count.assign(kMaxLevels, 0);
     for (int lvl = op.depth; lvl >= 1; --lvl) {
         op.row_begin[lvl] = static_cast<int64_t>(tasks.size());
         for (int64_t h = int64_t(1) << lvl; h < (int64_t(1) << (lvl + 1)); ++h)
@@ -413,124 +499,130 @@ void build_eval_plan(Op& op, hipStream_t s) {
     }
     op.row_total = static_cast<int64_t>(tasks.size());
     op.d_row_tasks = to_device(tasks, s);
-    if (!op.side) HDM_HIP(hipStreamCreateWithFlags(&op.side, hipStreamNonBlocking));
-    if (!op.ev_fork) HDM_HIP(hipEventCreateWithFlags(&op.ev_fork, hipEventDisableTiming));
-    if (!op.ev_join) HDM_HIP(hipEventCreateWithFlags(&op.ev_join, hipEventDisableTiming));
-    HDM_HIP(hipStreamSynchronize(s));
-}
-
-Op::~Op() {
-    if (side) (void)hipStreamSynchronize(side);
-    if (ev_fork) (void)hipEventDestroy(ev_fork);
-    if (ev_join) (void)hipEventDestroy(ev_join);
-    if (side) (void)hipStreamDestroy(side);
-}
-
-static void ensure_ws(Op& op, int nrhs, size_t vbytes) {
-    if (op.ws_nrhs >= nrhs && op.w_tree.bytes() >= static_cast<size_t>(op.n) * nrhs * vbytes) return;
-    op.w_tree.alloc(static_cast<size_t>(op.n) * nrhs * 8);
-    op.skw.alloc(static_cast<size_t>(std::max<int64_t>(op.nskel, 1)) * nrhs * 8);
-    op.sku.alloc(static_cast<size_t>(std::max<int64_t>(op.nskel, 1)) * nrhs * 8);
-    op.part.alloc(static_cast<size_t>(std::max<int64_t>(op.part_elems, 1)) * nrhs * 8);
-    op.ws_nrhs = nrhs;
+    op.lane.init();
+    ensure_ws(op, 1);
+    publish_descriptors(op, s);
 }
 
 template <typename V, typename TN, typename TF, typename TP>
-static void apply_t(Op& op, bool normalised, const TN* near, const float* nscale, const TF* far, const float* fscale,
-                    const TP* P, const double* x, double* y, int nrhs, hipStream_t s) {
-    ensure_ws(op, nrhs, sizeof(V));
-    const int64_t n = op.n;
-    V* w = reinterpret_cast<V*>(op.w_tree.get());
-    V* skw = reinterpret_cast<V*>(op.skw.get());
-    V* sku = reinterpret_cast<V*>(op.sku.get());
-    V* part = reinterpret_cast<V*>(op.part.get());
-    const int64_t ldsk = std::max<int64_t>(op.nskel, 1);
-    const int64_t ldp = std::max<int64_t>(op.part_elems, 1);
-    const double* scale = normalised ? op.c.get() : nullptr;
-    Ctx* cx = op.ctx;
-    {
-        KernelEvents ev(cx, HDM_PHASE_PREP);
-        hipExtLaunchKernelGGL((k_prep<V>), dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, s, ev.start, ev.stop, 0, n, nrhs,
-                              x, op.perm.get(), scale, w);
+static void apply_t(const ApplyReq* reqs, int nops, bool f64, int normalised, int nrhs, hipStream_t s, Lane& lane,
+                    Ctx* cx) {
+    Batch b{};
+    b.nops = nops;
+    b.nrhs = nrhs;
+    for (int o = 0; o < nops; ++o) {
+        b.op[o] = f64 ? reqs[o].op->dev64.get() : reqs[o].op->devT.get();
+        b.x[o] = reqs[o].x;
+        b.y[o] = reqs[o].y;
     }
-    // the upward pass and the far field run on a side stream while the near field streams its tiles
-    const bool tree = op.nskel > 0;
+    auto prefix = [&](auto count) {
+        b.pre[0] = 0;
+        for (int o = 0; o < nops; ++o) b.pre[o + 1] = b.pre[o] + count(*reqs[o].op, o);
+        return b.pre[nops];
+    };
     const int wpb = kBlock / kWave;
+    {   // gather + scale into tree order
+        for (int o = 0; o < nops; ++o) b.arg[o] = normalised;
+        const int64_t tot = prefix([](const Op& op, int) { return op.n; });
+        KernelEvents ev(cx, HDM_PHASE_PREP);
+        hipExtLaunchKernelGGL((k_prep<V>), dim3(ceil_div(tot, kBlock)), dim3(kBlock), 0, s, ev.start, ev.stop, 0, b);
+    }
+    bool tree = false;
+    int maxdepth = 0;
+    for (int o = 0; o < nops; ++o) {
+        tree = tree || reqs[o].op->nskel > 0;
+        maxdepth = std::max(maxdepth, reqs[o].op->depth);
+    }
     if (tree) {
-        HDM_HIP(hipEventRecord(op.ev_fork, s));
-        HDM_HIP(hipStreamWaitEvent(op.side, op.ev_fork, 0));
-        {
-            PhaseScope ph(cx, HDM_PHASE_N2S, op.side);
-            for (int lvl = op.depth; lvl >= 1; --lvl) {
-                const int64_t t0 = op.row_begin[lvl], nt = op.row_count[lvl];
-                if (nt == 0) continue;
-                hipLaunchKernelGGL((k_n2s<V, TP>), dim3(ceil_div(nt, wpb)), dim3(kBlock), 0, op.side,
-                                   op.d_row_tasks.get() + t0, nt, lvl == op.depth ? 1 : 0, op.d_start.get(),
-                                   op.d_ncand.get(), op.d_skoff.get(), op.d_poff.get(), P, w, n, skw, ldsk, nrhs);
+        HDM_HIP(hipEventRecord(lane.fork, s));
+        HDM_HIP(hipStreamWaitEvent(lane.side, lane.fork, 0));
+        {   // N2S: step k processes level depth - k of every operator
+            PhaseScope ph(cx, HDM_PHASE_N2S, lane.side);
+            for (int k = 0; k < maxdepth; ++k) {
+                for (int o = 0; o < nops; ++o) b.arg[o] = reqs[o].op->depth - k;
+                const int64_t tot = prefix([&](const Op& op, int) {
+                    const int lvl = op.depth - k;
+                    return lvl >= 1 ? op.row_count[lvl] : int64_t(0);
+                });
+                if (tot == 0) continue;
+                hipLaunchKernelGGL((k_n2s<V, TP>), dim3(ceil_div(tot, wpb)), dim3(kBlock), 0, lane.side, b);
             }
         }
         {
+            const int64_t tot = prefix([](const Op& op, int) { return op.row_total; });
             KernelEvents ev(cx, HDM_PHASE_S2S);
-            const int64_t nt = op.row_total;
-            hipExtLaunchKernelGGL((k_s2s<V, TF>), dim3(ceil_div(nt, wpb)), dim3(kBlock), 0, op.side, ev.start, ev.stop,
-                                  0, op.d_row_tasks.get(), nt, op.d_skoff.get(), op.d_far_block_off.get(),
-                               op.d_far_cols.get(), op.d_far_colbase.get(), op.far_colmap.get(), far, fscale, skw, sku,
-                               ldsk, nrhs);
+            if (tot > 0)
+                hipExtLaunchKernelGGL((k_s2s<V, TF>), dim3(ceil_div(tot, wpb)), dim3(kBlock), 0, lane.side, ev.start,
+                                      ev.stop, 0, b);
         }
-        HDM_HIP(hipEventRecord(op.ev_join, op.side));
+        HDM_HIP(hipEventRecord(lane.join, lane.side));
     }
     {
+        const int64_t tot = prefix([](const Op& op, int) { return static_cast<int64_t>(op.items.size()); });
         KernelEvents ev(cx, HDM_PHASE_L2L);
-        const int64_t nit = static_cast<int64_t>(op.items.size());
-        hipExtLaunchKernelGGL((k_l2l<V, TN>), dim3(ceil_div(nit, wpb)), dim3(kBlock), 0, s, ev.start, ev.stop, 0,
-                              op.d_items.get(), nit, near, nscale, w, n, part, ldp, nrhs);
+        hipExtLaunchKernelGGL((k_l2l<V, TN>), dim3(ceil_div(tot, wpb)), dim3(kBlock), 0, s, ev.start, ev.stop, 0, b);
     }
-    if (tree) HDM_HIP(hipStreamWaitEvent(s, op.ev_join, 0));
+    if (tree) HDM_HIP(hipStreamWaitEvent(s, lane.join, 0));
     {
+        for (int o = 0; o < nops; ++o) b.arg[o] = normalised;
+        const int64_t tot = prefix([](const Op& op, int) { return static_cast<int64_t>(op.L); });
         KernelEvents ev(cx, HDM_PHASE_COMBINE);
-        hipExtLaunchKernelGGL((k_combine<V, TP>), dim3(op.L), dim3(kBlock), 0, s, ev.start, ev.stop, 0,
-                              op.d_leaves.get(), part, ldp,
-                           tree ? op.depth : 0, op.d_rank.get(), op.d_ncand.get(), op.d_skoff.get(), op.d_poff.get(),
-                           P, sku, ldsk, op.perm.get(), scale, n, y, nrhs);
+        hipExtLaunchKernelGGL((k_combine<V, TP>), dim3(tot), dim3(kBlock), 0, s, ev.start, ev.stop, 0, b);
     }
     check_launch("apply");
 }
 
-void apply(Op& op, int normalised, bool exact64, const double* x, double* y, int nrhs, hipStream_t s) {
-    if (exact64 || (op.prm.near_prec == HDM_F64 && op.prm.far_prec == HDM_F64)) {
-        HDM_CHECK(op.near64.n > 0 || op.near_elems == 0, HDM_EINTERNAL, "float64 tiles are not resident");
-    HDM_CHECK(op.prm.max_rank_s <= kMaxRank, HDM_EINTERNAL, "rank above the combine kernel's limit");
-        apply_t<double, double, double, double>(op, normalised, op.near64.get(), nullptr, op.far64.get(), nullptr,
-                                                op.P64.get(), x, y, nrhs, s);
+static void apply_dispatch(const ApplyReq* reqs, int nops, bool f64, int normalised, int nrhs, hipStream_t s,
+                           Lane& lane, Ctx* cx) {
+    const Op& op0 = *reqs[0].op;
+    if (f64) {
+        apply_t<double, double, double, double>(reqs, nops, true, normalised, nrhs, s, lane, cx);
         return;
     }
-    const float* ns = op.near_scale.n ? op.near_scale.get() : nullptr;
-    const float* fs = op.far_scale.n ? op.far_scale.get() : nullptr;
-    const float* P = op.P32.get();
-    auto far_dispatch = [&](auto near_ptr) {
-        using TN = std::remove_cv_t<std::remove_pointer_t<decltype(near_ptr)>>;
-        switch (op.prm.far_prec) {
-            case HDM_F32:
-                apply_t<float, TN, float, float>(op, normalised, near_ptr, ns, reinterpret_cast<const float*>(op.farT.get()),
-                                                 fs, P, x, y, nrhs, s);
-                break;
-            case HDM_BF16:
-                apply_t<float, TN, bf16_t, float>(op, normalised, near_ptr, ns,
-                                                  reinterpret_cast<const bf16_t*>(op.farT.get()), fs, P, x, y, nrhs, s);
-                break;
-            case HDM_F16:
-                apply_t<float, TN, f16_t, float>(op, normalised, near_ptr, ns,
-                                                 reinterpret_cast<const f16_t*>(op.farT.get()), fs, P, x, y, nrhs, s);
-                break;
+    auto far_dispatch = [&](auto near_tag) {
+        using TN = decltype(near_tag);
+        switch (op0.prm.far_prec) {
+            case HDM_F32: apply_t<float, TN, float, float>(reqs, nops, false, normalised, nrhs, s, lane, cx); break;
+            case HDM_BF16: apply_t<float, TN, bf16_t, float>(reqs, nops, false, normalised, nrhs, s, lane, cx); break;
+            case HDM_F16: apply_t<float, TN, f16_t, float>(reqs, nops, false, normalised, nrhs, s, lane, cx); break;
             default: fail(HDM_EINVAL, "unsupported far precision with reduced near precision");
         }
     };
-    switch (op.prm.near_prec) {
-        case HDM_F32: far_dispatch(reinterpret_cast<const float*>(op.nearT.get())); break;
-        case HDM_BF16: far_dispatch(reinterpret_cast<const bf16_t*>(op.nearT.get())); break;
-        case HDM_F16: far_dispatch(reinterpret_cast<const f16_t*>(op.nearT.get())); break;
+    switch (op0.prm.near_prec) {
+        case HDM_F32: far_dispatch(float{}); break;
+        case HDM_BF16: far_dispatch(bf16_t{}); break;
+        case HDM_F16: far_dispatch(f16_t{}); break;
         default: fail(HDM_EINVAL, "unsupported near precision");
     }
+}
+
+void apply_batch(const ApplyReq* reqs, int nops, int normalised, int nrhs, hipStream_t s, Lane& lane, Ctx* cx) {
+    HDM_CHECK(nops >= 1 && nops <= kMaxBatch, HDM_EINVAL, "batch size out of range");
+    const Op& op0 = *reqs[0].op;
+    const bool f64 = op0.prm.near_prec == HDM_F64;
+    for (int o = 0; o < nops; ++o) {
+        Op& op = *reqs[o].op;
+        HDM_CHECK(op.prm.near_prec == op0.prm.near_prec && op.prm.far_prec == op0.prm.far_prec, HDM_EINVAL,
+                  "a batch must share its tile precisions");
+        HDM_CHECK(op.prm.max_rank_s <= kMaxRank, HDM_EINTERNAL, "rank above the combine kernel's limit");
+        if (op.ws_nrhs < nrhs) {
+            ensure_ws(op, nrhs);
+            publish_descriptors(op, s);
+        }
+    }
+    apply_dispatch(reqs, nops, f64, normalised, nrhs, s, lane, cx);
+}
+
+void apply(Op& op, int normalised, bool exact64, const double* x, double* y, int nrhs, hipStream_t s) {
+    HDM_CHECK(op.prm.max_rank_s <= kMaxRank, HDM_EINTERNAL, "rank above the combine kernel's limit");
+    if (op.ws_nrhs < nrhs) {
+        ensure_ws(op, nrhs);
+        publish_descriptors(op, s);
+    }
+    const ApplyReq r{&op, x, y};
+    const bool f64 = exact64 || op.prm.near_prec == HDM_F64;
+    HDM_CHECK(!f64 || op.near64.n > 0 || op.near_elems == 0, HDM_EINTERNAL, "float64 tiles are not resident");
+    apply_dispatch(&r, 1, f64, normalised, nrhs, s, op.lane, op.ctx);
 }
 
 // q = K~ 1, d = Q^-1 K~ Q^-1 1, c = 1 / (q sqrt(d)), with float64 tiles
@@ -554,6 +646,7 @@ void normalise_degrees(Op& op, hipStream_t s) {
     bad.download(&hb, 1, s);
     HDM_HIP(hipStreamSynchronize(s));
     HDM_CHECK(hb == 0, HDM_ENUMERIC, "non-positive degree in the alpha = 1 normalisation");
+    publish_descriptors(op, s);   // the descriptors now carry c
 }
 
 template <typename T>
@@ -615,6 +708,7 @@ void convert_eval_precision(Op& op, hipStream_t s) {
     // the float64 tiles were only needed for the degrees
     op.near64.release();
     op.far64.release();
+    publish_descriptors(op, s);
 }
 
 }  // namespace hdm

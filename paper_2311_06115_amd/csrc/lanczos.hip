@@ -314,71 +314,100 @@ __global__ void k_col_fix(double* Phi, int64_t n, const double* nrm, const int64
 
 }  // namespace
 
-hdm_status lanczos_eigs(Op& op, int r, double tol, int block, int max_basis, uint64_t seed, double* evals,
-                        double* evecs, hdm_eig_info_t* info, hipStream_t s) {
-    const auto t0 = std::chrono::steady_clock::now();
-    HDM_CHECK(block == 1, HDM_EINVAL, "only block = 1 is supported by this build");
-    const int64_t n = op.n;
-    HDM_CHECK(r >= 1 && r <= 64 && r <= n, HDM_EINVAL, "r must be in [1, min(64, n)]");
-    if (max_basis <= 0) max_basis = static_cast<int>(std::min<int64_t>(n, 300));
-    max_basis = static_cast<int>(std::min<int64_t>(max_basis, n));
-    HDM_CHECK(max_basis >= r && max_basis <= 1000, HDM_EINVAL, "max_basis must be in [r, 1000]");
-    const int nb = ceil_div(n, kRows);
-    const int ldp = max_basis + 1;
-    DevBuf<double> V(static_cast<size_t>(n) * (max_basis + 1)), y(n), part(static_cast<size_t>(nb) * ldp), h1(ldp),
-        h2(ldp), np(nb), alpha(max_basis), beta(max_basis), theta(r), bound(r), Y(static_cast<size_t>(r) * max_basis),
-        work(static_cast<size_t>(r) * 5 * max_basis);
+void LanczosRun::start(Op& o, int r_, double tol_, int max_basis_, uint64_t seed_, hipStream_t s) {
+    op = &o;
+    n = o.n;
+    HDM_CHECK(r_ >= 1 && r_ <= 64 && r_ <= n, HDM_EINVAL, "r must be in [1, min(64, n)]");
+    int mb = max_basis_ <= 0 ? static_cast<int>(std::min<int64_t>(n, 300)) : max_basis_;
+    mb = static_cast<int>(std::min<int64_t>(mb, n));
+    HDM_CHECK(mb >= r_ && mb <= 1000, HDM_EINVAL, "max_basis must be in [r, 1000]");
+    r = r_;
+    tol = tol_;
+    max_basis = mb;
+    seed = seed_;
+    nb = ceil_div(n, kRows);
+    ldp = max_basis + 1;
+    V.alloc(static_cast<size_t>(n) * (max_basis + 1));
+    y.alloc(n);
+    part.alloc(static_cast<size_t>(nb) * ldp);
+    h1.alloc(ldp);
+    h2.alloc(ldp);
+    np.alloc(nb);
+    alpha.alloc(max_basis);
+    beta.alloc(max_basis);
+    theta.alloc(r);
+    bound.alloc(r);
+    Y.alloc(static_cast<size_t>(r) * max_basis);
+    work.alloc(static_cast<size_t>(r) * 5 * max_basis);
+    h_theta.assign(r, 0.0);
+    h_bound.assign(r, 0.0);
+    j = m = matvecs = 0;
+    converged = finished = false;
+    t0 = std::chrono::steady_clock::now();
     const int gN = ceil_div(n, kBlock);
     hipLaunchKernelGGL(k_start, dim3(gN), dim3(kBlock), 0, s, V.get(), n, seed, 0u);
     hipLaunchKernelGGL(k_norm_partial, dim3(nb), dim3(kBlock), 0, s, V.get(), n, np.get());
     hipLaunchKernelGGL(k_scale_by_norm, dim3(std::min(gN, 1024)), dim3(kBlock), 0, s, V.get(), n, np.get(), nb);
-    std::vector<double> h_theta(r), h_bound(r);
-    int m = 0;
-    bool converged = false;
-    int matvecs = 0;
-    const int check_every = 5;
-    for (int j = 0; j < max_basis; ++j) {
-        double* vj = V.get() + static_cast<int64_t>(j) * n;
-        apply(op, 1, false, vj, y.get(), 1, s);
-        ++matvecs;
-        const int nc = j + 1;
-        {   // CGS2 against the whole basis, alpha_j, beta_j
-            PhaseScope ph(op.ctx, HDM_PHASE_ORTHO, s);
-            hipLaunchKernelGGL(k_gemvt, dim3(nb), dim3(kBlock), 0, s, V.get(), n, nc, y.get(), n, part.get(), ldp);
-            hipLaunchKernelGGL(k_reduce_cols, dim3(ceil_div(nc, 64)), dim3(64), 0, s, part.get(), nb, ldp, nc, h1.get());
-            hipLaunchKernelGGL(k_gemvn, dim3(nb), dim3(kBlock), 0, s, V.get(), n, nc, h1.get(), y.get(), n, nullptr);
-            hipLaunchKernelGGL(k_gemvt, dim3(nb), dim3(kBlock), 0, s, V.get(), n, nc, y.get(), n, part.get(), ldp);
-            hipLaunchKernelGGL(k_reduce_cols, dim3(ceil_div(nc, 64)), dim3(64), 0, s, part.get(), nb, ldp, nc, h2.get());
-            hipLaunchKernelGGL(k_gemvn, dim3(nb), dim3(kBlock), 0, s, V.get(), n, nc, h2.get(), y.get(), n, np.get());
-            hipLaunchKernelGGL(k_alpha_beta, dim3(1), dim3(1), 0, s, h1.get(), h2.get(), j, np.get(), nb, alpha.get(),
-                               beta.get());
-        }
-        check_launch("lanczos step");
-        m = j + 1;
-        const bool last = (j == max_basis - 1);
-        if (m >= r && ((m % check_every) == 0 || last)) {
-            {
-                KernelEvents ev(op.ctx, HDM_PHASE_TRIDIAG);
-                hipExtLaunchKernelGGL(k_tridiag, dim3(ceil_div(r, 4)), dim3(kBlock), 0, s, ev.start, ev.stop, 0,
-                                      alpha.get(), beta.get(), m, r, theta.get(), Y.get(), bound.get(), work.get());
-            }
-            check_launch("tridiagonal eigensolve");
-            theta.download(h_theta.data(), r, s);
-            bound.download(h_bound.data(), r, s);
-            HDM_HIP(hipStreamSynchronize(s));
-            bool ok = true;
-            for (int i = 0; i < r; ++i) ok = ok && (h_bound[i] <= tol * std::fabs(h_theta[i]));
-            if (ok) { converged = true; break; }
-        }
-        if (!last)
-            hipLaunchKernelGGL(k_next, dim3(gN), dim3(kBlock), 0, s, y.get(), beta.get(), j,
-                               V.get() + static_cast<int64_t>(j + 1) * n, n);
+    check_launch("lanczos start");
+}
+
+size_t LanczosRun::bytes() const {
+    return V.bytes() + y.bytes() + part.bytes() + h1.bytes() + h2.bytes() + np.bytes() + alpha.bytes() +
+           beta.bytes() + theta.bytes() + bound.bytes() + Y.bytes() + work.bytes();
+}
+
+bool LanczosRun::after_product(hipStream_t s) {
+    ++matvecs;
+    const int nc = j + 1;
+    {   // CGS2 against the whole basis, alpha_j, beta_j
+        PhaseScope ph(op->ctx, HDM_PHASE_ORTHO, s);
+        hipLaunchKernelGGL(k_gemvt, dim3(nb), dim3(kBlock), 0, s, V.get(), n, nc, y.get(), n, part.get(), ldp);
+        hipLaunchKernelGGL(k_reduce_cols, dim3(ceil_div(nc, 64)), dim3(64), 0, s, part.get(), nb, ldp, nc, h1.get());
+        hipLaunchKernelGGL(k_gemvn, dim3(nb), dim3(kBlock), 0, s, V.get(), n, nc, h1.get(), y.get(), n, nullptr);
+        hipLaunchKernelGGL(k_gemvt, dim3(nb), dim3(kBlock), 0, s, V.get(), n, nc, y.get(), n, part.get(), ldp);
+        hipLaunchKernelGGL(k_reduce_cols, dim3(ceil_div(nc, 64)), dim3(64), 0, s, part.get(), nb, ldp, nc, h2.get());
+        hipLaunchKernelGGL(k_gemvn, dim3(nb), dim3(kBlock), 0, s, V.get(), n, nc, h2.get(), y.get(), n, np.get());
+        hipLaunchKernelGGL(k_alpha_beta, dim3(1), dim3(1), 0, s, h1.get(), h2.get(), j, np.get(), nb, alpha.get(),
+                           beta.get());
     }
+    check_launch("lanczos step");
+    m = j + 1;
+    const bool last = (j == max_basis - 1);
+    if (m >= r && ((m % check_every) == 0 || last)) {
+        {
+            KernelEvents ev(op->ctx, HDM_PHASE_TRIDIAG);
+            hipExtLaunchKernelGGL(k_tridiag, dim3(ceil_div(r, 4)), dim3(kBlock), 0, s, ev.start, ev.stop, 0,
+                                  alpha.get(), beta.get(), m, r, theta.get(), Y.get(), bound.get(), work.get());
+        }
+        check_launch("tridiagonal eigensolve");
+        theta.download(h_theta.data(), r, s);
+        bound.download(h_bound.data(), r, s);
+        HDM_HIP(hipStreamSynchronize(s));
+        bool ok = true;
+        for (int i = 0; i < r; ++i) ok = ok && (h_bound[i] <= tol * std::fabs(h_theta[i]));
+        if (ok) {
+            converged = finished = true;
+            return true;
+        }
+    }
+    if (last) {
+        finished = true;
+        return true;
+    }
+    hipLaunchKernelGGL(k_next, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, s, y.get(), beta.get(), j,
+                       V.get() + static_cast<int64_t>(j + 1) * n, n);
+    ++j;
+    return false;
+}
+
+hdm_status LanczosRun::result(double* evals, double* evecs, hdm_eig_info_t* info, hipStream_t s) {
     // Ritz values are descending by construction (k-th largest)
-    for (int i = 0; i < r; ++i) evals[i] = h_theta[i];
+    if (evals)
+        for (int i = 0; i < r; ++i) evals[i] = h_theta[i];
     double worst = 0.0;
     for (int i = 0; i < r; ++i) worst = std::max(worst, h_bound[i] / std::max(std::fabs(h_theta[i]), 1e-300));
     if (evecs) {
+        const int gN = ceil_div(n, kBlock);
         hipLaunchKernelGGL(k_ritz, dim3(gN), dim3(kBlock), 0, s, V.get(), n, m, Y.get(), r, evecs, n);
         DevBuf<double> nrm(r);
         DevBuf<int64_t> arg(r);
@@ -395,6 +424,18 @@ hdm_status lanczos_eigs(Op& op, int r, double tol, int block, int max_basis, uin
         info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
     return converged ? HDM_OK : HDM_ENOCONV;
+}
+
+hdm_status lanczos_eigs(Op& op, int r, double tol, int block, int max_basis, uint64_t seed, double* evals,
+                        double* evecs, hdm_eig_info_t* info, hipStream_t s) {
+    HDM_CHECK(block == 1, HDM_EINVAL, "only block = 1 is supported by this build");
+    LanczosRun run;
+    run.start(op, r, tol, max_basis, seed, s);
+    while (!run.finished) {
+        apply(op, 1, false, run.current(), run.output(), 1, s);
+        run.after_product(s);
+    }
+    return run.result(evals, evecs, info, s);
 }
 
 }  // namespace hdm

@@ -1,17 +1,23 @@
 // The compressed operator resident in HBM, and the launch plans that apply it.
 #pragma once
 
+#include <chrono>
 #include <memory>
+#include <mutex>
 
 #include <hip/hip_ext.h>
 
 #include "common.hpp"
+
+struct hdm_ctx_s;
+struct hdm_op_s;
 
 namespace hdm {
 
 // HIP-event pairs around phase launches, accumulated per phase.
 struct Profiler {
     bool on = false;
+    std::mutex mu;                               // several host threads may record
     std::vector<hipEvent_t> pool;
     size_t used = 0;
     struct Mark { int phase; size_t a, b; };
@@ -84,9 +90,54 @@ struct RowTask {
     int32_t h, i;
 };
 
-struct NodeLevel {       // nodes of one tree level with their skeleton work
-    int level;
-    std::vector<int32_t> heap;  // heap ids with rank > 0
+constexpr int kMaxLevels = 17;   // tree depth <= 16
+
+// Everything a product kernel needs about one operator, resident in device
+// memory next to it.  Two copies exist per operator: one for the float64 tiles
+// (the degree products) and one for the evaluation precision.
+struct OpDev {
+    int64_t n;
+    int32_t depth, L;
+    const int32_t* perm;
+    const double* c;              // alpha = 1 scale, tree order
+    const int64_t* start;
+    const int32_t* rank;
+    const int32_t* ncand;
+    const int64_t* skoff;
+    const int64_t* poff;
+    const void* P;
+    const RowTask* rows;          // skeleton rows grouped by level (leaves first)
+    int64_t row_begin[kMaxLevels];
+    int64_t row_count[kMaxLevels];
+    int64_t row_total;
+    const int64_t* far_off;
+    const int32_t* far_cols;
+    const int64_t* far_colbase;
+    const int32_t* far_colmap;
+    const void* far;
+    const float* fscale;
+    const NearItem* items;
+    int64_t nitems;
+    const void* near;
+    const float* nscale;
+    const LeafPlan* leaves;
+    void* w;                      // workspaces (nrhs columns each)
+    void* skw;
+    void* sku;
+    void* part;
+    int64_t ldsk, ldp;
+};
+
+// A side stream with its fork/join events: the upward pass and the far field
+// run there while the near field streams on the caller's stream.
+struct Lane {
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+    void init();
+    Lane() = default;
+    Lane(const Lane&) = delete;
+    Lane& operator=(const Lane&) = delete;
+    ~Lane();
 };
 
 struct Op {
@@ -140,29 +191,67 @@ struct Op {
     DevBuf<LeafPlan> d_leaves;
     int64_t part_elems = 0;
     int near_rows_per_group = 256;
-    std::vector<NodeLevel> levels;             // index = level
-    DevBuf<int32_t> d_heaps;                   // heap ids per level, concatenated
-    std::vector<int64_t> heaps_off;            // per level
     DevBuf<int32_t> d_rank, d_ncand;
     DevBuf<int64_t> d_skoff, d_poff, d_far_block_off;
     DevBuf<int32_t> d_far_cols;
     std::vector<int64_t> row_begin, row_count; // per level: skeleton-row tasks of the upward pass
     int64_t row_total = 0;
     DevBuf<RowTask> d_row_tasks;
-    hipStream_t side = nullptr;                // upward pass + far field run here, concurrent with the near field
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    Lane lane;                                 // side stream of single-operator products
+    OpDev host64{}, hostT{};                   // descriptors (host copies)
+    DevBuf<OpDev> dev64, devT;                 // the same, in device memory
     // normalisation (tree order)
     DevBuf<double> q, d, c;
     // workspaces of the product
     int ws_nrhs = 0;
-    DevBuf<char> w_tree, u_tree, skw, sku, part;
+    DevBuf<char> w_tree, skw, sku, part;
     double seconds_compress = 0.0;
     size_t footprint() const;
     Op() = default;
     Op(const Op&) = delete;
     Op& operator=(const Op&) = delete;
-    ~Op();
 };
+
+// one operand of a batched product
+struct ApplyReq {
+    Op* op;
+    const double* x;
+    double* y;
+};
+
+// One Lanczos eigensolve (Sec. 2.2) that advances a step at a time: the caller
+// applies the normalised operator to current() into output() (possibly in a
+// batch with other solves), then after_product() reorthogonalises and, every
+// few steps, checks the Ritz pairs.  result() forms the Ritz vectors.
+struct LanczosRun {
+    Op* op = nullptr;
+    int r = 0, max_basis = 0, check_every = 5;
+    double tol = 0.0;
+    uint64_t seed = 0;
+    int64_t n = 0;
+    int nb = 0, ldp = 0;
+    DevBuf<double> V, y, part, h1, h2, np, alpha, beta, theta, bound, Y, work;
+    std::vector<double> h_theta, h_bound;
+    int j = 0, m = 0, matvecs = 0;
+    bool converged = false, finished = false;
+    std::chrono::steady_clock::time_point t0;
+    void start(Op& op, int r, double tol, int max_basis, uint64_t seed, hipStream_t s);
+    const double* current() const { return V.get() + static_cast<int64_t>(j) * n; }
+    double* output() { return y.get(); }
+    bool after_product(hipStream_t s);   // true once finished
+    hdm_status result(double* evals, double* evecs, hdm_eig_info_t* info, hipStream_t s);
+    size_t bytes() const;
+};
+
+// message of the last failure on the calling thread (hdm_last_error)
+void set_last_error(const char* msg);
+
+// builds a compressed, normalised operator (validation, compression, plan,
+// degrees, precision conversion); the caller owns the result (api.cpp)
+void validate_params(const hdm_params& p);
+hdm_op_s* make_operator(Ctx* ctx, const void* X, int x_on_device, const hdm_params& p, hipStream_t s);
+// upper bound of the device memory one request of the serving loop holds at its peak
+size_t footprint_estimate(const hdm_params& p, int max_basis);
 
 // compression (compress.hip)
 void compress_operator(Op& op, const void* X, int x_on_device, hipStream_t s);
@@ -171,8 +260,17 @@ void build_eval_plan(Op& op, hipStream_t s);
 void normalise_degrees(Op& op, hipStream_t s);
 void convert_eval_precision(Op& op, hipStream_t s);
 void apply(Op& op, int normalised, bool exact64, const double* x, double* y, int nrhs, hipStream_t s);
+// One launch per phase for every operator of the batch (same tile precisions,
+// at most kMaxBatch operators, one nrhs); each operator's result is the one a
+// single-operator product gives.
+constexpr int kMaxBatch = 8;
+void apply_batch(const ApplyReq* reqs, int nops, int normalised, int nrhs, hipStream_t s, Lane& lane, Ctx* prof_ctx);
 // eigensolver (lanczos.hip)
 hdm_status lanczos_eigs(Op& op, int r, double tol, int block, int max_basis, uint64_t seed, double* evals,
                         double* evecs, hdm_eig_info_t* info, hipStream_t s);
 
 }  // namespace hdm
+
+// the opaque handles of the C ABI are the internal objects
+struct hdm_ctx_s : hdm::Ctx {};
+struct hdm_op_s : hdm::Op {};

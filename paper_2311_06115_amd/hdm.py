@@ -58,7 +58,7 @@ class EigInfo(C.Structure):
 
 
 class ServerCfg(C.Structure):
-    _fields_ = [("max_slots", C.c_int32), ("mem_budget_bytes", C.c_size_t)]
+    _fields_ = [("max_slots", C.c_int32), ("mem_budget_bytes", C.c_size_t), ("compressors", C.c_int32)]
 
 
 class Request(C.Structure):
@@ -311,3 +311,66 @@ class Operator:
         if st not in (0, 4):
             check(st)
         return evals, (vecs.t() if vectors else None), info, st
+
+
+class Server:
+    """Continuous-batching eigensolve server (hdm_server_*)."""
+
+    def __init__(self, ctx: Context | None = None, max_slots: int = 4, mem_budget_bytes: int = 0,
+                 compressors: int = 2):
+        self.ctx = ctx or context(0)
+        cfg = ServerCfg(max_slots, mem_budget_bytes, compressors)
+        self.h = C.c_void_p()
+        check(lib().hdm_server_create(self.ctx.h, C.byref(cfg), C.byref(self.h)))
+
+    def submit(self, X, eps, m, s, tau, k, seed, r, tol=1e-6, near_prec="f32", far_prec=None, budget=0.05,
+               knn_iters=10, max_basis=0, arrival_s=0.0) -> int:
+        Xh = np.asarray(X)
+        Xh = np.ascontiguousarray(Xh if Xh.dtype == np.uint8 else Xh.astype(np.float64))
+        req = Request()
+        req.X = _ptr(Xh)
+        req.params = make_params(Xh, eps, m, s, tau, k, seed, near_prec, far_prec, budget, knn_iters)
+        req.r, req.rel_resid_tol, req.max_basis, req.arrival_s = int(r), float(tol), int(max_basis), float(arrival_s)
+        t = C.c_uint64()
+        check(lib().hdm_submit(self.h, C.byref(req), C.byref(t)))
+        return t.value
+
+    def poll(self, ticket):
+        """None while pending, else a dict with status, eigenvalues and latencies."""
+        res = Result()
+        st = lib().hdm_poll(self.h, C.c_uint64(ticket), C.byref(res))
+        if st == 5:
+            return None
+        check(st)
+        return dict(status=res.status, evals=np.array(res.evals[:res.r]), latency_s=res.latency_s,
+                    service_s=res.service_s, iters=res.iters)
+
+    def wait(self, ticket, timeout=120.0):
+        import time
+        t0 = time.monotonic()
+        while True:
+            r = self.poll(ticket)
+            if r is not None:
+                return r
+            if time.monotonic() - t0 > timeout:
+                raise TimeoutError(f"request {ticket} not done after {timeout} s")
+            time.sleep(0.0005)
+
+    def cancel(self, ticket):
+        check(lib().hdm_cancel(self.h, C.c_uint64(ticket)))
+
+    def stats(self):
+        st = ServerStats()
+        check(lib().hdm_server_stats(self.h, C.byref(st)))
+        return {f: getattr(st, f) for f, _ in ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().hdm_server_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
