@@ -24,13 +24,23 @@ constexpr int kBlock = 256;
 struct Pts {
     const double* xf;
     const uint8_t* xu;
+    const int32_t* nu;   // u8 codes: sum of squared codes per point (exact integer)
     int dim;
     int is_u8;
     double eps;
 };
 
-// ||x_i - x_j||^2 summed over coordinates in increasing order
+// ||x_i - x_j||^2 summed over coordinates in increasing order; for u8 codes the
+// exact integer sum (a - b)^2 = a.a + b.b - 2 a.b, then divided by 255^2
 __device__ inline double sqd(const Pts& P, int64_t i, int64_t j) {
+    if (P.is_u8 && P.nu) {
+        const uint32_t* a = reinterpret_cast<const uint32_t*>(P.xu + i * P.dim);
+        const uint32_t* b = reinterpret_cast<const uint32_t*>(P.xu + j * P.dim);
+        uint32_t g = 0;
+        for (int d = 0; d < P.dim / 4; ++d) g = __builtin_amdgcn_udot4(a[d], b[d], g, false);
+        const int32_t s2 = P.nu[i] + P.nu[j] - 2 * static_cast<int32_t>(g);
+        return static_cast<double>(s2) / 65025.0;
+    }
     if (P.is_u8) {
         const uint8_t* a = P.xu + i * P.dim;
         const uint8_t* b = P.xu + j * P.dim;
@@ -53,6 +63,104 @@ __device__ inline double sqd(const Pts& P, int64_t i, int64_t j) {
 
 // Eq. (2): exp(-||x_i - x_j||^2 / eps)
 __device__ inline double kval(const Pts& P, int64_t i, int64_t j) { return exp(-(sqd(P, i, j) / P.eps)); }
+
+// ---------------------------------------------------------------------------
+// u8 codes: exact squared distances of whole blocks with int8 matrix cores.
+// With a = code - 128 (an int8), ||a - b||^2 = |a|^2 + |b|^2 - 2 a.b exactly;
+// a.b comes from v_mfma_i32_16x16x64_i8 over 64-byte slices of the codes.
+// ---------------------------------------------------------------------------
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+struct GramBlock {
+    const int32_t* ridx;   // row points (original indices)
+    const int32_t* cidx;   // column points
+    int32_t nr, nc;
+    int64_t off;           // output offset (elements)
+    int32_t ld;            // leading dimension of the output
+    int32_t colmajor;      // 1: out[off + c * ld + r]; 0: out[off + r * ld + c]
+};
+
+__global__ void k_code_norms(const uint8_t* x, int64_t n, int dim, int32_t* nu, int32_t* ns) {
+    const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t* a = reinterpret_cast<const uint32_t*>(x + i * dim);
+    uint32_t g = 0;
+    int32_t t = 0;
+    for (int d = 0; d < dim / 4; ++d) {
+        g = __builtin_amdgcn_udot4(a[d], a[d], g, false);
+        const uint32_t w = a[d] ^ 0x80808080u;
+        t = __builtin_amdgcn_sdot4(static_cast<int32_t>(w), static_cast<int32_t>(w), t, false);
+    }
+    nu[i] = static_cast<int32_t>(g);
+    ns[i] = t;
+}
+
+// 16 code bytes of point idx at byte k, offset to int8 (zero outside)
+__device__ inline v4i codes16(const uint8_t* x, int32_t idx, int k, int dim) {
+    if (idx < 0 || k >= dim) return v4i{0, 0, 0, 0};
+    const uint4 u = *reinterpret_cast<const uint4*>(x + static_cast<int64_t>(idx) * dim + k);
+    return v4i{static_cast<int>(u.x ^ 0x80808080u), static_cast<int>(u.y ^ 0x80808080u),
+               static_cast<int>(u.z ^ 0x80808080u), static_cast<int>(u.w ^ 0x80808080u)};
+}
+
+// one 64 x 64 output tile per workgroup (blockIdx.x: tile, blockIdx.y: block);
+// mode 0 writes the integer 255^2 ||x - y||^2, mode 1 the float64 kernel value
+__global__ void __launch_bounds__(256) k_gram_u8(const GramBlock* blocks, const uint8_t* x, const int32_t* ns, int dim,
+                                                 double eps, int mode, void* out) {
+    const GramBlock B = blocks[blockIdx.y];
+    const int tiles_c = (B.nc + 63) / 64;
+    const int tr = blockIdx.x / tiles_c, tc = blockIdx.x % tiles_c;
+    if (tr * 64 >= B.nr) return;
+    const int wv = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int g = lane / 16, li = lane % 16;
+    const int r0 = tr * 64 + wv * 16, c0 = tc * 64;
+    const int32_t ia = r0 + li < B.nr ? B.ridx[r0 + li] : -1;
+    int32_t ib[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) ib[t] = c0 + 16 * t + li < B.nc ? B.cidx[c0 + 16 * t + li] : -1;
+    v4i acc[4] = {};
+    for (int k0 = 0; k0 < dim; k0 += 64) {
+        const int kk = k0 + 16 * g;
+        const v4i a = codes16(x, ia, kk, dim);
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            acc[t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, codes16(x, ib[t], kk, dim), acc[t], 0, 0, 0);
+    }
+    // acc[t][q] holds row r0 + 4 g + q, column c0 + 16 t + li
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int c = c0 + 16 * t + li;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = r0 + 4 * g + q;
+            if (r >= B.nr || c >= B.nc) continue;
+            const int32_t s2 = ns[B.ridx[r]] + ns[B.cidx[c]] - 2 * acc[t][q];
+            const int64_t e = B.off + (B.colmajor ? static_cast<int64_t>(c) * B.ld + r : static_cast<int64_t>(r) * B.ld + c);
+            if (mode == 0) static_cast<int32_t*>(out)[e] = s2;
+            else static_cast<double*>(out)[e] = exp(-((static_cast<double>(s2) / 65025.0) / eps));
+        }
+    }
+}
+
+// sequential sum of each row of a row-major matrix (the order the sample sum uses)
+__global__ void k_row_sums(const double* v, int64_t rows, const int32_t* ncols, int ld, int lvl,
+                           const int64_t* start, double* out) {
+    const int64_t pos = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    if (pos >= rows) return;
+    int64_t h = 1;
+    for (int l = 0; l < lvl; ++l) h = (pos < start[2 * h + 1]) ? 2 * h : 2 * h + 1;
+    const int nc = ncols[h - (int64_t(1) << lvl)];
+    double acc = 0.0;
+    for (int q = 0; q < nc; ++q) acc = acc + v[pos * ld + q];
+    out[pos] = acc;
+}
+
+// original indices of each node's sample (the Gram blocks' column lists)
+__global__ void k_sample_ids(const int32_t* samp, const int32_t* nsamp, const int32_t* perm, int nodes, int32_t* ids) {
+    const int t = blockIdx.x;
+    if (t >= nodes) return;
+    for (int q = threadIdx.x; q < nsamp[t]; q += blockDim.x) ids[t * 64 + q] = perm[samp[t * 64 + q]];
+}
 
 // heap id of the level-lvl node holding tree position pos
 __device__ inline int64_t node_of(int64_t pos, int lvl, const int64_t* start) {
@@ -347,7 +455,8 @@ __device__ inline bool knn_less(double da, int32_t ia, double db, int32_t ib) {
 
 __global__ void __launch_bounds__(kKnnBlock) k_knn_leaf(int depth, const int64_t* start, const int64_t* size,
                                                         const int32_t* perm, Pts P, int k, int stage, int splits,
-                                                        int32_t* kidx, double* kd2) {
+                                                        const int32_t* leafd2, int leafmax, int32_t* kidx,
+                                                        double* kd2) {
     extern __shared__ double xs[];          // staged coordinates (n x dim) when stage != 0
     __shared__ int32_t ids[kLeafStageMax];  // staged original indices
     const int64_t h = (int64_t(1) << depth) + blockIdx.x / splits;
@@ -373,7 +482,10 @@ __global__ void __launch_bounds__(kKnnBlock) k_knn_leaf(int depth, const int64_t
             int32_t j = -1;
             if (b < n && b != a) {
                 j = n <= kLeafStageMax ? ids[b] : perm[s0 + b];
-                if (stage) {
+                if (leafd2) {
+                    const int64_t lf = blockIdx.x / splits;
+                    d = static_cast<double>(leafd2[(lf * leafmax + a) * leafmax + b]) / 65025.0;
+                } else if (stage) {
                     const double* xa = xs + a * P.dim;
                     const double* xb = xs + b * P.dim;
                     double acc = 0.0;
@@ -813,6 +925,30 @@ T* ptr(DevBuf<T>& b) { return b.get(); }
 // ---------------------------------------------------------------------------
 // host orchestration
 // ---------------------------------------------------------------------------
+// Points as the kernels see them, plus the integer-code helpers when the
+// matrix-core path applies (u8 codes whose dimension is a multiple of 16).
+struct Geo {
+    Pts P{};
+    bool gram = false;
+    DevBuf<int32_t> nu, ns;   // sum of squared codes, unsigned and offset by 128
+};
+
+// exact u8 distance blocks with matrix cores (see k_gram_u8); blocks must stay
+// alive until the launches complete, so this synchronises the stream
+static void gram_launch(const Geo& G, const std::vector<GramBlock>& blocks, int mode, void* out, hipStream_t s) {
+    if (blocks.empty()) return;
+    DevBuf<GramBlock> d = to_device(blocks, s);
+    int64_t maxt = 0;
+    for (const GramBlock& b : blocks) maxt = std::max<int64_t>(maxt, int64_t((b.nr + 63) / 64) * ((b.nc + 63) / 64));
+    if (maxt == 0) return;
+    for (size_t base = 0; base < blocks.size(); base += 65535) {
+        const int cnt = static_cast<int>(std::min<size_t>(65535, blocks.size() - base));
+        hipLaunchKernelGGL(k_gram_u8, dim3(static_cast<unsigned>(maxt), cnt), dim3(256), 0, s, d.get() + base, G.P.xu,
+                           G.ns.get(), G.P.dim, G.P.eps, mode, out);
+    }
+    check_launch("u8 distance blocks");
+    HDM_HIP(hipStreamSynchronize(s));
+}
 static void tree_ranges(int64_t n, int depth, std::vector<int64_t>& start, std::vector<int64_t>& size) {
     const int64_t nn = int64_t(1) << (depth + 1);
     start.assign(nn, 0);
@@ -828,10 +964,17 @@ static void tree_ranges(int64_t n, int depth, std::vector<int64_t>& start, std::
 }
 
 // one perfect tree of the given depth: ball tree (mode 0) or random-pivot tree (mode 1)
-static void build_tree(Op& op, int mode, int it, DevBuf<int32_t>& perm, DevBuf<int32_t>& tmp, Pts P, hipStream_t s,
-                       DevBuf<int32_t>& samp, DevBuf<int32_t>& nsamp, DevBuf<int32_t>& pq, DevBuf<double>& sumk,
-                       DevBuf<double>& key) {
+static void build_tree(Op& op, int mode, int it, DevBuf<int32_t>& perm, DevBuf<int32_t>& tmp, const Geo& G,
+                       hipStream_t s, DevBuf<int32_t>& samp, DevBuf<int32_t>& nsamp, DevBuf<int32_t>& pq,
+                       DevBuf<double>& sumk, DevBuf<double>& key) {
+    const Pts& P = G.P;
     const int64_t n = op.n;
+    DevBuf<int32_t> sample_ids;
+    DevBuf<double> kvals;
+    if (mode == 0 && G.gram) {
+        sample_ids.alloc(static_cast<size_t>(op.L) * kSample);
+        kvals.alloc(static_cast<size_t>(n) * kSample);
+    }
     const int gN = ceil_div(n, kBlock);
     hipLaunchKernelGGL(k_iota, dim3(gN), dim3(kBlock), 0, s, perm.get(), n);
     for (int lvl = 0; lvl < op.depth; ++lvl) {
@@ -839,8 +982,25 @@ static void build_tree(Op& op, int mode, int it, DevBuf<int32_t>& perm, DevBuf<i
         if (mode == 0) {
             hipLaunchKernelGGL(k_tree_sample, dim3(nodes), dim3(64), 0, s, lvl, op.d_start.get(), op.d_size.get(),
                                op.prm.seed, samp.get(), nsamp.get());
-            hipLaunchKernelGGL(k_tree_sumk, dim3(gN), dim3(kBlock), 0, s, lvl, n, op.d_start.get(), perm.get(),
-                               samp.get(), nsamp.get(), P, sumk.get());
+            if (G.gram) {
+                // kernel values point x sample by matrix cores, then the sample sums in order
+                hipLaunchKernelGGL(k_sample_ids, dim3(nodes), dim3(64), 0, s, samp.get(), nsamp.get(), perm.get(), nodes,
+                                   sample_ids.get());
+                std::vector<GramBlock> blocks;
+                for (int t = 0; t < nodes; ++t) {
+                    const int64_t h = nodes + t;
+                    blocks.push_back(GramBlock{perm.get() + op.start[h], sample_ids.get() + int64_t(t) * kSample,
+                                               static_cast<int32_t>(op.size[h]),
+                                               static_cast<int32_t>(std::min<int64_t>(op.size[h], kSample)),
+                                               op.start[h] * kSample, kSample, 0});
+                }
+                gram_launch(G, blocks, 1, kvals.get(), s);
+                hipLaunchKernelGGL(k_row_sums, dim3(gN), dim3(kBlock), 0, s, kvals.get(), n, nsamp.get(), kSample, lvl,
+                                   op.d_start.get(), sumk.get());
+            } else {
+                hipLaunchKernelGGL(k_tree_sumk, dim3(gN), dim3(kBlock), 0, s, lvl, n, op.d_start.get(), perm.get(),
+                                   samp.get(), nsamp.get(), P, sumk.get());
+            }
             hipLaunchKernelGGL(k_tree_pq, dim3(nodes), dim3(kBlock), 0, s, lvl, op.d_start.get(), op.d_size.get(),
                                perm.get(), sumk.get(), P, pq.get());
         } else {
@@ -928,7 +1088,8 @@ static void build_far_lists(Op& op) {
     op.far_off[op.nnodes] = static_cast<int32_t>(op.far_idx.size());
 }
 
-static void skeletonize(Op& op, Pts P, hipStream_t s) {
+static void skeletonize(Op& op, const Geo& G, hipStream_t s) {
+    const Pts& P = G.P;
     const int64_t n = op.n;
     const int k = op.prm.knn_k, smax = op.prm.max_rank_s;
     op.rank.assign(op.nnodes, 0);
@@ -1000,8 +1161,19 @@ static void skeletonize(Op& op, Pts P, hipStream_t s) {
         hipLaunchKernelGGL(k_row_count, dim3(ceil_div(static_cast<int64_t>(cmax) * k, kBlock), nodes), dim3(kBlock), 0, s,
                            A);
         hipLaunchKernelGGL(k_row_select, dim3(nodes), dim3(kBlock), 0, s, A);
-        hipLaunchKernelGGL(k_block, dim3(ceil_div(static_cast<int64_t>(rmax) * cmax, kBlock), nodes), dim3(kBlock), 0,
-                           s, A, P);
+        if (G.gram) {
+            ncand.download(h_nc.data(), nodes, s);
+            nrows.download(h_nr.data(), nodes, s);
+            HDM_HIP(hipStreamSynchronize(s));
+            std::vector<GramBlock> blocks;
+            for (int t = 0; t < nodes; ++t)
+                blocks.push_back(GramBlock{rows.get() + int64_t(t) * rmax, cand.get() + int64_t(t) * cmax, h_nr[t],
+                                           h_nc[t], int64_t(t) * rmax * cmax, h_nc[t], 0});
+            gram_launch(G, blocks, 1, B.get(), s);
+        } else {
+            hipLaunchKernelGGL(k_block, dim3(ceil_div(static_cast<int64_t>(rmax) * cmax, kBlock), nodes), dim3(kBlock),
+                               0, s, A, P);
+        }
         hipLaunchKernelGGL(k_pivoted_id, dim3(nodes), dim3(kBlock), 0, s, A);
         check_launch("skeletonisation");
         rk.download(h_rk.data(), nodes, s);
@@ -1055,7 +1227,8 @@ static void skeletonize(Op& op, Pts P, hipStream_t s) {
     HDM_HIP(hipStreamSynchronize(s));
 }
 
-static void build_tiles(Op& op, Pts P, hipStream_t s) {
+static void build_tiles(Op& op, const Geo& G, hipStream_t s) {
+    const Pts& P = G.P;
     const int64_t L = op.L;
     // near blocks: per leaf, column-major ld x (sum of near leaf sizes), ld = rows rounded up to 8
     op.near_block_off.assign(L, 0);
@@ -1078,7 +1251,13 @@ static void build_tiles(Op& op, Pts P, hipStream_t s) {
     }
     op.near_elems = off;
     op.near64.alloc(off);
-    {
+    if (G.gram) {
+        HDM_HIP(hipMemsetAsync(op.near64.get(), 0, op.near64.bytes(), s));   // padded rows stay zero
+        std::vector<GramBlock> blocks;
+        for (const NearPair& pr : pairs)
+            blocks.push_back(GramBlock{op.perm.get() + pr.a0, op.perm.get() + pr.b0, pr.na, pr.nb, pr.off, pr.ld, 1});
+        gram_launch(G, blocks, 1, op.near64.get(), s);
+    } else {
         DevBuf<NearPair> dp = to_device(pairs, s);
         int64_t maxe = 0;
         for (auto& p : pairs) maxe = std::max<int64_t>(maxe, static_cast<int64_t>(p.ld) * p.nb);
@@ -1114,7 +1293,21 @@ static void build_tiles(Op& op, Pts P, hipStream_t s) {
     op.far_elems = foff;
     op.far64.alloc(foff > 0 ? foff : 1);
     op.far_colmap = to_device(colmap, s);
-    if (!blocks.empty()) {
+    if (G.gram) {
+        std::vector<GramBlock> gb;
+        for (int64_t h = 2; h < op.nnodes; ++h) {
+            if (op.rank[h] == 0) continue;
+            int64_t col = 0;
+            for (int32_t t = op.far_off[h]; t < op.far_off[h + 1]; ++t) {
+                const int32_t g = op.far_idx[t];
+                if (op.rank[g] > 0)
+                    gb.push_back(GramBlock{op.skel.get() + op.skoff[h], op.skel.get() + op.skoff[g], op.rank[h],
+                                           op.rank[g], op.far_block_off[h] + col, op.far_cols[h], 0});
+                col += op.rank[g];
+            }
+        }
+        gram_launch(G, gb, 1, op.far64.get(), s);
+    } else if (!blocks.empty()) {
         DevBuf<FarBlock> db = to_device(blocks, s);
         int64_t maxe = 0;
         for (auto& b : blocks) maxe = std::max<int64_t>(maxe, static_cast<int64_t>(b.rows) * b.cols);
@@ -1145,7 +1338,8 @@ void compress_operator(Op& op, const void* X, int x_on_device, hipStream_t s) {
     // points
     const size_t xb = static_cast<size_t>(op.n) * op.dim * dtype_size(p.x_dtype);
     const hipMemcpyKind kind = x_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-    Pts P{};
+    Geo G;
+    Pts& P = G.P;
     P.dim = op.dim;
     P.eps = p.eps;
     if (p.x_dtype == HDM_U8) {
@@ -1153,6 +1347,15 @@ void compress_operator(Op& op, const void* X, int x_on_device, hipStream_t s) {
         HDM_HIP(hipMemcpyAsync(op.xu.get(), X, xb, kind, s));
         P.xu = op.xu.get();
         P.is_u8 = 1;
+        if (op.dim % 16 == 0) {
+            G.gram = true;
+            G.nu.alloc(op.n);
+            G.ns.alloc(op.n);
+            hipLaunchKernelGGL(k_code_norms, dim3(ceil_div(op.n, kBlock)), dim3(kBlock), 0, s, op.xu.get(), op.n, op.dim,
+                               G.nu.get(), G.ns.get());
+            check_launch("code norms");
+            P.nu = G.nu.get();
+        }
     } else {
         op.xf.alloc(static_cast<size_t>(op.n) * op.dim);
         HDM_HIP(hipMemcpyAsync(op.xf.get(), X, xb, kind, s));
@@ -1171,7 +1374,7 @@ void compress_operator(Op& op, const void* X, int x_on_device, hipStream_t s) {
     const int64_t n = op.n;
     DevBuf<int32_t> perm(n), tmp(n), samp(static_cast<size_t>(op.L) * kSample), nsamp(op.L), pq(2 * op.L);
     DevBuf<double> sumk(n), key(n);
-    build_tree(op, 0, 0, perm, tmp, P, s, samp, nsamp, pq, sumk, key);
+    build_tree(op, 0, 0, perm, tmp, G, s, samp, nsamp, pq, sumk, key);
     op.perm = std::move(perm);
     op.iperm.alloc(n);
     hipLaunchKernelGGL(k_inverse_perm, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, s, op.perm.get(), op.iperm.get(), n);
@@ -1185,13 +1388,24 @@ void compress_operator(Op& op, const void* X, int x_on_device, hipStream_t s) {
     int64_t leafmax = 0;
     for (int64_t h = op.L; h < 2 * int64_t(op.L); ++h) leafmax = std::max(leafmax, op.size[h]);
     const int stage = (!P.is_u8 && P.dim <= kLeafStageDim && leafmax * P.dim * 8 <= 48 * 1024) ? 1 : 0;
+    DevBuf<int32_t> leafd2;
+    if (G.gram) leafd2.alloc(static_cast<size_t>(op.L) * leafmax * leafmax);
     const size_t shm = stage ? sizeof(double) * leafmax * P.dim : 0;
     // enough workgroups to cover the device: split each leaf's points over several
     const int splits = std::max(1, std::min(static_cast<int>((leafmax + 15) / 16), 2048 / op.L));
     for (int it = 0; it < p.knn_iters; ++it) {
-        build_tree(op, 1, it, kperm, tmp, P, s, samp, nsamp, pq, sumk, key);
+        build_tree(op, 1, it, kperm, tmp, G, s, samp, nsamp, pq, sumk, key);
+        if (G.gram) {
+            std::vector<GramBlock> blocks;
+            for (int64_t h = op.L; h < 2 * int64_t(op.L); ++h)
+                blocks.push_back(GramBlock{kperm.get() + op.start[h], kperm.get() + op.start[h],
+                                           static_cast<int32_t>(op.size[h]), static_cast<int32_t>(op.size[h]),
+                                           (h - op.L) * leafmax * leafmax, static_cast<int32_t>(leafmax), 0});
+            gram_launch(G, blocks, 0, leafd2.get(), s);
+        }
         hipLaunchKernelGGL(k_knn_leaf, dim3(op.L * splits), dim3(kKnnBlock), shm, s, op.depth, op.d_start.get(),
-                           op.d_size.get(), kperm.get(), P, k, stage, splits, op.knn_idx.get(), op.knn_d2.get());
+                           op.d_size.get(), kperm.get(), P, k, stage, splits, G.gram ? leafd2.get() : nullptr,
+                           static_cast<int>(leafmax), op.knn_idx.get(), op.knn_d2.get());
         check_launch("knn leaf");
     }
     // lists
@@ -1207,8 +1421,8 @@ void compress_operator(Op& op, const void* X, int x_on_device, hipStream_t s) {
         build_near_lists(op, hv);
         build_far_lists(op);
     }
-    skeletonize(op, P, s);
-    build_tiles(op, P, s);
+    skeletonize(op, G, s);
+    build_tiles(op, G, s);
     op.seconds_compress = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
 

@@ -1,0 +1,61 @@
+"""MNIST-shaped workload at full size (65536 points, 784 u8 codes): bf16 tiles against the f32 path.
+
+The oracle cannot compress 65536 x 784 points within a test, so the full-size
+checks are properties and sampled outputs: the exact dense operator on sampled
+rows (evaluated one by one by the oracle), the closed-form top eigenpair, and
+bf16 against f32 eigenvalues.  Structure parity against the oracle on u8 codes
+is covered by test_gpu_parity.py (mnist-2k, bit-exact).
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import hmatrix as HM
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def c3():
+    from paper_2311_06115_amd import hdm
+    cfg = synth.get_config("mnist-64k")
+    X, eps = synth.configs.make_inputs(cfg)
+    print(f"[gpu] compress mnist-64k n={X.shape[0]}", flush=True)
+    Xd = torch.from_numpy(X).cuda()
+    ops = {p: hdm.Operator(Xd, eps, cfg["m"], cfg["s"], cfg["tau"], cfg["k"], cfg["seed"], near_prec=p)
+           for p in ("bf16", "f32")}
+    return cfg, X, eps, ops
+
+
+def test_structure_independent_of_tile_precision(c3):
+    cfg, X, eps, ops = c3
+    assert np.array_equal(ops["bf16"].perm(), ops["f32"].perm())
+    assert np.array_equal(ops["bf16"].knn()[0], ops["f32"].knn()[0])
+
+
+def test_product_on_sampled_dense_rows(c3):
+    cfg, X, eps, ops = c3
+    rng = np.random.default_rng(31)
+    w = rng.standard_normal(X.shape[0])
+    rows = np.sort(rng.choice(X.shape[0], 64, replace=False))
+    dense = np.array([HM.dense_kmatvec(X, eps, w, (int(i), int(i) + 1))[0] for i in rows])
+    for prec, tol in (("f32", 10 * cfg["tau"]), ("bf16", 10 * cfg["tau"] + 1.5e-2)):
+        u = ops[prec].matvec(torch.from_numpy(w).cuda()).cpu().numpy()
+        rel = np.linalg.norm(u[rows] - dense) / np.linalg.norm(dense)
+        print(f"[gpu] mnist-64k {prec} product vs dense on 64 rows: {rel:.2e}")
+        assert rel <= tol
+
+
+def test_bf16_eigenvalues_against_f32(c3):
+    cfg, X, eps, ops = c3
+    ev32, v32, i32, s32 = ops["f32"].eigs(cfg["r"], tol=1e-10, seed=cfg["seed"])
+    ev16, v16, i16, s16 = ops["bf16"].eigs(cfg["r"], tol=1e-10, seed=cfg["seed"])
+    assert s32 == 0 and s16 == 0
+    rel = np.abs(ev16 - ev32) / np.abs(ev32)
+    print(f"[gpu] mnist-64k bf16 vs f32 eigenvalues: max rel {rel.max():.2e}; lambda_1 {ev32[0]!r} {ev16[0]!r}")
+    assert rel.max() <= 1e-4
+    assert abs(ev32[0] - 1.0) <= 1e-6
+    q, d, c = ops["f32"].degrees()
+    want = np.sqrt(d) / np.linalg.norm(np.sqrt(d))
+    assert np.linalg.norm(v32[:, 0].cpu().numpy() - want) <= 1e-5
