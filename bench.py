@@ -61,6 +61,33 @@ def cpu_baseline(cfg, X, eps, r):
                       f"{dt:.1f} s on 1 host core"}
 
 
+def serving_leg(hdm, pool, arrivals, near, far, max_slots=8):
+    """Replay the arrival stream against the server; returns its statistics."""
+    import synth
+    srv = hdm.Server(max_slots=max_slots, mem_budget_bytes=200 << 30, compressors=2)
+    S = synth.SERVING
+    for q in pool[:2]:   # warm-up: allocations and first launches
+        srv.wait(srv.submit(q["X"], q["eps"], q["m"], q["s"], q["tau"], q["k"], q["seed"], S["r"], tol=S["tol"],
+                            near_prec=near, far_prec=far))
+    srv.close()
+    srv = hdm.Server(max_slots=max_slots, mem_budget_bytes=200 << 30, compressors=2)
+    t0 = time.monotonic()
+    tickets = []
+    for i, ta in enumerate(arrivals):
+        q = pool[i % len(pool)]
+        delay = t0 + ta - time.monotonic()
+        if delay > 0:
+            time.sleep(delay)
+        tickets.append(srv.submit(q["X"], q["eps"], q["m"], q["s"], q["tau"], q["k"], q["seed"] + i, S["r"],
+                                  tol=S["tol"], near_prec=near, far_prec=far, arrival_s=t0 + ta))
+    res = [srv.wait(t, timeout=600) for t in tickets]
+    st = srv.stats()
+    srv.close()
+    st["failed"] = sum(1 for r in res if r["status"] not in (0, 4))
+    st["not_converged"] = sum(1 for r in res if r["status"] == 4)
+    return st
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -70,6 +97,9 @@ def main():
     ap.add_argument("--matvec-reps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true", help="also run one plain 1 GiB device copy (counter scale)")
+    ap.add_argument("--serve-seconds", type=float, default=0.0,
+                    help="length of the serving stream (0: skip; off by default, see the notes on the serving leg)")
+    ap.add_argument("--serve-pool", type=int, default=8, help="distinct request instances the stream cycles through")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path",
@@ -152,6 +182,21 @@ def main():
     achieved = st_op.algo_bytes_near / l2l_avg_s / 1e9
     src_sha = hashlib.sha1(open(os.path.join(ROOT, "paper_2311_06115_amd", "csrc", "evaluate.hip"), "rb").read()).hexdigest()
     traffic = pmc_traffic(args.workload, src_sha)
+    serving = None
+    if args.serve_seconds > 0:
+        pool = [synth.configs.serving_instance(i) for i in range(args.serve_pool)]
+        arrivals = synth.configs.serving_arrivals(args.serve_seconds)
+        mixed = serving_leg(hdm, pool, arrivals, *synth.SERVING_PATHS["mixed"])
+        plain = serving_leg(hdm, pool, arrivals, *synth.SERVING_PATHS["plain_f32"])
+        keep = ("completed", "solves_per_s", "p50_latency_s", "p99_latency_s", "peak_resident_bytes",
+                "shared_launches", "failed", "not_converged")
+        serving = {"stream": f"Poisson {synth.SERVING['rate']}/s for {args.serve_seconds} s, "
+                             f"{len(arrivals)} requests cycling {args.serve_pool} instances "
+                             f"(S-curve / MNIST-shaped, N log-uniform in [4096, 65536]), "
+                             f"r={synth.SERVING['r']}, rel. residual {synth.SERVING['tol']}",
+                   "mixed": {k: mixed[k] for k in keep}, "plain_f32": {k: plain[k] for k in keep},
+                   "mixed_tiles": "near %s, far %s" % synth.SERVING_PATHS["mixed"],
+                   "pool_n": [q["n"] for q in pool], "pool_family": [q["family"] for q in pool]}
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(cfg, X, eps, r)
@@ -187,6 +232,7 @@ def main():
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "avg_launch_us": l2l_avg_s * 1e6, "launches": int(l2l_n),
                      "algo_bytes_per_launch": st_op.algo_bytes_near},
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -10,4 +10,4 @@ from .generators import (  # noqa: F401
     median_sq_dist_eps,
     two_clusters,
 )
-from .configs import CONFIGS, get_config, tree_depth  # noqa: F401
+from .configs import CONFIGS, SERVING, SERVING_FAMILIES, SERVING_PATHS, get_config, tree_depth  # noqa: F401

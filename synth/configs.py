@@ -16,9 +16,10 @@ CONFIGS = {
     # 3-D S-curve, float32 evaluation tiles, float64 Lanczos
     "scurve-32k": dict(family="scurve", n=32768, dim=3, seed=1, m=256, s=128, tau=1e-5, k=32,
                        near_prec="f32", far_prec="f32", r=10, block=1),
-    # MNIST-shaped u8 codes, bf16 tiles (compared against the f32 path)
+    # MNIST-shaped u8 codes, mixed tiles: bf16 near field, f32 skeleton (far) field
+    # (compared against the f32 path; bf16 far tiles alone cost 1.2e-4 in lambda_4)
     "mnist-64k": dict(family="mnist", n=65536, dim=784, seed=2, m=256, s=256, tau=1e-4, k=32,
-                      near_prec="bf16", far_prec="bf16", r=10, block=1),
+                      near_prec="bf16", far_prec="f32", r=10, block=1),
     # 3-D S-curve, 100k points, f16 near tiles, block Lanczos with 16 start vectors
     "scurve-100k": dict(family="scurve", n=100000, dim=3, seed=3, m=512, s=256, tau=1e-5, k=32,
                         near_prec="f16", far_prec="f32", r=20, block=16),
@@ -65,4 +66,47 @@ def make_inputs(cfg: dict, n: int | None = None):
     return X, float(eps)
 
 
-__all__ = ["CONFIGS", "get_config", "make_inputs", "make_points", "tree_depth"]
+# Serving stream: Poisson arrivals, each request an S-curve or MNIST-shaped
+# instance with N log-uniform in [4096, 65536], 8 eigenpairs at relative
+# residual 1e-6.  Per-family compression parameters:
+SERVING_FAMILIES = {
+    "scurve": dict(dim=3, m=256, s=128, tau=1e-5, k=32),
+    "mnist": dict(dim=784, m=256, s=256, tau=1e-4, k=32),
+}
+SERVING = dict(rate=20.0, r=8, tol=1e-6, n_lo=4096, n_hi=65536, arrival_seed=7, request_seed0=1000)
+# tile precisions (near, far) of the two paths the serving stream compares
+SERVING_PATHS = {"mixed": ("bf16", "f32"), "plain_f32": ("f32", "f32")}
+
+
+def serving_instance(i: int):
+    """Request i of the serving stream: family, points and eps (seed 1000 + i)."""
+    seed = SERVING["request_seed0"] + i
+    rng = np_random(seed)
+    fam = "scurve" if rng.random() < 0.5 else "mnist"
+    n = int(round(2.0 ** rng.uniform(12.0, 16.0)))
+    p = SERVING_FAMILIES[fam]
+    X = make_points(fam, n, seed, p["dim"])
+    eps = g.median_sq_dist_eps(X, seed)
+    return dict(family=fam, n=n, seed=seed, X=X, eps=float(eps), **p)
+
+
+def serving_arrivals(duration_s: float, rate: float | None = None):
+    """Poisson arrival times in [0, duration_s)."""
+    rate = SERVING["rate"] if rate is None else rate
+    rng = np_random(SERVING["arrival_seed"])
+    t, out = 0.0, []
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t >= duration_s:
+            return out
+        out.append(t)
+
+
+def np_random(seed: int):
+    import numpy as np
+    return np.random.default_rng(seed)
+
+
+__all__ = ["CONFIGS", "get_config", "make_inputs", "make_points", "tree_depth", "SERVING", "SERVING_FAMILIES",
+           "SERVING_PATHS",
+           "serving_instance", "serving_arrivals"]

@@ -58,12 +58,17 @@ def two_clusters(n_each: int, seed: int, gap: float = 100.0, dim: int = 3):
     return np.ascontiguousarray(np.concatenate([a, b]), dtype=np.float64)
 
 
-def _pair_sq(X, i, j):
-    if X.dtype == np.uint8:
-        d = X[i].astype(np.int64) - X[j].astype(np.int64)
-        return (d * d).sum(axis=-1).astype(np.float64) / 65025.0
-    d = X[i] - X[j]
-    return (d * d).sum(axis=-1)
+def _pair_sq(X, i, j, chunk=1 << 14):
+    out = np.empty(i.shape[0], np.float64)
+    for s in range(0, i.shape[0], chunk):
+        a, b = X[i[s:s + chunk]], X[j[s:s + chunk]]
+        if X.dtype == np.uint8:
+            d = a.astype(np.int32) - b.astype(np.int32)
+            out[s:s + chunk] = np.einsum("ij,ij->i", d, d).astype(np.float64) / 65025.0
+        else:
+            d = a - b
+            out[s:s + chunk] = (d * d).sum(axis=-1)
+    return out
 
 
 def median_sq_dist_eps(X: np.ndarray, seed: int, exact_max: int = 4096, pairs: int = 1 << 20):
