@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <type_traits>
 
 #include "op.hpp"
 
@@ -108,6 +109,7 @@ __device__ inline v4i codes16(const uint8_t* x, int32_t idx, int k, int dim) {
 __global__ void __launch_bounds__(256) k_gram_u8(const GramBlock* blocks, const uint8_t* x, const int32_t* ns, int dim,
                                                  double eps, int mode, void* out) {
     const GramBlock B = blocks[blockIdx.y];
+    if (B.nr <= 0 || B.nc <= 0) return;
     const int tiles_c = (B.nc + 63) / 64;
     const int tr = blockIdx.x / tiles_c, tc = blockIdx.x % tiles_c;
     if (tr * 64 >= B.nr) return;
@@ -935,16 +937,28 @@ struct Geo {
 
 // exact u8 distance blocks with matrix cores (see k_gram_u8); blocks must stay
 // alive until the launches complete, so this synchronises the stream
-static void gram_launch(const Geo& G, const std::vector<GramBlock>& blocks, int mode, void* out, hipStream_t s) {
+// and checks every block against the output's extent before the launch
+template <typename T>
+static void gram_launch(const Geo& G, const std::vector<GramBlock>& blocks, int mode, DevBuf<T>& out, hipStream_t s) {
+    static_assert(sizeof(T) == (std::is_same<T, double>::value ? 8 : 4), "output is int32 or float64");
+    HDM_CHECK(((mode == 0) == std::is_same<T, int32_t>::value), HDM_EINTERNAL, "distance block output type");
     if (blocks.empty()) return;
-    DevBuf<GramBlock> d = to_device(blocks, s);
     int64_t maxt = 0;
-    for (const GramBlock& b : blocks) maxt = std::max<int64_t>(maxt, int64_t((b.nr + 63) / 64) * ((b.nc + 63) / 64));
+    for (const GramBlock& b : blocks) {
+        HDM_CHECK(b.nr >= 0 && b.nc >= 0 && b.off >= 0, HDM_EINTERNAL, "distance block with a negative extent");
+        if (b.nr == 0 || b.nc == 0) continue;
+        const int64_t last = b.colmajor ? b.off + int64_t(b.nc - 1) * b.ld + (b.nr - 1)
+                                        : b.off + int64_t(b.nr - 1) * b.ld + (b.nc - 1);
+        HDM_CHECK(b.ld >= (b.colmajor ? b.nr : b.nc) && last < static_cast<int64_t>(out.n), HDM_EINTERNAL,
+                  "distance block outside its output");
+        maxt = std::max<int64_t>(maxt, int64_t((b.nr + 63) / 64) * ((b.nc + 63) / 64));
+    }
+    DevBuf<GramBlock> d = to_device(blocks, s);
     if (maxt == 0) return;
     for (size_t base = 0; base < blocks.size(); base += 65535) {
         const int cnt = static_cast<int>(std::min<size_t>(65535, blocks.size() - base));
         hipLaunchKernelGGL(k_gram_u8, dim3(static_cast<unsigned>(maxt), cnt), dim3(256), 0, s, d.get() + base, G.P.xu,
-                           G.ns.get(), G.P.dim, G.P.eps, mode, out);
+                           G.ns.get(), G.P.dim, G.P.eps, mode, static_cast<void*>(out.get()));
     }
     check_launch("u8 distance blocks");
     HDM_HIP(hipStreamSynchronize(s));
@@ -994,7 +1008,7 @@ static void build_tree(Op& op, int mode, int it, DevBuf<int32_t>& perm, DevBuf<i
                                                static_cast<int32_t>(std::min<int64_t>(op.size[h], kSample)),
                                                op.start[h] * kSample, kSample, 0});
                 }
-                gram_launch(G, blocks, 1, kvals.get(), s);
+                gram_launch(G, blocks, 1, kvals, s);
                 hipLaunchKernelGGL(k_row_sums, dim3(gN), dim3(kBlock), 0, s, kvals.get(), n, nsamp.get(), kSample, lvl,
                                    op.d_start.get(), sumk.get());
             } else {
@@ -1169,7 +1183,7 @@ static void skeletonize(Op& op, const Geo& G, hipStream_t s) {
             for (int t = 0; t < nodes; ++t)
                 blocks.push_back(GramBlock{rows.get() + int64_t(t) * rmax, cand.get() + int64_t(t) * cmax, h_nr[t],
                                            h_nc[t], int64_t(t) * rmax * cmax, h_nc[t], 0});
-            gram_launch(G, blocks, 1, B.get(), s);
+            gram_launch(G, blocks, 1, B, s);
         } else {
             hipLaunchKernelGGL(k_block, dim3(ceil_div(static_cast<int64_t>(rmax) * cmax, kBlock), nodes), dim3(kBlock),
                                0, s, A, P);
@@ -1256,7 +1270,7 @@ static void build_tiles(Op& op, const Geo& G, hipStream_t s) {
         std::vector<GramBlock> blocks;
         for (const NearPair& pr : pairs)
             blocks.push_back(GramBlock{op.perm.get() + pr.a0, op.perm.get() + pr.b0, pr.na, pr.nb, pr.off, pr.ld, 1});
-        gram_launch(G, blocks, 1, op.near64.get(), s);
+        gram_launch(G, blocks, 1, op.near64, s);
     } else {
         DevBuf<NearPair> dp = to_device(pairs, s);
         int64_t maxe = 0;
@@ -1306,7 +1320,7 @@ static void build_tiles(Op& op, const Geo& G, hipStream_t s) {
                 col += op.rank[g];
             }
         }
-        gram_launch(G, gb, 1, op.far64.get(), s);
+        gram_launch(G, gb, 1, op.far64, s);
     } else if (!blocks.empty()) {
         DevBuf<FarBlock> db = to_device(blocks, s);
         int64_t maxe = 0;
@@ -1401,7 +1415,7 @@ void compress_operator(Op& op, const void* X, int x_on_device, hipStream_t s) {
                 blocks.push_back(GramBlock{kperm.get() + op.start[h], kperm.get() + op.start[h],
                                            static_cast<int32_t>(op.size[h]), static_cast<int32_t>(op.size[h]),
                                            (h - op.L) * leafmax * leafmax, static_cast<int32_t>(leafmax), 0});
-            gram_launch(G, blocks, 0, leafd2.get(), s);
+            gram_launch(G, blocks, 0, leafd2, s);
         }
         hipLaunchKernelGGL(k_knn_leaf, dim3(op.L * splits), dim3(kKnnBlock), shm, s, op.depth, op.d_start.get(),
                            op.d_size.get(), kperm.get(), P, k, stage, splits, G.gram ? leafd2.get() : nullptr,
