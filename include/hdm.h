@@ -164,15 +164,23 @@ hdm_status hdm_op_degrees(hdm_op op, double *q, double *d, double *c);
  * symmetric conjugate of the Markov matrix of Alg. 1.  x, y: device float64,
  * n x nrhs column-major (ld = n), 1 <= nrhs <= 64, x and y must not overlap.
  * Tiles are applied in the operator's near/far precision with float32
- * accumulation (float64 when the tiles are float64). */
+ * accumulation (float64 when the tiles are float64).  Columns are taken 16 at a
+ * time, each tile read once per pass.  Float16 near tiles run on the matrix
+ * cores: the vectors are staged per leaf and column as a power-of-two scale
+ * times a float16 hi + lo pair (about 22 bits), the sums are float32. */
 hdm_status hdm_matvec(hdm_op op, int normalised, const double *x, double *y, int32_t nrhs, void *stream);
 
 /* ---- eigensolver (Alg. 1 eigendecomposition; Sec. 2.2 Lanczos) --------------
  * Leading r eigenpairs (largest algebraic) of S~ by Lanczos with full float64
- * reorthogonalisation.  block = 1: single-vector Lanczos; block > 1: block
- * Lanczos with that many start vectors.  Stops when every pair i < r has
- * |beta_j y_{j,i}| <= rel_resid_tol |theta_i| or when the basis reaches
- * max_basis vectors (then HDM_ENOCONV with evals/info filled).
+ * reorthogonalisation.  block = 1: single-vector Lanczos, stops when every
+ * pair i < r has |beta_j y_{j,i}| <= rel_resid_tol |theta_i|.  2 <= block <= 16:
+ * block Lanczos with that many vectors per step (one product with block
+ * right-hand sides, block QR by shifted Cholesky QR, banded projected matrix
+ * solved after Householder tridiagonalisation); pair i is accepted when
+ * ||B_j y_i[last block entries]|| <= rel_resid_tol |theta_i|, and max_basis is
+ * at most 512 (default min(n, 512), rounded down to a multiple of block).
+ * Either stops with HDM_ENOCONV, evals/info filled, when the basis reaches
+ * max_basis vectors; HDM_ENUMERIC if a residual block loses rank.
  * evals: host, r entries, descending.  evecs: device float64 n x r (column-major,
  * phi: unit 2-norm, largest-magnitude entry positive) or NULL. */
 hdm_status hdm_eigs(hdm_op op, int32_t r, double rel_resid_tol, int32_t block, int32_t max_basis, uint64_t seed,

@@ -285,6 +285,284 @@ __global__ void __launch_bounds__(kBlock) k_combine(Batch b) {
     }
 }
 
+// ---- several right-hand sides (2 <= nrhs <= 16) -------------------------------
+// The same phases with every matrix element loaded once for all columns: each
+// lane keeps one partial sum per right-hand side.
+template <typename V, typename TP>
+__global__ void k_n2s_m(Batch b) {
+    const int64_t u = blockIdx.x * static_cast<int64_t>(blockDim.x / kWave) + threadIdx.x / kWave;
+    if (u >= b.pre[b.nops]) return;
+    const int o = batch_op(b, u);
+    const OpDev& D = *b.op[o];
+    const int lvl = b.arg[o];
+    const RowTask T = D.rows[D.row_begin[lvl] + (u - b.pre[o])];
+    const int nc = D.ncand[T.h];
+    const TP* row = static_cast<const TP*>(D.P) + D.poff[T.h] + static_cast<int64_t>(T.i) * nc;
+    V* skw = static_cast<V*>(D.skw);
+    const bool leaf = lvl == D.depth;
+    const V* in = leaf ? static_cast<const V*>(D.w) + D.start[T.h] : skw + D.skoff[2 * T.h];
+    const int64_t ldin = leaf ? D.n : D.ldsk;
+    const int lane = threadIdx.x % kWave;
+    V acc[kMaxRhs];
+#pragma unroll
+    for (int c = 0; c < kMaxRhs; ++c) acc[c] = 0;
+    // loads are unconditional (columns past nrhs repeat the last one) so that
+    // they issue together; only the stores are guarded
+    const int last = b.nrhs - 1;
+    for (int j = lane; j < nc; j += kWave) {
+        const V p = val<V>(row[j]);
+#pragma unroll
+        for (int c = 0; c < kMaxRhs; ++c) acc[c] += p * in[min(c, last) * ldin + j];
+    }
+#pragma unroll
+    for (int c = 0; c < kMaxRhs; ++c) {
+        if (c >= b.nrhs) break;
+        const V t = wave_sum(acc[c]);
+        if (lane == 0) skw[c * D.ldsk + D.skoff[T.h] + T.i] = t;
+    }
+}
+
+template <typename V, typename TF>
+__global__ void k_s2s_m(Batch b) {
+    const int64_t u = blockIdx.x * static_cast<int64_t>(blockDim.x / kWave) + threadIdx.x / kWave;
+    if (u >= b.pre[b.nops]) return;
+    const int o = batch_op(b, u);
+    const OpDev& D = *b.op[o];
+    const RowTask T = D.rows[u - b.pre[o]];
+    const int nc = D.far_cols[T.h];
+    const TF* row = static_cast<const TF*>(D.far) + D.far_off[T.h] + static_cast<int64_t>(T.i) * nc;
+    const int32_t* cm = D.far_colmap + D.far_colbase[T.h];
+    const V sc = D.fscale ? static_cast<V>(D.fscale[T.h]) : V(1);
+    const V* skw = static_cast<const V*>(D.skw);
+    V* sku = static_cast<V*>(D.sku);
+    const int lane = threadIdx.x % kWave;
+    V acc[kMaxRhs];
+#pragma unroll
+    for (int c = 0; c < kMaxRhs; ++c) acc[c] = 0;
+    const int last = b.nrhs - 1;
+    for (int j = lane; j < nc; j += kWave) {
+        const V p = val<V>(row[j]);
+        const int64_t col = cm[j];
+#pragma unroll
+        for (int c = 0; c < kMaxRhs; ++c) acc[c] += p * skw[min(c, last) * D.ldsk + col];
+    }
+#pragma unroll
+    for (int c = 0; c < kMaxRhs; ++c) {
+        if (c >= b.nrhs) break;
+        const V t = wave_sum(acc[c]);
+        if (lane == 0) sku[c * D.ldsk + D.skoff[T.h] + T.i] = t * sc;
+    }
+}
+
+// combine for several right-hand sides: the ancestor potentials of all columns
+// sit side by side in shared memory, so each P element is read once
+template <typename V, typename TP>
+__global__ void __launch_bounds__(kBlock) k_combine_m(Batch b) {
+    __shared__ V tot[2][kMaxRhs * kMaxRank];
+    const int64_t u = blockIdx.x;
+    const int o = batch_op(b, u);
+    const OpDev& D = *b.op[o];
+    const LeafPlan lp = D.leaves[u - b.pre[o]];
+    const TP* P = static_cast<const TP*>(D.P);
+    const V* sku = static_cast<const V*>(D.sku);
+    const int depth = D.row_total > 0 ? D.depth : 0;
+    const int nr = b.nrhs, last = nr - 1;   // loads past nrhs repeat the last column (unguarded, batched)
+    const int64_t ldp = D.ldp, ldsk = D.ldsk;
+    int cur = 0;
+    int rleaf = 0;
+    if (depth >= 1) {
+        const int64_t a1 = lp.heap >> (depth - 1);
+        const int r1 = D.rank[a1];
+        for (int e = threadIdx.x; e < nr * r1; e += blockDim.x) {
+            const int c = e / r1, i = e % r1;
+            tot[0][c * kMaxRank + i] = sku[c * ldsk + D.skoff[a1] + i];
+        }
+        __syncthreads();
+        for (int lvl = 2; lvl <= depth; ++lvl) {
+            const int64_t node = lp.heap >> (depth - lvl), par = node >> 1;
+            const int rp = D.rank[par], ncp = D.ncand[par], rn = D.rank[node];
+            const int off = (node & 1) ? D.rank[2 * par] : 0;
+            const TP* Pm = P + D.poff[par] + off;
+            for (int j = threadIdx.x; j < rn; j += blockDim.x) {
+                V acc[kMaxRhs];
+#pragma unroll
+                for (int c = 0; c < kMaxRhs; ++c) acc[c] = 0;
+                for (int i = 0; i < rp; ++i) {
+                    const V p = static_cast<V>(Pm[static_cast<int64_t>(i) * ncp + j]);
+#pragma unroll
+                    for (int c = 0; c < kMaxRhs; ++c) acc[c] += p * tot[cur][min(c, last) * kMaxRank + i];
+                }
+                const int64_t so = D.skoff[node] + j;
+                V sv[kMaxRhs];
+#pragma unroll
+                for (int c = 0; c < kMaxRhs; ++c) sv[c] = sku[min(c, last) * D.ldsk + so];
+#pragma unroll
+                for (int c = 0; c < kMaxRhs; ++c)
+                    if (c < nr) tot[cur ^ 1][c * kMaxRank + j] = sv[c] + acc[c];
+            }
+            __syncthreads();
+            cur ^= 1;
+        }
+        rleaf = D.rank[lp.heap];
+    }
+    const TP* Pl = P + D.poff[lp.heap];
+    const V* pc = static_cast<const V*>(D.part) + lp.part_off;
+    for (int j = threadIdx.x; j < lp.rows; j += blockDim.x) {
+        V f[kMaxRhs];
+#pragma unroll
+        for (int c = 0; c < kMaxRhs; ++c) f[c] = 0;
+        for (int q = 0; q < lp.nitems; ++q) {
+            const V* pq = pc + static_cast<int64_t>(q) * lp.ld + j;
+#pragma unroll
+            for (int c = 0; c < kMaxRhs; ++c) f[c] += pq[min(c, last) * ldp];
+        }
+        for (int i = 0; i < rleaf; ++i) {
+            const V p = static_cast<V>(Pl[static_cast<int64_t>(i) * lp.rows + j]);
+#pragma unroll
+            for (int c = 0; c < kMaxRhs; ++c) f[c] += p * tot[cur][min(c, last) * kMaxRank + i];
+        }
+        const int64_t pos = lp.start + j;
+        const double sc = b.arg[o] ? D.c[pos] : 1.0;
+        const int32_t dst = D.perm[pos];
+#pragma unroll
+        for (int c = 0; c < kMaxRhs; ++c)
+            if (c < nr) b.y[o][c * D.n + dst] = sc * static_cast<double>(f[c]);
+    }
+}
+
+// ---- half-precision near field on matrix cores --------------------------------
+// Packed tile layout: the block of near pair (a, b) is ld_a x kc_b (kc_b = |b|
+// rounded up to 8, zero padded) and element (r, k) sits at
+// ((k / 8) * ld_a + r) * 8 + k % 8, so one lane's 16-byte load is the 8
+// consecutive columns of one row that a 16x16x32 matrix instruction takes.
+// The vectors are staged per leaf as w = s (hi + lo) with hi, lo in float16
+// and s a power of two per leaf and column, so that the pair carries about 22
+// bits of w whatever its range; partial sums are float32.
+typedef _Float16 h8_t __attribute__((ext_vector_type(8)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+constexpr int kMmaRowTiles = 8;   // 16-row tiles per work item
+
+// stage w = c * x (tree order, float32) and its half-precision hi/lo pair per
+// leaf; one workgroup per leaf
+__global__ void __launch_bounds__(kBlock) k_prep_mma(Batch b) {
+    __shared__ uint32_t smax[kMaxRhs];
+    const int64_t u = blockIdx.x;
+    const int o = batch_op(b, u);
+    const OpDev& D = *b.op[o];
+    const int64_t a = u - b.pre[o];
+    const LeafPlan lp = D.leaves[a];
+    const int nr = lp.rows, nrhs = b.nrhs;
+    const int kc = (nr + 7) & ~7;
+    if (threadIdx.x < kMaxRhs) smax[threadIdx.x] = 0u;
+    __syncthreads();
+    float* w = static_cast<float*>(D.w);
+    for (int e = threadIdx.x; e < nrhs * nr; e += blockDim.x) {
+        const int c = e / nr, p = e % nr;
+        const int64_t pos = lp.start + p;
+        const double sc = b.arg[o] ? D.c[pos] : 1.0;
+        const float v = static_cast<float>(sc * b.x[o][c * D.n + D.perm[pos]]);
+        w[c * D.n + pos] = v;
+        atomicMax(&smax[c], __float_as_uint(fabsf(v)));
+    }
+    __syncthreads();
+    _Float16* hi = static_cast<_Float16*>(D.wh);
+    _Float16* lo = hi + kMaxRhs * D.ldw;
+    for (int e = threadIdx.x; e < nrhs * kc; e += blockDim.x) {
+        const int c = e / kc, p = e % kc;
+        const float m = __uint_as_float(smax[c]);
+        const int ex = m > 0.0f ? ilogbf(m) : 0;
+        float h = 0.0f, l = 0.0f;
+        if (p < nr) {
+            // the same float32 value as in the first pass, recomputed from x
+            const int64_t pos = lp.start + p;
+            const double sc = b.arg[o] ? D.c[pos] : 1.0;
+            const float v = ldexpf(static_cast<float>(sc * b.x[o][c * D.n + D.perm[pos]]), 13 - ex);   // |v| < 2^14
+            const _Float16 vh = static_cast<_Float16>(v);
+            h = static_cast<float>(vh);
+            l = v - h;
+        }
+        hi[c * D.ldw + lp.wpad + p] = static_cast<_Float16>(h);
+        lo[c * D.ldw + lp.wpad + p] = static_cast<_Float16>(l);
+        if (p == 0) D.wsc[a * kMaxRhs + c] = ldexpf(1.0f, ex - 13);
+    }
+}
+
+// One wave per item: up to 8 row tiles of 16 rows of one near tile against all
+// its columns, 32 columns per step, hi and lo halves of the vectors in turn.
+__global__ void __launch_bounds__(kBlock) k_l2l_mma(Batch b) {
+    const int64_t u = blockIdx.x * static_cast<int64_t>(blockDim.x / kWave) + threadIdx.x / kWave;
+    if (u >= b.pre[b.nops]) return;
+    const int o = batch_op(b, u);
+    const OpDev& D = *b.op[o];
+    const NearItem I = D.items[u - b.pre[o]];
+    const int lane = threadIdx.x % kWave, li = lane % 16, g = lane / 16;
+    const int nrt = I.nrows / 16;
+    const int kc = (I.ncols + 7) & ~7;
+    const _Float16* T = static_cast<const _Float16*>(D.near) + I.tile_off;
+    const bool jv = li < b.nrhs;   // B operand: column li of the vectors
+    const _Float16* whi = static_cast<const _Float16*>(D.wh) + static_cast<int64_t>(li) * D.ldw + I.col_pos;
+    const _Float16* wlo = whi + kMaxRhs * D.ldw;
+    f4_t acc[kMmaRowTiles];
+#pragma unroll
+    for (int t = 0; t < kMmaRowTiles; ++t) acc[t] = f4_t{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int k0 = 0; k0 < kc; k0 += 32) {
+        const int kg = k0 + 8 * g;   // this lane's 8 columns
+        const bool kv = kg < kc;
+        h8_t bh = {}, bl = {};
+        if (kv && jv) {
+            bh = *reinterpret_cast<const h8_t*>(whi + kg);
+            bl = *reinterpret_cast<const h8_t*>(wlo + kg);
+        }
+        h8_t av[kMmaRowTiles];
+#pragma unroll
+        for (int t = 0; t < kMmaRowTiles; ++t) {
+            const int r = I.row0 + 16 * t + li;
+            av[t] = {};
+            if (t < nrt && kv && r < I.ld)
+                av[t] = *reinterpret_cast<const h8_t*>(T + (static_cast<int64_t>(kg / 8) * I.ld + r) * 8);
+        }
+#pragma unroll
+        for (int t = 0; t < kMmaRowTiles; ++t) {
+            if (t < nrt) {
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(av[t], bh, acc[t], 0, 0, 0);
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(av[t], bl, acc[t], 0, 0, 0);
+            }
+        }
+    }
+    // lane holds rows 4 g + q (q < 4) of column li of every row tile
+    if (!jv) return;
+    const float sc = (D.nscale ? D.nscale[I.tile] : 1.0f) * D.wsc[static_cast<int64_t>(I.leaf_b) * kMaxRhs + li];
+    float* out = static_cast<float*>(D.part) + static_cast<int64_t>(li) * D.ldp + I.part_off;
+#pragma unroll
+    for (int t = 0; t < kMmaRowTiles; ++t) {
+        const int r = I.row0 + 16 * t + 4 * g;
+        if (t < nrt && r < I.ld)
+            *reinterpret_cast<f4_t*>(out + r) = f4_t{acc[t][0] * sc, acc[t][1] * sc, acc[t][2] * sc, acc[t][3] * sc};
+    }
+}
+
+// packed half-precision copy of the near tiles (layout above); rows past the
+// leaf and columns past |b| are zero
+__global__ void k_pack_near(const double* src, const int64_t* off64, const int64_t* offp, const int32_t* ld,
+                            const int32_t* na, const int32_t* nb, const float* scale, _Float16* dst) {
+    const int64_t t = blockIdx.y;
+    const int l = ld[t], rows = na[t], cols = nb[t];
+    const int groups = (cols + 7) / 8;
+    const double inv = scale ? 1.0 / static_cast<double>(scale[t]) : 1.0;
+    for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < static_cast<int64_t>(groups) * l;
+         e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int kg = static_cast<int>(e / l), r = static_cast<int>(e % l);
+        h8_t v;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int k = kg * 8 + q;
+            const double x = (r < rows && k < cols) ? src[off64[t] + static_cast<int64_t>(k) * l + r] * inv : 0.0;
+            v[q] = static_cast<_Float16>(static_cast<float>(x));
+        }
+        *reinterpret_cast<h8_t*>(dst + offp[t] + e * 8) = v;
+    }
+}
+
 // ---- normalisation and precision conversion --------------------------------
 __global__ void k_fill(double* x, int64_t n, double v) {
     const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
@@ -354,7 +632,7 @@ size_t Op::footprint() const {
            P64.bytes() + P32.bytes() + rows.bytes() + near64.bytes() + nearT.bytes() + near_scale.bytes() +
            far64.bytes() + farT.bytes() + far_scale.bytes() + far_colmap.bytes() + d_items.bytes() +
            d_leaves.bytes() + q.bytes() + d.bytes() + c.bytes() + w_tree.bytes() + skw.bytes() + sku.bytes() +
-           part.bytes() + d_row_tasks.bytes();
+           part.bytes() + d_row_tasks.bytes() + wh.bytes() + wsc.bytes() + d_items_mma.bytes() + d_leaves_mma.bytes();
 }
 
 void Lane::init() {
@@ -379,7 +657,7 @@ static void ensure_ws(Op& op, int nrhs) {
     op.w_tree.alloc(static_cast<size_t>(op.n) * nrhs * 8);
     op.skw.alloc(static_cast<size_t>(std::max<int64_t>(op.nskel, 1)) * nrhs * 8);
     op.sku.alloc(static_cast<size_t>(std::max<int64_t>(op.nskel, 1)) * nrhs * 8);
-    op.part.alloc(static_cast<size_t>(std::max<int64_t>(op.part_elems, 1)) * nrhs * 8);
+    op.part.alloc(static_cast<size_t>(std::max<int64_t>(std::max(op.part_elems, op.part_elems_mma), 1)) * nrhs * 8);
     op.ws_nrhs = nrhs;
 }
 
@@ -420,6 +698,18 @@ static void publish_descriptors(Op& op, hipStream_t s) {
         D.part = op.part.get();
         D.ldsk = std::max<int64_t>(op.nskel, 1);
         D.ldp = std::max<int64_t>(op.part_elems, 1);
+        D.wh = nullptr;
+        D.wsc = nullptr;
+        D.ldw = 0;
+        if (!f64 && op.packed) {   // matrix-core plan of the packed half-precision tiles
+            D.items = op.d_items_mma.get();
+            D.nitems = static_cast<int64_t>(op.items_mma.size());
+            D.leaves = op.d_leaves_mma.get();
+            D.ldp = std::max<int64_t>(op.part_elems_mma, 1);
+            D.wh = op.wh.get();
+            D.wsc = op.wsc.get();
+            D.ldw = op.ldw;
+        }
     };
     fill(op.host64, true);
     fill(op.hostT, false);
@@ -428,6 +718,71 @@ static void publish_descriptors(Op& op, hipStream_t s) {
     op.dev64.upload(&op.host64, 1, s);
     op.devT.upload(&op.hostT, 1, s);
     HDM_HIP(hipStreamSynchronize(s));
+}
+
+// Plan of the packed half-precision near field (k_l2l_mma): per near pair an
+// ld_a x kc_b packed tile; per (pair, group of at most 8 row tiles) one item;
+// per leaf one partial-sum slot of ld_a rows per near pair.  Vectors are staged
+// with every leaf padded to a multiple of 8 points.
+static void build_mma_plan(Op& op, hipStream_t s) {
+    const int64_t L = op.L;
+    op.packed = true;
+    std::vector<int64_t> wpad(L);
+    op.ldw = 0;
+    for (int64_t b = 0; b < L; ++b) {
+        wpad[b] = op.ldw;
+        op.ldw += (op.size[L + b] + 7) / 8 * 8;
+    }
+    op.near_tile_off_mma.assign(op.near_idx.size(), 0);
+    op.items_mma.clear();
+    op.leaves_mma.clear();
+    int64_t off = 0, part = 0;
+    for (int64_t a = 0; a < L; ++a) {
+        const int64_t ha = L + a;
+        const int32_t ld = op.near_ld[a];
+        const int ntiles = op.near_off[a + 1] - op.near_off[a];
+        LeafPlan lp{};
+        lp.part_off = part;
+        lp.nitems = ntiles;
+        lp.ld = ld;
+        lp.start = static_cast<int32_t>(op.start[ha]);
+        lp.rows = static_cast<int32_t>(op.size[ha]);
+        lp.heap = static_cast<int32_t>(ha);
+        const int rt = (ld + 15) / 16;                        // 16-row tiles covering ld rows
+        const int groups = (rt + kMmaRowTiles - 1) / kMmaRowTiles;
+        lp.ngroups = groups;
+        lp.wpad = wpad[a];
+        for (int32_t t = op.near_off[a]; t < op.near_off[a + 1]; ++t) {
+            const int32_t b = op.near_idx[t];
+            const int64_t nb = op.size[L + b];
+            op.near_tile_off_mma[t] = off;
+            const int q = t - op.near_off[a];
+            for (int g = 0, t0 = 0; g < groups; ++g) {
+                const int cnt = rt / groups + (g < rt % groups ? 1 : 0);
+                NearItem I{};
+                I.tile_off = off;
+                I.part_off = part + static_cast<int64_t>(q) * ld;
+                I.ld = ld;
+                I.row0 = 16 * t0;
+                I.ncols = static_cast<int32_t>(nb);
+                I.col_pos = static_cast<int32_t>(wpad[b]);
+                I.tile = t;
+                I.nrows = 16 * cnt;
+                I.leaf_b = b;
+                op.items_mma.push_back(I);
+                t0 += cnt;
+            }
+            off += static_cast<int64_t>(ld) * ((nb + 7) / 8 * 8);
+        }
+        part += static_cast<int64_t>(ntiles) * ld;
+        op.leaves_mma.push_back(lp);
+    }
+    op.near_elems_mma = off;
+    op.part_elems_mma = part;
+    op.d_items_mma = to_device(op.items_mma, s);
+    op.d_leaves_mma = to_device(op.leaves_mma, s);
+    op.wh.alloc(static_cast<size_t>(std::max<int64_t>(op.ldw, 1)) * 2 * kMaxRhs * sizeof(_Float16));
+    op.wsc.alloc(static_cast<size_t>(L) * kMaxRhs);
 }
 
 void build_eval_plan(Op& op, hipStream_t s) {
@@ -499,6 +854,7 @@ void build_eval_plan(Op& op, hipStream_t s) {
     }
     op.row_total = static_cast<int64_t>(tasks.size());
     op.d_row_tasks = to_device(tasks, s);
+    if (op.prm.near_prec == HDM_F16) build_mma_plan(op, s);
     op.lane.init();
     ensure_ws(op, 1);
     publish_descriptors(op, s);
@@ -507,6 +863,9 @@ void build_eval_plan(Op& op, hipStream_t s) {
 template <typename V, typename TN, typename TF, typename TP>
 static void apply_t(const ApplyReq* reqs, int nops, bool f64, int normalised, int nrhs, hipStream_t s, Lane& lane,
                     Ctx* cx) {
+    // half-precision near tiles are packed for the matrix cores (float64 products use the plain layout)
+    constexpr bool mma = std::is_same<TN, f16_t>::value;
+    const bool multi = nrhs > 1;
     Batch b{};
     b.nops = nops;
     b.nrhs = nrhs;
@@ -523,9 +882,15 @@ static void apply_t(const ApplyReq* reqs, int nops, bool f64, int normalised, in
     const int wpb = kBlock / kWave;
     {   // gather + scale into tree order
         for (int o = 0; o < nops; ++o) b.arg[o] = normalised;
-        const int64_t tot = prefix([](const Op& op, int) { return op.n; });
         KernelEvents ev(cx, HDM_PHASE_PREP);
-        hipExtLaunchKernelGGL((k_prep<V>), dim3(ceil_div(tot, kBlock)), dim3(kBlock), 0, s, ev.start, ev.stop, 0, b);
+        if (mma) {
+            const int64_t tot = prefix([](const Op& op, int) { return static_cast<int64_t>(op.L); });
+            hipExtLaunchKernelGGL(k_prep_mma, dim3(tot), dim3(kBlock), 0, s, ev.start, ev.stop, 0, b);
+        } else {
+            const int64_t tot = prefix([](const Op& op, int) { return op.n; });
+            hipExtLaunchKernelGGL((k_prep<V>), dim3(ceil_div(tot, kBlock)), dim3(kBlock), 0, s, ev.start, ev.stop, 0,
+                                  b);
+        }
     }
     bool tree = false;
     int maxdepth = 0;
@@ -545,29 +910,46 @@ static void apply_t(const ApplyReq* reqs, int nops, bool f64, int normalised, in
                     return lvl >= 1 ? op.row_count[lvl] : int64_t(0);
                 });
                 if (tot == 0) continue;
-                hipLaunchKernelGGL((k_n2s<V, TP>), dim3(ceil_div(tot, wpb)), dim3(kBlock), 0, lane.side, b);
+                if (multi)
+                    hipLaunchKernelGGL((k_n2s_m<V, TP>), dim3(ceil_div(tot, wpb)), dim3(kBlock), 0, lane.side, b);
+                else
+                    hipLaunchKernelGGL((k_n2s<V, TP>), dim3(ceil_div(tot, wpb)), dim3(kBlock), 0, lane.side, b);
             }
         }
         {
             const int64_t tot = prefix([](const Op& op, int) { return op.row_total; });
             KernelEvents ev(cx, HDM_PHASE_S2S);
-            if (tot > 0)
-                hipExtLaunchKernelGGL((k_s2s<V, TF>), dim3(ceil_div(tot, wpb)), dim3(kBlock), 0, lane.side, ev.start,
-                                      ev.stop, 0, b);
+            if (tot > 0) {
+                if (multi)
+                    hipExtLaunchKernelGGL((k_s2s_m<V, TF>), dim3(ceil_div(tot, wpb)), dim3(kBlock), 0, lane.side,
+                                          ev.start, ev.stop, 0, b);
+                else
+                    hipExtLaunchKernelGGL((k_s2s<V, TF>), dim3(ceil_div(tot, wpb)), dim3(kBlock), 0, lane.side,
+                                          ev.start, ev.stop, 0, b);
+            }
         }
         HDM_HIP(hipEventRecord(lane.join, lane.side));
     }
     {
-        const int64_t tot = prefix([](const Op& op, int) { return static_cast<int64_t>(op.items.size()); });
+        const int64_t tot = prefix([](const Op& op, int) {
+            return static_cast<int64_t>(mma ? op.items_mma.size() : op.items.size());
+        });
         KernelEvents ev(cx, HDM_PHASE_L2L);
-        hipExtLaunchKernelGGL((k_l2l<V, TN>), dim3(ceil_div(tot, wpb)), dim3(kBlock), 0, s, ev.start, ev.stop, 0, b);
+        if (mma)
+            hipExtLaunchKernelGGL(k_l2l_mma, dim3(ceil_div(tot, wpb)), dim3(kBlock), 0, s, ev.start, ev.stop, 0, b);
+        else
+            hipExtLaunchKernelGGL((k_l2l<V, TN>), dim3(ceil_div(tot, wpb)), dim3(kBlock), 0, s, ev.start, ev.stop, 0,
+                                  b);
     }
     if (tree) HDM_HIP(hipStreamWaitEvent(s, lane.join, 0));
     {
         for (int o = 0; o < nops; ++o) b.arg[o] = normalised;
         const int64_t tot = prefix([](const Op& op, int) { return static_cast<int64_t>(op.L); });
         KernelEvents ev(cx, HDM_PHASE_COMBINE);
-        hipExtLaunchKernelGGL((k_combine<V, TP>), dim3(tot), dim3(kBlock), 0, s, ev.start, ev.stop, 0, b);
+        if (multi)
+            hipExtLaunchKernelGGL((k_combine_m<V, TP>), dim3(tot), dim3(kBlock), 0, s, ev.start, ev.stop, 0, b);
+        else
+            hipExtLaunchKernelGGL((k_combine<V, TP>), dim3(tot), dim3(kBlock), 0, s, ev.start, ev.stop, 0, b);
     }
     check_launch("apply");
 }
@@ -598,6 +980,7 @@ static void apply_dispatch(const ApplyReq* reqs, int nops, bool f64, int normali
 
 void apply_batch(const ApplyReq* reqs, int nops, int normalised, int nrhs, hipStream_t s, Lane& lane, Ctx* cx) {
     HDM_CHECK(nops >= 1 && nops <= kMaxBatch, HDM_EINVAL, "batch size out of range");
+    HDM_CHECK(nrhs >= 1 && nrhs <= kMaxRhs, HDM_EINVAL, "a batched product takes 1 to 16 right-hand sides");
     const Op& op0 = *reqs[0].op;
     const bool f64 = op0.prm.near_prec == HDM_F64;
     for (int o = 0; o < nops; ++o) {
@@ -615,14 +998,18 @@ void apply_batch(const ApplyReq* reqs, int nops, int normalised, int nrhs, hipSt
 
 void apply(Op& op, int normalised, bool exact64, const double* x, double* y, int nrhs, hipStream_t s) {
     HDM_CHECK(op.prm.max_rank_s <= kMaxRank, HDM_EINTERNAL, "rank above the combine kernel's limit");
-    if (op.ws_nrhs < nrhs) {
-        ensure_ws(op, nrhs);
+    HDM_CHECK(nrhs >= 1, HDM_EINVAL, "nrhs must be >= 1");
+    const int per = std::min(nrhs, kMaxRhs);   // right-hand sides per pass
+    if (op.ws_nrhs < per) {
+        ensure_ws(op, per);
         publish_descriptors(op, s);
     }
-    const ApplyReq r{&op, x, y};
     const bool f64 = exact64 || op.prm.near_prec == HDM_F64;
     HDM_CHECK(!f64 || op.near64.n > 0 || op.near_elems == 0, HDM_EINTERNAL, "float64 tiles are not resident");
-    apply_dispatch(&r, 1, f64, normalised, nrhs, s, op.lane, op.ctx);
+    for (int c0 = 0; c0 < nrhs; c0 += per) {
+        const ApplyReq r{&op, x + static_cast<int64_t>(c0) * op.n, y + static_cast<int64_t>(c0) * op.n};
+        apply_dispatch(&r, 1, f64, normalised, std::min(per, nrhs - c0), s, op.lane, op.ctx);
+    }
 }
 
 // q = K~ 1, d = Q^-1 K~ Q^-1 1, c = 1 / (q sqrt(d)), with float64 tiles
@@ -671,6 +1058,42 @@ static void convert_tiles(const DevBuf<double>& src, const std::vector<int64_t>&
     HDM_HIP(hipStreamSynchronize(s));
 }
 
+// float16 near tiles in the packed matrix-core layout, one scale per tile
+static void pack_near(Op& op, const std::vector<int64_t>& noff, const std::vector<int64_t>& ncnt, hipStream_t s) {
+    const int64_t L = op.L;
+    const size_t nt = noff.size();
+    op.nearT.alloc(static_cast<size_t>(std::max<int64_t>(op.near_elems_mma, 1)) * sizeof(_Float16));
+    if (nt == 0) return;
+    std::vector<int64_t> offp(nt);
+    std::vector<int32_t> ld(nt), na(nt), nb(nt);
+    int64_t maxg = 0;
+    for (int64_t a = 0; a < L; ++a)
+        for (int32_t t = op.near_off[a]; t < op.near_off[a + 1]; ++t) {
+            offp[t] = op.near_tile_off_mma[t];
+            ld[t] = op.near_ld[a];
+            na[t] = static_cast<int32_t>(op.size[L + a]);
+            nb[t] = static_cast<int32_t>(op.size[L + op.near_idx[t]]);
+            maxg = std::max<int64_t>(maxg, static_cast<int64_t>(ld[t]) * ((nb[t] + 7) / 8));
+            HDM_CHECK(offp[t] + static_cast<int64_t>(ld[t]) * ((nb[t] + 7) / 8 * 8) <= op.near_elems_mma &&
+                          noff[t] + ncnt[t] <= op.near_elems && ncnt[t] == static_cast<int64_t>(ld[t]) * nb[t],
+                      HDM_EINTERNAL, "packed near tile outside its buffer");
+        }
+    DevBuf<int64_t> d_off = to_device(noff, s), d_cnt = to_device(ncnt, s), d_offp = to_device(offp, s);
+    DevBuf<int32_t> d_ld = to_device(ld, s), d_na = to_device(na, s), d_nb = to_device(nb, s);
+    op.near_scale.alloc(nt);
+    hipLaunchKernelGGL(k_tile_max, dim3(nt), dim3(kBlock), 0, s, op.near64.get(), d_off.get(), d_cnt.get(),
+                       op.near_scale.get());
+    const unsigned gx = static_cast<unsigned>(std::min<int64_t>(ceil_div(maxg, kBlock), 64));
+    for (size_t base = 0; base < nt; base += 65535) {
+        const int cnt = static_cast<int>(std::min<size_t>(65535, nt - base));
+        hipLaunchKernelGGL(k_pack_near, dim3(gx, cnt), dim3(kBlock), 0, s, op.near64.get(), d_off.get() + base,
+                           d_offp.get() + base, d_ld.get() + base, d_na.get() + base, d_nb.get() + base,
+                           op.near_scale.get() + base, reinterpret_cast<_Float16*>(op.nearT.get()));
+    }
+    check_launch("pack near tiles");
+    HDM_HIP(hipStreamSynchronize(s));
+}
+
 void convert_eval_precision(Op& op, hipStream_t s) {
     if (op.prm.near_prec == HDM_F64 && op.prm.far_prec == HDM_F64) return;
     HDM_CHECK(op.prm.near_prec != HDM_F64 && op.prm.far_prec != HDM_F64, HDM_EINVAL,
@@ -698,7 +1121,10 @@ void convert_eval_precision(Op& op, hipStream_t s) {
             default: fail(HDM_EINVAL, "bad tile precision");
         }
     };
-    go(op.prm.near_prec, op.near64, noff, ncnt, op.nearT, op.near_scale, op.near_elems);
+    if (op.packed)
+        pack_near(op, noff, ncnt, s);
+    else
+        go(op.prm.near_prec, op.near64, noff, ncnt, op.nearT, op.near_scale, op.near_elems);
     go(op.prm.far_prec, op.far64, foff, fcnt, op.farT, op.far_scale, op.far_elems);
     op.P32.alloc(std::max<int64_t>(op.np, 1));
     if (op.np > 0)

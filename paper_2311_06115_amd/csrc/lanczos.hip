@@ -60,13 +60,31 @@ __global__ void k_gemvt(const double* V, int64_t ldv, int ncols, const double* y
     }
 }
 
-// h[c] = sum_b partial[b][c] (fixed order)
-__global__ void k_reduce_cols(const double* partial, int nb, int ldp, int ncols, double* h) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= ncols) return;
-    double acc = 0.0;
-    for (int b = 0; b < nb; ++b) acc += partial[static_cast<int64_t>(b) * ldp + c];
-    h[c] = acc;
+// h[c] = sum_b partial[b][c] in a fixed order: a workgroup of 256 threads takes
+// 64 columns; each quarter of it sums a quarter of the blocks with eight
+// independent accumulators (loads in flight together), and the quarters and
+// accumulators are added in a fixed order.
+__global__ void __launch_bounds__(256) k_reduce_cols(const double* partial, int nb, int ldp, int ncols, double* h) {
+    __shared__ double qs[4][64];
+    const int cl = threadIdx.x % 64, qt = threadIdx.x / 64;
+    const int c = blockIdx.x * 64 + cl;
+    const int per = (nb + 3) / 4;
+    const int b0 = min(nb, qt * per), b1 = min(nb, b0 + per);
+    double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (c < ncols) {
+        int b = b0;
+        for (; b + 8 <= b1; b += 8) {
+            double x[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) x[u] = partial[static_cast<int64_t>(b + u) * ldp + c];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc[u] += x[u];
+        }
+        for (; b < b1; ++b) acc[0] += partial[static_cast<int64_t>(b) * ldp + c];
+    }
+    qs[qt][cl] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+    __syncthreads();
+    if (qt == 0 && c < ncols) h[c] = ((qs[0][cl] + qs[1][cl]) + qs[2][cl]) + qs[3][cl];
 }
 
 // y -= V h (c < ncols); partial norms of the result when np != nullptr
@@ -312,6 +330,298 @@ __global__ void k_col_fix(double* Phi, int64_t n, const double* nrm, const int64
         Phi[k * n + i] *= sc;
 }
 
+// ---------------------------------------------------------------------------
+// block Lanczos (b right-hand sides per product): basis products, the block QR
+// of the residual, the banded projected matrix and its Rayleigh-Ritz solve
+// ---------------------------------------------------------------------------
+constexpr int kBRows = 256;        // rows per workgroup in the block basis products
+constexpr int kMaxBlockBasis = 512;
+
+// the start block: column c of V takes the start-vector draws of column c
+__global__ void k_start_block(double* V, int64_t n, int b, uint64_t seed) {
+    const int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    if (e >= n * b) return;
+    const uint32_t c = static_cast<uint32_t>(e / n), i = static_cast<uint32_t>(e % n);
+    const uint32_t r = philox_draw(seed, kLanczosStart, c, 0, i);
+    V[e] = (static_cast<double>(r) + 0.5) / 4294967296.0 - 0.5;
+}
+
+// partial[blk][c * b + q] = sum over the block's rows of V[c][row] * Y[q][row]
+__global__ void __launch_bounds__(kBlock) k_gemmt(const double* V, int64_t ldv, int ncols, const double* Y,
+                                                  int64_t ldy, int b, int64_t n, double* partial, int64_t ldp) {
+    __shared__ double ys[kMaxRhs * kBRows];
+    const int64_t r0 = blockIdx.x * static_cast<int64_t>(kBRows);
+    for (int e = threadIdx.x; e < b * kBRows; e += blockDim.x) {
+        const int q = e / kBRows, rr = e % kBRows;
+        const int64_t row = r0 + rr;
+        ys[e] = row < n ? Y[q * ldy + row] : 0.0;
+    }
+    __syncthreads();
+    const int wv = threadIdx.x / 64, lane = threadIdx.x % 64, nw = blockDim.x / 64;
+    for (int c = wv; c < ncols; c += nw) {
+        double acc[kMaxRhs];
+#pragma unroll
+        for (int q = 0; q < kMaxRhs; ++q) acc[q] = 0.0;
+#pragma unroll
+        for (int k = 0; k < kBRows / 64; ++k) {
+            const int rr = lane + 64 * k;
+            const int64_t row = r0 + rr;
+            const double v = row < n ? V[c * ldv + row] : 0.0;
+#pragma unroll
+            for (int q = 0; q < kMaxRhs; ++q) acc[q] += v * ys[min(q, b - 1) * kBRows + rr];   // unguarded reads
+        }
+#pragma unroll
+        for (int q = 0; q < kMaxRhs; ++q) {
+            if (q >= b) break;
+            double t = acc[q];
+            for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+            if (lane == 0) partial[static_cast<int64_t>(blockIdx.x) * ldp + c * b + q] = t;
+        }
+    }
+}
+
+// Y[q][row] -= sum_c V[c][row] * H[c * b + q]
+__global__ void __launch_bounds__(kBlock) k_gemmn(const double* V, int64_t ldv, int ncols, const double* H, double* Y,
+                                                  int64_t ldy, int b, int64_t n) {
+    __shared__ double hs[kMaxBlockBasis * kMaxRhs];
+    for (int e = threadIdx.x; e < ncols * b; e += blockDim.x) hs[e] = H[e];
+    __syncthreads();
+    const int64_t row = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    if (row >= n) return;
+    double acc[kMaxRhs];
+#pragma unroll
+    for (int q = 0; q < kMaxRhs; ++q) acc[q] = 0.0;
+    for (int c = 0; c < ncols; ++c) {
+        const double v = V[c * ldv + row];
+#pragma unroll
+        for (int q = 0; q < kMaxRhs; ++q) acc[q] += v * hs[c * b + min(q, b - 1)];
+    }
+    double yv[kMaxRhs];
+#pragma unroll
+    for (int q = 0; q < kMaxRhs; ++q) yv[q] = Y[min(q, b - 1) * ldy + row];
+#pragma unroll
+    for (int q = 0; q < kMaxRhs; ++q)
+        if (q < b) Y[q * ldy + row] = yv[q] - acc[q];
+}
+
+__global__ void k_add(double* a, const double* b, int cnt) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < cnt) a[i] += b[i];
+}
+
+// Cholesky G + s I = R^T R (R upper, s = shift_coef * trace G), R^-1 and
+// R_tot <- R R_tot, by one workgroup of 256 threads (one per element of a
+// 16 x 16 block).  status = 1 when a pivot is not positive.
+__global__ void __launch_bounds__(256) k_chol(const double* G, int b, double shift_coef, double* Rinv, double* Rtot,
+                                              int* status) {
+    __shared__ double A[kMaxRhs * kMaxRhs], R[kMaxRhs * kMaxRhs], W[kMaxRhs * kMaxRhs];
+    __shared__ double sh;
+    __shared__ int bad;
+    const int t = threadIdx.x, i = t / kMaxRhs, k = t % kMaxRhs;
+    const bool in = i < b && k < b;
+    if (t == 0) {
+        double tr = 0.0;
+        for (int q = 0; q < b; ++q) tr += G[q * b + q];
+        sh = shift_coef * tr;
+        bad = 0;
+    }
+    __syncthreads();
+    if (in) {
+        A[i * b + k] = G[i * b + k] + (i == k ? sh : 0.0);
+        R[i * b + k] = 0.0;
+    }
+    __syncthreads();
+    // right-looking: row j of R, then the trailing update
+    for (int j = 0; j < b; ++j) {
+        if (t == 0) {
+            const double dj = A[j * b + j];
+            if (!(dj > 0.0)) bad = 1;
+            R[j * b + j] = dj > 0.0 ? sqrt(dj) : 1.0;
+        }
+        __syncthreads();
+        if (t > j && t < b) R[j * b + t] = A[j * b + t] / R[j * b + j];
+        __syncthreads();
+        if (in && i > j && k >= i) {
+            A[i * b + k] -= R[j * b + i] * R[j * b + k];
+            if (k > i) A[k * b + i] = A[i * b + k];
+        }
+        __syncthreads();
+    }
+    if (bad) {
+        if (t == 0) *status = 1;
+        return;
+    }
+    // R^-1: column c by back substitution (thread c)
+    if (t < b) {
+        const int c = t;
+        for (int r = b - 1; r >= 0; --r) {
+            double v = (r == c) ? 1.0 : 0.0;
+            for (int q = r + 1; q < b; ++q) v -= R[r * b + q] * W[q * b + c];
+            W[r * b + c] = r <= c ? v / R[r * b + r] : 0.0;
+        }
+    }
+    __syncthreads();
+    double rt = 0.0;
+    if (in) {
+        Rinv[i * b + k] = W[i * b + k];
+        for (int q = i; q <= k; ++q) rt += R[i * b + q] * Rtot[q * b + k];
+    }
+    __syncthreads();
+    if (in) Rtot[i * b + k] = k >= i ? rt : 0.0;
+}
+
+__global__ void k_eye(double* R, int b) {
+    const int e = threadIdx.x;
+    if (e < b * b) R[e] = (e / b == e % b) ? 1.0 : 0.0;
+}
+
+// rows of Y times R^-1 (upper), in place
+__global__ void __launch_bounds__(kBlock) k_trsm(double* Y, int64_t ldy, int b, int64_t n, const double* Rinv) {
+    __shared__ double ri[kMaxRhs * kMaxRhs];
+    for (int e = threadIdx.x; e < b * b; e += blockDim.x) ri[e] = Rinv[e];
+    __syncthreads();
+    const int64_t row = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    if (row >= n) return;
+    double y[kMaxRhs];
+#pragma unroll
+    for (int q = 0; q < kMaxRhs; ++q) y[q] = Y[min(q, b - 1) * ldy + row];
+#pragma unroll
+    for (int q = 0; q < kMaxRhs; ++q) {
+        if (q >= b) break;
+        double t = 0.0;
+#pragma unroll
+        for (int p = 0; p <= q; ++p) t += y[p] * ri[p * b + q];
+        Y[q * ldy + row] = t;
+    }
+}
+
+// block j of the banded projected matrix: T_jj = sym(A_j), T_{j+1,j} = B_j, T_{j,j+1} = B_j^T
+__global__ void k_put_T(double* T, int ldt, int j, int b, const double* H, const double* Rtot) {
+    const int e = threadIdx.x;
+    if (e >= b * b) return;
+    const int p = e / b, q = e % b;
+    const int64_t o = static_cast<int64_t>(j) * b;
+    T[(o + p) * ldt + o + q] = 0.5 * (H[(o + p) * b + q] + H[(o + q) * b + p]);
+    T[(o + b + p) * ldt + o + q] = Rtot[p * b + q];
+    T[(o + q) * ldt + o + b + p] = Rtot[p * b + q];
+}
+
+// sum over a workgroup of any size (multiple of 64), result in every thread
+__device__ inline double wg_sum(double v, double* red) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int wv = threadIdx.x / 64, lane = threadIdx.x % 64, nw = blockDim.x / 64;
+    __syncthreads();
+    if (lane == 0) red[wv] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int w = 0; w < nw; ++w) t += red[w];
+    return t;
+}
+
+// Householder tridiagonalisation (one workgroup) of the leading m x m block of
+// the symmetric T: d, e (e[m-1] = 0), the reflectors below the subdiagonal of
+// A's columns and tau, so that T = Q tridiag(d, e) Q^T, Q = H_0 ... H_{m-3}.
+__global__ void __launch_bounds__(1024) k_sytrd(const double* T, int ldt, int m, double* A, int lda, double* d,
+                                                 double* e, double* tau) {
+    __shared__ double v[kMaxBlockBasis], w[kMaxBlockBasis], red[16];
+    __shared__ double s_tau;
+    for (int64_t x = threadIdx.x; x < static_cast<int64_t>(m) * m; x += blockDim.x) {
+        const int i = static_cast<int>(x / m), j = static_cast<int>(x % m);
+        A[static_cast<int64_t>(i) * lda + j] = T[static_cast<int64_t>(i) * ldt + j];
+    }
+    __syncthreads();
+    for (int k = 0; k + 1 < m; ++k) {
+        const int len = m - k - 1;
+        const int i = threadIdx.x;
+        // x = column k below the diagonal, read as row k
+        const double xi = i < len ? A[static_cast<int64_t>(k) * lda + k + 1 + i] : 0.0;
+        const double sigma = wg_sum(i >= 1 && i < len ? xi * xi : 0.0, red);
+        const double alpha = A[static_cast<int64_t>(k) * lda + k + 1];
+        if (threadIdx.x == 0) d[k] = A[static_cast<int64_t>(k) * lda + k];
+        if (len == 1 || sigma == 0.0) {
+            if (threadIdx.x == 0) {
+                e[k] = alpha;
+                tau[k] = 0.0;
+            }
+            __syncthreads();
+            continue;
+        }
+        const double mu = sqrt(alpha * alpha + sigma);
+        const double beta = alpha <= 0.0 ? mu : -mu;
+        const double t = (beta - alpha) / beta;
+        const double inv = 1.0 / (alpha - beta);
+        if (i < len) v[i] = i == 0 ? 1.0 : xi * inv;
+        if (threadIdx.x == 0) {
+            e[k] = beta;
+            tau[k] = t;
+            s_tau = t;
+        }
+        __syncthreads();
+        // p = tau A22 v (A22 symmetric: element (j, i) read along rows, coalesced in i)
+        double pi = 0.0;
+        if (i < len) {
+            const double* col = A + static_cast<int64_t>(k + 1) * lda + k + 1 + i;
+            for (int j = 0; j < len; ++j) pi += col[static_cast<int64_t>(j) * lda] * v[j];
+            pi *= s_tau;
+        }
+        const double K = 0.5 * s_tau * wg_sum(i < len ? pi * v[i] : 0.0, red);
+        if (i < len) w[i] = pi - K * v[i];
+        __syncthreads();
+        // A22 -= v w^T + w v^T
+        for (int64_t x = threadIdx.x; x < static_cast<int64_t>(len) * len; x += blockDim.x) {
+            const int jj = static_cast<int>(x / len), ii = static_cast<int>(x % len);
+            A[static_cast<int64_t>(k + 1 + jj) * lda + k + 1 + ii] -= v[ii] * w[jj] + w[ii] * v[jj];
+        }
+        // keep the reflector in column k (rows k+2 .., never read again)
+        if (i >= 1 && i < len) A[static_cast<int64_t>(k + 1 + i) * lda + k] = v[i];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        d[m - 1] = A[static_cast<int64_t>(m - 1) * lda + m - 1];
+        e[m - 1] = 0.0;
+    }
+}
+
+// Z[k] <- Q Z[k] for the r eigenvectors of the tridiagonal matrix (one wave per vector)
+__global__ void __launch_bounds__(1024) k_ormtr(const double* A, int lda, const double* tau, int m, double* Z, int r) {
+    __shared__ double zs[16][kMaxBlockBasis];
+    const int wv = threadIdx.x / 64, lane = threadIdx.x % 64;
+    for (int k = wv; k < r; k += 16) {
+        double* z = zs[wv];
+        for (int i = lane; i < m; i += 64) z[i] = Z[static_cast<int64_t>(k) * m + i];
+        for (int kk = m - 3; kk >= 0; --kk) {
+            const double t = tau[kk];
+            if (t == 0.0) continue;
+            const int len = m - kk - 1;   // rows kk+1 .. m-1, v[kk+1] = 1
+            double dot = 0.0;
+            for (int i = lane; i < len; i += 64) {
+                const double vi = i == 0 ? 1.0 : A[static_cast<int64_t>(kk + 1 + i) * lda + kk];
+                dot += vi * z[kk + 1 + i];
+            }
+            for (int off = 32; off > 0; off >>= 1) dot += __shfl_xor(dot, off, 64);
+            for (int i = lane; i < len; i += 64) {
+                const double vi = i == 0 ? 1.0 : A[static_cast<int64_t>(kk + 1 + i) * lda + kk];
+                z[kk + 1 + i] -= t * dot * vi;
+            }
+        }
+        for (int i = lane; i < m; i += 64) Z[static_cast<int64_t>(k) * m + i] = z[i];
+    }
+}
+
+// residual bound of Ritz pair k: || B_j Z[k][m-b .. m) ||
+__global__ void k_block_bounds(const double* Z, int m, int b, const double* Bj, int r, double* bound) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= r) return;
+    const double* y = Z + static_cast<int64_t>(k) * m + (m - b);
+    double s = 0.0;
+    for (int p = 0; p < b; ++p) {
+        double t = 0.0;
+        for (int q = 0; q < b; ++q) t += Bj[p * b + q] * y[q];
+        s += t * t;
+    }
+    bound[k] = sqrt(s);
+}
+
 }  // namespace
 
 void LanczosRun::start(Op& o, int r_, double tol_, int max_basis_, uint64_t seed_, hipStream_t s) {
@@ -362,10 +672,10 @@ bool LanczosRun::after_product(hipStream_t s) {
     {   // CGS2 against the whole basis, alpha_j, beta_j
         PhaseScope ph(op->ctx, HDM_PHASE_ORTHO, s);
         hipLaunchKernelGGL(k_gemvt, dim3(nb), dim3(kBlock), 0, s, V.get(), n, nc, y.get(), n, part.get(), ldp);
-        hipLaunchKernelGGL(k_reduce_cols, dim3(ceil_div(nc, 64)), dim3(64), 0, s, part.get(), nb, ldp, nc, h1.get());
+        hipLaunchKernelGGL(k_reduce_cols, dim3(ceil_div(nc, 64)), dim3(256), 0, s, part.get(), nb, ldp, nc, h1.get());
         hipLaunchKernelGGL(k_gemvn, dim3(nb), dim3(kBlock), 0, s, V.get(), n, nc, h1.get(), y.get(), n, nullptr);
         hipLaunchKernelGGL(k_gemvt, dim3(nb), dim3(kBlock), 0, s, V.get(), n, nc, y.get(), n, part.get(), ldp);
-        hipLaunchKernelGGL(k_reduce_cols, dim3(ceil_div(nc, 64)), dim3(64), 0, s, part.get(), nb, ldp, nc, h2.get());
+        hipLaunchKernelGGL(k_reduce_cols, dim3(ceil_div(nc, 64)), dim3(256), 0, s, part.get(), nb, ldp, nc, h2.get());
         hipLaunchKernelGGL(k_gemvn, dim3(nb), dim3(kBlock), 0, s, V.get(), n, nc, h2.get(), y.get(), n, np.get());
         hipLaunchKernelGGL(k_alpha_beta, dim3(1), dim3(1), 0, s, h1.get(), h2.get(), j, np.get(), nb, alpha.get(),
                            beta.get());
@@ -426,9 +736,135 @@ hdm_status LanczosRun::result(double* evals, double* evecs, hdm_eig_info_t* info
     return converged ? HDM_OK : HDM_ENOCONV;
 }
 
+// Block Lanczos with b vectors per step (Sec. 2.2 with a block Krylov space):
+// each step applies S~ to the b newest basis vectors at once (one product with
+// b right-hand sides), reorthogonalises against the whole basis by classical
+// Gram-Schmidt twice, and orthonormalises the block by shifted Cholesky QR
+// three times (Fukaya et al., 2020), whose R is the next off-diagonal block
+// B_j of the banded projected matrix T.  Every second step T is reduced to
+// tridiagonal form by Householder reflections and solved like the
+// single-vector case; Ritz pair i is accepted when ||B_j y_i[last b]|| <=
+// tol |theta_i|.
+static hdm_status block_lanczos_eigs(Op& op, int r, double tol, int b, int max_basis, uint64_t seed, double* evals,
+                                     double* evecs, hdm_eig_info_t* info, hipStream_t s) {
+    const int64_t n = op.n;
+    HDM_CHECK(b >= 2 && b <= kMaxRhs && b <= n, HDM_EINVAL, "block must be in [2, min(16, n)]");
+    HDM_CHECK(r >= 1 && r <= 64 && r <= n, HDM_EINVAL, "r must be in [1, min(64, n)]");
+    int mb = max_basis <= 0 ? static_cast<int>(std::min<int64_t>(n, kMaxBlockBasis)) : max_basis;
+    mb = static_cast<int>(std::min<int64_t>(mb, n));
+    mb = mb / b * b;
+    HDM_CHECK(mb >= r && mb >= b && mb <= kMaxBlockBasis, HDM_EINVAL,
+              "max_basis must be in [max(r, block), 512] (rounded down to a multiple of block)");
+    const auto t0 = std::chrono::steady_clock::now();
+    const int ldt = mb + b;
+    const int nbk = ceil_div(n, kBRows);
+    const int64_t ldp = static_cast<int64_t>(mb + b) * b;
+    DevBuf<double> V(static_cast<size_t>(n) * (mb + b)), Y(static_cast<size_t>(n) * b), part(static_cast<size_t>(nbk) * ldp),
+        H1(ldp), H2(ldp), G(b * b), Rinv(b * b), Rtot(b * b), T(static_cast<size_t>(ldt) * ldt),
+        A(static_cast<size_t>(mb) * mb), dd(mb), ee(mb), tau(mb), theta(r), Z(static_cast<size_t>(r) * mb), bound(r),
+        work(static_cast<size_t>(r) * 5 * mb);
+    DevBuf<int> status(1);
+    HDM_HIP(hipMemsetAsync(status.get(), 0, sizeof(int), s));
+    HDM_HIP(hipMemsetAsync(T.get(), 0, T.bytes(), s));
+    const int gN = ceil_div(n, kBlock);
+    // Gram products X^T Y (ncols x b) over the basis or the block itself
+    auto gram = [&](const double* X, int ncols, const double* Yp, double* out) {
+        hipLaunchKernelGGL(k_gemmt, dim3(nbk), dim3(kBlock), 0, s, X, n, ncols, Yp, n, b, n, part.get(), ldp);
+        hipLaunchKernelGGL(k_reduce_cols, dim3(ceil_div(int64_t(ncols) * b, 64)), dim3(256), 0, s, part.get(), nbk,
+                           static_cast<int>(ldp), ncols * b, out);
+    };
+    // shifted Cholesky QR three times, in place; Rtot = R3 R2 R1
+    const double shift = 11.0 * (static_cast<double>(n) * b + static_cast<double>(b) * (b + 1)) * 1.1102230246251565e-16;
+    auto block_qr = [&](double* X) {
+        hipLaunchKernelGGL(k_eye, dim3(1), dim3(256), 0, s, Rtot.get(), b);
+        for (int pass = 0; pass < 3; ++pass) {
+            gram(X, b, X, G.get());
+            hipLaunchKernelGGL(k_chol, dim3(1), dim3(256), 0, s, G.get(), b, pass == 0 ? shift : 0.0, Rinv.get(),
+                               Rtot.get(), status.get());
+            hipLaunchKernelGGL(k_trsm, dim3(gN), dim3(kBlock), 0, s, X, n, b, n, Rinv.get());
+        }
+    };
+    hipLaunchKernelGGL(k_start_block, dim3(ceil_div(n * b, kBlock)), dim3(kBlock), 0, s, V.get(), n, b, seed);
+    block_qr(V.get());
+    check_launch("block lanczos start");
+    std::vector<double> h_theta(r), h_bound(r);
+    int m = 0, j = 0, since = 0, matvecs = 0;
+    bool converged = false;
+    for (;; ++j) {
+        const double* Q = V.get() + static_cast<int64_t>(j) * b * n;
+        apply(op, 1, false, Q, Y.get(), b, s);
+        matvecs += b;
+        const int nc = (j + 1) * b;
+        {
+            PhaseScope ph(op.ctx, HDM_PHASE_ORTHO, s);
+            gram(V.get(), nc, Y.get(), H1.get());
+            hipLaunchKernelGGL(k_gemmn, dim3(gN), dim3(kBlock), 0, s, V.get(), n, nc, H1.get(), Y.get(), n, b, n);
+            gram(V.get(), nc, Y.get(), H2.get());
+            hipLaunchKernelGGL(k_gemmn, dim3(gN), dim3(kBlock), 0, s, V.get(), n, nc, H2.get(), Y.get(), n, b, n);
+            hipLaunchKernelGGL(k_add, dim3(ceil_div(int64_t(nc) * b, 256)), dim3(256), 0, s, H1.get(), H2.get(), nc * b);
+            block_qr(Y.get());
+            HDM_HIP(hipMemcpyAsync(V.get() + static_cast<int64_t>(j + 1) * b * n, Y.get(), sizeof(double) * n * b,
+                                   hipMemcpyDeviceToDevice, s));
+            hipLaunchKernelGGL(k_put_T, dim3(1), dim3(256), 0, s, T.get(), ldt, j, b, H1.get(), Rtot.get());
+        }
+        check_launch("block lanczos step");
+        m = (j + 1) * b;
+        ++since;
+        const bool last = m + b > mb;
+        if (m >= r && (since >= 2 || last)) {
+            since = 0;
+            {
+                KernelEvents ev(op.ctx, HDM_PHASE_TRIDIAG);
+                hipExtLaunchKernelGGL(k_sytrd, dim3(1), dim3(1024), 0, s, ev.start, ev.stop, 0, T.get(), ldt, m,
+                                      A.get(), mb, dd.get(), ee.get(), tau.get());
+            }
+            hipLaunchKernelGGL(k_tridiag, dim3(ceil_div(r, 4)), dim3(kBlock), 0, s, dd.get(), ee.get(), m, r,
+                               theta.get(), Z.get(), bound.get(), work.get());
+            hipLaunchKernelGGL(k_ormtr, dim3(1), dim3(1024), 0, s, A.get(), mb, tau.get(), m, Z.get(), r);
+            hipLaunchKernelGGL(k_block_bounds, dim3(1), dim3(64), 0, s, Z.get(), m, b, Rtot.get(), r, bound.get());
+            check_launch("block rayleigh-ritz");
+            int st = 0;
+            status.download(&st, 1, s);
+            theta.download(h_theta.data(), r, s);
+            bound.download(h_bound.data(), r, s);
+            HDM_HIP(hipStreamSynchronize(s));
+            HDM_CHECK(st == 0, HDM_ENUMERIC, "block Lanczos: the residual block lost rank (Cholesky QR failed)");
+            bool ok = true;
+            for (int i = 0; i < r; ++i) ok = ok && (h_bound[i] <= tol * std::fabs(h_theta[i]));
+            if (ok) {
+                converged = true;
+                break;
+            }
+        }
+        if (last) break;
+    }
+    if (m < r || h_theta.empty()) fail(HDM_EINTERNAL, "block Lanczos ended before a Rayleigh-Ritz step");
+    for (int i = 0; i < r; ++i) evals[i] = h_theta[i];
+    double worst = 0.0;
+    for (int i = 0; i < r; ++i) worst = std::max(worst, h_bound[i] / std::max(std::fabs(h_theta[i]), 1e-300));
+    if (evecs) {
+        hipLaunchKernelGGL(k_ritz, dim3(gN), dim3(kBlock), 0, s, V.get(), n, m, Z.get(), r, evecs, n);
+        DevBuf<double> nrm(r);
+        DevBuf<int64_t> arg(r);
+        hipLaunchKernelGGL(k_col_stats, dim3(r), dim3(kBlock), 0, s, evecs, n, nrm.get(), arg.get());
+        hipLaunchKernelGGL(k_col_fix, dim3(std::min(gN, 256), r), dim3(kBlock), 0, s, evecs, n, nrm.get(), arg.get());
+        check_launch("ritz vectors");
+    }
+    HDM_HIP(hipStreamSynchronize(s));
+    if (info) {
+        info->iters = m;
+        info->matvecs = matvecs;
+        info->converged = converged ? 1 : 0;
+        info->max_rel_resid = worst;
+        info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return converged ? HDM_OK : HDM_ENOCONV;
+}
+
 hdm_status lanczos_eigs(Op& op, int r, double tol, int block, int max_basis, uint64_t seed, double* evals,
                         double* evecs, hdm_eig_info_t* info, hipStream_t s) {
-    HDM_CHECK(block == 1, HDM_EINVAL, "only block = 1 is supported by this build");
+    HDM_CHECK(block >= 1, HDM_EINVAL, "block must be >= 1");
+    if (block > 1) return block_lanczos_eigs(op, r, tol, block, max_basis, seed, evals, evecs, info, s);
     LanczosRun run;
     run.start(op, r, tol, max_basis, seed, s);
     while (!run.finished) {

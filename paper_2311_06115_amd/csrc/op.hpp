@@ -72,6 +72,7 @@ struct NearItem {
     int32_t col_pos;    // tree position of the first column's point
     int32_t tile;       // index of the near tile (for its scale)
     int32_t nrows;      // rows of the item: [row0, min(ld, row0 + nrows))
+    int32_t leaf_b;     // column leaf (matrix-core items: index of its vector scales)
 };
 
 // Per leaf: where its partial sums live and how many items feed each row group.
@@ -83,6 +84,7 @@ struct LeafPlan {
     int32_t rows;       // points in the leaf
     int32_t heap;       // heap id
     int32_t ngroups;    // row groups
+    int64_t wpad;       // matrix-core plans: offset of the leaf in the padded half-precision vectors
 };
 
 // one skeleton row: heap id and row index
@@ -91,6 +93,7 @@ struct RowTask {
 };
 
 constexpr int kMaxLevels = 17;   // tree depth <= 16
+constexpr int kMaxRhs = 16;      // right-hand sides per pass of a product (more are taken in passes)
 
 // Everything a product kernel needs about one operator, resident in device
 // memory next to it.  Two copies exist per operator: one for the float64 tiles
@@ -126,6 +129,12 @@ struct OpDev {
     void* sku;
     void* part;
     int64_t ldsk, ldp;
+    // half-precision near field on matrix cores: the staged vectors (hi and lo
+    // halves, 16 right-hand sides, leaves padded to 8 points) and their per
+    // leaf, per column scales
+    void* wh;
+    float* wsc;
+    int64_t ldw;
 };
 
 // A side stream with its fork/join events: the upward pass and the far field
@@ -191,6 +200,18 @@ struct Op {
     DevBuf<LeafPlan> d_leaves;
     int64_t part_elems = 0;
     int near_rows_per_group = 256;
+    // half-precision near tiles are packed for the matrix cores (evaluate.hip):
+    // their own tile offsets, items, leaf plans and partial-sum extent
+    bool packed = false;
+    std::vector<int64_t> near_tile_off_mma;
+    int64_t near_elems_mma = 0, part_elems_mma = 0;
+    std::vector<NearItem> items_mma;
+    DevBuf<NearItem> d_items_mma;
+    std::vector<LeafPlan> leaves_mma;
+    DevBuf<LeafPlan> d_leaves_mma;
+    int64_t ldw = 0;
+    DevBuf<char> wh;                           // 2 x 16 x ldw halves
+    DevBuf<float> wsc;                         // L x 16
     DevBuf<int32_t> d_rank, d_ncand;
     DevBuf<int64_t> d_skoff, d_poff, d_far_block_off;
     DevBuf<int32_t> d_far_cols;
