@@ -166,10 +166,11 @@ def main():
     gold = os.path.join(ROOT, "tests", "golden", f"eigs_{args.workload}.json")
     if os.path.exists(gold):
         g = json.load(open(gold))
-        dense = np.array(g["dense_eigenvalues"][:r])
         hm = np.array(g["hmatrix_eigenvalues"][:r])
-        ev_acc = {"max_rel_err_vs_dense_f64": float(np.max(np.abs(ev - dense) / np.abs(dense))),
-                  "max_rel_err_vs_oracle_hmatrix_f64": float(np.max(np.abs(ev - hm) / np.abs(hm)))}
+        ev_acc = {"max_rel_err_vs_oracle_hmatrix_f64": float(np.max(np.abs(ev - hm) / np.abs(hm)))}
+        if g["dense_eigenvalues"] is not None:   # not computed for the largest workloads
+            dense = np.array(g["dense_eigenvalues"][:r])
+            ev_acc["max_rel_err_vs_dense_f64"] = float(np.max(np.abs(ev - dense) / np.abs(dense)))
     if args.copy_probe:
         a = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
         b = torch.empty_like(a)

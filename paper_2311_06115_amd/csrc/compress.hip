@@ -1028,6 +1028,10 @@ static void build_tree(Op& op, int mode, int it, DevBuf<int32_t>& perm, DevBuf<i
         check_launch("tree level");
         std::swap(perm, tmp);
     }
+    // the sample buffers are freed on return while the last level's kernels may
+    // still be queued on s: wait for them first (hipFree's implicit
+    // synchronisation is not relied on, e.g. for non-blocking streams)
+    if (sample_ids.n || kvals.n) HDM_HIP(hipStreamSynchronize(s));
 }
 
 // near lists: self plus ceil(budget * L) other leaves by (votes desc, id asc), symmetrised

@@ -97,3 +97,35 @@ def test_rejections_and_cancellation():
     assert e.value.status == 2
     assert tiny.stats()["rejected"] == 1
     tiny.close()
+
+
+def _mnist_req(n, seed, near="bf16", far="f32"):
+    X, _ = synth.mnist_shaped(n, seed)
+    return dict(X=X, eps=synth.median_sq_dist_eps(X, seed), m=256, s=64, tau=1e-4, k=16, seed=seed,
+                near_prec=near, far_prec=far)
+
+
+def test_u8_requests_alone_equal_in_the_mix():
+    """u8 codes (matrix-core distance blocks), ragged leaves, compressed on the server's
+    worker threads and solved in shared launches: each result equals the one alone."""
+    hdm = _hdm()
+    reqs = [_mnist_req(3001, 201), _mnist_req(2048, 202), _mnist_req(4096, 203), _mnist_req(2500, 204)]
+    alone = []
+    for q in reqs:
+        op = hdm.Operator(q["X"], q["eps"], q["m"], q["s"], q["tau"], q["k"], q["seed"], near_prec=q["near_prec"],
+                          far_prec=q["far_prec"])
+        ev, _, info, st = op.eigs(6, tol=1e-8, seed=q["seed"], vectors=False)
+        op.close()
+        alone.append((ev, info.iters, st))
+    srv = hdm.Server(max_slots=4, compressors=2)
+    tickets = [srv.submit(q["X"], q["eps"], q["m"], q["s"], q["tau"], q["k"], q["seed"], 6, tol=1e-8,
+                          near_prec=q["near_prec"], far_prec=q["far_prec"]) for q in reqs]
+    res = [srv.wait(t) for t in tickets]
+    st = srv.stats()
+    srv.close()
+    print(f"[gpu] u8 serving stats {st}")
+    for (ev, iters, s0), r in zip(alone, res):
+        assert r["status"] == s0 == 0
+        assert r["iters"] == iters
+        assert np.array_equal(r["evals"], ev), (r["evals"], ev)
+    assert st["completed"] == len(reqs)
