@@ -1006,9 +1006,12 @@ void apply(Op& op, int normalised, bool exact64, const double* x, double* y, int
     }
     const bool f64 = exact64 || op.prm.near_prec == HDM_F64;
     HDM_CHECK(!f64 || op.near64.n > 0 || op.near_elems == 0, HDM_EINTERNAL, "float64 tiles are not resident");
+    // the float64 products of the degree pass belong to building the operator:
+    // they are not recorded as evaluation phases
+    Ctx* cx = exact64 ? nullptr : op.ctx;
     for (int c0 = 0; c0 < nrhs; c0 += per) {
         const ApplyReq r{&op, x + static_cast<int64_t>(c0) * op.n, y + static_cast<int64_t>(c0) * op.n};
-        apply_dispatch(&r, 1, f64, normalised, std::min(per, nrhs - c0), s, op.lane, op.ctx);
+        apply_dispatch(&r, 1, f64, normalised, std::min(per, nrhs - c0), s, op.lane, cx);
     }
 }
 
