@@ -98,9 +98,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true", help="also run one plain 1 GiB device copy (counter scale)")
     ap.add_argument("--serve-seconds", type=float, default=0.0,
-                    help="length of the serving stream (0: skip; off by default, see the notes on the serving leg)")
+                    help="length of the serving stream (disabled in this build: any value > 0 exits)")
     ap.add_argument("--serve-pool", type=int, default=8, help="distinct request instances the stream cycles through")
     args = ap.parse_args()
+    if args.serve_seconds > 0:
+        # two runs of this leg ended with a GPU memory fault whose cause is not yet found
+        print("the serving leg is disabled in this build (a GPU fault under investigation); "
+              "tests/test_gpu_serving.py covers the serving loop", file=sys.stderr)
+        sys.exit(2)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path",
               file=sys.stderr)
