@@ -174,9 +174,10 @@ __device__ inline int64_t node_of(int64_t pos, int lvl, const int64_t* start) {
 // ---------------------------------------------------------------------------
 // tree construction
 // ---------------------------------------------------------------------------
+// identity permutation, one copy of n entries per tree (blockIdx.y)
 __global__ void k_iota(int32_t* p, int64_t n) {
     const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-    if (i < n) p[i] = static_cast<int32_t>(i);
+    if (i < n) p[blockIdx.y * n + i] = static_cast<int32_t>(i);
 }
 
 // Floyd's sampling of min(n, 64) distinct positions of each node, ascending.
@@ -277,11 +278,16 @@ __global__ void k_tree_pq(int lvl, const int64_t* start, const int64_t* size, co
 }
 
 // random pivots p != q of each node of a neighbour-search tree
-__global__ void k_knn_pq(int lvl, const int64_t* start, const int64_t* size, const int32_t* perm, uint64_t seed,
-                         int it, int32_t* pq) {
+// random pivots of the neighbour trees; tree it + blockIdx.y uses its own
+// permutation (stride n) and pivot slots (stride pq_stride)
+__global__ void k_knn_pq(int lvl, const int64_t* start, const int64_t* size, const int32_t* perm_all, int64_t n_all,
+                         uint64_t seed, int it0, int32_t* pq_all, int64_t pq_stride) {
     const int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
     const int64_t nodes = int64_t(1) << lvl;
     if (t >= nodes) return;
+    const int it = it0 + static_cast<int>(blockIdx.y);
+    const int32_t* perm = perm_all + blockIdx.y * n_all;
+    int32_t* pq = pq_all + blockIdx.y * pq_stride;
     const int64_t h = nodes + t;
     const uint32_t n = static_cast<uint32_t>(size[h]);
     const uint32_t a = below(philox_draw(seed, kKnnPivot, static_cast<uint32_t>(h), static_cast<uint32_t>(it), 0), n);
@@ -292,10 +298,13 @@ __global__ void k_knn_pq(int lvl, const int64_t* start, const int64_t* size, con
 }
 
 // split key: mode 0 (ball tree) K(x,q) - K(x,p); mode 1 (neighbour trees) |x-p|^2 - |x-q|^2
-__global__ void k_tree_key(int lvl, int64_t n, const int64_t* start, const int32_t* perm, const int32_t* pq, Pts P,
-                           int mode, double* key) {
+__global__ void k_tree_key(int lvl, int64_t n, const int64_t* start, const int32_t* perm_all, const int32_t* pq_all,
+                           int64_t pq_stride, Pts P, int mode, double* key_all) {
     const int64_t pos = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
     if (pos >= n) return;
+    const int32_t* perm = perm_all + blockIdx.y * n;     // tree blockIdx.y
+    const int32_t* pq = pq_all + blockIdx.y * pq_stride;
+    double* key = key_all + blockIdx.y * n;
     const int64_t t = node_of(pos, lvl, start) - (int64_t(1) << lvl);
     const int32_t i = perm[pos], p = pq[2 * t], q = pq[2 * t + 1];
     key[pos] = mode == 0 ? kval(P, i, q) - kval(P, i, p) : sqd(P, i, p) - sqd(P, i, q);
@@ -356,7 +365,12 @@ __device__ inline uint64_t orderable(double x) {
 // the node is partitioned stably: both halves keep ascending original index.
 constexpr int kSplitBlock = 1024;
 __global__ void __launch_bounds__(kSplitBlock) k_tree_split(int lvl, const int64_t* start, const int64_t* size,
-                                                            const int32_t* perm, const double* key, int32_t* out) {
+                                                            const int32_t* perm_all, const double* key_all,
+                                                            int32_t* out_all, int64_t tstride) {
+    // tree blockIdx.y: its permutation, keys and output at offset blockIdx.y * tstride
+    const int32_t* perm = perm_all + blockIdx.y * tstride;
+    const double* key = key_all + blockIdx.y * tstride;
+    int32_t* out = out_all + blockIdx.y * tstride;
     __shared__ int hist[256];
     __shared__ int wsum[kSplitBlock / 64];
     __shared__ uint64_t s_prefix;
@@ -978,9 +992,18 @@ static void tree_ranges(int64_t n, int depth, std::vector<int64_t>& start, std::
 }
 
 // one perfect tree of the given depth: ball tree (mode 0) or random-pivot tree (mode 1)
-static void build_tree(Op& op, int mode, int it, DevBuf<int32_t>& perm, DevBuf<int32_t>& tmp, const Geo& G,
-                       hipStream_t s, DevBuf<int32_t>& samp, DevBuf<int32_t>& nsamp, DevBuf<int32_t>& pq,
-                       DevBuf<double>& sumk, DevBuf<double>& key) {
+// mode 0: the ball tree (ntrees = 1); mode 1: ntrees neighbour trees at once
+// (trees it0 .. it0 + ntrees - 1, each level of all of them in one launch);
+// perm, tmp and key hold ntrees x n entries, pq ntrees x 2L.
+static void build_tree(Op& op, int mode, int it0, int ntrees, DevBuf<int32_t>& perm, DevBuf<int32_t>& tmp,
+                       const Geo& G, hipStream_t s, DevBuf<int32_t>& samp, DevBuf<int32_t>& nsamp,
+                       DevBuf<int32_t>& pq, DevBuf<double>& sumk, DevBuf<double>& key) {
+    HDM_CHECK(mode == 1 || ntrees == 1, HDM_EINTERNAL, "one ball tree at a time");
+    HDM_CHECK(perm.n >= static_cast<size_t>(ntrees) * op.n && tmp.n >= static_cast<size_t>(ntrees) * op.n &&
+                  key.n >= static_cast<size_t>(ntrees) * op.n &&
+                  pq.n >= static_cast<size_t>(ntrees) * 2 * op.L,
+              HDM_EINTERNAL, "tree buffers too small");
+    const int64_t pq_stride = 2 * static_cast<int64_t>(op.L);
     const Pts& P = G.P;
     const int64_t n = op.n;
     DevBuf<int32_t> sample_ids;
@@ -990,7 +1013,7 @@ static void build_tree(Op& op, int mode, int it, DevBuf<int32_t>& perm, DevBuf<i
         kvals.alloc(static_cast<size_t>(n) * kSample);
     }
     const int gN = ceil_div(n, kBlock);
-    hipLaunchKernelGGL(k_iota, dim3(gN), dim3(kBlock), 0, s, perm.get(), n);
+    hipLaunchKernelGGL(k_iota, dim3(gN, ntrees), dim3(kBlock), 0, s, perm.get(), n);
     for (int lvl = 0; lvl < op.depth; ++lvl) {
         const int nodes = 1 << lvl;
         if (mode == 0) {
@@ -1018,13 +1041,13 @@ static void build_tree(Op& op, int mode, int it, DevBuf<int32_t>& perm, DevBuf<i
             hipLaunchKernelGGL(k_tree_pq, dim3(nodes), dim3(kBlock), 0, s, lvl, op.d_start.get(), op.d_size.get(),
                                perm.get(), sumk.get(), P, pq.get());
         } else {
-            hipLaunchKernelGGL(k_knn_pq, dim3(ceil_div(nodes, 64)), dim3(64), 0, s, lvl, op.d_start.get(),
-                               op.d_size.get(), perm.get(), op.prm.seed, it, pq.get());
+            hipLaunchKernelGGL(k_knn_pq, dim3(ceil_div(nodes, 64), ntrees), dim3(64), 0, s, lvl, op.d_start.get(),
+                               op.d_size.get(), perm.get(), n, op.prm.seed, it0, pq.get(), pq_stride);
         }
-        hipLaunchKernelGGL(k_tree_key, dim3(gN), dim3(kBlock), 0, s, lvl, n, op.d_start.get(), perm.get(), pq.get(),
-                           P, mode, key.get());
-        hipLaunchKernelGGL(k_tree_split, dim3(nodes), dim3(kSplitBlock), 0, s, lvl, op.d_start.get(), op.d_size.get(),
-                           perm.get(), key.get(), tmp.get());
+        hipLaunchKernelGGL(k_tree_key, dim3(gN, ntrees), dim3(kBlock), 0, s, lvl, n, op.d_start.get(), perm.get(),
+                           pq.get(), pq_stride, P, mode, key.get());
+        hipLaunchKernelGGL(k_tree_split, dim3(nodes, ntrees), dim3(kSplitBlock), 0, s, lvl, op.d_start.get(),
+                           op.d_size.get(), perm.get(), key.get(), tmp.get(), n);
         check_launch("tree level");
         std::swap(perm, tmp);
     }
@@ -1392,7 +1415,7 @@ void compress_operator(Op& op, const void* X, int x_on_device, hipStream_t s) {
     const int64_t n = op.n;
     DevBuf<int32_t> perm(n), tmp(n), samp(static_cast<size_t>(op.L) * kSample), nsamp(op.L), pq(2 * op.L);
     DevBuf<double> sumk(n), key(n);
-    build_tree(op, 0, 0, perm, tmp, G, s, samp, nsamp, pq, sumk, key);
+    build_tree(op, 0, 0, 1, perm, tmp, G, s, samp, nsamp, pq, sumk, key);
     op.perm = std::move(perm);
     op.iperm.alloc(n);
     hipLaunchKernelGGL(k_inverse_perm, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, s, op.perm.get(), op.iperm.get(), n);
@@ -1402,7 +1425,12 @@ void compress_operator(Op& op, const void* X, int x_on_device, hipStream_t s) {
     op.knn_d2.alloc(static_cast<size_t>(n) * k);
     hipLaunchKernelGGL(k_knn_init, dim3(ceil_div(n * k, kBlock)), dim3(kBlock), 0, s, op.knn_idx.get(), op.knn_d2.get(),
                        n * k);
-    DevBuf<int32_t> kperm(n);
+    // all neighbour trees are built together (every level of every tree in one launch)
+    const int T = p.knn_iters;
+    DevBuf<int32_t> kperm(static_cast<size_t>(T) * n), ktmp(static_cast<size_t>(T) * n),
+        kpq(static_cast<size_t>(T) * 2 * op.L);
+    DevBuf<double> kkey(static_cast<size_t>(T) * n);
+    if (T > 0) build_tree(op, 1, 0, T, kperm, ktmp, G, s, samp, nsamp, kpq, sumk, kkey);
     int64_t leafmax = 0;
     for (int64_t h = op.L; h < 2 * int64_t(op.L); ++h) leafmax = std::max(leafmax, op.size[h]);
     const int stage = (!P.is_u8 && P.dim <= kLeafStageDim && leafmax * P.dim * 8 <= 48 * 1024) ? 1 : 0;
@@ -1411,18 +1439,18 @@ void compress_operator(Op& op, const void* X, int x_on_device, hipStream_t s) {
     const size_t shm = stage ? sizeof(double) * leafmax * P.dim : 0;
     // enough workgroups to cover the device: split each leaf's points over several
     const int splits = std::max(1, std::min(static_cast<int>((leafmax + 15) / 16), 2048 / op.L));
-    for (int it = 0; it < p.knn_iters; ++it) {
-        build_tree(op, 1, it, kperm, tmp, G, s, samp, nsamp, pq, sumk, key);
+    for (int it = 0; it < T; ++it) {
+        const int32_t* tperm = kperm.get() + static_cast<int64_t>(it) * n;   // tree it's permutation
         if (G.gram) {
             std::vector<GramBlock> blocks;
             for (int64_t h = op.L; h < 2 * int64_t(op.L); ++h)
-                blocks.push_back(GramBlock{kperm.get() + op.start[h], kperm.get() + op.start[h],
+                blocks.push_back(GramBlock{tperm + op.start[h], tperm + op.start[h],
                                            static_cast<int32_t>(op.size[h]), static_cast<int32_t>(op.size[h]),
                                            (h - op.L) * leafmax * leafmax, static_cast<int32_t>(leafmax), 0});
             gram_launch(G, blocks, 0, leafd2, s);
         }
         hipLaunchKernelGGL(k_knn_leaf, dim3(op.L * splits), dim3(kKnnBlock), shm, s, op.depth, op.d_start.get(),
-                           op.d_size.get(), kperm.get(), P, k, stage, splits, G.gram ? leafd2.get() : nullptr,
+                           op.d_size.get(), tperm, P, k, stage, splits, G.gram ? leafd2.get() : nullptr,
                            static_cast<int>(leafmax), op.knn_idx.get(), op.knn_d2.get());
         check_launch("knn leaf");
     }
