@@ -20,6 +20,7 @@ namespace hdm {
 namespace {
 
 constexpr int kSample = 64;     // points sampled per node for the centroid
+constexpr int kMaxCand = 2048;  // candidates of one node (leaf points or children's skeletons)
 constexpr int kBlock = 256;
 
 struct Pts {
@@ -630,10 +631,12 @@ __global__ void k_row_count(LevelArgs A) {
 // the rest: uniform draws from outside the node (or every outside point when
 // that is all there is).  The draws are taken 64 at a time by one wave and
 // accepted in draw order, exactly as a sequential rejection loop would.
-constexpr int kRowStage = 8192;
+constexpr int kMaxRows = 1024;   // sampled rows per node (2 max_rank_s)
 __global__ void k_row_select(LevelArgs A) {
     __shared__ int wsum[kBlock / 64];
-    __shared__ int32_t cnt_s[kRowStage];
+    __shared__ int32_t hist[kMaxCand + 1];   // votes are at most the number of candidates
+    __shared__ int32_t selv[kMaxRows / 2], selc[kMaxRows / 2];
+    __shared__ int32_t s_t, s_need;
     __shared__ int32_t batch[64];
     const int64_t t = blockIdx.x;
     const int64_t h = (int64_t(1) << A.lvl) + t;
@@ -645,33 +648,74 @@ __global__ void k_row_select(LevelArgs A) {
     int64_t want = A.n - A.size[h];
     if (want > 2 * static_cast<int64_t>(A.s)) want = 2 * static_cast<int64_t>(A.s);
     const int64_t want_nb = want / 2;
-    // compaction of {i : cnt[i] > 0} in index order
+    // compaction of {i : cnt[i] > 0} in index order: a contiguous range per
+    // thread, one workgroup scan of the per-thread counts
     int64_t nu = 0;
-    for (int64_t base = 0; base < A.n; base += blockDim.x) {
-        const int64_t i = base + threadIdx.x;
-        const bool f = i < A.n && cnt[i] > 0;
+    {
+        const int64_t per = (A.n + kBlock - 1) / kBlock;
+        const int64_t i0 = min(A.n, static_cast<int64_t>(threadIdx.x) * per), i1 = min(A.n, i0 + per);
+        int mine = 0;
+        for (int64_t i = i0; i < i1; ++i) mine += cnt[i] > 0;
         int tot = 0;
-        const int pre = wg_flag_scan(f, wsum, &tot);
-        if (f) uq[nu + pre] = static_cast<int32_t>(i);
-        nu += tot;
+        int w = wg_scan_excl(mine, wsum, &tot);
+        for (int64_t i = i0; i < i1; ++i)
+            if (cnt[i] > 0) uq[w++] = static_cast<int32_t>(i);
+        nu = tot;
     }
-    // rank by (votes desc, index asc); keep the first want_nb
-    const bool staged = nu <= kRowStage;
-    if (staged)
-        for (int64_t u = threadIdx.x; u < nu; u += blockDim.x) cnt_s[u] = cnt[uq[u]];
+    for (int c = threadIdx.x; c <= kMaxCand; c += blockDim.x) hist[c] = 0;
     __syncthreads();
-    for (int64_t u = threadIdx.x; u < nu; u += blockDim.x) {
-        const int32_t iu = uq[u];
-        const int32_t cu = cnt[iu];
+    // rank by (votes desc, index asc) and keep the first want_nb: the vote
+    // threshold from a histogram, the ties at it in index order, then the
+    // (at most want_nb) kept entries ordered among themselves
+    for (int64_t u = threadIdx.x; u < nu; u += blockDim.x) atomicAdd(&hist[min(cnt[uq[u]], kMaxCand)], 1);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t above = 0;   // entries with more votes than c
+        int tc = 0, need = 0;
+        if (nu > want_nb) {
+            for (int c = kMaxCand; c >= 1; --c) {
+                if (above + hist[c] >= want_nb) { tc = c; need = static_cast<int>(want_nb - above); break; }
+                above += hist[c];
+            }
+        }
+        s_t = tc;        // 0: every entry is kept
+        s_need = need;
+    }
+    __syncthreads();
+    const int tcut = s_t, need = s_need;
+    int64_t m = 0;   // kept entries, collected in index order
+    {
+        const int64_t per = (nu + kBlock - 1) / kBlock;
+        const int64_t u0 = min(nu, static_cast<int64_t>(threadIdx.x) * per), u1 = min(nu, u0 + per);
+        int ties = 0;
+        for (int64_t u = u0; u < u1; ++u) ties += cnt[uq[u]] == tcut;
+        int tt = 0;
+        int tie_rank = wg_scan_excl(ties, wsum, &tt);
+        int keep = 0;
+        for (int64_t u = u0; u < u1; ++u) {
+            const int32_t c = cnt[uq[u]];
+            keep += c > tcut || (c == tcut && tie_rank++ < need);
+        }
+        int tk = 0;
+        int w = wg_scan_excl(keep, wsum, &tk);
+        tie_rank -= ties;   // back to this thread's first tie rank
+        for (int64_t u = u0; u < u1; ++u) {
+            const int32_t c = cnt[uq[u]];
+            if (c > tcut || (c == tcut && tie_rank++ < need)) {
+                selv[w] = uq[u];
+                selc[w] = c;
+                ++w;
+            }
+        }
+        m = tk;
+    }
+    __syncthreads();
+    for (int64_t e = threadIdx.x; e < m; e += blockDim.x) {
+        const int32_t iu = selv[e], cu = selc[e];
         int64_t r = 0;
-        for (int64_t v = 0; v < nu; ++v) {
-            const int32_t cv = staged ? cnt_s[v] : cnt[uq[v]];
-            r += (cv > cu) || (cv == cu && v < u);
-        }
-        if (r < want_nb) {
-            rows[r] = iu;
-            atomicOr(&bits[iu >> 5], 1u << (iu & 31));
-        }
+        for (int64_t v = 0; v < m; ++v) r += (selc[v] > cu) || (selc[v] == cu && v < e);
+        rows[r] = iu;
+        atomicOr(&bits[iu >> 5], 1u << (iu & 31));
     }
     __syncthreads();
     int64_t nr = nu < want_nb ? nu : want_nb;
@@ -758,7 +802,6 @@ __device__ inline double col_sumsq(const double* B, int nc, int c, int i0, int i
 // thread per column; every column norm and dot product is a sequential sum
 // over rows.  The squared norms that choose the next pivot are accumulated
 // while the reflector is applied (same values, same order as a separate pass).
-constexpr int kMaxCand = 2048;
 __global__ void __launch_bounds__(kBlock) k_pivoted_id(LevelArgs A) {
     __shared__ double sv[kBlock];
     __shared__ int64_t sp[kBlock];
