@@ -1203,7 +1203,8 @@ static void skeletonize(Op& op, const Geo& G, hipStream_t s) {
     std::vector<DevBuf<double>> Plevel(op.depth + 1);
     std::vector<int64_t> Plevel_base(op.depth + 1, 0);
     DevBuf<int32_t> d_rank(op.nnodes);
-    DevBuf<int64_t> d_skoff(op.nnodes), d_poff(op.nnodes), d_rowoff(op.nnodes);
+    DevBuf<int64_t> d_skoff(op.nnodes), d_poff(op.nnodes), d_rowoff(op.nnodes), d_plocal(op.nnodes);
+    std::vector<int64_t> poff_local(op.nnodes, 0);
     HDM_HIP(hipMemsetAsync(d_rank.get(), 0, d_rank.bytes(), s));
     int64_t sk_next = 0, row_next = 0, p_next = 0;
     std::vector<int32_t> h_rk(maxnodes), h_nc(maxnodes), h_nr(maxnodes), h_st(maxnodes);
@@ -1282,12 +1283,11 @@ static void skeletonize(Op& op, const Geo& G, hipStream_t s) {
         Plevel[lvl].alloc(plev > 0 ? plev : 1);
         Plevel_base[lvl] = p_next;
         // level-local P offsets for the compaction kernel
-        std::vector<int64_t> poff_local(op.nnodes, 0);
         for (int t = 0; t < nodes; ++t) poff_local[nodes + t] = op.poff[nodes + t] - p_next;
         p_next += plev;
         d_rank.upload(op.rank.data(), op.nnodes, s);
         d_skoff.upload(op.skoff.data(), op.nnodes, s);
-        DevBuf<int64_t> d_plocal = to_device(poff_local, s);
+        d_plocal.upload(poff_local.data(), op.nnodes, s);
         d_rowoff.upload(op.rowoff.data(), op.nnodes, s);
         hipLaunchKernelGGL(k_compact, dim3(nodes), dim3(kBlock), 0, s, A, d_skoff.get(), d_plocal.get(), d_rowoff.get(),
                            skel_buf.get(), Plevel[lvl].get(), rows_buf.get());
@@ -1311,7 +1311,9 @@ static void skeletonize(Op& op, const Geo& G, hipStream_t s) {
     HDM_HIP(hipStreamSynchronize(s));
 }
 
-static void build_tiles(Op& op, const Geo& G, hipStream_t s) {
+// near tiles; with float64 points the launch is left in flight on s (the pair
+// descriptors stay alive in `pairs_dev` until the caller has waited for s)
+static void build_near_tiles(Op& op, const Geo& G, hipStream_t s, DevBuf<NearPair>& pairs_dev) {
     const Pts& P = G.P;
     const int64_t L = op.L;
     // near blocks: per leaf, column-major ld x (sum of near leaf sizes), ld = rows rounded up to 8
@@ -1342,17 +1344,23 @@ static void build_tiles(Op& op, const Geo& G, hipStream_t s) {
             blocks.push_back(GramBlock{op.perm.get() + pr.a0, op.perm.get() + pr.b0, pr.na, pr.nb, pr.off, pr.ld, 1});
         gram_launch(G, blocks, 1, op.near64, s);
     } else {
-        DevBuf<NearPair> dp = to_device(pairs, s);
+        pairs_dev.alloc(pairs.size());
+        pairs_dev.upload(pairs.data(), pairs.size(), s);
+        HDM_HIP(hipStreamSynchronize(s));   // the host copy of the pairs goes out of scope
         int64_t maxe = 0;
         for (auto& p : pairs) maxe = std::max<int64_t>(maxe, static_cast<int64_t>(p.ld) * p.nb);
         for (size_t base = 0; base < pairs.size(); base += 65535) {
             const int cnt = static_cast<int>(std::min<size_t>(65535, pairs.size() - base));
-            hipLaunchKernelGGL(k_near_tiles, dim3(ceil_div(maxe, kBlock), cnt), dim3(kBlock), 0, s, dp.get() + base,
-                               op.perm.get(), P, op.near64.get());
+            hipLaunchKernelGGL(k_near_tiles, dim3(ceil_div(maxe, kBlock), cnt), dim3(kBlock), 0, s,
+                               pairs_dev.get() + base, op.perm.get(), P, op.near64.get());
         }
         check_launch("near tiles");
-        HDM_HIP(hipStreamSynchronize(s));
     }
+}
+
+// far tiles (after skeletonisation); synchronises s
+static void build_far_tiles(Op& op, const Geo& G, hipStream_t s) {
+    const Pts& P = G.P;
     // far blocks: per node, row-major rank x (sum of far ranks)
     op.far_block_off.assign(op.nnodes, 0);
     op.far_cols.assign(op.nnodes, 0);
@@ -1454,14 +1462,20 @@ void compress_operator(Op& op, const void* X, int x_on_device, hipStream_t s) {
         HDM_HIP(hipStreamSynchronize(s));
         HDM_CHECK(hb == 0, HDM_EINVAL, "points contain NaN or Inf");
     }
-    // trees
+    // trees: the ball tree on the side stream while the neighbour trees run on s
     const int64_t n = op.n;
+    op.lane.init();
+    hipStream_t side = op.lane.side;
+    HDM_HIP(hipEventRecord(op.lane.fork, s));
+    HDM_HIP(hipStreamWaitEvent(side, op.lane.fork, 0));
     DevBuf<int32_t> perm(n), tmp(n), samp(static_cast<size_t>(op.L) * kSample), nsamp(op.L), pq(2 * op.L);
     DevBuf<double> sumk(n), key(n);
-    build_tree(op, 0, 0, 1, perm, tmp, G, s, samp, nsamp, pq, sumk, key);
-    op.perm = std::move(perm);
     op.iperm.alloc(n);
-    hipLaunchKernelGGL(k_inverse_perm, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, s, op.perm.get(), op.iperm.get(), n);
+    build_tree(op, 0, 0, 1, perm, tmp, G, side, samp, nsamp, pq, sumk, key);
+    op.perm = std::move(perm);
+    hipLaunchKernelGGL(k_inverse_perm, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, side, op.perm.get(),
+                       op.iperm.get(), n);
+    HDM_HIP(hipEventRecord(op.lane.join, side));
     // neighbours: random-pivot trees, all pairs inside leaves
     const int k = p.knn_k;
     op.knn_idx.alloc(static_cast<size_t>(n) * k);
@@ -1497,6 +1511,7 @@ void compress_operator(Op& op, const void* X, int x_on_device, hipStream_t s) {
                            static_cast<int>(leafmax), op.knn_idx.get(), op.knn_d2.get());
         check_launch("knn leaf");
     }
+    HDM_HIP(hipStreamWaitEvent(s, op.lane.join, 0));   // the ball tree and its inverse permutation
     // lists
     {
         DevBuf<int32_t> votes(static_cast<size_t>(op.L) * op.L);
@@ -1510,8 +1525,16 @@ void compress_operator(Op& op, const void* X, int x_on_device, hipStream_t s) {
         build_near_lists(op, hv);
         build_far_lists(op);
     }
+    // near tiles on the side stream while the skeletons are computed on s
+    DevBuf<NearPair> pairs_dev;
+    HDM_HIP(hipEventRecord(op.lane.fork, s));
+    HDM_HIP(hipStreamWaitEvent(side, op.lane.fork, 0));
+    build_near_tiles(op, G, side, pairs_dev);
+    HDM_HIP(hipEventRecord(op.lane.join, side));
     skeletonize(op, G, s);
-    build_tiles(op, G, s);
+    HDM_HIP(hipStreamWaitEvent(s, op.lane.join, 0));
+    build_far_tiles(op, G, s);
+    HDM_HIP(hipStreamSynchronize(side));
     op.seconds_compress = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
 
