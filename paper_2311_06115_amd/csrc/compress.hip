@@ -655,11 +655,23 @@ __global__ void k_row_select(LevelArgs A) {
         const int64_t per = (A.n + kBlock - 1) / kBlock;
         const int64_t i0 = min(A.n, static_cast<int64_t>(threadIdx.x) * per), i1 = min(A.n, i0 + per);
         int mine = 0;
-        for (int64_t i = i0; i < i1; ++i) mine += cnt[i] > 0;
+        for (int64_t i = i0; i < i1; i += 16) {   // 16 loads in flight
+            int32_t v[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) v[u] = cnt[min(i + u, i1 - 1)];   // clamped: unguarded loads
+#pragma unroll
+            for (int u = 0; u < 16; ++u) mine += (i + u < i1) && v[u] > 0;
+        }
         int tot = 0;
         int w = wg_scan_excl(mine, wsum, &tot);
-        for (int64_t i = i0; i < i1; ++i)
-            if (cnt[i] > 0) uq[w++] = static_cast<int32_t>(i);
+        for (int64_t i = i0; i < i1; i += 16) {
+            int32_t v[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) v[u] = cnt[min(i + u, i1 - 1)];
+#pragma unroll
+            for (int u = 0; u < 16; ++u)
+                if (i + u < i1 && v[u] > 0) uq[w++] = static_cast<int32_t>(i + u);
+        }
         nu = tot;
     }
     for (int c = threadIdx.x; c <= kMaxCand; c += blockDim.x) hist[c] = 0;
@@ -688,7 +700,15 @@ __global__ void k_row_select(LevelArgs A) {
         const int64_t per = (nu + kBlock - 1) / kBlock;
         const int64_t u0 = min(nu, static_cast<int64_t>(threadIdx.x) * per), u1 = min(nu, u0 + per);
         int ties = 0;
-        for (int64_t u = u0; u < u1; ++u) ties += cnt[uq[u]] == tcut;
+        for (int64_t u = u0; u < u1; u += 16) {   // batched loads (clamped addresses)
+            int32_t v[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) v[q] = uq[min(u + q, u1 - 1)];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) v[q] = cnt[v[q]];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) ties += (u + q < u1) && v[q] == tcut;
+        }
         int tt = 0;
         int tie_rank = wg_scan_excl(ties, wsum, &tt);
         int keep = 0;
