@@ -1550,6 +1550,7 @@ void compress_operator(Op& op, const void* X, int x_on_device, hipStream_t s) {
     HDM_HIP(hipEventRecord(op.lane.fork, s));
     HDM_HIP(hipStreamWaitEvent(side, op.lane.fork, 0));
     build_near_tiles(op, G, side, pairs_dev);
+    convert_near_tiles(op, side);   // evaluation-precision copy, also on the side stream
     HDM_HIP(hipEventRecord(op.lane.join, side));
     skeletonize(op, G, s);
     HDM_HIP(hipStreamWaitEvent(s, op.lane.join, 0));

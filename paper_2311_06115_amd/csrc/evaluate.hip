@@ -720,6 +720,8 @@ static void publish_descriptors(Op& op, hipStream_t s) {
     HDM_HIP(hipStreamSynchronize(s));
 }
 
+static void packed_near_offsets(Op& op);
+
 // Plan of the packed half-precision near field (k_l2l_mma): per near pair an
 // ld_a x kc_b packed tile; per (pair, group of at most 8 row tiles) one item;
 // per leaf one partial-sum slot of ld_a rows per near pair.  Vectors are staged
@@ -733,7 +735,7 @@ static void build_mma_plan(Op& op, hipStream_t s) {
         wpad[b] = op.ldw;
         op.ldw += (op.size[L + b] + 7) / 8 * 8;
     }
-    op.near_tile_off_mma.assign(op.near_idx.size(), 0);
+    packed_near_offsets(op);
     op.items_mma.clear();
     op.leaves_mma.clear();
     int64_t off = 0, part = 0;
@@ -1039,12 +1041,44 @@ void normalise_degrees(Op& op, hipStream_t s) {
     publish_descriptors(op, s);   // the descriptors now carry c
 }
 
+// Upload of host index arrays for a conversion: kept in `keep` (host copy and
+// device buffer) when the caller does not wait for s, else temporaries.
+struct Staging {
+    Op::ConvKeep* keep;
+    hipStream_t s;
+    std::vector<DevBuf<int64_t>> t64;
+    std::vector<DevBuf<int32_t>> t32;
+    const int64_t* up(const std::vector<int64_t>& v) {
+        if (keep) {
+            keep->h64.push_back(v);
+            keep->d64.push_back(to_device(keep->h64.back(), s));
+            return keep->d64.back().get();
+        }
+        t64.push_back(to_device(v, s));
+        return t64.back().get();
+    }
+    const int32_t* up(const std::vector<int32_t>& v) {
+        if (keep) {
+            keep->h32.push_back(v);
+            keep->d32.push_back(to_device(keep->h32.back(), s));
+            return keep->d32.back().get();
+        }
+        t32.push_back(to_device(v, s));
+        return t32.back().get();
+    }
+};
+
 template <typename T>
 static void convert_tiles(const DevBuf<double>& src, const std::vector<int64_t>& off, const std::vector<int64_t>& cnt,
-                          bool scaled, DevBuf<char>& dst, DevBuf<float>& scale, int64_t elems, hipStream_t s) {
+                          bool scaled, DevBuf<char>& dst, DevBuf<float>& scale, int64_t elems, hipStream_t s,
+                          Op::ConvKeep* keep = nullptr) {
     dst.alloc(static_cast<size_t>(std::max<int64_t>(elems, 1)) * sizeof(T));
     if (off.empty()) return;
-    DevBuf<int64_t> doff = to_device(off, s), dcnt = to_device(cnt, s);
+    Staging st{keep, s, {}, {}};
+    st.t64.reserve(2);
+    const int64_t* doff_p = st.up(off);
+    const int64_t* dcnt_p = st.up(cnt);
+    struct { const int64_t* p; const int64_t* get() const { return p; } } doff{doff_p}, dcnt{dcnt_p};
     float* sp = nullptr;
     if (scaled) {
         scale.alloc(off.size());
@@ -1058,11 +1092,12 @@ static void convert_tiles(const DevBuf<double>& src, const std::vector<int64_t>&
                            dcnt.get() + base, sp ? sp + base : nullptr, reinterpret_cast<T*>(dst.get()));
     }
     check_launch("convert");
-    HDM_HIP(hipStreamSynchronize(s));
+    if (!keep) HDM_HIP(hipStreamSynchronize(s));
 }
 
 // float16 near tiles in the packed matrix-core layout, one scale per tile
-static void pack_near(Op& op, const std::vector<int64_t>& noff, const std::vector<int64_t>& ncnt, hipStream_t s) {
+static void pack_near(Op& op, const std::vector<int64_t>& noff, const std::vector<int64_t>& ncnt, hipStream_t s,
+                      Op::ConvKeep* keep = nullptr) {
     const int64_t L = op.L;
     const size_t nt = noff.size();
     op.nearT.alloc(static_cast<size_t>(std::max<int64_t>(op.near_elems_mma, 1)) * sizeof(_Float16));
@@ -1081,8 +1116,13 @@ static void pack_near(Op& op, const std::vector<int64_t>& noff, const std::vecto
                           noff[t] + ncnt[t] <= op.near_elems && ncnt[t] == static_cast<int64_t>(ld[t]) * nb[t],
                       HDM_EINTERNAL, "packed near tile outside its buffer");
         }
-    DevBuf<int64_t> d_off = to_device(noff, s), d_cnt = to_device(ncnt, s), d_offp = to_device(offp, s);
-    DevBuf<int32_t> d_ld = to_device(ld, s), d_na = to_device(na, s), d_nb = to_device(nb, s);
+    Staging st{keep, s, {}, {}};
+    st.t64.reserve(3);
+    st.t32.reserve(3);
+    struct P64 { const int64_t* p; const int64_t* get() const { return p; } };
+    struct P32 { const int32_t* p; const int32_t* get() const { return p; } };
+    const P64 d_off{st.up(noff)}, d_cnt{st.up(ncnt)}, d_offp{st.up(offp)};
+    const P32 d_ld{st.up(ld)}, d_na{st.up(na)}, d_nb{st.up(nb)};
     op.near_scale.alloc(nt);
     hipLaunchKernelGGL(k_tile_max, dim3(nt), dim3(kBlock), 0, s, op.near64.get(), d_off.get(), d_cnt.get(),
                        op.near_scale.get());
@@ -1094,7 +1134,46 @@ static void pack_near(Op& op, const std::vector<int64_t>& noff, const std::vecto
                            op.near_scale.get() + base, reinterpret_cast<_Float16*>(op.nearT.get()));
     }
     check_launch("pack near tiles");
-    HDM_HIP(hipStreamSynchronize(s));
+    if (!keep) HDM_HIP(hipStreamSynchronize(s));
+}
+
+// offsets of the near tiles in the float64 layout (one entry per near pair)
+static void near_ranges(const Op& op, std::vector<int64_t>& noff, std::vector<int64_t>& ncnt) {
+    const int64_t L = op.L;
+    noff.clear();
+    ncnt.clear();
+    for (int64_t a = 0; a < L; ++a)
+        for (int32_t t = op.near_off[a]; t < op.near_off[a + 1]; ++t) {
+            noff.push_back(op.near_tile_off[t]);
+            ncnt.push_back(static_cast<int64_t>(op.near_ld[a]) * op.size[L + op.near_idx[t]]);
+        }
+}
+
+// offsets of the packed float16 near tiles (ld_a x |b| rounded up to 8 per pair)
+static void packed_near_offsets(Op& op) {
+    op.near_tile_off_mma.assign(op.near_idx.size(), 0);
+    int64_t off = 0;
+    for (int64_t a = 0; a < op.L; ++a)
+        for (int32_t t = op.near_off[a]; t < op.near_off[a + 1]; ++t) {
+            op.near_tile_off_mma[t] = off;
+            off += static_cast<int64_t>(op.near_ld[a]) * ((op.size[op.L + op.near_idx[t]] + 7) / 8 * 8);
+        }
+    op.near_elems_mma = off;
+}
+
+void convert_near_tiles(Op& op, hipStream_t s) {
+    if (op.prm.near_prec == HDM_F64 || op.near_converted) return;
+    op.conv_keep.reset(new Op::ConvKeep());
+    Op::ConvKeep* keep = op.conv_keep.get();
+    std::vector<int64_t> noff, ncnt;
+    near_ranges(op, noff, ncnt);
+    switch (op.prm.near_prec) {
+        case HDM_F32: convert_tiles<float>(op.near64, noff, ncnt, false, op.nearT, op.near_scale, op.near_elems, s, keep); break;
+        case HDM_BF16: convert_tiles<bf16_t>(op.near64, noff, ncnt, true, op.nearT, op.near_scale, op.near_elems, s, keep); break;
+        case HDM_F16: packed_near_offsets(op); pack_near(op, noff, ncnt, s, keep); break;
+        default: fail(HDM_EINVAL, "bad tile precision");
+    }
+    op.near_converted = true;
 }
 
 void convert_eval_precision(Op& op, hipStream_t s) {
@@ -1103,12 +1182,7 @@ void convert_eval_precision(Op& op, hipStream_t s) {
               "float64 tiles cannot be mixed with reduced-precision tiles");
     // near: one scale per tile (pair)
     std::vector<int64_t> noff, ncnt;
-    const int64_t L = op.L;
-    for (int64_t a = 0; a < L; ++a)
-        for (int32_t t = op.near_off[a]; t < op.near_off[a + 1]; ++t) {
-            noff.push_back(op.near_tile_off[t]);
-            ncnt.push_back(static_cast<int64_t>(op.near_ld[a]) * op.size[L + op.near_idx[t]]);
-        }
+    near_ranges(op, noff, ncnt);
     // far: one scale per node block (indexed by heap id)
     std::vector<int64_t> foff(op.nnodes, 0), fcnt(op.nnodes, 0);
     for (int64_t h = 0; h < op.nnodes; ++h) {
@@ -1124,10 +1198,13 @@ void convert_eval_precision(Op& op, hipStream_t s) {
             default: fail(HDM_EINVAL, "bad tile precision");
         }
     };
-    if (op.packed)
+    if (op.near_converted) {
+        // converted on another stream while the operator was built; that stream has been synchronised
+    } else if (op.packed) {
         pack_near(op, noff, ncnt, s);
-    else
+    } else {
         go(op.prm.near_prec, op.near64, noff, ncnt, op.nearT, op.near_scale, op.near_elems);
+    }
     go(op.prm.far_prec, op.far64, foff, fcnt, op.farT, op.far_scale, op.far_elems);
     op.P32.alloc(std::max<int64_t>(op.np, 1));
     if (op.np > 0)
@@ -1135,6 +1212,7 @@ void convert_eval_precision(Op& op, hipStream_t s) {
     check_launch("P to f32");
     HDM_HIP(hipStreamSynchronize(s));
     // the float64 tiles were only needed for the degrees
+    op.conv_keep.reset();
     op.near64.release();
     op.far64.release();
     publish_descriptors(op, s);

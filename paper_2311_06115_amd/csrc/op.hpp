@@ -212,6 +212,16 @@ struct Op {
     int64_t ldw = 0;
     DevBuf<char> wh;                           // 2 x 16 x ldw halves
     DevBuf<float> wsc;                         // L x 16
+    // near tiles converted to the evaluation precision early (while the skeletons
+    // are computed); the conversion's staging buffers live until it has completed
+    bool near_converted = false;
+    struct ConvKeep {
+        std::vector<DevBuf<int64_t>> d64;
+        std::vector<DevBuf<int32_t>> d32;
+        std::vector<std::vector<int64_t>> h64;
+        std::vector<std::vector<int32_t>> h32;
+    };
+    std::unique_ptr<ConvKeep> conv_keep;
     DevBuf<int32_t> d_rank, d_ncand;
     DevBuf<int64_t> d_skoff, d_poff, d_far_block_off;
     DevBuf<int32_t> d_far_cols;
@@ -280,6 +290,9 @@ void compress_operator(Op& op, const void* X, int x_on_device, hipStream_t s);
 void build_eval_plan(Op& op, hipStream_t s);
 void normalise_degrees(Op& op, hipStream_t s);
 void convert_eval_precision(Op& op, hipStream_t s);
+// starts the conversion of the float64 near tiles to the evaluation precision
+// on s without waiting (convert_eval_precision completes it after s is synchronised)
+void convert_near_tiles(Op& op, hipStream_t s);
 void apply(Op& op, int normalised, bool exact64, const double* x, double* y, int nrhs, hipStream_t s);
 // One launch per phase for every operator of the batch (same tile precisions,
 // at most kMaxBatch operators, one nrhs); each operator's result is the one a
