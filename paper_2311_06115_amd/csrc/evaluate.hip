@@ -900,8 +900,21 @@ static void apply_t(const ApplyReq* reqs, int nops, bool f64, int normalised, in
         tree = tree || reqs[o].op->nskel > 0;
         maxdepth = std::max(maxdepth, reqs[o].op->depth);
     }
+    // fork after the staging; the near field goes first on s (it only needs the
+    // staged vectors), so it starts while the host still issues the upward pass
+    if (tree) HDM_HIP(hipEventRecord(lane.fork, s));
+    {
+        const int64_t tot = prefix([](const Op& op, int) {
+            return static_cast<int64_t>(mma ? op.items_mma.size() : op.items.size());
+        });
+        KernelEvents ev(cx, HDM_PHASE_L2L);
+        if (mma)
+            hipExtLaunchKernelGGL(k_l2l_mma, dim3(ceil_div(tot, wpb)), dim3(kBlock), 0, s, ev.start, ev.stop, 0, b);
+        else
+            hipExtLaunchKernelGGL((k_l2l<V, TN>), dim3(ceil_div(tot, wpb)), dim3(kBlock), 0, s, ev.start, ev.stop, 0,
+                                  b);
+    }
     if (tree) {
-        HDM_HIP(hipEventRecord(lane.fork, s));
         HDM_HIP(hipStreamWaitEvent(lane.side, lane.fork, 0));
         {   // N2S: step k processes level depth - k of every operator
             PhaseScope ph(cx, HDM_PHASE_N2S, lane.side);
@@ -931,17 +944,6 @@ static void apply_t(const ApplyReq* reqs, int nops, bool f64, int normalised, in
             }
         }
         HDM_HIP(hipEventRecord(lane.join, lane.side));
-    }
-    {
-        const int64_t tot = prefix([](const Op& op, int) {
-            return static_cast<int64_t>(mma ? op.items_mma.size() : op.items.size());
-        });
-        KernelEvents ev(cx, HDM_PHASE_L2L);
-        if (mma)
-            hipExtLaunchKernelGGL(k_l2l_mma, dim3(ceil_div(tot, wpb)), dim3(kBlock), 0, s, ev.start, ev.stop, 0, b);
-        else
-            hipExtLaunchKernelGGL((k_l2l<V, TN>), dim3(ceil_div(tot, wpb)), dim3(kBlock), 0, s, ev.start, ev.stop, 0,
-                                  b);
     }
     if (tree) HDM_HIP(hipStreamWaitEvent(s, lane.join, 0));
     {

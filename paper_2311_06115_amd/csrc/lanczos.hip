@@ -37,26 +37,29 @@ __device__ inline double block_sum(double v, double* sm) {
     return r;
 }
 
-// partial[b][c] = sum over the block's rows of V[row, c] * y[row], c < ncols
-__global__ void k_gemvt(const double* V, int64_t ldv, int ncols, const double* y, int64_t n, double* partial,
-                        int ldp) {
-    __shared__ double sm[kBlock / 64];
+// partial[b][c] = sum over the block's rows of V[row, c] * y[row], c < ncols.
+// Each wave takes whole columns (lanes over rows, y held in registers) and
+// reduces with a butterfly: no workgroup barriers per column.
+__global__ void __launch_bounds__(kBlock) k_gemvt(const double* V, int64_t ldv, int ncols, const double* y, int64_t n,
+                                                  double* partial, int ldp) {
+    constexpr int kPer = kRows / 64;   // rows per lane
     const int64_t r0 = blockIdx.x * static_cast<int64_t>(kRows);
-    double yr[kRows / kBlock];
+    const int wv = threadIdx.x / 64, lane = threadIdx.x % 64, nw = blockDim.x / 64;
+    double yr[kPer];
 #pragma unroll
-    for (int u = 0; u < kRows / kBlock; ++u) {
-        const int64_t row = r0 + u * kBlock + threadIdx.x;
+    for (int u = 0; u < kPer; ++u) {
+        const int64_t row = r0 + u * 64 + lane;
         yr[u] = row < n ? y[row] : 0.0;
     }
-    for (int c = 0; c < ncols; ++c) {
+    for (int c = wv; c < ncols; c += nw) {
         double acc = 0.0;
 #pragma unroll
-        for (int u = 0; u < kRows / kBlock; ++u) {
-            const int64_t row = r0 + u * kBlock + threadIdx.x;
-            if (row < n) acc += V[c * ldv + row] * yr[u];
+        for (int u = 0; u < kPer; ++u) {
+            const int64_t row = r0 + u * 64 + lane;
+            acc += (row < n ? V[c * ldv + row] : 0.0) * yr[u];
         }
-        const double t = block_sum(acc, sm);
-        if (threadIdx.x == 0) partial[static_cast<int64_t>(blockIdx.x) * ldp + c] = t;
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+        if (lane == 0) partial[static_cast<int64_t>(blockIdx.x) * ldp + c] = acc;
     }
 }
 
