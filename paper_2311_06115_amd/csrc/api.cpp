@@ -220,6 +220,14 @@ hdm_status hdm_ctx_destroy(hdm_ctx ctx) {
     });
 }
 
+hdm_status hdm_ctx_graphs(hdm_ctx ctx, int enable) {
+    return guarded([&] {
+        HDM_CHECK(ctx, HDM_EINVAL, "NULL context");
+        ctx->graphs = enable != 0;
+        return HDM_OK;
+    });
+}
+
 hdm_status hdm_ctx_profile(hdm_ctx ctx, int enable) {
     return guarded([&] {
         HDM_CHECK(ctx, HDM_EINVAL, "NULL context");

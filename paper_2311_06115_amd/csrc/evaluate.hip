@@ -7,6 +7,8 @@
 //   L2L  near:     u_a += sum_{b in Near(a)} K(a, b) w_b   (streams the near tiles)
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <memory>
 #include <type_traits>
 
 #include "op.hpp"
@@ -1000,6 +1002,160 @@ void apply_batch(const ApplyReq* reqs, int nops, int normalised, int nrhs, hipSt
     apply_dispatch(reqs, nops, f64, normalised, nrhs, s, lane, cx);
 }
 
+// ---- single-operator products as a HIP graph --------------------------------
+// The product's kernels (staging, near field, the upward pass level by level,
+// the far field, combine) are launch-latency bound on the host: as a graph the
+// whole product is one launch.  The graph is built once per (precision path,
+// normalised, right-hand sides); per call only the staging node (x) and the
+// combine node (y) get new arguments.  A profiling context launches eagerly, so
+// that every kernel is timed by its own start and end stamps.
+struct ProductGraph {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipGraphNode_t prep = nullptr, combine = nullptr;
+    hipKernelNodeParams prep_p{}, comb_p{};
+    Batch prep_b{}, comb_b{};
+    ~ProductGraph() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (g) (void)hipGraphDestroy(g);
+    }
+};
+
+struct Op::GraphCache {
+    std::map<uint32_t, std::unique_ptr<ProductGraph>> m;
+    bool broken = false;   // graph construction failed once: eager launches from then on
+};
+
+Op::~Op() { delete graphs; }
+
+template <typename V, typename TN, typename TF, typename TP>
+static void build_product_graph(Op& op, bool f64, int normalised, int nrhs, ProductGraph& G) {
+    constexpr bool mma = std::is_same<TN, f16_t>::value;
+    const bool multi = nrhs > 1;
+    const int wpb = kBlock / kWave;
+    HDM_HIP(hipGraphCreate(&G.g, 0));
+    Batch base{};
+    base.nops = 1;
+    base.nrhs = nrhs;
+    base.op[0] = f64 ? op.dev64.get() : op.devT.get();
+    base.pre[0] = 0;
+    auto kernel = [&](void* func, dim3 grid, Batch bb, std::vector<hipGraphNode_t> deps, hipKernelNodeParams* keep) {
+        hipKernelNodeParams p{};
+        void* args[] = {&bb};
+        p.func = func;
+        p.gridDim = grid;
+        p.blockDim = dim3(kBlock);
+        p.sharedMemBytes = 0;
+        p.kernelParams = args;
+        p.extra = nullptr;
+        hipGraphNode_t n = nullptr;
+        HDM_HIP(hipGraphAddKernelNode(&n, G.g, deps.empty() ? nullptr : deps.data(), deps.size(), &p));
+        if (keep) {
+            *keep = p;
+            keep->kernelParams = nullptr;
+        }
+        return n;
+    };
+    // staging
+    Batch bp = base;
+    bp.arg[0] = normalised;
+    bp.pre[1] = mma ? op.L : op.n;
+    G.prep = kernel(mma ? reinterpret_cast<void*>(&k_prep_mma) : reinterpret_cast<void*>(&k_prep<V>),
+                    mma ? dim3(op.L) : dim3(ceil_div(op.n, kBlock)), bp, {}, &G.prep_p);
+    G.prep_b = bp;
+    // near field
+    Batch bl = base;
+    const int64_t nitems = static_cast<int64_t>(mma ? op.items_mma.size() : op.items.size());
+    bl.pre[1] = nitems;
+    std::vector<hipGraphNode_t> comb_deps{
+        kernel(mma ? reinterpret_cast<void*>(&k_l2l_mma) : reinterpret_cast<void*>(&k_l2l<V, TN>),
+               dim3(ceil_div(nitems, wpb)), bl, {G.prep}, nullptr)};
+    if (op.nskel > 0) {
+        // upward pass, leaves first, one node per level, then the far field
+        hipGraphNode_t last = G.prep;
+        for (int lvl = op.depth; lvl >= 1; --lvl) {
+            if (op.row_count[lvl] == 0) continue;
+            Batch bn = base;
+            bn.arg[0] = lvl;
+            bn.pre[1] = op.row_count[lvl];
+            last = kernel(multi ? reinterpret_cast<void*>(&k_n2s_m<V, TP>) : reinterpret_cast<void*>(&k_n2s<V, TP>),
+                          dim3(ceil_div(op.row_count[lvl], wpb)), bn, {last}, nullptr);
+        }
+        if (op.row_total > 0) {
+            Batch bs = base;
+            bs.pre[1] = op.row_total;
+            last = kernel(multi ? reinterpret_cast<void*>(&k_s2s_m<V, TF>) : reinterpret_cast<void*>(&k_s2s<V, TF>),
+                          dim3(ceil_div(op.row_total, wpb)), bs, {last}, nullptr);
+        }
+        if (last != G.prep) comb_deps.push_back(last);
+    }
+    Batch bc = base;
+    bc.arg[0] = normalised;
+    bc.pre[1] = op.L;
+    G.combine = kernel(multi ? reinterpret_cast<void*>(&k_combine_m<V, TP>) : reinterpret_cast<void*>(&k_combine<V, TP>),
+                       dim3(op.L), bc, comb_deps, &G.comb_p);
+    G.comb_b = bc;
+    HDM_HIP(hipGraphInstantiate(&G.exec, G.g, nullptr, nullptr, 0));
+}
+
+static void build_product_graph_dispatch(Op& op, bool f64, int normalised, int nrhs, ProductGraph& G) {
+    if (f64) {
+        build_product_graph<double, double, double, double>(op, true, normalised, nrhs, G);
+        return;
+    }
+    auto far = [&](auto near_tag) {
+        using TN = decltype(near_tag);
+        switch (op.prm.far_prec) {
+            case HDM_F32: build_product_graph<float, TN, float, float>(op, false, normalised, nrhs, G); break;
+            case HDM_BF16: build_product_graph<float, TN, bf16_t, float>(op, false, normalised, nrhs, G); break;
+            case HDM_F16: build_product_graph<float, TN, f16_t, float>(op, false, normalised, nrhs, G); break;
+            default: fail(HDM_EINVAL, "unsupported far precision with reduced near precision");
+        }
+    };
+    switch (op.prm.near_prec) {
+        case HDM_F32: far(float{}); break;
+        case HDM_BF16: far(bf16_t{}); break;
+        case HDM_F16: far(f16_t{}); break;
+        default: fail(HDM_EINVAL, "unsupported near precision");
+    }
+}
+
+// one product pass through the cached graph; false when graphs are unavailable
+static bool apply_graph(Op& op, bool f64, int normalised, int nrhs, const double* x, double* y, hipStream_t s) {
+    Ctx* cx = op.ctx;
+    if (!cx || !cx->graphs || cx->prof.on) return false;
+    if (!op.graphs) op.graphs = new Op::GraphCache();
+    if (op.graphs->broken) return false;
+    const uint32_t key = (f64 ? 1u : 0u) | (normalised ? 2u : 0u) | (static_cast<uint32_t>(nrhs) << 2);
+    auto it = op.graphs->m.find(key);
+    if (it == op.graphs->m.end()) {
+        std::unique_ptr<ProductGraph> G(new ProductGraph());
+        try {
+            build_product_graph_dispatch(op, f64, normalised, nrhs, *G);
+        } catch (const Error&) {
+            op.graphs->broken = true;
+            (void)hipGetLastError();
+            return false;
+        }
+        it = op.graphs->m.emplace(key, std::move(G)).first;
+    }
+    ProductGraph& G = *it->second;
+    Batch bp = G.prep_b;
+    bp.x[0] = x;
+    void* pa[] = {&bp};
+    hipKernelNodeParams pp = G.prep_p;
+    pp.kernelParams = pa;
+    HDM_HIP(hipGraphExecKernelNodeSetParams(G.exec, G.prep, &pp));
+    Batch bc = G.comb_b;
+    bc.y[0] = y;
+    void* ca[] = {&bc};
+    hipKernelNodeParams cp = G.comb_p;
+    cp.kernelParams = ca;
+    HDM_HIP(hipGraphExecKernelNodeSetParams(G.exec, G.combine, &cp));
+    HDM_HIP(hipGraphLaunch(G.exec, s));
+    return true;
+}
+
 void apply(Op& op, int normalised, bool exact64, const double* x, double* y, int nrhs, hipStream_t s) {
     HDM_CHECK(op.prm.max_rank_s <= kMaxRank, HDM_EINTERNAL, "rank above the combine kernel's limit");
     HDM_CHECK(nrhs >= 1, HDM_EINVAL, "nrhs must be >= 1");
@@ -1015,7 +1171,9 @@ void apply(Op& op, int normalised, bool exact64, const double* x, double* y, int
     Ctx* cx = exact64 ? nullptr : op.ctx;
     for (int c0 = 0; c0 < nrhs; c0 += per) {
         const ApplyReq r{&op, x + static_cast<int64_t>(c0) * op.n, y + static_cast<int64_t>(c0) * op.n};
-        apply_dispatch(&r, 1, f64, normalised, std::min(per, nrhs - c0), s, op.lane, cx);
+        const int np = std::min(per, nrhs - c0);
+        if (!exact64 && apply_graph(op, f64, normalised, np, r.x, r.y, s)) continue;
+        apply_dispatch(&r, 1, f64, normalised, np, s, op.lane, cx);
     }
 }
 

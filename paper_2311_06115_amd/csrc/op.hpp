@@ -36,6 +36,7 @@ struct Ctx {
     int device = 0;
     size_t budget = 0;      // bytes, 0 = unlimited
     size_t resident = 0;    // bytes held by live operators of this context
+    bool graphs = true;     // single-operator products replay a HIP graph
     Profiler prof;
 };
 
@@ -222,6 +223,10 @@ struct Op {
         std::vector<std::vector<int32_t>> h32;
     };
     std::unique_ptr<ConvKeep> conv_keep;
+    // HIP graphs of the single-operator product, one per (precision path,
+    // normalised, right-hand sides, profiled) (evaluate.hip)
+    struct GraphCache;
+    GraphCache* graphs = nullptr;
     DevBuf<int32_t> d_rank, d_ncand;
     DevBuf<int64_t> d_skoff, d_poff, d_far_block_off;
     DevBuf<int32_t> d_far_cols;
@@ -241,6 +246,7 @@ struct Op {
     Op() = default;
     Op(const Op&) = delete;
     Op& operator=(const Op&) = delete;
+    ~Op();
 };
 
 // one operand of a batched product

@@ -103,6 +103,7 @@ def lib():
         "hdm_ctx_destroy": (st, [vp]),
         "hdm_ctx_profile": (st, [vp, C.c_int]),
         "hdm_ctx_phase_times": (st, [vp, C.POINTER(PhaseTimes)]),
+        "hdm_ctx_graphs": (st, [vp, C.c_int]),
         "hdm_compress": (st, [vp, vp, C.c_int, C.POINTER(Params), vp, C.POINTER(vp)]),
         "hdm_op_destroy": (st, [vp]),
         "hdm_op_stats": (st, [vp, C.POINTER(OpStats)]),
@@ -157,6 +158,10 @@ class Context:
 
     def profile(self, enable: bool):
         check(lib().hdm_ctx_profile(self.h, int(enable)))
+
+    def graphs(self, enable: bool):
+        """Single-operator products replay a HIP graph (True, the default) or launch eagerly."""
+        check(lib().hdm_ctx_graphs(self.h, int(enable)))
 
     def phase_times(self):
         """{phase: (launches, milliseconds)} recorded since profile(True)."""
