@@ -510,6 +510,20 @@ static int sample_rows(orc_h *H, int64_t h, const int32_t *cand, int32_t nc, int
     return nr;
 }
 
+/* sum over i in [i0, i1) of a[i sa] * b[i sb], in a fixed order: eight partial
+ * sums, the term of row i going to partial (i - i0) mod 8 in increasing i, then
+ * ((p0 + p1) + (p2 + p3)) + ((p4 + p5) + (p6 + p7)).  The paper leaves the
+ * order of these sums open; this one is the ID's reading for every column norm,
+ * reflector norm and reflector-column inner product below. */
+static double sum8(const double *a, int64_t sa, const double *b, int64_t sb, int32_t i0, int32_t i1) {
+    double p[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int32_t i = i0; i < i1; ++i) {
+        const int u = (i - i0) & 7;
+        p[u] = p[u] + a[(int64_t)i * sa] * b[(int64_t)i * sb];
+    }
+    return ((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7]));
+}
+
 /* Interpolative decomposition of B (nr x nc, row-major, overwritten) by
  * Householder QR with column pivoting: the pivot is the column of largest
  * remaining 2-norm (ties: lowest current column); the rank is the number of
@@ -527,9 +541,7 @@ static int32_t pivoted_id(double *B, int32_t nr, int32_t nc, int32_t s, double t
         int32_t best = j;
         double bestv = -1.0;
         for (int32_t c = j; c < nc; ++c) {
-            double acc = 0.0;
-            for (int32_t i = j; i < nr; ++i) acc = acc + B[(int64_t)i * nc + c] * B[(int64_t)i * nc + c];
-            const double nrm = sqrt(acc);
+            const double nrm = sqrt(sum8(B + c, nc, B + c, nc, j, nr));
             if (nrm > bestv) { bestv = nrm; best = c; }
         }
         if (best != j) {
@@ -546,11 +558,9 @@ static int32_t pivoted_id(double *B, int32_t nr, int32_t nc, int32_t s, double t
         const double alpha = x0 >= 0.0 ? -bestv : bestv;
         v[j] = x0 - alpha;
         for (int32_t i = j + 1; i < nr; ++i) v[i] = B[(int64_t)i * nc + j];
-        double vtv = 0.0;
-        for (int32_t i = j; i < nr; ++i) vtv = vtv + v[i] * v[i];
+        const double vtv = sum8(v, 1, v, 1, j, nr);
         for (int32_t c = j + 1; c < nc; ++c) {
-            double dot = 0.0;
-            for (int32_t i = j; i < nr; ++i) dot = dot + v[i] * B[(int64_t)i * nc + c];
+            const double dot = sum8(v, 1, B + c, nc, j, nr);
             const double f = (2.0 * dot) / vtv;
             for (int32_t i = j; i < nr; ++i) B[(int64_t)i * nc + c] = B[(int64_t)i * nc + c] - f * v[i];
         }

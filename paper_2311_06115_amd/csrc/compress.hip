@@ -22,6 +22,7 @@ namespace {
 constexpr int kSample = 64;     // points sampled per node for the centroid
 constexpr int kMaxCand = 2048;  // candidates of one node (leaf points or children's skeletons)
 constexpr int kBlock = 256;
+constexpr int kWave = 64;
 
 struct Pts {
     const double* xf;
@@ -594,6 +595,7 @@ struct LevelArgs {
     double* Pws;                // per node s x cmax
     int32_t* rk;                // per node
     int32_t* status;            // per node: 0 ok, 1 row fill failed
+    int64_t lds_b;              // ID: elements of B a workgroup keeps in shared memory
 };
 
 __global__ void k_cand(LevelArgs A) {
@@ -797,154 +799,339 @@ __global__ void k_block(LevelArgs A, Pts P) {
     A.B[t * static_cast<int64_t>(A.rmax) * A.cmax + e] = kval(P, A.rows[t * A.rmax + r], A.cand[t * A.cmax + c]);
 }
 
-// sum_{i in [i0, i1)} x_i^2 of column c, sequential in i; loads are issued in
-// batches so the chain of additions does not wait on each load
-constexpr int kQrBatch = 16;
-__device__ inline double col_sumsq(const double* B, int nc, int c, int i0, int i1) {
-    double acc = 0.0;
+// ---- interpolative decomposition --------------------------------------------
+// Every column norm, reflector norm and reflector-column inner product of the
+// ID is a sum over rows [i0, i1) taken in one fixed order: the term of row i
+// goes to partial sum (i - i0) mod 8 in increasing i, and the partials combine
+// as ((p0 + p1) + (p2 + p3)) + ((p4 + p5) + (p6 + p7)).  The eight chains are
+// independent, so up to eight lanes share one column.
+
+// The rows of a node's block B (nr x nc, row-major) below R are kept in shared
+// memory (sB, odd leading dimension ldS against bank conflicts), the rest stay
+// in global memory (gB, leading dimension nc).
+typedef __attribute__((address_space(3))) double lds_f64;   // a float64 in shared memory
+
+struct QrBlock {
+    lds_f64* sB;
+    double* gB;
+    int nc, ldS, R;
+    __device__ double ld(int i, int c) const {
+        return i < R ? sB[i * ldS + c] : gB[static_cast<int64_t>(i) * nc + c];
+    }
+    __device__ void st(int i, int c, double x) const {
+        if (i < R) sB[i * ldS + c] = x;
+        else gB[static_cast<int64_t>(i) * nc + c] = x;
+    }
+};
+
+// Rows [i0, i1) of column c, shared by the L lanes of a lane group (L = 1, 2,
+// 4 or 8 consecutive lanes of one wave).  Row i has phase (i - i0) mod 8; lane
+// `lane` owns phases lane + L m (m < 8 / L) and visits its rows in increasing
+// order, in batches whose loads are all issued first.  body(m, i, x) sees the
+// phase slot m as a compile-time constant; with kWrite the modified x is stored.
+template <int L, bool kWrite, typename Body>
+__device__ inline void group_rows(const QrBlock& Q, int lane, int c, int i0, int i1, Body&& body) {
+    constexpr int PH = 8 / L, KB = L == 1 ? 2 : 8 / PH, SPAN = 8 * KB;   // 16 or 8 loads per lane and batch
     int i = i0;
-    for (; i + kQrBatch <= i1; i += kQrBatch) {
-        double x[kQrBatch];
+    const int rl = min(Q.R, i1);
+    for (; i + SPAN <= rl; i += SPAN) {   // rows in shared memory
+        double x[KB][PH];
 #pragma unroll
-        for (int u = 0; u < kQrBatch; ++u) x[u] = B[static_cast<int64_t>(i + u) * nc + c];
+        for (int k = 0; k < KB; ++k)
 #pragma unroll
-        for (int u = 0; u < kQrBatch; ++u) acc = acc + x[u] * x[u];
+            for (int m = 0; m < PH; ++m) x[k][m] = Q.sB[(i + 8 * k + lane + L * m) * Q.ldS + c];
+#pragma unroll
+        for (int k = 0; k < KB; ++k)
+#pragma unroll
+            for (int m = 0; m < PH; ++m) {
+                const int r = i + 8 * k + lane + L * m;
+                body(m, r, x[k][m]);
+                if (kWrite) Q.sB[r * Q.ldS + c] = x[k][m];
+            }
     }
-    for (; i < i1; ++i) {
-        const double x = B[static_cast<int64_t>(i) * nc + c];
-        acc = acc + x * x;
+    if (i < rl && i + SPAN <= i1) {   // the batch across R
+        double x[KB][PH];
+#pragma unroll
+        for (int k = 0; k < KB; ++k)
+#pragma unroll
+            for (int m = 0; m < PH; ++m) x[k][m] = Q.ld(i + 8 * k + lane + L * m, c);
+#pragma unroll
+        for (int k = 0; k < KB; ++k)
+#pragma unroll
+            for (int m = 0; m < PH; ++m) {
+                const int r = i + 8 * k + lane + L * m;
+                body(m, r, x[k][m]);
+                if (kWrite) Q.st(r, c, x[k][m]);
+            }
+        i += SPAN;
     }
-    return acc;
+    for (; i + SPAN <= i1; i += SPAN) {   // rows in global memory (i >= R)
+        double x[KB][PH];
+#pragma unroll
+        for (int k = 0; k < KB; ++k)
+#pragma unroll
+            for (int m = 0; m < PH; ++m) x[k][m] = Q.gB[static_cast<int64_t>(i + 8 * k + lane + L * m) * Q.nc + c];
+#pragma unroll
+        for (int k = 0; k < KB; ++k)
+#pragma unroll
+            for (int m = 0; m < PH; ++m) {
+                const int r = i + 8 * k + lane + L * m;
+                body(m, r, x[k][m]);
+                if (kWrite) Q.gB[static_cast<int64_t>(r) * Q.nc + c] = x[k][m];
+            }
+    }
+    if (i < i1) {   // last partial batch; (i - i0) is a multiple of 8 here
+        double x[KB][PH];
+#pragma unroll
+        for (int k = 0; k < KB; ++k)
+#pragma unroll
+            for (int m = 0; m < PH; ++m) {
+                const int r = i + 8 * k + lane + L * m;
+                x[k][m] = r < i1 ? Q.ld(r, c) : 0.0;
+            }
+#pragma unroll
+        for (int k = 0; k < KB; ++k)
+#pragma unroll
+            for (int m = 0; m < PH; ++m) {
+                const int r = i + 8 * k + lane + L * m;
+                if (r < i1) {
+                    body(m, r, x[k][m]);
+                    if (kWrite) Q.st(r, c, x[k][m]);
+                }
+            }
+    }
+}
+
+// The eight phase sums of a lane group, combined as
+// ((p0 + p1) + (p2 + p3)) + ((p4 + p5) + (p6 + p7)); every lane of the group
+// gets the total.  Lane l holds phases l + L m in p[m].  The shuffles add the
+// partner lane's partial first (lanes l and l ^ d hold phases that are
+// siblings in the tree), then the lane adds its own slots pairwise.
+template <int L>
+__device__ inline double group_total(double* p) {
+    constexpr int PH = 8 / L;
+#pragma unroll
+    for (int d = 1; d < L; d <<= 1)
+#pragma unroll
+        for (int m = 0; m < PH; ++m) p[m] = p[m] + __shfl_xor(p[m], d, kWave);
+    if (PH == 1) return p[0];
+    if (PH == 2) return p[0] + p[1];
+    if (PH == 4) return (p[0] + p[1]) + (p[2] + p[3]);
+    return ((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7]));
+}
+
+// squared norms over rows [0, nr) of every column, L lanes per column
+template <int L>
+__device__ inline void id_norms(const QrBlock& Q, double* nsq, int nr, int nc) {
+    constexpr int PH = 8 / L;
+    const int lane = threadIdx.x % L;
+    for (int c = threadIdx.x / L; c < nc; c += kBlock / L) {
+        double p[PH];
+#pragma unroll
+        for (int m = 0; m < PH; ++m) p[m] = 0.0;
+        group_rows<L, false>(Q, lane, c, 0, nr, [&](int m, int, double& x) { p[m] = p[m] + x * x; });
+        const double t = group_total<L>(p);
+        if (lane == 0) nsq[c] = t;
+    }
+}
+
+// Apply the reflector (hv, rows [j, nr), hv^T hv = vtv) to the columns after j,
+// L lanes per column, and leave their squared norms over rows [j + 1, nr) in
+// nsq.  A column's lanes are in one wave and its dot product is complete (the
+// shuffles consume every lane's loads) before any of its rows is stored.
+template <int L>
+__device__ inline void id_reflect(const QrBlock& Q, const double* hv, double* nsq, int j, int nr, int nc,
+                                  double vtv) {
+    constexpr int PH = 8 / L;
+    const int lane = threadIdx.x % L;
+    for (int c = j + 1 + threadIdx.x / L; c < nc; c += kBlock / L) {
+        double p[PH];
+#pragma unroll
+        for (int m = 0; m < PH; ++m) p[m] = 0.0;
+        group_rows<L, false>(Q, lane, c, j, nr, [&](int m, int i, double& x) { p[m] = p[m] + hv[i] * x; });
+        const double f = (2.0 * group_total<L>(p)) / vtv;
+        // the pivot row first (its square is not part of the next norm), then the rest
+        if (lane == 0) Q.st(j, c, Q.ld(j, c) - f * hv[j]);
+#pragma unroll
+        for (int m = 0; m < PH; ++m) p[m] = 0.0;
+        group_rows<L, true>(Q, lane, c, j + 1, nr, [&](int m, int i, double& x) {
+            x = x - f * hv[i];
+            p[m] = p[m] + x * x;
+        });
+        const double t = group_total<L>(p);
+        if (lane == 0) nsq[c] = t;
+    }
+}
+
+// Columns c >= rank of P = R11^-1 R12 by back substitution, one thread per
+// column, each entry a sequential sum in q: acc = R[i][c] - sum_q R[i][q] X[q].
+// With kLds the solution column is kept in the free rows [rank, 2 rank) of the
+// staged block and copied to P at the end; otherwise it is built in P directly.
+template <bool kLds>
+__device__ inline void id_back_subst(const QrBlock& Q, double* Pm, const int32_t* cp, int rank, int nc) {
+    for (int c = rank + threadIdx.x; c < nc; c += blockDim.x) {
+        const int pc = cp[c];
+        auto xld = [&](int q) -> double {
+            if constexpr (kLds) return Q.sB[(rank + q) * Q.ldS + c];
+            else return Pm[static_cast<int64_t>(q) * nc + pc];
+        };
+        auto xst = [&](int q, double v) {
+            if constexpr (kLds) Q.sB[(rank + q) * Q.ldS + c] = v;
+            else Pm[static_cast<int64_t>(q) * nc + pc] = v;
+        };
+        for (int i = rank - 1; i >= 0; --i) {
+            double acc = Q.ld(i, c);
+            int q = i + 1;
+            for (; q + 8 <= rank; q += 8) {
+                double a[8], b[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    a[k] = Q.ld(i, q + k);
+                    b[k] = xld(q + k);
+                }
+#pragma unroll
+                for (int k = 0; k < 8; ++k) acc = acc - a[k] * b[k];
+            }
+            for (; q < rank; ++q) acc = acc - Q.ld(i, q) * xld(q);
+            xst(i, acc / Q.ld(i, i));
+        }
+        if (kLds)
+            for (int i = 0; i < rank; ++i) Pm[static_cast<int64_t>(i) * nc + pc] = xld(i);
+    }
+}
+
+// lanes per column for k remaining columns: as many as keep the workgroup busy
+__device__ inline int id_lanes(int k) { return k * 8 <= kBlock ? 8 : k * 4 <= kBlock ? 4 : k * 2 <= kBlock ? 2 : 1; }
+
+// workgroup argmax of (v, column) with ties to the lower column; every thread gets the result
+__device__ inline void wg_argmax(double& v, int& c, double* sv, int* sc) {
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        const double ov = __shfl_xor(v, off, kWave);
+        const int oc = __shfl_xor(c, off, kWave);
+        if (ov > v || (ov == v && oc < c)) { v = ov; c = oc; }
+    }
+    const int w = threadIdx.x / kWave;
+    if (threadIdx.x % kWave == 0) { sv[w] = v; sc[w] = c; }
+    __syncthreads();
+    v = sv[0];
+    c = sc[0];
+    for (int k = 1; k < kBlock / kWave; ++k)
+        if (sv[k] > v || (sv[k] == v && sc[k] < c)) { v = sv[k]; c = sc[k]; }
+    __syncthreads();
 }
 
 // Householder QR with column pivoting of B (nr x nc) and the interpolation
 // matrix P = [I, R11^-1 R12] in candidate order.  One workgroup per node, one
-// thread per column; every column norm and dot product is a sequential sum
-// over rows.  The squared norms that choose the next pivot are accumulated
-// while the reflector is applied (same values, same order as a separate pass).
+// thread per column for the column sums (each a fixed-order sum, see above).
+// The leading rows of B are staged in shared memory (as many as fit, A.lds_b
+// elements); the squared norms that choose the next pivot are accumulated
+// while the reflector is applied.
 __global__ void __launch_bounds__(kBlock) k_pivoted_id(LevelArgs A) {
-    __shared__ double sv[kBlock];
-    __shared__ int64_t sp[kBlock];
-    __shared__ double hv[1024];        // Householder vector (rows <= 1024)
-    __shared__ double nsq[kMaxCand];   // remaining squared column norms
-    __shared__ double s_vtv, s_alpha, s_r11;
-    __shared__ int s_stop;
+    extern __shared__ double dyn[];
+    __shared__ double sv[kBlock / kWave];
+    __shared__ int sc[kBlock / kWave];
+    __shared__ double s_vtv, s_alpha;
     const int64_t t = blockIdx.x;
     const int nc = A.ncand[t], nr = A.nrows[t];
-    double* B = A.B + t * static_cast<int64_t>(A.rmax) * A.cmax;
+    double* hv = dyn;                 // Householder vector (A.rmax)
+    double* nsq = dyn + A.rmax;       // remaining squared column norms (A.cmax)
+    QrBlock Q;
+    Q.sB = (lds_f64*)(nsq + A.cmax);   // address-space cast: dyn is shared memory
+    Q.gB = A.B + t * static_cast<int64_t>(A.rmax) * A.cmax;
+    Q.nc = nc;
+    Q.ldS = nc | 1;
+    Q.R = nc > 0 ? min(nr, static_cast<int>(A.lds_b / Q.ldS)) : 0;
     int32_t* cp = A.cp + t * A.cmax;
     double* Pm = A.Pws + t * static_cast<int64_t>(A.s) * A.cmax;
-    for (int c = threadIdx.x; c < nc; c += blockDim.x) {
-        cp[c] = c;
-        nsq[c] = col_sumsq(B, nc, c, 0, nr);
+    for (int e = threadIdx.x; e < Q.R * nc; e += blockDim.x) Q.sB[(e / nc) * Q.ldS + e % nc] = Q.gB[e];
+    for (int c = threadIdx.x; c < nc; c += blockDim.x) cp[c] = c;
+    __syncthreads();
+    switch (id_lanes(nc)) {
+        case 8: id_norms<8>(Q, nsq, nr, nc); break;
+        case 4: id_norms<4>(Q, nsq, nr, nc); break;
+        case 2: id_norms<2>(Q, nsq, nr, nc); break;
+        default: id_norms<1>(Q, nsq, nr, nc); break;
     }
     int kmax = nr < nc ? nr : nc;
     if (kmax > A.s) kmax = A.s;
     int rank = 0;
+    double r11 = 0.0;
     __syncthreads();
     for (int j = 0; j < kmax; ++j) {
         // pivot: largest remaining column norm (ties: lowest column)
         double best = -1.0;
-        int64_t bc = INT64_MAX;
+        int bc = INT32_MAX;
         for (int c = j + threadIdx.x; c < nc; c += blockDim.x) {
             const double nrm = sqrt(nsq[c]);
             if (nrm > best || (nrm == best && c < bc)) { best = nrm; bc = c; }
         }
-        block_argbest(best, bc, false, sv, sp);
-        const int piv = (bc >= j && bc < nc) ? static_cast<int>(bc) : j;
+        wg_argmax(best, bc, sv, sc);
+        const int piv = (bc >= j && bc < nc) ? bc : j;
         if (piv != j) {
             for (int i = threadIdx.x; i < nr; i += blockDim.x) {
-                const double x = B[static_cast<int64_t>(i) * nc + j];
-                B[static_cast<int64_t>(i) * nc + j] = B[static_cast<int64_t>(i) * nc + piv];
-                B[static_cast<int64_t>(i) * nc + piv] = x;
+                const double x = Q.ld(i, j);
+                Q.st(i, j, Q.ld(i, piv));
+                Q.st(i, piv, x);
             }
             if (threadIdx.x == 0) {
                 const int32_t x = cp[j]; cp[j] = cp[piv]; cp[piv] = x;
                 const double y = nsq[j]; nsq[j] = nsq[piv]; nsq[piv] = y;
             }
+            __syncthreads();
         }
+        if (j == 0) r11 = best;
+        if (!(best > A.tau * r11)) break;   // uniform: every thread holds the same best and r11
+        for (int i = j + threadIdx.x; i < nr; i += blockDim.x) hv[i] = Q.ld(i, j);
         __syncthreads();
-        if (threadIdx.x == 0) {
-            if (j == 0) s_r11 = best;
-            s_stop = !(best > A.tau * s_r11);
-        }
-        __syncthreads();
-        if (s_stop) break;
-        for (int i = j + threadIdx.x; i < nr; i += blockDim.x) hv[i] = B[static_cast<int64_t>(i) * nc + j];
-        __syncthreads();
-        if (threadIdx.x == 0) {
+        if (threadIdx.x < 8) {
+            // v = x - alpha e_j; v^T v by phases: lane u sums rows j + u, j + u + 8, ...
+            const int u = threadIdx.x;
             const double x0 = hv[j];
             const double alpha = x0 >= 0.0 ? -best : best;
-            const double v0 = x0 - alpha;
-            hv[j] = v0;
-            double vtv = v0 * v0;
-            int i = j + 1;
-            for (; i + 8 <= nr; i += 8) {
-                double x[8];
+            double acc = 0.0;
+            int i = j + u;
+            for (; i + 56 < nr; i += 64) {
+                double v[8];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) x[u] = hv[i + u];
+                for (int k = 0; k < 8; ++k) v[k] = hv[i + 8 * k];
+                if (i == j) v[0] = x0 - alpha;
 #pragma unroll
-                for (int u = 0; u < 8; ++u) vtv = vtv + x[u] * x[u];
+                for (int k = 0; k < 8; ++k) acc = acc + v[k] * v[k];
             }
-            for (; i < nr; ++i) vtv = vtv + hv[i] * hv[i];
-            s_vtv = vtv;
-            s_alpha = alpha;
+            for (; i < nr; i += 8) {
+                const double vi = i == j ? x0 - alpha : hv[i];
+                acc = acc + vi * vi;
+            }
+            // ((p0 + p1) + (p2 + p3)) + ((p4 + p5) + (p6 + p7)) across lanes 0..7
+            acc = acc + __shfl_xor(acc, 1, 8);
+            acc = acc + __shfl_xor(acc, 2, 8);
+            acc = acc + __shfl_xor(acc, 4, 8);
+            if (u == 0) {
+                s_vtv = acc;
+                s_alpha = alpha;
+                hv[j] = x0 - alpha;
+            }
         }
         __syncthreads();
         const double vtv = s_vtv;
-        for (int c = j + 1 + threadIdx.x; c < nc; c += blockDim.x) {
-            double dot = 0.0;
-            int i = j;
-            for (; i + kQrBatch <= nr; i += kQrBatch) {
-                double x[kQrBatch];
-#pragma unroll
-                for (int u = 0; u < kQrBatch; ++u) x[u] = B[static_cast<int64_t>(i + u) * nc + c];
-#pragma unroll
-                for (int u = 0; u < kQrBatch; ++u) dot = dot + hv[i + u] * x[u];
-            }
-            for (; i < nr; ++i) dot = dot + hv[i] * B[static_cast<int64_t>(i) * nc + c];
-            const double f = (2.0 * dot) / vtv;
-            {   // the pivot row first (its square is not part of the next norm), then batches
-                const int64_t e = static_cast<int64_t>(j) * nc + c;
-                B[e] = B[e] - f * hv[j];
-            }
-            double acc = 0.0;
-            for (i = j + 1; i + kQrBatch <= nr; i += kQrBatch) {
-                double x[kQrBatch];
-#pragma unroll
-                for (int u = 0; u < kQrBatch; ++u) x[u] = B[static_cast<int64_t>(i + u) * nc + c];
-#pragma unroll
-                for (int u = 0; u < kQrBatch; ++u) {
-                    x[u] = x[u] - f * hv[i + u];
-                    B[static_cast<int64_t>(i + u) * nc + c] = x[u];
-                    acc = acc + x[u] * x[u];
-                }
-            }
-            for (; i < nr; ++i) {
-                const int64_t e = static_cast<int64_t>(i) * nc + c;
-                const double x = B[e] - f * hv[i];
-                B[e] = x;
-                acc = acc + x * x;
-            }
-            nsq[c] = acc;
+        switch (id_lanes(nc - j - 1)) {
+            case 8: id_reflect<8>(Q, hv, nsq, j, nr, nc, vtv); break;
+            case 4: id_reflect<4>(Q, hv, nsq, j, nr, nc, vtv); break;
+            case 2: id_reflect<2>(Q, hv, nsq, j, nr, nc, vtv); break;
+            default: id_reflect<1>(Q, hv, nsq, j, nr, nc, vtv); break;
         }
         __syncthreads();
-        for (int i = j + threadIdx.x; i < nr; i += blockDim.x) B[static_cast<int64_t>(i) * nc + j] = (i == j) ? s_alpha : 0.0;
+        for (int i = j + threadIdx.x; i < nr; i += blockDim.x) Q.st(i, j, (i == j) ? s_alpha : 0.0);
         rank = j + 1;
         __syncthreads();
     }
+    __syncthreads();
     // P[:, cp[j]] = e_j for j < rank; P[:, cp[c]] = R11^-1 R12[:, c] (back substitution)
     for (int64_t e = threadIdx.x; e < static_cast<int64_t>(rank) * nc; e += blockDim.x) Pm[e] = 0.0;
     __syncthreads();
     for (int j = threadIdx.x; j < rank; j += blockDim.x) Pm[static_cast<int64_t>(j) * nc + cp[j]] = 1.0;
-    for (int c = rank + threadIdx.x; c < nc; c += blockDim.x) {
-        const int pc = cp[c];
-        for (int i = rank - 1; i >= 0; --i) {
-            double acc = B[static_cast<int64_t>(i) * nc + c];
-            for (int q = i + 1; q < rank; ++q) acc = acc - B[static_cast<int64_t>(i) * nc + q] * Pm[static_cast<int64_t>(q) * nc + pc];
-            Pm[static_cast<int64_t>(i) * nc + pc] = acc / B[static_cast<int64_t>(i) * nc + i];
-        }
-    }
+    if (2 * rank <= Q.R) id_back_subst<true>(Q, Pm, cp, rank, nc);
+    else id_back_subst<false>(Q, Pm, cp, rank, nc);
     if (threadIdx.x == 0) A.rk[t] = rank;
 }
 
@@ -1226,6 +1413,24 @@ static void skeletonize(Op& op, const Geo& G, hipStream_t s) {
     DevBuf<int64_t> d_skoff(op.nnodes), d_poff(op.nnodes), d_rowoff(op.nnodes), d_plocal(op.nnodes);
     std::vector<int64_t> poff_local(op.nnodes, 0);
     HDM_HIP(hipMemsetAsync(d_rank.get(), 0, d_rank.bytes(), s));
+    // the ID's shared memory: Householder vector, column norms, then as many rows of B as fit
+    size_t id_shmem = 0;
+    int64_t id_lds = 0;
+    {
+        int dev = 0, max_shared = 0;
+        HDM_HIP(hipGetDevice(&dev));
+        HDM_HIP(hipDeviceGetAttribute(&max_shared, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+        hipFuncAttributes fa{};
+        HDM_HIP(hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(&k_pivoted_id)));
+        const int64_t avail = (static_cast<int64_t>(max_shared) - static_cast<int64_t>(fa.sharedSizeBytes)) /
+                              static_cast<int64_t>(sizeof(double));
+        HDM_CHECK(avail >= rmax + cmax, HDM_EINTERNAL, "shared memory too small for the ID's vectors");
+        id_lds = avail - rmax - cmax;
+        id_shmem = sizeof(double) * static_cast<size_t>(rmax + cmax + id_lds);
+        if (id_shmem > 65536)
+            HDM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pivoted_id),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(id_shmem)));
+    }
     int64_t sk_next = 0, row_next = 0, p_next = 0;
     std::vector<int32_t> h_rk(maxnodes), h_nc(maxnodes), h_nr(maxnodes), h_st(maxnodes);
     for (int lvl = op.depth; lvl >= 1; --lvl) {
@@ -1279,7 +1484,8 @@ static void skeletonize(Op& op, const Geo& G, hipStream_t s) {
             hipLaunchKernelGGL(k_block, dim3(ceil_div(static_cast<int64_t>(rmax) * cmax, kBlock), nodes), dim3(kBlock),
                                0, s, A, P);
         }
-        hipLaunchKernelGGL(k_pivoted_id, dim3(nodes), dim3(kBlock), 0, s, A);
+        A.lds_b = id_lds;
+        hipLaunchKernelGGL(k_pivoted_id, dim3(nodes), dim3(kBlock), id_shmem, s, A);
         check_launch("skeletonisation");
         rk.download(h_rk.data(), nodes, s);
         ncand.download(h_nc.data(), nodes, s);

@@ -128,7 +128,10 @@ def test_block_lanczos_float16_matches_single_vector():
     th, _, _ = DF.eigs(H.matvec, X.shape[0], r, tol=1e-12)
     relo = np.abs(evb - th) / np.abs(th)
     print(f"[gpu] f16 block-16 vs single: {rel.max():.2e}; vs oracle f64 {relo.max():.2e}; basis {ib.iters} vs {i1.iters}")
-    assert rel.max() <= 1e-6
+    # The two solvers see products that differ by float32 accumulation order (up
+    # to 1e-6 relative per product, asserted above); over the trailing eigenvalues
+    # (lambda_20 ~ 0.2 lambda_1) that is a few 1e-6 relative.
+    assert rel.max() <= 5e-6
     assert relo.max() <= 1e-4
 
 
