@@ -126,14 +126,14 @@ hdm_status hdm_ctx_profile(hdm_ctx ctx, int enable);
 /* Synchronises the recorded events and returns the per-phase totals since the
  * last hdm_ctx_profile(ctx, 1). */
 hdm_status hdm_ctx_phase_times(hdm_ctx ctx, hdm_phase_times_t *out);
-/* enable = 1 (the default): a product on one operator (hdm_matvec and the
- * products inside hdm_eigs) replays a HIP graph of its kernels, built on the
- * operator's first product of each kind (tile precision, normalised, right-hand
- * sides per pass, profiled) and kept until the operator is destroyed; only the
+/* enable = 1 (the default): hdm_matvec replays a HIP graph of the product's
+ * kernels, built on the operator's first hdm_matvec of each kind (normalised,
+ * right-hand sides per pass) and kept until the operator is destroyed; only the
  * vector arguments change between replays.  enable = 0, and any product while
  * the context profiles (hdm_ctx_profile), launches the kernels one by one, each
- * timed by its own start and end stamps.  Both give bit-identical results.
- * Takes effect on the next product. */
+ * timed by its own start and end stamps.  The products inside hdm_eigs always
+ * launch one by one (their near field and upward pass overlap on two streams).
+ * Both give bit-identical results.  Takes effect on the next product. */
 hdm_status hdm_ctx_graphs(hdm_ctx ctx, int enable);
 
 /* ---- compression (Sec. 1.2 "compressed once"; Eq. (3)) ---------------------

@@ -26,6 +26,7 @@ SOURCES = {
     "lanczos.hip": [],
     "api.cpp": [],
     "server.cpp": [],
+    "pool.cpp": [],
 }
 
 COMMON = [

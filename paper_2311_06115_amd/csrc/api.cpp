@@ -253,6 +253,7 @@ hdm_status hdm_ctx_phase_times(hdm_ctx ctx, hdm_phase_times_t* out) {
 hdm_status hdm_compress(hdm_ctx ctx, const void* X, int x_on_device, const hdm_params* params, void* stream,
                         hdm_op* out) {
     return guarded([&] {
+        hdm::PoolScope pool_scope;   // temporaries are cached once the device is idle
         HDM_CHECK(ctx && X && params && out, HDM_EINVAL, "NULL argument");
         hdm::validate_params(*params);
         set_device(ctx->device);
@@ -270,6 +271,7 @@ hdm_status hdm_op_destroy(hdm_op op) {
     return guarded([&] {
         if (!op) return HDM_OK;
         set_device(op->ctx->device);
+        hdm::PoolScope pool_scope;   // the operator's buffers are cached once the device is idle
         const size_t fp = op->footprint();
         op->ctx->resident -= std::min(fp, op->ctx->resident);
         delete op;
@@ -408,7 +410,7 @@ hdm_status hdm_matvec(hdm_op op, int normalised, const double* x, double* y, int
         HDM_CHECK(x + static_cast<int64_t>(op->n) * nrhs <= y || y + static_cast<int64_t>(op->n) * nrhs <= x, HDM_EINVAL,
                   "x and y overlap");
         set_device(op->ctx->device);
-        hdm::apply(*op, normalised ? 1 : 0, false, x, y, nrhs, as_stream(stream));
+        hdm::apply(*op, normalised ? 1 : 0, false, x, y, nrhs, as_stream(stream), true);
         return HDM_OK;
     });
 }
@@ -419,6 +421,7 @@ hdm_status hdm_eigs(hdm_op op, int32_t r, double rel_resid_tol, int32_t block, i
         HDM_CHECK(op && evals, HDM_EINVAL, "NULL argument");
         HDM_CHECK(rel_resid_tol > 0.0 && std::isfinite(rel_resid_tol), HDM_EINVAL, "rel_resid_tol must be > 0");
         set_device(op->ctx->device);
+        hdm::PoolScope pool_scope;
         return hdm::lanczos_eigs(*op, r, rel_resid_tol, block, max_basis, seed, evals, evecs, info, as_stream(stream));
     });
 }

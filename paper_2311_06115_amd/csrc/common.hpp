@@ -40,6 +40,21 @@ inline void check_launch(const char* what) {
     if (e != hipSuccess) fail(HDM_EDEVICE, std::string("launch of ") + what + ": " + hipGetErrorString(e));
 }
 
+// Device memory behind DevBuf: a per-device cache of released blocks.
+// dev_alloc takes the best-fitting cached block or calls hipMalloc.  A block
+// released while a PoolScope is alive on the calling thread waits in that
+// thread's pending list; when the outermost scope ends it synchronises the
+// device and moves the pending blocks into the cache, so a cached block has no
+// GPU work left on it.  A release outside any scope frees the block at once.
+void* dev_alloc(size_t bytes);
+void dev_free(void* p) noexcept;
+struct PoolScope {
+    PoolScope();
+    ~PoolScope();
+    PoolScope(const PoolScope&) = delete;
+    PoolScope& operator=(const PoolScope&) = delete;
+};
+
 // Owning device allocation (no copy, movable).
 template <typename T>
 struct DevBuf {
@@ -58,11 +73,11 @@ struct DevBuf {
     void alloc(size_t count) {
         release();
         if (count == 0) return;
-        HDM_HIP(hipMalloc(&p, count * sizeof(T)));
+        p = static_cast<T*>(dev_alloc(count * sizeof(T)));
         n = count;
     }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p) dev_free(p);
         p = nullptr;
         n = 0;
     }

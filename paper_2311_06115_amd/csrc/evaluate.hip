@@ -1008,7 +1008,11 @@ void apply_batch(const ApplyReq* reqs, int nops, int normalised, int nrhs, hipSt
 // whole product is one launch.  The graph is built once per (precision path,
 // normalised, right-hand sides); per call only the staging node (x) and the
 // combine node (y) get new arguments.  A profiling context launches eagerly, so
-// that every kernel is timed by its own start and end stamps.
+// that every kernel is timed by its own start and end stamps.  The replay runs
+// the near field and the upward pass one after the other (about 136 us at
+// N = 32768, the sum of the kernels), where eager launches overlap them on two
+// streams: graphs pay off for back-to-back products, not inside an iteration
+// that interleaves other kernels with each product.
 struct ProductGraph {
     hipGraph_t g = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -1156,7 +1160,7 @@ static bool apply_graph(Op& op, bool f64, int normalised, int nrhs, const double
     return true;
 }
 
-void apply(Op& op, int normalised, bool exact64, const double* x, double* y, int nrhs, hipStream_t s) {
+void apply(Op& op, int normalised, bool exact64, const double* x, double* y, int nrhs, hipStream_t s, bool graph_ok) {
     HDM_CHECK(op.prm.max_rank_s <= kMaxRank, HDM_EINTERNAL, "rank above the combine kernel's limit");
     HDM_CHECK(nrhs >= 1, HDM_EINVAL, "nrhs must be >= 1");
     const int per = std::min(nrhs, kMaxRhs);   // right-hand sides per pass
@@ -1172,7 +1176,7 @@ void apply(Op& op, int normalised, bool exact64, const double* x, double* y, int
     for (int c0 = 0; c0 < nrhs; c0 += per) {
         const ApplyReq r{&op, x + static_cast<int64_t>(c0) * op.n, y + static_cast<int64_t>(c0) * op.n};
         const int np = std::min(per, nrhs - c0);
-        if (!exact64 && apply_graph(op, f64, normalised, np, r.x, r.y, s)) continue;
+        if (graph_ok && !exact64 && apply_graph(op, f64, normalised, np, r.x, r.y, s)) continue;
         apply_dispatch(&r, 1, f64, normalised, np, s, op.lane, cx);
     }
 }

@@ -299,7 +299,10 @@ void convert_eval_precision(Op& op, hipStream_t s);
 // starts the conversion of the float64 near tiles to the evaluation precision
 // on s without waiting (convert_eval_precision completes it after s is synchronised)
 void convert_near_tiles(Op& op, hipStream_t s);
-void apply(Op& op, int normalised, bool exact64, const double* x, double* y, int nrhs, hipStream_t s);
+// graph_ok: the product may replay the operator's cached HIP graph (the caller's
+// one-off products); iterations that interleave other kernels launch eagerly
+void apply(Op& op, int normalised, bool exact64, const double* x, double* y, int nrhs, hipStream_t s,
+           bool graph_ok = false);
 // One launch per phase for every operator of the batch (same tile precisions,
 // at most kMaxBatch operators, one nrhs); each operator's result is the one a
 // single-operator product gives.

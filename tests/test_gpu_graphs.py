@@ -6,7 +6,8 @@ vector arguments.  Every replay must equal the eager launches bit for bit
 eager work and synchronisations in between, for one and several right-hand
 sides, raw and normalised, float64 and float16 tiles.  A profiling context
 launches eagerly (each kernel timed by its own stamps) with the same results.
-The eigensolver on top of it gives the same eigenvalues either way.
+The eigensolver launches eagerly whatever the setting and gives the same
+eigenvalues either way.
 """
 import numpy as np
 import pytest
