@@ -580,9 +580,8 @@ struct LevelArgs {
     const int32_t* perm;
     const int32_t* iperm;
     const int32_t* kidx;
-    const int32_t* skel;        // compact skeletons of the level below
-    const int64_t* skoff;       // per heap id
-    const int32_t* rank;        // per heap id (level below filled)
+    const int32_t* skel_fix;    // skeletons of every node, heap id h at h * s (levels below filled)
+    const int32_t* rank;        // per heap id (levels below filled)
     int32_t* cand;              // per node cmax
     int32_t* ncand;             // per node
     int32_t* cnt;               // per node n
@@ -592,8 +591,8 @@ struct LevelArgs {
     int32_t* nrows;             // per node
     double* B;                  // per node rmax x cmax
     int32_t* cp;                // per node cmax
-    double* Pws;                // per node s x cmax
-    int32_t* rk;                // per node
+    double* Pfix;               // P of every node, heap id h at h * s * cmax (rank x ncand, row-major)
+    int32_t* rk;                // per heap id: rank
     int32_t* status;            // per node: 0 ok, 1 row fill failed
     int64_t lds_b;              // ID: elements of B a workgroup keeps in shared memory
 };
@@ -608,8 +607,9 @@ __global__ void k_cand(LevelArgs A) {
         if (threadIdx.x == 0) A.ncand[t] = static_cast<int32_t>(n);
     } else {
         const int rl = A.rank[2 * h], rr = A.rank[2 * h + 1];
-        for (int u = threadIdx.x; u < rl + rr; u += blockDim.x)
-            c[u] = u < rl ? A.skel[A.skoff[2 * h] + u] : A.skel[A.skoff[2 * h + 1] + (u - rl)];
+        const int32_t* sl = A.skel_fix + 2 * h * A.s;
+        const int32_t* sr = A.skel_fix + (2 * h + 1) * A.s;
+        for (int u = threadIdx.x; u < rl + rr; u += blockDim.x) c[u] = u < rl ? sl[u] : sr[u - rl];
         if (threadIdx.x == 0) A.ncand[t] = rl + rr;
     }
 }
@@ -1042,7 +1042,8 @@ __global__ void __launch_bounds__(kBlock) k_pivoted_id(LevelArgs A) {
     Q.ldS = nc | 1;
     Q.R = nc > 0 ? min(nr, static_cast<int>(A.lds_b / Q.ldS)) : 0;
     int32_t* cp = A.cp + t * A.cmax;
-    double* Pm = A.Pws + t * static_cast<int64_t>(A.s) * A.cmax;
+    const int64_t h = (int64_t(1) << A.lvl) + t;
+    double* Pm = A.Pfix + h * A.s * A.cmax;
     for (int e = threadIdx.x; e < Q.R * nc; e += blockDim.x) Q.sB[(e / nc) * Q.ldS + e % nc] = Q.gB[e];
     for (int c = threadIdx.x; c < nc; c += blockDim.x) cp[c] = c;
     __syncthreads();
@@ -1132,19 +1133,35 @@ __global__ void __launch_bounds__(kBlock) k_pivoted_id(LevelArgs A) {
     for (int j = threadIdx.x; j < rank; j += blockDim.x) Pm[static_cast<int64_t>(j) * nc + cp[j]] = 1.0;
     if (2 * rank <= Q.R) id_back_subst<true>(Q, Pm, cp, rank, nc);
     else id_back_subst<false>(Q, Pm, cp, rank, nc);
-    if (threadIdx.x == 0) A.rk[t] = rank;
+    if (threadIdx.x == 0) A.rk[h] = rank;
 }
 
-// move this level's skeletons, P and rows into the compact operator arrays
-__global__ void k_compact(LevelArgs A, const int64_t* skoff, const int64_t* poff, const int64_t* rowoff,
-                          int32_t* skel_out, double* P_out, int32_t* rows_out) {
+// keep this level's skeletons, sampled rows and sizes in the per-node slots
+__global__ void k_level_save(LevelArgs A, int32_t* skel_fix, int32_t* rows_fix, int32_t* nc_all, int32_t* nr_all,
+                             int32_t* st_all) {
     const int64_t t = blockIdx.x;
     const int64_t h = (int64_t(1) << A.lvl) + t;
-    const int rk = A.rk[t], nc = A.ncand[t], nr = A.nrows[t];
-    for (int u = threadIdx.x; u < rk; u += blockDim.x) skel_out[skoff[h] + u] = A.cand[t * A.cmax + A.cp[t * A.cmax + u]];
-    for (int64_t e = threadIdx.x; e < static_cast<int64_t>(rk) * nc; e += blockDim.x)
-        P_out[poff[h] + e] = A.Pws[t * static_cast<int64_t>(A.s) * A.cmax + e];
-    for (int u = threadIdx.x; u < nr; u += blockDim.x) rows_out[rowoff[h] + u] = A.rows[t * A.rmax + u];
+    const int rk = A.rk[h], nr = A.nrows[t];
+    for (int u = threadIdx.x; u < rk; u += blockDim.x) skel_fix[h * A.s + u] = A.cand[t * A.cmax + A.cp[t * A.cmax + u]];
+    for (int u = threadIdx.x; u < nr; u += blockDim.x) rows_fix[h * A.rmax + u] = A.rows[t * A.rmax + u];
+    if (threadIdx.x == 0) {
+        nc_all[h] = A.ncand[t];
+        nr_all[h] = nr;
+        st_all[h] = A.status[t];
+    }
+}
+
+// move every node's skeletons, P and rows into the compact operator arrays
+__global__ void k_compact(const int32_t* skel_fix, const int32_t* rows_fix, const double* Pfix, const int32_t* rank,
+                          const int32_t* nc_all, const int32_t* nr_all, const int64_t* skoff, const int64_t* poff,
+                          const int64_t* rowoff, int s, int cmax, int rmax, int32_t* skel_out, double* P_out,
+                          int32_t* rows_out) {
+    const int64_t h = 2 + blockIdx.x;
+    const int rk = rank[h], nc = nc_all[h], nr = nr_all[h];
+    for (int u = threadIdx.x; u < rk; u += blockDim.x) skel_out[skoff[h] + u] = skel_fix[h * s + u];
+    const double* src = Pfix + h * s * cmax;
+    for (int64_t e = threadIdx.x; e < static_cast<int64_t>(rk) * nc; e += blockDim.x) P_out[poff[h] + e] = src[e];
+    for (int u = threadIdx.x; u < nr; u += blockDim.x) rows_out[rowoff[h] + u] = rows_fix[h * rmax + u];
 }
 
 // ---------------------------------------------------------------------------
@@ -1383,36 +1400,32 @@ static void skeletonize(Op& op, const Geo& G, hipStream_t s) {
     const Pts& P = G.P;
     const int64_t n = op.n;
     const int k = op.prm.knn_k, smax = op.prm.max_rank_s;
-    op.rank.assign(op.nnodes, 0);
-    op.ncand.assign(op.nnodes, 0);
-    op.nrows.assign(op.nnodes, 0);
-    op.skoff.assign(op.nnodes, 0);
-    op.poff.assign(op.nnodes, 0);
-    op.rowoff.assign(op.nnodes, 0);
     int64_t leafmax = 0;
     for (int64_t h = op.L; h < 2 * int64_t(op.L); ++h) leafmax = std::max(leafmax, op.size[h]);
     const int cmax = static_cast<int>(std::max<int64_t>(leafmax, 2 * static_cast<int64_t>(smax)));
     HDM_CHECK(cmax <= kMaxCand, HDM_EINVAL, "leaf size and 2 * max_rank_s must be <= 2048");
     const int rmax = 2 * smax;
     HDM_CHECK(rmax <= 1024, HDM_EINVAL, "max_rank_s must be <= 512");
-    // per-level outputs collected on the host side as offsets; data in growing device arrays
-    const int64_t maxnodes = op.L;        // widest level
+    const int64_t NN = op.nnodes;
+    // per-level workspaces, sized for the widest level
+    const int64_t maxnodes = op.L;
     DevBuf<int32_t> cand(maxnodes * cmax), ncand(maxnodes), rows(maxnodes * rmax), nrows(maxnodes), cp(maxnodes * cmax),
-        rk(maxnodes), status(maxnodes);
+        status(maxnodes);
     DevBuf<int32_t> uniq(static_cast<size_t>(maxnodes) * cmax * k);
-    DevBuf<double> B(static_cast<size_t>(maxnodes) * rmax * cmax), Pws(static_cast<size_t>(maxnodes) * smax * cmax);
-    // count and bitmap workspaces are per node of the widest level
+    DevBuf<double> B(static_cast<size_t>(maxnodes) * rmax * cmax);
     DevBuf<int32_t> cnt(static_cast<size_t>(maxnodes) * n);
     DevBuf<uint32_t> bits(static_cast<size_t>(maxnodes) * ((n + 31) / 32));
-    // compact outputs: upper bounds on skeletons/rows; P sized per level and concatenated
-    DevBuf<int32_t> skel_buf(static_cast<size_t>(op.nnodes) * smax + 1);
-    DevBuf<int32_t> rows_buf(static_cast<size_t>(op.nnodes) * rmax + 1);
-    std::vector<DevBuf<double>> Plevel(op.depth + 1);
-    std::vector<int64_t> Plevel_base(op.depth + 1, 0);
-    DevBuf<int32_t> d_rank(op.nnodes);
-    DevBuf<int64_t> d_skoff(op.nnodes), d_poff(op.nnodes), d_rowoff(op.nnodes), d_plocal(op.nnodes);
-    std::vector<int64_t> poff_local(op.nnodes, 0);
-    HDM_HIP(hipMemsetAsync(d_rank.get(), 0, d_rank.bytes(), s));
+    // per-node slots filled level by level (heap id h): skeletons, sampled rows, P, and
+    // rank | candidates | rows | row-fill status; compacted once at the end, so the
+    // levels run back to back without the host
+    DevBuf<int32_t> skel_fix(static_cast<size_t>(NN) * smax), rows_fix(static_cast<size_t>(NN) * rmax);
+    DevBuf<double> Pfix(static_cast<size_t>(NN) * smax * cmax);
+    DevBuf<int32_t> sizes(4 * static_cast<size_t>(NN));
+    int32_t* d_rank = sizes.get();
+    int32_t* d_nc = d_rank + NN;
+    int32_t* d_nr = d_rank + 2 * NN;
+    int32_t* d_st = d_rank + 3 * NN;
+    HDM_HIP(hipMemsetAsync(sizes.get(), 0, sizes.bytes(), s));
     // the ID's shared memory: Householder vector, column norms, then as many rows of B as fit
     size_t id_shmem = 0;
     int64_t id_lds = 0;
@@ -1431,8 +1444,7 @@ static void skeletonize(Op& op, const Geo& G, hipStream_t s) {
             HDM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pivoted_id),
                                         hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(id_shmem)));
     }
-    int64_t sk_next = 0, row_next = 0, p_next = 0;
-    std::vector<int32_t> h_rk(maxnodes), h_nc(maxnodes), h_nr(maxnodes), h_st(maxnodes);
+    std::vector<int32_t> h_nc(maxnodes), h_nr(maxnodes);
     for (int lvl = op.depth; lvl >= 1; --lvl) {
         const int nodes = 1 << lvl;
         HDM_HIP(hipMemsetAsync(cnt.get(), 0, sizeof(int32_t) * static_cast<size_t>(nodes) * n, s));
@@ -1452,9 +1464,8 @@ static void skeletonize(Op& op, const Geo& G, hipStream_t s) {
         A.perm = op.perm.get();
         A.iperm = op.iperm.get();
         A.kidx = op.knn_idx.get();
-        A.skel = skel_buf.get();
-        A.skoff = d_skoff.get();
-        A.rank = d_rank.get();
+        A.skel_fix = skel_fix.get();
+        A.rank = d_rank;
         A.cand = cand.get();
         A.ncand = ncand.get();
         A.cnt = cnt.get();
@@ -1464,14 +1475,16 @@ static void skeletonize(Op& op, const Geo& G, hipStream_t s) {
         A.nrows = nrows.get();
         A.B = B.get();
         A.cp = cp.get();
-        A.Pws = Pws.get();
-        A.rk = rk.get();
+        A.Pfix = Pfix.get();
+        A.rk = d_rank;
         A.status = status.get();
+        A.lds_b = id_lds;
         hipLaunchKernelGGL(k_cand, dim3(nodes), dim3(kBlock), 0, s, A);
         hipLaunchKernelGGL(k_row_count, dim3(ceil_div(static_cast<int64_t>(cmax) * k, kBlock), nodes), dim3(kBlock), 0, s,
                            A);
         hipLaunchKernelGGL(k_row_select, dim3(nodes), dim3(kBlock), 0, s, A);
         if (G.gram) {
+            // the Gram-form kernel blocks are planned on the host from the level's sizes
             ncand.download(h_nc.data(), nodes, s);
             nrows.download(h_nr.data(), nodes, s);
             HDM_HIP(hipStreamSynchronize(s));
@@ -1484,56 +1497,50 @@ static void skeletonize(Op& op, const Geo& G, hipStream_t s) {
             hipLaunchKernelGGL(k_block, dim3(ceil_div(static_cast<int64_t>(rmax) * cmax, kBlock), nodes), dim3(kBlock),
                                0, s, A, P);
         }
-        A.lds_b = id_lds;
         hipLaunchKernelGGL(k_pivoted_id, dim3(nodes), dim3(kBlock), id_shmem, s, A);
+        hipLaunchKernelGGL(k_level_save, dim3(nodes), dim3(kBlock), 0, s, A, skel_fix.get(), rows_fix.get(), d_nc, d_nr,
+                           d_st);
         check_launch("skeletonisation");
-        rk.download(h_rk.data(), nodes, s);
-        ncand.download(h_nc.data(), nodes, s);
-        nrows.download(h_nr.data(), nodes, s);
-        status.download(h_st.data(), nodes, s);
-        HDM_HIP(hipStreamSynchronize(s));
-        int64_t plev = 0;
-        for (int t = 0; t < nodes; ++t) {
-            HDM_CHECK(h_st[t] == 0, HDM_EINTERNAL, "row sampling did not terminate");
-            const int64_t h = nodes + t;
-            op.rank[h] = h_rk[t];
-            op.ncand[h] = h_nc[t];
-            op.nrows[h] = h_nr[t];
-            op.skoff[h] = sk_next;
-            sk_next += h_rk[t];
-            op.rowoff[h] = row_next;
-            row_next += h_nr[t];
-            op.poff[h] = p_next + plev;
-            plev += static_cast<int64_t>(h_rk[t]) * h_nc[t];
-        }
-        Plevel[lvl].alloc(plev > 0 ? plev : 1);
-        Plevel_base[lvl] = p_next;
-        // level-local P offsets for the compaction kernel
-        for (int t = 0; t < nodes; ++t) poff_local[nodes + t] = op.poff[nodes + t] - p_next;
-        p_next += plev;
-        d_rank.upload(op.rank.data(), op.nnodes, s);
-        d_skoff.upload(op.skoff.data(), op.nnodes, s);
-        d_plocal.upload(poff_local.data(), op.nnodes, s);
-        d_rowoff.upload(op.rowoff.data(), op.nnodes, s);
-        hipLaunchKernelGGL(k_compact, dim3(nodes), dim3(kBlock), 0, s, A, d_skoff.get(), d_plocal.get(), d_rowoff.get(),
-                           skel_buf.get(), Plevel[lvl].get(), rows_buf.get());
-        check_launch("compact");
-        HDM_HIP(hipStreamSynchronize(s));
     }
+    // sizes of every node, then offsets in level order (leaves first, heap order within a level)
+    std::vector<int32_t> hs(4 * static_cast<size_t>(NN));
+    sizes.download(hs.data(), hs.size(), s);
+    HDM_HIP(hipStreamSynchronize(s));
+    op.rank.assign(NN, 0);
+    op.ncand.assign(NN, 0);
+    op.nrows.assign(NN, 0);
+    op.skoff.assign(NN, 0);
+    op.poff.assign(NN, 0);
+    op.rowoff.assign(NN, 0);
+    int64_t sk_next = 0, row_next = 0, p_next = 0;
+    for (int lvl = op.depth; lvl >= 1; --lvl)
+        for (int64_t h = int64_t(1) << lvl; h < (int64_t(2) << lvl); ++h) {
+            HDM_CHECK(hs[3 * NN + h] == 0, HDM_EINTERNAL, "row sampling did not terminate");
+            op.rank[h] = hs[h];
+            op.ncand[h] = hs[NN + h];
+            op.nrows[h] = hs[2 * NN + h];
+            op.skoff[h] = sk_next;
+            sk_next += op.rank[h];
+            op.rowoff[h] = row_next;
+            row_next += op.nrows[h];
+            op.poff[h] = p_next;
+            p_next += static_cast<int64_t>(op.rank[h]) * op.ncand[h];
+        }
+    std::vector<int64_t> offs(3 * static_cast<size_t>(NN));
+    std::copy(op.skoff.begin(), op.skoff.end(), offs.begin());
+    std::copy(op.poff.begin(), op.poff.end(), offs.begin() + NN);
+    std::copy(op.rowoff.begin(), op.rowoff.end(), offs.begin() + 2 * NN);
+    DevBuf<int64_t> d_offs = to_device(offs, s);
     op.nskel = sk_next;
-    op.skel = std::move(skel_buf);
-    op.rows = std::move(rows_buf);
+    op.skel.alloc(sk_next + 1);
+    op.rows.alloc(row_next + 1);
     op.np = p_next;
     op.P64.alloc(p_next > 0 ? p_next : 1);
-    for (int lvl = 1; lvl <= op.depth; ++lvl) {
-        if (Plevel[lvl].n == 0) continue;
-        int64_t cntp = 0;
-        for (int64_t h = int64_t(1) << lvl; h < (int64_t(1) << (lvl + 1)); ++h)
-            cntp += static_cast<int64_t>(op.rank[h]) * op.ncand[h];
-        if (cntp)
-            HDM_HIP(hipMemcpyAsync(op.P64.get() + Plevel_base[lvl], Plevel[lvl].get(), sizeof(double) * cntp,
-                                   hipMemcpyDeviceToDevice, s));
-    }
+    if (NN > 2)
+        hipLaunchKernelGGL(k_compact, dim3(NN - 2), dim3(kBlock), 0, s, skel_fix.get(), rows_fix.get(), Pfix.get(),
+                           d_rank, d_nc, d_nr, d_offs.get(), d_offs.get() + NN, d_offs.get() + 2 * NN, smax, cmax, rmax,
+                           op.skel.get(), op.P64.get(), op.rows.get());
+    check_launch("compact");
     HDM_HIP(hipStreamSynchronize(s));
 }
 
