@@ -1396,7 +1396,17 @@ static void build_far_lists(Op& op) {
     op.far_off[op.nnodes] = static_cast<int32_t>(op.far_idx.size());
 }
 
-static void skeletonize(Op& op, const Geo& G, hipStream_t s) {
+// Buffers of a skeletonisation in flight: the level loop is enqueued by
+// skeletonize_levels and completed (sizes downloaded, outputs compacted) by
+// skeletonize_finish, so the host can do other work while the levels run.
+struct SkelRun {
+    int cmax = 0, rmax = 0;
+    DevBuf<int32_t> cand, ncand, rows, nrows, cp, status, uniq, cnt, skel_fix, rows_fix, sizes;
+    DevBuf<uint32_t> bits;
+    DevBuf<double> B, Pfix;
+};
+
+static void skeletonize_levels(Op& op, const Geo& G, hipStream_t s, SkelRun& R) {
     const Pts& P = G.P;
     const int64_t n = op.n;
     const int k = op.prm.knn_k, smax = op.prm.max_rank_s;
@@ -1406,21 +1416,42 @@ static void skeletonize(Op& op, const Geo& G, hipStream_t s) {
     HDM_CHECK(cmax <= kMaxCand, HDM_EINVAL, "leaf size and 2 * max_rank_s must be <= 2048");
     const int rmax = 2 * smax;
     HDM_CHECK(rmax <= 1024, HDM_EINVAL, "max_rank_s must be <= 512");
+    R.cmax = cmax;
+    R.rmax = rmax;
     const int64_t NN = op.nnodes;
     // per-level workspaces, sized for the widest level
     const int64_t maxnodes = op.L;
-    DevBuf<int32_t> cand(maxnodes * cmax), ncand(maxnodes), rows(maxnodes * rmax), nrows(maxnodes), cp(maxnodes * cmax),
-        status(maxnodes);
-    DevBuf<int32_t> uniq(static_cast<size_t>(maxnodes) * cmax * k);
-    DevBuf<double> B(static_cast<size_t>(maxnodes) * rmax * cmax);
-    DevBuf<int32_t> cnt(static_cast<size_t>(maxnodes) * n);
-    DevBuf<uint32_t> bits(static_cast<size_t>(maxnodes) * ((n + 31) / 32));
+    R.cand.alloc(maxnodes * cmax);
+    R.ncand.alloc(maxnodes);
+    R.rows.alloc(maxnodes * rmax);
+    R.nrows.alloc(maxnodes);
+    R.cp.alloc(maxnodes * cmax);
+    R.status.alloc(maxnodes);
+    R.uniq.alloc(static_cast<size_t>(maxnodes) * cmax * k);
+    R.B.alloc(static_cast<size_t>(maxnodes) * rmax * cmax);
+    R.cnt.alloc(static_cast<size_t>(maxnodes) * n);
+    R.bits.alloc(static_cast<size_t>(maxnodes) * ((n + 31) / 32));
     // per-node slots filled level by level (heap id h): skeletons, sampled rows, P, and
     // rank | candidates | rows | row-fill status; compacted once at the end, so the
     // levels run back to back without the host
-    DevBuf<int32_t> skel_fix(static_cast<size_t>(NN) * smax), rows_fix(static_cast<size_t>(NN) * rmax);
-    DevBuf<double> Pfix(static_cast<size_t>(NN) * smax * cmax);
-    DevBuf<int32_t> sizes(4 * static_cast<size_t>(NN));
+    R.skel_fix.alloc(static_cast<size_t>(NN) * smax);
+    R.rows_fix.alloc(static_cast<size_t>(NN) * rmax);
+    R.Pfix.alloc(static_cast<size_t>(NN) * smax * cmax);
+    R.sizes.alloc(4 * static_cast<size_t>(NN));
+    auto& cand = R.cand;
+    auto& ncand = R.ncand;
+    auto& rows = R.rows;
+    auto& nrows = R.nrows;
+    auto& cp = R.cp;
+    auto& status = R.status;
+    auto& uniq = R.uniq;
+    auto& B = R.B;
+    auto& cnt = R.cnt;
+    auto& bits = R.bits;
+    auto& skel_fix = R.skel_fix;
+    auto& rows_fix = R.rows_fix;
+    auto& Pfix = R.Pfix;
+    auto& sizes = R.sizes;
     int32_t* d_rank = sizes.get();
     int32_t* d_nc = d_rank + NN;
     int32_t* d_nr = d_rank + 2 * NN;
@@ -1502,9 +1533,17 @@ static void skeletonize(Op& op, const Geo& G, hipStream_t s) {
                            d_st);
         check_launch("skeletonisation");
     }
+}
+
+static void skeletonize_finish(Op& op, hipStream_t s, SkelRun& R) {
+    const int64_t NN = op.nnodes;
+    const int smax = op.prm.max_rank_s;
+    int32_t* d_rank = R.sizes.get();
+    int32_t* d_nc = d_rank + NN;
+    int32_t* d_nr = d_rank + 2 * NN;
     // sizes of every node, then offsets in level order (leaves first, heap order within a level)
     std::vector<int32_t> hs(4 * static_cast<size_t>(NN));
-    sizes.download(hs.data(), hs.size(), s);
+    R.sizes.download(hs.data(), hs.size(), s);
     HDM_HIP(hipStreamSynchronize(s));
     op.rank.assign(NN, 0);
     op.ncand.assign(NN, 0);
@@ -1537,9 +1576,9 @@ static void skeletonize(Op& op, const Geo& G, hipStream_t s) {
     op.np = p_next;
     op.P64.alloc(p_next > 0 ? p_next : 1);
     if (NN > 2)
-        hipLaunchKernelGGL(k_compact, dim3(NN - 2), dim3(kBlock), 0, s, skel_fix.get(), rows_fix.get(), Pfix.get(),
-                           d_rank, d_nc, d_nr, d_offs.get(), d_offs.get() + NN, d_offs.get() + 2 * NN, smax, cmax, rmax,
-                           op.skel.get(), op.P64.get(), op.rows.get());
+        hipLaunchKernelGGL(k_compact, dim3(NN - 2), dim3(kBlock), 0, s, R.skel_fix.get(), R.rows_fix.get(),
+                           R.Pfix.get(), d_rank, d_nc, d_nr, d_offs.get(), d_offs.get() + NN, d_offs.get() + 2 * NN, smax,
+                           R.cmax, R.rmax, op.skel.get(), op.P64.get(), op.rows.get());
     check_launch("compact");
     HDM_HIP(hipStreamSynchronize(s));
 }
@@ -1744,28 +1783,32 @@ void compress_operator(Op& op, const void* X, int x_on_device, hipStream_t s) {
                            static_cast<int>(leafmax), op.knn_idx.get(), op.knn_d2.get());
         check_launch("knn leaf");
     }
+    // neighbour votes between leaves on the side stream (after the ball tree there
+    // and the neighbours on s); the skeletonisation levels are enqueued on s, and
+    // the host builds the interaction lists while they run
+    HDM_HIP(hipEventRecord(op.lane.fork, s));
     HDM_HIP(hipStreamWaitEvent(s, op.lane.join, 0));   // the ball tree and its inverse permutation
-    // lists
+    HDM_HIP(hipStreamWaitEvent(side, op.lane.fork, 0));
+    DevBuf<int32_t> votes(static_cast<size_t>(op.L) * op.L);
+    HDM_HIP(hipMemsetAsync(votes.get(), 0, votes.bytes(), side));
+    hipLaunchKernelGGL(k_votes, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, side, n, op.depth, op.d_start.get(),
+                       op.perm.get(), op.iperm.get(), op.knn_idx.get(), k, votes.get());
+    check_launch("votes");
+    SkelRun skr;
+    skeletonize_levels(op, G, s, skr);
     {
-        DevBuf<int32_t> votes(static_cast<size_t>(op.L) * op.L);
-        HDM_HIP(hipMemsetAsync(votes.get(), 0, votes.bytes(), s));
-        hipLaunchKernelGGL(k_votes, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, s, n, op.depth, op.d_start.get(),
-                           op.perm.get(), op.iperm.get(), op.knn_idx.get(), k, votes.get());
-        check_launch("votes");
         std::vector<int32_t> hv(static_cast<size_t>(op.L) * op.L);
-        votes.download(hv.data(), hv.size(), s);
-        HDM_HIP(hipStreamSynchronize(s));
+        votes.download(hv.data(), hv.size(), side);
+        HDM_HIP(hipStreamSynchronize(side));
         build_near_lists(op, hv);
         build_far_lists(op);
     }
-    // near tiles on the side stream while the skeletons are computed on s
+    // near tiles and their evaluation-precision copy on the side stream
     DevBuf<NearPair> pairs_dev;
-    HDM_HIP(hipEventRecord(op.lane.fork, s));
-    HDM_HIP(hipStreamWaitEvent(side, op.lane.fork, 0));
     build_near_tiles(op, G, side, pairs_dev);
-    convert_near_tiles(op, side);   // evaluation-precision copy, also on the side stream
+    convert_near_tiles(op, side);
     HDM_HIP(hipEventRecord(op.lane.join, side));
-    skeletonize(op, G, s);
+    skeletonize_finish(op, s, skr);
     HDM_HIP(hipStreamWaitEvent(s, op.lane.join, 0));
     build_far_tiles(op, G, s);
     HDM_HIP(hipStreamSynchronize(side));
