@@ -123,6 +123,9 @@ const char *hdm_version(void);
 /* enable = 1 clears the per-phase totals and starts recording a pair of HIP
  * events around every phase launched through this context; enable = 0 stops. */
 hdm_status hdm_ctx_profile(hdm_ctx ctx, int enable);
+/* As hdm_ctx_profile(ctx, 1), but only the phases p with bit (1u << p) set in
+ * phase_mask are timed (the others run without events); phase_mask = 0 stops. */
+hdm_status hdm_ctx_profile_phases(hdm_ctx ctx, uint32_t phase_mask);
 /* Synchronises the recorded events and returns the per-phase totals since the
  * last hdm_ctx_profile(ctx, 1). */
 hdm_status hdm_ctx_phase_times(hdm_ctx ctx, hdm_phase_times_t *out);

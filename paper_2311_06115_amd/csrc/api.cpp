@@ -228,18 +228,21 @@ hdm_status hdm_ctx_graphs(hdm_ctx ctx, int enable) {
     });
 }
 
-hdm_status hdm_ctx_profile(hdm_ctx ctx, int enable) {
+hdm_status hdm_ctx_profile_phases(hdm_ctx ctx, uint32_t phase_mask) {
     return guarded([&] {
         HDM_CHECK(ctx, HDM_EINVAL, "NULL context");
         set_device(ctx->device);
-        if (enable) {
+        if (phase_mask) {
             HDM_HIP(hipDeviceSynchronize());
             ctx->prof.reset();
         }
-        ctx->prof.on = enable != 0;
+        ctx->prof.mask = phase_mask;
+        ctx->prof.on = phase_mask != 0;
         return HDM_OK;
     });
 }
+
+hdm_status hdm_ctx_profile(hdm_ctx ctx, int enable) { return hdm_ctx_profile_phases(ctx, enable ? ~0u : 0u); }
 
 hdm_status hdm_ctx_phase_times(hdm_ctx ctx, hdm_phase_times_t* out) {
     return guarded([&] {

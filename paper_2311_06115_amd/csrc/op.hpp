@@ -17,6 +17,8 @@ namespace hdm {
 // HIP-event pairs around phase launches, accumulated per phase.
 struct Profiler {
     bool on = false;
+    uint32_t mask = ~0u;                         // phases recorded while on (bit 1 << hdm_phase)
+    bool records(int phase) const { return on && ((mask >> phase) & 1u); }
     std::mutex mu;                               // several host threads may record
     std::vector<hipEvent_t> pool;
     size_t used = 0;
@@ -44,7 +46,7 @@ struct Ctx {
 struct KernelEvents {
     hipEvent_t start = nullptr, stop = nullptr;
     KernelEvents(Ctx* c, int phase) {
-        if (c && c->prof.on) c->prof.kernel_events(phase, start, stop);
+        if (c && c->prof.records(phase)) c->prof.kernel_events(phase, start, stop);
     }
 };
 
@@ -53,7 +55,7 @@ struct PhaseScope {
     Profiler* p;
     hipStream_t s;
     size_t slot = 0;
-    PhaseScope(Ctx* c, int phase, hipStream_t st) : p(c && c->prof.on ? &c->prof : nullptr), s(st) {
+    PhaseScope(Ctx* c, int phase, hipStream_t st) : p(c && c->prof.records(phase) ? &c->prof : nullptr), s(st) {
         if (p) p->begin(phase, s, slot);
     }
     ~PhaseScope() {

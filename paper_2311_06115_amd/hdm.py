@@ -104,6 +104,7 @@ def lib():
         "hdm_ctx_profile": (st, [vp, C.c_int]),
         "hdm_ctx_phase_times": (st, [vp, C.POINTER(PhaseTimes)]),
         "hdm_ctx_graphs": (st, [vp, C.c_int]),
+        "hdm_ctx_profile_phases": (st, [vp, C.c_uint32]),
         "hdm_compress": (st, [vp, vp, C.c_int, C.POINTER(Params), vp, C.POINTER(vp)]),
         "hdm_op_destroy": (st, [vp]),
         "hdm_op_stats": (st, [vp, C.POINTER(OpStats)]),
@@ -156,8 +157,15 @@ class Context:
         check(lib().hdm_ctx_create(device, budget_bytes, C.byref(self.h)))
         self.device = device
 
-    def profile(self, enable: bool):
-        check(lib().hdm_ctx_profile(self.h, int(enable)))
+    def profile(self, enable: bool, phases=None):
+        """Time every phase (or only the named ones, e.g. phases=["l2l"]) until profile(False)."""
+        if phases is None or not enable:
+            check(lib().hdm_ctx_profile(self.h, int(enable)))
+        else:
+            mask = 0
+            for name in phases:
+                mask |= 1 << PHASES.index(name)
+            check(lib().hdm_ctx_profile_phases(self.h, mask))
 
     def graphs(self, enable: bool):
         """Single-operator products replay a HIP graph (True, the default) or launch eagerly."""

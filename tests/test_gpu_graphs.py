@@ -104,3 +104,19 @@ def test_graph_eigs_equal_eager():
     ctx.graphs(True)
     evb1, _, _, _ = op.eigs(8, tol=1e-10, block=4, seed=3, vectors=False)
     assert np.array_equal(evb0, evb1)
+
+
+def test_profiling_one_phase_only():
+    ctx, op, n = _op("f32", None)
+    x = torch.from_numpy(np.random.default_rng(8).standard_normal(n)).cuda()
+    ctx.graphs(False)
+    want = op.matvec(x, normalised=True).cpu().numpy()
+    ctx.graphs(True)
+    ctx.profile(True, phases=["l2l"])
+    for _ in range(2):
+        assert np.array_equal(op.matvec(x, normalised=True).cpu().numpy(), want)
+    ph = ctx.phase_times()
+    ctx.profile(False)
+    assert ph["l2l"][0] == 2 and ph["l2l"][1] > 0.0
+    for name in ("prep", "n2s", "s2s", "combine", "ortho", "compress"):
+        assert ph[name][0] == 0, name
