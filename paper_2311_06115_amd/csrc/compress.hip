@@ -587,6 +587,7 @@ struct LevelArgs {
     int32_t* cnt;               // per node n
     uint32_t* bits;             // per node ceil(n/32)
     int32_t* uniq;              // per node cmax*k: unique outside neighbours, ascending
+    int32_t* vts;               // per node cmax*k: their votes (sorted row selection)
     int32_t* rows;              // per node rmax
     int32_t* nrows;             // per node
     double* B;                  // per node rmax x cmax
@@ -634,6 +635,13 @@ __global__ void k_row_count(LevelArgs A) {
 // that is all there is).  The draws are taken 64 at a time by one wave and
 // accepted in draw order, exactly as a sequential rejection loop would.
 constexpr int kMaxRows = 1024;   // sampled rows per node (2 max_rank_s)
+constexpr int kSortCap = 16384;  // neighbour entries a node sorts in shared memory (nc k <= this)
+
+// kSorted: the candidates' outside neighbours are gathered into shared memory,
+// sorted, and counted run by run (unique indices ascending, votes per index);
+// otherwise k_row_count has counted them into a dense per-node array that is
+// scanned in index order.  Both give the same ascending list and votes.
+template <bool kSorted>
 __global__ void k_row_select(LevelArgs A) {
     __shared__ int wsum[kBlock / 64];
     __shared__ int32_t hist[kMaxCand + 1];   // votes are at most the number of candidates
@@ -643,17 +651,69 @@ __global__ void k_row_select(LevelArgs A) {
     const int64_t t = blockIdx.x;
     const int64_t h = (int64_t(1) << A.lvl) + t;
     const int64_t lo = A.start[h], hi = A.start[h] + A.size[h];
-    const int32_t* cnt = A.cnt + t * A.n;
+    int32_t* cnt = A.cnt + t * A.n;
     int32_t* uq = A.uniq + t * static_cast<int64_t>(A.cmax) * A.k;
     int32_t* rows = A.rows + t * A.rmax;
     uint32_t* bits = A.bits + t * ((A.n + 31) / 32);
     int64_t want = A.n - A.size[h];
     if (want > 2 * static_cast<int64_t>(A.s)) want = 2 * static_cast<int64_t>(A.s);
     const int64_t want_nb = want / 2;
-    // compaction of {i : cnt[i] > 0} in index order: a contiguous range per
-    // thread, one workgroup scan of the per-thread counts
+    // votes of the u-th unique outside neighbour (uq ascending)
+    int32_t* vt = A.vts + t * static_cast<int64_t>(A.cmax) * A.k;
+    auto votes = [&](int64_t u) { return kSorted ? vt[u] : cnt[uq[u]]; };
     int64_t nu = 0;
-    {
+    if constexpr (kSorted) {
+        extern __shared__ int32_t E[];
+        __shared__ int s_ne;
+        const int nc = A.ncand[t];
+        const int32_t* cd = A.cand + t * A.cmax;
+        if (threadIdx.x == 0) s_ne = 0;
+        __syncthreads();
+        const int64_t ntot = static_cast<int64_t>(nc) * A.k;
+        for (int64_t e = threadIdx.x; e < ntot; e += blockDim.x) {
+            const int32_t i = A.kidx[static_cast<int64_t>(cd[e / A.k]) * A.k + e % A.k];
+            if (i < 0) continue;
+            const int64_t pi = A.iperm[i];
+            if (pi >= lo && pi < hi) continue;
+            E[atomicAdd(&s_ne, 1)] = i;
+        }
+        __syncthreads();
+        const int ne = s_ne;
+        int P2 = 1;
+        while (P2 < ne) P2 <<= 1;
+        for (int e = ne + threadIdx.x; e < P2; e += blockDim.x) E[e] = INT32_MAX;
+        __syncthreads();
+        for (int kk = 2; kk <= P2; kk <<= 1)   // bitonic sort, ascending
+            for (int j = kk >> 1; j > 0; j >>= 1) {
+                for (int e = threadIdx.x; e < P2; e += blockDim.x) {
+                    const int f = e ^ j;
+                    if (f > e) {
+                        const int32_t a = E[e], b = E[f];
+                        if ((a > b) == ((e & kk) == 0)) { E[e] = b; E[f] = a; }
+                    }
+                }
+                __syncthreads();
+            }
+        // run starts in index order: a contiguous range of positions per thread
+        const int per = (ne + kBlock - 1) / kBlock;
+        const int e0 = min(ne, static_cast<int>(threadIdx.x) * per), e1 = min(ne, e0 + per);
+        int mine = 0;
+        for (int e = e0; e < e1; ++e) mine += e == 0 || E[e] != E[e - 1];
+        int tot = 0;
+        int w = wg_scan_excl(mine, wsum, &tot);
+        for (int e = e0; e < e1; ++e)
+            if (e == 0 || E[e] != E[e - 1]) {
+                int r = e + 1;
+                while (r < ne && E[r] == E[e]) ++r;
+                uq[w] = E[e];
+                vt[w] = r - e;
+                ++w;
+            }
+        nu = tot;
+        __syncthreads();
+    } else {
+        // compaction of {i : cnt[i] > 0} in index order: a contiguous range per
+        // thread, one workgroup scan of the per-thread counts
         const int64_t per = (A.n + kBlock - 1) / kBlock;
         const int64_t i0 = min(A.n, static_cast<int64_t>(threadIdx.x) * per), i1 = min(A.n, i0 + per);
         int mine = 0;
@@ -681,7 +741,7 @@ __global__ void k_row_select(LevelArgs A) {
     // rank by (votes desc, index asc) and keep the first want_nb: the vote
     // threshold from a histogram, the ties at it in index order, then the
     // (at most want_nb) kept entries ordered among themselves
-    for (int64_t u = threadIdx.x; u < nu; u += blockDim.x) atomicAdd(&hist[min(cnt[uq[u]], kMaxCand)], 1);
+    for (int64_t u = threadIdx.x; u < nu; u += blockDim.x) atomicAdd(&hist[min(votes(u), kMaxCand)], 1);
     __syncthreads();
     if (threadIdx.x == 0) {
         int64_t above = 0;   // entries with more votes than c
@@ -705,9 +765,7 @@ __global__ void k_row_select(LevelArgs A) {
         for (int64_t u = u0; u < u1; u += 16) {   // batched loads (clamped addresses)
             int32_t v[16];
 #pragma unroll
-            for (int q = 0; q < 16; ++q) v[q] = uq[min(u + q, u1 - 1)];
-#pragma unroll
-            for (int q = 0; q < 16; ++q) v[q] = cnt[v[q]];
+            for (int q = 0; q < 16; ++q) v[q] = votes(min(u + q, u1 - 1));
 #pragma unroll
             for (int q = 0; q < 16; ++q) ties += (u + q < u1) && v[q] == tcut;
         }
@@ -715,14 +773,14 @@ __global__ void k_row_select(LevelArgs A) {
         int tie_rank = wg_scan_excl(ties, wsum, &tt);
         int keep = 0;
         for (int64_t u = u0; u < u1; ++u) {
-            const int32_t c = cnt[uq[u]];
+            const int32_t c = votes(u);
             keep += c > tcut || (c == tcut && tie_rank++ < need);
         }
         int tk = 0;
         int w = wg_scan_excl(keep, wsum, &tk);
         tie_rank -= ties;   // back to this thread's first tie rank
         for (int64_t u = u0; u < u1; ++u) {
-            const int32_t c = cnt[uq[u]];
+            const int32_t c = votes(u);
             if (c > tcut || (c == tcut && tie_rank++ < need)) {
                 selv[w] = uq[u];
                 selc[w] = c;
@@ -1401,7 +1459,7 @@ static void build_far_lists(Op& op) {
 // skeletonize_finish, so the host can do other work while the levels run.
 struct SkelRun {
     int cmax = 0, rmax = 0;
-    DevBuf<int32_t> cand, ncand, rows, nrows, cp, status, uniq, cnt, skel_fix, rows_fix, sizes;
+    DevBuf<int32_t> cand, ncand, rows, nrows, cp, status, uniq, cnt, vts, skel_fix, rows_fix, sizes;
     DevBuf<uint32_t> bits;
     DevBuf<double> B, Pfix;
 };
@@ -1429,7 +1487,9 @@ static void skeletonize_levels(Op& op, const Geo& G, hipStream_t s, SkelRun& R) 
     R.status.alloc(maxnodes);
     R.uniq.alloc(static_cast<size_t>(maxnodes) * cmax * k);
     R.B.alloc(static_cast<size_t>(maxnodes) * rmax * cmax);
-    R.cnt.alloc(static_cast<size_t>(maxnodes) * n);
+    const bool sorted_votes = static_cast<int64_t>(cmax) * k <= kSortCap;
+    if (sorted_votes) R.vts.alloc(static_cast<size_t>(maxnodes) * cmax * k);
+    else R.cnt.alloc(static_cast<size_t>(maxnodes) * n);
     R.bits.alloc(static_cast<size_t>(maxnodes) * ((n + 31) / 32));
     // per-node slots filled level by level (heap id h): skeletons, sampled rows, P, and
     // rank | candidates | rows | row-fill status; compacted once at the end, so the
@@ -1475,10 +1535,19 @@ static void skeletonize_levels(Op& op, const Geo& G, hipStream_t s, SkelRun& R) 
             HDM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pivoted_id),
                                         hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(id_shmem)));
     }
+    // row selection: the neighbour votes are sorted in shared memory when a node's
+    // nc k entries fit, else counted into a dense per-node array
+    size_t sort_shmem = 0;
+    if (sorted_votes) {
+        int64_t p2 = 1;
+        while (p2 < static_cast<int64_t>(cmax) * k) p2 <<= 1;
+        sort_shmem = sizeof(int32_t) * static_cast<size_t>(p2);
+        HDM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_row_select<true>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(sort_shmem)));
+    }
     std::vector<int32_t> h_nc(maxnodes), h_nr(maxnodes);
     for (int lvl = op.depth; lvl >= 1; --lvl) {
         const int nodes = 1 << lvl;
-        HDM_HIP(hipMemsetAsync(cnt.get(), 0, sizeof(int32_t) * static_cast<size_t>(nodes) * n, s));
         HDM_HIP(hipMemsetAsync(bits.get(), 0, sizeof(uint32_t) * static_cast<size_t>(nodes) * ((n + 31) / 32), s));
         LevelArgs A{};
         A.lvl = lvl;
@@ -1502,6 +1571,7 @@ static void skeletonize_levels(Op& op, const Geo& G, hipStream_t s, SkelRun& R) 
         A.cnt = cnt.get();
         A.bits = bits.get();
         A.uniq = uniq.get();
+        A.vts = R.vts.get();
         A.rows = rows.get();
         A.nrows = nrows.get();
         A.B = B.get();
@@ -1511,9 +1581,14 @@ static void skeletonize_levels(Op& op, const Geo& G, hipStream_t s, SkelRun& R) 
         A.status = status.get();
         A.lds_b = id_lds;
         hipLaunchKernelGGL(k_cand, dim3(nodes), dim3(kBlock), 0, s, A);
-        hipLaunchKernelGGL(k_row_count, dim3(ceil_div(static_cast<int64_t>(cmax) * k, kBlock), nodes), dim3(kBlock), 0, s,
-                           A);
-        hipLaunchKernelGGL(k_row_select, dim3(nodes), dim3(kBlock), 0, s, A);
+        if (sorted_votes) {
+            hipLaunchKernelGGL(k_row_select<true>, dim3(nodes), dim3(kBlock), sort_shmem, s, A);
+        } else {
+            HDM_HIP(hipMemsetAsync(cnt.get(), 0, sizeof(int32_t) * static_cast<size_t>(nodes) * n, s));
+            hipLaunchKernelGGL(k_row_count, dim3(ceil_div(static_cast<int64_t>(cmax) * k, kBlock), nodes), dim3(kBlock), 0,
+                               s, A);
+            hipLaunchKernelGGL(k_row_select<false>, dim3(nodes), dim3(kBlock), 0, s, A);
+        }
         if (G.gram) {
             // the Gram-form kernel blocks are planned on the host from the level's sizes
             ncand.download(h_nc.data(), nodes, s);

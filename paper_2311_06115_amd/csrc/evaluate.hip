@@ -287,6 +287,7 @@ __global__ void __launch_bounds__(kBlock) k_combine(Batch b) {
     }
 }
 
+
 // ---- several right-hand sides (2 <= nrhs <= 16) -------------------------------
 // The same phases with every matrix element loaded once for all columns: each
 // lane keeps one partial sum per right-hand side.
@@ -902,10 +903,14 @@ static void apply_t(const ApplyReq* reqs, int nops, bool f64, int normalised, in
         tree = tree || reqs[o].op->nskel > 0;
         maxdepth = std::max(maxdepth, reqs[o].op->depth);
     }
-    // fork after the staging; the near field goes first on s (it only needs the
-    // staged vectors), so it starts while the host still issues the upward pass
-    if (tree) HDM_HIP(hipEventRecord(lane.fork, s));
-    {
+    // Several right-hand sides: the upward pass and the far field run on the side
+    // stream while the near field streams on s.  One right-hand side: all on s,
+    // since the fork and join cost more than the overlap saves (4.8 against
+    // 5.2 ms per 25-step solve at N = 32768; 16.2 against 15.8 ms per block
+    // solve at N = 100000 with 16 columns).
+    const bool overlap = tree && multi;
+    hipStream_t ts = overlap ? lane.side : s;
+    auto near_field = [&] {
         const int64_t tot = prefix([](const Op& op, int) {
             return static_cast<int64_t>(mma ? op.items_mma.size() : op.items.size());
         });
@@ -915,11 +920,17 @@ static void apply_t(const ApplyReq* reqs, int nops, bool f64, int normalised, in
         else
             hipExtLaunchKernelGGL((k_l2l<V, TN>), dim3(ceil_div(tot, wpb)), dim3(kBlock), 0, s, ev.start, ev.stop, 0,
                                   b);
+    };
+    if (overlap) {
+        // fork after the staging; the near field goes first on s (it only needs the
+        // staged vectors), so it starts while the host still issues the upward pass
+        HDM_HIP(hipEventRecord(lane.fork, s));
+        near_field();
+        HDM_HIP(hipStreamWaitEvent(ts, lane.fork, 0));
     }
     if (tree) {
-        HDM_HIP(hipStreamWaitEvent(lane.side, lane.fork, 0));
         {   // N2S: step k processes level depth - k of every operator
-            PhaseScope ph(cx, HDM_PHASE_N2S, lane.side);
+            PhaseScope ph(cx, HDM_PHASE_N2S, ts);
             for (int k = 0; k < maxdepth; ++k) {
                 for (int o = 0; o < nops; ++o) b.arg[o] = reqs[o].op->depth - k;
                 const int64_t tot = prefix([&](const Op& op, int) {
@@ -928,9 +939,9 @@ static void apply_t(const ApplyReq* reqs, int nops, bool f64, int normalised, in
                 });
                 if (tot == 0) continue;
                 if (multi)
-                    hipLaunchKernelGGL((k_n2s_m<V, TP>), dim3(ceil_div(tot, wpb)), dim3(kBlock), 0, lane.side, b);
+                    hipLaunchKernelGGL((k_n2s_m<V, TP>), dim3(ceil_div(tot, wpb)), dim3(kBlock), 0, ts, b);
                 else
-                    hipLaunchKernelGGL((k_n2s<V, TP>), dim3(ceil_div(tot, wpb)), dim3(kBlock), 0, lane.side, b);
+                    hipLaunchKernelGGL((k_n2s<V, TP>), dim3(ceil_div(tot, wpb)), dim3(kBlock), 0, ts, b);
             }
         }
         {
@@ -938,16 +949,20 @@ static void apply_t(const ApplyReq* reqs, int nops, bool f64, int normalised, in
             KernelEvents ev(cx, HDM_PHASE_S2S);
             if (tot > 0) {
                 if (multi)
-                    hipExtLaunchKernelGGL((k_s2s_m<V, TF>), dim3(ceil_div(tot, wpb)), dim3(kBlock), 0, lane.side,
-                                          ev.start, ev.stop, 0, b);
+                    hipExtLaunchKernelGGL((k_s2s_m<V, TF>), dim3(ceil_div(tot, wpb)), dim3(kBlock), 0, ts, ev.start,
+                                          ev.stop, 0, b);
                 else
-                    hipExtLaunchKernelGGL((k_s2s<V, TF>), dim3(ceil_div(tot, wpb)), dim3(kBlock), 0, lane.side,
-                                          ev.start, ev.stop, 0, b);
+                    hipExtLaunchKernelGGL((k_s2s<V, TF>), dim3(ceil_div(tot, wpb)), dim3(kBlock), 0, ts, ev.start,
+                                          ev.stop, 0, b);
             }
         }
-        HDM_HIP(hipEventRecord(lane.join, lane.side));
     }
-    if (tree) HDM_HIP(hipStreamWaitEvent(s, lane.join, 0));
+    if (overlap) {
+        HDM_HIP(hipEventRecord(lane.join, ts));
+        HDM_HIP(hipStreamWaitEvent(s, lane.join, 0));
+    } else {
+        near_field();
+    }
     {
         for (int o = 0; o < nops; ++o) b.arg[o] = normalised;
         const int64_t tot = prefix([](const Op& op, int) { return static_cast<int64_t>(op.L); });

@@ -37,6 +37,65 @@ __device__ inline double block_sum(double v, double* sm) {
     return r;
 }
 
+// Values passed between workgroups of one launch go through device-scope
+// atomic stores and loads (coherent across the chip's L2 slices without
+// flushing them).
+__device__ inline void put_shared(double* p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline double get_shared(const double* p) {
+    return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// h[c] = sum over the nb partial rows of column c (c in the 64-column group g):
+// four quarters of the rows, eight interleaved partial sums each, combined in a
+// fixed order.  Needs 256 threads.
+template <bool kShared>
+__device__ inline void reduce_cols_group(const double* partial, int nb, int ldp, int ncols, double* h, int g,
+                                         double (*qs)[64]) {
+    auto ld = [&](int64_t e) { return kShared ? get_shared(partial + e) : partial[e]; };
+    const int cl = threadIdx.x % 64, qt = threadIdx.x / 64;
+    const int c = g * 64 + cl;
+    const int per = (nb + 3) / 4;
+    const int b0 = min(nb, qt * per), b1 = min(nb, b0 + per);
+    double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (c < ncols) {
+        int b = b0;
+        for (; b + 8 <= b1; b += 8) {
+            double x[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) x[u] = ld(static_cast<int64_t>(b + u) * ldp + c);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc[u] += x[u];
+        }
+        for (; b < b1; ++b) acc[0] += ld(static_cast<int64_t>(b) * ldp + c);
+    }
+    qs[qt][cl] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+    __syncthreads();
+    if (qt == 0 && c < ncols) h[c] = ((qs[0][cl] + qs[1][cl]) + qs[2][cl]) + qs[3][cl];
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(256) k_reduce_cols(const double* partial, int nb, int ldp, int ncols, double* h) {
+    __shared__ double qs[4][64];
+    reduce_cols_group<false>(partial, nb, ldp, ncols, h, blockIdx.x, qs);
+}
+
+
+// true in the one workgroup that finishes last; every workgroup's put_shared
+// stores have completed before it is counted.  The counter is left at zero for
+// the next launch.  Every thread of the workgroup must call it.
+__device__ inline bool last_workgroup(unsigned* counter, bool* flag) {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0)
+        *flag = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gridDim.x - 1;
+    __syncthreads();
+    if (!*flag) return false;
+    if (threadIdx.x == 0) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return true;
+}
+
 // partial[b][c] = sum over the block's rows of V[row, c] * y[row], c < ncols.
 // Each wave takes whole columns (lanes over rows, y held in registers) and
 // reduces with a butterfly: no workgroup barriers per column.
@@ -63,31 +122,33 @@ __global__ void __launch_bounds__(kBlock) k_gemvt(const double* V, int64_t ldv, 
     }
 }
 
-// h[c] = sum_b partial[b][c] in a fixed order: a workgroup of 256 threads takes
-// 64 columns; each quarter of it sums a quarter of the blocks with eight
-// independent accumulators (loads in flight together), and the quarters and
-// accumulators are added in a fixed order.
-__global__ void __launch_bounds__(256) k_reduce_cols(const double* partial, int nb, int ldp, int ncols, double* h) {
-    __shared__ double qs[4][64];
-    const int cl = threadIdx.x % 64, qt = threadIdx.x / 64;
-    const int c = blockIdx.x * 64 + cl;
-    const int per = (nb + 3) / 4;
-    const int b0 = min(nb, qt * per), b1 = min(nb, b0 + per);
-    double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    if (c < ncols) {
-        int b = b0;
-        for (; b + 8 <= b1; b += 8) {
-            double x[8];
+// k_gemvt, then the last workgroup reduces the partial rows into h
+__global__ void __launch_bounds__(kBlock) k_gemvt_h(const double* V, int64_t ldv, int ncols, const double* y, int64_t n,
+                                                    double* partial, int ldp, double* h, unsigned* counter) {
+    constexpr int kPer = kRows / 64;   // rows per lane
+    const int64_t r0 = blockIdx.x * static_cast<int64_t>(kRows);
+    const int wv = threadIdx.x / 64, lane = threadIdx.x % 64, nw = blockDim.x / 64;
+    double yr[kPer];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) x[u] = partial[static_cast<int64_t>(b + u) * ldp + c];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) acc[u] += x[u];
-        }
-        for (; b < b1; ++b) acc[0] += partial[static_cast<int64_t>(b) * ldp + c];
+    for (int u = 0; u < kPer; ++u) {
+        const int64_t row = r0 + u * 64 + lane;
+        yr[u] = row < n ? y[row] : 0.0;
     }
-    qs[qt][cl] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
-    __syncthreads();
-    if (qt == 0 && c < ncols) h[c] = ((qs[0][cl] + qs[1][cl]) + qs[2][cl]) + qs[3][cl];
+    for (int c = wv; c < ncols; c += nw) {
+        double acc = 0.0;
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int64_t row = r0 + u * 64 + lane;
+            acc += (row < n ? V[c * ldv + row] : 0.0) * yr[u];
+        }
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+        if (lane == 0) put_shared(partial + static_cast<int64_t>(blockIdx.x) * ldp + c, acc);
+    }
+    // the last workgroup sums the partial rows into h (the k_reduce_cols order)
+    __shared__ bool last;
+    __shared__ double qs[4][64];
+    if (!last_workgroup(counter, &last)) return;
+    for (int g = 0; g * 64 < ncols; ++g) reduce_cols_group<true>(partial, gridDim.x, ldp, ncols, h, g, qs);
 }
 
 // y -= V h (c < ncols); partial norms of the result when np != nullptr
@@ -110,6 +171,37 @@ __global__ void k_gemvn(const double* V, int64_t ldv, int ncols, const double* h
     if (np) {
         const double t = block_sum(nrm, sm);
         if (threadIdx.x == 0) np[blockIdx.x] = t;
+    }
+}
+
+// k_gemvn with the partial norms, then the last workgroup forms alpha_j = h1[j] + h2[j]
+// and beta_j = sqrt(sum of the partial norms) (the k_alpha_beta order)
+__global__ void k_gemvn_ab(const double* V, int64_t ldv, int ncols, const double* h, double* y, int64_t n, double* np,
+                           const double* h1, int j, double* alpha, double* beta, unsigned* counter) {
+    __shared__ double sm[kBlock / 64];
+    __shared__ double hs[1024];
+    for (int c = threadIdx.x; c < ncols && c < 1024; c += blockDim.x) hs[c] = h[c];
+    __syncthreads();
+    const int64_t r0 = blockIdx.x * static_cast<int64_t>(kRows);
+    double nrm = 0.0;
+    for (int u = 0; u < kRows / kBlock; ++u) {
+        const int64_t row = r0 + u * kBlock + threadIdx.x;
+        if (row >= n) continue;
+        double acc = 0.0;
+        for (int c = 0; c < ncols; ++c) acc += V[c * ldv + row] * (c < 1024 ? hs[c] : h[c]);
+        const double v = y[row] - acc;
+        y[row] = v;
+        nrm += v * v;
+    }
+    const double t = block_sum(nrm, sm);
+    if (threadIdx.x == 0) put_shared(np + blockIdx.x, t);
+    __shared__ bool last;
+    if (!last_workgroup(counter, &last)) return;
+    if (threadIdx.x == 0) {
+        alpha[j] = h1[j] + h[j];
+        double s2 = 0.0;
+        for (int b = 0; b < static_cast<int>(gridDim.x); ++b) s2 += get_shared(np + b);
+        beta[j] = sqrt(s2);
     }
 }
 
@@ -652,6 +744,8 @@ void LanczosRun::start(Op& o, int r_, double tol_, int max_basis_, uint64_t seed
     bound.alloc(r);
     Y.alloc(static_cast<size_t>(r) * max_basis);
     work.alloc(static_cast<size_t>(r) * 5 * max_basis);
+    counters.alloc(2);
+    HDM_HIP(hipMemsetAsync(counters.get(), 0, counters.bytes(), s));
     h_theta.assign(r, 0.0);
     h_bound.assign(r, 0.0);
     j = m = matvecs = 0;
@@ -674,14 +768,14 @@ bool LanczosRun::after_product(hipStream_t s) {
     const int nc = j + 1;
     {   // CGS2 against the whole basis, alpha_j, beta_j
         PhaseScope ph(op->ctx, HDM_PHASE_ORTHO, s);
-        hipLaunchKernelGGL(k_gemvt, dim3(nb), dim3(kBlock), 0, s, V.get(), n, nc, y.get(), n, part.get(), ldp);
-        hipLaunchKernelGGL(k_reduce_cols, dim3(ceil_div(nc, 64)), dim3(256), 0, s, part.get(), nb, ldp, nc, h1.get());
+        unsigned* cnt = counters.get();
+        hipLaunchKernelGGL(k_gemvt_h, dim3(nb), dim3(kBlock), 0, s, V.get(), n, nc, y.get(), n, part.get(), ldp,
+                           h1.get(), cnt);
         hipLaunchKernelGGL(k_gemvn, dim3(nb), dim3(kBlock), 0, s, V.get(), n, nc, h1.get(), y.get(), n, nullptr);
-        hipLaunchKernelGGL(k_gemvt, dim3(nb), dim3(kBlock), 0, s, V.get(), n, nc, y.get(), n, part.get(), ldp);
-        hipLaunchKernelGGL(k_reduce_cols, dim3(ceil_div(nc, 64)), dim3(256), 0, s, part.get(), nb, ldp, nc, h2.get());
-        hipLaunchKernelGGL(k_gemvn, dim3(nb), dim3(kBlock), 0, s, V.get(), n, nc, h2.get(), y.get(), n, np.get());
-        hipLaunchKernelGGL(k_alpha_beta, dim3(1), dim3(1), 0, s, h1.get(), h2.get(), j, np.get(), nb, alpha.get(),
-                           beta.get());
+        hipLaunchKernelGGL(k_gemvt_h, dim3(nb), dim3(kBlock), 0, s, V.get(), n, nc, y.get(), n, part.get(), ldp,
+                           h2.get(), cnt);
+        hipLaunchKernelGGL(k_gemvn_ab, dim3(nb), dim3(kBlock), 0, s, V.get(), n, nc, h2.get(), y.get(), n, np.get(),
+                           h1.get(), j, alpha.get(), beta.get(), cnt + 1);
     }
     check_launch("lanczos step");
     m = j + 1;

@@ -38,7 +38,7 @@ struct Ctx {
     int device = 0;
     size_t budget = 0;      // bytes, 0 = unlimited
     size_t resident = 0;    // bytes held by live operators of this context
-    bool graphs = true;     // single-operator products replay a HIP graph
+    bool graphs = false;    // hdm_matvec replays a HIP graph (hdm_ctx_graphs)
     Profiler prof;
 };
 
@@ -270,6 +270,7 @@ struct LanczosRun {
     int64_t n = 0;
     int nb = 0, ldp = 0;
     DevBuf<double> V, y, part, h1, h2, np, alpha, beta, theta, bound, Y, work;
+    DevBuf<unsigned> counters;   // arrival counters of the last-workgroup reductions (zero between launches)
     std::vector<double> h_theta, h_bound;
     int j = 0, m = 0, matvecs = 0;
     bool converged = false, finished = false;

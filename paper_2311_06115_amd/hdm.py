@@ -168,7 +168,7 @@ class Context:
             check(lib().hdm_ctx_profile_phases(self.h, mask))
 
     def graphs(self, enable: bool):
-        """Single-operator products replay a HIP graph (True, the default) or launch eagerly."""
+        """hdm_matvec replays a HIP graph (True) or launches its kernels one by one (False, the default)."""
         check(lib().hdm_ctx_graphs(self.h, int(enable)))
 
     def phase_times(self):
