@@ -635,12 +635,13 @@ __global__ void k_row_count(LevelArgs A) {
 // that is all there is).  The draws are taken 64 at a time by one wave and
 // accepted in draw order, exactly as a sequential rejection loop would.
 constexpr int kMaxRows = 1024;   // sampled rows per node (2 max_rank_s)
-constexpr int kSortCap = 16384;  // neighbour entries a node sorts in shared memory (nc k <= this)
+constexpr int kVoteShared = 144 * 1024;   // shared memory for the bitmap vote counting (bytes)
 
-// kSorted: the candidates' outside neighbours are gathered into shared memory,
-// sorted, and counted run by run (unique indices ascending, votes per index);
-// otherwise k_row_count has counted them into a dense per-node array that is
-// scanned in index order.  Both give the same ascending list and votes.
+// kSorted: the candidates' outside neighbours are marked in a bitmap over the
+// points in shared memory, which lists them in ascending order, and their votes
+// are counted at their ranks; otherwise k_row_count has counted them into a
+// dense per-node array that is scanned in index order.  Both give the same
+// ascending list and votes.
 template <bool kSorted>
 __global__ void k_row_select(LevelArgs A) {
     __shared__ int wsum[kBlock / 64];
@@ -663,53 +664,55 @@ __global__ void k_row_select(LevelArgs A) {
     auto votes = [&](int64_t u) { return kSorted ? vt[u] : cnt[uq[u]]; };
     int64_t nu = 0;
     if constexpr (kSorted) {
-        extern __shared__ int32_t E[];
-        __shared__ int s_ne;
+        // an n-bit map of the outside neighbours, the running popcount of its
+        // words, and the votes at each neighbour's rank in index order
+        extern __shared__ uint32_t dsh[];
+        const int nw = static_cast<int>((A.n + 31) / 32);
+        uint32_t* bm = dsh;
+        int32_t* pre = reinterpret_cast<int32_t*>(dsh + nw);
+        int32_t* sv = pre + nw;
         const int nc = A.ncand[t];
         const int32_t* cd = A.cand + t * A.cmax;
-        if (threadIdx.x == 0) s_ne = 0;
-        __syncthreads();
         const int64_t ntot = static_cast<int64_t>(nc) * A.k;
-        for (int64_t e = threadIdx.x; e < ntot; e += blockDim.x) {
+        for (int w = threadIdx.x; w < nw; w += blockDim.x) bm[w] = 0u;
+        for (int64_t e = threadIdx.x; e < ntot; e += blockDim.x) sv[e] = 0;
+        __syncthreads();
+        auto outside = [&](int64_t e) -> int32_t {   // the neighbour of entry e, or -1
             const int32_t i = A.kidx[static_cast<int64_t>(cd[e / A.k]) * A.k + e % A.k];
-            if (i < 0) continue;
+            if (i < 0) return -1;
             const int64_t pi = A.iperm[i];
-            if (pi >= lo && pi < hi) continue;
-            E[atomicAdd(&s_ne, 1)] = i;
+            return (pi >= lo && pi < hi) ? -1 : i;
+        };
+        for (int64_t e = threadIdx.x; e < ntot; e += blockDim.x) {
+            const int32_t i = outside(e);
+            if (i >= 0) atomicOr(&bm[i >> 5], 1u << (i & 31));
         }
         __syncthreads();
-        const int ne = s_ne;
-        int P2 = 1;
-        while (P2 < ne) P2 <<= 1;
-        for (int e = ne + threadIdx.x; e < P2; e += blockDim.x) E[e] = INT32_MAX;
-        __syncthreads();
-        for (int kk = 2; kk <= P2; kk <<= 1)   // bitonic sort, ascending
-            for (int j = kk >> 1; j > 0; j >>= 1) {
-                for (int e = threadIdx.x; e < P2; e += blockDim.x) {
-                    const int f = e ^ j;
-                    if (f > e) {
-                        const int32_t a = E[e], b = E[f];
-                        if ((a > b) == ((e & kk) == 0)) { E[e] = b; E[f] = a; }
-                    }
-                }
-                __syncthreads();
-            }
-        // run starts in index order: a contiguous range of positions per thread
-        const int per = (ne + kBlock - 1) / kBlock;
-        const int e0 = min(ne, static_cast<int>(threadIdx.x) * per), e1 = min(ne, e0 + per);
+        // words in contiguous ranges per thread: exclusive popcount prefix, then
+        // the set bits in ascending order
+        const int per = (nw + kBlock - 1) / kBlock;
+        const int w0 = min(nw, static_cast<int>(threadIdx.x) * per), w1 = min(nw, w0 + per);
         int mine = 0;
-        for (int e = e0; e < e1; ++e) mine += e == 0 || E[e] != E[e - 1];
+        for (int w = w0; w < w1; ++w) mine += __popc(bm[w]);
         int tot = 0;
-        int w = wg_scan_excl(mine, wsum, &tot);
-        for (int e = e0; e < e1; ++e)
-            if (e == 0 || E[e] != E[e - 1]) {
-                int r = e + 1;
-                while (r < ne && E[r] == E[e]) ++r;
-                uq[w] = E[e];
-                vt[w] = r - e;
-                ++w;
+        int r = wg_scan_excl(mine, wsum, &tot);
+        for (int w = w0; w < w1; ++w) {
+            pre[w] = r;
+            uint32_t m = bm[w];
+            while (m) {
+                const int bit = __ffs(m) - 1;
+                m &= m - 1;
+                uq[r++] = w * 32 + bit;
             }
+        }
         nu = tot;
+        __syncthreads();
+        for (int64_t e = threadIdx.x; e < ntot; e += blockDim.x) {
+            const int32_t i = outside(e);
+            if (i >= 0) atomicAdd(&sv[pre[i >> 5] + __popc(bm[i >> 5] & ((1u << (i & 31)) - 1u))], 1);
+        }
+        __syncthreads();
+        for (int64_t u = threadIdx.x; u < nu; u += blockDim.x) vt[u] = sv[u];
         __syncthreads();
     } else {
         // compaction of {i : cnt[i] > 0} in index order: a contiguous range per
@@ -743,17 +746,31 @@ __global__ void k_row_select(LevelArgs A) {
     // (at most want_nb) kept entries ordered among themselves
     for (int64_t u = threadIdx.x; u < nu; u += blockDim.x) atomicAdd(&hist[min(votes(u), kMaxCand)], 1);
     __syncthreads();
-    if (threadIdx.x == 0) {
-        int64_t above = 0;   // entries with more votes than c
-        int tc = 0, need = 0;
-        if (nu > want_nb) {
-            for (int c = kMaxCand; c >= 1; --c) {
-                if (above + hist[c] >= want_nb) { tc = c; need = static_cast<int>(want_nb - above); break; }
+    // the threshold: the highest vote count c at which the entries with at least
+    // c votes reach want_nb.  Thread t owns the kBins bins kMaxCand - kBins t
+    // downwards; an exclusive scan gives the entries above its range.
+    {
+        constexpr int kBins = kMaxCand / kBlock;
+        static_assert(kBins * kBlock == kMaxCand, "bins per thread");
+        const int top = kMaxCand - kBins * static_cast<int>(threadIdx.x);
+        int mine = 0;
+        for (int c = top; c > top - kBins; --c) mine += hist[c];
+        int tot = 0;
+        int64_t above = wg_scan_excl(mine, wsum, &tot);
+        if (threadIdx.x == 0) {
+            s_t = 0;        // 0: every entry is kept
+            s_need = 0;
+        }
+        __syncthreads();
+        if (nu > want_nb && above < want_nb && above + mine >= want_nb)
+            for (int c = top; c > top - kBins; --c) {
+                if (above + hist[c] >= want_nb) {
+                    s_t = c;
+                    s_need = static_cast<int>(want_nb - above);
+                    break;
+                }
                 above += hist[c];
             }
-        }
-        s_t = tc;        // 0: every entry is kept
-        s_need = need;
     }
     __syncthreads();
     const int tcut = s_t, need = s_need;
@@ -1487,7 +1504,8 @@ static void skeletonize_levels(Op& op, const Geo& G, hipStream_t s, SkelRun& R) 
     R.status.alloc(maxnodes);
     R.uniq.alloc(static_cast<size_t>(maxnodes) * cmax * k);
     R.B.alloc(static_cast<size_t>(maxnodes) * rmax * cmax);
-    const bool sorted_votes = static_cast<int64_t>(cmax) * k <= kSortCap;
+    const size_t vote_shmem = sizeof(int32_t) * (2 * static_cast<size_t>((n + 31) / 32) + static_cast<size_t>(cmax) * k);
+    const bool sorted_votes = vote_shmem <= static_cast<size_t>(kVoteShared);
     if (sorted_votes) R.vts.alloc(static_cast<size_t>(maxnodes) * cmax * k);
     else R.cnt.alloc(static_cast<size_t>(maxnodes) * n);
     R.bits.alloc(static_cast<size_t>(maxnodes) * ((n + 31) / 32));
@@ -1535,13 +1553,11 @@ static void skeletonize_levels(Op& op, const Geo& G, hipStream_t s, SkelRun& R) 
             HDM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pivoted_id),
                                         hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(id_shmem)));
     }
-    // row selection: the neighbour votes are sorted in shared memory when a node's
-    // nc k entries fit, else counted into a dense per-node array
+    // row selection: the neighbour votes are counted through a bitmap over the
+    // points in shared memory when it fits, else in a dense per-node array
     size_t sort_shmem = 0;
     if (sorted_votes) {
-        int64_t p2 = 1;
-        while (p2 < static_cast<int64_t>(cmax) * k) p2 <<= 1;
-        sort_shmem = sizeof(int32_t) * static_cast<size_t>(p2);
+        sort_shmem = vote_shmem;
         HDM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_row_select<true>),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(sort_shmem)));
     }
