@@ -54,6 +54,14 @@ struct PoolScope {
     PoolScope(const PoolScope&) = delete;
     PoolScope& operator=(const PoolScope&) = delete;
 };
+// Pinned host memory for an upload made inside a PoolScope, valid until the
+// outermost scope ends (after its device synchronisation); nullptr outside a
+// scope.  Copies from it are asynchronous, where copies from pageable memory
+// are staged by the runtime and return only when done.
+void* host_stage(size_t bytes);
+// count elements from host memory to device memory on stream s, through
+// host_stage when a scope is open
+void upload_bytes(void* dst, const void* src, size_t bytes, hipStream_t s);
 
 // Owning device allocation (no copy, movable).
 template <typename T>
@@ -84,7 +92,7 @@ struct DevBuf {
     size_t bytes() const { return n * sizeof(T); }
     T* get() const { return p; }
     void upload(const T* host, size_t count, hipStream_t s) {
-        if (count) HDM_HIP(hipMemcpyAsync(p, host, count * sizeof(T), hipMemcpyHostToDevice, s));
+        if (count) upload_bytes(p, host, count * sizeof(T), s);
     }
     void upload(const std::vector<T>& v, hipStream_t s) {
         if (v.size() > n) alloc(v.size());

@@ -864,6 +864,38 @@ __global__ void k_row_select(LevelArgs A) {
     }
 }
 
+// B = K(rows, cand) for float64 points of at most kDimReg coordinates: a thread
+// keeps one candidate point in registers and walks a slice of the rows (the
+// same row point for every thread at a time); the same operations in the same
+// order as kval(P, row, candidate)
+constexpr int kDimReg = 16;
+constexpr int kBlockSlices = 4;   // row slices (workgroups) per node
+__global__ void k_block_reg(LevelArgs A, Pts P) {
+    const int64_t t = blockIdx.y;
+    const int nc = A.ncand[t], nr = A.nrows[t];
+    const int per = (nr + kBlockSlices - 1) / kBlockSlices;
+    const int r0 = static_cast<int>(blockIdx.x) * per, r1 = min(nr, r0 + per);
+    double* B = A.B + t * static_cast<int64_t>(A.rmax) * A.cmax;
+    const int32_t* rows = A.rows + t * A.rmax;
+    for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+        const double* xj = P.xf + static_cast<int64_t>(A.cand[t * A.cmax + c]) * P.dim;
+        double xc[kDimReg];
+#pragma unroll
+        for (int d = 0; d < kDimReg; ++d) xc[d] = d < P.dim ? xj[d] : 0.0;
+        for (int r = r0; r < r1; ++r) {
+            const double* xi = P.xf + static_cast<int64_t>(rows[r]) * P.dim;
+            double acc = 0.0;
+#pragma unroll
+            for (int d = 0; d < kDimReg; ++d)
+                if (d < P.dim) {
+                    const double tq = xi[d] - xc[d];
+                    acc = acc + tq * tq;
+                }
+            B[static_cast<int64_t>(r) * nc + c] = exp(-(acc / P.eps));
+        }
+    }
+}
+
 // B = K(rows, cand), row-major with leading dimension ncand
 __global__ void k_block(LevelArgs A, Pts P) {
     const int64_t t = blockIdx.y;
@@ -1337,26 +1369,45 @@ static void tree_ranges(int64_t n, int depth, std::vector<int64_t>& start, std::
 // mode 0: the ball tree (ntrees = 1); mode 1: ntrees neighbour trees at once
 // (trees it0 .. it0 + ntrees - 1, each level of all of them in one launch);
 // perm, tmp and key hold ntrees x n entries, pq ntrees x 2L.
-static void build_tree(Op& op, int mode, int it0, int ntrees, DevBuf<int32_t>& perm, DevBuf<int32_t>& tmp,
-                       const Geo& G, hipStream_t s, DevBuf<int32_t>& samp, DevBuf<int32_t>& nsamp,
-                       DevBuf<int32_t>& pq, DevBuf<double>& sumk, DevBuf<double>& key) {
-    HDM_CHECK(mode == 1 || ntrees == 1, HDM_EINTERNAL, "one ball tree at a time");
-    HDM_CHECK(perm.n >= static_cast<size_t>(ntrees) * op.n && tmp.n >= static_cast<size_t>(ntrees) * op.n &&
-                  key.n >= static_cast<size_t>(ntrees) * op.n &&
-                  pq.n >= static_cast<size_t>(ntrees) * 2 * op.L,
-              HDM_EINTERNAL, "tree buffers too small");
-    const int64_t pq_stride = 2 * static_cast<int64_t>(op.L);
-    const Pts& P = G.P;
-    const int64_t n = op.n;
+// One or several trees built level by level on a stream; the caller can
+// interleave the levels of two builds on two streams.
+struct TreeBuild {
+    Op& op;
+    int mode, it0, ntrees;
+    DevBuf<int32_t>& perm;
+    DevBuf<int32_t>& tmp;
+    const Geo& G;
+    hipStream_t s;
+    DevBuf<int32_t>& samp;
+    DevBuf<int32_t>& nsamp;
+    DevBuf<int32_t>& pq;
+    DevBuf<double>& sumk;
+    DevBuf<double>& key;
     DevBuf<int32_t> sample_ids;
     DevBuf<double> kvals;
-    if (mode == 0 && G.gram) {
-        sample_ids.alloc(static_cast<size_t>(op.L) * kSample);
-        kvals.alloc(static_cast<size_t>(n) * kSample);
+
+    TreeBuild(Op& op_, int mode_, int it0_, int ntrees_, DevBuf<int32_t>& perm_, DevBuf<int32_t>& tmp_, const Geo& G_,
+              hipStream_t s_, DevBuf<int32_t>& samp_, DevBuf<int32_t>& nsamp_, DevBuf<int32_t>& pq_,
+              DevBuf<double>& sumk_, DevBuf<double>& key_)
+        : op(op_), mode(mode_), it0(it0_), ntrees(ntrees_), perm(perm_), tmp(tmp_), G(G_), s(s_), samp(samp_),
+          nsamp(nsamp_), pq(pq_), sumk(sumk_), key(key_) {
+        HDM_CHECK(mode == 1 || ntrees == 1, HDM_EINTERNAL, "one ball tree at a time");
+        HDM_CHECK(perm.n >= static_cast<size_t>(ntrees) * op.n && tmp.n >= static_cast<size_t>(ntrees) * op.n &&
+                      key.n >= static_cast<size_t>(ntrees) * op.n &&
+                      pq.n >= static_cast<size_t>(ntrees) * 2 * op.L,
+                  HDM_EINTERNAL, "tree buffers too small");
+        if (mode == 0 && G.gram) {
+            sample_ids.alloc(static_cast<size_t>(op.L) * kSample);
+            kvals.alloc(static_cast<size_t>(op.n) * kSample);
+        }
+        hipLaunchKernelGGL(k_iota, dim3(ceil_div(op.n, kBlock), ntrees), dim3(kBlock), 0, s, perm.get(), op.n);
     }
-    const int gN = ceil_div(n, kBlock);
-    hipLaunchKernelGGL(k_iota, dim3(gN, ntrees), dim3(kBlock), 0, s, perm.get(), n);
-    for (int lvl = 0; lvl < op.depth; ++lvl) {
+
+    void level(int lvl) {
+        const int64_t pq_stride = 2 * static_cast<int64_t>(op.L);
+        const Pts& P = G.P;
+        const int64_t n = op.n;
+        const int gN = ceil_div(n, kBlock);
         const int nodes = 1 << lvl;
         if (mode == 0) {
             hipLaunchKernelGGL(k_tree_sample, dim3(nodes), dim3(64), 0, s, lvl, op.d_start.get(), op.d_size.get(),
@@ -1393,11 +1444,14 @@ static void build_tree(Op& op, int mode, int it0, int ntrees, DevBuf<int32_t>& p
         check_launch("tree level");
         std::swap(perm, tmp);
     }
+
     // the sample buffers are freed on return while the last level's kernels may
     // still be queued on s: wait for them first (hipFree's implicit
     // synchronisation is not relied on, e.g. for non-blocking streams)
-    if (sample_ids.n || kvals.n) HDM_HIP(hipStreamSynchronize(s));
-}
+    ~TreeBuild() {
+        if (sample_ids.n || kvals.n) (void)hipStreamSynchronize(s);
+    }
+};
 
 // near lists: self plus ceil(budget * L) other leaves by (votes desc, id asc), symmetrised
 static void build_near_lists(Op& op, const std::vector<int32_t>& votes) {
@@ -1615,6 +1669,10 @@ static void skeletonize_levels(Op& op, const Geo& G, hipStream_t s, SkelRun& R) 
                 blocks.push_back(GramBlock{rows.get() + int64_t(t) * rmax, cand.get() + int64_t(t) * cmax, h_nr[t],
                                            h_nc[t], int64_t(t) * rmax * cmax, h_nc[t], 0});
             gram_launch(G, blocks, 1, B, s);
+        } else if (!P.is_u8 && P.dim <= kDimReg && lvl == op.depth) {
+            // leaves: many candidates per node, one per thread (above the leaves the
+            // element-per-thread kernel keeps more threads busy)
+            hipLaunchKernelGGL(k_block_reg, dim3(kBlockSlices, nodes), dim3(kBlock), 0, s, A, P);
         } else {
             hipLaunchKernelGGL(k_block, dim3(ceil_div(static_cast<int64_t>(rmax) * cmax, kBlock), nodes), dim3(kBlock),
                                0, s, A, P);
@@ -1827,30 +1885,38 @@ void compress_operator(Op& op, const void* X, int x_on_device, hipStream_t s) {
     }
     // trees: the ball tree on the side stream while the neighbour trees run on s
     const int64_t n = op.n;
-    op.lane.init();
+    op.lane.init(op.ctx ? &op.ctx->lanes : nullptr);
     hipStream_t side = op.lane.side;
     HDM_HIP(hipEventRecord(op.lane.fork, s));
     HDM_HIP(hipStreamWaitEvent(side, op.lane.fork, 0));
     DevBuf<int32_t> perm(n), tmp(n), samp(static_cast<size_t>(op.L) * kSample), nsamp(op.L), pq(2 * op.L);
     DevBuf<double> sumk(n), key(n);
     op.iperm.alloc(n);
-    build_tree(op, 0, 0, 1, perm, tmp, G, side, samp, nsamp, pq, sumk, key);
-    op.perm = std::move(perm);
-    hipLaunchKernelGGL(k_inverse_perm, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, side, op.perm.get(),
-                       op.iperm.get(), n);
-    HDM_HIP(hipEventRecord(op.lane.join, side));
     // neighbours: random-pivot trees, all pairs inside leaves
     const int k = p.knn_k;
     op.knn_idx.alloc(static_cast<size_t>(n) * k);
     op.knn_d2.alloc(static_cast<size_t>(n) * k);
     hipLaunchKernelGGL(k_knn_init, dim3(ceil_div(n * k, kBlock)), dim3(kBlock), 0, s, op.knn_idx.get(), op.knn_d2.get(),
                        n * k);
-    // all neighbour trees are built together (every level of every tree in one launch)
+    // all neighbour trees are built together (every level of every tree in one launch);
+    // their levels and the ball tree's are issued alternately so both streams start at once
     const int T = p.knn_iters;
     DevBuf<int32_t> kperm(static_cast<size_t>(T) * n), ktmp(static_cast<size_t>(T) * n),
         kpq(static_cast<size_t>(T) * 2 * op.L);
     DevBuf<double> kkey(static_cast<size_t>(T) * n);
-    if (T > 0) build_tree(op, 1, 0, T, kperm, ktmp, G, s, samp, nsamp, kpq, sumk, kkey);
+    {
+        TreeBuild ball(op, 0, 0, 1, perm, tmp, G, side, samp, nsamp, pq, sumk, key);
+        std::unique_ptr<TreeBuild> knn;
+        if (T > 0) knn.reset(new TreeBuild(op, 1, 0, T, kperm, ktmp, G, s, samp, nsamp, kpq, sumk, kkey));
+        for (int lvl = 0; lvl < op.depth; ++lvl) {
+            ball.level(lvl);
+            if (knn) knn->level(lvl);
+        }
+    }
+    op.perm = std::move(perm);
+    hipLaunchKernelGGL(k_inverse_perm, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, side, op.perm.get(),
+                       op.iperm.get(), n);
+    HDM_HIP(hipEventRecord(op.lane.join, side));
     int64_t leafmax = 0;
     for (int64_t h = op.L; h < 2 * int64_t(op.L); ++h) leafmax = std::max(leafmax, op.size[h]);
     const int stage = (!P.is_u8 && P.dim <= kLeafStageDim && leafmax * P.dim * 8 <= 48 * 1024) ? 1 : 0;

@@ -638,17 +638,45 @@ size_t Op::footprint() const {
            part.bytes() + d_row_tasks.bytes() + wh.bytes() + wsc.bytes() + d_items_mma.bytes() + d_leaves_mma.bytes();
 }
 
-void Lane::init() {
-    if (!side) HDM_HIP(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
-    if (!fork) HDM_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
-    if (!join) HDM_HIP(hipEventCreateWithFlags(&join, hipEventDisableTiming));
+void Lane::init(LanePool* from) {
+    if (side) return;
+    pool = from;
+    if (from) {
+        std::lock_guard<std::mutex> g(from->mu);
+        if (!from->free.empty()) {
+            const LanePool::Entry e = from->free.back();
+            from->free.pop_back();
+            side = e.side;
+            fork = e.fork;
+            join = e.join;
+            return;
+        }
+    }
+    HDM_HIP(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
+    HDM_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+    HDM_HIP(hipEventCreateWithFlags(&join, hipEventDisableTiming));
 }
 
 Lane::~Lane() {
-    if (side) (void)hipStreamSynchronize(side);
+    if (!side) return;
+    (void)hipStreamSynchronize(side);
+    if (pool) {
+        std::lock_guard<std::mutex> g(pool->mu);
+        pool->free.push_back(LanePool::Entry{side, fork, join});
+        return;
+    }
     if (fork) (void)hipEventDestroy(fork);
     if (join) (void)hipEventDestroy(join);
-    if (side) (void)hipStreamDestroy(side);
+    (void)hipStreamDestroy(side);
+}
+
+LanePool::~LanePool() {
+    for (const Entry& e : free) {
+        (void)hipStreamSynchronize(e.side);
+        (void)hipEventDestroy(e.fork);
+        (void)hipEventDestroy(e.join);
+        (void)hipStreamDestroy(e.side);
+    }
 }
 
 static int rows_per_lane(int dt) { return 16 / static_cast<int>(dtype_size(dt)); }
@@ -860,7 +888,7 @@ void build_eval_plan(Op& op, hipStream_t s) {
     op.row_total = static_cast<int64_t>(tasks.size());
     op.d_row_tasks = to_device(tasks, s);
     if (op.prm.near_prec == HDM_F16) build_mma_plan(op, s);
-    op.lane.init();
+    op.lane.init(op.ctx ? &op.ctx->lanes : nullptr);
     ensure_ws(op, 1);
     publish_descriptors(op, s);
 }

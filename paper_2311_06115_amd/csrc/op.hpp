@@ -34,12 +34,25 @@ struct Profiler {
     ~Profiler();
 };
 
+// Side streams with their fork/join events, kept by a context for its next
+// operators: creating and destroying a stream costs ~60-80 us each.
+struct LanePool {
+    struct Entry {
+        hipStream_t side;
+        hipEvent_t fork, join;
+    };
+    std::mutex mu;
+    std::vector<Entry> free;
+    ~LanePool();
+};
+
 struct Ctx {
     int device = 0;
     size_t budget = 0;      // bytes, 0 = unlimited
     size_t resident = 0;    // bytes held by live operators of this context
     bool graphs = false;    // hdm_matvec replays a HIP graph (hdm_ctx_graphs)
     Profiler prof;
+    LanePool lanes;
 };
 
 // start/stop events of one profiled kernel launch (both null unless the context profiles)
@@ -145,7 +158,8 @@ struct OpDev {
 struct Lane {
     hipStream_t side = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;
-    void init();
+    LanePool* pool = nullptr;   // where the stream and events go back to (null: destroyed)
+    void init(LanePool* from = nullptr);
     Lane() = default;
     Lane(const Lane&) = delete;
     Lane& operator=(const Lane&) = delete;

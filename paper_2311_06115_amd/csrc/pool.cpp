@@ -4,6 +4,7 @@
 // tens to hundreds of microseconds apiece and hipFree waits for the device, so
 // repeated compressions spent milliseconds in them.
 #include <algorithm>
+#include <cstring>
 #include <map>
 #include <mutex>
 #include <unordered_map>
@@ -33,6 +34,20 @@ Pool& pool() {
 
 thread_local int t_depth = 0;
 thread_local std::vector<void*> t_pending;
+
+// pinned staging blocks of this thread, bump-allocated inside a scope and
+// reused after the scope's device synchronisation
+struct Stage {
+    struct Block {
+        char* p;
+        size_t size, top;
+    };
+    std::vector<Block> blocks;
+    void reset() {
+        for (Block& b : blocks) b.top = 0;
+    }
+};
+thread_local Stage t_stage;
 
 size_t round_up(size_t b) {
     const size_t g = b < (size_t(1) << 20) ? 256 : (size_t(1) << 16);
@@ -97,13 +112,48 @@ void dev_free(void* p) noexcept {
     (void)hipFree(p);
 }
 
+void* host_stage(size_t bytes) {
+    if (t_depth == 0) return nullptr;
+    const size_t need = (bytes + 255) / 256 * 256;
+    for (Stage::Block& b : t_stage.blocks)
+        if (b.size - b.top >= need) {
+            void* p = b.p + b.top;
+            b.top += need;
+            return p;
+        }
+    const size_t size = std::max(need, size_t(8) << 20);
+    void* p = nullptr;
+    if (hipHostMalloc(&p, size, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    t_stage.blocks.push_back(Stage::Block{static_cast<char*>(p), size, need});
+    return p;
+}
+
+void upload_bytes(void* dst, const void* src, size_t bytes, hipStream_t s) {
+    if (!bytes) return;
+    if (void* h = host_stage(bytes)) {
+        std::memcpy(h, src, bytes);
+        HDM_HIP(hipMemcpyAsync(dst, h, bytes, hipMemcpyHostToDevice, s));
+    } else {
+        HDM_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s));
+    }
+}
+
 PoolScope::PoolScope() { ++t_depth; }
 
 PoolScope::~PoolScope() {
-    if (--t_depth > 0 || t_pending.empty()) return;
+    if (--t_depth > 0) return;
+    bool staged = false;
+    for (const Stage::Block& b : t_stage.blocks) staged = staged || b.top > 0;
+    if (t_pending.empty() && !staged) return;
     Pool& P = pool();
-    // the blocks may still be read or written by queued work on any stream
+    // the blocks may still be read or written, and the staging memory still be
+    // copied from, by queued work on any stream
     const bool idle = hipDeviceSynchronize() == hipSuccess;
+    if (idle) t_stage.reset();
+    else t_stage.blocks.clear();   // in error: leave the staging blocks alone
     std::lock_guard<std::mutex> g(P.mu);
     for (void* p : t_pending) {
         auto it = P.live.find(p);
