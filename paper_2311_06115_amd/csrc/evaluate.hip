@@ -216,9 +216,36 @@ __global__ void __launch_bounds__(kBlock) k_l2l(Batch b) {
 // (the S2N pass restricted to one path), applies P_leaf^T, adds the near-field
 // partial sums of the leaf's rows and writes the scaled result in original order.
 constexpr int kMaxRank = 512;
+// Per leaf, one workgroup of kCombBlock threads: the downward chain along the
+// leaf's ancestors (the path's P slices and far-field values staged in shared
+// memory first, all loads independent), the near partial sums (four quarters of
+// the workgroup take a quarter of the items each, added in a fixed order), the
+// leaf's P^T u~, the alpha = 1 scale, and the scatter to the original order.
+constexpr int kCombBlock = 1024;
+constexpr int kChainStageBytes = 65536;
+
 template <typename V, typename TP>
-__global__ void __launch_bounds__(kBlock) k_combine(Batch b) {
+__device__ inline void stage_slice(V* dst, const TP* src, int rp, int rn, int ld) {
+    const int tot = rp * rn;
+    for (int e0 = threadIdx.x; e0 < tot; e0 += 4 * kCombBlock) {
+        TP x[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = min(e0 + q * kCombBlock, tot - 1);
+            x[q] = src[static_cast<int64_t>(e / rn) * ld + e % rn];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (e0 + q * kCombBlock < tot) dst[e0 + q * kCombBlock] = static_cast<V>(x[q]);
+    }
+}
+
+template <typename V, typename TP>
+__global__ void __launch_bounds__(kCombBlock) k_combine(Batch b) {
+    constexpr int kStage = kChainStageBytes / static_cast<int>(sizeof(V));
     __shared__ V tot[2][kMaxRank];
+    __shared__ V chain[kStage];
+    __shared__ V quarter[4][kCombBlock / 4];
     const int64_t u = blockIdx.x;
     const int o = batch_op(b, u);
     const OpDev& D = *b.op[o];
@@ -226,31 +253,45 @@ __global__ void __launch_bounds__(kBlock) k_combine(Batch b) {
     const TP* P = static_cast<const TP*>(D.P);
     const V* sku = static_cast<const V*>(D.sku);
     const int depth = D.row_total > 0 ? D.depth : 0;
+    int64_t need = 0;
+    for (int lvl = 2; lvl <= depth; ++lvl) {
+        const int64_t node = lp.heap >> (depth - lvl);
+        need += static_cast<int64_t>(D.rank[node >> 1]) * D.rank[node];
+    }
+    const bool staged = need <= kStage;
     for (int c = 0; c < b.nrhs; ++c) {
         int cur = 0;
         int rleaf = 0;
         if (depth >= 1) {
             const int64_t a1 = lp.heap >> (depth - 1);
             for (int i = threadIdx.x; i < D.rank[a1]; i += blockDim.x) tot[0][i] = sku[c * D.ldsk + D.skoff[a1] + i];
+            if (staged && c == 0) {
+                int64_t off = 0;
+                for (int lvl = 2; lvl <= depth; ++lvl) {
+                    const int64_t node = lp.heap >> (depth - lvl), par = node >> 1;
+                    const int rp = D.rank[par], rn = D.rank[node];
+                    const TP* Pm = P + D.poff[par] + ((node & 1) ? D.rank[2 * par] : 0);
+                    stage_slice<V>(chain + off, Pm, rp, rn, D.ncand[par]);
+                    off += static_cast<int64_t>(rp) * rn;
+                }
+            }
             __syncthreads();
+            int64_t off = 0;
             for (int lvl = 2; lvl <= depth; ++lvl) {
                 const int64_t node = lp.heap >> (depth - lvl), par = node >> 1;
                 const int rp = D.rank[par], ncp = D.ncand[par], rn = D.rank[node];
-                const int off = (node & 1) ? D.rank[2 * par] : 0;
-                const TP* Pm = P + D.poff[par] + off;
+                const TP* Pm = P + D.poff[par] + ((node & 1) ? D.rank[2 * par] : 0);
                 for (int j = threadIdx.x; j < rn; j += blockDim.x) {
                     V acc = 0;
-                    int i = 0;
-                    for (; i + 8 <= rp; i += 8) {
-                        TP pv[8];
-#pragma unroll
-                        for (int q = 0; q < 8; ++q) pv[q] = Pm[static_cast<int64_t>(i + q) * ncp + j];
-#pragma unroll
-                        for (int q = 0; q < 8; ++q) acc += static_cast<V>(pv[q]) * tot[cur][i + q];
+                    if (staged) {
+                        const V* Ps = chain + off;
+                        for (int i = 0; i < rp; ++i) acc += Ps[i * rn + j] * tot[cur][i];
+                    } else {
+                        for (int i = 0; i < rp; ++i) acc += static_cast<V>(Pm[static_cast<int64_t>(i) * ncp + j]) * tot[cur][i];
                     }
-                    for (; i < rp; ++i) acc += static_cast<V>(Pm[static_cast<int64_t>(i) * ncp + j]) * tot[cur][i];
                     tot[cur ^ 1][j] = sku[c * D.ldsk + D.skoff[node] + j] + acc;
                 }
+                off += static_cast<int64_t>(rp) * rn;
                 __syncthreads();
                 cur ^= 1;
             }
@@ -258,32 +299,43 @@ __global__ void __launch_bounds__(kBlock) k_combine(Batch b) {
         }
         const TP* Pl = P + D.poff[lp.heap];
         const V* pc = static_cast<const V*>(D.part) + c * D.ldp + lp.part_off;
-        for (int j = threadIdx.x; j < lp.rows; j += blockDim.x) {
+        const int q = threadIdx.x / (kCombBlock / 4), jq = threadIdx.x % (kCombBlock / 4);
+        const int per = (lp.nitems + 3) / 4;
+        const int i0 = min(lp.nitems, q * per), i1 = min(lp.nitems, i0 + per);
+        for (int j0 = 0; j0 < lp.rows; j0 += kCombBlock / 4) {
+            const int j = j0 + jq;
             V near = 0;
-            int q = 0;
-            for (; q + 8 <= lp.nitems; q += 8) {
-                V x[8];
+            if (j < lp.rows) {
+                int it = i0;
+                for (; it + 8 <= i1; it += 8) {
+                    V x[8];
 #pragma unroll
-                for (int t = 0; t < 8; ++t) x[t] = pc[static_cast<int64_t>(q + t) * lp.ld + j];
+                    for (int t = 0; t < 8; ++t) x[t] = pc[static_cast<int64_t>(it + t) * lp.ld + j];
 #pragma unroll
-                for (int t = 0; t < 8; ++t) near += x[t];
+                    for (int t = 0; t < 8; ++t) near += x[t];
+                }
+                for (; it < i1; ++it) near += pc[static_cast<int64_t>(it) * lp.ld + j];
             }
-            for (; q < lp.nitems; ++q) near += pc[static_cast<int64_t>(q) * lp.ld + j];
-            V f = 0;
-            int i = 0;
-            for (; i + 8 <= rleaf; i += 8) {
-                TP pv[8];
+            quarter[q][jq] = near;
+            __syncthreads();
+            if (q == 0 && j < lp.rows) {
+                V f = 0;
+                int i = 0;
+                for (; i + 8 <= rleaf; i += 8) {
+                    TP pv[8];
 #pragma unroll
-                for (int t = 0; t < 8; ++t) pv[t] = Pl[static_cast<int64_t>(i + t) * lp.rows + j];
+                    for (int t = 0; t < 8; ++t) pv[t] = Pl[static_cast<int64_t>(i + t) * lp.rows + j];
 #pragma unroll
-                for (int t = 0; t < 8; ++t) f += static_cast<V>(pv[t]) * tot[cur][i + t];
+                    for (int t = 0; t < 8; ++t) f += static_cast<V>(pv[t]) * tot[cur][i + t];
+                }
+                for (; i < rleaf; ++i) f += static_cast<V>(Pl[static_cast<int64_t>(i) * lp.rows + j]) * tot[cur][i];
+                const V nsum = (quarter[0][jq] + quarter[1][jq]) + (quarter[2][jq] + quarter[3][jq]);
+                const int64_t pos = lp.start + j;
+                const double sc = b.arg[o] ? D.c[pos] : 1.0;
+                b.y[o][c * D.n + D.perm[pos]] = sc * static_cast<double>(nsum + f);
             }
-            for (; i < rleaf; ++i) f += static_cast<V>(Pl[static_cast<int64_t>(i) * lp.rows + j]) * tot[cur][i];
-            const int64_t pos = lp.start + j;
-            const double sc = b.arg[o] ? D.c[pos] : 1.0;
-            b.y[o][c * D.n + D.perm[pos]] = sc * static_cast<double>(near + f);
+            __syncthreads();
         }
-        __syncthreads();
     }
 }
 
@@ -998,7 +1050,7 @@ static void apply_t(const ApplyReq* reqs, int nops, bool f64, int normalised, in
         if (multi)
             hipExtLaunchKernelGGL((k_combine_m<V, TP>), dim3(tot), dim3(kBlock), 0, s, ev.start, ev.stop, 0, b);
         else
-            hipExtLaunchKernelGGL((k_combine<V, TP>), dim3(tot), dim3(kBlock), 0, s, ev.start, ev.stop, 0, b);
+            hipExtLaunchKernelGGL((k_combine<V, TP>), dim3(tot), dim3(kCombBlock), 0, s, ev.start, ev.stop, 0, b);
     }
     check_launch("apply");
 }
@@ -1086,12 +1138,13 @@ static void build_product_graph(Op& op, bool f64, int normalised, int nrhs, Prod
     base.nrhs = nrhs;
     base.op[0] = f64 ? op.dev64.get() : op.devT.get();
     base.pre[0] = 0;
-    auto kernel = [&](void* func, dim3 grid, Batch bb, std::vector<hipGraphNode_t> deps, hipKernelNodeParams* keep) {
+    auto kernel = [&](void* func, dim3 grid, Batch bb, std::vector<hipGraphNode_t> deps, hipKernelNodeParams* keep,
+                      int threads = kBlock) {
         hipKernelNodeParams p{};
         void* args[] = {&bb};
         p.func = func;
         p.gridDim = grid;
-        p.blockDim = dim3(kBlock);
+        p.blockDim = dim3(threads);
         p.sharedMemBytes = 0;
         p.kernelParams = args;
         p.extra = nullptr;
@@ -1140,7 +1193,7 @@ static void build_product_graph(Op& op, bool f64, int normalised, int nrhs, Prod
     bc.arg[0] = normalised;
     bc.pre[1] = op.L;
     G.combine = kernel(multi ? reinterpret_cast<void*>(&k_combine_m<V, TP>) : reinterpret_cast<void*>(&k_combine<V, TP>),
-                       dim3(op.L), bc, comb_deps, &G.comb_p);
+                       dim3(op.L), bc, comb_deps, &G.comb_p, multi ? kBlock : kCombBlock);
     G.comb_b = bc;
     HDM_HIP(hipGraphInstantiate(&G.exec, G.g, nullptr, nullptr, 0));
 }
