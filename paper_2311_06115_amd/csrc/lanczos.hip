@@ -266,103 +266,179 @@ __device__ inline int sturm_below(const double* a, const double* b2, int m, doub
     return cnt;
 }
 
-// One wave per requested eigenvalue (k-th largest, k < r): multisection of the
-// Gershgorin interval with 64 Sturm counts per round, then inverse iteration
-// (two steps, Gaussian elimination with partial pivoting of T - theta I) for
-// the eigenvector.  Outputs theta[k], Y[:, k] (m entries, unit norm) and the
-// residual bound |beta_last * Y[m-1, k]|.
-__global__ void k_tridiag(const double* alpha, const double* beta, int m, int r, double* theta, double* Y,
-                          double* bound, double* work) {
-    __shared__ double a[1024], b2[1024], bb[1024];
-    for (int i = threadIdx.x; i < m; i += blockDim.x) {
-        a[i] = alpha[i];
-        if (i + 1 < m) { b2[i] = beta[i] * beta[i]; bb[i] = beta[i]; }
+// One 64-lane workgroup per requested eigenvalue (k-th largest, k < r):
+// multisection of the Gershgorin interval with 64 Sturm counts per round, then
+// inverse iteration (three solves with one Gaussian elimination with partial
+// pivoting of T - theta I) for the eigenvector.  T, the factors and the
+// iterate live in shared memory (tridiag_shmem(m) bytes); the sequential
+// passes of the elimination run on lane 0 in chunks of kTriChunk rows whose
+// operands are loaded together, so one shared-memory round trip serves a
+// chunk.  Outputs theta[k], Y[:, k] (m entries, unit norm) and the residual
+// bound |beta_last * Y[m-1, k]|.
+constexpr int kTriChunk = 8;
+
+inline size_t tridiag_shmem(int m) {
+    const size_t slots = static_cast<size_t>(m) + kTriChunk + 2;
+    return slots * (8 * sizeof(double) + 1);
+}
+
+__global__ void __launch_bounds__(64) k_tridiag(const double* alpha, const double* beta, int m, int r,
+                                                double* theta, double* Y, double* bound) {
+    extern __shared__ double tsh[];
+    const int ms = m + kTriChunk + 2;   // slots per array: chunk loads may run past m
+    double* a = tsh;
+    double* b2 = a + ms;
+    double* bb = b2 + ms;
+    double* u0 = bb + ms;   // U diagonal
+    double* u1 = u0 + ms;
+    double* u2 = u1 + ms;
+    double* lmul = u2 + ms;
+    double* x = lmul + ms;
+    unsigned char* swp = reinterpret_cast<unsigned char*>(x + ms);   // 1: rows i, i+1 exchanged
+    const int lane = threadIdx.x;
+    const int k = blockIdx.x;
+    for (int i = lane; i < ms; i += 64) {
+        const bool in = i < m, off = i + 1 < m;
+        a[i] = in ? alpha[i] : 0.0;
+        bb[i] = off ? beta[i] : 0.0;
+        b2[i] = off ? beta[i] * beta[i] : 0.0;
+        x[i] = in ? 1.0 : 0.0;
+        u0[i] = u1[i] = u2[i] = lmul[i] = 0.0;
+        swp[i] = 0;
     }
     __syncthreads();
-    const int wv = threadIdx.x / 64, lane = threadIdx.x % 64, nw = blockDim.x / 64;
-    // Gershgorin bounds
+    // Gershgorin bounds: each lane over a strided share of the rows, then the
+    // wave's min / max (exact, so the order does not matter)
     double lo = INFINITY, hi = -INFINITY, amax = 0.0;
-    for (int i = 0; i < m; ++i) {
-        const double rad = (i > 0 ? fabs(bb[i - 1]) : 0.0) + (i + 1 < m ? fabs(bb[i]) : 0.0);
+    for (int i = lane; i < m; i += 64) {
+        const double rad = (i > 0 ? fabs(bb[i - 1]) : 0.0) + fabs(bb[i]);
         lo = fmin(lo, a[i] - rad);
         hi = fmax(hi, a[i] + rad);
         amax = fmax(amax, fabs(a[i]) + rad);
     }
+    for (int off = 32; off > 0; off >>= 1) {
+        lo = fmin(lo, __shfl_xor(lo, off, 64));
+        hi = fmax(hi, __shfl_xor(hi, off, 64));
+        amax = fmax(amax, __shfl_xor(amax, off, 64));
+    }
     const double tiny = 1e-300 + amax * 1e-300;
-    for (int k = blockIdx.x * nw + wv; k < r; k += gridDim.x * nw) {
-        const int target = m - 1 - k;   // index in ascending order
-        double l = lo - 1e-12 * (fabs(lo) + 1.0), h = hi + 1e-12 * (fabs(hi) + 1.0);
-        for (int round = 0; round < 12; ++round) {
-            const double x = l + (h - l) * (lane + 1) / 65.0;
-            const int c = sturm_below(a, b2, m, x, tiny);
-            // largest x with count <= target, smallest with count > target
-            const unsigned long long le = __ballot(c <= target);
-            const int nle = __popcll(le);   // counts are monotone in x: lanes 0..nle-1 satisfy it
-            const double nl = nle > 0 ? l + (h - l) * nle / 65.0 : l;
-            const double nh = nle < 64 ? l + (h - l) * (nle + 1) / 65.0 : h;
-            l = nl;
-            h = nh;
-            if (h - l <= 2.0 * 2.220446049250313e-16 * fmax(fabs(l), fabs(h))) break;
-        }
-        const double th = 0.5 * (l + h);
-        // inverse iteration on lane 0 (sequential tridiagonal elimination)
-        if (lane == 0) {
-            double* swp = work + static_cast<int64_t>(k) * 5 * m;   // 1: rows i, i+1 exchanged
-            double* u0 = swp + m;   // U diagonal
-            double* u1 = swp + 2 * m;
-            double* u2 = swp + 3 * m;
-            double* lmul = swp + 4 * m;
-            const double shift_eps = 2.220446049250313e-16 * fmax(amax, 1e-300);
-            // LU with partial pivoting of T - th I, rows i and i+1
-            double d = a[0] - th, e = m > 1 ? bb[0] : 0.0, f = 0.0;
-            for (int i = 0; i < m - 1; ++i) {
-                const double sub = bb[i];
-                const double dn = a[i + 1] - th, en = (i + 2 < m) ? bb[i + 1] : 0.0;
+    const int target = m - 1 - k;   // index in ascending order
+    double l = lo - 1e-12 * (fabs(lo) + 1.0), h = hi + 1e-12 * (fabs(hi) + 1.0);
+    for (int round = 0; round < 12; ++round) {
+        const double xs = l + (h - l) * (lane + 1) / 65.0;
+        const int c = sturm_below(a, b2, m, xs, tiny);
+        // largest x with count <= target, smallest with count > target
+        const unsigned long long le = __ballot(c <= target);
+        const int nle = __popcll(le);   // counts are monotone in x: lanes 0..nle-1 satisfy it
+        const double nl = nle > 0 ? l + (h - l) * nle / 65.0 : l;
+        const double nh = nle < 64 ? l + (h - l) * (nle + 1) / 65.0 : h;
+        l = nl;
+        h = nh;
+        if (h - l <= 2.0 * 2.220446049250313e-16 * fmax(fabs(l), fabs(h))) break;
+    }
+    const double th = 0.5 * (l + h);
+    const double shift_eps = 2.220446049250313e-16 * fmax(amax, 1e-300);
+    if (lane == 0) {
+        // LU with partial pivoting of T - th I, rows i and i+1; the carried
+        // (d, e) is the pending row i
+        double d = a[0] - th, e = bb[0];
+        for (int i0 = 0; i0 < m - 1; i0 += kTriChunk) {
+            double ac[kTriChunk], bc[kTriChunk + 1];
+#pragma unroll
+            for (int u = 0; u < kTriChunk; ++u) { ac[u] = a[i0 + 1 + u]; bc[u] = bb[i0 + u]; }
+            bc[kTriChunk] = bb[i0 + kTriChunk];
+#pragma unroll
+            for (int u = 0; u < kTriChunk; ++u) {
+                const int i = i0 + u;
+                if (i >= m - 1) break;
+                const double sub = bc[u];
+                const double dn = ac[u] - th, en = (i + 2 < m) ? bc[u + 1] : 0.0;
                 if (fabs(d) >= fabs(sub)) {
                     const double piv_v = d == 0.0 ? shift_eps : d;
                     const double mult = sub / piv_v;
-                    u0[i] = piv_v; u1[i] = e; u2[i] = f;
+                    u0[i] = piv_v; u1[i] = e; u2[i] = 0.0;
                     lmul[i] = mult;
                     d = dn - mult * e;
-                    e = en - mult * 0.0;
-                    f = 0.0;
-                    swp[i] = 0.0;
+                    e = en;
+                    swp[i] = 0;
                 } else {
                     const double mult = d / sub;
                     u0[i] = sub; u1[i] = dn; u2[i] = en;
                     lmul[i] = mult;
                     d = e - mult * dn;
                     e = 0.0 - mult * en;
-                    f = 0.0;
-                    swp[i] = 1.0;
+                    swp[i] = 1;
                 }
             }
-            u0[m - 1] = d == 0.0 ? shift_eps : d;
-            // two solves with the same factors; start from the all-ones vector
-            double* x = Y + static_cast<int64_t>(k) * m;
-            for (int i = 0; i < m; ++i) x[i] = 1.0;
-            for (int iter = 0; iter < 3; ++iter) {
-                // forward elimination of the right-hand side
-                for (int i = 0; i < m - 1; ++i) {
-                    if (swp[i] != 0.0) { const double t = x[i]; x[i] = x[i + 1]; x[i + 1] = t; }
-                    x[i + 1] -= lmul[i] * x[i];
-                }
-                // back substitution with U (bandwidth 2)
-                for (int i = m - 1; i >= 0; --i) {
-                    double v = x[i];
-                    if (i + 1 < m) v -= u1[i] * x[i + 1];
-                    if (i + 2 < m) v -= u2[i] * x[i + 2];
-                    x[i] = v / u0[i];
-                }
-                double nrm = 0.0;
-                for (int i = 0; i < m; ++i) nrm += x[i] * x[i];
-                nrm = sqrt(nrm);
-                for (int i = 0; i < m; ++i) x[i] /= nrm;
-            }
-            theta[k] = th;
-            bound[k] = fabs(beta[m - 1] * x[m - 1]);
         }
+        u0[m - 1] = d == 0.0 ? shift_eps : d;
     }
+    for (int iter = 0; iter < 3; ++iter) {
+        if (lane == 0) {
+            // forward elimination of the right-hand side; c is the current x[i]
+            double c = x[0];
+            for (int i0 = 0; i0 < m - 1; i0 += kTriChunk) {
+                double lm[kTriChunk], nx[kTriChunk];
+                unsigned char sw[kTriChunk];
+#pragma unroll
+                for (int u = 0; u < kTriChunk; ++u) { lm[u] = lmul[i0 + u]; nx[u] = x[i0 + 1 + u]; sw[u] = swp[i0 + u]; }
+#pragma unroll
+                for (int u = 0; u < kTriChunk; ++u) {
+                    const int i = i0 + u;
+                    if (i >= m - 1) break;
+                    const double xi = sw[u] ? nx[u] : c, xn = sw[u] ? c : nx[u];
+                    x[i] = xi;
+                    c = xn - lm[u] * xi;
+                }
+            }
+            x[m - 1] = c;
+            // back substitution with U (bandwidth 2); x1, x2 are x[i+1], x[i+2]
+            double x1 = 0.0, x2 = 0.0;
+            for (int top = m - 1; top >= 0; top -= kTriChunk) {
+                double xv[kTriChunk], d0[kTriChunk], d1[kTriChunk], d2[kTriChunk];
+#pragma unroll
+                for (int u = 0; u < kTriChunk; ++u) {
+                    const int i = top - u < 0 ? 0 : top - u;
+                    xv[u] = x[i]; d0[u] = u0[i]; d1[u] = u1[i]; d2[u] = u2[i];
+                }
+#pragma unroll
+                for (int u = 0; u < kTriChunk; ++u) {
+                    const int i = top - u;
+                    if (i < 0) break;
+                    double v = xv[u];
+                    if (i + 1 < m) v -= d1[u] * x1;
+                    if (i + 2 < m) v -= d2[u] * x2;
+                    const double xi = v / d0[u];
+                    x[i] = xi;
+                    x2 = x1;
+                    x1 = xi;
+                }
+            }
+        }
+        __syncthreads();
+        double ss = 0.0;
+        for (int i = lane; i < m; i += 64) ss += x[i] * x[i];
+        for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off, 64);
+        const double nrm = sqrt(ss);
+        for (int i = lane; i < m; i += 64) x[i] /= nrm;
+        __syncthreads();
+    }
+    double* y = Y + static_cast<int64_t>(k) * m;
+    for (int i = lane; i < m; i += 64) y[i] = x[i];
+    if (lane == 0) {
+        theta[k] = th;
+        bound[k] = fabs(beta[m - 1] * x[m - 1]);
+    }
+}
+
+// one workgroup per eigenvalue, shared memory set for the basis size
+static void launch_tridiag(const double* alpha, const double* beta, int m, int r, double* theta, double* Y,
+                           double* bound, hipStream_t s, hipEvent_t start = nullptr, hipEvent_t stop = nullptr) {
+    const size_t shmem = tridiag_shmem(m);
+    if (shmem > 65536)
+        HDM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tridiag),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(shmem)));
+    hipExtLaunchKernelGGL(k_tridiag, dim3(r), dim3(64), shmem, s, start, stop, 0, alpha, beta, m, r, theta, Y, bound);
 }
 
 // Phi[:, k] = V Y[:, k] for k < r (rows per thread)
@@ -743,7 +819,6 @@ void LanczosRun::start(Op& o, int r_, double tol_, int max_basis_, uint64_t seed
     theta.alloc(r);
     bound.alloc(r);
     Y.alloc(static_cast<size_t>(r) * max_basis);
-    work.alloc(static_cast<size_t>(r) * 5 * max_basis);
     counters.alloc(2);
     HDM_HIP(hipMemsetAsync(counters.get(), 0, counters.bytes(), s));
     h_theta.assign(r, 0.0);
@@ -760,7 +835,7 @@ void LanczosRun::start(Op& o, int r_, double tol_, int max_basis_, uint64_t seed
 
 size_t LanczosRun::bytes() const {
     return V.bytes() + y.bytes() + part.bytes() + h1.bytes() + h2.bytes() + np.bytes() + alpha.bytes() +
-           beta.bytes() + theta.bytes() + bound.bytes() + Y.bytes() + work.bytes();
+           beta.bytes() + theta.bytes() + bound.bytes() + Y.bytes();
 }
 
 bool LanczosRun::after_product(hipStream_t s) {
@@ -783,8 +858,7 @@ bool LanczosRun::after_product(hipStream_t s) {
     if (m >= r && ((m % check_every) == 0 || last)) {
         {
             KernelEvents ev(op->ctx, HDM_PHASE_TRIDIAG);
-            hipExtLaunchKernelGGL(k_tridiag, dim3(ceil_div(r, 4)), dim3(kBlock), 0, s, ev.start, ev.stop, 0,
-                                  alpha.get(), beta.get(), m, r, theta.get(), Y.get(), bound.get(), work.get());
+            launch_tridiag(alpha.get(), beta.get(), m, r, theta.get(), Y.get(), bound.get(), s, ev.start, ev.stop);
         }
         check_launch("tridiagonal eigensolve");
         theta.download(h_theta.data(), r, s);
@@ -858,8 +932,7 @@ static hdm_status block_lanczos_eigs(Op& op, int r, double tol, int b, int max_b
     const int64_t ldp = static_cast<int64_t>(mb + b) * b;
     DevBuf<double> V(static_cast<size_t>(n) * (mb + b)), Y(static_cast<size_t>(n) * b), part(static_cast<size_t>(nbk) * ldp),
         H1(ldp), H2(ldp), G(b * b), Rinv(b * b), Rtot(b * b), T(static_cast<size_t>(ldt) * ldt),
-        A(static_cast<size_t>(mb) * mb), dd(mb), ee(mb), tau(mb), theta(r), Z(static_cast<size_t>(r) * mb), bound(r),
-        work(static_cast<size_t>(r) * 5 * mb);
+        A(static_cast<size_t>(mb) * mb), dd(mb), ee(mb), tau(mb), theta(r), Z(static_cast<size_t>(r) * mb), bound(r);
     DevBuf<int> status(1);
     HDM_HIP(hipMemsetAsync(status.get(), 0, sizeof(int), s));
     HDM_HIP(hipMemsetAsync(T.get(), 0, T.bytes(), s));
@@ -915,8 +988,7 @@ static hdm_status block_lanczos_eigs(Op& op, int r, double tol, int b, int max_b
                 hipExtLaunchKernelGGL(k_sytrd, dim3(1), dim3(1024), 0, s, ev.start, ev.stop, 0, T.get(), ldt, m,
                                       A.get(), mb, dd.get(), ee.get(), tau.get());
             }
-            hipLaunchKernelGGL(k_tridiag, dim3(ceil_div(r, 4)), dim3(kBlock), 0, s, dd.get(), ee.get(), m, r,
-                               theta.get(), Z.get(), bound.get(), work.get());
+            launch_tridiag(dd.get(), ee.get(), m, r, theta.get(), Z.get(), bound.get(), s);
             hipLaunchKernelGGL(k_ormtr, dim3(1), dim3(1024), 0, s, A.get(), mb, tau.get(), m, Z.get(), r);
             hipLaunchKernelGGL(k_block_bounds, dim3(1), dim3(64), 0, s, Z.get(), m, b, Rtot.get(), r, bound.get());
             check_launch("block rayleigh-ritz");

@@ -283,7 +283,7 @@ struct LanczosRun {
     uint64_t seed = 0;
     int64_t n = 0;
     int nb = 0, ldp = 0;
-    DevBuf<double> V, y, part, h1, h2, np, alpha, beta, theta, bound, Y, work;
+    DevBuf<double> V, y, part, h1, h2, np, alpha, beta, theta, bound, Y;
     DevBuf<unsigned> counters;   // arrival counters of the last-workgroup reductions (zero between launches)
     std::vector<double> h_theta, h_bound;
     int j = 0, m = 0, matvecs = 0;
