@@ -635,6 +635,7 @@ __global__ void k_row_count(LevelArgs A) {
 // that is all there is).  The draws are taken 64 at a time by one wave and
 // accepted in draw order, exactly as a sequential rejection loop would.
 constexpr int kMaxRows = 1024;   // sampled rows per node (2 max_rank_s)
+constexpr int kIdSink = 8;       // shared-memory slots of the ID that absorb padded stores
 constexpr int kVoteShared = 144 * 1024;   // shared memory for the bitmap vote counting (bytes)
 
 // kSorted: the candidates' outside neighbours are marked in a bitmap over the
@@ -918,15 +919,18 @@ __global__ void k_block(LevelArgs A, Pts P) {
 // in global memory (gB, leading dimension nc).
 typedef __attribute__((address_space(3))) double lds_f64;   // a float64 in shared memory
 
+// B of one node: rows [T0, T0 + R) = [T0, nr) staged in shared memory (the
+// trailing rows, which every reflector touches), the leading rows in global
+// memory.
 struct QrBlock {
     lds_f64* sB;
     double* gB;
-    int nc, ldS, R;
+    int nc, ldS, R, T0;
     __device__ double ld(int i, int c) const {
-        return i < R ? sB[i * ldS + c] : gB[static_cast<int64_t>(i) * nc + c];
+        return i >= T0 ? sB[(i - T0) * ldS + c] : gB[static_cast<int64_t>(i) * nc + c];
     }
     __device__ void st(int i, int c, double x) const {
-        if (i < R) sB[i * ldS + c] = x;
+        if (i >= T0) sB[(i - T0) * ldS + c] = x;
         else gB[static_cast<int64_t>(i) * nc + c] = x;
     }
 };
@@ -940,23 +944,23 @@ template <int L, bool kWrite, typename Body>
 __device__ inline void group_rows(const QrBlock& Q, int lane, int c, int i0, int i1, Body&& body) {
     constexpr int PH = 8 / L, KB = L == 1 ? 2 : 8 / PH, SPAN = 8 * KB;   // 16 or 8 loads per lane and batch
     int i = i0;
-    const int rl = min(Q.R, i1);
-    for (; i + SPAN <= rl; i += SPAN) {   // rows in shared memory
+    const int gl = min(Q.T0, i1);
+    for (; i + SPAN <= gl; i += SPAN) {   // rows in global memory (i < T0)
         double x[KB][PH];
 #pragma unroll
         for (int k = 0; k < KB; ++k)
 #pragma unroll
-            for (int m = 0; m < PH; ++m) x[k][m] = Q.sB[(i + 8 * k + lane + L * m) * Q.ldS + c];
+            for (int m = 0; m < PH; ++m) x[k][m] = Q.gB[static_cast<int64_t>(i + 8 * k + lane + L * m) * Q.nc + c];
 #pragma unroll
         for (int k = 0; k < KB; ++k)
 #pragma unroll
             for (int m = 0; m < PH; ++m) {
                 const int r = i + 8 * k + lane + L * m;
                 body(m, r, x[k][m]);
-                if (kWrite) Q.sB[r * Q.ldS + c] = x[k][m];
+                if (kWrite) Q.gB[static_cast<int64_t>(r) * Q.nc + c] = x[k][m];
             }
     }
-    if (i < rl && i + SPAN <= i1) {   // the batch across R
+    if (i < Q.T0 && i + SPAN <= i1) {   // the batch across T0
         double x[KB][PH];
 #pragma unroll
         for (int k = 0; k < KB; ++k)
@@ -972,19 +976,19 @@ __device__ inline void group_rows(const QrBlock& Q, int lane, int c, int i0, int
             }
         i += SPAN;
     }
-    for (; i + SPAN <= i1; i += SPAN) {   // rows in global memory (i >= R)
+    for (; i + SPAN <= i1; i += SPAN) {   // rows in shared memory (i >= T0)
         double x[KB][PH];
 #pragma unroll
         for (int k = 0; k < KB; ++k)
 #pragma unroll
-            for (int m = 0; m < PH; ++m) x[k][m] = Q.gB[static_cast<int64_t>(i + 8 * k + lane + L * m) * Q.nc + c];
+            for (int m = 0; m < PH; ++m) x[k][m] = Q.sB[(i - Q.T0 + 8 * k + lane + L * m) * Q.ldS + c];
 #pragma unroll
         for (int k = 0; k < KB; ++k)
 #pragma unroll
             for (int m = 0; m < PH; ++m) {
                 const int r = i + 8 * k + lane + L * m;
                 body(m, r, x[k][m]);
-                if (kWrite) Q.gB[static_cast<int64_t>(r) * Q.nc + c] = x[k][m];
+                if (kWrite) Q.sB[(r - Q.T0) * Q.ldS + c] = x[k][m];
             }
     }
     if (i < i1) {   // last partial batch; (i - i0) is a multiple of 8 here
@@ -1055,10 +1059,14 @@ __device__ inline void id_reflect(const QrBlock& Q, const double* hv, double* ns
         double p[PH];
 #pragma unroll
         for (int m = 0; m < PH; ++m) p[m] = 0.0;
-        group_rows<L, false>(Q, lane, c, j, nr, [&](int m, int i, double& x) { p[m] = p[m] + hv[i] * x; });
+        double xj = 0.0;   // the pivot row's entry, seen by lane 0 (phase 0)
+        group_rows<L, false>(Q, lane, c, j, nr, [&](int m, int i, double& x) {
+            p[m] = p[m] + hv[i] * x;
+            if (i == j) xj = x;
+        });
         const double f = (2.0 * group_total<L>(p)) / vtv;
         // the pivot row first (its square is not part of the next norm), then the rest
-        if (lane == 0) Q.st(j, c, Q.ld(j, c) - f * hv[j]);
+        if (lane == 0) Q.st(j, c, xj - f * hv[j]);
 #pragma unroll
         for (int m = 0; m < PH; ++m) p[m] = 0.0;
         group_rows<L, true>(Q, lane, c, j + 1, nr, [&](int m, int i, double& x) {
@@ -1070,20 +1078,107 @@ __device__ inline void id_reflect(const QrBlock& Q, const double* hv, double* ns
     }
 }
 
+// The reflector of step j formed and applied with each column's rows [j, nr)
+// in registers, once every active row is staged in shared memory (j >= T0):
+// every lane group builds hv from column j and its own v^T v.  The 8 lanes of a
+// group share a column, lane l holding rows j + l + 8u (u < NPL), which it
+// reads once and writes once; a group takes NCOL columns at a time (kBlock / 8
+// apart) so that their dependent sums interleave.  The dot product's phase l
+// sits on lane l (the order of group_total<8>).  The next norm is over rows
+// [j + 1, nr), whose phase k = (i - j - 1) mod 8 sits on lane (k + 1) mod 8,
+// so the partials move one lane down before the same combination.  The lane's
+// entries of hv stay in registers for the whole step, zero past row nr - 1: a
+// row slot past the end reads row nr - 1 and adds an exact zero to the dot
+// product (a sum that starts at +0 is never -0, so adding +-0 leaves it
+// unchanged), is not added to the norm and is stored to the sink.  A column
+// slot past nc works on column nc - 1 and stores only to the sink.
+template <int NPL, int NCOL>
+__device__ inline void id_reflect_regs(const QrBlock& Q, lds_f64* sink, double* nsq, int j, int nr, int nc,
+                                       double v0) {
+    constexpr int kGroups = kBlock / 8;
+    const int l = threadIdx.x % 8;
+    const int gbase = (threadIdx.x % kWave) & ~7;
+    // hv = column j below row j with v0 = x0 - alpha in row j, and v^T v
+    // summed by the same phases (lane l: rows j + l + 8u)
+    double hreg[NPL];
+#pragma unroll
+    for (int u = 0; u < NPL; ++u) {
+        const int i = j + l + 8 * u;
+        hreg[u] = i < nr ? Q.sB[(i - Q.T0) * Q.ldS + j] : 0.0;
+    }
+    if (l == 0) hreg[0] = v0;
+    double pv = 0.0;
+#pragma unroll
+    for (int u = 0; u < NPL; ++u) pv = pv + hreg[u] * hreg[u];
+    const double vtv = group_total<8>(&pv);
+    const int first = (j + l - Q.T0) * Q.ldS;   // staged offset of the lane's first row (column 0)
+    const int step = 8 * Q.ldS;
+    const int last = (nr - 1 - Q.T0) * Q.ldS;
+    for (int c0 = j + 1 + threadIdx.x / 8; c0 < nc; c0 += NCOL * kGroups) {
+        int lim = last;
+        asm volatile("" : "+v"(lim));   // row bounds tested per column, not held as masks
+        int cc[NCOL];
+        bool ok[NCOL];
+#pragma unroll
+        for (int v = 0; v < NCOL; ++v) {
+            ok[v] = c0 + v * kGroups < nc;
+            cc[v] = ok[v] ? c0 + v * kGroups : nc - 1;
+        }
+        double x[NCOL][NPL];
+#pragma unroll
+        for (int u = 0; u < NPL; ++u)
+#pragma unroll
+            for (int v = 0; v < NCOL; ++v) x[v][u] = Q.sB[min(first + u * step, lim) + cc[v]];
+        double p[NCOL];
+#pragma unroll
+        for (int v = 0; v < NCOL; ++v) p[v] = 0.0;
+#pragma unroll
+        for (int u = 0; u < NPL; ++u)
+#pragma unroll
+            for (int v = 0; v < NCOL; ++v) p[v] = p[v] + hreg[u] * x[v][u];
+        double f[NCOL], q[NCOL];
+#pragma unroll
+        for (int v = 0; v < NCOL; ++v) {
+            f[v] = (2.0 * group_total<8>(&p[v])) / vtv;
+            q[v] = 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < NPL; ++u) {
+            const int off = first + u * step;
+#pragma unroll
+            for (int v = 0; v < NCOL; ++v) {
+                const double xu = x[v][u] - f[v] * hreg[u];
+                const double qu = q[v] + xu * xu;
+                q[v] = (off <= lim && (u > 0 || l > 0)) ? qu : q[v];   // row j is not part of the next norm
+                lds_f64* dst = (off <= lim && ok[v]) ? Q.sB + (off + cc[v]) : sink;
+                *dst = xu;
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < NCOL; ++v) {
+            double r = __shfl(q[v], gbase + ((l + 1) & 7), kWave);   // phase l of the norm
+            const double t = group_total<8>(&r);
+            if (l == 0 && ok[v]) nsq[cc[v]] = t;
+        }
+    }
+}
+
 // Columns c >= rank of P = R11^-1 R12 by back substitution, one thread per
 // column, each entry a sequential sum in q: acc = R[i][c] - sum_q R[i][q] X[q].
-// With kLds the solution column is kept in the free rows [rank, 2 rank) of the
-// staged block and copied to P at the end; otherwise it is built in P directly.
+// With kLds the solution column is kept in the last rank staged rows (rows
+// [nr - rank, nr), free once nr >= 2 rank) and copied to P at the end;
+// otherwise it is built in P directly.
 template <bool kLds>
 __device__ inline void id_back_subst(const QrBlock& Q, double* Pm, const int32_t* cp, int rank, int nc) {
+    const int x0 = Q.R - rank;   // staged slot of X[0]
     for (int c = rank + threadIdx.x; c < nc; c += blockDim.x) {
         const int pc = cp[c];
         auto xld = [&](int q) -> double {
-            if constexpr (kLds) return Q.sB[(rank + q) * Q.ldS + c];
+            if constexpr (kLds) return Q.sB[(x0 + q) * Q.ldS + c];
             else return Pm[static_cast<int64_t>(q) * nc + pc];
         };
         auto xst = [&](int q, double v) {
-            if constexpr (kLds) Q.sB[(rank + q) * Q.ldS + c] = v;
+            if constexpr (kLds) Q.sB[(x0 + q) * Q.ldS + c] = v;
             else Pm[static_cast<int64_t>(q) * nc + pc] = v;
         };
         for (int i = rank - 1; i >= 0; --i) {
@@ -1127,10 +1222,29 @@ __device__ inline void wg_argmax(double& v, int& c, double* sv, int* sc) {
     __syncthreads();
 }
 
+// rows x nc values from global memory (row stride nc) into staged rows
+// (stride ldS), eight loads in flight per thread
+__device__ inline void stage_rows(lds_f64* dst, int ldS, const double* src, int nc, int rows) {
+    const int n = rows * nc;
+    for (int e0 = threadIdx.x; e0 < n; e0 += 8 * kBlock) {
+        double v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int e = e0 + k * kBlock;
+            v[k] = e < n ? src[e] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int e = e0 + k * kBlock;
+            if (e < n) dst[(e / nc) * ldS + e % nc] = v[k];
+        }
+    }
+}
+
 // Householder QR with column pivoting of B (nr x nc) and the interpolation
 // matrix P = [I, R11^-1 R12] in candidate order.  One workgroup per node, one
 // thread per column for the column sums (each a fixed-order sum, see above).
-// The leading rows of B are staged in shared memory (as many as fit, A.lds_b
+// The trailing rows of B are staged in shared memory (as many as fit, A.lds_b
 // elements); the squared norms that choose the next pivot are accumulated
 // while the reflector is applied.
 __global__ void __launch_bounds__(kBlock) k_pivoted_id(LevelArgs A) {
@@ -1141,17 +1255,19 @@ __global__ void __launch_bounds__(kBlock) k_pivoted_id(LevelArgs A) {
     const int64_t t = blockIdx.x;
     const int nc = A.ncand[t], nr = A.nrows[t];
     double* hv = dyn;                 // Householder vector (A.rmax)
-    double* nsq = dyn + A.rmax;       // remaining squared column norms (A.cmax)
+    lds_f64* sink = (lds_f64*)(dyn + A.rmax);   // kIdSink slots that absorb stores of row slots past the end
+    double* nsq = dyn + A.rmax + kIdSink;   // remaining squared column norms (A.cmax)
     QrBlock Q;
     Q.sB = (lds_f64*)(nsq + A.cmax);   // address-space cast: dyn is shared memory
     Q.gB = A.B + t * static_cast<int64_t>(A.rmax) * A.cmax;
     Q.nc = nc;
     Q.ldS = nc | 1;
     Q.R = nc > 0 ? min(nr, static_cast<int>(A.lds_b / Q.ldS)) : 0;
+    Q.T0 = nr - Q.R;
     int32_t* cp = A.cp + t * A.cmax;
     const int64_t h = (int64_t(1) << A.lvl) + t;
     double* Pm = A.Pfix + h * A.s * A.cmax;
-    for (int e = threadIdx.x; e < Q.R * nc; e += blockDim.x) Q.sB[(e / nc) * Q.ldS + e % nc] = Q.gB[e];
+    stage_rows(Q.sB, Q.ldS, Q.gB + static_cast<int64_t>(Q.T0) * nc, nc, Q.R);
     for (int c = threadIdx.x; c < nc; c += blockDim.x) cp[c] = c;
     __syncthreads();
     switch (id_lanes(nc)) {
@@ -1189,6 +1305,17 @@ __global__ void __launch_bounds__(kBlock) k_pivoted_id(LevelArgs A) {
         }
         if (j == 0) r11 = best;
         if (!(best > A.tau * r11)) break;   // uniform: every thread holds the same best and r11
+        if (j >= Q.T0 && nr <= 8 * 32) {
+            // rows [j, nr) all staged: the reflector lives in registers
+            const double x0 = Q.sB[(j - Q.T0) * Q.ldS + j];
+            const double alpha = x0 >= 0.0 ? -best : best;
+            id_reflect_regs<32, 2>(Q, sink, nsq, j, nr, nc, x0 - alpha);
+            __syncthreads();
+            for (int i = j + threadIdx.x; i < nr; i += blockDim.x) Q.sB[(i - Q.T0) * Q.ldS + j] = (i == j) ? alpha : 0.0;
+            rank = j + 1;
+            __syncthreads();
+            continue;
+        }
         for (int i = j + threadIdx.x; i < nr; i += blockDim.x) hv[i] = Q.ld(i, j);
         __syncthreads();
         if (threadIdx.x < 8) {
@@ -1238,7 +1365,14 @@ __global__ void __launch_bounds__(kBlock) k_pivoted_id(LevelArgs A) {
     for (int64_t e = threadIdx.x; e < static_cast<int64_t>(rank) * nc; e += blockDim.x) Pm[e] = 0.0;
     __syncthreads();
     for (int j = threadIdx.x; j < rank; j += blockDim.x) Pm[static_cast<int64_t>(j) * nc + cp[j]] = 1.0;
-    if (2 * rank <= Q.R) id_back_subst<true>(Q, Pm, cp, rank, nc);
+    if (Q.T0 >= rank && 2 * rank <= Q.R) {
+        // the rows of R are all in global memory and the staged rows are free
+        // (they hold rows >= T0 >= rank): stage R at the front for the solve
+        stage_rows(Q.sB, Q.ldS, Q.gB, nc, rank);
+        Q.T0 = 0;
+        __syncthreads();
+    }
+    if (rank <= Q.R && 2 * rank <= nr) id_back_subst<true>(Q, Pm, cp, rank, nc);
     else id_back_subst<false>(Q, Pm, cp, rank, nc);
     if (threadIdx.x == 0) A.rk[h] = rank;
 }
@@ -1600,9 +1734,9 @@ static void skeletonize_levels(Op& op, const Geo& G, hipStream_t s, SkelRun& R) 
         HDM_HIP(hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(&k_pivoted_id)));
         const int64_t avail = (static_cast<int64_t>(max_shared) - static_cast<int64_t>(fa.sharedSizeBytes)) /
                               static_cast<int64_t>(sizeof(double));
-        HDM_CHECK(avail >= rmax + cmax, HDM_EINTERNAL, "shared memory too small for the ID's vectors");
-        id_lds = avail - rmax - cmax;
-        id_shmem = sizeof(double) * static_cast<size_t>(rmax + cmax + id_lds);
+        HDM_CHECK(avail >= rmax + kIdSink + cmax, HDM_EINTERNAL, "shared memory too small for the ID's vectors");
+        id_lds = avail - rmax - kIdSink - cmax;
+        id_shmem = sizeof(double) * static_cast<size_t>(rmax + kIdSink + cmax + id_lds);
         if (id_shmem > 65536)
             HDM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pivoted_id),
                                         hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(id_shmem)));
