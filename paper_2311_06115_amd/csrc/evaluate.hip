@@ -68,6 +68,7 @@ __device__ inline A wave_sum(A v) {
 // operator's vectors.
 struct Batch {
     int nops, nrhs;
+    int flip;                     // near field: work items taken in reverse order
     const OpDev* op[kMaxBatch];
     int64_t pre[kMaxBatch + 1];
     int32_t arg[kMaxBatch];       // per operator: tree level (N2S) or normalised flag (prep, combine)
@@ -162,8 +163,9 @@ __global__ void k_s2s(Batch b) {
 template <typename V, typename TN>
 __global__ void __launch_bounds__(kBlock) k_l2l(Batch b) {
     constexpr int RPL = 16 / sizeof(TN);
-    const int64_t u = blockIdx.x * static_cast<int64_t>(blockDim.x / kWave) + threadIdx.x / kWave;
+    int64_t u = blockIdx.x * static_cast<int64_t>(blockDim.x / kWave) + threadIdx.x / kWave;
     if (u >= b.pre[b.nops]) return;
+    if (b.flip) u = b.pre[b.nops] - 1 - u;
     const int o = batch_op(b, u);
     const OpDev& D = *b.op[o];
     const NearItem I = D.items[u - b.pre[o]];
@@ -545,8 +547,9 @@ __global__ void __launch_bounds__(kBlock) k_prep_mma(Batch b) {
 // One wave per item: up to 8 row tiles of 16 rows of one near tile against all
 // its columns, 32 columns per step, hi and lo halves of the vectors in turn.
 __global__ void __launch_bounds__(kBlock) k_l2l_mma(Batch b) {
-    const int64_t u = blockIdx.x * static_cast<int64_t>(blockDim.x / kWave) + threadIdx.x / kWave;
+    int64_t u = blockIdx.x * static_cast<int64_t>(blockDim.x / kWave) + threadIdx.x / kWave;
     if (u >= b.pre[b.nops]) return;
+    if (b.flip) u = b.pre[b.nops] - 1 - u;
     const int o = batch_op(b, u);
     const OpDev& D = *b.op[o];
     const NearItem I = D.items[u - b.pre[o]];
@@ -990,10 +993,16 @@ static void apply_t(const ApplyReq* reqs, int nops, bool f64, int normalised, in
     // solve at N = 100000 with 16 columns).
     const bool overlap = tree && multi;
     hipStream_t ts = overlap ? lane.side : s;
+    // The near field streams every tile once per product, more bytes than the
+    // device's last-level cache holds; taking the items in reverse order on
+    // every other product starts each pass on the tiles the previous one read
+    // last, which are still cached.  Each item writes its own partial sums, so
+    // the order does not change the result.
     auto near_field = [&] {
         const int64_t tot = prefix([](const Op& op, int) {
             return static_cast<int64_t>(mma ? op.items_mma.size() : op.items.size());
         });
+        b.flip = static_cast<int>(reqs[0].op->near_calls++ & 1u);
         KernelEvents ev(cx, HDM_PHASE_L2L);
         if (mma)
             hipExtLaunchKernelGGL(k_l2l_mma, dim3(ceil_div(tot, wpb)), dim3(kBlock), 0, s, ev.start, ev.stop, 0, b);

@@ -197,6 +197,7 @@ struct Op {
     std::vector<int32_t> near_ld;              // per leaf
     std::vector<int64_t> near_tile_off;        // per near pair (elements; same order as near_idx)
     int64_t near_elems = 0;
+    mutable unsigned near_calls = 0;           // near-field products so far (their tile order alternates)
     DevBuf<double> near64;
     DevBuf<char> nearT;                        // eval precision copy (near_prec)
     DevBuf<float> near_scale;                  // per near pair
