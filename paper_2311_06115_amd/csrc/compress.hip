@@ -471,6 +471,24 @@ __device__ inline bool knn_less(double da, int32_t ia, double db, int32_t ib) {
     return da < db || (da == db && ia < ib);
 }
 
+// Wave-wide lane moves without shared memory: the value of a lane chosen by a
+// wave-uniform index (readlane), and the value of the next lower lane (DPP
+// wave shift right by one; lane 0 keeps its own).
+__device__ inline double lane_value(double v, int src) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_readlane(static_cast<int>(b & 0xffffffffll), src);
+    const int hi = __builtin_amdgcn_readlane(static_cast<int>(b >> 32), src);
+    return __builtin_bit_cast(double, (static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+__device__ inline int32_t lane_value(int32_t v, int src) { return __builtin_amdgcn_readlane(v, src); }
+__device__ inline int32_t from_lower_lane(int32_t v) { return __builtin_amdgcn_update_dpp(v, v, 0x138, 0xF, 0xF, false); }
+__device__ inline double from_lower_lane(double v) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = from_lower_lane(static_cast<int32_t>(b & 0xffffffffll));
+    const int hi = from_lower_lane(static_cast<int32_t>(b >> 32));
+    return __builtin_bit_cast(double, (static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
 __global__ void __launch_bounds__(kKnnBlock) k_knn_leaf(int depth, const int64_t* start, const int64_t* size,
                                                         const int32_t* perm, Pts P, int k, int stage, int splits,
                                                         const int32_t* leafd2, int leafmax, int32_t* kidx,
@@ -517,20 +535,20 @@ __global__ void __launch_bounds__(kKnnBlock) k_knn_leaf(int depth, const int64_t
                 }
             }
             // candidates that beat the current k-th entry
-            const double dk = __shfl(ld, k - 1, 64);
-            const int32_t ik = __shfl(li, k - 1, 64);
+            const double dk = lane_value(ld, k - 1);
+            const int32_t ik = lane_value(li, k - 1);
             uint64_t pend = __ballot(j >= 0 && knn_less(d, j, dk, ik));
             while (pend) {
                 const int src = __ffsll(static_cast<long long>(pend)) - 1;
                 pend &= pend - 1;
-                const double dc = __shfl(d, src, 64);
-                const int32_t jc = __shfl(j, src, 64);
+                const double dc = lane_value(d, src);
+                const int32_t jc = lane_value(j, src);
                 const bool dup = __ballot(lane < k && li == jc) != 0;
                 if (dup) continue;
                 const int pos = __popcll(__ballot(lane < k && knn_less(ld, li, dc, jc)));
                 if (pos >= k) continue;
-                const double up_d = __shfl_up(ld, 1, 64);
-                const int32_t up_i = __shfl_up(li, 1, 64);
+                const double up_d = from_lower_lane(ld);
+                const int32_t up_i = from_lower_lane(li);
                 if (lane == pos) { ld = dc; li = jc; }
                 else if (lane > pos && lane < k) { ld = up_d; li = up_i; }
             }
