@@ -696,15 +696,34 @@ __global__ void k_row_select(LevelArgs A) {
         for (int w = threadIdx.x; w < nw; w += blockDim.x) bm[w] = 0u;
         for (int64_t e = threadIdx.x; e < ntot; e += blockDim.x) sv[e] = 0;
         __syncthreads();
-        auto outside = [&](int64_t e) -> int32_t {   // the neighbour of entry e, or -1
-            const int32_t i = A.kidx[static_cast<int64_t>(cd[e / A.k]) * A.k + e % A.k];
-            if (i < 0) return -1;
-            const int64_t pi = A.iperm[i];
-            return (pi >= lo && pi < hi) ? -1 : i;
+        // the neighbours of entries e0 + kBlock q (q < 8) that lie outside the
+        // node (-1 otherwise), each chain of dependent loads issued for all
+        // eight entries at once
+        auto outside8 = [&](int64_t e0, int32_t* o) {
+            int32_t c[8], i[8];
+            int64_t pi[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int64_t e = min(e0 + q * kBlock, ntot - 1);
+                c[q] = cd[e / A.k];
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int64_t e = min(e0 + q * kBlock, ntot - 1);
+                i[q] = A.kidx[static_cast<int64_t>(c[q]) * A.k + e % A.k];
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) pi[q] = A.iperm[max(i[q], 0)];
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                o[q] = (e0 + q * kBlock >= ntot || i[q] < 0 || (pi[q] >= lo && pi[q] < hi)) ? -1 : i[q];
         };
-        for (int64_t e = threadIdx.x; e < ntot; e += blockDim.x) {
-            const int32_t i = outside(e);
-            if (i >= 0) atomicOr(&bm[i >> 5], 1u << (i & 31));
+        for (int64_t e0 = threadIdx.x; e0 < ntot; e0 += 8 * kBlock) {
+            int32_t o[8];
+            outside8(e0, o);
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (o[q] >= 0) atomicOr(&bm[o[q] >> 5], 1u << (o[q] & 31));
         }
         __syncthreads();
         // words in contiguous ranges per thread: exclusive popcount prefix, then
@@ -726,9 +745,14 @@ __global__ void k_row_select(LevelArgs A) {
         }
         nu = tot;
         __syncthreads();
-        for (int64_t e = threadIdx.x; e < ntot; e += blockDim.x) {
-            const int32_t i = outside(e);
-            if (i >= 0) atomicAdd(&sv[pre[i >> 5] + __popc(bm[i >> 5] & ((1u << (i & 31)) - 1u))], 1);
+        for (int64_t e0 = threadIdx.x; e0 < ntot; e0 += 8 * kBlock) {
+            int32_t o[8];
+            outside8(e0, o);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int32_t i = o[q];
+                if (i >= 0) atomicAdd(&sv[pre[i >> 5] + __popc(bm[i >> 5] & ((1u << (i & 31)) - 1u))], 1);
+            }
         }
         __syncthreads();
         for (int64_t u = threadIdx.x; u < nu; u += blockDim.x) vt[u] = sv[u];
@@ -863,8 +887,9 @@ __global__ void k_row_select(LevelArgs A) {
             const bool valid = !(pc >= lo && pc < hi) && !(bits[c >> 5] & (1u << (c & 31)));
             batch[lane] = valid ? c : -1;
             __builtin_amdgcn_wave_barrier();
-            bool dup = false;
-            for (int l = 0; l < lane; ++l) dup = dup || (batch[l] == c);
+            bool dup = false;   // an earlier draw of this batch has the same point
+#pragma unroll
+            for (int l = 0; l < 64; ++l) dup = dup || (l < lane && batch[l] == c);
             const bool acc = valid && !dup;
             const uint64_t bal = __ballot(acc);
             const int pre = __popcll(bal & ((1ull << lane) - 1ull));
@@ -2116,6 +2141,7 @@ void compress_operator(Op& op, const void* X, int x_on_device, hipStream_t s) {
     DevBuf<NearPair> pairs_dev;
     build_near_tiles(op, G, side, pairs_dev);
     convert_near_tiles(op, side);
+    build_near_plan(op, side);
     HDM_HIP(hipEventRecord(op.lane.join, side));
     skeletonize_finish(op, s, skr);
     HDM_HIP(hipStreamWaitEvent(s, op.lane.join, 0));

@@ -801,9 +801,10 @@ static void publish_descriptors(Op& op, hipStream_t s) {
     fill(op.hostT, false);
     if (!op.dev64.n) op.dev64.alloc(1);
     if (!op.devT.n) op.devT.alloc(1);
+    // the uploads read op.host64 / op.hostT (or a staged copy of them), which
+    // outlive the copies: no wait here
     op.dev64.upload(&op.host64, 1, s);
     op.devT.upload(&op.hostT, 1, s);
-    HDM_HIP(hipStreamSynchronize(s));
 }
 
 static void packed_near_offsets(Op& op);
@@ -873,15 +874,11 @@ static void build_mma_plan(Op& op, hipStream_t s) {
     op.wsc.alloc(static_cast<size_t>(L) * kMaxRhs);
 }
 
-void build_eval_plan(Op& op, hipStream_t s) {
+// The near-field part of the evaluation plan (work items and per-leaf plans):
+// it needs only the tree and the near lists, so the operator builds it while
+// the skeletonisation runs.
+void build_near_plan(Op& op, hipStream_t s) {
     const int64_t L = op.L;
-    op.d_rank = to_device(op.rank, s);
-    op.d_ncand = to_device(op.ncand, s);
-    op.d_skoff = to_device(op.skoff, s);
-    op.d_poff = to_device(op.poff, s);
-    op.d_far_block_off = to_device(op.far_block_off, s);
-    op.d_far_cols = to_device(op.far_cols, s);
-    op.d_far_colbase = to_device(op.far_colbase, s);
     // near-field items: per leaf, per row group, per near tile, per column chunk
     const int rg = kWave * rows_per_lane(op.prm.near_prec);
     op.near_rows_per_group = rg;
@@ -929,6 +926,18 @@ void build_eval_plan(Op& op, hipStream_t s) {
     op.part_elems = part;
     op.d_items = to_device(op.items, s);
     op.d_leaves = to_device(op.leaves, s);
+    if (op.prm.near_prec == HDM_F16) build_mma_plan(op, s);
+}
+
+// the rest of the plan, once the skeletons are known
+void build_eval_plan(Op& op, hipStream_t s) {
+    op.d_rank = to_device(op.rank, s);
+    op.d_ncand = to_device(op.ncand, s);
+    op.d_skoff = to_device(op.skoff, s);
+    op.d_poff = to_device(op.poff, s);
+    op.d_far_block_off = to_device(op.far_block_off, s);
+    op.d_far_cols = to_device(op.far_cols, s);
+    op.d_far_colbase = to_device(op.far_colbase, s);
     // one row task per skeleton row, grouped by level from the leaves up; the
     // same list, taken whole, gives the far-field (S2S) rows
     std::vector<RowTask> tasks;
@@ -942,7 +951,6 @@ void build_eval_plan(Op& op, hipStream_t s) {
     }
     op.row_total = static_cast<int64_t>(tasks.size());
     op.d_row_tasks = to_device(tasks, s);
-    if (op.prm.near_prec == HDM_F16) build_mma_plan(op, s);
     op.lane.init(op.ctx ? &op.ctx->lanes : nullptr);
     ensure_ws(op, 1);
     publish_descriptors(op, s);

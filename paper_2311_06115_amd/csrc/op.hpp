@@ -311,6 +311,7 @@ size_t footprint_estimate(const hdm_params& p, int max_basis);
 // compression (compress.hip)
 void compress_operator(Op& op, const void* X, int x_on_device, hipStream_t s);
 // evaluation (evaluate.hip)
+void build_near_plan(Op& op, hipStream_t s);
 void build_eval_plan(Op& op, hipStream_t s);
 void normalise_degrees(Op& op, hipStream_t s);
 void convert_eval_precision(Op& op, hipStream_t s);
