@@ -365,7 +365,28 @@ __device__ inline uint64_t orderable(double x) {
 // original index, so this is the (key, index) order.  The threshold is found by
 // radix selection (eight 8-bit digits of the key image, ties by position), then
 // the node is partitioned stably: both halves keep ascending original index.
+// Each thread owns a contiguous run of positions for the partition; with at
+// most kSplitReg per thread the run's key images stay in registers for all
+// passes (else the histograms read the keys strided over the node).  Histogram
+// counts of a wave whose active lanes share a bin (the common case for the
+// leading digits) go in as one atomic.
 constexpr int kSplitBlock = 1024;
+constexpr int kSplitReg = 32;
+
+__device__ inline void hist_add(int* hist, bool act, uint32_t bin) {
+    const uint64_t am = __ballot(act);
+    if (!am) return;
+    const int lead = __ffsll(static_cast<long long>(am)) - 1;
+    const uint32_t b0 = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(bin), lead));
+    const uint64_t same = __ballot(act && bin == b0);
+    if (same == am) {
+        if ((threadIdx.x & 63) == lead) atomicAdd(&hist[b0], __popcll(am));
+    } else if (act) {
+        atomicAdd(&hist[bin], 1);
+    }
+}
+
+template <bool kReg>
 __global__ void __launch_bounds__(kSplitBlock) k_tree_split(int lvl, const int64_t* start, const int64_t* size,
                                                             const int32_t* perm_all, const double* key_all,
                                                             int32_t* out_all, int64_t tstride) {
@@ -381,15 +402,41 @@ __global__ void __launch_bounds__(kSplitBlock) k_tree_split(int lvl, const int64
     const int64_t s0 = start[h];
     const int n = static_cast<int>(size[h]);
     const int nl = n / 2;
+    const int per = (n + static_cast<int>(blockDim.x) - 1) / static_cast<int>(blockDim.x);
+    const int a0 = min(n, static_cast<int>(threadIdx.x) * per), a1 = min(n, a0 + per);
+    constexpr int R = kReg ? kSplitReg : 1;
+    uint64_t ur[R];
+    if constexpr (kReg) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) ur[r] = a0 + r < a1 ? orderable(key[s0 + a0 + r]) : 0;
+    }
+    auto img = [&](int r) -> uint64_t {   // key image of position a0 + r
+        if constexpr (kReg) return ur[r];
+        else return orderable(key[s0 + a0 + r]);
+    };
+    const int cnt = a1 - a0;
+    constexpr int RU = kReg ? kSplitReg : 1;
     if (threadIdx.x == 0) { s_prefix = 0; s_k = nl; }
     uint64_t mask = 0;
     for (int shift = 56; shift >= 0; shift -= 8) {
         for (int b = threadIdx.x; b < 256; b += blockDim.x) hist[b] = 0;
         __syncthreads();
         const uint64_t prefix = s_prefix;
-        for (int a = threadIdx.x; a < n; a += blockDim.x) {
-            const uint64_t u = orderable(key[s0 + a]);
-            if ((u & mask) == prefix) atomicAdd(&hist[(u >> shift) & 255u], 1);
+        if constexpr (kReg) {
+#pragma unroll
+            for (int r = 0; r < RU; ++r) {
+                const bool in = r < cnt;
+                const uint64_t u = ur[r];
+                hist_add(hist, in && (u & mask) == prefix, static_cast<uint32_t>((u >> shift) & 255u));
+            }
+        } else {
+            // strided over the node (coalesced); every wave runs the same rounds
+            for (int q = 0; q < per; ++q) {
+                const int a = static_cast<int>(threadIdx.x) + q * static_cast<int>(blockDim.x);
+                const bool in = a < n;
+                const uint64_t u = in ? orderable(key[s0 + a]) : 0;
+                hist_add(hist, in && (u & mask) == prefix, static_cast<uint32_t>((u >> shift) & 255u));
+            }
         }
         __syncthreads();
         if (threadIdx.x < 64) {
@@ -417,32 +464,48 @@ __global__ void __launch_bounds__(kSplitBlock) k_tree_split(int lvl, const int64
         __syncthreads();
     }
     // the threshold is the (s_k)-th member (position order) whose key image
-    // equals s_prefix.  Each thread owns a contiguous run of positions, so two
-    // workgroup scans of per-thread counts give every member its place.
+    // equals s_prefix: two workgroup scans of per-thread counts give every
+    // member its place
     const uint64_t ustar = s_prefix;
     const int kstar = s_k;
-    const int per = (n + static_cast<int>(blockDim.x) - 1) / static_cast<int>(blockDim.x);
-    const int a0 = min(n, static_cast<int>(threadIdx.x) * per), a1 = min(n, a0 + per);
     int neq = 0;
-    for (int a = a0; a < a1; ++a) neq += orderable(key[s0 + a]) == ustar;
+#pragma unroll
+    for (int r = 0; r < (kReg ? R : 1); ++r)
+        if constexpr (kReg) neq += (r < cnt && img(r) == ustar);
+    if constexpr (!kReg)
+        for (int r = 0; r < cnt; ++r) neq += img(r) == ustar;
     int tot = 0;
     const int eq_base = wg_scan_excl(neq, wsum, &tot);
     int nleft = 0, e = eq_base;
-    for (int a = a0; a < a1; ++a) {
-        const uint64_t u = orderable(key[s0 + a]);
+    auto count_left = [&](int r) {
+        const uint64_t u = img(r);
         const bool eq = u == ustar;
         nleft += u < ustar || (eq && e < kstar);
         e += eq;
+    };
+    if constexpr (kReg) {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (r < cnt) count_left(r);
+    } else {
+        for (int r = 0; r < cnt; ++r) count_left(r);
     }
     const int l_base = wg_scan_excl(nleft, wsum, &tot);
     int li = l_base, ri = a0 - l_base;
     e = eq_base;
-    for (int a = a0; a < a1; ++a) {
-        const uint64_t u = orderable(key[s0 + a]);
+    auto place = [&](int r) {
+        const uint64_t u = img(r);
         const bool eq = u == ustar;
         const bool left = u < ustar || (eq && e < kstar);
         e += eq;
-        out[left ? s0 + li++ : s0 + nl + ri++] = perm[s0 + a];
+        out[left ? s0 + li++ : s0 + nl + ri++] = perm[s0 + a0 + r];
+    };
+    if constexpr (kReg) {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (r < cnt) place(r);
+    } else {
+        for (int r = 0; r < cnt; ++r) place(r);
     }
 }
 
@@ -1616,8 +1679,16 @@ struct TreeBuild {
         }
         hipLaunchKernelGGL(k_tree_key, dim3(gN, ntrees), dim3(kBlock), 0, s, lvl, n, op.d_start.get(), perm.get(),
                            pq.get(), pq_stride, P, mode, key.get());
-        hipLaunchKernelGGL(k_tree_split, dim3(nodes, ntrees), dim3(kSplitBlock), 0, s, lvl, op.d_start.get(),
-                           op.d_size.get(), perm.get(), key.get(), tmp.get(), n);
+        // a node has at most ceil(n / 2^lvl) members: keys in registers when a
+        // thread's run fits (and is long enough to be worth it)
+        const int64_t maxnode = (n + nodes - 1) / nodes;
+        const int64_t per = (maxnode + kSplitBlock - 1) / kSplitBlock;
+        if (per > 4 && per <= kSplitReg)
+            hipLaunchKernelGGL(k_tree_split<true>, dim3(nodes, ntrees), dim3(kSplitBlock), 0, s, lvl, op.d_start.get(),
+                               op.d_size.get(), perm.get(), key.get(), tmp.get(), n);
+        else
+            hipLaunchKernelGGL(k_tree_split<false>, dim3(nodes, ntrees), dim3(kSplitBlock), 0, s, lvl,
+                               op.d_start.get(), op.d_size.get(), perm.get(), key.get(), tmp.get(), n);
         check_launch("tree level");
         std::swap(perm, tmp);
     }
