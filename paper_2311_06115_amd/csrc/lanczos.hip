@@ -174,6 +174,51 @@ __global__ void k_gemvn(const double* V, int64_t ldv, int ncols, const double* h
     }
 }
 
+// y -= V h (the k_gemvn rows and order), then the block's rows of the result
+// (staged in shared memory) against V as in k_gemvt_h, whose last workgroup
+// reduces the partial rows into h_out: the second Gram-Schmidt projection read
+// with the first update, one pass over V instead of two
+__global__ void __launch_bounds__(kBlock) k_gemvn_t_h(const double* V, int64_t ldv, int ncols, const double* h,
+                                                      double* y, int64_t n, double* partial, int ldp, double* h_out,
+                                                      unsigned* counter) {
+    __shared__ double hs[1024];
+    __shared__ double ys[kRows];
+    for (int c = threadIdx.x; c < ncols && c < 1024; c += blockDim.x) hs[c] = h[c];
+    __syncthreads();
+    const int64_t r0 = blockIdx.x * static_cast<int64_t>(kRows);
+    for (int u = 0; u < kRows / kBlock; ++u) {
+        const int64_t row = r0 + u * kBlock + threadIdx.x;
+        double v = 0.0;
+        if (row < n) {
+            double acc = 0.0;
+            for (int c = 0; c < ncols; ++c) acc += V[c * ldv + row] * (c < 1024 ? hs[c] : h[c]);
+            v = y[row] - acc;
+            y[row] = v;
+        }
+        ys[u * kBlock + threadIdx.x] = v;
+    }
+    __syncthreads();
+    constexpr int kPer = kRows / 64;   // rows per lane
+    const int wv = threadIdx.x / 64, lane = threadIdx.x % 64, nw = blockDim.x / 64;
+    double yr[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) yr[u] = ys[u * 64 + lane];
+    for (int c = wv; c < ncols; c += nw) {
+        double acc = 0.0;
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int64_t row = r0 + u * 64 + lane;
+            acc += (row < n ? V[c * ldv + row] : 0.0) * yr[u];
+        }
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+        if (lane == 0) put_shared(partial + static_cast<int64_t>(blockIdx.x) * ldp + c, acc);
+    }
+    __shared__ bool last;
+    __shared__ double qs[4][64];
+    if (!last_workgroup(counter, &last)) return;
+    for (int g = 0; g * 64 < ncols; ++g) reduce_cols_group<true>(partial, gridDim.x, ldp, ncols, h_out, g, qs);
+}
+
 // k_gemvn with the partial norms, then the last workgroup forms alpha_j = h1[j] + h2[j]
 // and beta_j = sqrt(sum of the partial norms) (the k_alpha_beta order)
 __global__ void k_gemvn_ab(const double* V, int64_t ldv, int ncols, const double* h, double* y, int64_t n, double* np,
@@ -846,9 +891,8 @@ bool LanczosRun::after_product(hipStream_t s) {
         unsigned* cnt = counters.get();
         hipLaunchKernelGGL(k_gemvt_h, dim3(nb), dim3(kBlock), 0, s, V.get(), n, nc, y.get(), n, part.get(), ldp,
                            h1.get(), cnt);
-        hipLaunchKernelGGL(k_gemvn, dim3(nb), dim3(kBlock), 0, s, V.get(), n, nc, h1.get(), y.get(), n, nullptr);
-        hipLaunchKernelGGL(k_gemvt_h, dim3(nb), dim3(kBlock), 0, s, V.get(), n, nc, y.get(), n, part.get(), ldp,
-                           h2.get(), cnt);
+        hipLaunchKernelGGL(k_gemvn_t_h, dim3(nb), dim3(kBlock), 0, s, V.get(), n, nc, h1.get(), y.get(), n,
+                           part.get(), ldp, h2.get(), cnt);
         hipLaunchKernelGGL(k_gemvn_ab, dim3(nb), dim3(kBlock), 0, s, V.get(), n, nc, h2.get(), y.get(), n, np.get(),
                            h1.get(), j, alpha.get(), beta.get(), cnt + 1);
     }
