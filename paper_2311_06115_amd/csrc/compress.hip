@@ -677,10 +677,14 @@ struct LevelArgs {
     int32_t* rk;                // per heap id: rank
     int32_t* status;            // per node: 0 ok, 1 row fill failed
     int64_t lds_b;              // ID: elements of B a workgroup keeps in shared memory
+    int32_t* rows_fix;          // sampled rows of every node, heap id h at h * rmax
+    int32_t* nc_all;            // per heap id: candidates
+    int32_t* nr_all;            // per heap id: sampled rows
+    int32_t* st_all;            // per heap id: row fill status
 };
 
-__global__ void k_cand(LevelArgs A) {
-    const int64_t t = blockIdx.x;
+// the node's candidates: its points at the leaves, else its children's skeletons
+__device__ inline void node_cand(const LevelArgs& A, int64_t t) {
     const int64_t h = (int64_t(1) << A.lvl) + t;
     int32_t* c = A.cand + t * A.cmax;
     if (A.lvl == A.depth) {
@@ -695,6 +699,8 @@ __global__ void k_cand(LevelArgs A) {
         if (threadIdx.x == 0) A.ncand[t] = rl + rr;
     }
 }
+
+__global__ void k_cand(LevelArgs A) { node_cand(A, blockIdx.x); }
 
 // neighbour votes of the candidates, for points outside the node
 __global__ void k_row_count(LevelArgs A) {
@@ -746,6 +752,10 @@ __global__ void k_row_select(LevelArgs A) {
     auto votes = [&](int64_t u) { return kSorted ? vt[u] : cnt[uq[u]]; };
     int64_t nu = 0;
     if constexpr (kSorted) {
+        // the candidates are listed here (the dense variant's vote count needs them
+        // before it, from k_cand); the workgroup reads them after the barrier
+        node_cand(A, t);
+        __syncthreads();
         // an n-bit map of the outside neighbours, the running popcount of its
         // words, and the votes at each neighbour's rank in index order
         extern __shared__ uint32_t dsh[];
@@ -969,6 +979,10 @@ __global__ void k_row_select(LevelArgs A) {
         A.nrows[t] = static_cast<int32_t>(nr);
         A.status[t] = st;
     }
+    // leave the node's bitmap clear for the next level (which uses a prefix of
+    // these node slots)
+    __syncthreads();
+    for (int64_t w = threadIdx.x; w < (A.n + 31) / 32; w += blockDim.x) bits[w] = 0u;
 }
 
 // B = K(rows, cand) for float64 points of at most kDimReg coordinates: a thread
@@ -1480,21 +1494,15 @@ __global__ void __launch_bounds__(kBlock) k_pivoted_id(LevelArgs A) {
     }
     if (rank <= Q.R && 2 * rank <= nr) id_back_subst<true>(Q, Pm, cp, rank, nc);
     else id_back_subst<false>(Q, Pm, cp, rank, nc);
-    if (threadIdx.x == 0) A.rk[h] = rank;
-}
-
-// keep this level's skeletons, sampled rows and sizes in the per-node slots
-__global__ void k_level_save(LevelArgs A, int32_t* skel_fix, int32_t* rows_fix, int32_t* nc_all, int32_t* nr_all,
-                             int32_t* st_all) {
-    const int64_t t = blockIdx.x;
-    const int64_t h = (int64_t(1) << A.lvl) + t;
-    const int rk = A.rk[h], nr = A.nrows[t];
-    for (int u = threadIdx.x; u < rk; u += blockDim.x) skel_fix[h * A.s + u] = A.cand[t * A.cmax + A.cp[t * A.cmax + u]];
-    for (int u = threadIdx.x; u < nr; u += blockDim.x) rows_fix[h * A.rmax + u] = A.rows[t * A.rmax + u];
+    // this level's skeletons, sampled rows and sizes into the per-node slots
+    int32_t* skel_save = const_cast<int32_t*>(A.skel_fix) + h * A.s;
+    for (int u = threadIdx.x; u < rank; u += blockDim.x) skel_save[u] = A.cand[t * A.cmax + cp[u]];
+    for (int u = threadIdx.x; u < nr; u += blockDim.x) A.rows_fix[h * A.rmax + u] = A.rows[t * A.rmax + u];
     if (threadIdx.x == 0) {
-        nc_all[h] = A.ncand[t];
-        nr_all[h] = nr;
-        st_all[h] = A.status[t];
+        A.rk[h] = rank;
+        A.nc_all[h] = nc;
+        A.nr_all[h] = nr;
+        A.st_all[h] = A.status[t];
     }
 }
 
@@ -1864,9 +1872,10 @@ static void skeletonize_levels(Op& op, const Geo& G, hipStream_t s, SkelRun& R) 
                                     hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(sort_shmem)));
     }
     std::vector<int32_t> h_nc(maxnodes), h_nr(maxnodes);
+    // the row bitmaps start clear; each row selection clears its node's after use
+    HDM_HIP(hipMemsetAsync(bits.get(), 0, sizeof(uint32_t) * static_cast<size_t>(1 << op.depth) * ((n + 31) / 32), s));
     for (int lvl = op.depth; lvl >= 1; --lvl) {
         const int nodes = 1 << lvl;
-        HDM_HIP(hipMemsetAsync(bits.get(), 0, sizeof(uint32_t) * static_cast<size_t>(nodes) * ((n + 31) / 32), s));
         LevelArgs A{};
         A.lvl = lvl;
         A.depth = op.depth;
@@ -1898,10 +1907,14 @@ static void skeletonize_levels(Op& op, const Geo& G, hipStream_t s, SkelRun& R) 
         A.rk = d_rank;
         A.status = status.get();
         A.lds_b = id_lds;
-        hipLaunchKernelGGL(k_cand, dim3(nodes), dim3(kBlock), 0, s, A);
+        A.rows_fix = rows_fix.get();
+        A.nc_all = d_nc;
+        A.nr_all = d_nr;
+        A.st_all = d_st;
         if (sorted_votes) {
             hipLaunchKernelGGL(k_row_select<true>, dim3(nodes), dim3(kBlock), sort_shmem, s, A);
         } else {
+            hipLaunchKernelGGL(k_cand, dim3(nodes), dim3(kBlock), 0, s, A);
             HDM_HIP(hipMemsetAsync(cnt.get(), 0, sizeof(int32_t) * static_cast<size_t>(nodes) * n, s));
             hipLaunchKernelGGL(k_row_count, dim3(ceil_div(static_cast<int64_t>(cmax) * k, kBlock), nodes), dim3(kBlock), 0,
                                s, A);
@@ -1926,8 +1939,6 @@ static void skeletonize_levels(Op& op, const Geo& G, hipStream_t s, SkelRun& R) 
                                0, s, A, P);
         }
         hipLaunchKernelGGL(k_pivoted_id, dim3(nodes), dim3(kBlock), id_shmem, s, A);
-        hipLaunchKernelGGL(k_level_save, dim3(nodes), dim3(kBlock), 0, s, A, skel_fix.get(), rows_fix.get(), d_nc, d_nr,
-                           d_st);
         check_launch("skeletonisation");
     }
 }
