@@ -5,6 +5,7 @@
 //   S2S  far:      skeleton potentials u~_h = sum_{g in Far(h)} K(skel_h, skel_g) w~_g
 //   S2N  downward: [u~_l; u~_r] += P_h^T u~_h; leaves fold P^T u~ into the output
 //   L2L  near:     u_a += sum_{b in Near(a)} K(a, b) w_b   (streams the near tiles)
+#include <cstring>
 #include <algorithm>
 #include <cmath>
 #include <map>
@@ -690,7 +691,7 @@ size_t Op::footprint() const {
            P64.bytes() + P32.bytes() + rows.bytes() + near64.bytes() + nearT.bytes() + near_scale.bytes() +
            far64.bytes() + farT.bytes() + far_scale.bytes() + far_colmap.bytes() + d_items.bytes() +
            d_leaves.bytes() + q.bytes() + d.bytes() + c.bytes() + w_tree.bytes() + skw.bytes() + sku.bytes() +
-           part.bytes() + d_row_tasks.bytes() + wh.bytes() + wsc.bytes() + d_items_mma.bytes() + d_leaves_mma.bytes();
+           part.bytes() + plan_blob.bytes() + wh.bytes() + wsc.bytes() + d_items_mma.bytes() + d_leaves_mma.bytes();
 }
 
 void Lane::init(LanePool* from) {
@@ -756,20 +757,20 @@ static void publish_descriptors(Op& op, hipStream_t s) {
         D.perm = op.perm.get();
         D.c = op.c.get();
         D.start = op.d_start.get();
-        D.rank = op.d_rank.get();
-        D.ncand = op.d_ncand.get();
-        D.skoff = op.d_skoff.get();
-        D.poff = op.d_poff.get();
+        D.rank = op.d_rank;
+        D.ncand = op.d_ncand;
+        D.skoff = op.d_skoff;
+        D.poff = op.d_poff;
         D.P = f64 ? static_cast<const void*>(op.P64.get()) : static_cast<const void*>(op.P32.get());
-        D.rows = op.d_row_tasks.get();
+        D.rows = op.d_row_tasks;
         for (int l = 0; l < kMaxLevels; ++l) {
             D.row_begin[l] = l < static_cast<int>(op.row_begin.size()) ? op.row_begin[l] : 0;
             D.row_count[l] = l < static_cast<int>(op.row_count.size()) ? op.row_count[l] : 0;
         }
         D.row_total = op.row_total;
-        D.far_off = op.d_far_block_off.get();
-        D.far_cols = op.d_far_cols.get();
-        D.far_colbase = op.d_far_colbase.get();
+        D.far_off = op.d_far_block_off;
+        D.far_cols = op.d_far_cols;
+        D.far_colbase = op.d_far_colbase;
         D.far_colmap = op.far_colmap.get();
         D.far = f64 ? static_cast<const void*>(op.far64.get()) : static_cast<const void*>(op.farT.get());
         D.fscale = (!f64 && op.far_scale.n) ? op.far_scale.get() : nullptr;
@@ -931,13 +932,6 @@ void build_near_plan(Op& op, hipStream_t s) {
 
 // the rest of the plan, once the skeletons are known
 void build_eval_plan(Op& op, hipStream_t s) {
-    op.d_rank = to_device(op.rank, s);
-    op.d_ncand = to_device(op.ncand, s);
-    op.d_skoff = to_device(op.skoff, s);
-    op.d_poff = to_device(op.poff, s);
-    op.d_far_block_off = to_device(op.far_block_off, s);
-    op.d_far_cols = to_device(op.far_cols, s);
-    op.d_far_colbase = to_device(op.far_colbase, s);
     // one row task per skeleton row, grouped by level from the leaves up; the
     // same list, taken whole, gives the far-field (S2S) rows
     std::vector<RowTask> tasks;
@@ -950,7 +944,34 @@ void build_eval_plan(Op& op, hipStream_t s) {
         op.row_count[lvl] = static_cast<int64_t>(tasks.size()) - op.row_begin[lvl];
     }
     op.row_total = static_cast<int64_t>(tasks.size());
-    op.d_row_tasks = to_device(tasks, s);
+    // the skeleton-dependent arrays in one allocation and one copy
+    std::vector<char> blob;
+    auto add = [&](const void* src, size_t bytes) {
+        const size_t off = (blob.size() + 255) / 256 * 256;
+        blob.resize(off + bytes);
+        if (bytes) std::memcpy(blob.data() + off, src, bytes);
+        return off;
+    };
+    const size_t o_rank = add(op.rank.data(), op.rank.size() * sizeof(int32_t));
+    const size_t o_ncand = add(op.ncand.data(), op.ncand.size() * sizeof(int32_t));
+    const size_t o_skoff = add(op.skoff.data(), op.skoff.size() * sizeof(int64_t));
+    const size_t o_poff = add(op.poff.data(), op.poff.size() * sizeof(int64_t));
+    const size_t o_fbo = add(op.far_block_off.data(), op.far_block_off.size() * sizeof(int64_t));
+    const size_t o_fc = add(op.far_cols.data(), op.far_cols.size() * sizeof(int32_t));
+    const size_t o_fcb = add(op.far_colbase.data(), op.far_colbase.size() * sizeof(int64_t));
+    const size_t o_tasks = add(tasks.data(), tasks.size() * sizeof(RowTask));
+    blob.resize(blob.size() + 256);   // every piece, empty ones included, points inside the allocation
+    op.plan_blob.alloc(blob.size());
+    op.plan_blob.upload(blob.data(), blob.size(), s);
+    char* base = op.plan_blob.get();
+    op.d_rank = reinterpret_cast<const int32_t*>(base + o_rank);
+    op.d_ncand = reinterpret_cast<const int32_t*>(base + o_ncand);
+    op.d_skoff = reinterpret_cast<const int64_t*>(base + o_skoff);
+    op.d_poff = reinterpret_cast<const int64_t*>(base + o_poff);
+    op.d_far_block_off = reinterpret_cast<const int64_t*>(base + o_fbo);
+    op.d_far_cols = reinterpret_cast<const int32_t*>(base + o_fc);
+    op.d_far_colbase = reinterpret_cast<const int64_t*>(base + o_fcb);
+    op.d_row_tasks = reinterpret_cast<const RowTask*>(base + o_tasks);
     op.lane.init(op.ctx ? &op.ctx->lanes : nullptr);
     ensure_ws(op, 1);
     publish_descriptors(op, s);

@@ -210,7 +210,7 @@ struct Op {
     DevBuf<float> far_scale;                   // per heap id (one scale per block)
     DevBuf<int32_t> far_colmap;                // per block column: skeleton slot of the weight it multiplies
     std::vector<int64_t> far_colbase;          // per heap id: first column of its block in far_colmap
-    DevBuf<int64_t> d_far_colbase;
+    const int64_t* d_far_colbase = nullptr;     // in plan_blob
     // plans
     std::vector<NearItem> items;
     DevBuf<NearItem> d_items;
@@ -244,12 +244,17 @@ struct Op {
     // normalised, right-hand sides, profiled) (evaluate.hip)
     struct GraphCache;
     GraphCache* graphs = nullptr;
-    DevBuf<int32_t> d_rank, d_ncand;
-    DevBuf<int64_t> d_skoff, d_poff, d_far_block_off;
-    DevBuf<int32_t> d_far_cols;
+    // skeleton-dependent plan arrays, uploaded together into plan_blob
+    DevBuf<char> plan_blob;
+    const int32_t* d_rank = nullptr;
+    const int32_t* d_ncand = nullptr;
+    const int64_t* d_skoff = nullptr;
+    const int64_t* d_poff = nullptr;
+    const int64_t* d_far_block_off = nullptr;
+    const int32_t* d_far_cols = nullptr;
     std::vector<int64_t> row_begin, row_count; // per level: skeleton-row tasks of the upward pass
     int64_t row_total = 0;
-    DevBuf<RowTask> d_row_tasks;
+    const RowTask* d_row_tasks = nullptr;   // in plan_blob
     Lane lane;                                 // side stream of single-operator products
     OpDev host64{}, hostT{};                   // descriptors (host copies)
     DevBuf<OpDev> dev64, devT;                 // the same, in device memory
