@@ -112,8 +112,9 @@ hdm_op_s* make_operator(Ctx* ctx, const void* X, int x_on_device, const hdm_para
         PhaseScope ph(ctx, HDM_PHASE_COMPRESS, s);
         compress_operator(*op, X, x_on_device, s);
         build_eval_plan(*op, s);
+        convert_eval_precision(*op, s);   // does not need the degrees: enqueued first
         normalise_degrees(*op, s);
-        convert_eval_precision(*op, s);
+        finish_operator(*op, s);
     }
     HDM_HIP(hipStreamSynchronize(s));
     return op.release();

@@ -1478,6 +1478,10 @@ void convert_eval_precision(Op& op, hipStream_t s) {
     if (op.prm.near_prec == HDM_F64 && op.prm.far_prec == HDM_F64) return;
     HDM_CHECK(op.prm.near_prec != HDM_F64 && op.prm.far_prec != HDM_F64, HDM_EINVAL,
               "float64 tiles cannot be mixed with reduced-precision tiles");
+    // the index arrays of the conversions stay alive until finish_operator has
+    // waited for s
+    if (!op.conv_keep) op.conv_keep.reset(new Op::ConvKeep());
+    Op::ConvKeep* keep = op.conv_keep.get();
     // near: one scale per tile (pair)
     std::vector<int64_t> noff, ncnt;
     near_ranges(op, noff, ncnt);
@@ -1490,16 +1494,16 @@ void convert_eval_precision(Op& op, hipStream_t s) {
     auto go = [&](int prec, const DevBuf<double>& src, const std::vector<int64_t>& off, const std::vector<int64_t>& cnt,
                   DevBuf<char>& dst, DevBuf<float>& scale, int64_t elems) {
         switch (prec) {
-            case HDM_F32: convert_tiles<float>(src, off, cnt, false, dst, scale, elems, s); break;
-            case HDM_BF16: convert_tiles<bf16_t>(src, off, cnt, true, dst, scale, elems, s); break;
-            case HDM_F16: convert_tiles<f16_t>(src, off, cnt, true, dst, scale, elems, s); break;
+            case HDM_F32: convert_tiles<float>(src, off, cnt, false, dst, scale, elems, s, keep); break;
+            case HDM_BF16: convert_tiles<bf16_t>(src, off, cnt, true, dst, scale, elems, s, keep); break;
+            case HDM_F16: convert_tiles<f16_t>(src, off, cnt, true, dst, scale, elems, s, keep); break;
             default: fail(HDM_EINVAL, "bad tile precision");
         }
     };
     if (op.near_converted) {
-        // converted on another stream while the operator was built; that stream has been synchronised
+        // converted on the side stream while the operator was built; s has waited for it
     } else if (op.packed) {
-        pack_near(op, noff, ncnt, s);
+        pack_near(op, noff, ncnt, s, keep);
     } else {
         go(op.prm.near_prec, op.near64, noff, ncnt, op.nearT, op.near_scale, op.near_elems);
     }
@@ -1508,11 +1512,16 @@ void convert_eval_precision(Op& op, hipStream_t s) {
     if (op.np > 0)
         hipLaunchKernelGGL(k_to_f32, dim3(ceil_div(op.np, kBlock)), dim3(kBlock), 0, s, op.P64.get(), op.P32.get(), op.np);
     check_launch("P to f32");
+}
+
+void finish_operator(Op& op, hipStream_t s) {
     HDM_HIP(hipStreamSynchronize(s));
-    // the float64 tiles were only needed for the degrees
     op.conv_keep.reset();
-    op.near64.release();
-    op.far64.release();
+    if (!(op.prm.near_prec == HDM_F64 && op.prm.far_prec == HDM_F64)) {
+        // the float64 tiles were only needed for the degrees
+        op.near64.release();
+        op.far64.release();
+    }
     publish_descriptors(op, s);
 }
 

@@ -319,9 +319,13 @@ void compress_operator(Op& op, const void* X, int x_on_device, hipStream_t s);
 void build_near_plan(Op& op, hipStream_t s);
 void build_eval_plan(Op& op, hipStream_t s);
 void normalise_degrees(Op& op, hipStream_t s);
+// evaluation-precision copies of the tiles and P, enqueued on s without waiting
 void convert_eval_precision(Op& op, hipStream_t s);
+// waits for s, releases the float64 tiles (unless they are the evaluation tiles)
+// and publishes the descriptors
+void finish_operator(Op& op, hipStream_t s);
 // starts the conversion of the float64 near tiles to the evaluation precision
-// on s without waiting (convert_eval_precision completes it after s is synchronised)
+// on s without waiting (its index arrays live in conv_keep until finish_operator)
 void convert_near_tiles(Op& op, hipStream_t s);
 // graph_ok: the product may replay the operator's cached HIP graph (the caller's
 // one-off products); iterations that interleave other kernels launch eagerly
