@@ -522,8 +522,9 @@ __global__ void k_knn_init(int32_t* idx, double* d2, int64_t cnt) {
 // smallest (d2, index).  One wave per point: the list lives across lanes 0..k-1
 // (ascending), each lane evaluates a share of the leaf's candidates, and the
 // candidates that beat the current k-th entry are inserted one at a time
-// (duplicate check and insert position by ballot, shift by one lane).  The
-// result is the unique k smallest entries, whatever the insertion order.
+// (duplicate check and insert position by ballot, shift by one lane); an empty
+// list takes a chunk's k smallest by their ranks in the chunk.  The result is
+// the unique k smallest entries, whatever the insertion order.
 constexpr int kLeafStageDim = 8;
 constexpr int kLeafStageMax = 2048;
 constexpr int kKnnBlock = 1024;
@@ -558,6 +559,8 @@ __global__ void __launch_bounds__(kKnnBlock) k_knn_leaf(int depth, const int64_t
                                                         double* kd2) {
     extern __shared__ double xs[];          // staged coordinates (n x dim) when stage != 0
     __shared__ int32_t ids[kLeafStageMax];  // staged original indices
+    __shared__ double sd[kKnnBlock];        // per wave: a list placed by rank
+    __shared__ int32_t sj[kKnnBlock];
     const int64_t h = (int64_t(1) << depth) + blockIdx.x / splits;
     const int part = blockIdx.x % splits;
     const int64_t s0 = start[h], n = size[h];
@@ -596,6 +599,32 @@ __global__ void __launch_bounds__(kKnnBlock) k_knn_leaf(int depth, const int64_t
                 } else {
                     d = sqd(P, i, j);
                 }
+            }
+            if (lane_value(li, 0) < 0) {
+                // an empty list takes the chunk's k smallest: each candidate's rank
+                // among the chunk (a strict order: the indices differ) is its slot
+                int rank = 0;
+                for (int m = 0; m < 64; ++m) {
+                    const double dm = lane_value(d, m);
+                    const int32_t jm = lane_value(j, m);
+                    rank += jm >= 0 && knn_less(dm, jm, d, j);
+                }
+                double* wd = sd + wv * 64;
+                int32_t* wj = sj + wv * 64;
+                wd[lane] = INFINITY;
+                wj[lane] = -1;
+                __builtin_amdgcn_wave_barrier();
+                if (j >= 0 && rank < k) {
+                    wd[rank] = d;
+                    wj[rank] = j;
+                }
+                __builtin_amdgcn_wave_barrier();
+                if (lane < k) {
+                    ld = wd[lane];
+                    li = wj[lane];
+                }
+                __builtin_amdgcn_wave_barrier();
+                continue;
             }
             // candidates that beat the current k-th entry
             const double dk = lane_value(ld, k - 1);
