@@ -2021,8 +2021,8 @@ static void skeletonize_finish(Op& op, hipStream_t s, SkelRun& R) {
 }
 
 // near tiles; with float64 points the launch is left in flight on s (the pair
-// descriptors stay alive in `pairs_dev` until the caller has waited for s)
-static void build_near_tiles(Op& op, const Geo& G, hipStream_t s, DevBuf<NearPair>& pairs_dev) {
+// descriptors stay alive in op.near_pairs until the operator is finished)
+static void build_near_tiles(Op& op, const Geo& G, hipStream_t s) {
     const Pts& P = G.P;
     const int64_t L = op.L;
     // near blocks: per leaf, column-major ld x (sum of near leaf sizes), ld = rows rounded up to 8
@@ -2053,15 +2053,16 @@ static void build_near_tiles(Op& op, const Geo& G, hipStream_t s, DevBuf<NearPai
             blocks.push_back(GramBlock{op.perm.get() + pr.a0, op.perm.get() + pr.b0, pr.na, pr.nb, pr.off, pr.ld, 1});
         gram_launch(G, blocks, 1, op.near64, s);
     } else {
-        pairs_dev.alloc(pairs.size());
-        pairs_dev.upload(pairs.data(), pairs.size(), s);
+        op.near_pairs.alloc(pairs.size() * sizeof(NearPair));
+        op.near_pairs.upload(reinterpret_cast<const char*>(pairs.data()), pairs.size() * sizeof(NearPair), s);
+        const NearPair* pairs_dev = reinterpret_cast<const NearPair*>(op.near_pairs.get());
         HDM_HIP(hipStreamSynchronize(s));   // the host copy of the pairs goes out of scope
         int64_t maxe = 0;
         for (auto& p : pairs) maxe = std::max<int64_t>(maxe, static_cast<int64_t>(p.ld) * p.nb);
         for (size_t base = 0; base < pairs.size(); base += 65535) {
             const int cnt = static_cast<int>(std::min<size_t>(65535, pairs.size() - base));
             hipLaunchKernelGGL(k_near_tiles, dim3(ceil_div(maxe, kBlock), cnt), dim3(kBlock), 0, s,
-                               pairs_dev.get() + base, op.perm.get(), P, op.near64.get());
+                               pairs_dev + base, op.perm.get(), P, op.near64.get());
         }
         check_launch("near tiles");
     }
@@ -2249,15 +2250,16 @@ void compress_operator(Op& op, const void* X, int x_on_device, hipStream_t s) {
         build_far_lists(op);
     }
     // near tiles and their evaluation-precision copy on the side stream
-    DevBuf<NearPair> pairs_dev;
-    build_near_tiles(op, G, side, pairs_dev);
-    convert_near_tiles(op, side);
+    // the main stream waits for the float64 tiles and the near plan only (the
+    // degree products need them); their conversion to the evaluation precision
+    // runs on through the far tiles and the degrees, and finish_operator waits
+    build_near_tiles(op, G, side);
     build_near_plan(op, side);
-    HDM_HIP(hipEventRecord(op.lane.join, side));
+    HDM_HIP(hipEventRecord(op.lane.ready, side));
+    convert_near_tiles(op, side);
     skeletonize_finish(op, s, skr);
-    HDM_HIP(hipStreamWaitEvent(s, op.lane.join, 0));
+    HDM_HIP(hipStreamWaitEvent(s, op.lane.ready, 0));
     build_far_tiles(op, G, s);
-    HDM_HIP(hipStreamSynchronize(side));
     op.seconds_compress = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
 

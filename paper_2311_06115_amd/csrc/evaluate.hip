@@ -705,12 +705,14 @@ void Lane::init(LanePool* from) {
             side = e.side;
             fork = e.fork;
             join = e.join;
+            ready = e.ready;
             return;
         }
     }
     HDM_HIP(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
     HDM_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
     HDM_HIP(hipEventCreateWithFlags(&join, hipEventDisableTiming));
+    HDM_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
 }
 
 Lane::~Lane() {
@@ -718,11 +720,12 @@ Lane::~Lane() {
     (void)hipStreamSynchronize(side);
     if (pool) {
         std::lock_guard<std::mutex> g(pool->mu);
-        pool->free.push_back(LanePool::Entry{side, fork, join});
+        pool->free.push_back(LanePool::Entry{side, fork, join, ready});
         return;
     }
     if (fork) (void)hipEventDestroy(fork);
     if (join) (void)hipEventDestroy(join);
+    if (ready) (void)hipEventDestroy(ready);
     (void)hipStreamDestroy(side);
 }
 
@@ -731,6 +734,7 @@ LanePool::~LanePool() {
         (void)hipStreamSynchronize(e.side);
         (void)hipEventDestroy(e.fork);
         (void)hipEventDestroy(e.join);
+        (void)hipEventDestroy(e.ready);
         (void)hipStreamDestroy(e.side);
     }
 }
@@ -1515,7 +1519,10 @@ void convert_eval_precision(Op& op, hipStream_t s) {
 }
 
 void finish_operator(Op& op, hipStream_t s) {
+    // the near tiles' conversion may still run on the side stream
+    if (op.lane.side) HDM_HIP(hipStreamSynchronize(op.lane.side));
     HDM_HIP(hipStreamSynchronize(s));
+    op.near_pairs.release();
     op.conv_keep.reset();
     if (!(op.prm.near_prec == HDM_F64 && op.prm.far_prec == HDM_F64)) {
         // the float64 tiles were only needed for the degrees

@@ -39,7 +39,7 @@ struct Profiler {
 struct LanePool {
     struct Entry {
         hipStream_t side;
-        hipEvent_t fork, join;
+        hipEvent_t fork, join, ready;
     };
     std::mutex mu;
     std::vector<Entry> free;
@@ -158,6 +158,7 @@ struct OpDev {
 struct Lane {
     hipStream_t side = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;
+    hipEvent_t ready = nullptr;   // operator build: float64 near tiles and near plan on the side stream
     LanePool* pool = nullptr;   // where the stream and events go back to (null: destroyed)
     void init(LanePool* from = nullptr);
     Lane() = default;
@@ -198,6 +199,7 @@ struct Op {
     std::vector<int64_t> near_tile_off;        // per near pair (elements; same order as near_idx)
     int64_t near_elems = 0;
     mutable unsigned near_calls = 0;           // near-field products so far (their tile order alternates)
+    DevBuf<char> near_pairs;                   // pair descriptors of the near-tile launch, until finish_operator
     DevBuf<double> near64;
     DevBuf<char> nearT;                        // eval precision copy (near_prec)
     DevBuf<float> near_scale;                  // per near pair
