@@ -751,7 +751,6 @@ __global__ void k_row_count(LevelArgs A) {
 // that is all there is).  The draws are taken 64 at a time by one wave and
 // accepted in draw order, exactly as a sequential rejection loop would.
 constexpr int kMaxRows = 1024;   // sampled rows per node (2 max_rank_s)
-constexpr int kIdSink = 8;       // shared-memory slots of the ID that absorb padded stores
 constexpr int kVoteShared = 144 * 1024;   // shared memory for the bitmap vote counting (bytes)
 
 // kSorted: the candidates' outside neighbours are marked in a bitmap over the
@@ -1235,44 +1234,35 @@ __device__ inline void id_reflect(const QrBlock& Q, const double* hv, double* ns
 // apart) so that their dependent sums interleave.  The dot product's phase l
 // sits on lane l (the order of group_total<8>).  The next norm is over rows
 // [j + 1, nr), whose phase k = (i - j - 1) mod 8 sits on lane (k + 1) mod 8,
-// so the partials move one lane down before the same combination.  The lane's
-// entries of hv stay in registers for the whole step, zero past row nr - 1: a
-// row slot past the end reads row nr - 1 and adds an exact zero to the dot
-// product (a sum that starts at +0 is never -0, so adding +-0 leaves it
-// unchanged), is not added to the norm and is stored to the sink.  A column
-// slot past nc works on column nc - 1 and stores only to the sink.
+// so the partials move one lane down before the same combination.  A row slot
+// past the end reads and writes the zero row kept after the staged rows, and a
+// column slot past nc the zero padding column: their terms are exact zeros (a
+// sum that starts at +0 is never -0, so adding +-0 leaves it unchanged, and
+// 0 - f * 0 stores +0 back).
 template <int NPL, int NCOL>
-__device__ inline void id_reflect_regs(const QrBlock& Q, lds_f64* sink, double* nsq, int j, int nr, int nc,
-                                       double v0) {
+__device__ inline void id_reflect_regs(const QrBlock& Q, double* nsq, int j, int nr, int nc, double v0) {
     constexpr int kGroups = kBlock / 8;
     const int l = threadIdx.x % 8;
     const int gbase = (threadIdx.x % kWave) & ~7;
+    const int first = (j + l - Q.T0) * Q.ldS;   // staged offset of the lane's first row (column 0)
+    const int step = 8 * Q.ldS;
+    const int zrow = Q.R * Q.ldS;                 // the zero row (logical row nr)
     // hv = column j below row j with v0 = x0 - alpha in row j, and v^T v
     // summed by the same phases (lane l: rows j + l + 8u)
     double hreg[NPL];
 #pragma unroll
-    for (int u = 0; u < NPL; ++u) {
-        const int i = j + l + 8 * u;
-        hreg[u] = i < nr ? Q.sB[(i - Q.T0) * Q.ldS + j] : 0.0;
-    }
+    for (int u = 0; u < NPL; ++u) hreg[u] = Q.sB[min(first + u * step, zrow) + j];
     if (l == 0) hreg[0] = v0;
     double pv = 0.0;
 #pragma unroll
     for (int u = 0; u < NPL; ++u) pv = pv + hreg[u] * hreg[u];
     const double vtv = group_total<8>(&pv);
-    const int first = (j + l - Q.T0) * Q.ldS;   // staged offset of the lane's first row (column 0)
-    const int step = 8 * Q.ldS;
-    const int last = (nr - 1 - Q.T0) * Q.ldS;
     for (int c0 = j + 1 + threadIdx.x / 8; c0 < nc; c0 += NCOL * kGroups) {
-        int lim = last;
-        asm volatile("" : "+v"(lim));   // row bounds tested per column, not held as masks
+        int lim = zrow;
+        asm volatile("" : "+v"(lim));   // row offsets clamped per column, not held in registers
         int cc[NCOL];
-        bool ok[NCOL];
 #pragma unroll
-        for (int v = 0; v < NCOL; ++v) {
-            ok[v] = c0 + v * kGroups < nc;
-            cc[v] = ok[v] ? c0 + v * kGroups : nc - 1;
-        }
+        for (int v = 0; v < NCOL; ++v) cc[v] = min(c0 + v * kGroups, nc);   // nc: the zero column
         double x[NCOL][NPL];
 #pragma unroll
         for (int u = 0; u < NPL; ++u)
@@ -1287,27 +1277,23 @@ __device__ inline void id_reflect_regs(const QrBlock& Q, lds_f64* sink, double* 
             for (int v = 0; v < NCOL; ++v) p[v] = p[v] + hreg[u] * x[v][u];
         double f[NCOL], q[NCOL];
 #pragma unroll
-        for (int v = 0; v < NCOL; ++v) {
-            f[v] = (2.0 * group_total<8>(&p[v])) / vtv;
-            q[v] = 0.0;
-        }
+        for (int v = 0; v < NCOL; ++v) f[v] = (2.0 * group_total<8>(&p[v])) / vtv;
 #pragma unroll
         for (int u = 0; u < NPL; ++u) {
-            const int off = first + u * step;
+            const int off = min(first + u * step, lim);
 #pragma unroll
             for (int v = 0; v < NCOL; ++v) {
                 const double xu = x[v][u] - f[v] * hreg[u];
-                const double qu = q[v] + xu * xu;
-                q[v] = (off <= lim && (u > 0 || l > 0)) ? qu : q[v];   // row j is not part of the next norm
-                lds_f64* dst = (off <= lim && ok[v]) ? Q.sB + (off + cc[v]) : sink;
-                *dst = xu;
+                if (u == 0) q[v] = l > 0 ? xu * xu : 0.0;   // row j is not part of the next norm
+                else q[v] = q[v] + xu * xu;
+                Q.sB[off + cc[v]] = xu;
             }
         }
 #pragma unroll
         for (int v = 0; v < NCOL; ++v) {
             double r = __shfl(q[v], gbase + ((l + 1) & 7), kWave);   // phase l of the norm
             const double t = group_total<8>(&r);
-            if (l == 0 && ok[v]) nsq[cc[v]] = t;
+            if (l == 0 && c0 + v * kGroups < nc) nsq[c0 + v * kGroups] = t;
         }
     }
 }
@@ -1404,19 +1390,25 @@ __global__ void __launch_bounds__(kBlock) k_pivoted_id(LevelArgs A) {
     const int64_t t = blockIdx.x;
     const int nc = A.ncand[t], nr = A.nrows[t];
     double* hv = dyn;                 // Householder vector (A.rmax)
-    lds_f64* sink = (lds_f64*)(dyn + A.rmax);   // kIdSink slots that absorb stores of row slots past the end
-    double* nsq = dyn + A.rmax + kIdSink;   // remaining squared column norms (A.cmax)
+    double* nsq = dyn + A.rmax;       // remaining squared column norms (A.cmax)
     QrBlock Q;
     Q.sB = (lds_f64*)(nsq + A.cmax);   // address-space cast: dyn is shared memory
     Q.gB = A.B + t * static_cast<int64_t>(A.rmax) * A.cmax;
     Q.nc = nc;
-    Q.ldS = nc | 1;
-    Q.R = nc > 0 ? min(nr, static_cast<int>(A.lds_b / Q.ldS)) : 0;
+    Q.ldS = (nc + 1) | 1;   // at least one padding column, kept zero
+    // staged rows, then one zero row
+    Q.R = nc > 0 ? max(0, min(nr, static_cast<int>(A.lds_b / Q.ldS) - 1)) : 0;
     Q.T0 = nr - Q.R;
     int32_t* cp = A.cp + t * A.cmax;
     const int64_t h = (int64_t(1) << A.lvl) + t;
     double* Pm = A.Pfix + h * A.s * A.cmax;
     stage_rows(Q.sB, Q.ldS, Q.gB + static_cast<int64_t>(Q.T0) * nc, nc, Q.R);
+    if (nc > 0) {
+        // the padding columns of every staged row and the whole zero row
+        const int pad = Q.ldS - nc;
+        for (int e = threadIdx.x; e < Q.R * pad; e += blockDim.x) Q.sB[(e / pad) * Q.ldS + nc + e % pad] = 0.0;
+        for (int c = threadIdx.x; c < Q.ldS; c += blockDim.x) Q.sB[Q.R * Q.ldS + c] = 0.0;
+    }
     for (int c = threadIdx.x; c < nc; c += blockDim.x) cp[c] = c;
     __syncthreads();
     switch (id_lanes(nc)) {
@@ -1458,7 +1450,7 @@ __global__ void __launch_bounds__(kBlock) k_pivoted_id(LevelArgs A) {
             // rows [j, nr) all staged: the reflector lives in registers
             const double x0 = Q.sB[(j - Q.T0) * Q.ldS + j];
             const double alpha = x0 >= 0.0 ? -best : best;
-            id_reflect_regs<32, 2>(Q, sink, nsq, j, nr, nc, x0 - alpha);
+            id_reflect_regs<32, 2>(Q, nsq, j, nr, nc, x0 - alpha);
             __syncthreads();
             for (int i = j + threadIdx.x; i < nr; i += blockDim.x) Q.sB[(i - Q.T0) * Q.ldS + j] = (i == j) ? alpha : 0.0;
             rank = j + 1;
@@ -1885,9 +1877,9 @@ static void skeletonize_levels(Op& op, const Geo& G, hipStream_t s, SkelRun& R) 
         HDM_HIP(hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(&k_pivoted_id)));
         const int64_t avail = (static_cast<int64_t>(max_shared) - static_cast<int64_t>(fa.sharedSizeBytes)) /
                               static_cast<int64_t>(sizeof(double));
-        HDM_CHECK(avail >= rmax + kIdSink + cmax, HDM_EINTERNAL, "shared memory too small for the ID's vectors");
-        id_lds = avail - rmax - kIdSink - cmax;
-        id_shmem = sizeof(double) * static_cast<size_t>(rmax + kIdSink + cmax + id_lds);
+        HDM_CHECK(avail >= rmax + cmax, HDM_EINTERNAL, "shared memory too small for the ID's vectors");
+        id_lds = avail - rmax - cmax;
+        id_shmem = sizeof(double) * static_cast<size_t>(rmax + cmax + id_lds);
         if (id_shmem > 65536)
             HDM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pivoted_id),
                                         hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(id_shmem)));
@@ -2243,9 +2235,17 @@ void compress_operator(Op& op, const void* X, int x_on_device, hipStream_t s) {
     SkelRun skr;
     skeletonize_levels(op, G, s, skr);
     {
+        // through pinned staging when there is some: a pageable download took
+        // hundreds of microseconds longer to come back
         std::vector<int32_t> hv(static_cast<size_t>(op.L) * op.L);
-        votes.download(hv.data(), hv.size(), side);
-        HDM_HIP(hipStreamSynchronize(side));
+        if (void* pin = host_stage(hv.size() * sizeof(int32_t))) {
+            votes.download(static_cast<int32_t*>(pin), hv.size(), side);
+            HDM_HIP(hipStreamSynchronize(side));
+            std::memcpy(hv.data(), pin, hv.size() * sizeof(int32_t));
+        } else {
+            votes.download(hv.data(), hv.size(), side);
+            HDM_HIP(hipStreamSynchronize(side));
+        }
         build_near_lists(op, hv);
         build_far_lists(op);
     }
