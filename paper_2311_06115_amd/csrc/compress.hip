@@ -1548,12 +1548,16 @@ struct NearPair {
     int32_t ld, a0, na, b0, nb, pad;   // a0/b0: tree positions of row 0 / column 0
 };
 
-__global__ void k_near_tiles(const NearPair* pairs, const int32_t* perm, Pts P, double* out) {
+// float64 near tiles; with out32 also their float32 copy (the unscaled
+// round-to-nearest conversion of the evaluation tiles, written at the same offsets)
+__global__ void k_near_tiles(const NearPair* pairs, const int32_t* perm, Pts P, double* out, float* out32) {
     const NearPair pr = pairs[blockIdx.y];
     const int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
     if (e >= static_cast<int64_t>(pr.ld) * pr.nb) return;
     const int i = static_cast<int>(e % pr.ld), j = static_cast<int>(e / pr.ld);
-    out[pr.off + e] = i < pr.na ? kval(P, perm[pr.a0 + i], perm[pr.b0 + j]) : 0.0;
+    const double v = i < pr.na ? kval(P, perm[pr.a0 + i], perm[pr.b0 + j]) : 0.0;
+    out[pr.off + e] = v;
+    if (out32) out32[pr.off + e] = static_cast<float>(v);
 }
 
 struct FarBlock {
@@ -2051,10 +2055,17 @@ static void build_near_tiles(Op& op, const Geo& G, hipStream_t s) {
         HDM_HIP(hipStreamSynchronize(s));   // the host copy of the pairs goes out of scope
         int64_t maxe = 0;
         for (auto& p : pairs) maxe = std::max<int64_t>(maxe, static_cast<int64_t>(p.ld) * p.nb);
+        // float32 evaluation tiles are written by the same launch
+        float* out32 = nullptr;
+        if (op.prm.near_prec == HDM_F32) {
+            op.nearT.alloc(static_cast<size_t>(std::max<int64_t>(op.near_elems, 1)) * sizeof(float));
+            out32 = reinterpret_cast<float*>(op.nearT.get());
+            op.near_converted = true;
+        }
         for (size_t base = 0; base < pairs.size(); base += 65535) {
             const int cnt = static_cast<int>(std::min<size_t>(65535, pairs.size() - base));
             hipLaunchKernelGGL(k_near_tiles, dim3(ceil_div(maxe, kBlock), cnt), dim3(kBlock), 0, s,
-                               pairs_dev + base, op.perm.get(), P, op.near64.get());
+                               pairs_dev + base, op.perm.get(), P, op.near64.get(), out32);
         }
         check_launch("near tiles");
     }
