@@ -1450,7 +1450,7 @@ __global__ void __launch_bounds__(kBlock) k_pivoted_id(LevelArgs A) {
             // rows [j, nr) all staged: the reflector lives in registers
             const double x0 = Q.sB[(j - Q.T0) * Q.ldS + j];
             const double alpha = x0 >= 0.0 ? -best : best;
-            id_reflect_regs<32, 2>(Q, nsq, j, nr, nc, x0 - alpha);
+            id_reflect_regs<32, 1>(Q, nsq, j, nr, nc, x0 - alpha);
             __syncthreads();
             for (int i = j + threadIdx.x; i < nr; i += blockDim.x) Q.sB[(i - Q.T0) * Q.ldS + j] = (i == j) ? alpha : 0.0;
             rank = j + 1;
