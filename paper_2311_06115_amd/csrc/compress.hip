@@ -1814,6 +1814,7 @@ struct SkelRun {
     DevBuf<int32_t> cand, ncand, rows, nrows, cp, status, uniq, cnt, vts, skel_fix, rows_fix, sizes;
     DevBuf<uint32_t> bits;
     DevBuf<double> B, Pfix;
+    DevBuf<int64_t> offs;   // compaction offsets (skeletons, P, rows), read by k_compact
 };
 
 static void skeletonize_levels(Op& op, const Geo& G, hipStream_t s, SkelRun& R) {
@@ -2002,7 +2003,8 @@ static void skeletonize_finish(Op& op, hipStream_t s, SkelRun& R) {
     std::copy(op.skoff.begin(), op.skoff.end(), offs.begin());
     std::copy(op.poff.begin(), op.poff.end(), offs.begin() + NN);
     std::copy(op.rowoff.begin(), op.rowoff.end(), offs.begin() + 2 * NN);
-    DevBuf<int64_t> d_offs = to_device(offs, s);
+    R.offs = to_device(offs, s);
+    const DevBuf<int64_t>& d_offs = R.offs;
     op.nskel = sk_next;
     op.skel.alloc(sk_next + 1);
     op.rows.alloc(row_next + 1);
@@ -2013,7 +2015,8 @@ static void skeletonize_finish(Op& op, hipStream_t s, SkelRun& R) {
                            R.Pfix.get(), d_rank, d_nc, d_nr, d_offs.get(), d_offs.get() + NN, d_offs.get() + 2 * NN, smax,
                            R.cmax, R.rmax, op.skel.get(), op.P64.get(), op.rows.get());
     check_launch("compact");
-    HDM_HIP(hipStreamSynchronize(s));
+    // no wait: R outlives the compaction (the far tiles wait for s before the
+    // operator build goes on)
 }
 
 // near tiles; with float64 points the launch is left in flight on s (the pair
