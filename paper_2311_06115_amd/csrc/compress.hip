@@ -2074,8 +2074,9 @@ static void build_near_tiles(Op& op, const Geo& G, hipStream_t s) {
     }
 }
 
-// far tiles (after skeletonisation); synchronises s
-static void build_far_tiles(Op& op, const Geo& G, hipStream_t s) {
+// far tiles (after skeletonisation), left in flight on s; their block
+// descriptors go to `keep` (alive until the operator is finished)
+static void build_far_tiles(Op& op, const Geo& G, hipStream_t s, DevBuf<char>& keep) {
     const Pts& P = G.P;
     // far blocks: per node, row-major rank x (sum of far ranks)
     op.far_block_off.assign(op.nnodes, 0);
@@ -2116,18 +2117,26 @@ static void build_far_tiles(Op& op, const Geo& G, hipStream_t s) {
         }
         gram_launch(G, gb, 1, op.far64, s);
     } else if (!blocks.empty()) {
-        DevBuf<FarBlock> db = to_device(blocks, s);
+        keep.alloc(blocks.size() * sizeof(FarBlock));
+        keep.upload(reinterpret_cast<const char*>(blocks.data()), blocks.size() * sizeof(FarBlock), s);
+        const FarBlock* db = reinterpret_cast<const FarBlock*>(keep.get());
         int64_t maxe = 0;
         for (auto& b : blocks) maxe = std::max<int64_t>(maxe, static_cast<int64_t>(b.rows) * b.cols);
         for (size_t base = 0; base < blocks.size(); base += 65535) {
             const int cnt = static_cast<int>(std::min<size_t>(65535, blocks.size() - base));
-            hipLaunchKernelGGL(k_far_tiles, dim3(ceil_div(maxe, kBlock), cnt), dim3(kBlock), 0, s, db.get() + base,
+            hipLaunchKernelGGL(k_far_tiles, dim3(ceil_div(maxe, kBlock), cnt), dim3(kBlock), 0, s, db + base,
                                op.far_colmap.get(), op.skel.get(), P, op.far64.get());
         }
         check_launch("far tiles");
     }
-    HDM_HIP(hipStreamSynchronize(s));
 }
+
+// buffers of the build that queued kernels still read when compress_operator
+// returns: the skeletonisation run (the compaction) and the far-tile descriptors
+struct BuildKeep {
+    SkelRun skel;
+    DevBuf<char> far_blocks;
+};
 
 void compress_operator(Op& op, const void* X, int x_on_device, hipStream_t s) {
     const auto t0 = std::chrono::steady_clock::now();
@@ -2246,7 +2255,8 @@ void compress_operator(Op& op, const void* X, int x_on_device, hipStream_t s) {
     hipLaunchKernelGGL(k_votes, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, side, n, op.depth, op.d_start.get(),
                        op.perm.get(), op.iperm.get(), op.knn_idx.get(), k, votes.get());
     check_launch("votes");
-    SkelRun skr;
+    auto keep = std::make_shared<BuildKeep>();
+    SkelRun& skr = keep->skel;
     skeletonize_levels(op, G, s, skr);
     {
         // through pinned staging when there is some: a pageable download took
@@ -2273,7 +2283,8 @@ void compress_operator(Op& op, const void* X, int x_on_device, hipStream_t s) {
     convert_near_tiles(op, side);
     skeletonize_finish(op, s, skr);
     HDM_HIP(hipStreamWaitEvent(s, op.lane.ready, 0));
-    build_far_tiles(op, G, s);
+    build_far_tiles(op, G, s, keep->far_blocks);
+    op.build_keep = keep;   // released by finish_operator after it has waited for s
     op.seconds_compress = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
 

@@ -1523,6 +1523,7 @@ void finish_operator(Op& op, hipStream_t s) {
     if (op.lane.side) HDM_HIP(hipStreamSynchronize(op.lane.side));
     HDM_HIP(hipStreamSynchronize(s));
     op.near_pairs.release();
+    op.build_keep.reset();
     op.conv_keep.reset();
     if (!(op.prm.near_prec == HDM_F64 && op.prm.far_prec == HDM_F64)) {
         // the float64 tiles were only needed for the degrees

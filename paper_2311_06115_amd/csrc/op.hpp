@@ -200,6 +200,7 @@ struct Op {
     int64_t near_elems = 0;
     mutable unsigned near_calls = 0;           // near-field products so far (their tile order alternates)
     DevBuf<char> near_pairs;                   // pair descriptors of the near-tile launch, until finish_operator
+    std::shared_ptr<void> build_keep;          // build buffers read by work still queued, until finish_operator
     DevBuf<double> near64;
     DevBuf<char> nearT;                        // eval precision copy (near_prec)
     DevBuf<float> near_scale;                  // per near pair
