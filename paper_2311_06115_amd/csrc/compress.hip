@@ -213,16 +213,56 @@ __global__ void __launch_bounds__(64) k_tree_sample(int lvl, const int64_t* star
     if (lane == 0) nsamp[t] = kSample;
 }
 
-// sum over the node's sample of K(x_i, x_j), in ascending sample position
-__global__ void k_tree_sumk(int lvl, int64_t n, const int64_t* start, const int32_t* perm, const int32_t* samp,
-                            const int32_t* nsamp, Pts P, double* sumk) {
-    const int64_t pos = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+// sum over the node's sample of K(x_i, x_j), in ascending sample position.
+// When the workgroup's positions lie in at most two nodes (float64 points of
+// at most kTreeDim coordinates), the nodes' sample points are staged in shared
+// memory and every term is formed from registers and shared memory with the
+// operations of kval in the same order.
+constexpr int kTreeDim = 16;
+__global__ void __launch_bounds__(kBlock) k_tree_sumk(int lvl, int64_t n, const int64_t* start,
+                                                       const int32_t* perm, const int32_t* samp,
+                                                       const int32_t* nsamp, Pts P, double* sumk) {
+    __shared__ double xs[2][kSample][kTreeDim];
+    const int64_t b0 = blockIdx.x * static_cast<int64_t>(blockDim.x);
+    const int64_t b1 = min(n, b0 + static_cast<int64_t>(blockDim.x)) - 1;
+    const int64_t base = int64_t(1) << lvl;
+    const int64_t t0 = node_of(b0, lvl, start) - base, t1 = node_of(b1, lvl, start) - base;
+    const int64_t pos = b0 + threadIdx.x;
+    if (P.is_u8 || P.dim > kTreeDim || t1 - t0 > 1) {   // uniform over the workgroup
+        if (pos >= n) return;
+        const int64_t t = node_of(pos, lvl, start) - base;
+        const int32_t i = perm[pos];
+        double acc = 0.0;
+        const int ns = nsamp[t];
+        for (int q = 0; q < ns; ++q) acc = acc + kval(P, i, perm[samp[t * kSample + q]]);
+        sumk[pos] = acc;
+        return;
+    }
+    const int dim = P.dim;
+    for (int e = threadIdx.x; e < 2 * kSample * dim; e += blockDim.x) {
+        const int k = e / (kSample * dim), q = (e / dim) % kSample, d = e % dim;
+        const int64_t t = k == 0 ? t0 : t1;
+        xs[k][q][d] = q < nsamp[t] ? P.xf[static_cast<int64_t>(perm[samp[t * kSample + q]]) * dim + d] : 0.0;
+    }
+    __syncthreads();
     if (pos >= n) return;
-    const int64_t t = node_of(pos, lvl, start) - (int64_t(1) << lvl);
-    const int32_t i = perm[pos];
+    const int k = (t1 != t0 && pos >= start[base + t1]) ? 1 : 0;
+    const int ns = nsamp[k == 0 ? t0 : t1];
+    const double* xi = P.xf + static_cast<int64_t>(perm[pos]) * dim;
+    double a[kTreeDim];
+#pragma unroll
+    for (int d = 0; d < kTreeDim; ++d) a[d] = d < dim ? xi[d] : 0.0;
     double acc = 0.0;
-    const int ns = nsamp[t];
-    for (int q = 0; q < ns; ++q) acc = acc + kval(P, i, perm[samp[t * kSample + q]]);
+    for (int q = 0; q < ns; ++q) {
+        double sq = 0.0;
+#pragma unroll
+        for (int d = 0; d < kTreeDim; ++d)
+            if (d < dim) {
+                const double t = a[d] - xs[k][q][d];
+                sq = sq + t * t;
+            }
+        acc = acc + exp(-(sq / P.eps));
+    }
     sumk[pos] = acc;
 }
 
@@ -248,31 +288,49 @@ __device__ inline void block_argbest(double& v, int64_t& p, bool want_min, doubl
 }
 
 // p = argmin sumk (the point farthest from the sample centroid in feature space),
-// q = argmax ||x - x_p||^2; ties go to the lower position
-__global__ void k_tree_pq(int lvl, const int64_t* start, const int64_t* size, const int32_t* perm,
-                          const double* sumk, Pts P, int32_t* pq) {
-    __shared__ double sv[kBlock];
-    __shared__ int64_t sp[kBlock];
+// q = argmax ||x - x_p||^2; ties go to the lower position.  Each thread scans
+// its positions in increasing order, eight loads in flight.
+constexpr int kPqBlock = 1024;
+__global__ void __launch_bounds__(kPqBlock) k_tree_pq(int lvl, const int64_t* start, const int64_t* size,
+                                                      const int32_t* perm, const double* sumk, Pts P, int32_t* pq) {
+    __shared__ double sv[kPqBlock];
+    __shared__ int64_t sp[kPqBlock];
     const int64_t t = blockIdx.x;
     const int64_t h = (int64_t(1) << lvl) + t;
-    const int64_t s0 = start[h], n = size[h];
+    const int64_t s0 = start[h], n = size[h], s1 = s0 + n;
+    const int64_t B = blockDim.x;
     double best = INFINITY;
     int64_t bpos = INT64_MAX;
-    for (int64_t pos = s0 + threadIdx.x; pos < s0 + n; pos += blockDim.x) {
-        const double v = sumk[pos];
-        if (v < best || (v == best && pos < bpos)) { best = v; bpos = pos; }
+    for (int64_t p0 = s0 + threadIdx.x; p0 < s1; p0 += 8 * B) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = p0 + u * B < s1 ? sumk[p0 + u * B] : INFINITY;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int64_t pos = p0 + u * B;
+            if (pos < s1 && (v[u] < best || (v[u] == best && pos < bpos))) { best = v[u]; bpos = pos; }
+        }
     }
     block_argbest(best, bpos, true, sv, sp);
-    if (bpos < s0 || bpos >= s0 + n) bpos = s0;   // only reachable with non-finite sums
+    if (bpos < s0 || bpos >= s1) bpos = s0;   // only reachable with non-finite sums
     const int32_t ip = perm[bpos];
     double far = -1.0;
     int64_t fpos = INT64_MAX;
-    for (int64_t pos = s0 + threadIdx.x; pos < s0 + n; pos += blockDim.x) {
-        const double d = sqd(P, perm[pos], ip);
-        if (d > far || (d == far && pos < fpos)) { far = d; fpos = pos; }
+    for (int64_t p0 = s0 + threadIdx.x; p0 < s1; p0 += 8 * B) {
+        int32_t ii[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) ii[u] = perm[min(p0 + u * B, s1 - 1)];
+        double d[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) d[u] = sqd(P, ii[u], ip);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int64_t pos = p0 + u * B;
+            if (pos < s1 && (d[u] > far || (d[u] == far && pos < fpos))) { far = d[u]; fpos = pos; }
+        }
     }
     block_argbest(far, fpos, false, sv, sp);
-    if (fpos < s0 || fpos >= s0 + n) fpos = s0;
+    if (fpos < s0 || fpos >= s1) fpos = s0;
     if (threadIdx.x == 0) {
         pq[2 * t] = ip;
         pq[2 * t + 1] = perm[fpos];
@@ -1704,7 +1762,7 @@ struct TreeBuild {
                 hipLaunchKernelGGL(k_tree_sumk, dim3(gN), dim3(kBlock), 0, s, lvl, n, op.d_start.get(), perm.get(),
                                    samp.get(), nsamp.get(), P, sumk.get());
             }
-            hipLaunchKernelGGL(k_tree_pq, dim3(nodes), dim3(kBlock), 0, s, lvl, op.d_start.get(), op.d_size.get(),
+            hipLaunchKernelGGL(k_tree_pq, dim3(nodes), dim3(kPqBlock), 0, s, lvl, op.d_start.get(), op.d_size.get(),
                                perm.get(), sumk.get(), P, pq.get());
         } else {
             hipLaunchKernelGGL(k_knn_pq, dim3(ceil_div(nodes, 64), ntrees), dim3(64), 0, s, lvl, op.d_start.get(),
