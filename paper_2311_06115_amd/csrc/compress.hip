@@ -2271,8 +2271,8 @@ void compress_operator(Op& op, const void* X, int x_on_device, hipStream_t s) {
         std::unique_ptr<TreeBuild> knn;
         if (T > 0) knn.reset(new TreeBuild(op, 1, 0, T, kperm, ktmp, G, s, samp, nsamp, kpq, sumk, kkey));
         for (int lvl = 0; lvl < op.depth; ++lvl) {
-            ball.level(lvl);
             if (knn) knn->level(lvl);
+            ball.level(lvl);
         }
     }
     op.perm = std::move(perm);
