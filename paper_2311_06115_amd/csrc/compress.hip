@@ -718,19 +718,37 @@ __global__ void k_inverse_perm(const int32_t* perm, int32_t* iperm, int64_t n) {
     if (t < n) iperm[perm[t]] = static_cast<int32_t>(t);
 }
 
-// votes[a][b] = number of (point in leaf a, neighbour in leaf b) pairs
-__global__ void k_votes(int64_t n, int depth, const int64_t* start, const int32_t* perm, const int32_t* iperm,
-                        const int32_t* kidx, int k, int32_t* votes) {
-    const int64_t pos = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-    if (pos >= n) return;
+// leaf index of every tree position (one workgroup per leaf)
+__global__ void k_leaf_of(int depth, const int64_t* start, const int64_t* size, int32_t* leaf_of) {
+    const int64_t a = blockIdx.x, h = (int64_t(1) << depth) + a;
+    for (int64_t p = start[h] + threadIdx.x; p < start[h] + size[h]; p += blockDim.x)
+        leaf_of[p] = static_cast<int32_t>(a);
+}
+
+// votes[a][b] = number of (point in leaf a, neighbour in leaf b) pairs: one
+// workgroup per leaf a counts its row in shared memory (L bins) and writes it;
+// with kGlobal (too many leaves for shared memory) it counts straight into the
+// zeroed row
+template <bool kGlobal>
+__global__ void k_votes(int depth, const int64_t* start, const int64_t* size, const int32_t* perm,
+                        const int32_t* iperm, const int32_t* kidx, int k, const int32_t* leaf_of, int32_t* votes) {
+    extern __shared__ int32_t vh[];
     const int64_t L = int64_t(1) << depth;
-    const int64_t a = node_of(pos, depth, start) - L;
-    const int32_t i = perm[pos];
-    for (int t = 0; t < k; ++t) {
-        const int32_t j = kidx[static_cast<int64_t>(i) * k + t];
-        if (j < 0) continue;
-        const int64_t b = node_of(iperm[j], depth, start) - L;
-        atomicAdd(&votes[a * L + b], 1);
+    const int64_t a = blockIdx.x, h = L + a;
+    const int64_t s0 = start[h], cnt = size[h] * k;
+    int32_t* row = kGlobal ? votes + a * L : vh;
+    if (!kGlobal) {
+        for (int64_t b = threadIdx.x; b < L; b += blockDim.x) vh[b] = 0;
+        __syncthreads();
+    }
+    for (int64_t e = threadIdx.x; e < cnt; e += blockDim.x) {
+        const int32_t i = perm[s0 + e / k];
+        const int32_t j = kidx[static_cast<int64_t>(i) * k + e % k];
+        if (j >= 0) atomicAdd(&row[leaf_of[iperm[j]]], 1);
+    }
+    if (!kGlobal) {
+        __syncthreads();
+        for (int64_t b = threadIdx.x; b < L; b += blockDim.x) votes[a * L + b] = vh[b];
     }
 }
 
@@ -2308,10 +2326,19 @@ void compress_operator(Op& op, const void* X, int x_on_device, hipStream_t s) {
     HDM_HIP(hipEventRecord(op.lane.fork, s));
     HDM_HIP(hipStreamWaitEvent(s, op.lane.join, 0));   // the ball tree and its inverse permutation
     HDM_HIP(hipStreamWaitEvent(side, op.lane.fork, 0));
-    DevBuf<int32_t> votes(static_cast<size_t>(op.L) * op.L);
-    HDM_HIP(hipMemsetAsync(votes.get(), 0, votes.bytes(), side));
-    hipLaunchKernelGGL(k_votes, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, side, n, op.depth, op.d_start.get(),
-                       op.perm.get(), op.iperm.get(), op.knn_idx.get(), k, votes.get());
+    DevBuf<int32_t> votes(static_cast<size_t>(op.L) * op.L), leaf_of(n);
+    hipLaunchKernelGGL(k_leaf_of, dim3(op.L), dim3(kBlock), 0, side, op.depth, op.d_start.get(), op.d_size.get(),
+                       leaf_of.get());
+    if (op.L <= 8192) {
+        hipLaunchKernelGGL(k_votes<false>, dim3(op.L), dim3(kBlock), sizeof(int32_t) * static_cast<size_t>(op.L), side,
+                           op.depth, op.d_start.get(), op.d_size.get(), op.perm.get(), op.iperm.get(),
+                           op.knn_idx.get(), k, leaf_of.get(), votes.get());
+    } else {
+        HDM_HIP(hipMemsetAsync(votes.get(), 0, votes.bytes(), side));
+        hipLaunchKernelGGL(k_votes<true>, dim3(op.L), dim3(kBlock), 0, side, op.depth, op.d_start.get(),
+                           op.d_size.get(), op.perm.get(), op.iperm.get(), op.knn_idx.get(), k, leaf_of.get(),
+                           votes.get());
+    }
     check_launch("votes");
     auto keep = std::make_shared<BuildKeep>();
     SkelRun& skr = keep->skel;
