@@ -1821,11 +1821,13 @@ static void build_near_lists(Op& op, const std::vector<int32_t>& votes) {
         int cnt = 0;
         for (int64_t b = 0; b < L; ++b)
             if (b != a) order[cnt++] = static_cast<int32_t>(b);
-        std::stable_sort(order.begin(), order.begin() + cnt, [&](int32_t x, int32_t y) {
+        // the first `extra` by (votes desc, id asc), a strict order: only they are sorted
+        const int64_t top = std::min<int64_t>(extra, cnt);
+        std::partial_sort(order.begin(), order.begin() + top, order.begin() + cnt, [&](int32_t x, int32_t y) {
             const int32_t vx = votes[a * L + x], vy = votes[a * L + y];
             return vx != vy ? vx > vy : x < y;
         });
-        for (int64_t t = 0; t < extra && t < cnt; ++t) rel[a * L + order[t]] = 1;
+        for (int64_t t = 0; t < top; ++t) rel[a * L + order[t]] = 1;
     }
     for (int64_t a = 0; a < L; ++a)
         for (int64_t b = 0; b < L; ++b)
