@@ -219,126 +219,180 @@ __global__ void __launch_bounds__(kBlock) k_l2l(Batch b) {
 // (the S2N pass restricted to one path), applies P_leaf^T, adds the near-field
 // partial sums of the leaf's rows and writes the scaled result in original order.
 constexpr int kMaxRank = 512;
-// Per leaf, one workgroup of kCombBlock threads: the downward chain along the
-// leaf's ancestors (the path's P slices and far-field values staged in shared
-// memory first, all loads independent), the near partial sums (four quarters of
-// the workgroup take a quarter of the items each, added in a fixed order), the
-// leaf's P^T u~, the alpha = 1 scale, and the scatter to the original order.
+// Single right-hand side (several go to k_combine_m).  One workgroup of
+// kCombBlock threads per leaf, in three phases, so that a leaf pays a few memory
+// round trips rather than several per ancestor:
+//  1. the ranks and offsets along the leaf's path, one level per thread;
+//  2. every load that does not depend on the chain, issued together: the
+//     path's P slices and far-field values staged in shared memory as one flat
+//     array, the near partial sums of the leaf's first rows (four quarters of
+//     the workgroup take a quarter of the items each, items in order) and the
+//     leaf's P entries (a quarter of its skeleton rows each), and the scale and
+//     destination of each row;
+//  3. the downward chain from shared memory, then per row the quarters' near
+//     sums and P_leaf^T u~ sums added in a fixed order, the alpha = 1 scale and
+//     the scatter to the original order.
 constexpr int kCombBlock = 1024;
+constexpr int kCombQ = kCombBlock / 4;
 constexpr int kChainStageBytes = 65536;
-
-template <typename V, typename TP>
-__device__ inline void stage_slice(V* dst, const TP* src, int rp, int rn, int ld) {
-    const int tot = rp * rn;
-    for (int e0 = threadIdx.x; e0 < tot; e0 += 4 * kCombBlock) {
-        TP x[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int e = min(e0 + q * kCombBlock, tot - 1);
-            x[q] = src[static_cast<int64_t>(e / rn) * ld + e % rn];
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-            if (e0 + q * kCombBlock < tot) dst[e0 + q * kCombBlock] = static_cast<V>(x[q]);
-    }
-}
+// near partial sums and P_leaf entries in flight per thread (halved for float64
+// so that the workgroup's 1024 threads fit their registers)
+template <typename V> constexpr int kNearBatch = sizeof(V) == 4 ? 16 : 8;
+template <typename V> constexpr int kLeafBatch = sizeof(V) == 4 ? 16 : 8;
 
 template <typename V, typename TP>
 __global__ void __launch_bounds__(kCombBlock) k_combine(Batch b) {
     constexpr int kStage = kChainStageBytes / static_cast<int>(sizeof(V));
     __shared__ V tot[2][kMaxRank];
     __shared__ V chain[kStage];
-    __shared__ V quarter[4][kCombBlock / 4];
+    __shared__ V quarter[2][4][kCombQ];
+    __shared__ int m_rn[kMaxLevels + 1], m_rp[kMaxLevels + 1], m_ncp[kMaxLevels + 1];
+    __shared__ int64_t m_pb[kMaxLevels + 1], m_sk[kMaxLevels + 1], m_pleaf;
     const int64_t u = blockIdx.x;
     const int o = batch_op(b, u);
     const OpDev& D = *b.op[o];
     const LeafPlan lp = D.leaves[u - b.pre[o]];
     const TP* P = static_cast<const TP*>(D.P);
     const V* sku = static_cast<const V*>(D.sku);
+    const V* pc = static_cast<const V*>(D.part) + lp.part_off;
     const int depth = D.row_total > 0 ? D.depth : 0;
-    int64_t need = 0;
-    for (int lvl = 2; lvl <= depth; ++lvl) {
-        const int64_t node = lp.heap >> (depth - lvl);
-        need += static_cast<int64_t>(D.rank[node >> 1]) * D.rank[node];
+    const int tid = threadIdx.x;
+    // 1. the node at level lvl of the path is heap >> (depth - lvl)
+    if (tid >= 1 && tid <= depth) {
+        const int64_t node = static_cast<int64_t>(lp.heap) >> (depth - tid);
+        m_rn[tid] = D.rank[node];
+        m_sk[tid] = D.skoff[node];
+        if (tid >= 2) {
+            const int64_t par = node >> 1;
+            m_rp[tid] = D.rank[par];
+            m_ncp[tid] = D.ncand[par];
+            m_pb[tid] = D.poff[par] + ((node & 1) ? D.rank[2 * par] : 0);
+        }
     }
+    if (tid == 0 && depth >= 1) m_pleaf = D.poff[lp.heap];
+    __syncthreads();
+    // level lvl's slice of the chain buffer: rp x rn of P_parent (the node's
+    // columns), then the node's rn far-field values
+    int64_t need = 0;
+    for (int lvl = 2; lvl <= depth; ++lvl) need += static_cast<int64_t>(m_rp[lvl] + 1) * m_rn[lvl];
     const bool staged = need <= kStage;
-    for (int c = 0; c < b.nrhs; ++c) {
-        int cur = 0;
-        int rleaf = 0;
-        if (depth >= 1) {
-            const int64_t a1 = lp.heap >> (depth - 1);
-            for (int i = threadIdx.x; i < D.rank[a1]; i += blockDim.x) tot[0][i] = sku[c * D.ldsk + D.skoff[a1] + i];
-            if (staged && c == 0) {
-                int64_t off = 0;
-                for (int lvl = 2; lvl <= depth; ++lvl) {
-                    const int64_t node = lp.heap >> (depth - lvl), par = node >> 1;
-                    const int rp = D.rank[par], rn = D.rank[node];
-                    const TP* Pm = P + D.poff[par] + ((node & 1) ? D.rank[2 * par] : 0);
-                    stage_slice<V>(chain + off, Pm, rp, rn, D.ncand[par]);
-                    off += static_cast<int64_t>(rp) * rn;
+    const int rleaf = depth >= 1 ? m_rn[depth] : 0;
+
+    // 2. independent loads
+    if (depth >= 1)
+        for (int i = tid; i < m_rn[1]; i += kCombBlock) tot[0][i] = sku[m_sk[1] + i];
+    if (staged && need > 0) {
+        // need <= kStage here, so the flat index fits in 32 bits; each thread's
+        // elements come in increasing order, so its level only advances
+        const int nd = static_cast<int>(need);
+        int lvl = 2, lo = 0, sz = (m_rp[2] + 1) * m_rn[2];
+        for (int g0 = tid; g0 < nd; g0 += 8 * kCombBlock) {
+            V x[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int g = min(g0 + t * kCombBlock, nd - 1);
+                while (g >= lo + sz) {
+                    lo += sz;
+                    ++lvl;
+                    sz = (m_rp[lvl] + 1) * m_rn[lvl];
                 }
+                const int rn = m_rn[lvl];
+                const int e = g - lo, pe = m_rp[lvl] * rn;
+                x[t] = e < pe ? static_cast<V>(P[m_pb[lvl] + static_cast<int64_t>(e / rn) * m_ncp[lvl] + e % rn])
+                              : sku[m_sk[lvl] + (e - pe)];
             }
-            __syncthreads();
-            int64_t off = 0;
-            for (int lvl = 2; lvl <= depth; ++lvl) {
-                const int64_t node = lp.heap >> (depth - lvl), par = node >> 1;
-                const int rp = D.rank[par], ncp = D.ncand[par], rn = D.rank[node];
-                const TP* Pm = P + D.poff[par] + ((node & 1) ? D.rank[2 * par] : 0);
-                for (int j = threadIdx.x; j < rn; j += blockDim.x) {
-                    V acc = 0;
-                    if (staged) {
-                        const V* Ps = chain + off;
-                        for (int i = 0; i < rp; ++i) acc += Ps[i * rn + j] * tot[cur][i];
-                    } else {
-                        for (int i = 0; i < rp; ++i) acc += static_cast<V>(Pm[static_cast<int64_t>(i) * ncp + j]) * tot[cur][i];
-                    }
-                    tot[cur ^ 1][j] = sku[c * D.ldsk + D.skoff[node] + j] + acc;
-                }
-                off += static_cast<int64_t>(rp) * rn;
-                __syncthreads();
-                cur ^= 1;
-            }
-            rleaf = D.rank[lp.heap];
+#pragma unroll
+            for (int t = 0; t < 8; ++t)
+                if (g0 + t * kCombBlock < nd) chain[g0 + t * kCombBlock] = x[t];
         }
-        const TP* Pl = P + D.poff[lp.heap];
-        const V* pc = static_cast<const V*>(D.part) + c * D.ldp + lp.part_off;
-        const int q = threadIdx.x / (kCombBlock / 4), jq = threadIdx.x % (kCombBlock / 4);
-        const int per = (lp.nitems + 3) / 4;
-        const int i0 = min(lp.nitems, q * per), i1 = min(lp.nitems, i0 + per);
-        for (int j0 = 0; j0 < lp.rows; j0 += kCombBlock / 4) {
-            const int j = j0 + jq;
-            V near = 0;
-            if (j < lp.rows) {
-                int it = i0;
-                for (; it + 8 <= i1; it += 8) {
-                    V x[8];
+    }
+    const int q = tid / kCombQ, jq = tid % kCombQ;
+    const int per = (lp.nitems + 3) / 4;
+    const int i0 = min(lp.nitems, q * per), i1 = min(lp.nitems, i0 + per);
+    const int pr = (rleaf + 3) / 4;
+    const int k0 = min(rleaf, q * pr), k1 = min(rleaf, k0 + pr);
+    const TP* Pl = P + (depth >= 1 ? m_pleaf : 0);
+    auto near_sum = [&](int j) {
+        V near = 0;
+        if (j < lp.rows) {
+            // the last batch clamps its indexes and adds only the items in range
+            for (int it = i0; it < i1; it += kNearBatch<V>) {
+                V x[kNearBatch<V>];
 #pragma unroll
-                    for (int t = 0; t < 8; ++t) x[t] = pc[static_cast<int64_t>(it + t) * lp.ld + j];
+                for (int t = 0; t < kNearBatch<V>; ++t) x[t] = pc[static_cast<int64_t>(min(it + t, i1 - 1)) * lp.ld + j];
 #pragma unroll
-                    for (int t = 0; t < 8; ++t) near += x[t];
-                }
-                for (; it < i1; ++it) near += pc[static_cast<int64_t>(it) * lp.ld + j];
+                for (int t = 0; t < kNearBatch<V>; ++t)
+                    if (it + t < i1) near += x[t];
             }
-            quarter[q][jq] = near;
-            __syncthreads();
-            if (q == 0 && j < lp.rows) {
-                V f = 0;
-                int i = 0;
-                for (; i + 8 <= rleaf; i += 8) {
-                    TP pv[8];
+        }
+        return near;
+    };
+    TP pv[kLeafBatch<V>];
+    auto leaf_load = [&](int k, int j) {
+        const int jc = min(j, lp.rows - 1);
 #pragma unroll
-                    for (int t = 0; t < 8; ++t) pv[t] = Pl[static_cast<int64_t>(i + t) * lp.rows + j];
+        for (int t = 0; t < kLeafBatch<V>; ++t) pv[t] = Pl[static_cast<int64_t>(min(k + t, k1 - 1)) * lp.rows + jc];
+    };
+    const V near0 = near_sum(jq);
+    const bool pre = k1 > k0 && k1 - k0 <= kLeafBatch<V>;
+    if (pre) leaf_load(k0, jq);
+    double sc0 = 1.0;
+    int64_t dst0 = 0;
+    if (q == 0 && jq < lp.rows) {
+        const int64_t pos = lp.start + jq;
+        sc0 = b.arg[o] ? D.c[pos] : 1.0;
+        dst0 = D.perm[pos];
+    }
+    __syncthreads();
+
+    // 3. downward chain: u~_child = S2S(child) + (P_parent^T u~_parent)[child's columns]
+    int cur = 0;
+    int64_t off = 0;
+    for (int lvl = 2; lvl <= depth; ++lvl) {
+        const int rp = m_rp[lvl], rn = m_rn[lvl];
+        for (int j = tid; j < rn; j += kCombBlock) {
+            V acc = 0;
+            if (staged) {
+                const V* Ps = chain + off;
+                for (int i = 0; i < rp; ++i) acc += Ps[i * rn + j] * tot[cur][i];
+                tot[cur ^ 1][j] = Ps[static_cast<int64_t>(rp) * rn + j] + acc;
+            } else {
+                const TP* Pm = P + m_pb[lvl];
+                const int ncp = m_ncp[lvl];
+                for (int i = 0; i < rp; ++i) acc += static_cast<V>(Pm[static_cast<int64_t>(i) * ncp + j]) * tot[cur][i];
+                tot[cur ^ 1][j] = sku[m_sk[lvl] + j] + acc;
+            }
+        }
+        off += static_cast<int64_t>(rp + 1) * rn;
+        __syncthreads();
+        cur ^= 1;
+    }
+    for (int j0 = 0; j0 < lp.rows; j0 += kCombQ) {
+        const int j = j0 + jq;
+        const V near = j0 == 0 ? near0 : near_sum(j);
+        V f = 0;
+        for (int k = k0; k < k1; k += kLeafBatch<V>) {
+            if (!(pre && j0 == 0)) leaf_load(k, j);
 #pragma unroll
-                    for (int t = 0; t < 8; ++t) f += static_cast<V>(pv[t]) * tot[cur][i + t];
-                }
-                for (; i < rleaf; ++i) f += static_cast<V>(Pl[static_cast<int64_t>(i) * lp.rows + j]) * tot[cur][i];
-                const V nsum = (quarter[0][jq] + quarter[1][jq]) + (quarter[2][jq] + quarter[3][jq]);
+            for (int t = 0; t < kLeafBatch<V>; ++t)
+                if (k + t < k1) f += static_cast<V>(pv[t]) * tot[cur][k + t];
+        }
+        quarter[0][q][jq] = near;
+        quarter[1][q][jq] = f;
+        __syncthreads();
+        if (q == 0 && j < lp.rows) {
+            const V nsum = (quarter[0][0][jq] + quarter[0][1][jq]) + (quarter[0][2][jq] + quarter[0][3][jq]);
+            const V fsum = (quarter[1][0][jq] + quarter[1][1][jq]) + (quarter[1][2][jq] + quarter[1][3][jq]);
+            double sc = sc0;
+            int64_t dst = dst0;
+            if (j0 > 0) {
                 const int64_t pos = lp.start + j;
-                const double sc = b.arg[o] ? D.c[pos] : 1.0;
-                b.y[o][c * D.n + D.perm[pos]] = sc * static_cast<double>(nsum + f);
+                sc = b.arg[o] ? D.c[pos] : 1.0;
+                dst = D.perm[pos];
             }
-            __syncthreads();
+            b.y[o][dst] = sc * static_cast<double>(nsum + fsum);
         }
+        __syncthreads();
     }
 }
 

@@ -75,7 +75,11 @@ def test_block_eigenvalues_against_stored_oracle(c4):
     V = vecs.cpu().numpy()
     assert np.linalg.norm(V[:, 0] - want) <= 1e-5
     np.testing.assert_allclose(np.linalg.norm(V, axis=0), 1.0, atol=1e-12)
-    # single-vector Lanczos on the same operator agrees
+    # single-vector Lanczos on the same operator agrees.  The two paths apply the
+    # same tiles with float32 sums in different orders; by Weyl's inequality each
+    # eigenvalue moves by at most the norm of the difference of the two products,
+    # so the bound is absolute, on the scale of ||K~|| = lambda_1 = 1 (measured
+    # 1.2e-8 at lambda_1, 3e-9 at lambda_20 = 2.5e-3)
     ev1, _, i1, s1 = op.eigs(cfg["r"], tol=1e-10, block=1, seed=cfg["seed"], vectors=False)
     assert s1 == 0
-    assert np.max(np.abs(ev1 - ev) / np.abs(ev1)) <= 1e-6
+    assert np.max(np.abs(ev1 - ev)) <= 1e-7 * abs(ev1[0])
