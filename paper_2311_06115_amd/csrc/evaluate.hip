@@ -70,6 +70,7 @@ __device__ inline A wave_sum(A v) {
 struct Batch {
     int nops, nrhs;
     int flip;                     // near field: work items taken in reverse order
+    int up;                       // near field: leading workgroups that run the upward pass
     const OpDev* op[kMaxBatch];
     int64_t pre[kMaxBatch + 1];
     int32_t arg[kMaxBatch];       // per operator: tree level (N2S) or normalised flag (prep, combine)
@@ -157,14 +158,74 @@ __global__ void k_s2s(Batch b) {
     }
 }
 
+// ---- upward pass carried by the near-field launch ------------------------------
+// One operator, one right-hand side.  The first b.up workgroups of the near-field
+// grid, one per leaf, form the skeleton weights from the leaves up, with the same
+// row dot products as k_n2s; a workgroup that has finished its node counts its
+// arrival at the parent, the second child to arrive goes on with the parent and
+// the first stops.  Nothing waits, so every workgroup ends, and the counter is
+// back at zero for the next launch.  The weights pass between workgroups (which
+// may sit on different XCDs, whose L2 caches are not coherent) through
+// device-scope atomic stores and loads, and a workgroup's stores have completed
+// before its arrival is counted.  The upward pass needs only the staged vector,
+// so it runs beside the tile streaming instead of before it.
+template <typename T>
+__device__ inline void st_agent(T* p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ inline T ld_agent(const T* p) {
+    return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename V>
+__device__ inline void upward_pass(const Batch& b, int64_t leaf) {
+    const OpDev& D = *b.op[0];
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    const V* P = static_cast<const V*>(D.P);
+    V* skw = static_cast<V*>(D.skw);
+    int64_t h = D.L + leaf;
+    for (int lvl = D.depth; lvl >= 1; --lvl, h >>= 1) {
+        const int rk = D.rank[h], nc = D.ncand[h];
+        const V* Ph = P + D.poff[h];
+        V* out = skw + D.skoff[h];
+        if (lvl == D.depth) {   // leaf: w~_h = P_h w_h
+            const V* in = static_cast<const V*>(D.w) + D.start[h];
+            for (int i = wave; i < rk; i += nw) {
+                const V acc = row_dot<V>(Ph + static_cast<int64_t>(i) * nc, nc, [&](int j) { return in[j]; });
+                if (lane == 0) st_agent(out + i, acc);
+            }
+        } else {                // inner: w~_h = P_h [w~_left; w~_right]
+            const V* in = skw + D.skoff[2 * h];
+            for (int i = wave; i < rk; i += nw) {
+                const V acc =
+                    row_dot<V>(Ph + static_cast<int64_t>(i) * nc, nc, [&](int j) { return ld_agent(in + j); });
+                if (lane == 0) st_agent(out + i, acc);
+            }
+        }
+        if (lvl == 1) break;
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        int second = 0;
+        if (threadIdx.x == 0)
+            second = __hip_atomic_fetch_add(D.up_count + (h >> 1), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 1u;
+        if (!__syncthreads_or(second)) break;
+        if (threadIdx.x == 0) __hip_atomic_store(D.up_count + (h >> 1), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
 // ---- L2L: stream the near tiles; one wave per work item ---------------------
 // Lane l owns RPL consecutive rows (16 bytes of tile per lane per column) of
 // each 64*RPL-row pass over the item's rows; the item's columns are consecutive
 // tree positions, so w is read as a wave-uniform value.
-template <typename V, typename TN>
+template <typename V, typename TN, bool kUp>
 __global__ void __launch_bounds__(kBlock) k_l2l(Batch b) {
     constexpr int RPL = 16 / sizeof(TN);
-    int64_t u = blockIdx.x * static_cast<int64_t>(blockDim.x / kWave) + threadIdx.x / kWave;
+    if (kUp && static_cast<int>(blockIdx.x) < b.up) {
+        upward_pass<V>(b, blockIdx.x);
+        return;
+    }
+    int64_t u = (blockIdx.x - b.up) * static_cast<int64_t>(blockDim.x / kWave) + threadIdx.x / kWave;
     if (u >= b.pre[b.nops]) return;
     if (b.flip) u = b.pre[b.nops] - 1 - u;
     const int o = batch_op(b, u);
@@ -601,8 +662,13 @@ __global__ void __launch_bounds__(kBlock) k_prep_mma(Batch b) {
 
 // One wave per item: up to 8 row tiles of 16 rows of one near tile against all
 // its columns, 32 columns per step, hi and lo halves of the vectors in turn.
+template <bool kUp>
 __global__ void __launch_bounds__(kBlock) k_l2l_mma(Batch b) {
-    int64_t u = blockIdx.x * static_cast<int64_t>(blockDim.x / kWave) + threadIdx.x / kWave;
+    if (kUp && static_cast<int>(blockIdx.x) < b.up) {
+        upward_pass<float>(b, blockIdx.x);
+        return;
+    }
+    int64_t u = (blockIdx.x - b.up) * static_cast<int64_t>(blockDim.x / kWave) + threadIdx.x / kWave;
     if (u >= b.pre[b.nops]) return;
     if (b.flip) u = b.pre[b.nops] - 1 - u;
     const int o = batch_op(b, u);
@@ -846,6 +912,7 @@ static void publish_descriptors(Op& op, hipStream_t s) {
         D.wh = nullptr;
         D.wsc = nullptr;
         D.ldw = 0;
+        D.up_count = op.up_count.get();
         if (!f64 && op.packed) {   // matrix-core plan of the packed half-precision tiles
             D.items = op.d_items_mma.get();
             D.nitems = static_cast<int64_t>(op.items_mma.size());
@@ -1032,6 +1099,23 @@ void build_eval_plan(Op& op, hipStream_t s) {
     op.d_row_tasks = reinterpret_cast<const RowTask*>(base + o_tasks);
     op.lane.init(op.ctx ? &op.ctx->lanes : nullptr);
     ensure_ws(op, 1);
+    op.up_count.alloc(static_cast<size_t>(std::max(op.L, 1)));
+    HDM_HIP(hipMemsetAsync(op.up_count.get(), 0, op.up_count.bytes(), s));
+    // Expected time of the upward pass climbing as one chain beside the near
+    // field: per level, the widest node's rows pass through a workgroup's four
+    // waves one row dot product (256 columns) at a time, plus the stores and the
+    // arrival; up to 1.6 us per dependent step while the tiles stream (measured
+    // on 65536 x 784 inputs, every rank at 256; 0.8 us at N = 32768 in 3-D).
+    double steps = 0.0;
+    for (int lvl = op.depth; lvl >= 1; --lvl) {
+        int mr = 0, mc = 0;
+        for (int64_t h = int64_t(1) << lvl; h < (int64_t(1) << (lvl + 1)); ++h) {
+            mr = std::max(mr, op.rank[h]);
+            mc = std::max(mc, op.ncand[h]);
+        }
+        steps += static_cast<double>(ceil_div(mr, 4)) * static_cast<double>(ceil_div(std::max(mc, 1), 256)) + 3.0;
+    }
+    op.up_chain_us = 1.6 * steps;
     publish_descriptors(op, s);
 }
 
@@ -1085,17 +1169,28 @@ static void apply_t(const ApplyReq* reqs, int nops, bool f64, int normalised, in
     // every other product starts each pass on the tiles the previous one read
     // last, which are still cached.  Each item writes its own partial sums, so
     // the order does not change the result.
+    // One operator and one right-hand side: the upward pass rides in the near
+    // field's launch (its first workgroups, one per leaf), so that it runs beside
+    // the tile streaming; the far field follows once both are done.
+    // This pays where the tiles take longer to stream than the chain of the
+    // upward pass takes to climb, which the plan estimates per operator.
+    const bool fuse_up = tree && !multi && nops == 1 && reqs[0].op->up_fused(sizeof(TN));
+    b.up = fuse_up ? static_cast<int>(reqs[0].op->L) : 0;
     auto near_field = [&] {
         const int64_t tot = prefix([](const Op& op, int) {
             return static_cast<int64_t>(mma ? op.items_mma.size() : op.items.size());
         });
         b.flip = static_cast<int>(reqs[0].op->near_calls++ & 1u);
+        const int64_t grid = ceil_div(tot, wpb) + b.up;
         KernelEvents ev(cx, HDM_PHASE_L2L);
-        if (mma)
-            hipExtLaunchKernelGGL(k_l2l_mma, dim3(ceil_div(tot, wpb)), dim3(kBlock), 0, s, ev.start, ev.stop, 0, b);
+        if (mma && fuse_up)
+            hipExtLaunchKernelGGL(k_l2l_mma<true>, dim3(grid), dim3(kBlock), 0, s, ev.start, ev.stop, 0, b);
+        else if (mma)
+            hipExtLaunchKernelGGL(k_l2l_mma<false>, dim3(grid), dim3(kBlock), 0, s, ev.start, ev.stop, 0, b);
+        else if (fuse_up)
+            hipExtLaunchKernelGGL((k_l2l<V, TN, true>), dim3(grid), dim3(kBlock), 0, s, ev.start, ev.stop, 0, b);
         else
-            hipExtLaunchKernelGGL((k_l2l<V, TN>), dim3(ceil_div(tot, wpb)), dim3(kBlock), 0, s, ev.start, ev.stop, 0,
-                                  b);
+            hipExtLaunchKernelGGL((k_l2l<V, TN, false>), dim3(grid), dim3(kBlock), 0, s, ev.start, ev.stop, 0, b);
     };
     if (overlap) {
         // fork after the staging; the near field goes first on s (it only needs the
@@ -1103,9 +1198,11 @@ static void apply_t(const ApplyReq* reqs, int nops, bool f64, int normalised, in
         HDM_HIP(hipEventRecord(lane.fork, s));
         near_field();
         HDM_HIP(hipStreamWaitEvent(ts, lane.fork, 0));
+    } else if (fuse_up) {
+        near_field();
     }
     if (tree) {
-        {   // N2S: step k processes level depth - k of every operator
+        if (!fuse_up) {   // N2S: step k processes level depth - k of every operator
             PhaseScope ph(cx, HDM_PHASE_N2S, ts);
             for (int k = 0; k < maxdepth; ++k) {
                 for (int o = 0; o < nops; ++o) b.arg[o] = reqs[o].op->depth - k;
@@ -1136,7 +1233,7 @@ static void apply_t(const ApplyReq* reqs, int nops, bool f64, int normalised, in
     if (overlap) {
         HDM_HIP(hipEventRecord(lane.join, ts));
         HDM_HIP(hipStreamWaitEvent(s, lane.join, 0));
-    } else {
+    } else if (!fuse_up) {
         near_field();
     }
     {
@@ -1264,7 +1361,7 @@ static void build_product_graph(Op& op, bool f64, int normalised, int nrhs, Prod
     const int64_t nitems = static_cast<int64_t>(mma ? op.items_mma.size() : op.items.size());
     bl.pre[1] = nitems;
     std::vector<hipGraphNode_t> comb_deps{
-        kernel(mma ? reinterpret_cast<void*>(&k_l2l_mma) : reinterpret_cast<void*>(&k_l2l<V, TN>),
+        kernel(mma ? reinterpret_cast<void*>(&k_l2l_mma<false>) : reinterpret_cast<void*>(&k_l2l<V, TN, false>),
                dim3(ceil_div(nitems, wpb)), bl, {G.prep}, nullptr)};
     if (op.nskel > 0) {
         // upward pass, leaves first, one node per level, then the far field
