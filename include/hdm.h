@@ -81,8 +81,8 @@ typedef struct {
     int64_t bytes_near, bytes_far, bytes_p, bytes_total;  /* resident operator bytes in HBM */
     int64_t algo_bytes_matvec;   /* bytes one single-vector product must move (tiles once + vectors) */
     int64_t algo_bytes_near;     /* of which the near-field launch: unpadded near tiles, its input and output
-                                    vectors, and, where that launch carries the upward pass (large tile sets
-                                    with a short tree), P once and the skeleton weights twice */
+                                    vectors, and the leaf level of the upward pass it carries (the leaves' P
+                                    once, their skeleton weights written) */
     int64_t flops_matvec;        /* 2 x multiply-adds of one single-vector product */
     double seconds_compress;     /* wall time of hdm_compress */
 } hdm_op_stats_t;

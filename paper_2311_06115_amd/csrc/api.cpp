@@ -320,10 +320,15 @@ hdm_status hdm_op_stats(hdm_op op, hdm_op_stats_t* out) {
         const size_t ev = op->prm.near_prec == HDM_F64 ? 8 : 4;
         st.algo_bytes_matvec = static_cast<int64_t>(near_alg * en + op->far_elems * ef + 2 * op->np * ep +
                                                      2 * op->n * 8 + 4 * op->nskel * ev);
-        // where the near-field launch of a single-vector product also carries
-        // the upward pass: P once, skeleton weights written once and read once
-        st.algo_bytes_near = static_cast<int64_t>(near_alg * en + 2 * op->n * ev);
-        if (op->nskel > 0 && op->up_fused(en)) st.algo_bytes_near += static_cast<int64_t>(op->np * ep + 2 * op->nskel * ev);
+        // the near-field launch of a single-vector product also forms the leaves'
+        // skeleton weights: their P once and the weights written
+        int64_t leaf_p = 0, leaf_sk = 0;
+        if (op->nskel > 0)
+            for (int64_t h = op->L; h < 2 * op->L; ++h) {
+                leaf_p += static_cast<int64_t>(op->rank[h]) * op->ncand[h];
+                leaf_sk += op->rank[h];
+            }
+        st.algo_bytes_near = static_cast<int64_t>(near_alg * en + 2 * op->n * ev + leaf_p * ep + leaf_sk * ev);
         st.flops_matvec = 2 * (near_alg + op->far_elems + 2 * op->np);
         st.seconds_compress = op->seconds_compress;
         *out = st;

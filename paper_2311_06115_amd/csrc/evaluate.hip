@@ -158,60 +158,108 @@ __global__ void k_s2s(Batch b) {
     }
 }
 
-// ---- upward pass carried by the near-field launch ------------------------------
-// One operator, one right-hand side.  The first b.up workgroups of the near-field
-// grid, one per leaf, form the skeleton weights from the leaves up, with the same
-// row dot products as k_n2s; a workgroup that has finished its node counts its
-// arrival at the parent, the second child to arrive goes on with the parent and
-// the first stops.  Nothing waits, so every workgroup ends, and the counter is
-// back at zero for the next launch.  The weights pass between workgroups (which
-// may sit on different XCDs, whose L2 caches are not coherent) through
-// device-scope atomic stores and loads, and a workgroup's stores have completed
-// before its arrival is counted.  The upward pass needs only the staged vector,
-// so it runs beside the tile streaming instead of before it.
-template <typename T>
-__device__ inline void st_agent(T* p, T v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-template <typename T>
-__device__ inline T ld_agent(const T* p) {
-    return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
+// ---- upward pass: leaf level carried by the near-field launch -----------------
+// One operator, one right-hand side: the first b.up workgroups of the near-field
+// grid, one per leaf, form the leaves' skeleton weights w~_h = P_h w_h with the
+// same row dot products as k_n2s.  They need only the staged vector, so they run
+// beside the tile streaming; the levels above follow in their own launch.
 template <typename V>
-__device__ inline void upward_pass(const Batch& b, int64_t leaf) {
+__device__ inline void leaf_n2s(const Batch& b, int64_t leaf) {
     const OpDev& D = *b.op[0];
     const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave, nw = blockDim.x / kWave;
-    const V* P = static_cast<const V*>(D.P);
-    V* skw = static_cast<V*>(D.skw);
-    int64_t h = D.L + leaf;
-    for (int lvl = D.depth; lvl >= 1; --lvl, h >>= 1) {
-        const int rk = D.rank[h], nc = D.ncand[h];
-        const V* Ph = P + D.poff[h];
-        V* out = skw + D.skoff[h];
-        if (lvl == D.depth) {   // leaf: w~_h = P_h w_h
-            const V* in = static_cast<const V*>(D.w) + D.start[h];
-            for (int i = wave; i < rk; i += nw) {
-                const V acc = row_dot<V>(Ph + static_cast<int64_t>(i) * nc, nc, [&](int j) { return in[j]; });
-                if (lane == 0) st_agent(out + i, acc);
-            }
-        } else {                // inner: w~_h = P_h [w~_left; w~_right]
-            const V* in = skw + D.skoff[2 * h];
-            for (int i = wave; i < rk; i += nw) {
-                const V acc =
-                    row_dot<V>(Ph + static_cast<int64_t>(i) * nc, nc, [&](int j) { return ld_agent(in + j); });
-                if (lane == 0) st_agent(out + i, acc);
-            }
-        }
-        if (lvl == 1) break;
-        __builtin_amdgcn_s_waitcnt(0);
-        __syncthreads();
-        int second = 0;
-        if (threadIdx.x == 0)
-            second = __hip_atomic_fetch_add(D.up_count + (h >> 1), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 1u;
-        if (!__syncthreads_or(second)) break;
-        if (threadIdx.x == 0) __hip_atomic_store(D.up_count + (h >> 1), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int64_t h = D.L + leaf;
+    const int rk = D.rank[h], nc = D.ncand[h];
+    const V* Ph = static_cast<const V*>(D.P) + D.poff[h];
+    const V* in = static_cast<const V*>(D.w) + D.start[h];
+    V* out = static_cast<V*>(D.skw) + D.skoff[h];
+    for (int i = wave; i < rk; i += nw) {
+        const V acc = row_dot<V>(Ph + static_cast<int64_t>(i) * nc, nc, [&](int j) { return in[j]; });
+        if (lane == 0) out[i] = acc;
     }
+}
+
+// The leaf skeletons under an inner node h at level lvl are one contiguous run
+// of skeleton slots (leaves take the first slots, in heap order): from the slot
+// of its first leaf, nlk long.
+struct LeafRun {
+    int64_t base;
+    int nlk, nlk_left;
+};
+__device__ inline LeafRun leaf_run(const int64_t* skoff, const int32_t* rank, int depth, int64_t h, int lvl) {
+    const int sh = depth - lvl;
+    const int64_t fl = h << sh, ll = ((h + 1) << sh) - 1, lm = ((2 * h + 1) << (sh - 1)) - 1;
+    LeafRun r;
+    r.base = skoff[fl];
+    r.nlk = static_cast<int>(skoff[ll] + rank[ll] - r.base);
+    r.nlk_left = static_cast<int>(skoff[lm] + rank[lm] - r.base);
+    return r;
+}
+
+// ---- composites of the nested bases (built once per operator) -------------------
+// The skeleton weights of an inner node are a fixed linear map of the leaf
+// skeleton weights under it: w~_h = C_h w~_leaves(h), with
+//   C_h = P_h [C_left 0; 0 C_right]   and a leaf's C the identity,
+// so C_h = P_h one level above the leaves.  One launch per level from the leaves
+// up; a wave per (row of C_h, 64 of its columns) (grid y = column chunk), eight
+// child rows loaded at a time; float64 from P's float64 copy, also stored
+// rounded to float32 for the evaluation-precision products.
+constexpr int kComposeBatch = 8;
+__global__ void k_compose(const double* P64, const int64_t* poff, const int32_t* rank, const int32_t* ncand,
+                          const int64_t* skoff, const int64_t* coff, const RowTask* rows, int64_t row0,
+                          int64_t nrows, int depth, int lvl, double* C64, float* C32) {
+    const int64_t u = blockIdx.x * static_cast<int64_t>(blockDim.x / kWave) + threadIdx.x / kWave;
+    if (u >= nrows) return;
+    const RowTask T = rows[row0 + u];
+    const int64_t h = T.h;
+    const LeafRun lr = leaf_run(skoff, rank, depth, h, lvl);
+    const int c = static_cast<int>(blockIdx.y) * kWave + static_cast<int>(threadIdx.x % kWave);
+    if (c >= lr.nlk) return;
+    const double* Prow = P64 + poff[h] + static_cast<int64_t>(T.i) * ncand[h];
+    double acc = 0.0;
+    if (lvl == depth - 1) {
+        acc = Prow[c];
+    } else {
+        // the child whose leaves hold column c, and c within its run
+        const bool left = c < lr.nlk_left;
+        const int64_t ch = left ? 2 * h : 2 * h + 1;
+        const int rc = rank[ch], nlk_c = left ? lr.nlk_left : lr.nlk - lr.nlk_left;
+        const double* Pc = Prow + (left ? 0 : rank[2 * h]);
+        const double* Cc = C64 + coff[ch] + (left ? c : c - lr.nlk_left);
+        for (int j0 = 0; j0 < rc; j0 += kComposeBatch) {
+            double pv[kComposeBatch], cv[kComposeBatch];
+#pragma unroll
+            for (int t = 0; t < kComposeBatch; ++t) {
+                const int j = min(j0 + t, rc - 1);
+                pv[t] = Pc[j];
+                cv[t] = Cc[static_cast<int64_t>(j) * nlk_c];
+            }
+#pragma unroll
+            for (int t = 0; t < kComposeBatch; ++t)
+                if (j0 + t < rc) acc += pv[t] * cv[t];
+        }
+    }
+    const int64_t o = coff[h] + static_cast<int64_t>(T.i) * lr.nlk + c;
+    C64[o] = acc;
+    C32[o] = static_cast<float>(acc);
+}
+
+// ---- upper levels of the upward pass in one launch, one wave per skeleton row ----
+//   w~_h = C_h w~_leaves(h)  for every inner node below the root
+template <typename V>
+__global__ void k_n2s_up(Batch b) {
+    const int64_t u = blockIdx.x * static_cast<int64_t>(blockDim.x / kWave) + threadIdx.x / kWave;
+    if (u >= b.pre[b.nops]) return;
+    const int o = batch_op(b, u);
+    const OpDev& D = *b.op[o];
+    const RowTask T = D.rows[D.row_count[D.depth] + (u - b.pre[o])];
+    const int64_t h = T.h;
+    const int lvl = 63 - __builtin_clzll(static_cast<unsigned long long>(h));
+    const LeafRun lr = leaf_run(D.skoff, D.rank, D.depth, h, lvl);
+    const V* row = static_cast<const V*>(D.comp) + D.coff[h] + static_cast<int64_t>(T.i) * lr.nlk;
+    V* skw = static_cast<V*>(D.skw);
+    const V* in = skw + lr.base;
+    const V acc = row_dot<V>(row, lr.nlk, [&](int j) { return in[j]; });
+    if (threadIdx.x % kWave == 0) skw[D.skoff[h] + T.i] = acc;
 }
 
 // ---- L2L: stream the near tiles; one wave per work item ---------------------
@@ -222,7 +270,7 @@ template <typename V, typename TN, bool kUp>
 __global__ void __launch_bounds__(kBlock) k_l2l(Batch b) {
     constexpr int RPL = 16 / sizeof(TN);
     if (kUp && static_cast<int>(blockIdx.x) < b.up) {
-        upward_pass<V>(b, blockIdx.x);
+        leaf_n2s<V>(b, blockIdx.x);
         return;
     }
     int64_t u = (blockIdx.x - b.up) * static_cast<int64_t>(blockDim.x / kWave) + threadIdx.x / kWave;
@@ -665,7 +713,7 @@ __global__ void __launch_bounds__(kBlock) k_prep_mma(Batch b) {
 template <bool kUp>
 __global__ void __launch_bounds__(kBlock) k_l2l_mma(Batch b) {
     if (kUp && static_cast<int>(blockIdx.x) < b.up) {
-        upward_pass<float>(b, blockIdx.x);
+        leaf_n2s<float>(b, blockIdx.x);
         return;
     }
     int64_t u = (blockIdx.x - b.up) * static_cast<int64_t>(blockDim.x / kWave) + threadIdx.x / kWave;
@@ -808,7 +856,7 @@ __global__ void k_to_f32(const double* src, float* dst, int64_t n) {
 // ---------------------------------------------------------------------------
 size_t Op::footprint() const {
     return xf.bytes() + xu.bytes() + perm.bytes() + iperm.bytes() + knn_idx.bytes() + knn_d2.bytes() + skel.bytes() +
-           P64.bytes() + P32.bytes() + rows.bytes() + near64.bytes() + nearT.bytes() + near_scale.bytes() +
+           P64.bytes() + P32.bytes() + C64.bytes() + C32.bytes() + rows.bytes() + near64.bytes() + nearT.bytes() + near_scale.bytes() +
            far64.bytes() + farT.bytes() + far_scale.bytes() + far_colmap.bytes() + d_items.bytes() +
            d_leaves.bytes() + q.bytes() + d.bytes() + c.bytes() + w_tree.bytes() + skw.bytes() + sku.bytes() +
            part.bytes() + plan_blob.bytes() + wh.bytes() + wsc.bytes() + d_items_mma.bytes() + d_leaves_mma.bytes();
@@ -912,7 +960,9 @@ static void publish_descriptors(Op& op, hipStream_t s) {
         D.wh = nullptr;
         D.wsc = nullptr;
         D.ldw = 0;
-        D.up_count = op.up_count.get();
+        D.comp = op.ncomp > 0 ? (f64 ? static_cast<const void*>(op.C64.get()) : static_cast<const void*>(op.C32.get()))
+                              : nullptr;
+        D.coff = op.d_coff;
         if (!f64 && op.packed) {   // matrix-core plan of the packed half-precision tiles
             D.items = op.d_items_mma.get();
             D.nitems = static_cast<int64_t>(op.items_mma.size());
@@ -1069,6 +1119,27 @@ void build_eval_plan(Op& op, hipStream_t s) {
         op.row_count[lvl] = static_cast<int64_t>(tasks.size()) - op.row_begin[lvl];
     }
     op.row_total = static_cast<int64_t>(tasks.size());
+    // composites of the nested bases, where they are not much larger than the
+    // inner nodes' P (one launch then forms every level above the leaves)
+    op.coff.assign(static_cast<size_t>(2 * op.L), 0);
+    op.ncomp = 0;
+    {
+        int64_t comp = 0, inner_p = 0;
+        bool nested = true;   // an inner node's candidates are its children's skeletons
+        for (int64_t h = 2; h < op.L; ++h)
+            nested = nested && op.ncand[h] == op.rank[2 * h] + op.rank[2 * h + 1];
+        for (int lvl = op.depth - 1; lvl >= 1; --lvl) {
+            const int sh = op.depth - lvl;
+            for (int64_t h = int64_t(1) << lvl; h < (int64_t(1) << (lvl + 1)); ++h) {
+                const int64_t fl = h << sh, ll = ((h + 1) << sh) - 1;
+                const int64_t nlk = op.skoff[ll] + op.rank[ll] - op.skoff[fl];
+                op.coff[h] = comp;
+                comp += op.rank[h] * nlk;
+                inner_p += static_cast<int64_t>(op.rank[h]) * op.ncand[h];
+            }
+        }
+        if (nested && op.depth >= 2 && comp <= 2 * inner_p + 262144) op.ncomp = comp;
+    }
     // the skeleton-dependent arrays in one allocation and one copy
     std::vector<char> blob;
     auto add = [&](const void* src, size_t bytes) {
@@ -1085,6 +1156,7 @@ void build_eval_plan(Op& op, hipStream_t s) {
     const size_t o_fc = add(op.far_cols.data(), op.far_cols.size() * sizeof(int32_t));
     const size_t o_fcb = add(op.far_colbase.data(), op.far_colbase.size() * sizeof(int64_t));
     const size_t o_tasks = add(tasks.data(), tasks.size() * sizeof(RowTask));
+    const size_t o_coff = add(op.coff.data(), op.coff.size() * sizeof(int64_t));
     blob.resize(blob.size() + 256);   // every piece, empty ones included, points inside the allocation
     op.plan_blob.alloc(blob.size());
     op.plan_blob.upload(blob.data(), blob.size(), s);
@@ -1097,25 +1169,29 @@ void build_eval_plan(Op& op, hipStream_t s) {
     op.d_far_cols = reinterpret_cast<const int32_t*>(base + o_fc);
     op.d_far_colbase = reinterpret_cast<const int64_t*>(base + o_fcb);
     op.d_row_tasks = reinterpret_cast<const RowTask*>(base + o_tasks);
+    op.d_coff = reinterpret_cast<const int64_t*>(base + o_coff);
+    op.C64.release();
+    op.C32.release();
+    if (op.ncomp > 0) {
+        op.C64.alloc(static_cast<size_t>(op.ncomp));
+        op.C32.alloc(static_cast<size_t>(op.ncomp));
+        const int wpb = kBlock / kWave;
+        for (int lvl = op.depth - 1; lvl >= 1; --lvl) {
+            const int64_t nr = op.row_count[lvl];
+            if (nr == 0) continue;
+            const int sh = op.depth - lvl;
+            int64_t maxnlk = 1;
+            for (int64_t h = int64_t(1) << lvl; h < (int64_t(1) << (lvl + 1)); ++h)
+                maxnlk = std::max(maxnlk, op.skoff[((h + 1) << sh) - 1] + op.rank[((h + 1) << sh) - 1] - op.skoff[h << sh]);
+            hipLaunchKernelGGL(k_compose, dim3(ceil_div(nr, wpb), ceil_div(maxnlk, kWave)), dim3(kBlock), 0, s,
+                               op.P64.get(), op.d_poff,
+                               op.d_rank, op.d_ncand, op.d_skoff, op.d_coff, op.d_row_tasks, op.row_begin[lvl], nr,
+                               op.depth, lvl, op.C64.get(), op.C32.get());
+        }
+        check_launch("composites");
+    }
     op.lane.init(op.ctx ? &op.ctx->lanes : nullptr);
     ensure_ws(op, 1);
-    op.up_count.alloc(static_cast<size_t>(std::max(op.L, 1)));
-    HDM_HIP(hipMemsetAsync(op.up_count.get(), 0, op.up_count.bytes(), s));
-    // Expected time of the upward pass climbing as one chain beside the near
-    // field: per level, the widest node's rows pass through a workgroup's four
-    // waves one row dot product (256 columns) at a time, plus the stores and the
-    // arrival; up to 1.6 us per dependent step while the tiles stream (measured
-    // on 65536 x 784 inputs, every rank at 256; 0.8 us at N = 32768 in 3-D).
-    double steps = 0.0;
-    for (int lvl = op.depth; lvl >= 1; --lvl) {
-        int mr = 0, mc = 0;
-        for (int64_t h = int64_t(1) << lvl; h < (int64_t(1) << (lvl + 1)); ++h) {
-            mr = std::max(mr, op.rank[h]);
-            mc = std::max(mc, op.ncand[h]);
-        }
-        steps += static_cast<double>(ceil_div(mr, 4)) * static_cast<double>(ceil_div(std::max(mc, 1), 256)) + 3.0;
-    }
-    op.up_chain_us = 1.6 * steps;
     publish_descriptors(op, s);
 }
 
@@ -1169,12 +1245,11 @@ static void apply_t(const ApplyReq* reqs, int nops, bool f64, int normalised, in
     // every other product starts each pass on the tiles the previous one read
     // last, which are still cached.  Each item writes its own partial sums, so
     // the order does not change the result.
-    // One operator and one right-hand side: the upward pass rides in the near
-    // field's launch (its first workgroups, one per leaf), so that it runs beside
-    // the tile streaming; the far field follows once both are done.
-    // This pays where the tiles take longer to stream than the chain of the
-    // upward pass takes to climb, which the plan estimates per operator.
-    const bool fuse_up = tree && !multi && nops == 1 && reqs[0].op->up_fused(sizeof(TN));
+    // One operator and one right-hand side: the leaf level of the upward pass
+    // rides in the near field's launch (its first workgroups, one per leaf), beside
+    // the tile streaming; the levels above follow in one launch through the
+    // composites (or one launch per level without them), then the far field.
+    const bool fuse_up = tree && !multi && nops == 1;
     b.up = fuse_up ? static_cast<int>(reqs[0].op->L) : 0;
     auto near_field = [&] {
         const int64_t tot = prefix([](const Op& op, int) {
@@ -1202,20 +1277,30 @@ static void apply_t(const ApplyReq* reqs, int nops, bool f64, int normalised, in
         near_field();
     }
     if (tree) {
-        if (!fuse_up) {   // N2S: step k processes level depth - k of every operator
+        {   // N2S: the leaves (unless the near-field launch has formed them), then
+            // every level above them in one launch for operators with composites,
+            // level by level for the others; the same arithmetic whatever the batch
             PhaseScope ph(cx, HDM_PHASE_N2S, ts);
-            for (int k = 0; k < maxdepth; ++k) {
+            auto level_launch = [&](int k, bool with_comp) {
                 for (int o = 0; o < nops; ++o) b.arg[o] = reqs[o].op->depth - k;
                 const int64_t tot = prefix([&](const Op& op, int) {
                     const int lvl = op.depth - k;
-                    return lvl >= 1 ? op.row_count[lvl] : int64_t(0);
+                    return lvl >= 1 && (with_comp || op.ncomp == 0) ? op.row_count[lvl] : int64_t(0);
                 });
-                if (tot == 0) continue;
+                if (tot == 0) return;
                 if (multi)
                     hipLaunchKernelGGL((k_n2s_m<V, TP>), dim3(ceil_div(tot, wpb)), dim3(kBlock), 0, ts, b);
                 else
                     hipLaunchKernelGGL((k_n2s<V, TP>), dim3(ceil_div(tot, wpb)), dim3(kBlock), 0, ts, b);
+            };
+            if (!fuse_up) level_launch(0, true);
+            if (!multi) {
+                const int64_t tot = prefix([](const Op& op, int) {
+                    return op.ncomp > 0 ? op.row_total - op.row_count[op.depth] : int64_t(0);
+                });
+                if (tot > 0) hipLaunchKernelGGL((k_n2s_up<V>), dim3(ceil_div(tot, wpb)), dim3(kBlock), 0, ts, b);
             }
+            for (int k = 1; k < maxdepth; ++k) level_launch(k, multi);
         }
         {
             const int64_t tot = prefix([](const Op& op, int) { return op.row_total; });
@@ -1356,14 +1441,44 @@ static void build_product_graph(Op& op, bool f64, int normalised, int nrhs, Prod
     G.prep = kernel(mma ? reinterpret_cast<void*>(&k_prep_mma) : reinterpret_cast<void*>(&k_prep<V>),
                     mma ? dim3(op.L) : dim3(ceil_div(op.n, kBlock)), bp, {}, &G.prep_p);
     G.prep_b = bp;
-    // near field
+    // near field (one column: with the leaf level of the upward pass, as in the
+    // eager schedule, and the rest of the tree after it)
     Batch bl = base;
     const int64_t nitems = static_cast<int64_t>(mma ? op.items_mma.size() : op.items.size());
     bl.pre[1] = nitems;
-    std::vector<hipGraphNode_t> comb_deps{
-        kernel(mma ? reinterpret_cast<void*>(&k_l2l_mma<false>) : reinterpret_cast<void*>(&k_l2l<V, TN, false>),
-               dim3(ceil_div(nitems, wpb)), bl, {G.prep}, nullptr)};
-    if (op.nskel > 0) {
+    const bool fuse_up = op.nskel > 0 && !multi;
+    bl.up = fuse_up ? op.L : 0;
+    void* l2l_fn = mma ? (fuse_up ? reinterpret_cast<void*>(&k_l2l_mma<true>) : reinterpret_cast<void*>(&k_l2l_mma<false>))
+                       : (fuse_up ? reinterpret_cast<void*>(&k_l2l<V, TN, true>)
+                                  : reinterpret_cast<void*>(&k_l2l<V, TN, false>));
+    const hipGraphNode_t near = kernel(l2l_fn, dim3(ceil_div(nitems, wpb) + bl.up), bl, {G.prep}, nullptr);
+    std::vector<hipGraphNode_t> comb_deps{near};
+    if (fuse_up) {
+        hipGraphNode_t last = near;
+        if (op.ncomp > 0) {
+            Batch bu = base;
+            bu.pre[1] = op.row_total - op.row_count[op.depth];
+            if (bu.pre[1] > 0)
+                last = kernel(reinterpret_cast<void*>(&k_n2s_up<V>), dim3(ceil_div(bu.pre[1], wpb)), bu, {last},
+                              nullptr);
+        } else {
+            for (int lvl = op.depth - 1; lvl >= 1; --lvl) {
+                if (op.row_count[lvl] == 0) continue;
+                Batch bn = base;
+                bn.arg[0] = lvl;
+                bn.pre[1] = op.row_count[lvl];
+                last = kernel(reinterpret_cast<void*>(&k_n2s<V, TP>), dim3(ceil_div(op.row_count[lvl], wpb)), bn,
+                              {last}, nullptr);
+            }
+        }
+        if (op.row_total > 0) {
+            Batch bs = base;
+            bs.pre[1] = op.row_total;
+            last = kernel(reinterpret_cast<void*>(&k_s2s<V, TF>), dim3(ceil_div(op.row_total, wpb)), bs, {last},
+                          nullptr);
+        }
+        comb_deps = {last};
+    } else if (op.nskel > 0) {
         // upward pass, leaves first, one node per level, then the far field
         hipGraphNode_t last = G.prep;
         for (int lvl = op.depth; lvl >= 1; --lvl) {

@@ -151,7 +151,8 @@ struct OpDev {
     void* wh;
     float* wsc;
     int64_t ldw;
-    unsigned* up_count;           // per inner node: children of the upward pass that have arrived
+    const void* comp;             // composites of the nested bases (nullptr: level by level)
+    const int64_t* coff;
 };
 
 // A side stream with its fork/join events: the upward pass and the far field
@@ -267,12 +268,15 @@ struct Op {
     // workspaces of the product
     int ws_nrhs = 0;
     DevBuf<char> w_tree, skw, sku, part;
-    DevBuf<unsigned> up_count;                 // arrival counters of the upward pass (left at zero)
-    double up_chain_us = 0.0;                  // expected time of the upward pass as one chain
-    // whether a single-column product with near tiles of elem bytes carries its
-    // upward pass in the near-field launch: where the tiles (streamed at about
-    // 5 TB/s) take longer than the chain
-    bool up_fused(size_t elem) const { return static_cast<double>(near_elems) * elem / 5.0e6 > up_chain_us; }
+    // composites of the nested bases: per inner node below the root, the
+    // rank x (leaf skeletons under it) map from the leaves' skeleton weights to
+    // its own; none where they would outweigh P (the upper levels then run level
+    // by level)
+    std::vector<int64_t> coff;                 // per heap id
+    int64_t ncomp = 0;
+    DevBuf<double> C64;
+    DevBuf<float> C32;
+    const int64_t* d_coff = nullptr;           // in plan_blob
     double seconds_compress = 0.0;
     size_t footprint() const;
     Op() = default;

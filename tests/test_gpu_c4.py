@@ -59,12 +59,13 @@ def test_block_product_against_dense_rows(c4):
     assert worst <= C4_PRODUCT_BOUND
 
 
-def test_single_column_product_with_upward_pass_in_near_launch(c4):
-    """At this size the near-field launch of a single-column product also climbs
-    the tree (the tiles take longer to stream than the upward pass's chain), with
-    no per-level launches.  Its result must match the same column of a two-column
-    product, whose upward pass runs level by level in other kernels, up to the
-    float32 summation order, and the dense operator on sampled rows."""
+def test_single_column_product_with_composite_upward_pass(c4):
+    """A single-column product forms the leaves' skeleton weights inside the
+    near-field launch and every level above them in one launch through the
+    composites of the nested bases.  Its result must match the same column of a
+    two-column product, whose upward pass runs level by level through P in other
+    kernels, up to the float32 rounding of the two routes, and the dense operator
+    on sampled rows."""
     cfg, X, eps, op = c4
     rng = np.random.default_rng(67)
     W = rng.standard_normal((X.shape[0], 2))
@@ -74,10 +75,10 @@ def test_single_column_product_with_upward_pass_in_near_launch(c4):
     y = op.matvec(torch.from_numpy(np.ascontiguousarray(W[:, 0])).cuda()).cpu().numpy()
     ph = ctx.phase_times()
     ctx.profile(False)
-    assert ph["l2l"][0] == 1 and ph["n2s"][0] == 0, ph
+    assert ph["l2l"][0] == 1 and ph["n2s"][0] == 1, ph
     Y2 = op.matvec(torch.from_numpy(W).cuda()).cpu().numpy()
     rel = np.linalg.norm(y - Y2[:, 0]) / np.linalg.norm(Y2[:, 0])
-    print(f"[gpu] scurve-100k single column (upward pass in the near launch) vs 2-column product: {rel:.2e}")
+    print(f"[gpu] scurve-100k single column (composite upward pass) vs 2-column product: {rel:.2e}")
     assert rel <= 1e-5
     rows = np.sort(rng.choice(X.shape[0], 32, replace=False))
     dense = np.array([HM.dense_kmatvec(X, eps, W[:, 0], (int(i), int(i) + 1))[0] for i in rows])
