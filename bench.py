@@ -242,7 +242,7 @@ def main():
         "phase_ms_per_step": {k: v[1] for k, v in breakdown.items()},   # one extra step, every phase timed
         "phase_launches_per_step": {k: v[0] for k, v in breakdown.items()},
         "eigenvalue_accuracy": ev_acc,
-        "roofline": {"kernel": "k_l2l (near field)", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+        "roofline": {"kernel": "k_l2l (near field, with the leaf level of the upward pass)", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "avg_launch_us": l2l_avg_s * 1e6, "launches": int(l2l_n),
                      "algo_bytes_per_launch": st_op.algo_bytes_near},
