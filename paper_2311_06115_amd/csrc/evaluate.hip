@@ -576,10 +576,25 @@ __global__ void k_s2s_m(Batch b) {
 }
 
 // combine for several right-hand sides: the ancestor potentials of all columns
-// sit side by side in shared memory, so each P element is read once
+// sit side by side in shared memory, so each P element is read once.  One
+// workgroup of kCombBlock threads per leaf, in the phases of k_combine: the
+// ranks and offsets along the path, the path's P slices staged in shared memory
+// in one batch (where they fit), the chain walk from there; then per row the
+// near partial sums (float32: two halves of the workgroup over half of the items
+// each, added in a fixed order, two items of every column in flight) and
+// P_leaf^T u~ with eight of its entries in flight.
+template <typename V> constexpr int kStageM = sizeof(V) == 4 ? kMaxRhs * (kCombBlock / 2) : 1024;
+template <typename V> constexpr bool kSplitM = sizeof(V) == 4;
+template <typename V> constexpr int kItemBatchM = sizeof(V) == 4 ? 2 : 1;
+
 template <typename V, typename TP>
-__global__ void __launch_bounds__(kBlock) k_combine_m(Batch b) {
+__global__ void __launch_bounds__(kCombBlock) k_combine_m(Batch b) {
+    constexpr int kHalf = kCombBlock / 2;
+    constexpr int IB = kItemBatchM<V>;
     __shared__ V tot[2][kMaxRhs * kMaxRank];
+    __shared__ V stage[kStageM<V>];   // the chain's P slices, then the second half's near sums
+    __shared__ int m_rn[kMaxLevels + 1], m_rp[kMaxLevels + 1], m_ncp[kMaxLevels + 1];
+    __shared__ int64_t m_pb[kMaxLevels + 1], m_sk[kMaxLevels + 1], m_pleaf;
     const int64_t u = blockIdx.x;
     const int o = batch_op(b, u);
     const OpDev& D = *b.op[o];
@@ -589,65 +604,157 @@ __global__ void __launch_bounds__(kBlock) k_combine_m(Batch b) {
     const int depth = D.row_total > 0 ? D.depth : 0;
     const int nr = b.nrhs, last = nr - 1;   // loads past nrhs repeat the last column (unguarded, batched)
     const int64_t ldp = D.ldp, ldsk = D.ldsk;
-    int cur = 0;
-    int rleaf = 0;
+    const int tid = threadIdx.x;
+    if (tid >= 1 && tid <= depth) {
+        const int64_t node = static_cast<int64_t>(lp.heap) >> (depth - tid);
+        m_rn[tid] = D.rank[node];
+        m_sk[tid] = D.skoff[node];
+        if (tid >= 2) {
+            const int64_t par = node >> 1;
+            m_rp[tid] = D.rank[par];
+            m_ncp[tid] = D.ncand[par];
+            m_pb[tid] = D.poff[par] + ((node & 1) ? D.rank[2 * par] : 0);
+        }
+    }
+    if (tid == 0 && depth >= 1) m_pleaf = D.poff[lp.heap];
+    __syncthreads();
     if (depth >= 1) {
-        const int64_t a1 = lp.heap >> (depth - 1);
-        const int r1 = D.rank[a1];
-        for (int e = threadIdx.x; e < nr * r1; e += blockDim.x) {
+        const int r1 = m_rn[1];
+        for (int e = tid; e < nr * r1; e += kCombBlock) {
             const int c = e / r1, i = e % r1;
-            tot[0][c * kMaxRank + i] = sku[c * ldsk + D.skoff[a1] + i];
+            tot[0][c * kMaxRank + i] = sku[c * ldsk + m_sk[1] + i];
+        }
+    }
+    // the chain walk; as many consecutive levels' P slices as fit are staged in
+    // shared memory at a time (one batch of loads), a level too large for it
+    // reads P from global memory
+    int cur = 0;
+    for (int l0 = 2; l0 <= depth;) {
+        int l1 = l0, nd = 0;
+        while (l1 <= depth && nd + m_rp[l1] * m_rn[l1] <= kStageM<V>) {
+            nd += m_rp[l1] * m_rn[l1];
+            ++l1;
+        }
+        const bool staged = l1 > l0;
+        if (!staged) l1 = l0 + 1;
+        if (staged && nd > 0) {
+            // each thread's elements come in increasing order, so its level only advances
+            int lvl = l0, lo = 0, sz = m_rp[l0] * m_rn[l0];
+            for (int g0 = tid; g0 < nd; g0 += 8 * kCombBlock) {
+                V x[8];
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    const int g = min(g0 + t * kCombBlock, nd - 1);
+                    while (g >= lo + sz) {
+                        lo += sz;
+                        ++lvl;
+                        sz = m_rp[lvl] * m_rn[lvl];
+                    }
+                    const int rn = m_rn[lvl], e = g - lo;
+                    x[t] = static_cast<V>(P[m_pb[lvl] + static_cast<int64_t>(e / rn) * m_ncp[lvl] + e % rn]);
+                }
+#pragma unroll
+                for (int t = 0; t < 8; ++t)
+                    if (g0 + t * kCombBlock < nd) stage[g0 + t * kCombBlock] = x[t];
+            }
         }
         __syncthreads();
-        for (int lvl = 2; lvl <= depth; ++lvl) {
-            const int64_t node = lp.heap >> (depth - lvl), par = node >> 1;
-            const int rp = D.rank[par], ncp = D.ncand[par], rn = D.rank[node];
-            const int off = (node & 1) ? D.rank[2 * par] : 0;
-            const TP* Pm = P + D.poff[par] + off;
-            for (int j = threadIdx.x; j < rn; j += blockDim.x) {
+        int off = 0;
+        for (int lvl = l0; lvl < l1; ++lvl) {
+            const int rp = m_rp[lvl], rn = m_rn[lvl], ncp = m_ncp[lvl];
+            const TP* Pm = P + m_pb[lvl];
+            for (int j = tid; j < rn; j += kCombBlock) {
+                V sv[kMaxRhs];
+#pragma unroll
+                for (int c = 0; c < kMaxRhs; ++c) sv[c] = sku[min(c, last) * ldsk + m_sk[lvl] + j];
                 V acc[kMaxRhs];
 #pragma unroll
                 for (int c = 0; c < kMaxRhs; ++c) acc[c] = 0;
-                for (int i = 0; i < rp; ++i) {
-                    const V p = static_cast<V>(Pm[static_cast<int64_t>(i) * ncp + j]);
+                if (staged) {
+                    const V* Ps = stage + off;
+                    for (int i = 0; i < rp; ++i) {
+                        const V p = Ps[i * rn + j];
 #pragma unroll
-                    for (int c = 0; c < kMaxRhs; ++c) acc[c] += p * tot[cur][min(c, last) * kMaxRank + i];
+                        for (int c = 0; c < kMaxRhs; ++c) acc[c] += p * tot[cur][min(c, last) * kMaxRank + i];
+                    }
+                } else {
+                    for (int i = 0; i < rp; ++i) {
+                        const V p = static_cast<V>(Pm[static_cast<int64_t>(i) * ncp + j]);
+#pragma unroll
+                        for (int c = 0; c < kMaxRhs; ++c) acc[c] += p * tot[cur][min(c, last) * kMaxRank + i];
+                    }
                 }
-                const int64_t so = D.skoff[node] + j;
-                V sv[kMaxRhs];
-#pragma unroll
-                for (int c = 0; c < kMaxRhs; ++c) sv[c] = sku[min(c, last) * D.ldsk + so];
 #pragma unroll
                 for (int c = 0; c < kMaxRhs; ++c)
                     if (c < nr) tot[cur ^ 1][c * kMaxRank + j] = sv[c] + acc[c];
             }
+            off += rp * rn;
             __syncthreads();
             cur ^= 1;
         }
-        rleaf = D.rank[lp.heap];
+        l0 = l1;
     }
-    const TP* Pl = P + D.poff[lp.heap];
+    __syncthreads();
+    const int rleaf = depth >= 1 ? m_rn[depth] : 0;
+    const TP* Pl = P + (depth >= 1 ? m_pleaf : 0);
     const V* pc = static_cast<const V*>(D.part) + lp.part_off;
-    for (int j = threadIdx.x; j < lp.rows; j += blockDim.x) {
+    const int half = kSplitM<V> ? tid / kHalf : 0;
+    const int jt = kSplitM<V> ? tid % kHalf : tid;
+    constexpr int rstep = kSplitM<V> ? kHalf : kCombBlock;
+    const int ih = kSplitM<V> ? (lp.nitems + 1) / 2 : lp.nitems;
+    const int i0 = min(lp.nitems, half * ih), i1 = min(lp.nitems, i0 + ih);
+    for (int j0 = 0; j0 < lp.rows; j0 += rstep) {
+        const int j = j0 + jt;
+        const bool live = j < lp.rows;
         V f[kMaxRhs];
 #pragma unroll
         for (int c = 0; c < kMaxRhs; ++c) f[c] = 0;
-        for (int q = 0; q < lp.nitems; ++q) {
-            const V* pq = pc + static_cast<int64_t>(q) * lp.ld + j;
+        if (live) {
+            // IB items in flight; the last batch clamps and adds only the items in range
+            for (int q = i0; q < i1; q += IB) {
+                V x[IB][kMaxRhs];
 #pragma unroll
-            for (int c = 0; c < kMaxRhs; ++c) f[c] += pq[min(c, last) * ldp];
+                for (int t = 0; t < IB; ++t) {
+                    const V* pq = pc + static_cast<int64_t>(min(q + t, i1 - 1)) * lp.ld + j;
+#pragma unroll
+                    for (int c = 0; c < kMaxRhs; ++c) x[t][c] = pq[min(c, last) * ldp];
+                }
+#pragma unroll
+                for (int t = 0; t < IB; ++t)
+                    if (q + t < i1) {
+#pragma unroll
+                        for (int c = 0; c < kMaxRhs; ++c) f[c] += x[t][c];
+                    }
+            }
         }
-        for (int i = 0; i < rleaf; ++i) {
-            const V p = static_cast<V>(Pl[static_cast<int64_t>(i) * lp.rows + j]);
-#pragma unroll
-            for (int c = 0; c < kMaxRhs; ++c) f[c] += p * tot[cur][min(c, last) * kMaxRank + i];
+        if (kSplitM<V>) {
+            if (half == 1 && live)
+                for (int c = 0; c < nr; ++c) stage[c * kHalf + jt] = f[c];
+            __syncthreads();
         }
-        const int64_t pos = lp.start + j;
-        const double sc = b.arg[o] ? D.c[pos] : 1.0;
-        const int32_t dst = D.perm[pos];
+        if (half == 0 && live) {
+            if (kSplitM<V>)
+                for (int c = 0; c < nr; ++c) f[c] += stage[c * kHalf + jt];
+            for (int i = 0; i < rleaf; i += 8) {
+                TP pv[8];
 #pragma unroll
-        for (int c = 0; c < kMaxRhs; ++c)
-            if (c < nr) b.y[o][c * D.n + dst] = sc * static_cast<double>(f[c]);
+                for (int t = 0; t < 8; ++t) pv[t] = Pl[static_cast<int64_t>(min(i + t, rleaf - 1)) * lp.rows + j];
+#pragma unroll
+                for (int t = 0; t < 8; ++t)
+                    if (i + t < rleaf) {
+                        const V p = static_cast<V>(pv[t]);
+#pragma unroll
+                        for (int c = 0; c < kMaxRhs; ++c) f[c] += p * tot[cur][min(c, last) * kMaxRank + i + t];
+                    }
+            }
+            const int64_t pos = lp.start + j;
+            const double sc = b.arg[o] ? D.c[pos] : 1.0;
+            const int32_t dst = D.perm[pos];
+#pragma unroll
+            for (int c = 0; c < kMaxRhs; ++c)
+                if (c < nr) b.y[o][c * D.n + dst] = sc * static_cast<double>(f[c]);
+        }
+        if (kSplitM<V>) __syncthreads();   // stage is rewritten by the next rows
     }
 }
 
@@ -1326,7 +1433,7 @@ static void apply_t(const ApplyReq* reqs, int nops, bool f64, int normalised, in
         const int64_t tot = prefix([](const Op& op, int) { return static_cast<int64_t>(op.L); });
         KernelEvents ev(cx, HDM_PHASE_COMBINE);
         if (multi)
-            hipExtLaunchKernelGGL((k_combine_m<V, TP>), dim3(tot), dim3(kBlock), 0, s, ev.start, ev.stop, 0, b);
+            hipExtLaunchKernelGGL((k_combine_m<V, TP>), dim3(tot), dim3(kCombBlock), 0, s, ev.start, ev.stop, 0, b);
         else
             hipExtLaunchKernelGGL((k_combine<V, TP>), dim3(tot), dim3(kCombBlock), 0, s, ev.start, ev.stop, 0, b);
     }
@@ -1501,7 +1608,7 @@ static void build_product_graph(Op& op, bool f64, int normalised, int nrhs, Prod
     bc.arg[0] = normalised;
     bc.pre[1] = op.L;
     G.combine = kernel(multi ? reinterpret_cast<void*>(&k_combine_m<V, TP>) : reinterpret_cast<void*>(&k_combine<V, TP>),
-                       dim3(op.L), bc, comb_deps, &G.comb_p, multi ? kBlock : kCombBlock);
+                       dim3(op.L), bc, comb_deps, &G.comb_p, kCombBlock);
     G.comb_b = bc;
     HDM_HIP(hipGraphInstantiate(&G.exec, G.g, nullptr, nullptr, 0));
 }
