@@ -575,6 +575,35 @@ __global__ void k_s2s_m(Batch b) {
     }
 }
 
+// ---- several right-hand sides: partial sums of busy leaves pre-added ------------
+// A leaf near many others has many near-field items, each with its own partial
+// sums; the one workgroup that combines the leaf would add them all.  Here the
+// items of such a leaf are added in groups of gstep, in item order, into the
+// group's first item (grid: leaf x group x column), so that its combine reads
+// one partial per group.
+template <typename V>
+__global__ void __launch_bounds__(kBlock) k_part_reduce(Batch b) {
+    const int64_t u = blockIdx.x;
+    const int o = batch_op(b, u);
+    const OpDev& D = *b.op[o];
+    const LeafPlan lp = D.leaves[u - b.pre[o]];
+    const int k = static_cast<int>(blockIdx.y), c = static_cast<int>(blockIdx.z);
+    const int q0 = k * lp.gstep;
+    if (lp.gstep <= 1 || q0 >= lp.nitems) return;
+    const int cnt = min(lp.gstep, lp.nitems - q0);
+    V* pc = static_cast<V*>(D.part) + c * D.ldp + lp.part_off + static_cast<int64_t>(q0) * lp.ld;
+    for (int j = threadIdx.x; j < lp.rows; j += blockDim.x) {
+        V x[kReduceGroup];
+#pragma unroll
+        for (int t = 0; t < kReduceGroup; ++t) x[t] = pc[static_cast<int64_t>(min(t, cnt - 1)) * lp.ld + j];
+        V acc = x[0];
+#pragma unroll
+        for (int t = 1; t < kReduceGroup; ++t)
+            if (t < cnt) acc += x[t];
+        pc[j] = acc;
+    }
+}
+
 // combine for several right-hand sides: the ancestor potentials of all columns
 // sit side by side in shared memory, so each P element is read once.  One
 // workgroup of kCombBlock threads per leaf, in the phases of k_combine: the
@@ -701,8 +730,12 @@ __global__ void __launch_bounds__(kCombBlock) k_combine_m(Batch b) {
     const int half = kSplitM<V> ? tid / kHalf : 0;
     const int jt = kSplitM<V> ? tid % kHalf : tid;
     constexpr int rstep = kSplitM<V> ? kHalf : kCombBlock;
-    const int ih = kSplitM<V> ? (lp.nitems + 1) / 2 : lp.nitems;
-    const int i0 = min(lp.nitems, half * ih), i1 = min(lp.nitems, i0 + ih);
+    // a busy leaf's partial sums were pre-added in groups: one per group
+    const int gs = max(lp.gstep, 1);
+    const int ng = (lp.nitems + gs - 1) / gs;
+    const int64_t qld = static_cast<int64_t>(gs) * lp.ld;
+    const int ih = kSplitM<V> ? (ng + 1) / 2 : ng;
+    const int i0 = min(ng, half * ih), i1 = min(ng, i0 + ih);
     for (int j0 = 0; j0 < lp.rows; j0 += rstep) {
         const int j = j0 + jt;
         const bool live = j < lp.rows;
@@ -715,7 +748,7 @@ __global__ void __launch_bounds__(kCombBlock) k_combine_m(Batch b) {
                 V x[IB][kMaxRhs];
 #pragma unroll
                 for (int t = 0; t < IB; ++t) {
-                    const V* pq = pc + static_cast<int64_t>(min(q + t, i1 - 1)) * lp.ld + j;
+                    const V* pq = pc + static_cast<int64_t>(min(q + t, i1 - 1)) * qld + j;
 #pragma unroll
                     for (int c = 0; c < kMaxRhs; ++c) x[t][c] = pq[min(c, last) * ldp];
                 }
@@ -1108,6 +1141,7 @@ static void build_mma_plan(Op& op, hipStream_t s) {
     packed_near_offsets(op);
     op.items_mma.clear();
     op.leaves_mma.clear();
+    op.red_groups_mma = 0;
     int64_t off = 0, part = 0;
     for (int64_t a = 0; a < L; ++a) {
         const int64_t ha = L + a;
@@ -1124,6 +1158,8 @@ static void build_mma_plan(Op& op, hipStream_t s) {
         const int groups = (rt + kMmaRowTiles - 1) / kMmaRowTiles;
         lp.ngroups = groups;
         lp.wpad = wpad[a];
+        lp.gstep = ntiles > kReduceAbove ? kReduceGroup : 1;
+        if (lp.gstep > 1) op.red_groups_mma = std::max(op.red_groups_mma, ceil_div(ntiles, kReduceGroup));
         for (int32_t t = op.near_off[a]; t < op.near_off[a + 1]; ++t) {
             const int32_t b = op.near_idx[t];
             const int64_t nb = op.size[L + b];
@@ -1168,6 +1204,7 @@ void build_near_plan(Op& op, hipStream_t s) {
     op.items.clear();
     op.leaves.clear();
     int64_t part = 0;
+    op.red_groups = 0;
     for (int64_t a = 0; a < L; ++a) {
         const int64_t ha = L + a;
         const int32_t ld = op.near_ld[a];
@@ -1184,6 +1221,8 @@ void build_near_plan(Op& op, hipStream_t s) {
             per_group += static_cast<int>((nb + kChunk - 1) / kChunk);
         }
         lp.nitems = per_group;
+        lp.gstep = per_group > kReduceAbove ? kReduceGroup : 1;
+        if (lp.gstep > 1) op.red_groups = std::max(op.red_groups, ceil_div(per_group, kReduceGroup));
         for (int g = 0; g < lp.ngroups; ++g) {
             int q = 0;
             for (int32_t t = op.near_off[a]; t < op.near_off[a + 1]; ++t) {
@@ -1374,11 +1413,21 @@ static void apply_t(const ApplyReq* reqs, int nops, bool f64, int normalised, in
         else
             hipExtLaunchKernelGGL((k_l2l<V, TN, false>), dim3(grid), dim3(kBlock), 0, s, ev.start, ev.stop, 0, b);
     };
+    // several columns: busy leaves' partial sums pre-added in groups, after the near field
+    auto part_reduce = [&] {
+        int maxg = 0;
+        for (int o = 0; o < nops; ++o)
+            maxg = std::max(maxg, mma ? reqs[o].op->red_groups_mma : reqs[o].op->red_groups);
+        if (!multi || maxg == 0) return;
+        const int64_t tot = prefix([](const Op& op, int) { return static_cast<int64_t>(op.L); });
+        hipLaunchKernelGGL((k_part_reduce<V>), dim3(tot, maxg, nrhs), dim3(kBlock), 0, s, b);
+    };
     if (overlap) {
         // fork after the staging; the near field goes first on s (it only needs the
         // staged vectors), so it starts while the host still issues the upward pass
         HDM_HIP(hipEventRecord(lane.fork, s));
         near_field();
+        part_reduce();
         HDM_HIP(hipStreamWaitEvent(ts, lane.fork, 0));
     } else if (fuse_up) {
         near_field();
@@ -1427,6 +1476,7 @@ static void apply_t(const ApplyReq* reqs, int nops, bool f64, int normalised, in
         HDM_HIP(hipStreamWaitEvent(s, lane.join, 0));
     } else if (!fuse_up) {
         near_field();
+        part_reduce();
     }
     {
         for (int o = 0; o < nops; ++o) b.arg[o] = normalised;
@@ -1558,7 +1608,13 @@ static void build_product_graph(Op& op, bool f64, int normalised, int nrhs, Prod
     void* l2l_fn = mma ? (fuse_up ? reinterpret_cast<void*>(&k_l2l_mma<true>) : reinterpret_cast<void*>(&k_l2l_mma<false>))
                        : (fuse_up ? reinterpret_cast<void*>(&k_l2l<V, TN, true>)
                                   : reinterpret_cast<void*>(&k_l2l<V, TN, false>));
-    const hipGraphNode_t near = kernel(l2l_fn, dim3(ceil_div(nitems, wpb) + bl.up), bl, {G.prep}, nullptr);
+    hipGraphNode_t near = kernel(l2l_fn, dim3(ceil_div(nitems, wpb) + bl.up), bl, {G.prep}, nullptr);
+    const int maxg = mma ? op.red_groups_mma : op.red_groups;
+    if (multi && maxg > 0) {
+        Batch br = base;
+        br.pre[1] = op.L;
+        near = kernel(reinterpret_cast<void*>(&k_part_reduce<V>), dim3(op.L, maxg, nrhs), br, {near}, nullptr);
+    }
     std::vector<hipGraphNode_t> comb_deps{near};
     if (fuse_up) {
         hipGraphNode_t last = near;

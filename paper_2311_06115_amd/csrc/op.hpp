@@ -101,7 +101,13 @@ struct LeafPlan {
     int32_t heap;       // heap id
     int32_t ngroups;    // row groups
     int64_t wpad;       // matrix-core plans: offset of the leaf in the padded half-precision vectors
+    int32_t gstep;      // products of several columns: its partial sums pre-added in groups of gstep items
 };
+
+// partial sums of a leaf with more than kReduceAbove near-field items are
+// pre-added in groups of kReduceGroup (products of several columns)
+constexpr int kReduceAbove = 16;
+constexpr int kReduceGroup = 8;
 
 // one skeleton row: heap id and row index
 struct RowTask {
@@ -228,6 +234,7 @@ struct Op {
     bool packed = false;
     std::vector<int64_t> near_tile_off_mma;
     int64_t near_elems_mma = 0, part_elems_mma = 0;
+    int red_groups = 0, red_groups_mma = 0;   // most pre-added groups of one leaf (plain, packed plans)
     std::vector<NearItem> items_mma;
     DevBuf<NearItem> d_items_mma;
     std::vector<LeafPlan> leaves_mma;
