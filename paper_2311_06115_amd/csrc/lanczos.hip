@@ -899,7 +899,9 @@ bool LanczosRun::after_product(hipStream_t s) {
     check_launch("lanczos step");
     m = j + 1;
     const bool last = (j == max_basis - 1);
-    if (m >= r && ((m % check_every) == 0 || last)) {
+    // Each check costs a tridiagonal eigensolve and a host synchronisation; r
+    // pairs rarely meet the tolerance before 2r steps, so checking starts there.
+    if ((m >= 2 * r && (m % check_every) == 0) || (last && m >= r)) {
         {
             KernelEvents ev(op->ctx, HDM_PHASE_TRIDIAG);
             launch_tridiag(alpha.get(), beta.get(), m, r, theta.get(), Y.get(), bound.get(), s, ev.start, ev.stop);
