@@ -321,6 +321,8 @@ typedef struct {
     double **pmat;           /* per heap id: rank x ncand row-major */
     int32_t *nrows;          /* per heap id: sampled rows */
     int32_t **rows;          /* per heap id: original indices of the sampled rows */
+    int32_t *nsteps;         /* per heap id: pivot steps the ID examined */
+    double **trace;          /* per heap id: 2 x nsteps (largest, second largest remaining norm) */
 } orc_h;
 
 static int leaf_of_pos(const orc_h *H, int64_t pos) {
@@ -510,40 +512,38 @@ static int sample_rows(orc_h *H, int64_t h, const int32_t *cand, int32_t nc, int
     return nr;
 }
 
-/* sum over i in [i0, i1) of a[i sa] * b[i sb], in a fixed order: eight partial
- * sums, the term of row i going to partial (i - i0) mod 8 in increasing i, then
- * ((p0 + p1) + (p2 + p3)) + ((p4 + p5) + (p6 + p7)).  The paper leaves the
- * order of these sums open; this one is the ID's reading for every column norm,
- * reflector norm and reflector-column inner product below. */
-static double sum8(const double *a, int64_t sa, const double *b, int64_t sb, int32_t i0, int32_t i1) {
-    double p[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int32_t i = i0; i < i1; ++i) {
-        const int u = (i - i0) & 7;
-        p[u] = p[u] + a[(int64_t)i * sa] * b[(int64_t)i * sb];
-    }
-    return ((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7]));
-}
-
 /* Interpolative decomposition of B (nr x nc, row-major, overwritten) by
  * Householder QR with column pivoting: the pivot is the column of largest
  * remaining 2-norm (ties: lowest current column); the rank is the number of
  * pivots whose norm exceeds tau times the first, at most s.  Returns the rank;
  * cp[0..nc) receives the column order; P (rank x nc) satisfies
- * B[:, cp[j]] = I for j < rank and B ~ B[:, skel] P. */
+ * B[:, cp[j]] = I for j < rank and B ~ B[:, skel] P.  Every norm and inner
+ * product is a plain sequential sum over increasing row index.
+ *
+ * trace (2 (kmax + 1) doubles, or NULL) records, for every pivot step j that
+ * was examined, the largest remaining column norm (|R_jj|) and the second
+ * largest (-1 when only one column remains); *nsteps receives the number of
+ * examined steps.  Another implementation that sums in another order may pick
+ * another pivot only where these two are within its rounding error. */
 static int32_t pivoted_id(double *B, int32_t nr, int32_t nc, int32_t s, double tau, int32_t *cp, double *P,
-                          double *v) {
+                          double *v, double *trace, int32_t *nsteps) {
     for (int32_t c = 0; c < nc; ++c) cp[c] = c;
     int32_t kmax = nr < nc ? nr : nc;
     if (kmax > s) kmax = s;
     double r11 = 0.0;
-    int32_t rank = 0;
+    int32_t rank = 0, steps = 0;
     for (int32_t j = 0; j < kmax; ++j) {
         int32_t best = j;
-        double bestv = -1.0;
+        double bestv = -1.0, second = -1.0;
         for (int32_t c = j; c < nc; ++c) {
-            const double nrm = sqrt(sum8(B + c, nc, B + c, nc, j, nr));
-            if (nrm > bestv) { bestv = nrm; best = c; }
+            double acc = 0.0;
+            for (int32_t i = j; i < nr; ++i) acc = acc + B[(int64_t)i * nc + c] * B[(int64_t)i * nc + c];
+            const double nrm = sqrt(acc);
+            if (nrm > bestv) { second = bestv; bestv = nrm; best = c; }
+            else if (nrm > second) second = nrm;
         }
+        if (trace) { trace[2 * j] = bestv; trace[2 * j + 1] = second; }
+        steps = j + 1;
         if (best != j) {
             for (int32_t i = 0; i < nr; ++i) {
                 const double t = B[(int64_t)i * nc + j];
@@ -558,9 +558,11 @@ static int32_t pivoted_id(double *B, int32_t nr, int32_t nc, int32_t s, double t
         const double alpha = x0 >= 0.0 ? -bestv : bestv;
         v[j] = x0 - alpha;
         for (int32_t i = j + 1; i < nr; ++i) v[i] = B[(int64_t)i * nc + j];
-        const double vtv = sum8(v, 1, v, 1, j, nr);
+        double vtv = 0.0;
+        for (int32_t i = j; i < nr; ++i) vtv = vtv + v[i] * v[i];
         for (int32_t c = j + 1; c < nc; ++c) {
-            const double dot = sum8(v, 1, B + c, nc, j, nr);
+            double dot = 0.0;
+            for (int32_t i = j; i < nr; ++i) dot = dot + v[i] * B[(int64_t)i * nc + c];
             const double f = (2.0 * dot) / vtv;
             for (int32_t i = j; i < nr; ++i) B[(int64_t)i * nc + c] = B[(int64_t)i * nc + c] - f * v[i];
         }
@@ -568,6 +570,7 @@ static int32_t pivoted_id(double *B, int32_t nr, int32_t nc, int32_t s, double t
         for (int32_t i = j + 1; i < nr; ++i) B[(int64_t)i * nc + j] = 0.0;
         rank = j + 1;
     }
+    if (nsteps) *nsteps = steps;
     /* P[:, cp[j]] = e_j (j < rank); P[:, cp[rank + c]] = R11^{-1} R12[:, c] */
     for (int64_t t = 0; t < (int64_t)rank * nc; ++t) P[t] = 0.0;
     for (int32_t j = 0; j < rank; ++j) P[(int64_t)j * nc + cp[j]] = 1.0;
@@ -614,7 +617,8 @@ static int skeletonize(orc_h *H) {
             for (int32_t r = 0; r < nr; ++r)
                 for (int32_t c = 0; c < nc; ++c) B[(int64_t)r * nc + c] = kval(&H->P, H->rows[h][r], cand[c]);
             double *Pm = malloc(sizeof(double) * (size_t)(H->s) * (size_t)(nc > 0 ? nc : 1));
-            const int32_t rk = pivoted_id(B, nr, nc, H->s, H->tau, cp, Pm, v);
+            H->trace[h] = malloc(sizeof(double) * 2 * ((size_t)H->s + 1));
+            const int32_t rk = pivoted_id(B, nr, nc, H->s, H->tau, cp, Pm, v, H->trace[h], &H->nsteps[h]);
             H->rank[h] = rk;
             H->pmat[h] = Pm;
             H->skel[h] = malloc(sizeof(int32_t) * (rk > 0 ? rk : 1));
@@ -631,8 +635,9 @@ void orc_free(orc_h *H) {
         if (H->skel) free(H->skel[h]);
         if (H->pmat) free(H->pmat[h]);
         if (H->rows) free(H->rows[h]);
+        if (H->trace) free(H->trace[h]);
     }
-    free(H->skel); free(H->pmat); free(H->rows); free(H->nrows); free(H->ncand); free(H->rank);
+    free(H->skel); free(H->pmat); free(H->rows); free(H->trace); free(H->nsteps); free(H->nrows); free(H->ncand); free(H->rank);
     free(H->start); free(H->size); free(H->perm); free(H->iperm); free(H->knn_idx); free(H->knn_d2);
     free(H->near_off); free(H->near_idx); free(H->far_off); free(H->far_idx);
     free(H);
@@ -669,6 +674,9 @@ orc_h *orc_compress(const void *x, int64_t n, int dim, int is_u8, double eps, in
     H->skel = calloc((size_t)H->nnodes, sizeof(int32_t *));
     H->pmat = calloc((size_t)H->nnodes, sizeof(double *));
     H->rows = calloc((size_t)H->nnodes, sizeof(int32_t *));
+    H->trace = calloc((size_t)H->nnodes, sizeof(double *));
+    H->nsteps = calloc((size_t)H->nnodes, sizeof(int32_t));
+    if (!H->trace || !H->nsteps) { orc_free(H); return NULL; }
     if (!H->start || !H->size || !H->perm || !H->iperm || !H->knn_idx || !H->knn_d2 || !H->rank || !H->ncand ||
         !H->nrows || !H->skel || !H->pmat || !H->rows) { orc_free(H); return NULL; }
     tree_ranges(n, depth, H->start, H->size);
@@ -712,12 +720,40 @@ void orc_get_node(const orc_h *H, int64_t h, int32_t *skel, int32_t *rows, doubl
     if (H->nrows[h] > 0) memcpy(rows, H->rows[h], sizeof(int32_t) * H->nrows[h]);
 }
 
+/* pivot trace of the ID of heap node h: returns the number of examined steps;
+ * trace receives 2 per step (largest, second largest remaining column norm) */
+int32_t orc_get_trace(const orc_h *H, int64_t h, double *trace) {
+    const int32_t ns = H->nsteps[h];
+    if (trace && ns > 0 && H->trace[h]) memcpy(trace, H->trace[h], sizeof(double) * 2 * (size_t)ns);
+    return ns;
+}
+
+/* Floyd's sample of ns distinct positions of [0, n) for tree node `node`,
+ * ascending (the ball tree's centroid sample; exported for its pin) */
+int orc_sample_positions(uint64_t seed, uint32_t node, int64_t n, int ns, int64_t *out) {
+    return sample_positions(seed, node, n, ns, out);
+}
+
+/* ID of one block (tests): B nr x nc row-major (overwritten), P rank x nc,
+ * cp nc entries, trace 2 (min(nr, nc, s) + 1) doubles; returns the rank */
+int32_t orc_pivoted_id(double *B, int32_t nr, int32_t nc, int32_t s, double tau, int32_t *cp, double *P,
+                       double *trace, int32_t *nsteps) {
+    double *v = malloc(sizeof(double) * (size_t)(nr > 0 ? nr : 1));
+    if (!v) return -1;
+    const int32_t rk = pivoted_id(B, nr, nc, s, tau, cp, P, v, trace, nsteps);
+    free(v);
+    return rk;
+}
+
 /* ------------------------------------------------------------------------- */
 /* u = K~ w (float64), w and u n x nrhs column-major in original point order.  */
 /* Upward pass (skeleton weights), far products between skeletons, downward     */
 /* pass (skeleton potentials back to points) and the exact near blocks.         */
 /* ------------------------------------------------------------------------- */
-int orc_hmatvec(const orc_h *H, const double *w, double *u, int nrhs) {
+/* The same loops with every factor replaced by its magnitude (abs_mode = 1):
+ * u = |K~| |w|, the row-wise scale that bounds the rounding error of any
+ * evaluation of K~ w (each term of (K~ w)_i enters with its magnitude). */
+static int hmatvec_impl(const orc_h *H, const double *w, double *u, int nrhs, int abs_mode) {
     const int64_t n = H->P.n, L = (int64_t)1 << H->depth;
     double **wt = calloc((size_t)H->nnodes, sizeof(double *));
     double **ut = calloc((size_t)H->nnodes, sizeof(double *));
@@ -739,12 +775,13 @@ int orc_hmatvec(const orc_h *H, const double *w, double *u, int nrhs) {
                         double xj;
                         if (lvl == H->depth) {
                             xj = w[(int64_t)c * n + H->perm[H->start[h] + j]];
+                            if (abs_mode) xj = fabs(xj);
                         } else {
                             const int32_t rl = H->rank[2 * h];
                             xj = j < rl ? wt[2 * h][(int64_t)c * rl + j]
                                         : wt[2 * h + 1][(int64_t)c * H->rank[2 * h + 1] + (j - rl)];
                         }
-                        acc = acc + Pm[(int64_t)i * nc + j] * xj;
+                        acc = acc + (abs_mode ? fabs(Pm[(int64_t)i * nc + j]) : Pm[(int64_t)i * nc + j]) * xj;
                     }
                     wt[h][(int64_t)c * rk + i] = acc;
                 }
@@ -771,7 +808,8 @@ int orc_hmatvec(const orc_h *H, const double *w, double *u, int nrhs) {
             for (int c = 0; c < nrhs; ++c) {
                 for (int32_t j = 0; j < nc; ++j) {
                     double acc = 0.0;
-                    for (int32_t i = 0; i < rk; ++i) acc = acc + Pm[(int64_t)i * nc + j] * ut[h][(int64_t)c * rk + i];
+                    for (int32_t i = 0; i < rk; ++i)
+                        acc = acc + (abs_mode ? fabs(Pm[(int64_t)i * nc + j]) : Pm[(int64_t)i * nc + j]) * ut[h][(int64_t)c * rk + i];
                     if (lvl == H->depth) {
                         u[(int64_t)c * n + H->perm[H->start[h] + j]] += acc;
                     } else {
@@ -794,7 +832,8 @@ int orc_hmatvec(const orc_h *H, const double *w, double *u, int nrhs) {
                     double acc = 0.0;
                     for (int64_t j = 0; j < H->size[hb]; ++j) {
                         const int32_t pj = H->perm[H->start[hb] + j];
-                        acc = acc + kval(&H->P, pi, pj) * w[(int64_t)c * n + pj];
+                        const double wj = w[(int64_t)c * n + pj];
+                        acc = acc + kval(&H->P, pi, pj) * (abs_mode ? fabs(wj) : wj);
                     }
                     u[(int64_t)c * n + pi] += acc;
                 }
@@ -805,6 +844,11 @@ int orc_hmatvec(const orc_h *H, const double *w, double *u, int nrhs) {
     free(wt); free(ut);
     return 0;
 }
+
+int orc_hmatvec(const orc_h *H, const double *w, double *u, int nrhs) { return hmatvec_impl(H, w, u, nrhs, 0); }
+
+/* u = |K~| |w| (see hmatvec_impl) */
+int orc_hmatvec_abs(const orc_h *H, const double *w, double *u, int nrhs) { return hmatvec_impl(H, w, u, nrhs, 1); }
 
 /* ------------------------------------------------------------------------- */
 /* Dense definitions (Eq. (2)): rows [r0, r1) of u = K w, K evaluated on the  */

@@ -36,6 +36,8 @@ def lib():
         L.orc_get_node.argtypes = [vp, i64, vp, vp, vp]
         L.orc_hmatvec.restype = i32
         L.orc_hmatvec.argtypes = [vp, vp, vp, i32]
+        L.orc_hmatvec_abs.restype = i32
+        L.orc_hmatvec_abs.argtypes = [vp, vp, vp, i32]
         L.orc_dense_kmatvec.argtypes = [vp, i64, i32, i32, f64, vp, i32, vp, i64, i64]
         L.orc_dense_sqdist.argtypes = [vp, i64, i32, i32, i64, i64, vp]
         L.orc_kernel.restype = f64
@@ -44,6 +46,12 @@ def lib():
         L.orc_rand_u32.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32]
         L.orc_philox4x32_10.argtypes = [vp, vp, vp]
         L.orc_build_tree.restype = i32
+        L.orc_get_trace.restype = i32
+        L.orc_get_trace.argtypes = [vp, i64, vp]
+        L.orc_sample_positions.restype = i32
+        L.orc_sample_positions.argtypes = [C.c_uint64, C.c_uint32, i64, i32, vp]
+        L.orc_pivoted_id.restype = i32
+        L.orc_pivoted_id.argtypes = [vp, i32, i32, i32, f64, vp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -68,6 +76,26 @@ def philox4x32_10(ctr, key):
 
 def rand_u32(seed, purpose, a, b, i):
     return int(lib().orc_rand_u32(seed, purpose, a, b, i))
+
+
+def sample_positions(seed, node, n, ns):
+    """Floyd's sample of ns distinct positions of [0, n) for tree node ``node`` (ascending)."""
+    out = np.zeros(max(ns, 1), np.int64)
+    cnt = lib().orc_sample_positions(seed, node, n, ns, _ptr(out))
+    return out[:cnt]
+
+
+def pivoted_id(B, s, tau):
+    """Oracle ID of one block: (rank, column order cp, P [rank x nc], trace [steps x 2])."""
+    B = np.array(B, dtype=np.float64, order="C", copy=True)
+    nr, nc = B.shape
+    cp = np.zeros(max(nc, 1), np.int32)
+    P = np.zeros(max(s * nc, 1), np.float64)
+    kmax = min(nr, nc, s)
+    trace = np.zeros(2 * (kmax + 1), np.float64)
+    steps = C.c_int32(0)
+    rk = lib().orc_pivoted_id(_ptr(B), nr, nc, s, float(tau), _ptr(cp), _ptr(P), _ptr(trace), C.byref(steps))
+    return rk, cp[:nc], P[:rk * nc].reshape(rk, nc), trace[:2 * steps.value].reshape(-1, 2)
 
 
 def tree_depth(n: int, m: int) -> int:
@@ -156,6 +184,13 @@ class HMatrix:
         lib().orc_get_node(self.h, h, _ptr(skel), _ptr(rows), _ptr(P))
         return skel[:r[h]], rows[:nr[h]], P[:r[h] * c[h]].reshape(r[h], c[h])
 
+    def trace(self, h):
+        """Pivot trace of heap node h's ID: per examined step the largest and the
+        second largest remaining column norm (-1: no second column)."""
+        tr = np.zeros(2 * (self.s + 1), np.float64)
+        ns = lib().orc_get_trace(self.h, h, _ptr(tr))
+        return tr[:2 * ns].reshape(-1, 2)
+
     def candidates(self, h):
         """Candidate columns of heap node h (points of a leaf, children's skeletons otherwise)."""
         if h >= self.L:
@@ -171,6 +206,16 @@ class HMatrix:
         W = np.asfortranarray(w.reshape(self.n, -1))
         U = np.zeros_like(W, order="F")
         if lib().orc_hmatvec(self.h, _ptr(W), _ptr(U), W.shape[1]):
+            raise RuntimeError("oracle hmatvec failed")
+        return U[:, 0] if vec else U
+
+    def matvec_abs(self, w):
+        """|K~| |w| in float64 (every factor of the product by its magnitude)."""
+        w = np.asarray(w, dtype=np.float64)
+        vec = w.ndim == 1
+        W = np.asfortranarray(w.reshape(self.n, -1))
+        U = np.zeros_like(W, order="F")
+        if lib().orc_hmatvec_abs(self.h, _ptr(W), _ptr(U), W.shape[1]):
             raise RuntimeError("oracle hmatvec failed")
         return U[:, 0] if vec else U
 

@@ -228,3 +228,163 @@ def test_dense_rows_match_numpy(orc, c1):
     u = W @ w
     np.testing.assert_allclose(orc.dense_kmatvec(X, eps, w, (100, 300)), u[100:300], rtol=0,
                                atol=1e-13 * np.abs(u).max())
+
+
+# ---------------------------------------------------------------- |K~| |w|
+def test_abs_product_without_compression_is_kernel_times_abs(orc):
+    # tau = 0, s = n/2: every P is a column selection (entries 0 and 1), so the
+    # magnitude product through the tree is K |w|.
+    X, _ = synth.s_curve(512, 4)
+    eps = synth.median_sq_dist_eps(X, 4)
+    H = orc.HMatrix(X, eps, 64, 256, 0.0, 16, 4)
+    W = D.kernel_matrix(X, eps)
+    w = np.random.default_rng(5).standard_normal(H.n)
+    np.testing.assert_allclose(H.matvec_abs(w), W @ np.abs(w), rtol=1e-12)
+
+
+def test_abs_product_bounds_every_row(orc, c1):
+    # |(K~ w)_i| <= (|K~| |w|)_i for every w (triangle inequality), with equality
+    # when w >= 0 and no P entry is negative on the row's paths; and |K~||w| >= K~|w|.
+    X, eps, cfg, H = c1
+    rng = np.random.default_rng(6)
+    w = rng.standard_normal((H.n, 2))
+    u, a = H.matvec(w), H.matvec_abs(w)
+    assert np.all(np.abs(u) <= a * (1 + 1e-12))
+    assert np.all(H.matvec(np.abs(w)) <= a * (1 + 1e-12))
+    # the near blocks alone (budget 1) have no P: |K~||w| = K |w|
+    Hn = orc.HMatrix(X, eps, cfg["m"], cfg["s"], cfg["tau"], cfg["k"], cfg["seed"], budget=1.0)
+    Wk = D.kernel_matrix(X, eps)
+    np.testing.assert_allclose(Hn.matvec_abs(w[:, 0]), Wk @ np.abs(w[:, 0]), rtol=1e-12)
+
+
+# ---------------------------------------------------------------- sampling steps
+def _floyd(orc, seed, node, n, ns):
+    """Floyd's algorithm written out: for j = n - ns .. n - 1 draw t uniform in
+    [0, j]; take t unless already taken, else j.  One Philox draw (purpose 1,
+    counter (j, node, 0)) per step, mapped to [0, j] by multiply-shift."""
+    chosen = []
+    for j in range(n - ns, n):
+        t = (orc.rand_u32(seed, 1, node, 0, j) * (j + 1)) >> 32
+        chosen.append(j if t in chosen else t)
+    return sorted(chosen)
+
+
+@pytest.mark.parametrize("seed,node,n", [(0, 1, 2048), (3, 17, 65), (9, 5, 1000), (1, 2, 64)])
+def test_sample_positions_is_floyd(orc, seed, node, n):
+    ns = min(n, 64)
+    got = orc.sample_positions(seed, node, n, ns)
+    assert got.size == ns
+    assert np.all((got >= 0) & (got < n)) and np.all(np.diff(got) > 0)
+    assert list(got) == _floyd(orc, seed, node, n, ns)
+
+
+def _near_brute(H):
+    """Votes of leaf a for leaf b: neighbours of a's points that sit in b.  Each
+    leaf keeps itself and the ceil(budget L) others with most votes (ties: lower
+    leaf id); the relation is then made symmetric."""
+    L = H.L
+    perm = H.perm()
+    iperm = np.empty_like(perm)
+    iperm[perm] = np.arange(H.n)
+    leaf_of_pos = np.searchsorted(H.start[L:2 * L], np.arange(H.n), side="right") - 1
+    idx, _ = H.knn()
+    votes = np.zeros((L, L), np.int64)
+    for pos in range(H.n):
+        for j in idx[perm[pos]]:
+            if j >= 0:
+                votes[leaf_of_pos[pos], leaf_of_pos[iperm[j]]] += 1
+    extra = int(np.ceil(H.budget * L))
+    rel = np.eye(L, dtype=bool)
+    for a in range(L):
+        others = [b for b in range(L) if b != a]
+        others.sort(key=lambda b: (-votes[a, b], b))
+        rel[a, others[:extra]] = True
+    rel = rel | rel.T
+    off = np.concatenate([[0], np.cumsum(rel.sum(axis=1))]).astype(np.int32)
+    return off, np.nonzero(rel)[1].astype(np.int32)
+
+
+@pytest.mark.parametrize("budget", [0.05, 0.2])
+def test_near_lists_from_vote_matrix(orc, budget):
+    X, _ = synth.s_curve(2048, 0)
+    eps = synth.median_sq_dist_eps(X, 0)
+    H = orc.HMatrix(X, eps, 64, 16, 1e-5, 16, 0, budget=budget)
+    off, idx = H.near()
+    boff, bidx = _near_brute(H)
+    assert np.array_equal(off, boff)
+    assert np.array_equal(idx, bidx)
+
+
+def _rows_brute(orc, H, h):
+    """Sampled rows of node h, written out: the candidates' neighbours outside h
+    ranked by (votes desc, index asc), the first min(count, want // 2) kept, where
+    want = min(n - |h|, 2 s); then every outside point in index order when
+    want = n - |h|, else uniform Philox draws (purpose 3, counter (t, h, 0)) from
+    outside h, skipping repeats, until want rows are taken."""
+    perm = H.perm()
+    iperm = np.empty_like(perm)
+    iperm[perm] = np.arange(H.n)
+    lo, hi = H.start[h], H.start[h] + H.size[h]
+    inside = lambda i: lo <= iperm[i] < hi  # noqa: E731
+    want = min(H.n - H.size[h], 2 * H.s)
+    idx, _ = H.knn()
+    votes = {}
+    for c in H.candidates(h):
+        for i in idx[c]:
+            if i >= 0 and not inside(i):
+                votes[i] = votes.get(i, 0) + 1
+    ranked = sorted(votes, key=lambda i: (-votes[i], i))
+    rows = ranked[:want // 2]
+    taken = set(rows)
+    if len(rows) < want:
+        if want == H.n - H.size[h]:
+            rows += [i for i in range(H.n) if not inside(i) and i not in taken][:want - len(rows)]
+        else:
+            t = 0
+            while len(rows) < want:
+                i = (orc.rand_u32(H.seed, 3, h, 0, t) * H.n) >> 32
+                t += 1
+                if inside(i) or i in taken:
+                    continue
+                rows.append(i)
+                taken.add(i)
+    return np.array(rows, np.int32)
+
+
+@pytest.mark.parametrize("n,m,s", [(2048, 128, 64), (300, 64, 128)])
+def test_sampled_rows_brute_force(orc, n, m, s):
+    # (300, 64, 128): 2 s exceeds the points outside the upper nodes, so they take every outside point
+    X, _ = synth.s_curve(n, 8)
+    eps = synth.median_sq_dist_eps(X, 8)
+    H = orc.HMatrix(X, eps, m, s, 1e-5, 16, 8)
+    perm = H.perm()
+    iperm = np.empty_like(perm)
+    iperm[perm] = np.arange(H.n)
+    for h in range(2, H.nnodes):
+        rows = H.node(h)[1]
+        assert rows.size == min(H.n - H.size[h], 2 * s)
+        assert np.unique(rows).size == rows.size
+        pos = iperm[rows]
+        assert np.all((pos < H.start[h]) | (pos >= H.start[h] + H.size[h]))
+        assert np.array_equal(rows, _rows_brute(orc, H, h)), h
+
+
+def test_pivot_trace_matches_column_norms(orc, c1):
+    # The first recorded pair is the largest and second largest column norm of B;
+    # each recorded largest is |R_jj| of LAPACK's pivoted QR.
+    X, eps, cfg, H = c1
+    W = D.kernel_matrix(X, eps)
+    for h in [3, H.L + 2]:
+        skel, rows, P = H.node(h)
+        B = W[np.ix_(rows, H.candidates(h))]
+        tr = H.trace(h)
+        cn = np.sort(np.linalg.norm(B, axis=0))[::-1]
+        np.testing.assert_allclose(tr[0], cn[:2], rtol=1e-13)
+        _, R, _ = sl.qr(B, mode="economic", pivoting=True)
+        k = tr.shape[0]
+        np.testing.assert_allclose(tr[:, 0], np.abs(np.diag(R))[:k], rtol=1e-9)
+        # the block routine on the same B (numpy's exp may differ from the C
+        # library's in the last bit, so the traces agree to rounding)
+        rk, cp, P1, tr1 = orc.pivoted_id(B, cfg["s"], cfg["tau"])
+        assert rk == P.shape[0]
+        np.testing.assert_allclose(tr1, tr, rtol=1e-12, atol=1e-14 * tr[0, 0])
