@@ -13,6 +13,7 @@ import pytest
 
 import synth
 from oracle import hmatrix as HM
+from structure_check import check_product, check_skeletons, product_bound
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -42,11 +43,8 @@ def test_structure_bit_exact(c2):
         assert np.array_equal(a, b)
     for a, b in zip(op.far(), H.far()):
         assert np.array_equal(a, b)
-    gr, orr = op.ranks(), H.ranks()
-    for a, b in zip(gr, orr):
-        assert np.array_equal(a[2:], b[2:])
-    mism = [h for h in range(2, H.nnodes) if not np.array_equal(op.node(h)[0], H.node(h)[0])]
-    assert mism == []
+    compared, ties, pmax = check_skeletons(op, H, cfg["s"], cfg["tau"])
+    print(f"[gpu] scurve-32k: {compared} nodes compared, {ties} near-tie pivots, max P deviation {pmax:.2e}")
 
 
 def test_product_against_oracle_and_dense_rows(c2):
@@ -58,6 +56,8 @@ def test_product_against_oracle_and_dense_rows(c2):
     rel = np.linalg.norm(u - ref) / np.linalg.norm(ref)
     print(f"[gpu] f32 product vs oracle K~: {rel:.2e}")
     assert rel <= 2e-6
+    worst = check_product(u, ref, product_bound(H, w, "f32"), "scurve-32k f32")
+    print(f"[gpu] f32 product at full size: worst entry at {worst:.2e} of its bound")
     rows = np.sort(rng.choice(X.shape[0], 256, replace=False))
     dense = np.array([HM.dense_kmatvec(X, eps, w, (int(i), int(i) + 1))[0] for i in rows])
     rel_d = np.linalg.norm(u[rows] - dense) / np.linalg.norm(dense)
