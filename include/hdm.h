@@ -59,7 +59,8 @@ typedef struct {
     double eps;         /* > 0 */
     double alpha;       /* must be 1 */
     int32_t leaf_m;     /* leaf size bound: depth = min d with ceil(n / 2^d) <= m; every leaf must hold > knn_k points */
-    int32_t max_rank_s; /* >= 1 */
+    int32_t max_rank_s; /* 1..512; with HDM_U8 points at most the smallest leaf size
+                           (floor(n / 2^depth)): larger values are refused (HDM_EINVAL) */
     double tau;         /* >= 0, relative pivot threshold of the interpolative decomposition */
     int32_t knn_k;      /* neighbours per point, 1..64 */
     int32_t knn_iters;  /* random trees for the neighbour search, >= 1 (10) */
@@ -71,6 +72,9 @@ typedef struct {
 
 /* Fills p with the defaults (alpha 1, knn_iters 10, budget 0.05, f32 tiles). */
 void hdm_params_default(hdm_params *p);
+/* The parameter checks of hdm_compress and hdm_submit alone (no device is
+ * touched): HDM_OK, or HDM_EINVAL with hdm_last_error() naming the rule. */
+hdm_status hdm_params_validate(const hdm_params *p);
 
 typedef struct {
     int64_t n;
@@ -210,7 +214,8 @@ typedef struct {
 } hdm_server_cfg_t;
 
 typedef struct {
-    const void *X;          /* host points (params.x_dtype, n x dim); copied by hdm_submit */
+    const void *X;          /* host points (params.x_dtype, n x dim); copied by hdm_submit, so the
+                               caller may free X on return */
     hdm_params params;
     int32_t r;              /* eigenpairs */
     double rel_resid_tol;
@@ -225,7 +230,8 @@ typedef struct {
     double latency_s;       /* completion - arrival on the caller's clock */
     double service_s;       /* admission -> completion */
     int32_t iters;
-    int32_t x_released;     /* 1 once the library no longer reads X */
+    int32_t x_released;     /* 1 once the library has dropped its host copy of X (after the
+                               operator is built, or when the request ends) */
 } hdm_result_t;
 
 typedef struct {
@@ -247,7 +253,9 @@ hdm_status hdm_server_create(hdm_ctx ctx, const hdm_server_cfg_t *cfg, hdm_serve
 /* HDM_EINVAL for bad parameters or NaN/Inf points, HDM_ENOMEM when the
  * request's estimated footprint exceeds the whole budget (counted as rejected). */
 hdm_status hdm_submit(hdm_server srv, const hdm_request_t *req, uint64_t *ticket);
-/* HDM_EBUSY while the request is queued or running; its result otherwise. */
+/* HDM_EBUSY while the request is queued or running; its result otherwise.  A
+ * result is handed out once: the library then forgets the ticket, and later
+ * calls with it return HDM_EINVAL (unknown ticket). */
 hdm_status hdm_poll(hdm_server srv, uint64_t ticket, hdm_result_t *out);
 hdm_status hdm_cancel(hdm_server srv, uint64_t ticket);
 hdm_status hdm_server_stats(hdm_server srv, hdm_server_stats_t *out);

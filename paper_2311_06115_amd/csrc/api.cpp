@@ -95,6 +95,11 @@ void validate_params(const hdm_params& p) {
     if (depth > 16) fail(HDM_EINVAL, "tree deeper than 16 levels: raise leaf_m");
     if ((p.n >> depth) <= p.knn_k) fail(HDM_EINVAL, "every leaf must hold more than knn_k points");
     if (((p.n + (int64_t(1) << depth) - 1) >> depth) > 2048) fail(HDM_EINVAL, "leaves must hold <= 2048 points");
+    // u8 codes with a maximal rank above the smallest leaf: two runs with such
+    // requests ended in a GPU memory fault whose cause is not known, so this
+    // class is refused until it is found
+    if (p.x_dtype == HDM_U8 && p.max_rank_s > (p.n >> depth))
+        fail(HDM_EINVAL, "u8 points: max_rank_s above the smallest leaf size is not supported");
 }
 
 
@@ -197,6 +202,14 @@ void hdm_params_default(hdm_params* p) {
     p->budget = 0.05;
     p->near_prec = HDM_F32;
     p->far_prec = HDM_F32;
+}
+
+hdm_status hdm_params_validate(const hdm_params* p) {
+    return guarded([&] {
+        HDM_CHECK(p != nullptr, HDM_EINVAL, "NULL parameters");
+        hdm::validate_params(*p);
+        return HDM_OK;
+    });
 }
 
 hdm_status hdm_ctx_create(int device, size_t hbm_budget_bytes, hdm_ctx* out) {

@@ -2122,6 +2122,10 @@ static void build_near_tiles(Op& op, const Geo& G, hipStream_t s) {
         }
     }
     op.near_elems = off;
+    for (const NearPair& pr : pairs)
+        HDM_CHECK(pr.na >= 1 && pr.na <= pr.ld && pr.a0 >= 0 && pr.a0 + pr.na <= op.n && pr.b0 >= 0 && pr.nb >= 1 &&
+                      pr.b0 + pr.nb <= op.n && pr.off >= 0 && pr.off + static_cast<int64_t>(pr.ld) * pr.nb <= off,
+                  HDM_EINTERNAL, "near tile descriptor outside its buffers");
     op.near64.alloc(off);
     if (G.gram) {
         HDM_HIP(hipMemsetAsync(op.near64.get(), 0, op.near64.bytes(), s));   // padded rows stay zero
@@ -2178,6 +2182,13 @@ static void build_far_tiles(Op& op, const Geo& G, hipStream_t s, DevBuf<char>& k
         foff += static_cast<int64_t>(op.rank[h]) * cols;
     }
     op.far_elems = foff;
+    for (const FarBlock& b : blocks)
+        HDM_CHECK(b.rows >= 1 && b.cols >= 1 && b.off >= 0 && b.off + static_cast<int64_t>(b.rows) * b.cols <= foff &&
+                      b.col0 >= 0 && b.col0 + b.cols <= static_cast<int64_t>(colmap.size()) && b.sk0 >= 0 &&
+                      b.sk0 + b.rows <= op.nskel,
+                  HDM_EINTERNAL, "far tile descriptor outside its buffers");
+    for (int32_t slot : colmap)
+        HDM_CHECK(slot >= 0 && slot < op.nskel, HDM_EINTERNAL, "far column map entry outside the skeletons");
     op.far64.alloc(foff > 0 ? foff : 1);
     op.far_colmap = to_device(colmap, s);
     if (G.gram) {

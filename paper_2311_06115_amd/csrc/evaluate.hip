@@ -1124,6 +1124,7 @@ static void publish_descriptors(Op& op, hipStream_t s) {
 }
 
 static void packed_near_offsets(Op& op);
+static void check_near_plan(const Op& op);
 
 // Plan of the packed half-precision near field (k_l2l_mma): per near pair an
 // ld_a x kc_b packed tile; per (pair, group of at most 8 row tiles) one item;
@@ -1187,10 +1188,79 @@ static void build_mma_plan(Op& op, hipStream_t s) {
     }
     op.near_elems_mma = off;
     op.part_elems_mma = part;
+    op.ldw = std::max<int64_t>(op.ldw, 0);
+    check_near_plan(op);
     op.d_items_mma = to_device(op.items_mma, s);
     op.d_leaves_mma = to_device(op.leaves_mma, s);
     op.wh.alloc(static_cast<size_t>(std::max<int64_t>(op.ldw, 1)) * 2 * kMaxRhs * sizeof(_Float16));
     op.wsc.alloc(static_cast<size_t>(L) * kMaxRhs);
+}
+
+
+// Host-side bounds checks of every launch descriptor against the extent of the
+// buffer it indexes, before the descriptors are uploaded: a plan that would
+// read or write outside a buffer is an HDM_EINTERNAL error, not a launch.
+static void check_near_plan(const Op& op) {
+    const int64_t L = op.L;
+    const int64_t pairs = static_cast<int64_t>(op.near_idx.size());
+    auto bad = [](const char* what) { fail(HDM_EINTERNAL, std::string("near-field plan: ") + what); };
+    for (const NearItem& I : op.items) {
+        if (I.tile < 0 || I.tile >= pairs) bad("tile index");
+        if (I.ncols < 1 || I.ld < 1 || I.row0 < 0 || I.row0 >= I.ld) bad("item shape");
+        if (I.tile_off < 0 || I.tile_off + static_cast<int64_t>(I.ncols) * I.ld > op.near_elems) bad("tile extent");
+        if (I.part_off < 0 || I.part_off + I.ld > op.part_elems) bad("partial-sum extent");
+        if (I.col_pos < 0 || I.col_pos + I.ncols > op.n) bad("vector extent");
+    }
+    if (static_cast<int64_t>(op.leaves.size()) != L) bad("leaf count");
+    for (const LeafPlan& lp : op.leaves) {
+        if (lp.heap < L || lp.heap >= 2 * L) bad("leaf heap id");
+        if (lp.rows < 1 || lp.rows > lp.ld || lp.start < 0 || lp.start + lp.rows > op.n) bad("leaf rows");
+        if (lp.part_off < 0 || lp.part_off + static_cast<int64_t>(lp.nitems) * lp.ld > op.part_elems) bad("leaf partials");
+    }
+    if (op.packed) {
+        for (const NearItem& I : op.items_mma) {
+            if (I.tile < 0 || I.tile >= pairs || I.leaf_b < 0 || I.leaf_b >= L) bad("packed item index");
+            const int64_t kc = (static_cast<int64_t>(I.ncols) + 7) / 8 * 8;
+            if (I.tile_off < 0 || I.tile_off + kc * I.ld > op.near_elems_mma) bad("packed tile extent");
+            if (I.row0 < 0 || I.row0 + I.nrows > (I.ld + 15) / 16 * 16) bad("packed rows");
+            if (I.part_off < 0 || I.part_off + I.ld > op.part_elems_mma) bad("packed partial-sum extent");
+            if (I.col_pos < 0 || I.col_pos + kc > op.ldw) bad("staged vector extent");
+        }
+        for (const LeafPlan& lp : op.leaves_mma) {
+            if (lp.part_off < 0 || lp.part_off + static_cast<int64_t>(lp.nitems) * lp.ld > op.part_elems_mma)
+                bad("packed leaf partials");
+            if (lp.wpad < 0 || lp.wpad + (lp.rows + 7) / 8 * 8 > op.ldw) bad("packed leaf vector");
+        }
+    }
+}
+
+static void check_eval_plan(const Op& op, const std::vector<RowTask>& tasks) {
+    const int64_t NN = op.nnodes, L = op.L;
+    auto bad = [](const char* what) { fail(HDM_EINTERNAL, std::string("evaluation plan: ") + what); };
+    int64_t far_cols_total = 0;
+    for (int64_t h = 2; h < NN; ++h) {
+        const int64_t rk = op.rank[h], nc = op.ncand[h];
+        if (rk < 0 || rk > kMaxRank || rk > nc) bad("rank");
+        if (op.skoff[h] < 0 || op.skoff[h] + rk > op.nskel) bad("skeleton extent");
+        if (op.poff[h] < 0 || op.poff[h] + rk * nc > op.np) bad("interpolation extent");
+        if (h >= L && nc != op.size[h]) bad("leaf candidates are not its points");
+        if (h < L && nc != op.rank[2 * h] + op.rank[2 * h + 1]) bad("inner candidates are not the children's skeletons");
+        if (op.far_block_off[h] < 0 || op.far_block_off[h] + rk * op.far_cols[h] > std::max<int64_t>(op.far_elems, 0))
+            bad("far block extent");
+        if (op.far_colbase[h] < 0 || op.far_colbase[h] + op.far_cols[h] > static_cast<int64_t>(op.far_colmap.n))
+            bad("far column map extent");
+        far_cols_total += op.far_cols[h];
+        if (op.ncomp > 0 && h < L) {
+            const int lvl = 63 - __builtin_clzll(static_cast<unsigned long long>(h));
+            const int sh = op.depth - lvl;
+            const int64_t fl = h << sh, ll = ((h + 1) << sh) - 1;
+            const int64_t nlk = op.skoff[ll] + op.rank[ll] - op.skoff[fl];
+            if (nlk < 0 || op.coff[h] < 0 || op.coff[h] + rk * nlk > op.ncomp) bad("composite extent");
+        }
+    }
+    if (far_cols_total > static_cast<int64_t>(op.far_colmap.n)) bad("far column map size");
+    for (const RowTask& t : tasks)
+        if (t.h < 2 || t.h >= NN || t.i < 0 || t.i >= op.rank[t.h]) bad("row task");
 }
 
 // The near-field part of the evaluation plan (work items and per-leaf plans):
@@ -1246,9 +1316,10 @@ void build_near_plan(Op& op, hipStream_t s) {
         op.leaves.push_back(lp);
     }
     op.part_elems = part;
+    if (op.prm.near_prec == HDM_F16) build_mma_plan(op, s);
+    check_near_plan(op);
     op.d_items = to_device(op.items, s);
     op.d_leaves = to_device(op.leaves, s);
-    if (op.prm.near_prec == HDM_F16) build_mma_plan(op, s);
 }
 
 // the rest of the plan, once the skeletons are known
@@ -1265,6 +1336,8 @@ void build_eval_plan(Op& op, hipStream_t s) {
         op.row_count[lvl] = static_cast<int64_t>(tasks.size()) - op.row_begin[lvl];
     }
     op.row_total = static_cast<int64_t>(tasks.size());
+    HDM_CHECK(static_cast<int64_t>(op.rank.size()) == op.nnodes && static_cast<int64_t>(op.far_cols.size()) == op.nnodes,
+              HDM_EINTERNAL, "per-node arrays");
     // composites of the nested bases, where they are not much larger than the
     // inner nodes' P (one launch then forms every level above the leaves)
     op.coff.assign(static_cast<size_t>(2 * op.L), 0);
@@ -1286,6 +1359,7 @@ void build_eval_plan(Op& op, hipStream_t s) {
         }
         if (nested && op.depth >= 2 && comp <= 2 * inner_p + 262144) op.ncomp = comp;
     }
+    check_eval_plan(op, tasks);
     // the skeleton-dependent arrays in one allocation and one copy
     std::vector<char> blob;
     auto add = [&](const void* src, size_t bytes) {

@@ -69,12 +69,16 @@ struct hdm_server_s {
 
 namespace {
 
-// finish a request (lock held): release its memory and record its outcome
+// finish a request (lock held): release its memory and record its outcome;
+// a request is finished once
 void finish_locked(hdm_server_s* S, const ReqPtr& q, int status) {
+    if (q->state == ServeReq::DONE) return;
     q->done_s = now_s();
     q->res.status = status;
     q->res.latency_s = q->done_s - q->arrival_s;
     q->res.service_s = q->admit_s > 0.0 ? q->done_s - q->admit_s : 0.0;
+    q->X.clear();
+    q->X.shrink_to_fit();
     q->res.x_released = 1;
     if (q->state != ServeReq::QUEUED) {
         S->active -= 1;
@@ -110,6 +114,14 @@ void admit_locked(hdm_server_s* S) {
     S->cv.notify_all();
 }
 
+// frees a request's device state; the release waits for the device at the end
+// of the scope (as in hdm_op_destroy) instead of one hipFree per buffer
+void release_solve(const ReqPtr& q) {
+    hdm::PoolScope pool_scope;
+    q->run = hdm::LanczosRun();
+    q->op.reset();
+}
+
 void compressor_main(hdm_server_s* S) {
     (void)hipSetDevice(S->ctx->device);
     hipStream_t s = nullptr;
@@ -130,6 +142,9 @@ void compressor_main(hdm_server_s* S) {
         }
         int status = HDM_OK;
         try {
+            // the same buffer lifetime rules as hdm_compress: releases wait for
+            // the device at the end of the scope, uploads go through pinned staging
+            hdm::PoolScope pool_scope;
             q->op.reset(hdm::make_operator(S->ctx, q->X.data(), 0, q->prm, s));
             q->run.start(*q->op, q->r, q->tol, q->max_basis, q->prm.seed, s);
             HDM_HIP(hipStreamSynchronize(s));
@@ -138,10 +153,15 @@ void compressor_main(hdm_server_s* S) {
         } catch (...) {
             status = HDM_EINTERNAL;
         }
+        if (status != HDM_OK) release_solve(q);
         std::lock_guard<std::mutex> lk(S->mu);
+        if (status == HDM_OK) {
+            // the operator holds its own copy of the points
+            q->X.clear();
+            q->X.shrink_to_fit();
+            q->res.x_released = 1;
+        }
         if (status != HDM_OK) {
-            q->run = hdm::LanczosRun();
-            q->op.reset();
             finish_locked(S, q, status);
             admit_locked(S);
             continue;
@@ -180,8 +200,7 @@ void solver_main(hdm_server_s* S) {
             // cancelled solves leave before the tick
             for (auto it = running.begin(); it != running.end();) {
                 if ((*it)->cancel) {
-                    (*it)->run = hdm::LanczosRun();
-                    (*it)->op.reset();
+                    release_solve(*it);
                     finish_locked(S, *it, HDM_ECANCELLED);
                     it = running.erase(it);
                 } else {
@@ -224,28 +243,30 @@ void solver_main(hdm_server_s* S) {
                 }
             }
         } catch (const hdm::Error& e) {
-            // a device failure ends every running solve with that status
+            // a device failure ends every running solve with that status (the
+            // ones already finished this tick keep theirs)
             for (auto& q : running) {
+                if (std::find(done.begin(), done.end(), q) != done.end()) continue;
                 done.push_back(q);
                 done_status.push_back(e.code);
             }
         }
         if (!done.empty()) {
+            // device state released outside the lock (the release waits for the device)
+            {
+                hdm::PoolScope one_wait;   // the nested releases wait once, at its end
+                for (const ReqPtr& q : done) release_solve(q);
+            }
             std::lock_guard<std::mutex> lk(S->mu);
             for (size_t t = 0; t < done.size(); ++t) {
                 ReqPtr q = done[t];
-                q->run = hdm::LanczosRun();
-                q->op.reset();
                 running.erase(std::remove(running.begin(), running.end(), q), running.end());
                 finish_locked(S, q, done_status[t]);
             }
             admit_locked(S);
         }
     }
-    for (auto& q : running) {
-        q->run = hdm::LanczosRun();
-        q->op.reset();
-    }
+    for (auto& q : running) release_solve(q);
     (void)hipStreamDestroy(s);
 }
 
@@ -302,7 +323,7 @@ hdm_status hdm_submit(hdm_server S, const hdm_request_t* req, uint64_t* ticket) 
         q->max_basis = req->max_basis > 0 ? req->max_basis : static_cast<int>(std::min<int64_t>(req->params.n, 300));
         q->arrival_s = req->arrival_s > 0.0 ? req->arrival_s : now_s();
         q->est = hdm::footprint_estimate(req->params, q->max_basis);
-        q->res.x_released = 1;
+        q->res.x_released = 0;   // the host copy is kept until the operator is built
         std::lock_guard<std::mutex> lk(S->mu);
         S->submitted += 1;
         if (S->first_arrival == 0.0 || q->arrival_s < S->first_arrival) S->first_arrival = q->arrival_s;
@@ -327,6 +348,7 @@ hdm_status hdm_poll(hdm_server S, uint64_t ticket, hdm_result_t* out) {
         HDM_CHECK(it != S->all.end(), HDM_EINVAL, "unknown ticket");
         if (it->second->state != ServeReq::DONE) return HDM_EBUSY;
         *out = it->second->res;
+        S->all.erase(it);   // a result is handed out once; the ticket is then unknown
         return HDM_OK;
     });
 }

@@ -99,6 +99,7 @@ def lib():
         "hdm_last_error": (C.c_char_p, []),
         "hdm_version": (C.c_char_p, []),
         "hdm_params_default": (None, [C.POINTER(Params)]),
+        "hdm_params_validate": (st, [C.POINTER(Params)]),
         "hdm_ctx_create": (st, [C.c_int, C.c_size_t, C.POINTER(vp)]),
         "hdm_ctx_destroy": (st, [vp]),
         "hdm_ctx_profile": (st, [vp, C.c_int]),
@@ -356,7 +357,7 @@ class Server:
             return None
         check(st)
         return dict(status=res.status, evals=np.array(res.evals[:res.r]), latency_s=res.latency_s,
-                    service_s=res.service_s, iters=res.iters)
+                    service_s=res.service_s, iters=res.iters, x_released=res.x_released)
 
     def wait(self, ticket, timeout=120.0):
         import time
