@@ -502,7 +502,9 @@ __global__ void k_ritz(const double* V, int64_t ldv, int m, const double* Y, int
 }
 
 // per column: 2-norm and index of the largest |entry| (first on ties)
-__global__ void k_col_stats(const double* Phi, int64_t n, double* nrm, int64_t* arg) {
+// per column k: the scale that makes it unit-norm with its largest-magnitude entry
+// (first index on ties) positive; computed before any entry is rescaled
+__global__ void k_col_stats(const double* Phi, int64_t n, double* scale) {
     __shared__ double sv[kBlock];
     __shared__ int64_t si[kBlock];
     __shared__ double sn[kBlock];
@@ -531,16 +533,17 @@ __global__ void k_col_stats(const double* Phi, int64_t n, double* nrm, int64_t* 
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        nrm[k] = sqrt(sn[0]);
-        arg[k] = si[0];
+        const int64_t a = si[0];
+        const double sgn = (a >= 0 && a < n && Phi[k * n + a] < 0.0) ? -1.0 : 1.0;
+        scale[k] = sgn / sqrt(sn[0]);
     }
 }
 
-__global__ void k_col_fix(double* Phi, int64_t n, const double* nrm, const int64_t* arg) {
+// Phi[:, k] *= scale[k]; the scale is fixed before this launch (workgroups of one
+// launch rescale entries in place, so none of them may read an entry to decide it)
+__global__ void k_col_fix(double* Phi, int64_t n, const double* scale) {
     const int k = blockIdx.y;
-    const int64_t a = arg[k];
-    const double sgn = (a >= 0 && a < n && Phi[k * n + a] < 0.0) ? -1.0 : 1.0;
-    const double sc = sgn / nrm[k];
+    const double sc = scale[k];
     for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
          i += static_cast<int64_t>(gridDim.x) * blockDim.x)
         Phi[k * n + i] *= sc;
@@ -936,10 +939,9 @@ hdm_status LanczosRun::result(double* evals, double* evecs, hdm_eig_info_t* info
     if (evecs) {
         const int gN = ceil_div(n, kBlock);
         hipLaunchKernelGGL(k_ritz, dim3(gN), dim3(kBlock), 0, s, V.get(), n, m, Y.get(), r, evecs, n);
-        DevBuf<double> nrm(r);
-        DevBuf<int64_t> arg(r);
-        hipLaunchKernelGGL(k_col_stats, dim3(r), dim3(kBlock), 0, s, evecs, n, nrm.get(), arg.get());
-        hipLaunchKernelGGL(k_col_fix, dim3(std::min(gN, 256), r), dim3(kBlock), 0, s, evecs, n, nrm.get(), arg.get());
+        DevBuf<double> scale(r);
+        hipLaunchKernelGGL(k_col_stats, dim3(r), dim3(kBlock), 0, s, evecs, n, scale.get());
+        hipLaunchKernelGGL(k_col_fix, dim3(std::min(gN, 256), r), dim3(kBlock), 0, s, evecs, n, scale.get());
         check_launch("ritz vectors");
         HDM_HIP(hipStreamSynchronize(s));
     }
@@ -1059,10 +1061,9 @@ static hdm_status block_lanczos_eigs(Op& op, int r, double tol, int b, int max_b
     for (int i = 0; i < r; ++i) worst = std::max(worst, h_bound[i] / std::max(std::fabs(h_theta[i]), 1e-300));
     if (evecs) {
         hipLaunchKernelGGL(k_ritz, dim3(gN), dim3(kBlock), 0, s, V.get(), n, m, Z.get(), r, evecs, n);
-        DevBuf<double> nrm(r);
-        DevBuf<int64_t> arg(r);
-        hipLaunchKernelGGL(k_col_stats, dim3(r), dim3(kBlock), 0, s, evecs, n, nrm.get(), arg.get());
-        hipLaunchKernelGGL(k_col_fix, dim3(std::min(gN, 256), r), dim3(kBlock), 0, s, evecs, n, nrm.get(), arg.get());
+        DevBuf<double> scale(r);
+        hipLaunchKernelGGL(k_col_stats, dim3(r), dim3(kBlock), 0, s, evecs, n, scale.get());
+        hipLaunchKernelGGL(k_col_fix, dim3(std::min(gN, 256), r), dim3(kBlock), 0, s, evecs, n, scale.get());
         check_launch("ritz vectors");
     }
     HDM_HIP(hipStreamSynchronize(s));
