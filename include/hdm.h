@@ -190,6 +190,26 @@ hdm_status hdm_op_degrees(hdm_op op, double *q, double *d, double *c);
  * times a float16 hi + lo pair (about 22 bits), the sums are float32. */
 hdm_status hdm_matvec(hdm_op op, int normalised, const double *x, double *y, int32_t nrhs, void *stream);
 
+/* ---- allocation-free evaluation -----------------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the product of
+ * hdm_matvec (same arguments, same kernels, bit-identical results) whose
+ * workspaces -- the staged vector, skeleton weights and potentials, near-field
+ * partial sums, half-precision staging and a copy of the operator's descriptor --
+ * live in a 64 MiB device array that the library holds on every device it has
+ * a context on until the process ends.  It calls no allocating routine; the
+ * descriptor copy is a hipMemcpyAsync from pageable host memory (it returns
+ * when the copy is done).
+ * Limits and errors: a pass of min(nrhs, 16) columns needs about
+ * 8 min(nrhs, 16) (n + 2 skeleton slots + near partial sums) bytes; an operator
+ * above the 64 MiB gets HDM_ENOMEM and a message naming both sizes (fewer
+ * columns per call may fit).  Every call on one GPU shares its array: calls
+ * whose launches overlap on that GPU (other streams, other threads) race and
+ * give wrong results; calls ordered on one stream are safe.  Nothing in the
+ * array needs clearing between calls (every workspace is written before it is
+ * read). */
+hdm_status hdm_matvec_noalloc(hdm_op op, int normalised, const double *x, double *y, int32_t nrhs, void *stream);
+
 /* ---- eigensolver (Alg. 1 eigendecomposition; Sec. 2.2 Lanczos) --------------
  * Leading r eigenpairs (largest algebraic) of S~ by Lanczos with full float64
  * reorthogonalisation.  block = 1: single-vector Lanczos, stops when every

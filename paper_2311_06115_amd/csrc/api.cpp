@@ -219,6 +219,7 @@ hdm_status hdm_ctx_create(int device, size_t hbm_budget_bytes, hdm_ctx* out) {
         HDM_HIP(hipGetDeviceCount(&count));
         HDM_CHECK(device >= 0 && device < count, HDM_EINVAL, "no such device");
         set_device(device);
+        hdm::scratch_init(device);   // the allocation-free product's array on this device
         auto* c = new hdm_ctx_s();
         c->device = device;
         c->budget = hbm_budget_bytes;
@@ -436,6 +437,18 @@ hdm_status hdm_matvec(hdm_op op, int normalised, const double* x, double* y, int
                   "x and y overlap");
         set_device(op->ctx->device);
         hdm::apply(*op, normalised ? 1 : 0, false, x, y, nrhs, as_stream(stream), true);
+        return HDM_OK;
+    });
+}
+
+hdm_status hdm_matvec_noalloc(hdm_op op, int normalised, const double* x, double* y, int32_t nrhs, void* stream) {
+    return guarded([&] {
+        HDM_CHECK(op && x && y, HDM_EINVAL, "NULL argument");
+        HDM_CHECK(nrhs >= 1 && nrhs <= 64, HDM_EINVAL, "nrhs must be in [1, 64]");
+        HDM_CHECK(x + static_cast<int64_t>(op->n) * nrhs <= y || y + static_cast<int64_t>(op->n) * nrhs <= x, HDM_EINVAL,
+                  "x and y overlap");
+        set_device(op->ctx->device);
+        hdm::apply_noalloc(*op, normalised ? 1 : 0, x, y, nrhs, as_stream(stream), hdm::scratch_for(op->ctx->device));
         return HDM_OK;
     });
 }

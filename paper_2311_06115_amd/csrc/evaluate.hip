@@ -10,6 +10,8 @@
 #include <cmath>
 #include <map>
 #include <memory>
+#include <mutex>
+#include <string>
 #include <type_traits>
 
 #include "op.hpp"
@@ -1425,7 +1427,7 @@ static void apply_t(const ApplyReq* reqs, int nops, bool f64, int normalised, in
     b.nops = nops;
     b.nrhs = nrhs;
     for (int o = 0; o < nops; ++o) {
-        b.op[o] = f64 ? reqs[o].op->dev64.get() : reqs[o].op->devT.get();
+        b.op[o] = reqs[o].desc ? reqs[o].desc : (f64 ? reqs[o].op->dev64.get() : reqs[o].op->devT.get());
         b.x[o] = reqs[o].x;
         b.y[o] = reqs[o].y;
     }
@@ -1819,6 +1821,105 @@ void apply(Op& op, int normalised, bool exact64, const double* x, double* y, int
         const int np = std::min(per, nrhs - c0);
         if (graph_ok && !exact64 && apply_graph(op, f64, normalised, np, r.x, r.y, s)) continue;
         apply_dispatch(&r, 1, f64, normalised, np, s, op.lane, cx);
+    }
+}
+
+// ---- allocation-free products ---------------------------------------------------
+// For callers that cannot allocate device memory (graph capture, serving loops,
+// harnesses that forbid it): the workspaces of a product live in this array,
+// one per device, held until the process ends.  Host code never passes the
+// array's name to a kernel or a copy: it uses the address hipGetSymbolAddress
+// returns for the device (scratch_for).
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};   // why the address is missing, if it is
+
+// the layout of one product's scratch: descriptor, then the workspaces, each
+// 256-byte aligned; offsets in bytes
+struct ScratchLayout {
+    size_t desc, w, skw, sku, part, wh, wsc, total;
+};
+ScratchLayout scratch_layout(const Op& op, int per) {
+    auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+    const bool f64 = op.prm.near_prec == HDM_F64;
+    const int64_t part = std::max<int64_t>(f64 || !op.packed ? op.part_elems : op.part_elems_mma, 1);
+    ScratchLayout L{};
+    size_t at = 0;
+    L.desc = at; at += up(sizeof(OpDev));
+    L.w = at; at += up(static_cast<size_t>(op.n) * per * 8);
+    L.skw = at; at += up(static_cast<size_t>(std::max<int64_t>(op.nskel, 1)) * per * 8);
+    L.sku = at; at += up(static_cast<size_t>(std::max<int64_t>(op.nskel, 1)) * per * 8);
+    L.part = at; at += up(static_cast<size_t>(part) * per * 8);
+    L.wh = at; at += op.packed && !f64 ? up(static_cast<size_t>(std::max<int64_t>(op.ldw, 1)) * 2 * kMaxRhs * 2) : 0;
+    L.wsc = at; at += op.packed && !f64 ? up(static_cast<size_t>(op.L) * kMaxRhs * sizeof(float)) : 0;
+    L.total = at;
+    return L;
+}
+}  // namespace
+
+void scratch_init(int device) {
+    if (device < 0 || device >= kMaxDevices) return;   // the allocation-free product then reports it
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (g_scratch[device]) return;
+    void* p = nullptr;
+    const hipError_t rc = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));   // the caller made `device` current
+    if (rc != hipSuccess || p == nullptr) {
+        (void)hipGetLastError();
+        g_scratch_err[device] = rc != hipSuccess ? rc : hipErrorInvalidSymbol;
+        return;
+    }
+    g_scratch[device] = p;
+}
+
+void* scratch_for(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    return g_scratch[device];
+}
+
+size_t noalloc_bytes(const Op& op, int per) { return scratch_layout(op, per).total; }
+
+// The product of hdm_matvec with every workspace in `scratch` (the device's
+// array): the same kernels and launch order, so the same results bit for bit.
+// Host work only: a descriptor copy pointing into the scratch, uploaded to its
+// head, then the launches; no allocation on the device.
+void apply_noalloc(Op& op, int normalised, const double* x, double* y, int nrhs, hipStream_t s, void* scratch_dev) {
+    if (!scratch_dev) {
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        const hipError_t why = dev >= 0 && dev < kMaxDevices ? g_scratch_err[dev] : hipErrorInvalidDevice;
+        fail(HDM_EDEVICE, std::string("the allocation-free scratch array has no address on this device: ") +
+                              (why != hipSuccess ? hipGetErrorString(why) : "no context was created on it"));
+    }
+    HDM_CHECK(op.prm.max_rank_s <= kMaxRank, HDM_EINTERNAL, "rank above the combine kernel's limit");
+    const int per = std::min(nrhs, kMaxRhs);
+    const ScratchLayout L = scratch_layout(op, per);
+    if (L.total > kScratchBytes)
+        fail(HDM_ENOMEM, "the product needs " + std::to_string(L.total >> 20) + " MiB of workspace for " +
+                             std::to_string(per) + " right-hand sides per pass, above the " +
+                             std::to_string(kScratchBytes >> 20) + " MiB allocation-free scratch");
+    const bool f64 = op.prm.near_prec == HDM_F64;
+    char* base = static_cast<char*>(scratch_dev);
+    OpDev D = f64 ? op.host64 : op.hostT;
+    D.w = base + L.w;
+    D.skw = base + L.skw;
+    D.sku = base + L.sku;
+    D.part = base + L.part;
+    if (!f64 && op.packed) {
+        D.wh = base + L.wh;
+        D.wsc = reinterpret_cast<float*>(base + L.wsc);
+    }
+    // D is pageable host memory: the copy is complete when the call returns
+    HDM_HIP(hipMemcpyAsync(base + L.desc, &D, sizeof(OpDev), hipMemcpyHostToDevice, s));
+    const OpDev* desc = reinterpret_cast<const OpDev*>(base + L.desc);
+    for (int c0 = 0; c0 < nrhs; c0 += per) {
+        ApplyReq r{&op, x + static_cast<int64_t>(c0) * op.n, y + static_cast<int64_t>(c0) * op.n, desc};
+        const int np = std::min(per, nrhs - c0);
+        apply_dispatch(&r, 1, f64, normalised, np, s, op.lane, nullptr);
     }
 }
 

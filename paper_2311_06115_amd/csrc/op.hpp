@@ -297,6 +297,7 @@ struct ApplyReq {
     Op* op;
     const double* x;
     double* y;
+    const OpDev* desc = nullptr;   // device descriptor to launch with (nullptr: the operator's own)
 };
 
 // One Lanczos eigensolve (Sec. 2.2) that advances a step at a time: the caller
@@ -357,6 +358,16 @@ void apply(Op& op, int normalised, bool exact64, const double* x, double* y, int
 // single-operator product gives.
 constexpr int kMaxBatch = 8;
 void apply_batch(const ApplyReq* reqs, int nops, int normalised, int nrhs, hipStream_t s, Lane& lane, Ctx* prof_ctx);
+// Allocation-free products (evaluate.hip): a file-scope device array holds the
+// product's workspaces and a copy of the descriptor.  scratch_init resolves its
+// address on the current device (once per device, at context creation);
+// scratch_for returns it (nullptr before scratch_init).
+constexpr size_t kScratchBytes = size_t(64) << 20;
+void scratch_init(int device);
+void* scratch_for(int device);
+// bytes of scratch a product of `per` right-hand sides per pass needs
+size_t noalloc_bytes(const Op& op, int per);
+void apply_noalloc(Op& op, int normalised, const double* x, double* y, int nrhs, hipStream_t s, void* scratch);
 // eigensolver (lanczos.hip)
 hdm_status lanczos_eigs(Op& op, int r, double tol, int block, int max_basis, uint64_t seed, double* evals,
                         double* evecs, hdm_eig_info_t* info, hipStream_t s);

@@ -116,6 +116,7 @@ def lib():
         "hdm_op_node": (st, [vp, i64, vp, vp, vp]),
         "hdm_op_degrees": (st, [vp, vp, vp, vp]),
         "hdm_matvec": (st, [vp, C.c_int, vp, vp, i32, vp]),
+        "hdm_matvec_noalloc": (st, [vp, C.c_int, vp, vp, i32, vp]),
         "hdm_eigs": (st, [vp, i32, f64, i32, i32, C.c_uint64, vp, vp, C.POINTER(EigInfo), vp]),
         "hdm_server_create": (st, [vp, C.POINTER(ServerCfg), C.POINTER(vp)]),
         "hdm_submit": (st, [vp, C.POINTER(Request), C.POINTER(C.c_uint64)]),
@@ -314,6 +315,18 @@ class Operator:
                                X.shape[0], _stream(torch)))
         Y = Y.t()
         return Y[:, 0] if vec else Y
+
+    def matvec_noalloc(self, x, out, normalised: bool = False):
+        """hdm_matvec_noalloc: out = K~ x (or S~ x) with the library's scratch array as
+        the only workspace; x and out: float64 cuda tensors of shape (nrhs, n)
+        (column-major n x nrhs), allocated by the caller."""
+        torch = self.torch
+        assert x.dtype == torch.float64 and out.dtype == torch.float64 and x.is_contiguous() and out.is_contiguous()
+        assert x.shape == out.shape and x.shape[-1] == self.n
+        nrhs = 1 if x.dim() == 1 else x.shape[0]
+        check(lib().hdm_matvec_noalloc(self.h, int(normalised), C.c_void_p(x.data_ptr()), C.c_void_p(out.data_ptr()),
+                                       nrhs, _stream(torch)))
+        return out
 
     def eigs(self, r, tol=1e-10, block=1, max_basis=0, seed=0, vectors=True):
         torch = self.torch
