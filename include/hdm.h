@@ -89,6 +89,8 @@ typedef struct {
                                     once, their skeleton weights written) */
     int64_t flops_matvec;        /* 2 x multiply-adds of one single-vector product */
     double seconds_compress;     /* wall time of hdm_compress */
+    int64_t near_tile_bytes;     /* unpadded near tiles in the evaluation precision (read once per product pass) */
+    int64_t near_elems;          /* unpadded near-tile elements (multiply-adds per right-hand side) */
 } hdm_op_stats_t;
 
 typedef struct {

@@ -343,6 +343,8 @@ hdm_status hdm_op_stats(hdm_op op, hdm_op_stats_t* out) {
                 leaf_sk += op->rank[h];
             }
         st.algo_bytes_near = static_cast<int64_t>(near_alg * en + 2 * op->n * ev + leaf_p * ep + leaf_sk * ev);
+        st.near_tile_bytes = static_cast<int64_t>(near_alg * en);
+        st.near_elems = near_alg;
         st.flops_matvec = 2 * (near_alg + op->far_elems + 2 * op->np);
         st.seconds_compress = op->seconds_compress;
         *out = st;

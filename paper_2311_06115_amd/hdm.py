@@ -42,7 +42,7 @@ class OpStats(C.Structure):
                 ("bytes_near", C.c_int64), ("bytes_far", C.c_int64), ("bytes_p", C.c_int64),
                 ("bytes_total", C.c_int64), ("algo_bytes_matvec", C.c_int64), ("algo_bytes_near", C.c_int64),
                 ("flops_matvec", C.c_int64),
-                ("seconds_compress", C.c_double)]
+                ("seconds_compress", C.c_double), ("near_tile_bytes", C.c_int64), ("near_elems", C.c_int64)]
 
 
 PHASES = ["prep", "n2s", "s2s", "s2n", "l2l", "combine", "ortho", "tridiag", "compress"]

@@ -20,6 +20,10 @@ CONFIGS = {
     # (compared against the f32 path; bf16 far tiles alone cost 1.2e-4 in lambda_4)
     "mnist-64k": dict(family="mnist", n=65536, dim=784, seed=2, m=256, s=256, tau=1e-4, k=32,
                       near_prec="bf16", far_prec="f32", r=10, block=1),
+    # the MNIST-shaped workload's parameters at a size whose dense float64 spectrum the
+    # oracle computes (the golden eigenvalues of the mixed path)
+    "mnist-8k": dict(family="mnist", n=8192, dim=784, seed=2, m=256, s=256, tau=1e-4, k=32,
+                     near_prec="bf16", far_prec="f32", r=10, block=1),
     # 3-D S-curve, 100k points, f16 near tiles, block Lanczos with 16 start vectors
     "scurve-100k": dict(family="scurve", n=100000, dim=3, seed=3, m=512, s=256, tau=1e-5, k=32,
                         near_prec="f16", far_prec="f32", r=20, block=16),
@@ -69,9 +73,11 @@ def make_inputs(cfg: dict, n: int | None = None):
 # Serving stream: Poisson arrivals, each request an S-curve or MNIST-shaped
 # instance with N log-uniform in [4096, 65536], 8 eigenpairs at relative
 # residual 1e-6.  Per-family compression parameters:
+# (MNIST-shaped: s = 128, below every leaf of m = 256; u8 requests with a rank
+# above the smallest leaf are refused by the library)
 SERVING_FAMILIES = {
     "scurve": dict(dim=3, m=256, s=128, tau=1e-5, k=32),
-    "mnist": dict(dim=784, m=256, s=256, tau=1e-4, k=32),
+    "mnist": dict(dim=784, m=256, s=128, tau=1e-4, k=32),
 }
 SERVING = dict(rate=20.0, r=8, tol=1e-6, n_lo=4096, n_hi=65536, arrival_seed=7, request_seed0=1000)
 # tile precisions (near, far) of the two paths the serving stream compares

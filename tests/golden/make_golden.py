@@ -1,11 +1,17 @@
 """Write the stored expected values under tests/golden/ by calling only the oracle.
 
-    python tests/golden/make_golden.py [config ...]
+    python tests/golden/make_golden.py [config ...]            eigenvalues
+    python tests/golden/make_golden.py --structure [config ...] structure digests
 
 For each named workload it records the leading eigenvalues of the dense
 alpha = 1 normalised Gaussian operator (Alg. 1; Eq. (2)), computed by the
 oracle's float64 Lanczos (Sec. 2.2) over the oracle's exact dense product, and
 the same for the oracle's compressed operator K~ (Eq. (3)).
+
+With --structure it records SHA-256 digests of the oracle's compressed
+structure at full size (tree permutation, neighbour lists, near and far lists,
+ranks and skeletons; Sec. 2.1 and Eq. (3)), for workloads whose arrays are too
+large to store.
 """
 from __future__ import annotations
 
@@ -37,7 +43,7 @@ def golden(name: str) -> dict:
     else:   # matrix-free dense products of 1e10 kernel values each are out of reach here
         lam_d, info_d = None, {"iters": 0}
     t1 = time.time()
-    H = HM.HMatrix(X, eps, cfg["m"], cfg["s"], cfg["tau"], cfg["k"], cfg["seed"])
+    H = HM.HMatrix(X, eps, cfg["m"], cfg["s"], cfg["tau"], cfg["k"], cfg["seed"], budget=cfg.get("budget", 0.05))
     lam_h, _, info_h = DF.eigs(H.matvec, n, r, tol=1e-11, seed=cfg["seed"])
     t2 = time.time()
     return {
@@ -53,6 +59,42 @@ def golden(name: str) -> dict:
     }
 
 
+def structure_digests(H) -> dict:
+    """SHA-256 of each structure array in a fixed little-endian layout (tests compare the GPU's)."""
+    import hashlib
+
+    def sha(*arrays):
+        h = hashlib.sha256()
+        for a in arrays:
+            h.update(np.ascontiguousarray(a).astype(a.dtype.newbyteorder("<"), copy=False).tobytes())
+        return h.hexdigest()
+
+    idx, d2 = H.knn()
+    r, c, nr = H.ranks()
+    skel = [H.node(h)[0] for h in range(2, H.nnodes)]
+    return {
+        "perm": sha(H.perm().astype(np.int32)),
+        "knn_idx": sha(idx.astype(np.int32)),
+        "knn_d2": sha(d2.astype(np.float64)),
+        "near": sha(*[a.astype(np.int32) for a in H.near()]),
+        "far": sha(*[a.astype(np.int32) for a in H.far()]),
+        "ranks": sha(r[2:].astype(np.int32), c[2:].astype(np.int32), nr[2:].astype(np.int32)),
+        "skeletons": sha(*[s.astype(np.int32) for s in skel]),
+    }
+
+
+def structure(name: str) -> dict:
+    cfg = synth.get_config(name)
+    X, eps = synth.configs.make_inputs(cfg)
+    t0 = time.time()
+    H = HM.HMatrix(X, eps, cfg["m"], cfg["s"], cfg["tau"], cfg["k"], cfg["seed"], budget=cfg.get("budget", 0.05))
+    dig = structure_digests(H)
+    r, _, _ = H.ranks()
+    return {"config": name, "n": X.shape[0], "eps": eps,
+            "source": "oracle: CPU build of the compression (Sec. 2.1, Eq. (3)), SHA-256 per array",
+            "digests": dig, "max_rank": int(r[2:].max()), "seconds": time.time() - t0}
+
+
 def main(names):
     for name in names:
         g = golden(name)
@@ -62,5 +104,18 @@ def main(names):
         print(path, g["seconds"], g["dense_eigenvalues"], g["hmatrix_eigenvalues"])
 
 
+def main_structure(names):
+    for name in names:
+        g = structure(name)
+        path = os.path.join(HERE, f"structure_{name}.json")
+        with open(path, "w") as f:
+            json.dump(g, f, indent=1)
+        print(path, g["seconds"])
+
+
 if __name__ == "__main__":
-    main(sys.argv[1:] or ["scurve-2k", "scurve-32k"])
+    args = sys.argv[1:]
+    if args and args[0] == "--structure":
+        main_structure(args[1:] or ["scurve-32k", "mnist-64k", "scurve-100k"])
+    else:
+        main(args or ["scurve-2k", "scurve-32k"])
