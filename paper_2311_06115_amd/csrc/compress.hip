@@ -1626,15 +1626,212 @@ struct NearPair {
 
 // float64 near tiles; with out32 also their float32 copy (the unscaled
 // round-to-nearest conversion of the evaluation tiles, written at the same offsets)
+// (a tile has at most 2048 x 2048 entries, so its element index fits 32 bits)
 __global__ void k_near_tiles(const NearPair* pairs, const int32_t* perm, Pts P, double* out, float* out32) {
     const NearPair pr = pairs[blockIdx.y];
-    const int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-    if (e >= static_cast<int64_t>(pr.ld) * pr.nb) return;
-    const int i = static_cast<int>(e % pr.ld), j = static_cast<int>(e / pr.ld);
+    const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= static_cast<uint32_t>(pr.ld) * static_cast<uint32_t>(pr.nb)) return;
+    const int i = static_cast<int>(e % static_cast<uint32_t>(pr.ld)), j = static_cast<int>(e / static_cast<uint32_t>(pr.ld));
     const double v = i < pr.na ? kval(P, perm[pr.a0 + i], perm[pr.b0 + j]) : 0.0;
-    out[pr.off + e] = v;
+    if (out) out[pr.off + e] = v;
     if (out32) out32[pr.off + e] = static_cast<float>(v);
 }
+
+// ---------------------------------------------------------------------------
+// Near tiles written directly in the evaluation precision (float64 points of at
+// most kDimReg coordinates): no float64 copy is kept, and the two float64 degree
+// products evaluate the kernel values on the fly (k_near_otf).
+// ---------------------------------------------------------------------------
+constexpr int kDirectDim = 16;
+
+// The coordinates of point i in registers.  The kernels below are compiled per
+// point dimension D (1..8, and 16 for 9..16 with the unused slots zero), so a
+// thread keeps only the registers its points need.
+template <int D>
+__device__ inline void load_point(const Pts& P, int32_t i, double (&x)[D]) {
+    const double* p = P.xf + static_cast<int64_t>(i) * P.dim;
+#pragma unroll
+    for (int d = 0; d < D; ++d) x[d] = d < P.dim ? p[d] : 0.0;
+}
+
+// squared distance, coordinates in increasing order, one rounding per operation
+// (zero slots past the point's dimension add exact zeros)
+template <int D>
+__device__ inline double sqd_regs(const double (&x)[D], const double (&y)[D]) {
+    double acc = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        const double t = x[d] - y[d];
+        acc = acc + t * t;
+    }
+    return acc;
+}
+
+// Per tile (one workgroup): its largest kernel value, exp(-(min d2) / eps) since
+// the kernel decreases with the distance, as the float scale of the reduced-
+// precision tile (1 where every value underflows to 0).  The column points are
+// staged in shared memory a chunk at a time; a thread keeps one row point in
+// registers and reads the columns as broadcasts.
+constexpr int kScaleChunk = 256;
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_near_scale(const NearPair* pairs, const int32_t* perm, Pts P,
+                                                       float* scale) {
+    __shared__ double cs[kScaleChunk * D];
+    __shared__ double sm[kBlock];
+    const NearPair pr = pairs[blockIdx.x];
+    double best = INFINITY;
+    for (int c0 = 0; c0 < pr.nb; c0 += kScaleChunk) {
+        const int nc = min(kScaleChunk, pr.nb - c0);
+        __syncthreads();
+        for (int e = threadIdx.x; e < nc * D; e += blockDim.x) {
+            const int j = e / D, d = e % D;
+            cs[e] = d < P.dim ? P.xf[static_cast<int64_t>(perm[pr.b0 + c0 + j]) * P.dim + d] : 0.0;
+        }
+        __syncthreads();
+        for (int r = threadIdx.x; r < pr.na; r += blockDim.x) {
+            double xr[D];
+            load_point<D>(P, perm[pr.a0 + r], xr);
+            for (int j = 0; j < nc; ++j) {
+                double y[D];
+#pragma unroll
+                for (int d = 0; d < D; ++d) y[d] = cs[j * D + d];
+                best = fmin(best, sqd_regs<D>(xr, y));
+            }
+        }
+    }
+    sm[threadIdx.x] = best;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sm[threadIdx.x] = fmin(sm[threadIdx.x], sm[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double m = exp(-(sm[0] / P.eps));
+        scale[blockIdx.x] = m > 0.0 ? static_cast<float>(m) : 1.0f;
+    }
+}
+
+typedef _Float16 direct_h8 __attribute__((ext_vector_type(8)));
+
+// K / scale for a reduced-precision tile: the squared distance in float64 (the
+// coordinates' differences would lose digits in float32), the exponential in
+// float32.  Its relative error, about |d2 / eps| 2^-24 with |d2 / eps| < 104
+// before the value underflows, stays below 1e-5 of the value: far under half an
+// ulp of float16 (2^-12) or bfloat16 (2^-9).
+template <int D>
+__device__ inline float kval_scaled_f32(const double (&x)[D], const double (&y)[D], float neg_inv_eps,
+                                        float inv_scale) {
+    return __expf(static_cast<float>(sqd_regs<D>(x, y)) * neg_inv_eps) * inv_scale;
+}
+
+// float16 tiles packed for the matrix cores: tile t is ld x kc (kc = nb rounded
+// up to 8, zero padded) with element (r, k) at ((k / 8) ld + r) 8 + k mod 8; one
+// thread writes the 8 consecutive columns of one row (16 bytes).  Consecutive
+// threads take consecutive rows of one 8-column group, so the group's column
+// points are the same for most of a wave (cached loads).
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_near_direct_f16(const NearPair* pairs, const int64_t* offp,
+                                                            const int32_t* perm, Pts P, const float* scale,
+                                                            _Float16* dst) {
+    const NearPair pr = pairs[blockIdx.y];
+    const uint32_t groups = static_cast<uint32_t>((pr.nb + 7) / 8);
+    const uint32_t tot = groups * static_cast<uint32_t>(pr.ld);
+    const float inv = 1.0f / scale[blockIdx.y];
+    const float nie = static_cast<float>(-1.0 / P.eps);
+    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += gridDim.x * blockDim.x) {
+        const int kg = static_cast<int>(e / static_cast<uint32_t>(pr.ld)), r = static_cast<int>(e % static_cast<uint32_t>(pr.ld));
+        double xr[D];
+        load_point<D>(P, perm[pr.a0 + min(r, pr.na - 1)], xr);
+        direct_h8 v;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            double xc[D];
+            load_point<D>(P, perm[pr.b0 + min(kg * 8 + q, pr.nb - 1)], xc);
+            const bool in = r < pr.na && kg * 8 + q < pr.nb;
+            v[q] = static_cast<_Float16>(in ? kval_scaled_f32<D>(xr, xc, nie, inv) : 0.0f);
+        }
+        *reinterpret_cast<direct_h8*>(dst + offp[blockIdx.y] + static_cast<int64_t>(e) * 8) = v;
+    }
+}
+
+// bfloat16 tiles (column-major ld x nb, padded rows zero): round-to-nearest-even
+// of K / scale in float32
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_near_direct_bf16(const NearPair* pairs, const int32_t* perm, Pts P,
+                                                             const float* scale, uint16_t* dst) {
+    const NearPair pr = pairs[blockIdx.y];
+    const uint32_t tot = static_cast<uint32_t>(pr.ld) * static_cast<uint32_t>(pr.nb);
+    const float inv = 1.0f / scale[blockIdx.y];
+    const float nie = static_cast<float>(-1.0 / P.eps);
+    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += gridDim.x * blockDim.x) {
+        const int i = static_cast<int>(e % static_cast<uint32_t>(pr.ld)), j = static_cast<int>(e / static_cast<uint32_t>(pr.ld));
+        double xr[D], xc[D];
+        load_point<D>(P, perm[pr.a0 + min(i, pr.na - 1)], xr);
+        load_point<D>(P, perm[pr.b0 + j], xc);
+        const float x = i < pr.na ? kval_scaled_f32<D>(xr, xc, nie, inv) : 0.0f;
+        const uint32_t u = __float_as_uint(x);
+        dst[pr.off + e] = static_cast<uint16_t>((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+    }
+}
+
+// The float64 near field of one column with the kernel evaluated on the fly:
+// one wave per work item of the plain plan (as the stored-tile kernel), lane l
+// owning rows row0 + 2 l and row0 + 2 l + 1 of each 128-row pass.  The item's
+// (at most 64) column points and weights are loaded once, one per lane, and
+// broadcast from their lane column by column; part[part_off + row] = sum over the
+// columns in increasing order of K(row, col) w[col], K as the oracle evaluates it
+// (float64, one rounding per operation).
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_near_otf(const NearItem* items, int64_t nitems, const int32_t* perm, Pts P,
+                                                    const double* w, double* part) {
+    const int64_t u = blockIdx.x * static_cast<int64_t>(blockDim.x / kWave) + threadIdx.x / kWave;
+    if (u >= nitems) return;
+    const NearItem I = items[u];
+    const int lane = threadIdx.x % kWave;
+    double xc[D];
+    load_point<D>(P, perm[I.col_pos + min(lane, I.ncols - 1)], xc);
+    const double wl = w[I.col_pos + min(lane, I.ncols - 1)];
+    const int rend = min(I.ld, I.row0 + I.nrows);
+    for (int r0 = I.row0; r0 < rend; r0 += 2 * kWave) {
+        const int row = r0 + 2 * lane;
+        double x0[D], x1[D];
+        const bool v0 = row < I.row_n, v1 = row + 1 < I.row_n;
+        load_point<D>(P, perm[I.row_pos + min(row, I.row_n - 1)], x0);
+        load_point<D>(P, perm[I.row_pos + min(row + 1, I.row_n - 1)], x1);
+        double a0 = 0.0, a1 = 0.0;
+        for (int j = 0; j < I.ncols; ++j) {
+            double y[D];
+#pragma unroll
+            for (int d = 0; d < D; ++d) y[d] = lane_value(xc[d], j);
+            const double wj = lane_value(wl, j);
+            const double k0 = exp(-(sqd_regs<D>(x0, y) / P.eps));
+            const double k1 = exp(-(sqd_regs<D>(x1, y) / P.eps));
+            a0 = a0 + (v0 ? k0 : 0.0) * wj;
+            a1 = a1 + (v1 ? k1 : 0.0) * wj;
+        }
+        if (row < rend) {
+            double* out = part + I.part_off + row;
+            out[0] = a0;
+            if (row + 1 < rend) out[1] = a1;
+        }
+    }
+}
+
+// launches a kernel template specialised on the point dimension
+#define HDM_DIM_DISPATCH(dim, KERNEL, ...)                                                          \
+    do {                                                                                           \
+        switch (dim) {                                                                             \
+            case 1: hipLaunchKernelGGL(KERNEL<1>, __VA_ARGS__); break;                              \
+            case 2: hipLaunchKernelGGL(KERNEL<2>, __VA_ARGS__); break;                              \
+            case 3: hipLaunchKernelGGL(KERNEL<3>, __VA_ARGS__); break;                              \
+            case 4: hipLaunchKernelGGL(KERNEL<4>, __VA_ARGS__); break;                              \
+            case 5: hipLaunchKernelGGL(KERNEL<5>, __VA_ARGS__); break;                              \
+            case 6: hipLaunchKernelGGL(KERNEL<6>, __VA_ARGS__); break;                              \
+            case 7: hipLaunchKernelGGL(KERNEL<7>, __VA_ARGS__); break;                              \
+            case 8: hipLaunchKernelGGL(KERNEL<8>, __VA_ARGS__); break;                              \
+            default: hipLaunchKernelGGL(KERNEL<kDirectDim>, __VA_ARGS__); break;                    \
+        }                                                                                          \
+    } while (0)
 
 struct FarBlock {
     int64_t off;       // element offset (row-major rank x cols)
@@ -2126,7 +2323,58 @@ static void build_near_tiles(Op& op, const Geo& G, hipStream_t s) {
         HDM_CHECK(pr.na >= 1 && pr.na <= pr.ld && pr.a0 >= 0 && pr.a0 + pr.na <= op.n && pr.b0 >= 0 && pr.nb >= 1 &&
                       pr.b0 + pr.nb <= op.n && pr.off >= 0 && pr.off + static_cast<int64_t>(pr.ld) * pr.nb <= off,
                   HDM_EINTERNAL, "near tile descriptor outside its buffers");
-    op.near64.alloc(off);
+    // float64 points of few coordinates: the tiles go straight to the evaluation
+    // precision and the degree products evaluate the kernel on the fly
+    const bool direct = !G.gram && !P.is_u8 && P.dim <= kDirectDim && op.prm.near_prec != HDM_F64;
+    op.near_direct = direct;
+    if (!direct) op.near64.alloc(off);
+    if (direct) {
+        op.near_pairs.alloc(pairs.size() * sizeof(NearPair));
+        op.near_pairs.upload(reinterpret_cast<const char*>(pairs.data()), pairs.size() * sizeof(NearPair), s);
+        const NearPair* pairs_dev = reinterpret_cast<const NearPair*>(op.near_pairs.get());
+        const int64_t np = static_cast<int64_t>(pairs.size());
+        int64_t maxe = 0;
+        for (auto& p : pairs) maxe = std::max<int64_t>(maxe, static_cast<int64_t>(p.ld) * p.nb);
+        if (op.prm.near_prec == HDM_F32) {
+            // unscaled float32 values of the float64 kernel
+            op.nearT.alloc(static_cast<size_t>(std::max<int64_t>(op.near_elems, 1)) * sizeof(float));
+            for (int64_t base = 0; base < np; base += 65535) {
+                const int cnt = static_cast<int>(std::min<int64_t>(65535, np - base));
+                hipLaunchKernelGGL(k_near_tiles, dim3(ceil_div(maxe, kBlock), cnt), dim3(kBlock), 0, s, pairs_dev + base,
+                                   op.perm.get(), P, nullptr, reinterpret_cast<float*>(op.nearT.get()));
+            }
+        } else {
+            op.near_scale.alloc(static_cast<size_t>(np));
+            HDM_DIM_DISPATCH(P.dim, k_near_scale, dim3(static_cast<unsigned>(np)), dim3(kBlock), 0, s, pairs_dev,
+                             op.perm.get(), P, op.near_scale.get());
+            const unsigned gx = static_cast<unsigned>(std::min<int64_t>(ceil_div(maxe, 8 * kBlock), 64));
+            if (op.prm.near_prec == HDM_BF16) {
+                op.nearT.alloc(static_cast<size_t>(std::max<int64_t>(op.near_elems, 1)) * sizeof(uint16_t));
+                for (int64_t base = 0; base < np; base += 65535) {
+                    const int cnt = static_cast<int>(std::min<int64_t>(65535, np - base));
+                    HDM_DIM_DISPATCH(P.dim, k_near_direct_bf16, dim3(std::max(gx, 1u), cnt), dim3(kBlock), 0, s,
+                                     pairs_dev + base, op.perm.get(), P, op.near_scale.get() + base,
+                                     reinterpret_cast<uint16_t*>(op.nearT.get()));
+                }
+            } else {   // float16, packed for the matrix cores
+                packed_near_offsets(op);
+                if (!op.conv_keep) op.conv_keep.reset(new Op::ConvKeep());
+                op.conv_keep->h64.push_back(op.near_tile_off_mma);
+                op.conv_keep->d64.push_back(to_device(op.conv_keep->h64.back(), s));
+                const int64_t* offp = op.conv_keep->d64.back().get();
+                op.nearT.alloc(static_cast<size_t>(std::max<int64_t>(op.near_elems_mma, 1)) * sizeof(_Float16));
+                for (int64_t base = 0; base < np; base += 65535) {
+                    const int cnt = static_cast<int>(std::min<int64_t>(65535, np - base));
+                    HDM_DIM_DISPATCH(P.dim, k_near_direct_f16, dim3(std::max(gx, 1u), cnt), dim3(kBlock), 0, s,
+                                     pairs_dev + base, offp + base, op.perm.get(), P, op.near_scale.get() + base,
+                                     reinterpret_cast<_Float16*>(op.nearT.get()));
+                }
+            }
+        }
+        check_launch("near tiles (evaluation precision)");
+        op.near_converted = true;
+        return;
+    }
     if (G.gram) {
         HDM_HIP(hipMemsetAsync(op.near64.get(), 0, op.near64.bytes(), s));   // padded rows stay zero
         std::vector<GramBlock> blocks;
@@ -2218,6 +2466,22 @@ static void build_far_tiles(Op& op, const Geo& G, hipStream_t s, DevBuf<char>& k
         }
         check_launch("far tiles");
     }
+}
+
+void near_field_otf(const Op& op, const double* w_tree, double* part, hipStream_t s) {
+    HDM_CHECK(op.near_direct && op.xf.get() && op.dim <= kDirectDim, HDM_EINTERNAL,
+              "on-the-fly near field needs float64 points of few coordinates");
+    Pts P{};
+    P.xf = op.xf.get();
+    P.dim = op.dim;
+    P.is_u8 = 0;
+    P.eps = op.prm.eps;
+    const int64_t ni = static_cast<int64_t>(op.items.size());
+    if (ni == 0) return;
+    const int wpb = kBlock / kWave;
+    HDM_DIM_DISPATCH(P.dim, k_near_otf, dim3(ceil_div(ni, wpb)), dim3(kBlock), 0, s, op.d_items.get(), ni,
+                     op.perm.get(), P, w_tree, part);
+    check_launch("near field (kernel on the fly)");
 }
 
 // buffers of the build that queued kernels still read when compress_operator

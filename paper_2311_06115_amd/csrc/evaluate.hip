@@ -1125,7 +1125,6 @@ static void publish_descriptors(Op& op, hipStream_t s) {
     op.devT.upload(&op.hostT, 1, s);
 }
 
-static void packed_near_offsets(Op& op);
 static void check_near_plan(const Op& op);
 
 // Plan of the packed half-precision near field (k_l2l_mma): per near pair an
@@ -1310,6 +1309,8 @@ void build_near_plan(Op& op, hipStream_t s) {
                     I.col_pos = static_cast<int32_t>(op.start[hb] + c0);
                     I.tile = t;
                     I.nrows = rg;
+                    I.row_pos = lp.start;
+                    I.row_n = lp.rows;
                     op.items.push_back(I);
                 }
             }
@@ -1471,7 +1472,11 @@ static void apply_t(const ApplyReq* reqs, int nops, bool f64, int normalised, in
     // rides in the near field's launch (its first workgroups, one per leaf), beside
     // the tile streaming; the levels above follow in one launch through the
     // composites (or one launch per level without them), then the far field.
-    const bool fuse_up = tree && !multi && nops == 1;
+    // float64 products of an operator without float64 near tiles (its degrees):
+    // the near field evaluates the kernel on the fly
+    const bool otf = f64 && reqs[0].op->near_direct;
+    HDM_CHECK(!otf || (nops == 1 && !multi), HDM_EINTERNAL, "on-the-fly near field takes one operator and one column");
+    const bool fuse_up = tree && !multi && nops == 1 && !otf;
     b.up = fuse_up ? static_cast<int>(reqs[0].op->L) : 0;
     auto near_field = [&] {
         const int64_t tot = prefix([](const Op& op, int) {
@@ -1479,6 +1484,11 @@ static void apply_t(const ApplyReq* reqs, int nops, bool f64, int normalised, in
         });
         b.flip = static_cast<int>(reqs[0].op->near_calls++ & 1u);
         const int64_t grid = ceil_div(tot, wpb) + b.up;
+        if (otf) {
+            const Op& o0 = *reqs[0].op;
+            near_field_otf(o0, reinterpret_cast<const double*>(o0.w_tree.get()), reinterpret_cast<double*>(o0.part.get()), s);
+            return;
+        }
         KernelEvents ev(cx, HDM_PHASE_L2L);
         if (mma && fuse_up)
             hipExtLaunchKernelGGL(k_l2l_mma<true>, dim3(grid), dim3(kBlock), 0, s, ev.start, ev.stop, 0, b);
@@ -1812,7 +1822,8 @@ void apply(Op& op, int normalised, bool exact64, const double* x, double* y, int
         publish_descriptors(op, s);
     }
     const bool f64 = exact64 || op.prm.near_prec == HDM_F64;
-    HDM_CHECK(!f64 || op.near64.n > 0 || op.near_elems == 0, HDM_EINTERNAL, "float64 tiles are not resident");
+    HDM_CHECK(!f64 || op.near64.n > 0 || op.near_elems == 0 || (exact64 && op.near_direct), HDM_EINTERNAL,
+              "float64 tiles are not resident");
     // the float64 products of the degree pass belong to building the operator:
     // they are not recorded as evaluation phases
     Ctx* cx = exact64 ? nullptr : op.ctx;
@@ -2056,7 +2067,7 @@ static void near_ranges(const Op& op, std::vector<int64_t>& noff, std::vector<in
 }
 
 // offsets of the packed float16 near tiles (ld_a x |b| rounded up to 8 per pair)
-static void packed_near_offsets(Op& op) {
+void packed_near_offsets(Op& op) {
     op.near_tile_off_mma.assign(op.near_idx.size(), 0);
     int64_t off = 0;
     for (int64_t a = 0; a < op.L; ++a)

@@ -89,6 +89,8 @@ struct NearItem {
     int32_t tile;       // index of the near tile (for its scale)
     int32_t nrows;      // rows of the item: [row0, min(ld, row0 + nrows))
     int32_t leaf_b;     // column leaf (matrix-core items: index of its vector scales)
+    int32_t row_pos;    // tree position of the row leaf's first point (plain items)
+    int32_t row_n;      // points in the row leaf (rows at or past it are padding)
 };
 
 // Per leaf: where its partial sums live and how many items feed each row group.
@@ -245,6 +247,9 @@ struct Op {
     // near tiles converted to the evaluation precision early (while the skeletons
     // are computed); the conversion's staging buffers live until it has completed
     bool near_converted = false;
+    // near tiles written directly in the evaluation precision (no float64 copy);
+    // the float64 degree products evaluate the kernel on the fly (compress.hip)
+    bool near_direct = false;
     struct ConvKeep {
         std::vector<DevBuf<int64_t>> d64;
         std::vector<DevBuf<int32_t>> d32;
@@ -337,6 +342,12 @@ size_t footprint_estimate(const hdm_params& p, int max_basis);
 
 // compression (compress.hip)
 void compress_operator(Op& op, const void* X, int x_on_device, hipStream_t s);
+// float64 near field of one column with the kernel evaluated on the fly from the
+// points (operators with near_direct): part[item] = K(rows, cols) w over the
+// plain work items, w and part the product's float64 workspaces
+void near_field_otf(const Op& op, const double* w_tree, double* part, hipStream_t s);
+// offsets of the packed half-precision near tiles (evaluate.hip)
+void packed_near_offsets(Op& op);
 // evaluation (evaluate.hip)
 void build_near_plan(Op& op, hipStream_t s);
 void build_eval_plan(Op& op, hipStream_t s);

@@ -129,6 +129,19 @@ def test_degrees_and_normalised_product(name):
     assert np.linalg.norm(u - ref) <= 1e-12 * np.linalg.norm(ref)
 
 
+@pytest.mark.parametrize("prec", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("name", ["scurve-2k", "scurve-ragged-1537", "gauss6-3k"])
+def test_degrees_of_reduced_precision_operators(name, prec):
+    # float64 points: the near tiles exist only in the evaluation precision and the
+    # degree products evaluate the float64 kernel on the fly (reading 6 of Alg. 1)
+    X, eps, op, H = build_pair(name, prec)
+    q, d, c = op.degrees()
+    oq, od, oc = DF.degrees(H.matvec, X.shape[0])
+    np.testing.assert_allclose(q, oq, rtol=1e-12)
+    np.testing.assert_allclose(d, od, rtol=1e-12)
+    np.testing.assert_allclose(c, oc, rtol=1e-12)
+
+
 # tile-format bounds on the relative error of one product: unit roundoff of the
 # tile format (values in (0, 1]) plus float32 rounding of the vectors and sums
 PREC_TOL = {"f32": 2e-6, "f16": 2e-3, "bf16": 1.5e-2}
