@@ -22,6 +22,7 @@ import time
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+sys.path.insert(0, os.path.dirname(HERE))   # tests/: the digest layout shared with the GPU tests
 
 import numpy as np  # noqa: E402
 
@@ -59,35 +60,12 @@ def golden(name: str) -> dict:
     }
 
 
-def structure_digests(H) -> dict:
-    """SHA-256 of each structure array in a fixed little-endian layout (tests compare the GPU's)."""
-    import hashlib
-
-    def sha(*arrays):
-        h = hashlib.sha256()
-        for a in arrays:
-            h.update(np.ascontiguousarray(a).astype(a.dtype.newbyteorder("<"), copy=False).tobytes())
-        return h.hexdigest()
-
-    idx, d2 = H.knn()
-    r, c, nr = H.ranks()
-    skel = [H.node(h)[0] for h in range(2, H.nnodes)]
-    return {
-        "perm": sha(H.perm().astype(np.int32)),
-        "knn_idx": sha(idx.astype(np.int32)),
-        "knn_d2": sha(d2.astype(np.float64)),
-        "near": sha(*[a.astype(np.int32) for a in H.near()]),
-        "far": sha(*[a.astype(np.int32) for a in H.far()]),
-        "ranks": sha(r[2:].astype(np.int32), c[2:].astype(np.int32), nr[2:].astype(np.int32)),
-        "skeletons": sha(*[s.astype(np.int32) for s in skel]),
-    }
-
-
 def structure(name: str) -> dict:
     cfg = synth.get_config(name)
     X, eps = synth.configs.make_inputs(cfg)
     t0 = time.time()
     H = HM.HMatrix(X, eps, cfg["m"], cfg["s"], cfg["tau"], cfg["k"], cfg["seed"], budget=cfg.get("budget", 0.05))
+    from structure_check import structure_digests
     dig = structure_digests(H)
     r, _, _ = H.ranks()
     return {"config": name, "n": X.shape[0], "eps": eps,

@@ -138,3 +138,32 @@ def check_product(u: np.ndarray, ref: np.ndarray, bound: np.ndarray, what: str =
     i = np.unravel_index(int(np.argmax(ratio)), ratio.shape)
     assert worst <= 1.0, f"{what}: entry {i} off by {err[i]:.3e} > bound {bound[i]:.3e}"
     return worst
+
+
+def structure_digests(op) -> dict:
+    """SHA-256 of each structure array of an operator (oracle or GPU: anything with
+    perm(), knn(), near(), far(), ranks() and node(h)), little-endian, in a fixed
+    layout: the tree permutation, neighbour indices and squared distances, the near
+    and far CSR lists, ranks | candidates | sampled rows per heap id from 2 on, and
+    the skeletons of heap ids 2, 3, ... concatenated."""
+    import hashlib
+
+    def sha(*arrays):
+        h = hashlib.sha256()
+        for a in arrays:
+            a = np.ascontiguousarray(a)
+            h.update(a.astype(a.dtype.newbyteorder("<"), copy=False).tobytes())
+        return h.hexdigest()
+
+    idx, d2 = op.knn()
+    r, c, nr = op.ranks()
+    nn = len(r)
+    return {
+        "perm": sha(np.asarray(op.perm(), np.int32)),
+        "knn_idx": sha(np.asarray(idx, np.int32)),
+        "knn_d2": sha(np.asarray(d2, np.float64)),
+        "near": sha(*[np.asarray(a, np.int32) for a in op.near()]),
+        "far": sha(*[np.asarray(a, np.int32) for a in op.far()]),
+        "ranks": sha(np.asarray(r[2:], np.int32), np.asarray(c[2:], np.int32), np.asarray(nr[2:], np.int32)),
+        "skeletons": sha(*[np.asarray(op.node(h)[0], np.int32) for h in range(2, nn)]),
+    }
