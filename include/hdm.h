@@ -215,18 +215,40 @@ hdm_status hdm_matvec_noalloc(hdm_op op, int normalised, const double *x, double
 /* ---- eigensolver (Alg. 1 eigendecomposition; Sec. 2.2 Lanczos) --------------
  * Leading r eigenpairs (largest algebraic) of S~ by Lanczos with full float64
  * reorthogonalisation.  block = 1: single-vector Lanczos, stops when every
- * pair i < r has |beta_j y_{j,i}| <= rel_resid_tol |theta_i|.  2 <= block <= 16:
+ * pair i < r has |beta_j y_{j,i}| <= rel_resid_tol |theta_i|; when the basis
+ * reaches max_basis vectors (r + 2 <= max_basis <= 512) before that, it is
+ * thick-restarted (Sec. 2.2, the implicit restart with exact shifts): the
+ * leading min(max_basis - 2, max(r + 1, (max_basis + r) / 2)) Ritz vectors and
+ * the next Lanczos vector become the new basis, up to 100 times.  2 <= block <= 16:
  * block Lanczos with that many vectors per step (one product with block
  * right-hand sides, block QR by shifted Cholesky QR, banded projected matrix
  * solved after Householder tridiagonalisation); pair i is accepted when
  * ||B_j y_i[last block entries]|| <= rel_resid_tol |theta_i|, and max_basis is
  * at most 512 (default min(n, 512), rounded down to a multiple of block).
  * Either stops with HDM_ENOCONV, evals/info filled, when the basis reaches
- * max_basis vectors; HDM_ENUMERIC if a residual block loses rank.
+ * max_basis vectors (block = 1: after the last restart); HDM_ENUMERIC if a
+ * residual block loses rank.  info->iters: steps taken (block steps for block > 1).
  * evals: host, r entries, descending.  evecs: device float64 n x r (column-major,
  * phi: unit 2-norm, largest-magnitude entry positive) or NULL. */
 hdm_status hdm_eigs(hdm_op op, int32_t r, double rel_resid_tol, int32_t block, int32_t max_basis, uint64_t seed,
                     double *evals, double *evecs, hdm_eig_info_t *info, void *stream);
+
+/* ---- diffusion-map outputs (Alg. 1, last steps) -------------------------------
+ * From the leading eigenpairs (lambda_k, phi_k) of S~ (hdm_eigs: evals on the
+ * host, phi on the device, n x r column-major, original order):
+ *  - psi_k = phi_k / sqrt(d), the right eigenvectors of the Markov matrix
+ *    P = D^-1 Q^-1 K~ Q^-1 (the eigenvectors of Alg. 1's eigendecomposition step),
+ *    d the alpha = 1 degrees of the operator;
+ *  - evals_t[k] = lambda_k^t, the eigenvalues of P^t after t steps of the walk;
+ *  - coords_k = lambda_k^t psi_k, the diffusion map at time t;
+ *  - dim_t = max{l : |lambda_l|^t > delta |lambda_1|^t} (l from 1; 0 if none), the
+ *    lower dimension of Alg. 1 (its printed inequality reads "<"; the intended
+ *    reading, the largest l whose weight still exceeds delta times the first, is ">").
+ * t >= 0 (an integer number of steps), delta >= 0.  psi, coords: device n x r or
+ * NULL; evals_t: host r or NULL; dim_t: host or NULL.  phi may be NULL when psi and
+ * coords are.  Synchronises the stream when it writes device outputs. */
+hdm_status hdm_diffusion_map(hdm_op op, int32_t r, const double *evals, const double *phi, int32_t t, double delta,
+                             double *psi, double *coords, double *evals_t, int32_t *dim_t, void *stream);
 
 /* ---- serving --------------------------------------------------------------- */
 typedef struct {

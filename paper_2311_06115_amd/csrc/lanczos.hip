@@ -827,6 +827,46 @@ __global__ void __launch_bounds__(1024) k_ormtr(const double* A, int lda, const 
     }
 }
 
+// ---- thick restart of the single-vector iteration ---------------------------------
+// The projected matrix T = V^T S~ V after a restart with k kept Ritz pairs is the
+// diagonal of their Ritz values, coupled to the first new Lanczos vector by
+// s_i = beta_m y_i[m - 1] (row and column k), followed by the tridiagonal of the
+// steps since (Wu and Simon, thick-restart Lanczos, 2000; the exact-shift case of
+// the implicitly restarted Lanczos method).
+__global__ void k_thick_head(double* T, int ldt, int keep, int m_old, const double* theta, const double* Y,
+                             const double* beta, int jlast) {
+    // T is cleared by the caller; one thread per kept pair
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= keep) return;
+    const double s = beta[jlast] * Y[static_cast<int64_t>(i) * m_old + (m_old - 1)];
+    T[static_cast<int64_t>(i) * ldt + i] = theta[i];
+    T[static_cast<int64_t>(i) * ldt + keep] = s;
+    T[static_cast<int64_t>(keep) * ldt + i] = s;
+}
+
+// the tridiagonal tail of T from the Lanczos coefficients of steps k .. m - 1
+__global__ void k_thick_tail(double* T, int ldt, int k, int m, const double* alpha, const double* beta) {
+    const int i = k + blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    T[static_cast<int64_t>(i) * ldt + i] = alpha[i];
+    if (i + 1 < m) {
+        T[static_cast<int64_t>(i) * ldt + i + 1] = beta[i];
+        T[static_cast<int64_t>(i + 1) * ldt + i] = beta[i];
+    }
+}
+
+// residual bound of Ritz pair i of T (eigenvector row i of Y, m entries): |beta_{m-1} y_i[m - 1]|
+__global__ void k_thick_bounds(const double* Y, int m, const double* beta, int jlast, int r, double* bound) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= r) return;
+    bound[i] = fabs(beta[jlast] * Y[static_cast<int64_t>(i) * m + (m - 1)]);
+}
+
+__global__ void k_fill0(double* p, int64_t n) {
+    const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    if (i < n) p[i] = 0.0;
+}
+
 // residual bound of Ritz pair k: || B_j Z[k][m-b .. m) ||
 __global__ void k_block_bounds(const double* Z, int m, int b, const double* Bj, int r, double* bound) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -864,9 +904,11 @@ void LanczosRun::start(Op& o, int r_, double tol_, int max_basis_, uint64_t seed
     np.alloc(nb);
     alpha.alloc(max_basis);
     beta.alloc(max_basis);
-    theta.alloc(r);
-    bound.alloc(r);
-    Y.alloc(static_cast<size_t>(r) * max_basis);
+    theta.alloc(max_basis);
+    bound.alloc(max_basis);
+    Y.alloc(static_cast<size_t>(max_basis) * max_basis);
+    restarts = keep = 0;
+    restarted = false;
     counters.alloc(2);
     HDM_HIP(hipMemsetAsync(counters.get(), 0, counters.bytes(), s));
     h_theta.assign(r, 0.0);
@@ -905,7 +947,9 @@ bool LanczosRun::after_product(hipStream_t s) {
     // Each check costs a tridiagonal eigensolve and a host synchronisation; r
     // pairs rarely meet the tolerance before 2r steps, so checking starts there.
     if ((m >= 2 * r && (m % check_every) == 0) || (last && m >= r)) {
-        {
+        if (restarted) {
+            solve_projected(r, s);
+        } else {
             KernelEvents ev(op->ctx, HDM_PHASE_TRIDIAG);
             launch_tridiag(alpha.get(), beta.get(), m, r, theta.get(), Y.get(), bound.get(), s, ev.start, ev.stop);
         }
@@ -920,14 +964,70 @@ bool LanczosRun::after_product(hipStream_t s) {
             return true;
         }
     }
-    if (last) {
-        finished = true;
-        return true;
-    }
     hipLaunchKernelGGL(k_next, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, s, y.get(), beta.get(), j,
                        V.get() + static_cast<int64_t>(j + 1) * n, n);
+    if (last) {
+        if (restarts >= max_restarts || max_basis > kMaxBlockBasis || max_basis < r + 2) {
+            finished = true;
+            return true;
+        }
+        restart(s);
+        return false;
+    }
     ++j;
     return false;
+}
+
+// Ritz pairs of the (restarted) projected matrix: its tail from the latest
+// Lanczos coefficients, Householder tridiagonalisation, the tridiagonal
+// eigensolve for the nvec largest, back-transformation, residual bounds
+void LanczosRun::solve_projected(int nvec, hipStream_t s) {
+    const int ldt = max_basis + 1;
+    hipLaunchKernelGGL(k_thick_tail, dim3(ceil_div(m - keep, kBlock)), dim3(kBlock), 0, s, T.get(), ldt, keep, m,
+                       alpha.get(), beta.get());
+    KernelEvents ev(op->ctx, HDM_PHASE_TRIDIAG);
+    hipLaunchKernelGGL(k_sytrd, dim3(1), dim3(1024), 0, s, T.get(), ldt, m, A.get(), ldt, dd.get(), ee.get(), tau.get());
+    launch_tridiag(dd.get(), ee.get(), m, nvec, theta.get(), Y.get(), bound.get(), s, ev.start, nullptr);
+    hipLaunchKernelGGL(k_ormtr, dim3(1), dim3(1024), 0, s, A.get(), ldt, tau.get(), m, Y.get(), nvec);
+    hipExtLaunchKernelGGL(k_thick_bounds, dim3(ceil_div(nvec, 64)), dim3(64), 0, s, nullptr, ev.stop, 0, Y.get(), m,
+                          beta.get(), m - 1, nvec, bound.get());
+}
+
+// Thick restart at a full basis of m = max_basis vectors: keep the leading
+// `keep` Ritz vectors V Y_keep and the next Lanczos vector v_{m+1} (already
+// formed in column m), and restart the projected matrix from their Ritz values
+// and couplings.  The iteration then continues from column keep.
+void LanczosRun::restart(hipStream_t s) {
+    const int ldt = max_basis + 1;
+    if (!restarted) {
+        T.alloc(static_cast<size_t>(ldt) * ldt);
+        A.alloc(static_cast<size_t>(ldt) * ldt);
+        dd.alloc(ldt);
+        ee.alloc(ldt);
+        tau.alloc(ldt);
+        // the basis so far is plain Lanczos: its projected matrix is the tridiagonal
+        hipLaunchKernelGGL(k_fill0, dim3(ceil_div(int64_t(ldt) * ldt, kBlock)), dim3(kBlock), 0, s, T.get(),
+                           int64_t(ldt) * ldt);
+        keep = 0;
+    }
+    // keep about half of the free space beyond the r wanted pairs, at most max_basis - 2
+    const int kp = std::min(max_basis - 2, std::max(r + 1, (max_basis + r) / 2));
+    solve_projected(kp, s);
+    tmp.alloc(static_cast<size_t>(n) * kp);
+    hipLaunchKernelGGL(k_ritz, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, s, V.get(), n, m, Y.get(), kp, tmp.get(), n);
+    HDM_HIP(hipMemcpyAsync(V.get(), tmp.get(), sizeof(double) * n * kp, hipMemcpyDeviceToDevice, s));
+    HDM_HIP(hipMemcpyAsync(V.get() + static_cast<int64_t>(kp) * n, V.get() + static_cast<int64_t>(m) * n,
+                           sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(k_fill0, dim3(ceil_div(int64_t(ldt) * ldt, kBlock)), dim3(kBlock), 0, s, T.get(),
+                       int64_t(ldt) * ldt);
+    hipLaunchKernelGGL(k_thick_head, dim3(ceil_div(kp, 64)), dim3(64), 0, s, T.get(), ldt, kp, m, theta.get(), Y.get(),
+                       beta.get(), m - 1);
+    check_launch("thick restart");
+    keep = kp;
+    restarted = true;
+    ++restarts;
+    j = kp;
+    m = kp;
 }
 
 hdm_status LanczosRun::result(double* evals, double* evecs, hdm_eig_info_t* info, hipStream_t s) {
@@ -946,7 +1046,7 @@ hdm_status LanczosRun::result(double* evals, double* evecs, hdm_eig_info_t* info
         HDM_HIP(hipStreamSynchronize(s));
     }
     if (info) {
-        info->iters = m;
+        info->iters = matvecs;   // steps taken, restarts included
         info->matvecs = matvecs;
         info->converged = converged ? 1 : 0;
         info->max_rel_resid = worst;
@@ -1077,17 +1177,72 @@ static hdm_status block_lanczos_eigs(Op& op, int r, double tol, int b, int max_b
     return converged ? HDM_OK : HDM_ENOCONV;
 }
 
+// restarts of one single-vector solve before it ends with HDM_ENOCONV
+constexpr int kMaxRestarts = 100;
+
 hdm_status lanczos_eigs(Op& op, int r, double tol, int block, int max_basis, uint64_t seed, double* evals,
                         double* evecs, hdm_eig_info_t* info, hipStream_t s) {
     HDM_CHECK(block >= 1, HDM_EINVAL, "block must be >= 1");
     if (block > 1) return block_lanczos_eigs(op, r, tol, block, max_basis, seed, evals, evecs, info, s);
     LanczosRun run;
     run.start(op, r, tol, max_basis, seed, s);
+    run.max_restarts = kMaxRestarts;
     while (!run.finished) {
         apply(op, 1, false, run.current(), run.output(), 1, s);
         run.after_product(s);
     }
     return run.result(evals, evecs, info, s);
+}
+
+// ---- diffusion-map outputs (Alg. 1, last steps) ---------------------------------
+// psi_k = phi_k / sqrt(d) (right eigenvectors of the Markov matrix from the
+// eigenvectors of its symmetric conjugate) and the coordinates lambda_k^t psi_k,
+// one thread per point (tree position p, original index perm[p])
+struct PowT {
+    double v[64];
+};
+__global__ void k_diffusion_coords(const double* phi, const double* d_tree, const int32_t* perm, int64_t n, int r,
+                                   PowT lt, double* psi, double* coords) {
+    const int64_t p = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    if (p >= n) return;
+    const int64_t i = perm[p];
+    const double s = 1.0 / sqrt(d_tree[p]);
+    for (int k = 0; k < r; ++k) {
+        const double v = phi[k * n + i] * s;
+        if (psi) psi[k * n + i] = v;
+        if (coords) coords[k * n + i] = lt.v[k] * v;
+    }
+}
+
+hdm_status diffusion_map(Op& op, int r, const double* evals, const double* phi, int t, double delta, double* psi,
+                         double* coords, double* evals_t, int32_t* dim_t, hipStream_t s) {
+    HDM_CHECK(r >= 1 && r <= 64 && r <= op.n, HDM_EINVAL, "r must be in [1, min(64, n)]");
+    HDM_CHECK(t >= 0, HDM_EINVAL, "t (random-walk steps) must be >= 0");
+    HDM_CHECK(delta >= 0.0 && std::isfinite(delta), HDM_EINVAL, "delta must be finite and >= 0");
+    HDM_CHECK((psi || coords) ? phi != nullptr : true, HDM_EINVAL, "phi is needed for psi or the coordinates");
+    PowT lt{};
+    for (int k = 0; k < r; ++k) {
+        HDM_CHECK(std::isfinite(evals[k]), HDM_EINVAL, "eigenvalues must be finite");
+        double p = 1.0;
+        for (int j = 0; j < t; ++j) p *= evals[k];   // lambda^t of P^t, t steps of the walk
+        lt.v[k] = p;
+    }
+    if (evals_t)
+        for (int k = 0; k < r; ++k) evals_t[k] = lt.v[k];
+    if (dim_t) {
+        // max{l : |lambda_l|^t > delta |lambda_1|^t}, l counted from 1 (0 when none)
+        int best = 0;
+        for (int k = 0; k < r; ++k)
+            if (std::fabs(lt.v[k]) > delta * std::fabs(lt.v[0])) best = k + 1;
+        *dim_t = best;
+    }
+    if (psi || coords) {
+        hipLaunchKernelGGL(k_diffusion_coords, dim3(ceil_div(op.n, kBlock)), dim3(kBlock), 0, s, phi, op.d.get(),
+                           op.perm.get(), op.n, r, lt, psi, coords);
+        check_launch("diffusion coordinates");
+        HDM_HIP(hipStreamSynchronize(s));
+    }
+    return HDM_OK;
 }
 
 }  // namespace hdm

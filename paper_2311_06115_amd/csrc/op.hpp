@@ -322,6 +322,15 @@ struct LanczosRun {
     int j = 0, m = 0, matvecs = 0;
     bool converged = false, finished = false;
     std::chrono::steady_clock::time_point t0;
+    // thick restart (Sec. 2.2, implicitly restarted Lanczos with exact shifts):
+    // when the basis is full and the pairs have not converged, the leading `keep`
+    // Ritz vectors and the last Lanczos vector become the new basis (at most
+    // max_restarts times; 0 = no restarts, the basis limit ends the solve)
+    int max_restarts = 0, restarts = 0, keep = 0;
+    bool restarted = false;                    // the projected matrix is no longer tridiagonal
+    DevBuf<double> T, A, dd, ee, tau, tmp;     // projected matrix, its reduction, the new basis
+    void restart(hipStream_t s);
+    void solve_projected(int nvec, hipStream_t s);   // Ritz pairs of the restarted projected matrix
     void start(Op& op, int r, double tol, int max_basis, uint64_t seed, hipStream_t s);
     const double* current() const { return V.get() + static_cast<int64_t>(j) * n; }
     double* output() { return y.get(); }
@@ -382,6 +391,9 @@ void apply_noalloc(Op& op, int normalised, const double* x, double* y, int nrhs,
 // eigensolver (lanczos.hip)
 hdm_status lanczos_eigs(Op& op, int r, double tol, int block, int max_basis, uint64_t seed, double* evals,
                         double* evecs, hdm_eig_info_t* info, hipStream_t s);
+// diffusion-map outputs from the eigenpairs of S~ (lanczos.hip)
+hdm_status diffusion_map(Op& op, int r, const double* evals, const double* phi, int t, double delta, double* psi,
+                         double* coords, double* evals_t, int32_t* dim_t, hipStream_t s);
 
 }  // namespace hdm
 
