@@ -466,4 +466,13 @@ hdm_status hdm_eigs(hdm_op op, int32_t r, double rel_resid_tol, int32_t block, i
     });
 }
 
+hdm_status hdm_diffusion_map(hdm_op op, int32_t r, const double* evals, const double* phi, int32_t t, double delta,
+                             double* psi, double* coords, double* evals_t, int32_t* dim_t, void* stream) {
+    return guarded([&] {
+        HDM_CHECK(op && evals, HDM_EINVAL, "NULL argument");
+        set_device(op->ctx->device);
+        return hdm::diffusion_map(*op, r, evals, phi, t, delta, psi, coords, evals_t, dim_t, as_stream(stream));
+    });
+}
+
 }  // extern "C"

@@ -118,6 +118,7 @@ def lib():
         "hdm_matvec": (st, [vp, C.c_int, vp, vp, i32, vp]),
         "hdm_matvec_noalloc": (st, [vp, C.c_int, vp, vp, i32, vp]),
         "hdm_eigs": (st, [vp, i32, f64, i32, i32, C.c_uint64, vp, vp, C.POINTER(EigInfo), vp]),
+        "hdm_diffusion_map": (st, [vp, i32, vp, vp, i32, f64, vp, vp, vp, C.POINTER(i32), vp]),
         "hdm_server_create": (st, [vp, C.POINTER(ServerCfg), C.POINTER(vp)]),
         "hdm_submit": (st, [vp, C.POINTER(Request), C.POINTER(C.c_uint64)]),
         "hdm_poll": (st, [vp, C.c_uint64, C.POINTER(Result)]),
@@ -338,6 +339,38 @@ class Operator:
         if st not in (0, 4):
             check(st)
         return evals, (vecs.t() if vectors else None), info, st
+
+
+def diffusion_map(op, evals, vecs, t=1, delta=0.1):
+    """hdm_diffusion_map: psi = phi / sqrt(d), lambda^t, the coordinates lambda^t psi and
+    d(t), from the eigenpairs hdm_eigs returned (evals numpy [r], vecs cuda [n, r])."""
+    torch = op.torch
+    ev = np.ascontiguousarray(evals, dtype=np.float64)
+    r = ev.shape[0]
+    phi = vecs.t().contiguous()   # r x n: column-major n x r
+    psi = torch.empty_like(phi)
+    coords = torch.empty_like(phi)
+    lt = np.zeros(r, np.float64)
+    dim = C.c_int32()
+    check(lib().hdm_diffusion_map(op.h, r, _ptr(ev), C.c_void_p(phi.data_ptr()), int(t), float(delta),
+                                  C.c_void_p(psi.data_ptr()), C.c_void_p(coords.data_ptr()), _ptr(lt), C.byref(dim),
+                                  _stream(torch)))
+    return psi.t(), coords.t(), lt, dim.value
+
+
+def linear_operator(op, normalised=True):
+    """A scipy LinearOperator whose products run on the GPU through hdm_matvec (the
+    paper's integration: scipy's eigsh drives the compressed operator's matvec).
+    Host float64 vectors in and out; only the copies and the call are done here."""
+    import scipy.sparse.linalg as spla
+    torch = op.torch
+
+    def mv(x):
+        X = np.asarray(x, dtype=np.float64).reshape(op.n, -1)
+        Y = op.matvec(torch.from_numpy(np.ascontiguousarray(X)).cuda(), normalised=normalised).cpu().numpy()
+        return Y.reshape(np.shape(x)) if np.ndim(x) == 1 else Y
+
+    return spla.LinearOperator((op.n, op.n), matvec=mv, matmat=mv, rmatvec=mv, dtype=np.float64)
 
 
 class Server:
