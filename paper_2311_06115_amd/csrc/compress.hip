@@ -1779,8 +1779,9 @@ __global__ void __launch_bounds__(kBlock) k_near_direct_bf16(const NearPair* pai
 // owning rows row0 + 2 l and row0 + 2 l + 1 of each 128-row pass.  The item's
 // (at most 64) column points and weights are loaded once, one per lane, and
 // broadcast from their lane column by column; part[part_off + row] = sum over the
-// columns in increasing order of K(row, col) w[col], K as the oracle evaluates it
-// (float64, one rounding per operation).
+// columns in increasing order of K(row, col) w[col], K in float64 with one
+// rounding per operation (the exponent's argument d2 times 1/eps: within an ulp
+// of the oracle's d2 / eps).
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_near_otf(const NearItem* items, int64_t nitems, const int32_t* perm, Pts P,
                                                     const double* w, double* part) {
@@ -1790,7 +1791,8 @@ __global__ void __launch_bounds__(kBlock) k_near_otf(const NearItem* items, int6
     const int lane = threadIdx.x % kWave;
     double xc[D];
     load_point<D>(P, perm[I.col_pos + min(lane, I.ncols - 1)], xc);
-    const double wl = w[I.col_pos + min(lane, I.ncols - 1)];
+    const double wl = w ? w[I.col_pos + min(lane, I.ncols - 1)] : 1.0;   // w = nullptr: all ones
+    const double ie = 1.0 / P.eps;
     const int rend = min(I.ld, I.row0 + I.nrows);
     for (int r0 = I.row0; r0 < rend; r0 += 2 * kWave) {
         const int row = r0 + 2 * lane;
@@ -1804,8 +1806,8 @@ __global__ void __launch_bounds__(kBlock) k_near_otf(const NearItem* items, int6
 #pragma unroll
             for (int d = 0; d < D; ++d) y[d] = lane_value(xc[d], j);
             const double wj = lane_value(wl, j);
-            const double k0 = exp(-(sqd_regs<D>(x0, y) / P.eps));
-            const double k1 = exp(-(sqd_regs<D>(x1, y) / P.eps));
+            const double k0 = exp(-(sqd_regs<D>(x0, y) * ie));
+            const double k1 = exp(-(sqd_regs<D>(x1, y) * ie));
             a0 = a0 + (v0 ? k0 : 0.0) * wj;
             a1 = a1 + (v1 ? k1 : 0.0) * wj;
         }
@@ -2468,6 +2470,11 @@ static void build_far_tiles(Op& op, const Geo& G, hipStream_t s, DevBuf<char>& k
     }
 }
 
+void near_field_ones(Op& op, hipStream_t s) {
+    op.part_ones.alloc(static_cast<size_t>(std::max<int64_t>(op.part_elems, 1)));
+    near_field_otf(op, nullptr, op.part_ones.get(), s);
+}
+
 void near_field_otf(const Op& op, const double* w_tree, double* part, hipStream_t s) {
     HDM_CHECK(op.near_direct && op.xf.get() && op.dim <= kDirectDim, HDM_EINTERNAL,
               "on-the-fly near field needs float64 points of few coordinates");
@@ -2641,6 +2648,7 @@ void compress_operator(Op& op, const void* X, int x_on_device, hipStream_t s) {
     // runs on through the far tiles and the degrees, and finish_operator waits
     build_near_tiles(op, G, side);
     build_near_plan(op, side);
+    if (op.near_direct) near_field_ones(op, side);   // the near part of K~ 1, beside the skeletonisation
     HDM_HIP(hipEventRecord(op.lane.ready, side));
     convert_near_tiles(op, side);
     skeletonize_finish(op, s, skr);

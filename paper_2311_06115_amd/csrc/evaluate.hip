@@ -264,6 +264,40 @@ __global__ void k_n2s_up(Batch b) {
     if (threadIdx.x % kWave == 0) skw[D.skoff[h] + T.i] = acc;
 }
 
+// The same for several right-hand sides: each lane keeps one partial sum per
+// column and every composite element is loaded once (columns past nrhs repeat
+// the last one so that the loads issue together; only the stores are guarded)
+template <typename V>
+__global__ void k_n2s_up_m(Batch b) {
+    const int64_t u = blockIdx.x * static_cast<int64_t>(blockDim.x / kWave) + threadIdx.x / kWave;
+    if (u >= b.pre[b.nops]) return;
+    const int o = batch_op(b, u);
+    const OpDev& D = *b.op[o];
+    const RowTask T = D.rows[D.row_count[D.depth] + (u - b.pre[o])];
+    const int64_t h = T.h;
+    const int lvl = 63 - __builtin_clzll(static_cast<unsigned long long>(h));
+    const LeafRun lr = leaf_run(D.skoff, D.rank, D.depth, h, lvl);
+    const V* row = static_cast<const V*>(D.comp) + D.coff[h] + static_cast<int64_t>(T.i) * lr.nlk;
+    V* skw = static_cast<V*>(D.skw);
+    const V* in = skw + lr.base;
+    const int lane = threadIdx.x % kWave;
+    const int last = b.nrhs - 1;
+    V acc[kMaxRhs];
+#pragma unroll
+    for (int c = 0; c < kMaxRhs; ++c) acc[c] = 0;
+    for (int j = lane; j < lr.nlk; j += kWave) {
+        const V p = row[j];
+#pragma unroll
+        for (int c = 0; c < kMaxRhs; ++c) acc[c] += p * in[min(c, last) * D.ldsk + j];
+    }
+#pragma unroll
+    for (int c = 0; c < kMaxRhs; ++c) {
+        if (c >= b.nrhs) break;
+        const V t = wave_sum(acc[c]);
+        if (lane == 0) skw[c * D.ldsk + D.skoff[h] + T.i] = t;
+    }
+}
+
 // ---- L2L: stream the near tiles; one wave per work item ---------------------
 // Lane l owns RPL consecutive rows (16 bytes of tile per lane per column) of
 // each 64*RPL-row pass over the item's rows; the item's columns are consecutive
@@ -1485,8 +1519,14 @@ static void apply_t(const ApplyReq* reqs, int nops, bool f64, int normalised, in
         b.flip = static_cast<int>(reqs[0].op->near_calls++ & 1u);
         const int64_t grid = ceil_div(tot, wpb) + b.up;
         if (otf) {
-            const Op& o0 = *reqs[0].op;
-            near_field_otf(o0, reinterpret_cast<const double*>(o0.w_tree.get()), reinterpret_cast<double*>(o0.part.get()), s);
+            Op& o0 = *reqs[0].op;
+            if (o0.near_ones_next && o0.part_ones.n) {   // K~ 1: its near field is already computed
+                HDM_HIP(hipMemcpyAsync(o0.part.get(), o0.part_ones.get(), o0.part_ones.bytes(), hipMemcpyDeviceToDevice, s));
+                o0.near_ones_next = false;
+            } else {
+                near_field_otf(o0, reinterpret_cast<const double*>(o0.w_tree.get()), reinterpret_cast<double*>(o0.part.get()),
+                               s);
+            }
             return;
         }
         KernelEvents ev(cx, HDM_PHASE_L2L);
@@ -1536,13 +1576,16 @@ static void apply_t(const ApplyReq* reqs, int nops, bool f64, int normalised, in
                     hipLaunchKernelGGL((k_n2s<V, TP>), dim3(ceil_div(tot, wpb)), dim3(kBlock), 0, ts, b);
             };
             if (!fuse_up) level_launch(0, true);
-            if (!multi) {
+            {   // every level above the leaves in one launch through the composites
                 const int64_t tot = prefix([](const Op& op, int) {
                     return op.ncomp > 0 ? op.row_total - op.row_count[op.depth] : int64_t(0);
                 });
-                if (tot > 0) hipLaunchKernelGGL((k_n2s_up<V>), dim3(ceil_div(tot, wpb)), dim3(kBlock), 0, ts, b);
+                if (tot > 0 && multi)
+                    hipLaunchKernelGGL((k_n2s_up_m<V>), dim3(ceil_div(tot, wpb)), dim3(kBlock), 0, ts, b);
+                else if (tot > 0)
+                    hipLaunchKernelGGL((k_n2s_up<V>), dim3(ceil_div(tot, wpb)), dim3(kBlock), 0, ts, b);
             }
-            for (int k = 1; k < maxdepth; ++k) level_launch(k, multi);
+            for (int k = 1; k < maxdepth; ++k) level_launch(k, false);   // operators without composites
         }
         {
             const int64_t tot = prefix([](const Op& op, int) { return op.row_total; });
@@ -1728,10 +1771,19 @@ static void build_product_graph(Op& op, bool f64, int normalised, int nrhs, Prod
         }
         comb_deps = {last};
     } else if (op.nskel > 0) {
-        // upward pass, leaves first, one node per level, then the far field
+        // upward pass, leaves first, then the levels above through the composites
+        // (one launch) or one launch per level, then the far field (as eager)
         hipGraphNode_t last = G.prep;
         for (int lvl = op.depth; lvl >= 1; --lvl) {
             if (op.row_count[lvl] == 0) continue;
+            if (lvl < op.depth && op.ncomp > 0) {
+                Batch bu = base;
+                bu.pre[1] = op.row_total - op.row_count[op.depth];
+                if (bu.pre[1] > 0)
+                    last = kernel(multi ? reinterpret_cast<void*>(&k_n2s_up_m<V>) : reinterpret_cast<void*>(&k_n2s_up<V>),
+                                  dim3(ceil_div(bu.pre[1], wpb)), bu, {last}, nullptr);
+                break;
+            }
             Batch bn = base;
             bn.arg[0] = lvl;
             bn.pre[1] = op.row_count[lvl];
@@ -1944,7 +1996,9 @@ void normalise_degrees(Op& op, hipStream_t s) {
     op.d.alloc(n);
     op.c.alloc(n);
     hipLaunchKernelGGL(k_fill, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, s, ones.get(), n, 1.0);
+    op.near_ones_next = op.part_ones.n > 0;   // the product of K~ with ones reuses the near field made early
     apply(op, 0, true, ones.get(), qo.get(), 1, s);
+    op.near_ones_next = false;
     hipLaunchKernelGGL(k_deg1, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, s, qo.get(), op.perm.get(), n, op.q.get(),
                        xinv.get(), bad.get());
     apply(op, 0, true, xinv.get(), kq.get(), 1, s);
@@ -2138,6 +2192,7 @@ void finish_operator(Op& op, hipStream_t s) {
     if (op.lane.side) HDM_HIP(hipStreamSynchronize(op.lane.side));
     HDM_HIP(hipStreamSynchronize(s));
     op.near_pairs.release();
+    op.part_ones.release();
     op.build_keep.reset();
     op.conv_keep.reset();
     if (!(op.prm.near_prec == HDM_F64 && op.prm.far_prec == HDM_F64)) {

@@ -883,6 +883,10 @@ __global__ void k_block_bounds(const double* Z, int m, int b, const double* Bj, 
 
 }  // namespace
 
+// restarts of one single-vector solve before it ends with HDM_ENOCONV (the
+// standalone solve and the serving loop alike, so their results agree)
+constexpr int kMaxRestarts = 100;
+
 void LanczosRun::start(Op& o, int r_, double tol_, int max_basis_, uint64_t seed_, hipStream_t s) {
     op = &o;
     n = o.n;
@@ -908,6 +912,7 @@ void LanczosRun::start(Op& o, int r_, double tol_, int max_basis_, uint64_t seed
     bound.alloc(max_basis);
     Y.alloc(static_cast<size_t>(max_basis) * max_basis);
     restarts = keep = 0;
+    max_restarts = kMaxRestarts;
     restarted = false;
     counters.alloc(2);
     HDM_HIP(hipMemsetAsync(counters.get(), 0, counters.bytes(), s));
@@ -1177,16 +1182,12 @@ static hdm_status block_lanczos_eigs(Op& op, int r, double tol, int b, int max_b
     return converged ? HDM_OK : HDM_ENOCONV;
 }
 
-// restarts of one single-vector solve before it ends with HDM_ENOCONV
-constexpr int kMaxRestarts = 100;
-
 hdm_status lanczos_eigs(Op& op, int r, double tol, int block, int max_basis, uint64_t seed, double* evals,
                         double* evecs, hdm_eig_info_t* info, hipStream_t s) {
     HDM_CHECK(block >= 1, HDM_EINVAL, "block must be >= 1");
     if (block > 1) return block_lanczos_eigs(op, r, tol, block, max_basis, seed, evals, evecs, info, s);
     LanczosRun run;
     run.start(op, r, tol, max_basis, seed, s);
-    run.max_restarts = kMaxRestarts;
     while (!run.finished) {
         apply(op, 1, false, run.current(), run.output(), 1, s);
         run.after_product(s);

@@ -250,6 +250,10 @@ struct Op {
     // near tiles written directly in the evaluation precision (no float64 copy);
     // the float64 degree products evaluate the kernel on the fly (compress.hip)
     bool near_direct = false;
+    // with near_direct: the near field of K~ 1 (the first degree product), computed
+    // on the side stream while the skeletons are found, and taken by that product
+    DevBuf<double> part_ones;
+    bool near_ones_next = false;
     struct ConvKeep {
         std::vector<DevBuf<int64_t>> d64;
         std::vector<DevBuf<int32_t>> d32;
@@ -355,6 +359,8 @@ void compress_operator(Op& op, const void* X, int x_on_device, hipStream_t s);
 // points (operators with near_direct): part[item] = K(rows, cols) w over the
 // plain work items, w and part the product's float64 workspaces
 void near_field_otf(const Op& op, const double* w_tree, double* part, hipStream_t s);
+// the same with w = 1 into op.part_ones (launched on the side stream after the near plan)
+void near_field_ones(Op& op, hipStream_t s);
 // offsets of the packed half-precision near tiles (evaluate.hip)
 void packed_near_offsets(Op& op);
 // evaluation (evaluate.hip)
