@@ -1394,7 +1394,9 @@ void build_eval_plan(Op& op, hipStream_t s) {
                 inner_p += static_cast<int64_t>(op.rank[h]) * op.ncand[h];
             }
         }
-        if (nested && op.depth >= 2 && comp <= 2 * inner_p + 262144) op.ncomp = comp;
+        // (a few MB at the S-curve sizes; the MNIST-shaped operator, every rank at
+        // the cap, would need 7x its P and keeps the per-level launches)
+        if (nested && op.depth >= 2 && comp <= 4 * inner_p + (int64_t(1) << 20)) op.ncomp = comp;
     }
     check_eval_plan(op, tasks);
     // the skeleton-dependent arrays in one allocation and one copy
