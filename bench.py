@@ -163,7 +163,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=10.0, help="length of each serving stream (0: skip)")
     ap.add_argument("--serve-pool", type=int, default=8, help="distinct request instances the stream cycles through")
     ap.add_argument("--thrash-mib", type=int, default=0,
-                    help="also time the standalone product with a write of this many MiB between products")
+                    help="also time the standalone product with this many MiB evicted from the caches between "
+                         "products (once by a write, once by a read)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path",
@@ -237,21 +238,28 @@ def main():
     mv_s = e0.elapsed_time(e1) / 1e3 / args.matvec_reps
     thrash = None
     if args.thrash_mib > 0:
-        # a write of M MiB between products evicts the last-level cache (256 MiB)
+        # M MiB touched between products evict the last-level cache (256 MiB): by a
+        # write (its dirty lines are written back while the product runs) and by a
+        # read (clean eviction: the product starts from a cold cache)
         junk = torch.empty(args.thrash_mib << 17, dtype=torch.float64, device=dev)
-        times = []
-        for i in range(args.matvec_reps):
-            junk.fill_(float(i))
-            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            a.record()
-            op.matvec(x, normalised=True)
-            b.record()
-            torch.cuda.synchronize()
-            times.append(a.elapsed_time(b) / 1e3)
-        t_med = float(np.median(times))
-        thrash = {"mib_written_between_products": args.thrash_mib, "us_per_call_median": t_med * 1e6,
-                  "GBps": st_op.algo_bytes_matvec / t_med / 1e9,
-                  "frac_hbm": st_op.algo_bytes_matvec / t_med / 1e9 / HBM_PEAK_GBS}
+        junk.fill_(1.0)
+        thrash = {"mib_between_products": args.thrash_mib}
+        for mode in ("write", "read"):
+            times = []
+            for i in range(args.matvec_reps):
+                if mode == "write":
+                    junk.fill_(float(i))
+                else:
+                    junk.sum()
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                op.matvec(x, normalised=True)
+                b.record()
+                torch.cuda.synchronize()
+                times.append(a.elapsed_time(b) / 1e3)
+            t_med = float(np.median(times))
+            thrash[mode] = {"us_per_call_median": t_med * 1e6, "GBps": st_op.algo_bytes_matvec / t_med / 1e9,
+                            "frac_hbm": st_op.algo_bytes_matvec / t_med / 1e9 / HBM_PEAK_GBS}
         del junk
     ev_acc = None
     gold = os.path.join(ROOT, "tests", "golden", f"eigs_{args.workload}.json")

@@ -840,7 +840,10 @@ typedef float f4_t __attribute__((ext_vector_type(4)));
 constexpr int kMmaRowTiles = 8;   // 16-row tiles per work item
 
 // stage w = c * x (tree order, float32) and its half-precision hi/lo pair per
-// leaf; one workgroup per leaf
+// leaf; one workgroup per leaf.  The halves of padded position p and column c
+// sit at (p / 8) 8 nrhs + 8 c + p % 8: the 8 consecutive points of one column
+// that a matrix-core lane takes are 16 contiguous bytes, and those of the
+// nrhs columns follow each other.
 __global__ void __launch_bounds__(kBlock) k_prep_mma(Batch b) {
     __shared__ uint32_t smax[kMaxRhs];
     const int64_t u = blockIdx.x;
@@ -878,14 +881,66 @@ __global__ void __launch_bounds__(kBlock) k_prep_mma(Batch b) {
             h = static_cast<float>(vh);
             l = v - h;
         }
-        hi[c * D.ldw + lp.wpad + p] = static_cast<_Float16>(h);
-        lo[c * D.ldw + lp.wpad + p] = static_cast<_Float16>(l);
+        const int64_t at = (lp.wpad + (p & ~7)) * nrhs + c * 8 + (p & 7);
+        hi[at] = static_cast<_Float16>(h);
+        lo[at] = static_cast<_Float16>(l);
         if (p == 0) D.wsc[a * kMaxRhs + c] = ldexpf(1.0f, ex - 13);
     }
+    if (a == 0 && threadIdx.x < 8) hi[2 * kMaxRhs * D.ldw + threadIdx.x] = static_cast<_Float16>(0.0f);   // the zero block
 }
 
-// One wave per item: up to 8 row tiles of 16 rows of one near tile against all
-// its columns, 32 columns per step, hi and lo halves of the vectors in turn.
+// One wave per item: up to 8 row tiles of 16 rows of a run of near tiles of
+// one leaf against all their columns, 32 columns per step, hi and lo halves of
+// the vectors in turn.  Each tile's products are scaled by its tile and vector
+// scales and added to the run's sums in tile order; the run writes one
+// partial-sum slot.
+//
+// The steps of the whole run form one sequence, software-pipelined: the loads
+// of step s + 1 (8 A fragments, 2 B fragments, 16 bytes per lane each) are
+// issued before the matrix instructions of step s, so every wave keeps two
+// steps of tile data in flight.  No load is guarded: a row past the item (or
+// past the tile) reads the item's last row, whose products land in output rows
+// that are never stored, and a column group past the tile reads the tile's
+// last group against a zero B fragment; B lanes past nrhs or past the tile
+// read a block of zeros kept after the staged vectors.
+typedef const __attribute__((address_space(1))) h8_t gh8_t;
+
+// a 16-byte load through a global-memory pointer (not a flat one)
+__device__ inline h8_t gload16(const _Float16* p) { return *(gh8_t*)(p); }
+
+struct MmaStep {
+    h8_t a[kMmaRowTiles];
+    h8_t bh, bl;
+};
+
+// position in a run's step sequence, wave-uniform (scalar registers): tile q
+// of the run and its fields, columns k0 .. k0 + 31, the tile's scale and the
+// vector scales of its column leaf (one per right-hand side)
+struct MmaPos {
+    int q, k0, kc, col_pos;
+    int64_t tile_off;
+    float ts;
+    float ws[kMaxRhs];
+};
+
+__device__ inline int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
+// read-only descriptors through the constant address space: scalar loads,
+// which do not wait behind the tile loads in flight
+typedef const __attribute__((address_space(4))) NearItem cNearItem;
+typedef const __attribute__((address_space(4))) float cfloat;
+
+__device__ inline void mma_tile(const OpDev& D, int t, MmaPos& p) {
+    cNearItem* T = (cNearItem*)D.tiles + t;
+    p.kc = (T->ncols + 7) & ~7;
+    p.col_pos = T->col_pos;
+    p.tile_off = T->tile_off;
+    p.ts = D.nscale ? *((cfloat*)D.nscale + T->tile) : 1.0f;
+    cfloat* w = (cfloat*)D.wsc + static_cast<int64_t>(T->leaf_b) * kMaxRhs;
+#pragma unroll
+    for (int c = 0; c < kMaxRhs; ++c) p.ws[c] = w[c];
+}
+
 template <bool kUp>
 __global__ void __launch_bounds__(kBlock) k_l2l_mma(Batch b) {
     if (kUp && static_cast<int>(blockIdx.x) < b.up) {
@@ -893,54 +948,105 @@ __global__ void __launch_bounds__(kBlock) k_l2l_mma(Batch b) {
         return;
     }
     int64_t u = (blockIdx.x - b.up) * static_cast<int64_t>(blockDim.x / kWave) + threadIdx.x / kWave;
+    u = uni(static_cast<int>(u));   // wave-uniform: the descriptors load as scalars
     if (u >= b.pre[b.nops]) return;
     if (b.flip) u = b.pre[b.nops] - 1 - u;
     const int o = batch_op(b, u);
     const OpDev& D = *b.op[o];
-    const NearItem I = D.items[u - b.pre[o]];
+    cNearItem* Ip = (cNearItem*)D.items + (u - b.pre[o]);
+    const struct {
+        int64_t part_off;
+        int32_t ld, row0, nrows, tile, ntiles;
+    } I = {Ip->part_off, Ip->ld, Ip->row0, Ip->nrows, Ip->tile, Ip->ntiles};
     const int lane = threadIdx.x % kWave, li = lane % 16, g = lane / 16;
-    const int nrt = I.nrows / 16;
-    const int kc = (I.ncols + 7) & ~7;
-    const _Float16* T = static_cast<const _Float16*>(D.near) + I.tile_off;
-    const bool jv = li < b.nrhs;   // B operand: column li of the vectors
-    const _Float16* whi = static_cast<const _Float16*>(D.wh) + static_cast<int64_t>(li) * D.ldw + I.col_pos;
-    const _Float16* wlo = whi + kMaxRhs * D.ldw;
-    f4_t acc[kMmaRowTiles];
+    const int nrt = I.nrows / 16, nrhs = b.nrhs, ntiles = I.ntiles;
+    const bool jv = li < nrhs;   // B operand: column li of the vectors
+    // element offset (in halves) of this lane's row in each row tile, clamped to the item
+    int roff[kMmaRowTiles];
 #pragma unroll
-    for (int t = 0; t < kMmaRowTiles; ++t) acc[t] = f4_t{0.0f, 0.0f, 0.0f, 0.0f};
-    for (int k0 = 0; k0 < kc; k0 += 32) {
-        const int kg = k0 + 8 * g;   // this lane's 8 columns
-        const bool kv = kg < kc;
-        h8_t bh = {}, bl = {};
-        if (kv && jv) {
-            bh = *reinterpret_cast<const h8_t*>(whi + kg);
-            bl = *reinterpret_cast<const h8_t*>(wlo + kg);
-        }
-        h8_t av[kMmaRowTiles];
+    for (int t = 0; t < kMmaRowTiles; ++t) roff[t] = min(I.row0 + 16 * min(t, nrt - 1) + li, I.ld - 1) * 8;
+    const int64_t ld8 = static_cast<int64_t>(I.ld) * 8;
+    const int lc = min(li, nrhs - 1);
+    const _Float16* whi = static_cast<const _Float16*>(D.wh) + 8 * lc;
+    const int64_t lo_off = kMaxRhs * D.ldw;
+    const _Float16* zero = static_cast<const _Float16*>(D.wh) + 2 * lo_off;   // 8 zero halves
+    const _Float16* near = static_cast<const _Float16*>(D.near);
+    auto load = [&](const MmaPos& p, MmaStep& st) {
+        const int kg = p.k0 + 8 * g;               // this lane's 8 columns
+        const int kgc = min(kg, p.kc - 8);
+        const _Float16* tp = near + p.tile_off + (kgc / 8) * ld8;
+#pragma unroll
+        for (int t = 0; t < kMmaRowTiles; ++t) st.a[t] = gload16(tp + roff[t]);
+        // B lanes past nrhs or past the tile read the zero block
+        const bool bv = jv && kg < p.kc;
+        const _Float16* wq = whi + (static_cast<int64_t>(p.col_pos) + kgc) * nrhs;
+        st.bh = gload16(bv ? wq : zero);
+        st.bl = gload16(bv ? wq + lo_off : zero);
+    };
+    // the next position; false past the run's last step
+    auto advance = [&](MmaPos& p) {
+        p.k0 += 32;
+        if (p.k0 < p.kc) return true;
+        p.k0 = 0;
+        ++p.q;
+        if (p.q >= ntiles) return false;
+        mma_tile(D, I.tile + p.q, p);
+        return true;
+    };
+    f4_t tot[kMmaRowTiles], acc[kMmaRowTiles];
+#pragma unroll
+    for (int t = 0; t < kMmaRowTiles; ++t) {
+        tot[t] = f4_t{0.0f, 0.0f, 0.0f, 0.0f};
+        acc[t] = f4_t{0.0f, 0.0f, 0.0f, 0.0f};
+    }
+    auto compute = [&](const MmaStep& st, const MmaPos& p) {
 #pragma unroll
         for (int t = 0; t < kMmaRowTiles; ++t) {
-            const int r = I.row0 + 16 * t + li;
-            av[t] = {};
-            if (t < nrt && kv && r < I.ld)
-                av[t] = *reinterpret_cast<const h8_t*>(T + (static_cast<int64_t>(kg / 8) * I.ld + r) * 8);
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(st.a[t], st.bh, acc[t], 0, 0, 0);
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(st.a[t], st.bl, acc[t], 0, 0, 0);
         }
+        if (p.k0 + 32 >= p.kc) {   // the tile's last step: scale and add in tile order
+            float w = 0.0f;
 #pragma unroll
-        for (int t = 0; t < kMmaRowTiles; ++t) {
-            if (t < nrt) {
-                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(av[t], bh, acc[t], 0, 0, 0);
-                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(av[t], bl, acc[t], 0, 0, 0);
+            for (int c = 0; c < kMaxRhs; ++c) w = li == c ? p.ws[c] : w;
+            const float sc = jv ? p.ts * w : 0.0f;
+#pragma unroll
+            for (int t = 0; t < kMmaRowTiles; ++t) {
+                tot[t] += f4_t{acc[t][0] * sc, acc[t][1] * sc, acc[t][2] * sc, acc[t][3] * sc};
+                acc[t] = f4_t{0.0f, 0.0f, 0.0f, 0.0f};
             }
         }
+    };
+    // two step buffers in turn: the loads of one step are in flight while the
+    // matrix instructions of the previous one run
+    MmaStep s0, s1;
+    MmaPos p0{};
+    p0.q = 0;
+    p0.k0 = 0;
+    mma_tile(D, I.tile, p0);
+    load(p0, s0);
+    // (past the last step the loads repeat the current position: unconditional
+    // loads keep the loop free of branches around them, so each step waits only
+    // for its own loads)
+    for (;;) {
+        MmaPos p1 = p0;
+        const bool m1 = advance(p1);
+        load(m1 ? p1 : p0, s1);
+        compute(s0, p0);
+        if (!m1) break;
+        p0 = p1;
+        const bool m0 = advance(p0);
+        load(m0 ? p0 : p1, s0);
+        compute(s1, p1);
+        if (!m0) break;
     }
     // lane holds rows 4 g + q (q < 4) of column li of every row tile
     if (!jv) return;
-    const float sc = (D.nscale ? D.nscale[I.tile] : 1.0f) * D.wsc[static_cast<int64_t>(I.leaf_b) * kMaxRhs + li];
     float* out = static_cast<float*>(D.part) + static_cast<int64_t>(li) * D.ldp + I.part_off;
 #pragma unroll
     for (int t = 0; t < kMmaRowTiles; ++t) {
         const int r = I.row0 + 16 * t + 4 * g;
-        if (t < nrt && r < I.ld)
-            *reinterpret_cast<f4_t*>(out + r) = f4_t{acc[t][0] * sc, acc[t][1] * sc, acc[t][2] * sc, acc[t][3] * sc};
+        if (t < nrt && r < I.ld) *reinterpret_cast<f4_t*>(out + r) = tot[t];
     }
 }
 
@@ -1035,7 +1141,7 @@ size_t Op::footprint() const {
            P64.bytes() + P32.bytes() + C64.bytes() + C32.bytes() + rows.bytes() + near64.bytes() + nearT.bytes() + near_scale.bytes() +
            far64.bytes() + farT.bytes() + far_scale.bytes() + far_colmap.bytes() + d_items.bytes() +
            d_leaves.bytes() + q.bytes() + d.bytes() + c.bytes() + w_tree.bytes() + skw.bytes() + sku.bytes() +
-           part.bytes() + plan_blob.bytes() + wh.bytes() + wsc.bytes() + d_items_mma.bytes() + d_leaves_mma.bytes();
+           part.bytes() + plan_blob.bytes() + wh.bytes() + wsc.bytes() + d_items_mma.bytes() + d_tiles_mma.bytes() + d_leaves_mma.bytes();
 }
 
 void Lane::init(LanePool* from) {
@@ -1124,6 +1230,7 @@ static void publish_descriptors(Op& op, hipStream_t s) {
         D.fscale = (!f64 && op.far_scale.n) ? op.far_scale.get() : nullptr;
         D.items = op.d_items.get();
         D.nitems = static_cast<int64_t>(op.items.size());
+        D.tiles = nullptr;
         D.near = f64 ? static_cast<const void*>(op.near64.get()) : static_cast<const void*>(op.nearT.get());
         D.nscale = (!f64 && op.near_scale.n) ? op.near_scale.get() : nullptr;
         D.leaves = op.d_leaves.get();
@@ -1142,6 +1249,7 @@ static void publish_descriptors(Op& op, hipStream_t s) {
         if (!f64 && op.packed) {   // matrix-core plan of the packed half-precision tiles
             D.items = op.d_items_mma.get();
             D.nitems = static_cast<int64_t>(op.items_mma.size());
+            D.tiles = op.d_tiles_mma.get();
             D.leaves = op.d_leaves_mma.get();
             D.ldp = std::max<int64_t>(op.part_elems_mma, 1);
             D.wh = op.wh.get();
@@ -1162,9 +1270,14 @@ static void publish_descriptors(Op& op, hipStream_t s) {
 static void check_near_plan(const Op& op);
 
 // Plan of the packed half-precision near field (k_l2l_mma): per near pair an
-// ld_a x kc_b packed tile; per (pair, group of at most 8 row tiles) one item;
-// per leaf one partial-sum slot of ld_a rows per near pair.  Vectors are staged
-// with every leaf padded to a multiple of 8 points.
+// ld_a x kc_b packed tile, the tiles of one leaf consecutive in memory.  One
+// item is a run of consecutive tiles of leaf a (about kMmaRunCols padded columns,
+// the leaf's tiles split into runs of nearly equal count) times a group of at
+// most 8 row tiles; it accumulates the whole run in registers and writes one
+// partial-sum slot of ld_a rows per run.  Vectors are staged with every leaf
+// padded to a multiple of 8 points.
+constexpr int kMmaRunCols = 2048;
+
 static void build_mma_plan(Op& op, hipStream_t s) {
     const int64_t L = op.L;
     op.packed = true;
@@ -1176,16 +1289,34 @@ static void build_mma_plan(Op& op, hipStream_t s) {
     }
     packed_near_offsets(op);
     op.items_mma.clear();
+    op.tiles_mma.clear();
     op.leaves_mma.clear();
     op.red_groups_mma = 0;
     int64_t off = 0, part = 0;
     for (int64_t a = 0; a < L; ++a) {
         const int64_t ha = L + a;
         const int32_t ld = op.near_ld[a];
-        const int ntiles = op.near_off[a + 1] - op.near_off[a];
+        const int32_t t_begin = op.near_off[a], ntiles = op.near_off[a + 1] - op.near_off[a];
+        int64_t cols = 0;
+        for (int32_t t = t_begin; t < t_begin + ntiles; ++t) {
+            const int32_t b = op.near_idx[t];
+            const int64_t nb = op.size[L + b];
+            NearItem T{};
+            T.tile_off = off;
+            T.ld = ld;
+            T.ncols = static_cast<int32_t>(nb);
+            T.col_pos = static_cast<int32_t>(wpad[b]);
+            T.tile = t;
+            T.leaf_b = b;
+            T.ntiles = 1;
+            op.tiles_mma.push_back(T);
+            off += static_cast<int64_t>(ld) * ((nb + 7) / 8 * 8);
+            cols += (nb + 7) / 8 * 8;
+        }
+        const int nrun = static_cast<int>(std::min<int64_t>(ntiles, std::max<int64_t>(1, ceil_div(cols, kMmaRunCols))));
         LeafPlan lp{};
         lp.part_off = part;
-        lp.nitems = ntiles;
+        lp.nitems = nrun;
         lp.ld = ld;
         lp.start = static_cast<int32_t>(op.start[ha]);
         lp.rows = static_cast<int32_t>(op.size[ha]);
@@ -1194,31 +1325,23 @@ static void build_mma_plan(Op& op, hipStream_t s) {
         const int groups = (rt + kMmaRowTiles - 1) / kMmaRowTiles;
         lp.ngroups = groups;
         lp.wpad = wpad[a];
-        lp.gstep = ntiles > kReduceAbove ? kReduceGroup : 1;
-        if (lp.gstep > 1) op.red_groups_mma = std::max(op.red_groups_mma, ceil_div(ntiles, kReduceGroup));
-        for (int32_t t = op.near_off[a]; t < op.near_off[a + 1]; ++t) {
-            const int32_t b = op.near_idx[t];
-            const int64_t nb = op.size[L + b];
-            op.near_tile_off_mma[t] = off;
-            const int q = t - op.near_off[a];
-            for (int g = 0, t0 = 0; g < groups; ++g) {
+        lp.gstep = nrun > kReduceAbove ? kReduceGroup : 1;
+        if (lp.gstep > 1) op.red_groups_mma = std::max(op.red_groups_mma, ceil_div(nrun, kReduceGroup));
+        for (int q = 0, t0 = t_begin; q < nrun; ++q) {
+            const int cnt_t = ntiles / nrun + (q < ntiles % nrun ? 1 : 0);
+            for (int g = 0, r0 = 0; g < groups; ++g) {
                 const int cnt = rt / groups + (g < rt % groups ? 1 : 0);
-                NearItem I{};
-                I.tile_off = off;
+                NearItem I = op.tiles_mma[t0];
                 I.part_off = part + static_cast<int64_t>(q) * ld;
-                I.ld = ld;
-                I.row0 = 16 * t0;
-                I.ncols = static_cast<int32_t>(nb);
-                I.col_pos = static_cast<int32_t>(wpad[b]);
-                I.tile = t;
+                I.row0 = 16 * r0;
                 I.nrows = 16 * cnt;
-                I.leaf_b = b;
+                I.ntiles = cnt_t;
                 op.items_mma.push_back(I);
-                t0 += cnt;
+                r0 += cnt;
             }
-            off += static_cast<int64_t>(ld) * ((nb + 7) / 8 * 8);
+            t0 += cnt_t;
         }
-        part += static_cast<int64_t>(ntiles) * ld;
+        part += static_cast<int64_t>(nrun) * ld;
         op.leaves_mma.push_back(lp);
     }
     op.near_elems_mma = off;
@@ -1226,8 +1349,9 @@ static void build_mma_plan(Op& op, hipStream_t s) {
     op.ldw = std::max<int64_t>(op.ldw, 0);
     check_near_plan(op);
     op.d_items_mma = to_device(op.items_mma, s);
+    op.d_tiles_mma = to_device(op.tiles_mma, s);
     op.d_leaves_mma = to_device(op.leaves_mma, s);
-    op.wh.alloc(static_cast<size_t>(std::max<int64_t>(op.ldw, 1)) * 2 * kMaxRhs * sizeof(_Float16));
+    op.wh.alloc((static_cast<size_t>(std::max<int64_t>(op.ldw, 1)) * 2 * kMaxRhs + 8) * sizeof(_Float16));
     op.wsc.alloc(static_cast<size_t>(L) * kMaxRhs);
 }
 
@@ -1253,13 +1377,22 @@ static void check_near_plan(const Op& op) {
         if (lp.part_off < 0 || lp.part_off + static_cast<int64_t>(lp.nitems) * lp.ld > op.part_elems) bad("leaf partials");
     }
     if (op.packed) {
+        if (static_cast<int64_t>(op.tiles_mma.size()) != pairs) bad("packed tile records");
+        for (int64_t t = 0; t < pairs; ++t) {
+            const NearItem& T = op.tiles_mma[t];
+            if (T.tile != t || T.leaf_b < 0 || T.leaf_b >= L || T.ncols < 1) bad("packed tile index");
+            const int64_t kc = (static_cast<int64_t>(T.ncols) + 7) / 8 * 8;
+            if (T.tile_off < 0 || T.tile_off + kc * T.ld > op.near_elems_mma) bad("packed tile extent");
+            if (T.col_pos < 0 || T.col_pos + kc > op.ldw) bad("staged vector extent");
+        }
         for (const NearItem& I : op.items_mma) {
-            if (I.tile < 0 || I.tile >= pairs || I.leaf_b < 0 || I.leaf_b >= L) bad("packed item index");
-            const int64_t kc = (static_cast<int64_t>(I.ncols) + 7) / 8 * 8;
-            if (I.tile_off < 0 || I.tile_off + kc * I.ld > op.near_elems_mma) bad("packed tile extent");
+            if (I.tile < 0 || I.ntiles < 1 || static_cast<int64_t>(I.tile) + I.ntiles > pairs) bad("packed item tiles");
+            // a run stays inside one leaf's near block
+            const int64_t a = std::upper_bound(op.near_off.begin(), op.near_off.end(), I.tile) - op.near_off.begin() - 1;
+            if (a < 0 || a >= L || static_cast<int64_t>(I.tile) + I.ntiles > op.near_off[a + 1]) bad("packed run across leaves");
+            if (I.tile_off != op.tiles_mma[I.tile].tile_off || I.ld != op.near_ld[a]) bad("packed run start");
             if (I.row0 < 0 || I.row0 + I.nrows > (I.ld + 15) / 16 * 16) bad("packed rows");
             if (I.part_off < 0 || I.part_off + I.ld > op.part_elems_mma) bad("packed partial-sum extent");
-            if (I.col_pos < 0 || I.col_pos + kc > op.ldw) bad("staged vector extent");
         }
         for (const LeafPlan& lp : op.leaves_mma) {
             if (lp.part_off < 0 || lp.part_off + static_cast<int64_t>(lp.nitems) * lp.ld > op.part_elems_mma)
@@ -1919,7 +2052,7 @@ ScratchLayout scratch_layout(const Op& op, int per) {
     L.skw = at; at += up(static_cast<size_t>(std::max<int64_t>(op.nskel, 1)) * per * 8);
     L.sku = at; at += up(static_cast<size_t>(std::max<int64_t>(op.nskel, 1)) * per * 8);
     L.part = at; at += up(static_cast<size_t>(part) * per * 8);
-    L.wh = at; at += op.packed && !f64 ? up(static_cast<size_t>(std::max<int64_t>(op.ldw, 1)) * 2 * kMaxRhs * 2) : 0;
+    L.wh = at; at += op.packed && !f64 ? up((static_cast<size_t>(std::max<int64_t>(op.ldw, 1)) * 2 * kMaxRhs + 8) * 2) : 0;
     L.wsc = at; at += op.packed && !f64 ? up(static_cast<size_t>(op.L) * kMaxRhs * sizeof(float)) : 0;
     L.total = at;
     return L;

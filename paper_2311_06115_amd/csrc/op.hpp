@@ -91,6 +91,7 @@ struct NearItem {
     int32_t leaf_b;     // column leaf (matrix-core items: index of its vector scales)
     int32_t row_pos;    // tree position of the row leaf's first point (plain items)
     int32_t row_n;      // points in the row leaf (rows at or past it are padding)
+    int32_t ntiles;     // matrix-core items: consecutive near tiles from `tile` on (one per tile record)
 };
 
 // Per leaf: where its partial sums live and how many items feed each row group.
@@ -145,6 +146,7 @@ struct OpDev {
     const float* fscale;
     const NearItem* items;
     int64_t nitems;
+    const NearItem* tiles;        // matrix-core plans: one record per near tile (items take runs of them)
     const void* near;
     const float* nscale;
     const LeafPlan* leaves;
@@ -237,8 +239,8 @@ struct Op {
     std::vector<int64_t> near_tile_off_mma;
     int64_t near_elems_mma = 0, part_elems_mma = 0;
     int red_groups = 0, red_groups_mma = 0;   // most pre-added groups of one leaf (plain, packed plans)
-    std::vector<NearItem> items_mma;
-    DevBuf<NearItem> d_items_mma;
+    std::vector<NearItem> items_mma, tiles_mma;
+    DevBuf<NearItem> d_items_mma, d_tiles_mma;
     std::vector<LeafPlan> leaves_mma;
     DevBuf<LeafPlan> d_leaves_mma;
     int64_t ldw = 0;
