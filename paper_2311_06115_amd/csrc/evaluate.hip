@@ -314,7 +314,8 @@ __global__ void __launch_bounds__(kBlock) k_l2l(Batch b) {
     if (b.flip) u = b.pre[b.nops] - 1 - u;
     const int o = batch_op(b, u);
     const OpDev& D = *b.op[o];
-    const NearItem I = D.items[u - b.pre[o]];
+    const NearItem I = (b.nrhs > 1 ? D.items : D.items1)[u - b.pre[o]];
+    const int64_t ldp = b.nrhs > 1 ? D.ldp : D.ldp1;
     const int lane = threadIdx.x % kWave;
     const int rend = min(I.ld, I.row0 + I.nrows);
     const V sc = D.nscale ? static_cast<V>(D.nscale[I.tile]) : V(1);
@@ -351,7 +352,7 @@ __global__ void __launch_bounds__(kBlock) k_l2l(Batch b) {
 #pragma unroll
                 for (int r = 0; r < RPL; ++r) acc[r] += val<V>(v0[r]) * w0;
             }
-            V* out = static_cast<V*>(D.part) + c * D.ldp + I.part_off + row;
+            V* out = static_cast<V*>(D.part) + c * ldp + I.part_off + row;
 #pragma unroll
             for (int r = 0; r < RPL; ++r) out[r] = acc[r];
         }
@@ -396,7 +397,7 @@ __global__ void __launch_bounds__(kCombBlock) k_combine(Batch b) {
     const int64_t u = blockIdx.x;
     const int o = batch_op(b, u);
     const OpDev& D = *b.op[o];
-    const LeafPlan lp = D.leaves[u - b.pre[o]];
+    const LeafPlan lp = D.leaves1[u - b.pre[o]];   // one column
     const TP* P = static_cast<const TP*>(D.P);
     const V* sku = static_cast<const V*>(D.sku);
     const V* pc = static_cast<const V*>(D.part) + lp.part_off;
@@ -953,7 +954,7 @@ __global__ void __launch_bounds__(kBlock) k_l2l_mma(Batch b) {
     if (b.flip) u = b.pre[b.nops] - 1 - u;
     const int o = batch_op(b, u);
     const OpDev& D = *b.op[o];
-    cNearItem* Ip = (cNearItem*)D.items + (u - b.pre[o]);
+    cNearItem* Ip = (cNearItem*)(b.nrhs > 1 ? D.items : D.items1) + (u - b.pre[o]);
     const struct {
         int64_t part_off;
         int32_t ld, row0, nrows, tile, ntiles;
@@ -1042,7 +1043,7 @@ __global__ void __launch_bounds__(kBlock) k_l2l_mma(Batch b) {
     }
     // lane holds rows 4 g + q (q < 4) of column li of every row tile
     if (!jv) return;
-    float* out = static_cast<float*>(D.part) + static_cast<int64_t>(li) * D.ldp + I.part_off;
+    float* out = static_cast<float*>(D.part) + static_cast<int64_t>(li) * (nrhs > 1 ? D.ldp : D.ldp1) + I.part_off;
 #pragma unroll
     for (int t = 0; t < kMmaRowTiles; ++t) {
         const int r = I.row0 + 16 * t + 4 * g;
@@ -1141,7 +1142,8 @@ size_t Op::footprint() const {
            P64.bytes() + P32.bytes() + C64.bytes() + C32.bytes() + rows.bytes() + near64.bytes() + nearT.bytes() + near_scale.bytes() +
            far64.bytes() + farT.bytes() + far_scale.bytes() + far_colmap.bytes() + d_items.bytes() +
            d_leaves.bytes() + q.bytes() + d.bytes() + c.bytes() + w_tree.bytes() + skw.bytes() + sku.bytes() +
-           part.bytes() + plan_blob.bytes() + wh.bytes() + wsc.bytes() + d_items_mma.bytes() + d_tiles_mma.bytes() + d_leaves_mma.bytes();
+           part.bytes() + plan_blob.bytes() + wh.bytes() + wsc.bytes() + d_items_mma[0].bytes() + d_items_mma[1].bytes() + d_tiles_mma.bytes() +
+           d_leaves_mma[0].bytes() + d_leaves_mma[1].bytes();
 }
 
 void Lane::init(LanePool* from) {
@@ -1198,7 +1200,9 @@ static void ensure_ws(Op& op, int nrhs) {
     op.w_tree.alloc(static_cast<size_t>(op.n) * nrhs * 8);
     op.skw.alloc(static_cast<size_t>(std::max<int64_t>(op.nskel, 1)) * nrhs * 8);
     op.sku.alloc(static_cast<size_t>(std::max<int64_t>(op.nskel, 1)) * nrhs * 8);
-    op.part.alloc(static_cast<size_t>(std::max<int64_t>(std::max(op.part_elems, op.part_elems_mma), 1)) * nrhs * 8);
+    // the several-column plans hold nrhs columns, the packed one-column plan one
+    const int64_t pe = std::max<int64_t>(std::max(op.part_elems, op.part_elems_mma[1]) * nrhs, op.part_elems_mma[0]);
+    op.part.alloc(static_cast<size_t>(std::max<int64_t>(pe, 1)) * 8);
     op.ws_nrhs = nrhs;
 }
 
@@ -1228,18 +1232,18 @@ static void publish_descriptors(Op& op, hipStream_t s) {
         D.far_colmap = op.far_colmap.get();
         D.far = f64 ? static_cast<const void*>(op.far64.get()) : static_cast<const void*>(op.farT.get());
         D.fscale = (!f64 && op.far_scale.n) ? op.far_scale.get() : nullptr;
-        D.items = op.d_items.get();
-        D.nitems = static_cast<int64_t>(op.items.size());
+        D.items = D.items1 = op.d_items.get();
+        D.nitems = D.nitems1 = static_cast<int64_t>(op.items.size());
         D.tiles = nullptr;
         D.near = f64 ? static_cast<const void*>(op.near64.get()) : static_cast<const void*>(op.nearT.get());
         D.nscale = (!f64 && op.near_scale.n) ? op.near_scale.get() : nullptr;
-        D.leaves = op.d_leaves.get();
+        D.leaves = D.leaves1 = op.d_leaves.get();
         D.w = op.w_tree.get();
         D.skw = op.skw.get();
         D.sku = op.sku.get();
         D.part = op.part.get();
         D.ldsk = std::max<int64_t>(op.nskel, 1);
-        D.ldp = std::max<int64_t>(op.part_elems, 1);
+        D.ldp = D.ldp1 = std::max<int64_t>(op.part_elems, 1);
         D.wh = nullptr;
         D.wsc = nullptr;
         D.ldw = 0;
@@ -1247,11 +1251,15 @@ static void publish_descriptors(Op& op, hipStream_t s) {
                               : nullptr;
         D.coff = op.d_coff;
         if (!f64 && op.packed) {   // matrix-core plan of the packed half-precision tiles
-            D.items = op.d_items_mma.get();
-            D.nitems = static_cast<int64_t>(op.items_mma.size());
+            D.items = op.d_items_mma[1].get();
+            D.nitems = static_cast<int64_t>(op.items_mma[1].size());
+            D.leaves = op.d_leaves_mma[1].get();
+            D.ldp = std::max<int64_t>(op.part_elems_mma[1], 1);
+            D.items1 = op.d_items_mma[0].get();
+            D.nitems1 = static_cast<int64_t>(op.items_mma[0].size());
+            D.leaves1 = op.d_leaves_mma[0].get();
+            D.ldp1 = std::max<int64_t>(op.part_elems_mma[0], 1);
             D.tiles = op.d_tiles_mma.get();
-            D.leaves = op.d_leaves_mma.get();
-            D.ldp = std::max<int64_t>(op.part_elems_mma, 1);
             D.wh = op.wh.get();
             D.wsc = op.wsc.get();
             D.ldw = op.ldw;
@@ -1271,11 +1279,15 @@ static void check_near_plan(const Op& op);
 
 // Plan of the packed half-precision near field (k_l2l_mma): per near pair an
 // ld_a x kc_b packed tile, the tiles of one leaf consecutive in memory.  One
-// item is a run of consecutive tiles of leaf a (about kMmaRunCols padded columns,
-// the leaf's tiles split into runs of nearly equal count) times a group of at
-// most 8 row tiles; it accumulates the whole run in registers and writes one
-// partial-sum slot of ld_a rows per run.  Vectors are staged with every leaf
-// padded to a multiple of 8 points.
+// item is a run of consecutive tiles of leaf a times a group of at most 8 row
+// tiles; it accumulates the whole run in registers and writes one partial-sum
+// slot of ld_a rows per run.  Two plans over the same tiles: for one right-hand
+// side a run is one tile (more, shorter items: the single-column stream is
+// bound by how many loads are in flight), for several a run holds about
+// kMmaRunCols padded columns, the leaf's tiles split into runs of nearly equal
+// count (fewer partial sums to write and add; measured at N = 100000: 16
+// columns 372 -> 345 us, one column 266 -> 290 us).  Vectors are staged with
+// every leaf padded to a multiple of 8 points.
 constexpr int kMmaRunCols = 2048;
 
 static void build_mma_plan(Op& op, hipStream_t s) {
@@ -1288,17 +1300,12 @@ static void build_mma_plan(Op& op, hipStream_t s) {
         op.ldw += (op.size[L + b] + 7) / 8 * 8;
     }
     packed_near_offsets(op);
-    op.items_mma.clear();
     op.tiles_mma.clear();
-    op.leaves_mma.clear();
-    op.red_groups_mma = 0;
-    int64_t off = 0, part = 0;
+    std::vector<int64_t> leaf_cols(L, 0);
+    int64_t off = 0;
     for (int64_t a = 0; a < L; ++a) {
-        const int64_t ha = L + a;
         const int32_t ld = op.near_ld[a];
-        const int32_t t_begin = op.near_off[a], ntiles = op.near_off[a + 1] - op.near_off[a];
-        int64_t cols = 0;
-        for (int32_t t = t_begin; t < t_begin + ntiles; ++t) {
+        for (int32_t t = op.near_off[a]; t < op.near_off[a + 1]; ++t) {
             const int32_t b = op.near_idx[t];
             const int64_t nb = op.size[L + b];
             NearItem T{};
@@ -1311,46 +1318,63 @@ static void build_mma_plan(Op& op, hipStream_t s) {
             T.ntiles = 1;
             op.tiles_mma.push_back(T);
             off += static_cast<int64_t>(ld) * ((nb + 7) / 8 * 8);
-            cols += (nb + 7) / 8 * 8;
+            leaf_cols[a] += (nb + 7) / 8 * 8;
         }
-        const int nrun = static_cast<int>(std::min<int64_t>(ntiles, std::max<int64_t>(1, ceil_div(cols, kMmaRunCols))));
-        LeafPlan lp{};
-        lp.part_off = part;
-        lp.nitems = nrun;
-        lp.ld = ld;
-        lp.start = static_cast<int32_t>(op.start[ha]);
-        lp.rows = static_cast<int32_t>(op.size[ha]);
-        lp.heap = static_cast<int32_t>(ha);
-        const int rt = (ld + 15) / 16;                        // 16-row tiles covering ld rows
-        const int groups = (rt + kMmaRowTiles - 1) / kMmaRowTiles;
-        lp.ngroups = groups;
-        lp.wpad = wpad[a];
-        lp.gstep = nrun > kReduceAbove ? kReduceGroup : 1;
-        if (lp.gstep > 1) op.red_groups_mma = std::max(op.red_groups_mma, ceil_div(nrun, kReduceGroup));
-        for (int q = 0, t0 = t_begin; q < nrun; ++q) {
-            const int cnt_t = ntiles / nrun + (q < ntiles % nrun ? 1 : 0);
-            for (int g = 0, r0 = 0; g < groups; ++g) {
-                const int cnt = rt / groups + (g < rt % groups ? 1 : 0);
-                NearItem I = op.tiles_mma[t0];
-                I.part_off = part + static_cast<int64_t>(q) * ld;
-                I.row0 = 16 * r0;
-                I.nrows = 16 * cnt;
-                I.ntiles = cnt_t;
-                op.items_mma.push_back(I);
-                r0 += cnt;
-            }
-            t0 += cnt_t;
-        }
-        part += static_cast<int64_t>(nrun) * ld;
-        op.leaves_mma.push_back(lp);
     }
     op.near_elems_mma = off;
-    op.part_elems_mma = part;
+    for (int k = 0; k < 2; ++k) {
+        std::vector<NearItem>& items = op.items_mma[k];
+        std::vector<LeafPlan>& leaves = op.leaves_mma[k];
+        items.clear();
+        leaves.clear();
+        op.red_groups_mma[k] = 0;
+        int64_t part = 0;
+        for (int64_t a = 0; a < L; ++a) {
+            const int64_t ha = L + a;
+            const int32_t ld = op.near_ld[a];
+            const int32_t t_begin = op.near_off[a], ntiles = op.near_off[a + 1] - op.near_off[a];
+            const int nrun = k == 0 ? ntiles
+                                    : static_cast<int>(std::min<int64_t>(
+                                          ntiles, std::max<int64_t>(1, ceil_div(leaf_cols[a], kMmaRunCols))));
+            LeafPlan lp{};
+            lp.part_off = part;
+            lp.nitems = nrun;
+            lp.ld = ld;
+            lp.start = static_cast<int32_t>(op.start[ha]);
+            lp.rows = static_cast<int32_t>(op.size[ha]);
+            lp.heap = static_cast<int32_t>(ha);
+            const int rt = (ld + 15) / 16;                        // 16-row tiles covering ld rows
+            const int groups = (rt + kMmaRowTiles - 1) / kMmaRowTiles;
+            lp.ngroups = groups;
+            lp.wpad = wpad[a];
+            lp.gstep = nrun > kReduceAbove ? kReduceGroup : 1;
+            if (lp.gstep > 1) op.red_groups_mma[k] = std::max(op.red_groups_mma[k], ceil_div(nrun, kReduceGroup));
+            for (int q = 0, t0 = t_begin; q < nrun; ++q) {
+                const int cnt_t = ntiles / nrun + (q < ntiles % nrun ? 1 : 0);
+                for (int g = 0, r0 = 0; g < groups; ++g) {
+                    const int cnt = rt / groups + (g < rt % groups ? 1 : 0);
+                    NearItem I = op.tiles_mma[t0];
+                    I.part_off = part + static_cast<int64_t>(q) * ld;
+                    I.row0 = 16 * r0;
+                    I.nrows = 16 * cnt;
+                    I.ntiles = cnt_t;
+                    items.push_back(I);
+                    r0 += cnt;
+                }
+                t0 += cnt_t;
+            }
+            part += static_cast<int64_t>(nrun) * ld;
+            leaves.push_back(lp);
+        }
+        op.part_elems_mma[k] = part;
+    }
     op.ldw = std::max<int64_t>(op.ldw, 0);
     check_near_plan(op);
-    op.d_items_mma = to_device(op.items_mma, s);
+    for (int k = 0; k < 2; ++k) {
+        op.d_items_mma[k] = to_device(op.items_mma[k], s);
+        op.d_leaves_mma[k] = to_device(op.leaves_mma[k], s);
+    }
     op.d_tiles_mma = to_device(op.tiles_mma, s);
-    op.d_leaves_mma = to_device(op.leaves_mma, s);
     op.wh.alloc((static_cast<size_t>(std::max<int64_t>(op.ldw, 1)) * 2 * kMaxRhs + 8) * sizeof(_Float16));
     op.wsc.alloc(static_cast<size_t>(L) * kMaxRhs);
 }
@@ -1385,17 +1409,19 @@ static void check_near_plan(const Op& op) {
             if (T.tile_off < 0 || T.tile_off + kc * T.ld > op.near_elems_mma) bad("packed tile extent");
             if (T.col_pos < 0 || T.col_pos + kc > op.ldw) bad("staged vector extent");
         }
-        for (const NearItem& I : op.items_mma) {
+        for (int k = 0; k < 2; ++k)
+        for (const NearItem& I : op.items_mma[k]) {
             if (I.tile < 0 || I.ntiles < 1 || static_cast<int64_t>(I.tile) + I.ntiles > pairs) bad("packed item tiles");
             // a run stays inside one leaf's near block
             const int64_t a = std::upper_bound(op.near_off.begin(), op.near_off.end(), I.tile) - op.near_off.begin() - 1;
             if (a < 0 || a >= L || static_cast<int64_t>(I.tile) + I.ntiles > op.near_off[a + 1]) bad("packed run across leaves");
             if (I.tile_off != op.tiles_mma[I.tile].tile_off || I.ld != op.near_ld[a]) bad("packed run start");
             if (I.row0 < 0 || I.row0 + I.nrows > (I.ld + 15) / 16 * 16) bad("packed rows");
-            if (I.part_off < 0 || I.part_off + I.ld > op.part_elems_mma) bad("packed partial-sum extent");
+            if (I.part_off < 0 || I.part_off + I.ld > op.part_elems_mma[k]) bad("packed partial-sum extent");
         }
-        for (const LeafPlan& lp : op.leaves_mma) {
-            if (lp.part_off < 0 || lp.part_off + static_cast<int64_t>(lp.nitems) * lp.ld > op.part_elems_mma)
+        for (int k = 0; k < 2; ++k)
+        for (const LeafPlan& lp : op.leaves_mma[k]) {
+            if (lp.part_off < 0 || lp.part_off + static_cast<int64_t>(lp.nitems) * lp.ld > op.part_elems_mma[k])
                 bad("packed leaf partials");
             if (lp.wpad < 0 || lp.wpad + (lp.rows + 7) / 8 * 8 > op.ldw) bad("packed leaf vector");
         }
@@ -1648,8 +1674,8 @@ static void apply_t(const ApplyReq* reqs, int nops, bool f64, int normalised, in
     const bool fuse_up = tree && !multi && nops == 1 && !otf;
     b.up = fuse_up ? static_cast<int>(reqs[0].op->L) : 0;
     auto near_field = [&] {
-        const int64_t tot = prefix([](const Op& op, int) {
-            return static_cast<int64_t>(mma ? op.items_mma.size() : op.items.size());
+        const int64_t tot = prefix([multi](const Op& op, int) {
+            return static_cast<int64_t>(mma ? op.items_mma[multi].size() : op.items.size());
         });
         b.flip = static_cast<int>(reqs[0].op->near_calls++ & 1u);
         const int64_t grid = ceil_div(tot, wpb) + b.up;
@@ -1678,7 +1704,7 @@ static void apply_t(const ApplyReq* reqs, int nops, bool f64, int normalised, in
     auto part_reduce = [&] {
         int maxg = 0;
         for (int o = 0; o < nops; ++o)
-            maxg = std::max(maxg, mma ? reqs[o].op->red_groups_mma : reqs[o].op->red_groups);
+            maxg = std::max(maxg, mma ? reqs[o].op->red_groups_mma[1] : reqs[o].op->red_groups);
         if (!multi || maxg == 0) return;
         const int64_t tot = prefix([](const Op& op, int) { return static_cast<int64_t>(op.L); });
         hipLaunchKernelGGL((k_part_reduce<V>), dim3(tot, maxg, nrhs), dim3(kBlock), 0, s, b);
@@ -1865,7 +1891,7 @@ static void build_product_graph(Op& op, bool f64, int normalised, int nrhs, Prod
     // near field (one column: with the leaf level of the upward pass, as in the
     // eager schedule, and the rest of the tree after it)
     Batch bl = base;
-    const int64_t nitems = static_cast<int64_t>(mma ? op.items_mma.size() : op.items.size());
+    const int64_t nitems = static_cast<int64_t>(mma ? op.items_mma[nrhs > 1].size() : op.items.size());
     bl.pre[1] = nitems;
     const bool fuse_up = op.nskel > 0 && !multi;
     bl.up = fuse_up ? op.L : 0;
@@ -1873,7 +1899,7 @@ static void build_product_graph(Op& op, bool f64, int normalised, int nrhs, Prod
                        : (fuse_up ? reinterpret_cast<void*>(&k_l2l<V, TN, true>)
                                   : reinterpret_cast<void*>(&k_l2l<V, TN, false>));
     hipGraphNode_t near = kernel(l2l_fn, dim3(ceil_div(nitems, wpb) + bl.up), bl, {G.prep}, nullptr);
-    const int maxg = mma ? op.red_groups_mma : op.red_groups;
+    const int maxg = mma ? op.red_groups_mma[1] : op.red_groups;
     if (multi && maxg > 0) {
         Batch br = base;
         br.pre[1] = op.L;
@@ -2044,14 +2070,18 @@ struct ScratchLayout {
 ScratchLayout scratch_layout(const Op& op, int per) {
     auto up = [](size_t b) { return (b + 255) / 256 * 256; };
     const bool f64 = op.prm.near_prec == HDM_F64;
-    const int64_t part = std::max<int64_t>(f64 || !op.packed ? op.part_elems : op.part_elems_mma, 1);
+    // partial sums: a several-column pass holds per columns of its plan, a
+    // one-column pass (per = 1, or the last pass of nrhs > per) one of its own
+    const int64_t part = f64 || !op.packed
+                             ? std::max<int64_t>(op.part_elems, 1) * per
+                             : std::max<int64_t>(std::max<int64_t>(op.part_elems_mma[1], 1) * per, op.part_elems_mma[0]);
     ScratchLayout L{};
     size_t at = 0;
     L.desc = at; at += up(sizeof(OpDev));
     L.w = at; at += up(static_cast<size_t>(op.n) * per * 8);
     L.skw = at; at += up(static_cast<size_t>(std::max<int64_t>(op.nskel, 1)) * per * 8);
     L.sku = at; at += up(static_cast<size_t>(std::max<int64_t>(op.nskel, 1)) * per * 8);
-    L.part = at; at += up(static_cast<size_t>(part) * per * 8);
+    L.part = at; at += up(static_cast<size_t>(part) * 8);
     L.wh = at; at += op.packed && !f64 ? up((static_cast<size_t>(std::max<int64_t>(op.ldw, 1)) * 2 * kMaxRhs + 8) * 2) : 0;
     L.wsc = at; at += op.packed && !f64 ? up(static_cast<size_t>(op.L) * kMaxRhs * sizeof(float)) : 0;
     L.total = at;

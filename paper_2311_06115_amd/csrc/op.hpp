@@ -144,17 +144,22 @@ struct OpDev {
     const int32_t* far_colmap;
     const void* far;
     const float* fscale;
-    const NearItem* items;
+    const NearItem* items;        // work items and per-leaf plans of products of several columns
     int64_t nitems;
+    const LeafPlan* leaves;
+    int64_t ldp;                  // column stride of the partial sums
+    const NearItem* items1;       // the same for one column (the plain plan: the same arrays)
+    int64_t nitems1;
+    const LeafPlan* leaves1;
+    int64_t ldp1;
     const NearItem* tiles;        // matrix-core plans: one record per near tile (items take runs of them)
     const void* near;
     const float* nscale;
-    const LeafPlan* leaves;
     void* w;                      // workspaces (nrhs columns each)
     void* skw;
     void* sku;
     void* part;
-    int64_t ldsk, ldp;
+    int64_t ldsk;
     // half-precision near field on matrix cores: the staged vectors (hi and lo
     // halves, 16 right-hand sides, leaves padded to 8 points) and their per
     // leaf, per column scales
@@ -237,12 +242,14 @@ struct Op {
     // their own tile offsets, items, leaf plans and partial-sum extent
     bool packed = false;
     std::vector<int64_t> near_tile_off_mma;
-    int64_t near_elems_mma = 0, part_elems_mma = 0;
-    int red_groups = 0, red_groups_mma = 0;   // most pre-added groups of one leaf (plain, packed plans)
-    std::vector<NearItem> items_mma, tiles_mma;
-    DevBuf<NearItem> d_items_mma, d_tiles_mma;
-    std::vector<LeafPlan> leaves_mma;
-    DevBuf<LeafPlan> d_leaves_mma;
+    // packed (matrix-core) plans, [0] for one right-hand side (a run is one
+    // tile), [1] for several (runs of about kMmaRunCols columns)
+    int64_t near_elems_mma = 0, part_elems_mma[2] = {0, 0};
+    int red_groups = 0, red_groups_mma[2] = {0, 0};   // most pre-added groups of one leaf (plain, packed plans)
+    std::vector<NearItem> items_mma[2], tiles_mma;
+    DevBuf<NearItem> d_items_mma[2], d_tiles_mma;
+    std::vector<LeafPlan> leaves_mma[2];
+    DevBuf<LeafPlan> d_leaves_mma[2];
     int64_t ldw = 0;
     DevBuf<char> wh;                           // 2 x 16 x ldw halves
     DevBuf<float> wsc;                         // L x 16
