@@ -553,7 +553,6 @@ __global__ void k_col_fix(double* Phi, int64_t n, const double* scale) {
 // block Lanczos (b right-hand sides per product): basis products, the block QR
 // of the residual, the banded projected matrix and its Rayleigh-Ritz solve
 // ---------------------------------------------------------------------------
-constexpr int kBRows = 256;        // rows per workgroup in the block basis products
 constexpr int kMaxBlockBasis = 512;
 
 // the start block: column c of V takes the start-vector draws of column c
@@ -565,36 +564,69 @@ __global__ void k_start_block(double* V, int64_t n, int b, uint64_t seed) {
     V[e] = (static_cast<double>(r) + 0.5) / 4294967296.0 - 0.5;
 }
 
-// partial[blk][c * b + q] = sum over the block's rows of V[c][row] * Y[q][row]
-__global__ void __launch_bounds__(kBlock) k_gemmt(const double* V, int64_t ldv, int ncols, const double* Y,
-                                                  int64_t ldy, int b, int64_t n, double* partial, int64_t ldp) {
-    __shared__ double ys[kMaxRhs * kBRows];
-    const int64_t r0 = blockIdx.x * static_cast<int64_t>(kBRows);
-    for (int e = threadIdx.x; e < b * kBRows; e += blockDim.x) {
-        const int q = e / kBRows, rr = e % kBRows;
-        const int64_t row = r0 + rr;
-        ys[e] = row < n ? Y[q * ldy + row] : 0.0;
-    }
-    __syncthreads();
-    const int wv = threadIdx.x / 64, lane = threadIdx.x % 64, nw = blockDim.x / 64;
-    for (int c = wv; c < ncols; c += nw) {
-        double acc[kMaxRhs];
+// partial[blk][c * b + q] = sum over the block's rows of X[c][row] * Y[q][row]
+// (c < ncols, q < b <= 16) on the float64 matrix cores.  One workgroup per
+// (block of kGramRows rows, group of up to kGramTiles 16-column tiles of X); its
+// four waves take a quarter of the rows each, 16 at a time: lane (m, k) loads
+// rows 4k .. 4k + 3 of column m of X (for every tile) and of Y, and the four
+// 16 x 16 x 4 instructions of a step take row 4k + s as their k-th term
+// (s < 4).  The waves' sums meet in shared memory and are added in wave
+// order.  Columns past ncols or b read the last column and rows past n read
+// zeros; neither is stored.
+typedef double d4_t __attribute__((ext_vector_type(4)));
+constexpr int kGramRows = 256;
+constexpr int kGramTiles = 8;
+__global__ void __launch_bounds__(kBlock) k_gram_mma(const double* X, int64_t ldx, int ncols, const double* Y,
+                                                     int64_t ldy, int b, int64_t n, double* partial, int64_t ldp) {
+    __shared__ d4_t red[3][kGramTiles][64];
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64, m = lane % 16, k = lane / 16;
+    const int t0 = blockIdx.y * kGramTiles;
+    const int nt = min(kGramTiles, (ncols + 15) / 16 - t0);
+    const int64_t r0 = blockIdx.x * static_cast<int64_t>(kGramRows) + wave * (kGramRows / 4);
+    const int64_t r1 = min(n, r0 + kGramRows / 4);
+    const double* yp = Y + static_cast<int64_t>(min(m, b - 1)) * ldy;
+    const double* xp[kGramTiles];
 #pragma unroll
-        for (int q = 0; q < kMaxRhs; ++q) acc[q] = 0.0;
+    for (int t = 0; t < kGramTiles; ++t)
+        xp[t] = X + static_cast<int64_t>(min(16 * (t0 + min(t, nt - 1)) + m, ncols - 1)) * ldx;
+    d4_t acc[kGramTiles];
 #pragma unroll
-        for (int k = 0; k < kBRows / 64; ++k) {
-            const int rr = lane + 64 * k;
-            const int64_t row = r0 + rr;
-            const double v = row < n ? V[c * ldv + row] : 0.0;
+    for (int t = 0; t < kGramTiles; ++t) acc[t] = d4_t{0.0, 0.0, 0.0, 0.0};
+    for (int64_t r = r0; r < r1; r += 16) {
+        const int64_t row = r + 4 * k;
+        double y[4], x[kGramTiles][4];
 #pragma unroll
-            for (int q = 0; q < kMaxRhs; ++q) acc[q] += v * ys[min(q, b - 1) * kBRows + rr];   // unguarded reads
+        for (int s = 0; s < 4; ++s) {
+            const bool in = row + s < r1;
+            const int64_t rr = in ? row + s : r0;
+            y[s] = in ? yp[rr] : 0.0;
+#pragma unroll
+            for (int t = 0; t < kGramTiles; ++t) x[t][s] = t < nt ? xp[t][rr] : 0.0;
         }
 #pragma unroll
-        for (int q = 0; q < kMaxRhs; ++q) {
-            if (q >= b) break;
-            double t = acc[q];
-            for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
-            if (lane == 0) partial[static_cast<int64_t>(blockIdx.x) * ldp + c * b + q] = t;
+        for (int t = 0; t < kGramTiles; ++t)
+            if (t < nt) {
+#pragma unroll
+                for (int s = 0; s < 4; ++s) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[t][s], y[s], acc[t], 0, 0, 0);
+            }
+    }
+    if (wave > 0) {
+#pragma unroll
+        for (int t = 0; t < kGramTiles; ++t)
+            if (t < nt) red[wave - 1][t][lane] = acc[t];
+    }
+    __syncthreads();
+    if (wave > 0) return;
+    // lane (m, k) holds entries (k + 4v, m) of every tile (the float64 instruction's
+    // result layout): column 16 t + k + 4v of X against column m of Y
+#pragma unroll
+    for (int t = 0; t < kGramTiles; ++t) {
+        if (t >= nt) break;
+        const d4_t g = ((acc[t] + red[0][t][lane]) + red[1][t][lane]) + red[2][t][lane];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int c = 16 * (t0 + t) + k + 4 * v;
+            if (c < ncols && m < b) partial[static_cast<int64_t>(blockIdx.x) * ldp + c * b + m] = g[v];
         }
     }
 }
@@ -1081,7 +1113,7 @@ static hdm_status block_lanczos_eigs(Op& op, int r, double tol, int b, int max_b
               "max_basis must be in [max(r, block), 512] (rounded down to a multiple of block)");
     const auto t0 = std::chrono::steady_clock::now();
     const int ldt = mb + b;
-    const int nbk = ceil_div(n, kBRows);
+    const int nbk = ceil_div(n, kGramRows);
     const int64_t ldp = static_cast<int64_t>(mb + b) * b;
     DevBuf<double> V(static_cast<size_t>(n) * (mb + b)), Y(static_cast<size_t>(n) * b), part(static_cast<size_t>(nbk) * ldp),
         H1(ldp), H2(ldp), G(b * b), Rinv(b * b), Rtot(b * b), T(static_cast<size_t>(ldt) * ldt),
@@ -1092,7 +1124,8 @@ static hdm_status block_lanczos_eigs(Op& op, int r, double tol, int b, int max_b
     const int gN = ceil_div(n, kBlock);
     // Gram products X^T Y (ncols x b) over the basis or the block itself
     auto gram = [&](const double* X, int ncols, const double* Yp, double* out) {
-        hipLaunchKernelGGL(k_gemmt, dim3(nbk), dim3(kBlock), 0, s, X, n, ncols, Yp, n, b, n, part.get(), ldp);
+        hipLaunchKernelGGL(k_gram_mma, dim3(nbk, ceil_div(ceil_div(ncols, 16), kGramTiles)), dim3(kBlock), 0, s, X, n,
+                           ncols, Yp, n, b, n, part.get(), ldp);
         hipLaunchKernelGGL(k_reduce_cols, dim3(ceil_div(int64_t(ncols) * b, 64)), dim3(256), 0, s, part.get(), nbk,
                            static_cast<int>(ldp), ncols * b, out);
     };
