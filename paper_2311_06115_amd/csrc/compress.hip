@@ -1667,46 +1667,85 @@ __device__ inline double sqd_regs(const double (&x)[D], const double (&y)[D]) {
     return acc;
 }
 
-// Per tile (one workgroup): its largest kernel value, exp(-(min d2) / eps) since
-// the kernel decreases with the distance, as the float scale of the reduced-
-// precision tile (1 where every value underflows to 0).  The column points are
-// staged in shared memory a chunk at a time; a thread keeps one row point in
-// registers and reads the columns as broadcasts.
-constexpr int kScaleChunk = 256;
+// Per tile (one workgroup): a bound on its largest kernel value, used as the
+// float scale of the reduced-precision tile (values K / scale <= 1).  The
+// kernel decreases with the distance, and every pair of points of leaves a and
+// b is at least g = max(0, |c_a - c_b| - r_a - r_b) apart, c the centre of a
+// leaf's bounding box and r its largest distance from it; so exp(-g^2 / eps) is
+// at least the tile's largest value (1 for a leaf with itself; 1 where the bound
+// underflows, since then every value does).  Two passes over the tile's 2 x 390
+// points instead of its 390 x 390 distances: the scale only keeps a tile of
+// small values clear of the half-precision subnormals, and any value between
+// the largest entry and 1 does that.
+template <int D>
+__device__ inline void wg_reduce(double (&v)[D], bool is_max, double* sm) {
+    // every thread's D values combined over the workgroup (min or max); result in every thread
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        double x = v[d];
+        for (int off = 32; off > 0; off >>= 1) {
+            const double y = __shfl_xor(x, off, 64);
+            x = is_max ? fmax(x, y) : fmin(x, y);
+        }
+        v[d] = x;
+    }
+    __syncthreads();
+    const int wv = threadIdx.x / 64, nw = blockDim.x / 64;
+    if (threadIdx.x % 64 == 0)
+#pragma unroll
+        for (int d = 0; d < D; ++d) sm[wv * D + d] = v[d];
+    __syncthreads();
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        double x = sm[d];
+        for (int w = 1; w < nw; ++w) x = is_max ? fmax(x, sm[w * D + d]) : fmin(x, sm[w * D + d]);
+        v[d] = x;
+    }
+}
+
+template <int D>
+__device__ inline void leaf_ball(const Pts& P, const int32_t* perm, int p0, int np, double (&c)[D], double& r,
+                                 double* sm) {
+    double lo[D], hi[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        lo[d] = INFINITY;
+        hi[d] = -INFINITY;
+    }
+    for (int i = threadIdx.x; i < np; i += blockDim.x) {
+        double x[D];
+        load_point<D>(P, perm[p0 + i], x);
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            lo[d] = fmin(lo[d], x[d]);
+            hi[d] = fmax(hi[d], x[d]);
+        }
+    }
+    wg_reduce<D>(lo, false, sm);
+    wg_reduce<D>(hi, true, sm);
+#pragma unroll
+    for (int d = 0; d < D; ++d) c[d] = 0.5 * (lo[d] + hi[d]);
+    double r2[1] = {0.0};
+    for (int i = threadIdx.x; i < np; i += blockDim.x) {
+        double x[D];
+        load_point<D>(P, perm[p0 + i], x);
+        r2[0] = fmax(r2[0], sqd_regs<D>(x, c));
+    }
+    wg_reduce<1>(r2, true, sm);
+    r = sqrt(r2[0]);
+}
+
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_near_scale(const NearPair* pairs, const int32_t* perm, Pts P,
                                                        float* scale) {
-    __shared__ double cs[kScaleChunk * D];
-    __shared__ double sm[kBlock];
+    __shared__ double sm[(kBlock / 64) * D];
     const NearPair pr = pairs[blockIdx.x];
-    double best = INFINITY;
-    for (int c0 = 0; c0 < pr.nb; c0 += kScaleChunk) {
-        const int nc = min(kScaleChunk, pr.nb - c0);
-        __syncthreads();
-        for (int e = threadIdx.x; e < nc * D; e += blockDim.x) {
-            const int j = e / D, d = e % D;
-            cs[e] = d < P.dim ? P.xf[static_cast<int64_t>(perm[pr.b0 + c0 + j]) * P.dim + d] : 0.0;
-        }
-        __syncthreads();
-        for (int r = threadIdx.x; r < pr.na; r += blockDim.x) {
-            double xr[D];
-            load_point<D>(P, perm[pr.a0 + r], xr);
-            for (int j = 0; j < nc; ++j) {
-                double y[D];
-#pragma unroll
-                for (int d = 0; d < D; ++d) y[d] = cs[j * D + d];
-                best = fmin(best, sqd_regs<D>(xr, y));
-            }
-        }
-    }
-    sm[threadIdx.x] = best;
-    __syncthreads();
-    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w) sm[threadIdx.x] = fmin(sm[threadIdx.x], sm[threadIdx.x + w]);
-        __syncthreads();
-    }
+    double ca[D], cb[D], ra, rb;
+    leaf_ball<D>(P, perm, pr.a0, pr.na, ca, ra, sm);
+    leaf_ball<D>(P, perm, pr.b0, pr.nb, cb, rb, sm);
     if (threadIdx.x == 0) {
-        const double m = exp(-(sm[0] / P.eps));
+        const double g = fmax(0.0, sqrt(sqd_regs<D>(ca, cb)) - ra - rb);
+        const double m = exp(-(g * g / P.eps));
         scale[blockIdx.x] = m > 0.0 ? static_cast<float>(m) : 1.0f;
     }
 }
