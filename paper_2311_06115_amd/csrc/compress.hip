@@ -2136,7 +2136,13 @@ struct SkelRun {
     DevBuf<int64_t> offs;   // compaction offsets (skeletons, P, rows), read by k_compact
 };
 
-static void skeletonize_levels(Op& op, const Geo& G, hipStream_t s, SkelRun& R) {
+// The evaluation-precision near tiles and the near field of K~ 1 run on the side
+// stream from the level with at most kSideGateNodes nodes on: the levels above
+// are latency-bound (a few workgroups each) and leave the device mostly idle,
+// while the leaf levels need its bandwidth (0: from the start).
+constexpr int kSideGateNodes = 8;   // N = 100000: 0 -> 17.1 ms, 64 -> 18.1, 16 -> 16.4, 8 -> 16.1, 4 -> 16.8, 2 -> 17.9
+
+static void skeletonize_levels(Op& op, const Geo& G, hipStream_t s, SkelRun& R, hipEvent_t gate) {
     const Pts& P = G.P;
     const int64_t n = op.n;
     const int k = op.prm.knn_k, smax = op.prm.max_rank_s;
@@ -2219,7 +2225,12 @@ static void skeletonize_levels(Op& op, const Geo& G, hipStream_t s, SkelRun& R) 
     std::vector<int32_t> h_nc(maxnodes), h_nr(maxnodes);
     // the row bitmaps start clear; each row selection clears its node's after use
     HDM_HIP(hipMemsetAsync(bits.get(), 0, sizeof(uint32_t) * static_cast<size_t>(1 << op.depth) * ((n + 31) / 32), s));
+    bool gated = false;
     for (int lvl = op.depth; lvl >= 1; --lvl) {
+        if (!gated && (kSideGateNodes <= 0 || (int64_t(1) << lvl) <= kSideGateNodes)) {
+            HDM_HIP(hipEventRecord(gate, s));
+            gated = true;
+        }
         const int nodes = 1 << lvl;
         LevelArgs A{};
         A.lvl = lvl;
@@ -2293,6 +2304,7 @@ static void skeletonize_levels(Op& op, const Geo& G, hipStream_t s, SkelRun& R) 
         A.node0 = 0;
         check_launch("skeletonisation");
     }
+    if (!gated) HDM_HIP(hipEventRecord(gate, s));
 }
 
 static void skeletonize_finish(Op& op, hipStream_t s, SkelRun& R) {
@@ -2675,7 +2687,13 @@ void compress_operator(Op& op, const void* X, int x_on_device, hipStream_t s) {
     check_launch("votes");
     auto keep = std::make_shared<BuildKeep>();
     SkelRun& skr = keep->skel;
-    skeletonize_levels(op, G, s, skr);
+    hipEvent_t gate = nullptr;
+    HDM_HIP(hipEventCreateWithFlags(&gate, hipEventDisableTiming));
+    struct EventGuard {
+        hipEvent_t e;
+        ~EventGuard() { (void)hipEventDestroy(e); }
+    } gate_guard{gate};
+    skeletonize_levels(op, G, s, skr, gate);
     {
         // through pinned staging when there is some: a pageable download took
         // hundreds of microseconds longer to come back
@@ -2695,6 +2713,7 @@ void compress_operator(Op& op, const void* X, int x_on_device, hipStream_t s) {
     // the main stream waits for the float64 tiles and the near plan only (the
     // degree products need them); their conversion to the evaluation precision
     // runs on through the far tiles and the degrees, and finish_operator waits
+    HDM_HIP(hipStreamWaitEvent(side, gate, 0));
     build_near_tiles(op, G, side);
     build_near_plan(op, side);
     if (op.near_direct) near_field_ones(op, side);   // the near part of K~ 1, beside the skeletonisation

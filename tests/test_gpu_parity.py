@@ -39,6 +39,7 @@ CASES = {
     "scurve-ragged-1537": "ragged",
     "mnist-2k": "mnist",
     "gauss6-3k": "gauss6",
+    "scurve-2k-hss": "hss",   # budget 0: HSS mode, every node's far list is its sibling
 }
 
 
@@ -53,6 +54,10 @@ def _case(name):
     if name == "mnist-2k":
         X, _ = synth.mnist_shaped(2048, 2)
         return X, synth.median_sq_dist_eps(X, 2), 128, 64, 1e-4, 16, 2, 0.05
+    if name == "scurve-2k-hss":
+        cfg = synth.get_config("scurve-2k")
+        X, eps = synth.configs.make_inputs(cfg)
+        return X, eps, cfg["m"], cfg["s"], cfg["tau"], cfg["k"], cfg["seed"], 0.0
     if name == "gauss6-3k":
         X = synth.gaussian_cloud(3000, 5)
         return X, synth.median_sq_dist_eps(X, 5), 200, 100, 1e-3, 24, 5, 0.1
@@ -229,3 +234,25 @@ def test_invalid_inputs_are_rejected():
     # leaves must hold more than k points
     with pytest.raises(hdm.HdmError):
         hdm.Operator(X, 1.0, 20, 16, 1e-5, 32, 0)
+
+
+def test_hss_mode_against_the_oracle():
+    """HSS mode (budget 0, the paper's Sec. 5 alternative to FMM mode): each leaf is
+    near only itself and every node's far list is exactly its sibling, on the GPU as
+    in the oracle; the normalised operator's eigenvalues match the oracle's Lanczos on
+    the same compressed operator to 1e-10 (float64 tiles)."""
+    X, eps, op, H = build_pair("scurve-2k-hss")
+    L = H.L
+    noff, nidx = op.near()
+    assert np.array_equal(np.diff(noff), np.ones(L, dtype=np.diff(noff).dtype))
+    assert np.array_equal(nidx, np.arange(L))
+    foff, fidx = op.far()
+    for h in range(2, 2 * L):
+        assert list(fidx[foff[h]:foff[h + 1]]) == [h ^ 1], h
+    r = 10
+    ev, _, info, st = op.eigs(r, tol=1e-10, seed=0, vectors=False)
+    assert st == 0
+    th, _, _ = DF.eigs(H.matvec, X.shape[0], r, tol=1e-12)
+    rel = np.abs(ev - th) / np.abs(th)
+    print(f"[gpu] HSS mode eigenvalues vs oracle: {rel.max():.2e}")
+    assert rel.max() <= 1e-10
