@@ -419,19 +419,22 @@ __global__ void __launch_bounds__(kCombBlock) k_combine(Batch b) {
     __syncthreads();
     // level lvl's slice of the chain buffer: rp x rn of P_parent (the node's
     // columns), then the node's rn far-field values
+    // the walk starts at level 1, or at the leaf when a per-level downward pass
+    // has completed every potential already
+    const int top = D.s2n_levels && depth >= 1 ? depth : 1;
     int64_t need = 0;
-    for (int lvl = 2; lvl <= depth; ++lvl) need += static_cast<int64_t>(m_rp[lvl] + 1) * m_rn[lvl];
+    for (int lvl = top + 1; lvl <= depth; ++lvl) need += static_cast<int64_t>(m_rp[lvl] + 1) * m_rn[lvl];
     const bool staged = need <= kStage;
     const int rleaf = depth >= 1 ? m_rn[depth] : 0;
 
     // 2. independent loads
     if (depth >= 1)
-        for (int i = tid; i < m_rn[1]; i += kCombBlock) tot[0][i] = sku[m_sk[1] + i];
+        for (int i = tid; i < m_rn[top]; i += kCombBlock) tot[0][i] = sku[m_sk[top] + i];
     if (staged && need > 0) {
         // need <= kStage here, so the flat index fits in 32 bits; each thread's
         // elements come in increasing order, so its level only advances
         const int nd = static_cast<int>(need);
-        int lvl = 2, lo = 0, sz = (m_rp[2] + 1) * m_rn[2];
+        int lvl = top + 1, lo = 0, sz = (m_rp[top + 1] + 1) * m_rn[top + 1];
         for (int g0 = tid; g0 < nd; g0 += 8 * kCombBlock) {
             V x[8];
 #pragma unroll
@@ -494,7 +497,7 @@ __global__ void __launch_bounds__(kCombBlock) k_combine(Batch b) {
     // 3. downward chain: u~_child = S2S(child) + (P_parent^T u~_parent)[child's columns]
     int cur = 0;
     int64_t off = 0;
-    for (int lvl = 2; lvl <= depth; ++lvl) {
+    for (int lvl = top + 1; lvl <= depth; ++lvl) {
         const int rp = m_rp[lvl], rn = m_rn[lvl];
         for (int j = tid; j < rn; j += kCombBlock) {
             V acc = 0;
@@ -542,6 +545,42 @@ __global__ void __launch_bounds__(kCombBlock) k_combine(Batch b) {
     }
 }
 
+
+// ---- S2N by level (operators with large ranks) ---------------------------------
+// u~_h = S2S(h) + (P_parent^T u~_parent)[h's columns] for every node h of level
+// lvl (b.arg), in place on the far-field potentials, parents' potentials already
+// complete: one workgroup per node, thread j owns column j of the parent's P
+// slice (consecutive threads read consecutive entries of a P row) and sums over
+// the parent's rows in increasing order, the arithmetic of the combine's walk.
+template <typename V, typename TP, bool kMulti>
+__global__ void __launch_bounds__(kBlock) k_s2n(Batch b) {
+    const int64_t u = blockIdx.x;
+    const int o = batch_op(b, u);
+    const OpDev& D = *b.op[o];
+    const int lvl = b.arg[o];
+    const int64_t h = (int64_t(1) << lvl) + (u - b.pre[o]);
+    const int64_t p = h >> 1;
+    const int rn = D.rank[h], rp = D.rank[p], ncp = D.ncand[p];
+    const int coff = (h & 1) ? D.rank[2 * p] : 0;
+    const TP* Pp = static_cast<const TP*>(D.P) + D.poff[p] + coff;
+    V* sku = static_cast<V*>(D.sku);
+    const int64_t ldsk = D.ldsk, sp = D.skoff[p], sh = D.skoff[h];
+    constexpr int NC = kMulti ? kMaxRhs : 1;
+    const int last = b.nrhs - 1;
+    for (int j = threadIdx.x; j < rn; j += blockDim.x) {
+        V acc[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc[c] = 0;
+        for (int i = 0; i < rp; ++i) {
+            const V pij = static_cast<V>(Pp[static_cast<int64_t>(i) * ncp + j]);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) acc[c] += pij * sku[min(c, last) * ldsk + sp + i];
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            if (c <= last) sku[c * ldsk + sh + j] = sku[c * ldsk + sh + j] + acc[c];
+    }
+}
 
 // ---- several right-hand sides (2 <= nrhs <= 16) -------------------------------
 // The same phases with every matrix element loaded once for all columns: each
@@ -684,18 +723,21 @@ __global__ void __launch_bounds__(kCombBlock) k_combine_m(Batch b) {
     }
     if (tid == 0 && depth >= 1) m_pleaf = D.poff[lp.heap];
     __syncthreads();
+    // the walk starts at level 1, or at the leaf when a per-level downward pass
+    // has completed every potential already
+    const int top = D.s2n_levels && depth >= 1 ? depth : 1;
     if (depth >= 1) {
-        const int r1 = m_rn[1];
+        const int r1 = m_rn[top];
         for (int e = tid; e < nr * r1; e += kCombBlock) {
             const int c = e / r1, i = e % r1;
-            tot[0][c * kMaxRank + i] = sku[c * ldsk + m_sk[1] + i];
+            tot[0][c * kMaxRank + i] = sku[c * ldsk + m_sk[top] + i];
         }
     }
     // the chain walk; as many consecutive levels' P slices as fit are staged in
     // shared memory at a time (one batch of loads), a level too large for it
     // reads P from global memory
     int cur = 0;
-    for (int l0 = 2; l0 <= depth;) {
+    for (int l0 = top + 1; l0 <= depth;) {
         int l1 = l0, nd = 0;
         while (l1 <= depth && nd + m_rp[l1] * m_rn[l1] <= kStageM<V>) {
             nd += m_rp[l1] * m_rn[l1];
@@ -1250,6 +1292,7 @@ static void publish_descriptors(Op& op, hipStream_t s) {
         D.comp = op.ncomp > 0 ? (f64 ? static_cast<const void*>(op.C64.get()) : static_cast<const void*>(op.C32.get()))
                               : nullptr;
         D.coff = op.d_coff;
+        D.s2n_levels = op.s2n_levels ? 1 : 0;
         if (!f64 && op.packed) {   // matrix-core plan of the packed half-precision tiles
             D.items = op.d_items_mma[1].get();
             D.nitems = static_cast<int64_t>(op.items_mma[1].size());
@@ -1553,9 +1596,26 @@ void build_eval_plan(Op& op, hipStream_t s) {
                 inner_p += static_cast<int64_t>(op.rank[h]) * op.ncand[h];
             }
         }
-        // (a few MB at the S-curve sizes; the MNIST-shaped operator, every rank at
-        // the cap, would need 7x its P and keeps the per-level launches)
-        if (nested && op.depth >= 2 && comp <= 4 * inner_p + (int64_t(1) << 20)) op.ncomp = comp;
+        // Used where the extra entries cost less to stream than the per-level
+        // launches they save: at most 16M more than the inner nodes' P (a few MB at
+        // the S-curve sizes; the MNIST-shaped operator, every rank at the cap, would
+        // read 117M entries per product instead of P's 33M and keeps the per-level
+        // launches)
+        if (nested && op.depth >= 2 && comp <= inner_p + (int64_t(16) << 20)) op.ncomp = comp;
+        // The combine walks each leaf's path down from the root, re-reading the
+        // ancestors' P slices once per leaf; where that re-reads more than 16M
+        // entries beyond the slices themselves (every rank at the cap of the
+        // MNIST-shaped operator: 117M against 33M) the downward pass runs once per
+        // product instead, one launch per level, with the same arithmetic.
+        int64_t chain = 0, slices = 0;
+        for (int64_t h = 2; h < 2 * op.L; ++h) {
+            const int64_t e = static_cast<int64_t>(op.rank[h >> 1]) * op.rank[h];
+            slices += e;
+            int64_t under = 1;   // leaves below h
+            for (int64_t g = h; g < op.L; g <<= 1) under <<= 1;
+            chain += e * under;
+        }
+        op.s2n_levels = nested && op.depth >= 2 && chain > slices + (int64_t(16) << 20);
     }
     check_eval_plan(op, tasks);
     // the skeleton-dependent arrays in one allocation and one copy
@@ -1760,6 +1820,20 @@ static void apply_t(const ApplyReq* reqs, int nops, bool f64, int normalised, in
                                           ev.stop, 0, b);
             }
         }
+        {   // S2N level by level for the operators that take it (large ranks)
+            PhaseScope ph(cx, HDM_PHASE_S2N, ts);
+            for (int lvl = 2; lvl <= maxdepth; ++lvl) {
+                for (int o = 0; o < nops; ++o) b.arg[o] = lvl;
+                const int64_t tot = prefix([lvl](const Op& op, int) {
+                    return op.s2n_levels && lvl <= op.depth ? int64_t(1) << lvl : int64_t(0);
+                });
+                if (tot == 0) continue;
+                if (multi)
+                    hipLaunchKernelGGL((k_s2n<V, TP, true>), dim3(tot), dim3(kBlock), 0, ts, b);
+                else
+                    hipLaunchKernelGGL((k_s2n<V, TP, false>), dim3(tot), dim3(kBlock), 0, ts, b);
+            }
+        }
     }
     if (overlap) {
         HDM_HIP(hipEventRecord(lane.join, ts));
@@ -1906,6 +1980,18 @@ static void build_product_graph(Op& op, bool f64, int normalised, int nrhs, Prod
         near = kernel(reinterpret_cast<void*>(&k_part_reduce<V>), dim3(op.L, maxg, nrhs), br, {near}, nullptr);
     }
     std::vector<hipGraphNode_t> comb_deps{near};
+    // S2N by level after the far field, for operators with large ranks (as eager)
+    auto s2n_levels = [&](hipGraphNode_t last) {
+        if (!op.s2n_levels) return last;
+        for (int lvl = 2; lvl <= op.depth; ++lvl) {
+            Batch bn = base;
+            bn.arg[0] = lvl;
+            bn.pre[1] = int64_t(1) << lvl;
+            last = kernel(multi ? reinterpret_cast<void*>(&k_s2n<V, TP, true>) : reinterpret_cast<void*>(&k_s2n<V, TP, false>),
+                          dim3(static_cast<unsigned>(bn.pre[1])), bn, {last}, nullptr);
+        }
+        return last;
+    };
     if (fuse_up) {
         hipGraphNode_t last = near;
         if (op.ncomp > 0) {
@@ -1930,6 +2016,7 @@ static void build_product_graph(Op& op, bool f64, int normalised, int nrhs, Prod
             last = kernel(reinterpret_cast<void*>(&k_s2s<V, TF>), dim3(ceil_div(op.row_total, wpb)), bs, {last},
                           nullptr);
         }
+        last = s2n_levels(last);
         comb_deps = {last};
     } else if (op.nskel > 0) {
         // upward pass, leaves first, then the levels above through the composites
@@ -1957,6 +2044,7 @@ static void build_product_graph(Op& op, bool f64, int normalised, int nrhs, Prod
             last = kernel(multi ? reinterpret_cast<void*>(&k_s2s_m<V, TF>) : reinterpret_cast<void*>(&k_s2s<V, TF>),
                           dim3(ceil_div(op.row_total, wpb)), bs, {last}, nullptr);
         }
+        last = s2n_levels(last);
         if (last != G.prep) comb_deps.push_back(last);
     }
     Batch bc = base;

@@ -167,6 +167,7 @@ struct OpDev {
     float* wsc;
     int64_t ldw;
     const void* comp;             // composites of the nested bases (nullptr: level by level)
+    int32_t s2n_levels;           // 1: the downward pass runs level by level before the combine
     const int64_t* coff;
 };
 
@@ -299,6 +300,7 @@ struct Op {
     // by level)
     std::vector<int64_t> coff;                 // per heap id
     int64_t ncomp = 0;
+    bool s2n_levels = false;   // downward pass in per-level launches (large ranks) instead of per leaf path
     DevBuf<double> C64;
     DevBuf<float> C32;
     const int64_t* d_coff = nullptr;           // in plan_blob
