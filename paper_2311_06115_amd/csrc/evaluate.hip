@@ -567,14 +567,27 @@ __global__ void __launch_bounds__(kBlock) k_s2n(Batch b) {
     const int64_t ldsk = D.ldsk, sp = D.skoff[p], sh = D.skoff[h];
     constexpr int NC = kMulti ? kMaxRhs : 1;
     const int last = b.nrhs - 1;
+    constexpr int IB = kMulti ? 4 : 16;   // rows of P in flight per thread
     for (int j = threadIdx.x; j < rn; j += blockDim.x) {
         V acc[NC];
 #pragma unroll
         for (int c = 0; c < NC; ++c) acc[c] = 0;
-        for (int i = 0; i < rp; ++i) {
-            const V pij = static_cast<V>(Pp[static_cast<int64_t>(i) * ncp + j]);
+        // the last batch clamps its indexes and adds only the rows in range
+        for (int i0 = 0; i0 < rp; i0 += IB) {
+            V pv[IB], uv[IB][NC];
 #pragma unroll
-            for (int c = 0; c < NC; ++c) acc[c] += pij * sku[min(c, last) * ldsk + sp + i];
+            for (int t = 0; t < IB; ++t) {
+                const int i = min(i0 + t, rp - 1);
+                pv[t] = static_cast<V>(Pp[static_cast<int64_t>(i) * ncp + j]);
+#pragma unroll
+                for (int c = 0; c < NC; ++c) uv[t][c] = sku[min(c, last) * ldsk + sp + i];
+            }
+#pragma unroll
+            for (int t = 0; t < IB; ++t)
+                if (i0 + t < rp) {
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) acc[c] += pv[t] * uv[t][c];
+                }
         }
 #pragma unroll
         for (int c = 0; c < NC; ++c)
@@ -1820,7 +1833,9 @@ static void apply_t(const ApplyReq* reqs, int nops, bool f64, int normalised, in
                                           ev.stop, 0, b);
             }
         }
-        {   // S2N level by level for the operators that take it (large ranks)
+        bool any_s2n = false;
+        for (int o = 0; o < nops; ++o) any_s2n = any_s2n || reqs[o].op->s2n_levels;
+        if (any_s2n) {   // S2N level by level for the operators that take it (large ranks)
             PhaseScope ph(cx, HDM_PHASE_S2N, ts);
             for (int lvl = 2; lvl <= maxdepth; ++lvl) {
                 for (int o = 0; o < nops; ++o) b.arg[o] = lvl;

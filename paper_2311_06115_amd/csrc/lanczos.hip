@@ -82,14 +82,17 @@ __global__ void __launch_bounds__(256) k_reduce_cols(const double* partial, int 
 }
 
 
-// true in the one workgroup that finishes last; every workgroup's put_shared
-// stores have completed before it is counted.  The counter is left at zero for
-// the next launch.  Every thread of the workgroup must call it.
+// true in the one workgroup that finishes last.  Every thread's put_shared
+// stores are ordered before thread 0's arrival by the barrier, and the arrival
+// is a release at device scope; the last workgroup's arrival is also an
+// acquire, and the barrier after it orders its threads' get_shared loads after
+// it: the loads see every workgroup's stores (happens-before through the
+// counter, under the HIP/HSA scoped memory model).  The counter is left at
+// zero for the next launch.  Every thread of the workgroup must call it.
 __device__ inline bool last_workgroup(unsigned* counter, bool* flag) {
-    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (threadIdx.x == 0)
-        *flag = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gridDim.x - 1;
+        *flag = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == gridDim.x - 1;
     __syncthreads();
     if (!*flag) return false;
     if (threadIdx.x == 0) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
