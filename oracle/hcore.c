@@ -104,8 +104,46 @@ static double sqd(const orc_points *P, int64_t i, int64_t j) {
     return acc;
 }
 
-/* Eq. (2): W_ij = exp(-||x_i - x_j||^2 / sigma^2), sigma^2 = eps */
+/* ------------------------------------------------------------------------- */
+/* The exponential of the compression's kernel values.  The tree, neighbour    */
+/* and skeleton decisions are taken on kernel values, so the CPU build and the  */
+/* device evaluate e^x by the same sequence of IEEE operations (a library exp   */
+/* is correctly rounded on neither side): Cody and Waite's argument reduction   */
+/* x = n ln2 + r (Cody & Waite, Software Manual for the Elementary Functions,   */
+/* 1980), n = floor(x / ln2 + 1/2), ln2 split in a high part of 32 significant  */
+/* bits (n times it is exact) and the rest; e^r by the Taylor polynomial of     */
+/* degree 13 (|r| <= ln2 / 2: the omitted terms are below 1e-17 relative),      */
+/* Horner with fused multiply-adds; then times 2^n, in two exact powers of two  */
+/* when the result is subnormal.  Arguments <= -745.2 give 0 (e^x is below half */
+/* the smallest subnormal).  Within 2 ulp of e^x (tests/test_oracle_hmatrix.py).*/
+/* The constants are the doubles nearest to ln2's high part, ln2 - high, 1/ln2  */
+/* and 1/k!, written as hexadecimal floats.                                     */
+/* ------------------------------------------------------------------------- */
+static const double EXP_LN2_HI = 0x1.62e42fee00000p-1;
+static const double EXP_LN2_LO = 0x1.a39ef35793c76p-33;
+static const double EXP_INV_LN2 = 0x1.71547652b82fep+0;
+static const double EXP_INV_FACT[14] = {  /* 1/k!, k = 0..13 */
+    1.0, 1.0, 0x1.0000000000000p-1, 0x1.5555555555555p-3, 0x1.5555555555555p-5, 0x1.1111111111111p-7,
+    0x1.6c16c16c16c17p-10, 0x1.a01a01a01a01ap-13, 0x1.a01a01a01a01ap-16, 0x1.71de3a556c734p-19,
+    0x1.27e4fb7789f5cp-22, 0x1.ae64567f544e4p-26, 0x1.1eed8eff8d898p-29, 0x1.6124613a86d09p-33};
+
+double orc_det_exp(double x) {
+    if (!(x > -745.2)) return 0.0;
+    const double n = floor(x * EXP_INV_LN2 + 0.5);
+    const double r = (x - n * EXP_LN2_HI) - n * EXP_LN2_LO;
+    double p = EXP_INV_FACT[13];
+    for (int k = 12; k >= 0; --k) p = fma(p, r, EXP_INV_FACT[k]);
+    const int e = (int)n;
+    if (e >= -1021) return p * ldexp(1.0, e);
+    return (p * ldexp(1.0, e + 600)) * ldexp(1.0, -600);
+}
+
+/* Eq. (2): W_ij = exp(-||x_i - x_j||^2 / sigma^2), sigma^2 = eps; the compression's
+ * values through orc_det_exp, the dense definitions through the C library's exp */
 static double kval(const orc_points *P, int64_t i, int64_t j) {
+    return orc_det_exp(-(sqd(P, i, j) / P->eps));
+}
+static double kval_libm(const orc_points *P, int64_t i, int64_t j) {
     return exp(-(sqd(P, i, j) / P->eps));
 }
 
@@ -861,7 +899,7 @@ void orc_dense_kmatvec(const void *x, int64_t n, int dim, int is_u8, double eps,
     for (int64_t i = r0; i < r1; ++i) {
         for (int c = 0; c < nrhs; ++c) {
             double acc = 0.0;
-            for (int64_t j = 0; j < n; ++j) acc = acc + kval(&P, i, j) * w[(int64_t)c * n + j];
+            for (int64_t j = 0; j < n; ++j) acc = acc + kval_libm(&P, i, j) * w[(int64_t)c * n + j];
             u[(int64_t)c * (r1 - r0) + (i - r0)] = acc;
         }
     }

@@ -42,6 +42,8 @@ def lib():
         L.orc_dense_sqdist.argtypes = [vp, i64, i32, i32, i64, i64, vp]
         L.orc_kernel.restype = f64
         L.orc_kernel.argtypes = [vp, i64, i32, i32, f64, i64, i64]
+        L.orc_det_exp.restype = f64
+        L.orc_det_exp.argtypes = [f64]
         L.orc_rand_u32.restype = C.c_uint32
         L.orc_rand_u32.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32]
         L.orc_philox4x32_10.argtypes = [vp, vp, vp]
@@ -76,6 +78,12 @@ def philox4x32_10(ctr, key):
 
 def rand_u32(seed, purpose, a, b, i):
     return int(lib().orc_rand_u32(seed, purpose, a, b, i))
+
+
+def det_exp(x: float) -> float:
+    """The compression's exponential (Cody-Waite reduction, Taylor polynomial of
+    degree 13), as the CPU build evaluates it."""
+    return lib().orc_det_exp(float(x))
 
 
 def sample_positions(seed, node, n, ns):

@@ -64,8 +64,44 @@ __device__ inline double sqd(const Pts& P, int64_t i, int64_t j) {
     return acc;
 }
 
+// e^x for the kernel values.  The tree, neighbour and skeleton decisions are
+// taken on kernel values, and the library exponentials of the device and of a
+// CPU are not correctly rounded, so e^x is evaluated here by one fixed sequence
+// of IEEE operations (this file is built with -ffp-contract=off): Cody and
+// Waite's reduction x = n ln2 + r with n = floor(x / ln2 + 1/2) and ln2 split
+// into a 32-bit high part (n times it is exact) and the rest; e^r by its Taylor
+// polynomial of degree 13 (|r| <= ln2 / 2, omitted terms below 1e-17 relative) in
+// Horner form with fused multiply-adds; the product with 2^n, through two exact
+// powers of two when it is subnormal.  x <= -745.2 gives 0.  Within 1-2 ulp of
+// e^x.  Constants: the doubles nearest ln2's high part, ln2 - high, 1/ln2 and 1/k!.
+// Kernels whose kernel values decide nothing (the float64 degree products'
+// near field, the tile scales) use the device's faster exp instead.
+__device__ inline double det_exp(double x) {
+    constexpr double kLn2Hi = 0x1.62e42fee00000p-1, kLn2Lo = 0x1.a39ef35793c76p-33, kInvLn2 = 0x1.71547652b82fep+0;
+    if (!(x > -745.2)) return 0.0;
+    const double n = floor(x * kInvLn2 + 0.5);
+    const double r = (x - n * kLn2Hi) - n * kLn2Lo;
+    double p = 0x1.6124613a86d09p-33;   // 1/13!
+    p = fma(p, r, 0x1.1eed8eff8d898p-29);   // 1/12!
+    p = fma(p, r, 0x1.ae64567f544e4p-26);   // 1/11!
+    p = fma(p, r, 0x1.27e4fb7789f5cp-22);   // 1/10!
+    p = fma(p, r, 0x1.71de3a556c734p-19);   // 1/9!
+    p = fma(p, r, 0x1.a01a01a01a01ap-16);   // 1/8!
+    p = fma(p, r, 0x1.a01a01a01a01ap-13);   // 1/7!
+    p = fma(p, r, 0x1.6c16c16c16c17p-10);   // 1/6!
+    p = fma(p, r, 0x1.1111111111111p-7);    // 1/5!
+    p = fma(p, r, 0x1.5555555555555p-5);    // 1/4!
+    p = fma(p, r, 0x1.5555555555555p-3);    // 1/3!
+    p = fma(p, r, 0.5);
+    p = fma(p, r, 1.0);
+    p = fma(p, r, 1.0);
+    const int e = static_cast<int>(n);
+    if (e >= -1021) return p * ldexp(1.0, e);
+    return (p * ldexp(1.0, e + 600)) * ldexp(1.0, -600);
+}
+
 // Eq. (2): exp(-||x_i - x_j||^2 / eps)
-__device__ inline double kval(const Pts& P, int64_t i, int64_t j) { return exp(-(sqd(P, i, j) / P.eps)); }
+__device__ inline double kval(const Pts& P, int64_t i, int64_t j) { return det_exp(-(sqd(P, i, j) / P.eps)); }
 
 // ---------------------------------------------------------------------------
 // u8 codes: exact squared distances of whole blocks with int8 matrix cores.
@@ -141,7 +177,7 @@ __global__ void __launch_bounds__(256) k_gram_u8(const GramBlock* blocks, const 
             const int32_t s2 = ns[B.ridx[r]] + ns[B.cidx[c]] - 2 * acc[t][q];
             const int64_t e = B.off + (B.colmajor ? static_cast<int64_t>(c) * B.ld + r : static_cast<int64_t>(r) * B.ld + c);
             if (mode == 0) static_cast<int32_t*>(out)[e] = s2;
-            else static_cast<double*>(out)[e] = exp(-((static_cast<double>(s2) / 65025.0) / eps));
+            else static_cast<double*>(out)[e] = det_exp(-((static_cast<double>(s2) / 65025.0) / eps));
         }
     }
 }
@@ -261,7 +297,7 @@ __global__ void __launch_bounds__(kBlock) k_tree_sumk(int lvl, int64_t n, const 
                 const double t = a[d] - xs[k][q][d];
                 sq = sq + t * t;
             }
-        acc = acc + exp(-(sq / P.eps));
+        acc = acc + det_exp(-(sq / P.eps));
     }
     sumk[pos] = acc;
 }
@@ -1117,7 +1153,7 @@ __global__ void k_block_reg(LevelArgs A, Pts P) {
                     const double tq = xi[d] - xc[d];
                     acc = acc + tq * tq;
                 }
-            B[static_cast<int64_t>(r) * nc + c] = exp(-(acc / P.eps));
+            B[static_cast<int64_t>(r) * nc + c] = det_exp(-(acc / P.eps));
         }
     }
 }
@@ -1848,7 +1884,7 @@ __global__ void __launch_bounds__(kBlock) k_near_otf(const NearItem* items, int6
 #pragma unroll
             for (int d = 0; d < D; ++d) y[d] = lane_value(xc[d], j);
             const double wj = lane_value(wl, j);
-            const double k0 = exp(-(sqd_regs<D>(x0, y) * ie));
+            const double k0 = exp(-(sqd_regs<D>(x0, y) * ie));   // values only: the device's exp
             const double k1 = exp(-(sqd_regs<D>(x1, y) * ie));
             a0 = a0 + (v0 ? k0 : 0.0) * wj;
             a1 = a1 + (v1 ? k1 : 0.0) * wj;
