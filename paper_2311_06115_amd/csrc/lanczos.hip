@@ -836,6 +836,95 @@ __global__ void __launch_bounds__(1024) k_sytrd(const double* T, int ldt, int m,
     }
 }
 
+// The same reduction with the matrix in shared memory (m <= kSytrdLds, leading
+// dimension m + 1 against bank conflicts) and the product p = tau A22 v taken by
+// eight threads per row (columns j = t mod 8, then combined across the eight in
+// a fixed order), so that a step is a few barriers rather than len dependent
+// global loads per thread.  The reflectors go to A's columns in global memory
+// as they are formed (k_ormtr reads them there).
+constexpr int kSytrdLds = 128;
+__global__ void __launch_bounds__(1024) k_sytrd_lds(const double* T, int ldt, int m, double* A, int lda, double* d,
+                                                     double* e, double* tau) {
+    extern __shared__ double M[];
+    __shared__ double v[kSytrdLds], w[kSytrdLds], red[16];
+    __shared__ double s_tau;
+    const int ldm = m + 1;
+    for (int x = threadIdx.x; x < m * m; x += blockDim.x) {
+        const int i = x / m, j = x % m;
+        M[i * ldm + j] = T[static_cast<int64_t>(i) * ldt + j];
+    }
+    __syncthreads();
+    const int row = threadIdx.x / 8, t8 = threadIdx.x % 8;
+    for (int k = 0; k + 1 < m; ++k) {
+        const int len = m - k - 1;
+        const int i = threadIdx.x;
+        const double xi = i < len ? M[k * ldm + k + 1 + i] : 0.0;
+        const double sigma = wg_sum(i >= 1 && i < len ? xi * xi : 0.0, red);
+        const double alpha = M[k * ldm + k + 1];
+        if (threadIdx.x == 0) d[k] = M[k * ldm + k];
+        if (len == 1 || sigma == 0.0) {
+            if (threadIdx.x == 0) {
+                e[k] = alpha;
+                tau[k] = 0.0;
+            }
+            __syncthreads();
+            continue;
+        }
+        const double mu = sqrt(alpha * alpha + sigma);
+        const double beta = alpha <= 0.0 ? mu : -mu;
+        const double tk = (beta - alpha) / beta;
+        const double inv = 1.0 / (alpha - beta);
+        if (i < len) {
+            v[i] = i == 0 ? 1.0 : xi * inv;
+            if (i >= 1) A[static_cast<int64_t>(k + 1 + i) * lda + k] = xi * inv;   // the reflector, below the subdiagonal
+        }
+        if (threadIdx.x == 0) {
+            e[k] = beta;
+            tau[k] = tk;
+            s_tau = tk;
+        }
+        __syncthreads();
+        // p_row = tau sum_j A22[row][j] v[j]: eight partial sums (j = t8 mod 8), combined in a fixed order
+        double part = 0.0;
+        if (row < len) {
+            const double* r = M + (k + 1 + row) * ldm + k + 1;
+            for (int j = t8; j < len; j += 8) part += r[j] * v[j];
+        }
+        part += __shfl_xor(part, 1, 8);
+        part += __shfl_xor(part, 2, 8);
+        part += __shfl_xor(part, 4, 8);
+        const double pi = part * s_tau;
+        const double K = 0.5 * s_tau * wg_sum(row < len && t8 == 0 ? pi * v[row] : 0.0, red);
+        if (row < len && t8 == 0) w[row] = pi - K * v[row];
+        __syncthreads();
+        // A22 -= v w^T + w v^T
+        for (int x = threadIdx.x; x < len * len; x += blockDim.x) {
+            const int jj = x / len, ii = x % len;
+            M[(k + 1 + jj) * ldm + k + 1 + ii] -= v[ii] * w[jj] + w[ii] * v[jj];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        d[m - 1] = M[(m - 1) * ldm + m - 1];
+        e[m - 1] = 0.0;
+    }
+}
+
+// the reduction of the leading m x m block of T: in shared memory up to
+// kSytrdLds, else in global memory (A)
+static void launch_sytrd(const double* T, int ldt, int m, double* A, int lda, double* d, double* e, double* tau,
+                         hipStream_t s, hipEvent_t start = nullptr, hipEvent_t stop = nullptr) {
+    if (m <= kSytrdLds) {
+        const size_t shmem = static_cast<size_t>(m) * (m + 1) * sizeof(double);
+        if (shmem > 65536)
+            HDM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sytrd_lds),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(shmem)));
+        hipExtLaunchKernelGGL(k_sytrd_lds, dim3(1), dim3(1024), shmem, s, start, stop, 0, T, ldt, m, A, lda, d, e, tau);
+    } else {
+        hipExtLaunchKernelGGL(k_sytrd, dim3(1), dim3(1024), 0, s, start, stop, 0, T, ldt, m, A, lda, d, e, tau);
+    }
+}
+
 // Z[k] <- Q Z[k] for the r eigenvectors of the tridiagonal matrix (one wave per vector)
 __global__ void __launch_bounds__(1024) k_ormtr(const double* A, int lda, const double* tau, int m, double* Z, int r) {
     __shared__ double zs[16][kMaxBlockBasis];
@@ -1026,7 +1115,7 @@ void LanczosRun::solve_projected(int nvec, hipStream_t s) {
     hipLaunchKernelGGL(k_thick_tail, dim3(ceil_div(m - keep, kBlock)), dim3(kBlock), 0, s, T.get(), ldt, keep, m,
                        alpha.get(), beta.get());
     KernelEvents ev(op->ctx, HDM_PHASE_TRIDIAG);
-    hipLaunchKernelGGL(k_sytrd, dim3(1), dim3(1024), 0, s, T.get(), ldt, m, A.get(), ldt, dd.get(), ee.get(), tau.get());
+    launch_sytrd(T.get(), ldt, m, A.get(), ldt, dd.get(), ee.get(), tau.get(), s);
     launch_tridiag(dd.get(), ee.get(), m, nvec, theta.get(), Y.get(), bound.get(), s, ev.start, nullptr);
     hipLaunchKernelGGL(k_ormtr, dim3(1), dim3(1024), 0, s, A.get(), ldt, tau.get(), m, Y.get(), nvec);
     hipExtLaunchKernelGGL(k_thick_bounds, dim3(ceil_div(nvec, 64)), dim3(64), 0, s, nullptr, ev.stop, 0, Y.get(), m,
@@ -1174,8 +1263,7 @@ static hdm_status block_lanczos_eigs(Op& op, int r, double tol, int b, int max_b
             since = 0;
             {
                 KernelEvents ev(op.ctx, HDM_PHASE_TRIDIAG);
-                hipExtLaunchKernelGGL(k_sytrd, dim3(1), dim3(1024), 0, s, ev.start, ev.stop, 0, T.get(), ldt, m,
-                                      A.get(), mb, dd.get(), ee.get(), tau.get());
+                launch_sytrd(T.get(), ldt, m, A.get(), mb, dd.get(), ee.get(), tau.get(), s, ev.start, ev.stop);
             }
             launch_tridiag(dd.get(), ee.get(), m, r, theta.get(), Z.get(), bound.get(), s);
             hipLaunchKernelGGL(k_ormtr, dim3(1), dim3(1024), 0, s, A.get(), mb, tau.get(), m, Z.get(), r);
