@@ -497,10 +497,24 @@ __global__ void k_ritz(const double* V, int64_t ldv, int m, const double* Y, int
     __syncthreads();
     const int64_t row = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
     if (row >= n) return;
-    for (int k = 0; k < r; ++k) {
-        double acc = 0.0;
-        for (int c = 0; c < m; ++c) acc += V[c * ldv + row] * (k * m + c < 4096 ? ys[k * m + c] : Y[k * m + c]);
-        Phi[k * n + row] = acc;
+    // sixteen vectors per pass over the basis (each V element loaded once per
+    // pass); every output sums over the basis columns in increasing order
+    constexpr int KB = 16;
+    for (int k0 = 0; k0 < r; k0 += KB) {
+        double acc[KB];
+#pragma unroll
+        for (int t = 0; t < KB; ++t) acc[t] = 0.0;
+        for (int c = 0; c < m; ++c) {
+            const double v = V[c * ldv + row];
+#pragma unroll
+            for (int t = 0; t < KB; ++t) {
+                const int e = min(k0 + t, r - 1) * m + c;
+                acc[t] += v * (e < 4096 ? ys[e] : Y[e]);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < KB; ++t)
+            if (k0 + t < r) Phi[(k0 + t) * n + row] = acc[t];
     }
 }
 
@@ -951,6 +965,51 @@ __global__ void __launch_bounds__(1024) k_ormtr(const double* A, int lda, const 
     }
 }
 
+// The same back-transformation with the reflectors and tau staged in shared
+// memory first (m <= kSytrdLds): each vector's m - 2 dependent steps then read
+// no global memory.  Same sums in the same order as k_ormtr.
+__global__ void __launch_bounds__(1024) k_ormtr_lds(const double* A, int lda, const double* tau, int m, double* Z,
+                                                     int r) {
+    extern __shared__ double sh[];
+    double* refl = sh;               // reflector kk in row kk: entry i at refl[kk m + i] (v_0 = 1)
+    double* ts = sh + m * m;         // tau
+    double* zs = ts + m;             // one vector per wave
+    for (int x = threadIdx.x; x < m * m; x += blockDim.x) {
+        const int kk = x / m, i = x % m, len = m - kk - 1;
+        refl[x] = i == 0 ? 1.0 : (i < len ? A[static_cast<int64_t>(kk + 1 + i) * lda + kk] : 0.0);
+    }
+    for (int x = threadIdx.x; x < m; x += blockDim.x) ts[x] = tau[x];
+    __syncthreads();
+    const int wv = threadIdx.x / 64, lane = threadIdx.x % 64;
+    for (int k = wv; k < r; k += 16) {
+        double* z = zs + wv * m;
+        for (int i = lane; i < m; i += 64) z[i] = Z[static_cast<int64_t>(k) * m + i];
+        for (int kk = m - 3; kk >= 0; --kk) {
+            const double t = ts[kk];
+            if (t == 0.0) continue;
+            const int len = m - kk - 1;
+            const double* v = refl + kk * m;
+            double dot = 0.0;
+            for (int i = lane; i < len; i += 64) dot += v[i] * z[kk + 1 + i];
+            for (int off = 32; off > 0; off >>= 1) dot += __shfl_xor(dot, off, 64);
+            for (int i = lane; i < len; i += 64) z[kk + 1 + i] -= t * dot * v[i];
+        }
+        for (int i = lane; i < m; i += 64) Z[static_cast<int64_t>(k) * m + i] = z[i];
+    }
+}
+
+static void launch_ormtr(const double* A, int lda, const double* tau, int m, double* Z, int r, hipStream_t s) {
+    if (m <= kSytrdLds) {
+        const size_t shmem = (static_cast<size_t>(m) * m + m + 16 * static_cast<size_t>(m)) * sizeof(double);
+        if (shmem > 65536)
+            HDM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_ormtr_lds),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(shmem)));
+        hipLaunchKernelGGL(k_ormtr_lds, dim3(1), dim3(1024), shmem, s, A, lda, tau, m, Z, r);
+    } else {
+        hipLaunchKernelGGL(k_ormtr, dim3(1), dim3(1024), 0, s, A, lda, tau, m, Z, r);
+    }
+}
+
 // ---- thick restart of the single-vector iteration ---------------------------------
 // The projected matrix T = V^T S~ V after a restart with k kept Ritz pairs is the
 // diagonal of their Ritz values, coupled to the first new Lanczos vector by
@@ -1117,7 +1176,7 @@ void LanczosRun::solve_projected(int nvec, hipStream_t s) {
     KernelEvents ev(op->ctx, HDM_PHASE_TRIDIAG);
     launch_sytrd(T.get(), ldt, m, A.get(), ldt, dd.get(), ee.get(), tau.get(), s);
     launch_tridiag(dd.get(), ee.get(), m, nvec, theta.get(), Y.get(), bound.get(), s, ev.start, nullptr);
-    hipLaunchKernelGGL(k_ormtr, dim3(1), dim3(1024), 0, s, A.get(), ldt, tau.get(), m, Y.get(), nvec);
+    launch_ormtr(A.get(), ldt, tau.get(), m, Y.get(), nvec, s);
     hipExtLaunchKernelGGL(k_thick_bounds, dim3(ceil_div(nvec, 64)), dim3(64), 0, s, nullptr, ev.stop, 0, Y.get(), m,
                           beta.get(), m - 1, nvec, bound.get());
 }
@@ -1266,7 +1325,7 @@ static hdm_status block_lanczos_eigs(Op& op, int r, double tol, int b, int max_b
                 launch_sytrd(T.get(), ldt, m, A.get(), mb, dd.get(), ee.get(), tau.get(), s, ev.start, ev.stop);
             }
             launch_tridiag(dd.get(), ee.get(), m, r, theta.get(), Z.get(), bound.get(), s);
-            hipLaunchKernelGGL(k_ormtr, dim3(1), dim3(1024), 0, s, A.get(), mb, tau.get(), m, Z.get(), r);
+            launch_ormtr(A.get(), mb, tau.get(), m, Z.get(), r, s);
             hipLaunchKernelGGL(k_block_bounds, dim3(1), dim3(64), 0, s, Z.get(), m, b, Rtot.get(), r, bound.get());
             check_launch("block rayleigh-ritz");
             int st = 0;
