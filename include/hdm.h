@@ -59,8 +59,10 @@ typedef struct {
     double eps;         /* > 0 */
     double alpha;       /* must be 1 */
     int32_t leaf_m;     /* leaf size bound: depth = min d with ceil(n / 2^d) <= m; every leaf must hold > knn_k points */
-    int32_t max_rank_s; /* 1..512; with HDM_U8 points at most the smallest leaf size
-                           (floor(n / 2^depth)): larger values are refused (HDM_EINVAL) */
+    int32_t max_rank_s; /* 1..1024; above 512 only with leaves of at most 512 points
+                           (ceil(n / 2^depth) <= 512); with HDM_U8 points at most the
+                           smallest leaf size (floor(n / 2^depth)): other values are
+                           refused (HDM_EINVAL) */
     double tau;         /* >= 0, relative pivot threshold of the interpolative decomposition */
     int32_t knn_k;      /* neighbours per point, 1..64 */
     int32_t knn_iters;  /* random trees for the neighbour search, >= 1 (10) */

@@ -82,7 +82,7 @@ void validate_params(const hdm_params& p) {
     if (!(p.eps > 0.0) || !std::isfinite(p.eps)) fail(HDM_EINVAL, "eps must be finite and > 0");
     if (p.alpha != 1.0) fail(HDM_EINVAL, "only alpha = 1 is supported");
     if (p.leaf_m < 2) fail(HDM_EINVAL, "leaf_m must be >= 2");
-    if (p.max_rank_s < 1 || p.max_rank_s > 512) fail(HDM_EINVAL, "max_rank_s must be in [1, 512]");
+    if (p.max_rank_s < 1 || p.max_rank_s > 1024) fail(HDM_EINVAL, "max_rank_s must be in [1, 1024]");
     if (!(p.tau >= 0.0) || !std::isfinite(p.tau)) fail(HDM_EINVAL, "tau must be finite and >= 0");
     if (p.knn_k < 1 || p.knn_k > 64) fail(HDM_EINVAL, "knn_k must be in [1, 64]");
     if (p.knn_iters < 1 || p.knn_iters > 1000) fail(HDM_EINVAL, "knn_iters must be in [1, 1000]");
@@ -95,6 +95,10 @@ void validate_params(const hdm_params& p) {
     if (depth > 16) fail(HDM_EINVAL, "tree deeper than 16 levels: raise leaf_m");
     if ((p.n >> depth) <= p.knn_k) fail(HDM_EINVAL, "every leaf must hold more than knn_k points");
     if (((p.n + (int64_t(1) << depth) - 1) >> depth) > 2048) fail(HDM_EINVAL, "leaves must hold <= 2048 points");
+    // the combine keeps a leaf's skeleton potentials (at most min(s, leaf size))
+    // in shared memory for up to 512 of them
+    if (p.max_rank_s > 512 && ((p.n + (int64_t(1) << depth) - 1) >> depth) > 512)
+        fail(HDM_EINVAL, "max_rank_s above 512 needs leaves of at most 512 points");
     // u8 codes with a maximal rank above the smallest leaf: two runs with such
     // requests ended in a GPU memory fault whose cause is not known, so this
     // class is refused until it is found

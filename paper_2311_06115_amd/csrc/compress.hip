@@ -863,7 +863,7 @@ __global__ void k_row_count(LevelArgs A) {
 // the rest: uniform draws from outside the node (or every outside point when
 // that is all there is).  The draws are taken 64 at a time by one wave and
 // accepted in draw order, exactly as a sequential rejection loop would.
-constexpr int kMaxRows = 1024;   // sampled rows per node (2 max_rank_s)
+constexpr int kMaxRows = 2048;   // sampled rows per node (2 max_rank_s)
 constexpr int kVoteShared = 144 * 1024;   // shared memory for the bitmap vote counting (bytes)
 
 // kSorted: the candidates' outside neighbours are marked in a bitmap over the
@@ -2187,7 +2187,7 @@ static void skeletonize_levels(Op& op, const Geo& G, hipStream_t s, SkelRun& R, 
     const int cmax = static_cast<int>(std::max<int64_t>(leafmax, 2 * static_cast<int64_t>(smax)));
     HDM_CHECK(cmax <= kMaxCand, HDM_EINVAL, "leaf size and 2 * max_rank_s must be <= 2048");
     const int rmax = 2 * smax;
-    HDM_CHECK(rmax <= 1024, HDM_EINVAL, "max_rank_s must be <= 512");
+    HDM_CHECK(rmax <= kMaxRows, HDM_EINVAL, "max_rank_s must be <= 1024");
     R.cmax = cmax;
     R.rmax = rmax;
     const int64_t NN = op.nnodes;
@@ -2202,7 +2202,12 @@ static void skeletonize_levels(Op& op, const Geo& G, hipStream_t s, SkelRun& R, 
     R.uniq.alloc(static_cast<size_t>(maxnodes) * cmax * k);
     R.B.alloc(static_cast<size_t>(maxnodes) * rmax * cmax);
     const size_t vote_shmem = sizeof(int32_t) * (2 * static_cast<size_t>((n + 31) / 32) + static_cast<size_t>(cmax) * k);
-    const bool sorted_votes = vote_shmem <= static_cast<size_t>(kVoteShared);
+    bool sorted_votes = vote_shmem <= static_cast<size_t>(kVoteShared);
+    if (sorted_votes) {   // the kernel's own shared arrays plus the dynamic part within the 160 KB of a CU
+        hipFuncAttributes fa{};
+        HDM_HIP(hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(&k_row_select<true>)));
+        sorted_votes = vote_shmem + fa.sharedSizeBytes <= 160 * 1024;
+    }
     if (sorted_votes) R.vts.alloc(static_cast<size_t>(maxnodes) * cmax * k);
     else R.cnt.alloc(static_cast<size_t>(maxnodes) * n);
     R.bits.alloc(static_cast<size_t>(maxnodes) * ((n + 31) / 32));

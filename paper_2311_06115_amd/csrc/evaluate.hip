@@ -1490,7 +1490,8 @@ static void check_eval_plan(const Op& op, const std::vector<RowTask>& tasks) {
     int64_t far_cols_total = 0;
     for (int64_t h = 2; h < NN; ++h) {
         const int64_t rk = op.rank[h], nc = op.ncand[h];
-        if (rk < 0 || rk > kMaxRank || rk > nc) bad("rank");
+        if (rk < 0 || rk > nc || (h >= L && rk > kMaxRank)) bad("rank");
+        if (rk > kMaxRank && !op.s2n_levels) bad("inner rank above the combine's walk without the level-wise pass");
         if (op.skoff[h] < 0 || op.skoff[h] + rk > op.nskel) bad("skeleton extent");
         if (op.poff[h] < 0 || op.poff[h] + rk * nc > op.np) bad("interpolation extent");
         if (h >= L && nc != op.size[h]) bad("leaf candidates are not its points");
@@ -1629,6 +1630,13 @@ void build_eval_plan(Op& op, hipStream_t s) {
             chain += e * under;
         }
         op.s2n_levels = nested && op.depth >= 2 && chain > slices + (int64_t(16) << 20);
+        // ranks above the combine's 512 potentials are only ever held by inner
+        // nodes (leaves: at most 512 by the parameter rules): pass them level-wise
+        int max_inner = 0;
+        for (int64_t h = 2; h < op.L; ++h) max_inner = std::max(max_inner, static_cast<int>(op.rank[h]));
+        if (max_inner > kMaxRank) op.s2n_levels = true;
+        op.max_leaf_rank = 0;
+        for (int64_t h = op.L; h < 2 * op.L; ++h) op.max_leaf_rank = std::max(op.max_leaf_rank, static_cast<int>(op.rank[h]));
     }
     check_eval_plan(op, tasks);
     // the skeleton-dependent arrays in one allocation and one copy
@@ -1902,7 +1910,7 @@ void apply_batch(const ApplyReq* reqs, int nops, int normalised, int nrhs, hipSt
         Op& op = *reqs[o].op;
         HDM_CHECK(op.prm.near_prec == op0.prm.near_prec && op.prm.far_prec == op0.prm.far_prec, HDM_EINVAL,
                   "a batch must share its tile precisions");
-        HDM_CHECK(op.prm.max_rank_s <= kMaxRank, HDM_EINTERNAL, "rank above the combine kernel's limit");
+        HDM_CHECK(op.max_leaf_rank <= kMaxRank, HDM_EINTERNAL, "leaf rank above the combine kernel's limit");
         if (op.ws_nrhs < nrhs) {
             ensure_ws(op, nrhs);
             publish_descriptors(op, s);
@@ -2130,7 +2138,7 @@ static bool apply_graph(Op& op, bool f64, int normalised, int nrhs, const double
 }
 
 void apply(Op& op, int normalised, bool exact64, const double* x, double* y, int nrhs, hipStream_t s, bool graph_ok) {
-    HDM_CHECK(op.prm.max_rank_s <= kMaxRank, HDM_EINTERNAL, "rank above the combine kernel's limit");
+    HDM_CHECK(op.max_leaf_rank <= kMaxRank, HDM_EINTERNAL, "leaf rank above the combine kernel's limit");
     HDM_CHECK(nrhs >= 1, HDM_EINVAL, "nrhs must be >= 1");
     const int per = std::min(nrhs, kMaxRhs);   // right-hand sides per pass
     if (op.ws_nrhs < per) {
@@ -2226,7 +2234,7 @@ void apply_noalloc(Op& op, int normalised, const double* x, double* y, int nrhs,
         fail(HDM_EDEVICE, std::string("the allocation-free scratch array has no address on this device: ") +
                               (why != hipSuccess ? hipGetErrorString(why) : "no context was created on it"));
     }
-    HDM_CHECK(op.prm.max_rank_s <= kMaxRank, HDM_EINTERNAL, "rank above the combine kernel's limit");
+    HDM_CHECK(op.max_leaf_rank <= kMaxRank, HDM_EINTERNAL, "leaf rank above the combine kernel's limit");
     const int per = std::min(nrhs, kMaxRhs);
     const ScratchLayout L = scratch_layout(op, per);
     if (L.total > kScratchBytes)

@@ -301,6 +301,7 @@ struct Op {
     std::vector<int64_t> coff;                 // per heap id
     int64_t ncomp = 0;
     bool s2n_levels = false;   // downward pass in per-level launches (large ranks) instead of per leaf path
+    int max_leaf_rank = 0;
     DevBuf<double> C64;
     DevBuf<float> C32;
     const int64_t* d_coff = nullptr;           // in plan_blob

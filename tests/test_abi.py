@@ -58,6 +58,12 @@ def test_parameter_rules_without_a_device(L):
     assert L.hdm_params_validate(C.byref(_params(4278, 256, 256, hdm.U8))) == 1
     # the rule is about u8 codes only
     assert L.hdm_params_validate(C.byref(_params(21850, 256, 256, hdm.F64, dim=3))) == 0
+    # ranks above 512 (up to 1024) only with leaves of at most 512 points: the
+    # 6-D shape of the scaling study (m = s = 768) at N = 100000 has 391-point leaves
+    assert L.hdm_params_validate(C.byref(_params(100000, 768, 768, hdm.F64, k=64, dim=6))) == 0
+    assert L.hdm_params_validate(C.byref(_params(6000, 768, 768, hdm.F64, k=64, dim=6))) == 1   # 750-point leaves
+    assert b"512 points" in L.hdm_last_error()
+    assert L.hdm_params_validate(C.byref(_params(100000, 768, 1025, hdm.F64, k=64, dim=6))) == 1
     for field, val in [("eps", 0.0), ("alpha", 0.5), ("max_rank_s", 0), ("knn_k", 65), ("leaf_m", 1),
                        ("budget", 1.5), ("near_prec", 7)]:
         p = _params(4096, 256, 64, hdm.F64, dim=3)
