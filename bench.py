@@ -162,6 +162,8 @@ def main():
     ap.add_argument("--copy-probe", action="store_true", help="also run one plain 1 GiB device copy (counter scale)")
     ap.add_argument("--serve-seconds", type=float, default=10.0, help="length of each serving stream (0: skip)")
     ap.add_argument("--serve-pool", type=int, default=8, help="distinct request instances the stream cycles through")
+    ap.add_argument("--rhs", type=int, default=0,
+                    help="also time one product of K~ with this many right-hand sides (16 per pass)")
     ap.add_argument("--thrash-mib", type=int, default=0,
                     help="also time the standalone product with this many MiB evicted from the caches between "
                          "products (once by a write, once by a read)")
@@ -261,6 +263,27 @@ def main():
             thrash[mode] = {"us_per_call_median": t_med * 1e6, "GBps": st_op.algo_bytes_matvec / t_med / 1e9,
                             "frac_hbm": st_op.algo_bytes_matvec / t_med / 1e9 / HBM_PEAK_GBS}
         del junk
+    multi = None
+    if args.rhs > 0:
+        # the scaling study's evaluation: K~ times args.rhs right-hand sides
+        Wm = torch.randn(X.shape[0], args.rhs, dtype=torch.float64, device=dev)
+        op.matvec(Wm)
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(3):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            op.matvec(Wm)
+            b.record()
+            torch.cuda.synchronize()
+            times.append(a.elapsed_time(b) / 1e3)
+        t_med = float(np.median(times))
+        passes = (args.rhs + 15) // 16
+        multi = {"rhs": args.rhs, "s_per_product": t_med, "ms_per_rhs": t_med * 1e3 / args.rhs,
+                 "passes_of_16": passes,
+                 "GBps_near_tiles": st_op.near_tile_bytes * passes / t_med / 1e9,
+                 "what": "K~ times the right-hand sides (not normalised), median of 3"}
+        del Wm
     ev_acc = None
     gold = os.path.join(ROOT, "tests", "golden", f"eigs_{args.workload}.json")
     if os.path.exists(gold):
@@ -339,6 +362,7 @@ def main():
                      "algo_bytes_per_launch": algo_near,
                      "mfma_tflops": near_flops / l2l_avg_s / 1e12,
                      "mfma_frac_f16_peak": near_flops / l2l_avg_s / 1e12 / MFMA_F16_PEAK_TFLOPS},
+        "multi_rhs": multi,
         "serving": serve,
         "cpu_baseline": cpu,
     }

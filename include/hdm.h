@@ -186,7 +186,8 @@ hdm_status hdm_op_degrees(hdm_op op, double *q, double *d, double *c);
 /* ---- evaluation (Eq. (3); called once per Lanczos step) --------------------
  * y = K~ x (normalised = 0) or y = S~ x = c * K~ (c * x) (normalised = 1), the
  * symmetric conjugate of the Markov matrix of Alg. 1.  x, y: device float64,
- * n x nrhs column-major (ld = n), 1 <= nrhs <= 64, x and y must not overlap.
+ * n x nrhs column-major (ld = n), 1 <= nrhs <= 4096 (the scaling study of
+ * Sec. 4.2.3 evaluates 512), x and y must not overlap.
  * Tiles are applied in the operator's near/far precision with float32
  * accumulation (float64 when the tiles are float64).  Columns are taken 16 at a
  * time, each tile read once per pass.  Float16 near tiles run on the matrix

@@ -438,7 +438,7 @@ hdm_status hdm_op_degrees(hdm_op op, double* q, double* d, double* c) {
 hdm_status hdm_matvec(hdm_op op, int normalised, const double* x, double* y, int32_t nrhs, void* stream) {
     return guarded([&] {
         HDM_CHECK(op && x && y, HDM_EINVAL, "NULL argument");
-        HDM_CHECK(nrhs >= 1 && nrhs <= 64, HDM_EINVAL, "nrhs must be in [1, 64]");
+        HDM_CHECK(nrhs >= 1 && nrhs <= 4096, HDM_EINVAL, "nrhs must be in [1, 4096]");
         HDM_CHECK(x + static_cast<int64_t>(op->n) * nrhs <= y || y + static_cast<int64_t>(op->n) * nrhs <= x, HDM_EINVAL,
                   "x and y overlap");
         set_device(op->ctx->device);
@@ -450,7 +450,7 @@ hdm_status hdm_matvec(hdm_op op, int normalised, const double* x, double* y, int
 hdm_status hdm_matvec_noalloc(hdm_op op, int normalised, const double* x, double* y, int32_t nrhs, void* stream) {
     return guarded([&] {
         HDM_CHECK(op && x && y, HDM_EINVAL, "NULL argument");
-        HDM_CHECK(nrhs >= 1 && nrhs <= 64, HDM_EINVAL, "nrhs must be in [1, 64]");
+        HDM_CHECK(nrhs >= 1 && nrhs <= 4096, HDM_EINVAL, "nrhs must be in [1, 4096]");
         HDM_CHECK(x + static_cast<int64_t>(op->n) * nrhs <= y || y + static_cast<int64_t>(op->n) * nrhs <= x, HDM_EINVAL,
                   "x and y overlap");
         set_device(op->ctx->device);

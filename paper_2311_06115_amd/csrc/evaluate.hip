@@ -298,65 +298,176 @@ __global__ void k_n2s_up_m(Batch b) {
     }
 }
 
+__device__ inline int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
+// read-only descriptors through the constant address space: scalar loads,
+// which do not wait behind the tile loads in flight
+typedef const __attribute__((address_space(4))) NearItem cNearItem;
+typedef const __attribute__((address_space(4))) float cfloat;
+
 // ---- L2L: stream the near tiles; one wave per work item ---------------------
 // Lane l owns RPL consecutive rows (16 bytes of tile per lane per column) of
 // each 64*RPL-row pass over the item's rows; the item's columns are consecutive
 // tree positions, so w is read as a wave-uniform value.
+template <typename V, typename TN>
+__device__ __forceinline__ void l2l_one(const Batch& b, const OpDev& D, int64_t ui, int lane) {
+    constexpr int RPL = 16 / sizeof(TN);
+    const NearItem I = D.items1[ui];
+    const int rend = min(I.ld, I.row0 + I.nrows);
+    const V sc = D.nscale ? static_cast<V>(D.nscale[I.tile]) : V(1);
+    const TN* tiles = static_cast<const TN*>(D.near);
+    const V* wc = static_cast<const V*>(D.w) + I.col_pos;
+    for (int r0 = I.row0; r0 < rend; r0 += kWave * RPL) {
+        const int row = r0 + lane * RPL;
+        if (row >= rend) continue;
+        V acc[RPL];
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) acc[r] = 0;
+        const TN* col = tiles + I.tile_off + row;
+        int j = 0;
+        for (; j + 4 <= I.ncols; j += 4) {
+            TN v0[RPL], v1[RPL], v2[RPL], v3[RPL];
+            __builtin_memcpy(v0, col + static_cast<int64_t>(j) * I.ld, sizeof(v0));
+            __builtin_memcpy(v1, col + static_cast<int64_t>(j + 1) * I.ld, sizeof(v1));
+            __builtin_memcpy(v2, col + static_cast<int64_t>(j + 2) * I.ld, sizeof(v2));
+            __builtin_memcpy(v3, col + static_cast<int64_t>(j + 3) * I.ld, sizeof(v3));
+            const V w0 = wc[j] * sc, w1 = wc[j + 1] * sc, w2 = wc[j + 2] * sc, w3 = wc[j + 3] * sc;
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) {
+                acc[r] += val<V>(v0[r]) * w0;
+                acc[r] += val<V>(v1[r]) * w1;
+                acc[r] += val<V>(v2[r]) * w2;
+                acc[r] += val<V>(v3[r]) * w3;
+            }
+        }
+        for (; j < I.ncols; ++j) {
+            TN v0[RPL];
+            __builtin_memcpy(v0, col + static_cast<int64_t>(j) * I.ld, sizeof(v0));
+            const V w0 = wc[j] * sc;
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) acc[r] += val<V>(v0[r]) * w0;
+        }
+        V* out = static_cast<V*>(D.part) + I.part_off + row;
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) out[r] = acc[r];
+    }
+}
+
+// Several right-hand sides: each tile element is read once per group of CG
+// columns.  Lane l keeps RPL rows x CG columns of sums.  The group's weights of
+// the item's columns (one per right-hand side and tile column, the same for
+// every lane) are staged in the wave's slice of shared memory, one tile column's
+// CG weights contiguous, and read back as broadcasts; the tile's scale
+// multiplies the finished sums.  Columns past the last right-hand side repeat
+// its weights and store nothing.
+template <typename TN> constexpr int kL2lRpl = 16 / static_cast<int>(sizeof(TN));
+template <typename TN> constexpr int kL2lCols = kMaxRhs < 64 / kL2lRpl<TN> ? kMaxRhs : 64 / kL2lRpl<TN>;
+
+typedef uint32_t u4_t __attribute__((ext_vector_type(4)));
+typedef const __attribute__((address_space(1))) u4_t gu4_t;
+// 16 bytes from global memory as a global (not flat) load
+template <typename T>
+__device__ inline void gload_16b(T (&dst)[16 / sizeof(T)], const T* p) {
+    const u4_t v = *(gu4_t*)(p);
+    __builtin_memcpy(dst, &v, 16);
+}
+template <typename T>
+__device__ inline T gload1(const T* p) { return *(const __attribute__((address_space(1))) T*)(p); }
+
+template <typename V, typename TN>
+__device__ __forceinline__ void l2l_multi(const Batch& b, const OpDev& D, int64_t ui, int lane, V* ws) {
+    constexpr int RPL = kL2lRpl<TN>;
+    constexpr int CG = kL2lCols<TN>;
+    constexpr int JB = 4;   // tile columns per step; the next step's loads are in flight meanwhile
+    cNearItem* Ip = (cNearItem*)D.items + ui;
+    const int64_t tile_off = Ip->tile_off, part_off = Ip->part_off;
+    const int ld = Ip->ld, row0 = Ip->row0, ncols = Ip->ncols, col_pos = Ip->col_pos, tile = Ip->tile;
+    const int rend = min(ld, row0 + Ip->nrows);
+    const V sc = D.nscale ? static_cast<V>(*((cfloat*)D.nscale + tile)) : V(1);
+    const TN* tiles = static_cast<const TN*>(D.near) + tile_off;
+    const int64_t n = D.n, ldp = D.ldp;
+    const int last = b.nrhs - 1;
+    const int nsteps = (ncols + JB - 1) / JB;
+    for (int c0 = 0; c0 <= last; c0 += CG) {
+        {   // lane j stages tile column j's weights (ncols <= 64); zeros past the item's columns
+            const int j = min(lane, ncols - 1);
+            const V* wj = static_cast<const V*>(D.w) + col_pos + j;
+            V wv[CG];
+#pragma unroll
+            for (int c = 0; c < CG; ++c) wv[c] = gload1(wj + min(c0 + c, last) * n);
+#pragma unroll
+            for (int c = 0; c < CG; ++c) wv[c] = lane < ncols ? wv[c] : V(0);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_memcpy(ws + lane * CG, wv, sizeof(wv));
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+        for (int r0 = row0; r0 < rend; r0 += kWave * RPL) {
+            const int row = r0 + lane * RPL;
+            // lanes past the item's rows read its last row group and store nothing
+            const TN* col = tiles + min(row, rend - 1) / RPL * RPL;
+            V acc[RPL][CG];
+#pragma unroll
+            for (int r = 0; r < RPL; ++r)
+#pragma unroll
+                for (int c = 0; c < CG; ++c) acc[r][c] = 0;
+            // steps past the item's columns read its last column (their weights are zero)
+            auto load = [&](int step, TN (&t)[JB][RPL]) {
+#pragma unroll
+                for (int q = 0; q < JB; ++q)
+                    gload_16b(t[q], col + static_cast<int64_t>(min(step * JB + q, ncols - 1)) * ld);
+            };
+            TN cur[JB][RPL], nxt[JB][RPL];
+            load(0, cur);
+            for (int st = 0; st < nsteps; ++st) {
+                load(min(st + 1, nsteps - 1), nxt);
+#pragma unroll
+                for (int q = 0; q < JB; ++q) {
+                    V w0[CG];
+                    __builtin_memcpy(w0, ws + (st * JB + q) * CG, sizeof(w0));
+#pragma unroll
+                    for (int c = 0; c < CG; ++c)
+#pragma unroll
+                        for (int r = 0; r < RPL; ++r) acc[r][c] += val<V>(cur[q][r]) * w0[c];
+                }
+#pragma unroll
+                for (int q = 0; q < JB; ++q)
+#pragma unroll
+                    for (int r = 0; r < RPL; ++r) cur[q][r] = nxt[q][r];
+            }
+            if (row < rend) {
+                V* out = static_cast<V*>(D.part) + part_off + row;
+#pragma unroll
+                for (int c = 0; c < CG; ++c) {
+                    if (c0 + c > last) break;
+#pragma unroll
+                    for (int r = 0; r < RPL; ++r) out[(c0 + c) * ldp + r] = acc[r][c] * sc;
+                }
+            }
+        }
+    }
+}
+
 template <typename V, typename TN, bool kUp>
 __global__ void __launch_bounds__(kBlock) k_l2l(Batch b) {
-    constexpr int RPL = 16 / sizeof(TN);
     if (kUp && static_cast<int>(blockIdx.x) < b.up) {
         leaf_n2s<V>(b, blockIdx.x);
         return;
     }
     int64_t u = (blockIdx.x - b.up) * static_cast<int64_t>(blockDim.x / kWave) + threadIdx.x / kWave;
+    u = uni(static_cast<int>(u));   // wave-uniform: the descriptors load as scalars
     if (u >= b.pre[b.nops]) return;
     if (b.flip) u = b.pre[b.nops] - 1 - u;
     const int o = batch_op(b, u);
     const OpDev& D = *b.op[o];
-    const NearItem I = (b.nrhs > 1 ? D.items : D.items1)[u - b.pre[o]];
-    const int64_t ldp = b.nrhs > 1 ? D.ldp : D.ldp1;
     const int lane = threadIdx.x % kWave;
-    const int rend = min(I.ld, I.row0 + I.nrows);
-    const V sc = D.nscale ? static_cast<V>(D.nscale[I.tile]) : V(1);
-    const TN* tiles = static_cast<const TN*>(D.near);
-    for (int c = 0; c < b.nrhs; ++c) {
-        const V* wc = static_cast<const V*>(D.w) + c * D.n + I.col_pos;
-        for (int r0 = I.row0; r0 < rend; r0 += kWave * RPL) {
-            const int row = r0 + lane * RPL;
-            if (row >= rend) continue;
-            V acc[RPL];
-#pragma unroll
-            for (int r = 0; r < RPL; ++r) acc[r] = 0;
-            const TN* col = tiles + I.tile_off + row;
-            int j = 0;
-            for (; j + 4 <= I.ncols; j += 4) {
-                TN v0[RPL], v1[RPL], v2[RPL], v3[RPL];
-                __builtin_memcpy(v0, col + static_cast<int64_t>(j) * I.ld, sizeof(v0));
-                __builtin_memcpy(v1, col + static_cast<int64_t>(j + 1) * I.ld, sizeof(v1));
-                __builtin_memcpy(v2, col + static_cast<int64_t>(j + 2) * I.ld, sizeof(v2));
-                __builtin_memcpy(v3, col + static_cast<int64_t>(j + 3) * I.ld, sizeof(v3));
-                const V w0 = wc[j] * sc, w1 = wc[j + 1] * sc, w2 = wc[j + 2] * sc, w3 = wc[j + 3] * sc;
-#pragma unroll
-                for (int r = 0; r < RPL; ++r) {
-                    acc[r] += val<V>(v0[r]) * w0;
-                    acc[r] += val<V>(v1[r]) * w1;
-                    acc[r] += val<V>(v2[r]) * w2;
-                    acc[r] += val<V>(v3[r]) * w3;
-                }
-            }
-            for (; j < I.ncols; ++j) {
-                TN v0[RPL];
-                __builtin_memcpy(v0, col + static_cast<int64_t>(j) * I.ld, sizeof(v0));
-                const V w0 = wc[j] * sc;
-#pragma unroll
-                for (int r = 0; r < RPL; ++r) acc[r] += val<V>(v0[r]) * w0;
-            }
-            V* out = static_cast<V*>(D.part) + c * ldp + I.part_off + row;
-#pragma unroll
-            for (int r = 0; r < RPL; ++r) out[r] = acc[r];
-        }
-    }
+    __shared__ V wstage[kBlock / kWave][kWave * kL2lCols<TN>];
+    if (b.nrhs > 1)
+        l2l_multi<V, TN>(b, D, u - b.pre[o], lane, wstage[threadIdx.x / kWave]);
+    else
+        l2l_one<V, TN>(b, D, u - b.pre[o], lane);
 }
 
 // ---- combine: downward pass, near partial sums, scale, scatter ---------------
@@ -979,12 +1090,6 @@ struct MmaPos {
     float ws[kMaxRhs];
 };
 
-__device__ inline int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
-
-// read-only descriptors through the constant address space: scalar loads,
-// which do not wait behind the tile loads in flight
-typedef const __attribute__((address_space(4))) NearItem cNearItem;
-typedef const __attribute__((address_space(4))) float cfloat;
 
 __device__ inline void mma_tile(const OpDev& D, int t, MmaPos& p) {
     cNearItem* T = (cNearItem*)D.tiles + t;

@@ -1,8 +1,9 @@
 """Several right-hand sides per product and block Lanczos, against the oracle.
 
-* products with 2..20 right-hand sides (passes of at most 16) equal the oracle's
-  compressed product column by column: float64 tiles to 1e-12, float16 tiles
-  (packed for the matrix cores, vectors staged as hi + lo halves) to the format bound;
+* products with 2..33 right-hand sides (passes of at most 16) equal the oracle's
+  compressed product column by column: float64 tiles to 1e-12, float32, bfloat16
+  and float16 tiles (float16 packed for the matrix cores, vectors staged as
+  hi + lo halves) to the format bound;
 * block Lanczos (16 vectors per step) finds the oracle's eigenvalues of the same
   compressed operator, and its leading pair is the closed form (lambda_1 = 1,
   phi_1 proportional to sqrt(d)).
@@ -64,6 +65,28 @@ def test_multi_rhs_float64_product(name, nrhs):
     R = H.matvec(W)
     for c in range(nrhs):
         assert np.linalg.norm(U[:, c] - R[:, c]) <= 1e-12 * np.linalg.norm(R[:, c]), c
+
+
+# float32 and bfloat16 near tiles with several columns take the plain (not matrix
+# core) near field, one tile read per group of columns: the format bound per
+# column, and a column equals its single-column product up to float32 rounding
+PLAIN_TOL = {"f32": 2e-6, "bf16": 1.5e-2}
+
+
+@pytest.mark.parametrize("nrhs", [2, 9, 16, 20, 33])
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+@pytest.mark.parametrize("name", ["scurve-2k", "scurve-ragged-1537", "mnist-2k"])
+def test_multi_rhs_plain_reduced_product(name, prec, nrhs):
+    X, eps, op, H = build(name, prec, "f32")
+    W = np.random.default_rng(60 + nrhs).standard_normal((X.shape[0], nrhs))
+    U = op.matvec(torch.from_numpy(W).cuda()).cpu().numpy()
+    R = H.matvec(W)
+    errs = [np.linalg.norm(U[:, c] - R[:, c]) / np.linalg.norm(R[:, c]) for c in range(nrhs)]
+    print(f"[gpu] {name} {prec} nrhs={nrhs}: max rel err {max(errs):.2e}")
+    assert max(errs) <= PLAIN_TOL[prec]
+    for c in (0, nrhs - 1):
+        u1 = op.matvec(torch.from_numpy(np.ascontiguousarray(W[:, c])).cuda()).cpu().numpy()
+        assert np.linalg.norm(u1 - U[:, c]) <= 1e-6 * np.linalg.norm(U[:, c]), c
 
 
 # one product with float16 tiles: unit roundoff 2^-11 of the tiles plus float32 sums
