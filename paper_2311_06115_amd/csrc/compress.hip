@@ -1293,11 +1293,11 @@ __device__ inline double group_total(double* p) {
 }
 
 // squared norms over rows [0, nr) of every column, L lanes per column
-template <int L>
+template <int L, int NT>
 __device__ inline void id_norms(const QrBlock& Q, double* nsq, int nr, int nc) {
     constexpr int PH = 8 / L;
     const int lane = threadIdx.x % L;
-    for (int c = threadIdx.x / L; c < nc; c += kBlock / L) {
+    for (int c = threadIdx.x / L; c < nc; c += NT / L) {
         double p[PH];
 #pragma unroll
         for (int m = 0; m < PH; ++m) p[m] = 0.0;
@@ -1311,12 +1311,12 @@ __device__ inline void id_norms(const QrBlock& Q, double* nsq, int nr, int nc) {
 // L lanes per column, and leave their squared norms over rows [j + 1, nr) in
 // nsq.  A column's lanes are in one wave and its dot product is complete (the
 // shuffles consume every lane's loads) before any of its rows is stored.
-template <int L>
+template <int L, int NT>
 __device__ inline void id_reflect(const QrBlock& Q, const double* hv, double* nsq, int j, int nr, int nc,
                                   double vtv) {
     constexpr int PH = 8 / L;
     const int lane = threadIdx.x % L;
-    for (int c = j + 1 + threadIdx.x / L; c < nc; c += kBlock / L) {
+    for (int c = j + 1 + threadIdx.x / L; c < nc; c += NT / L) {
         double p[PH];
 #pragma unroll
         for (int m = 0; m < PH; ++m) p[m] = 0.0;
@@ -1450,10 +1450,12 @@ __device__ inline void id_back_subst(const QrBlock& Q, double* Pm, const int32_t
     }
 }
 
-// lanes per column for k remaining columns: as many as keep the workgroup busy
-__device__ inline int id_lanes(int k) { return k * 8 <= kBlock ? 8 : k * 4 <= kBlock ? 4 : k * 2 <= kBlock ? 2 : 1; }
+// lanes per column for k remaining columns: as many as keep the workgroup's NT threads busy
+template <int NT>
+__device__ inline int id_lanes(int k) { return k * 8 <= NT ? 8 : k * 4 <= NT ? 4 : k * 2 <= NT ? 2 : 1; }
 
 // workgroup argmax of (v, column) with ties to the lower column; every thread gets the result
+template <int NT>
 __device__ inline void wg_argmax(double& v, int& c, double* sv, int* sc) {
     for (int off = kWave / 2; off > 0; off >>= 1) {
         const double ov = __shfl_xor(v, off, kWave);
@@ -1465,31 +1467,43 @@ __device__ inline void wg_argmax(double& v, int& c, double* sv, int* sc) {
     __syncthreads();
     v = sv[0];
     c = sc[0];
-    for (int k = 1; k < kBlock / kWave; ++k)
+    for (int k = 1; k < NT / kWave; ++k)
         if (sv[k] > v || (sv[k] == v && sc[k] < c)) { v = sv[k]; c = sc[k]; }
     __syncthreads();
 }
 
 // rows x nc values from global memory (row stride nc) into staged rows
 // (stride ldS), eight loads in flight per thread
+template <int NT>
 __device__ inline void stage_rows(lds_f64* dst, int ldS, const double* src, int nc, int rows) {
     const int n = rows * nc;
-    for (int e0 = threadIdx.x; e0 < n; e0 += 8 * kBlock) {
+    for (int e0 = threadIdx.x; e0 < n; e0 += 8 * NT) {
         double v[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-            const int e = e0 + k * kBlock;
+            const int e = e0 + k * NT;
             v[k] = e < n ? src[e] : 0.0;
         }
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-            const int e = e0 + k * kBlock;
+            const int e = e0 + k * NT;
             if (e < n) dst[(e / nc) * ldS + e % nc] = v[k];
         }
     }
 }
 
-constexpr int kIdNodes = 128;   // measured at N = 100000 (256 leaves): 17.3 -> 17.1 ms per compression; 64: 18.9
+// Levels that sample more than kIdWideRows rows run the ID in workgroups of
+// kIdWide threads.  The register path of the 256-thread kernel (nodes of at most
+// 256 rows, once their rows are staged) does not fit the wider workgroup's
+// registers, so the wide kernel leaves it out; both paths and both sizes sum in
+// the same phase order, so the result does not depend on the choice.  Measured
+// at N = 100000 (s = 256): 16.2 -> 15.2 ms per compression (1024 threads: 17.6,
+// with register spills); MNIST-shaped N = 65536: 217 -> 195 ms.
+constexpr int kIdWide = 512;
+constexpr int kIdWideRows = 256;
+// leaves per ID launch (with 512-thread workgroups at N = 100000, 256 leaves:
+// 128 per launch 15.2 ms per compression, 256 14.8)
+constexpr int kIdNodes = 256;
 
 // Householder QR with column pivoting of B (nr x nc) and the interpolation
 // matrix P = [I, R11^-1 R12] in candidate order.  One workgroup per node, one
@@ -1497,10 +1511,11 @@ constexpr int kIdNodes = 128;   // measured at N = 100000 (256 leaves): 17.3 -> 
 // The trailing rows of B are staged in shared memory (as many as fit, A.lds_b
 // elements); the squared norms that choose the next pivot are accumulated
 // while the reflector is applied.
-__global__ void __launch_bounds__(kBlock) k_pivoted_id(LevelArgs A) {
+template <int NT>
+__global__ void __launch_bounds__(NT) k_pivoted_id(LevelArgs A) {
     extern __shared__ double dyn[];
-    __shared__ double sv[kBlock / kWave];
-    __shared__ int sc[kBlock / kWave];
+    __shared__ double sv[NT / kWave];
+    __shared__ int sc[NT / kWave];
     __shared__ double s_vtv, s_alpha;
     const int64_t t = A.node0 + blockIdx.x;
     const int nc = A.ncand[t], nr = A.nrows[t];
@@ -1517,7 +1532,7 @@ __global__ void __launch_bounds__(kBlock) k_pivoted_id(LevelArgs A) {
     int32_t* cp = A.cp + t * A.cmax;
     const int64_t h = (int64_t(1) << A.lvl) + t;
     double* Pm = A.Pfix + h * A.s * A.cmax;
-    stage_rows(Q.sB, Q.ldS, Q.gB + static_cast<int64_t>(Q.T0) * nc, nc, Q.R);
+    stage_rows<NT>(Q.sB, Q.ldS, Q.gB + static_cast<int64_t>(Q.T0) * nc, nc, Q.R);
     if (nc > 0) {
         // the padding columns of every staged row and the whole zero row
         const int pad = Q.ldS - nc;
@@ -1526,11 +1541,11 @@ __global__ void __launch_bounds__(kBlock) k_pivoted_id(LevelArgs A) {
     }
     for (int c = threadIdx.x; c < nc; c += blockDim.x) cp[c] = c;
     __syncthreads();
-    switch (id_lanes(nc)) {
-        case 8: id_norms<8>(Q, nsq, nr, nc); break;
-        case 4: id_norms<4>(Q, nsq, nr, nc); break;
-        case 2: id_norms<2>(Q, nsq, nr, nc); break;
-        default: id_norms<1>(Q, nsq, nr, nc); break;
+    switch (id_lanes<NT>(nc)) {
+        case 8: id_norms<8, NT>(Q, nsq, nr, nc); break;
+        case 4: id_norms<4, NT>(Q, nsq, nr, nc); break;
+        case 2: id_norms<2, NT>(Q, nsq, nr, nc); break;
+        default: id_norms<1, NT>(Q, nsq, nr, nc); break;
     }
     int kmax = nr < nc ? nr : nc;
     if (kmax > A.s) kmax = A.s;
@@ -1545,7 +1560,7 @@ __global__ void __launch_bounds__(kBlock) k_pivoted_id(LevelArgs A) {
             const double nrm = sqrt(nsq[c]);
             if (nrm > best || (nrm == best && c < bc)) { best = nrm; bc = c; }
         }
-        wg_argmax(best, bc, sv, sc);
+        wg_argmax<NT>(best, bc, sv, sc);
         const int piv = (bc >= j && bc < nc) ? bc : j;
         if (piv != j) {
             for (int i = threadIdx.x; i < nr; i += blockDim.x) {
@@ -1561,7 +1576,7 @@ __global__ void __launch_bounds__(kBlock) k_pivoted_id(LevelArgs A) {
         }
         if (j == 0) r11 = best;
         if (!(best > A.tau * r11)) break;   // uniform: every thread holds the same best and r11
-        if (j >= Q.T0 && nr <= 8 * 32) {
+        if (NT == kBlock && j >= Q.T0 && nr <= 8 * 32) {
             // rows [j, nr) all staged: the reflector lives in registers
             const double x0 = Q.sB[(j - Q.T0) * Q.ldS + j];
             const double alpha = x0 >= 0.0 ? -best : best;
@@ -1605,11 +1620,11 @@ __global__ void __launch_bounds__(kBlock) k_pivoted_id(LevelArgs A) {
         }
         __syncthreads();
         const double vtv = s_vtv;
-        switch (id_lanes(nc - j - 1)) {
-            case 8: id_reflect<8>(Q, hv, nsq, j, nr, nc, vtv); break;
-            case 4: id_reflect<4>(Q, hv, nsq, j, nr, nc, vtv); break;
-            case 2: id_reflect<2>(Q, hv, nsq, j, nr, nc, vtv); break;
-            default: id_reflect<1>(Q, hv, nsq, j, nr, nc, vtv); break;
+        switch (id_lanes<NT>(nc - j - 1)) {
+            case 8: id_reflect<8, NT>(Q, hv, nsq, j, nr, nc, vtv); break;
+            case 4: id_reflect<4, NT>(Q, hv, nsq, j, nr, nc, vtv); break;
+            case 2: id_reflect<2, NT>(Q, hv, nsq, j, nr, nc, vtv); break;
+            default: id_reflect<1, NT>(Q, hv, nsq, j, nr, nc, vtv); break;
         }
         __syncthreads();
         for (int i = j + threadIdx.x; i < nr; i += blockDim.x) Q.st(i, j, (i == j) ? s_alpha : 0.0);
@@ -1624,7 +1639,7 @@ __global__ void __launch_bounds__(kBlock) k_pivoted_id(LevelArgs A) {
     if (Q.T0 >= rank && 2 * rank <= Q.R) {
         // the rows of R are all in global memory and the staged rows are free
         // (they hold rows >= T0 >= rank): stage R at the front for the solve
-        stage_rows(Q.sB, Q.ldS, Q.gB, nc, rank);
+        stage_rows<NT>(Q.sB, Q.ldS, Q.gB, nc, rank);
         Q.T0 = 0;
         __syncthreads();
     }
@@ -1802,53 +1817,89 @@ __device__ inline float kval_scaled_f32(const double (&x)[D], const double (&y)[
     return __expf(static_cast<float>(sqd_regs<D>(x, y)) * neg_inv_eps) * inv_scale;
 }
 
+// Column points of a near tile in shared memory, kColStage at a time: slot c
+// holds column c0 + c (clamped to the last column), its D coordinates together.
+constexpr int kColStage = 256;
+
+template <int D>
+__device__ inline void stage_cols(const Pts& P, const int32_t* perm, int b0, int c0, int nb, double* cs) {
+    for (int e = threadIdx.x; e < kColStage * D; e += blockDim.x) {
+        const int c = e / D, d = e % D;
+        const int32_t idx = perm[b0 + min(c0 + c, nb - 1)];
+        cs[e] = d < P.dim ? P.xf[static_cast<int64_t>(idx) * P.dim + d] : 0.0;
+    }
+}
+
 // float16 tiles packed for the matrix cores: tile t is ld x kc (kc = nb rounded
-// up to 8, zero padded) with element (r, k) at ((k / 8) ld + r) 8 + k mod 8; one
-// thread writes the 8 consecutive columns of one row (16 bytes).  Consecutive
-// threads take consecutive rows of one 8-column group, so the group's column
-// points are the same for most of a wave (cached loads).
+// up to 8, zero padded) with element (r, k) at ((k / 8) ld + r) 8 + k mod 8.
+// Grid: (row blocks of kBlock rows, tiles).  A thread owns one row (its point in
+// registers) and writes the 8 consecutive columns of each group (16 bytes;
+// consecutive threads, consecutive rows); the column points come from shared
+// memory as broadcasts.
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_near_direct_f16(const NearPair* pairs, const int64_t* offp,
                                                             const int32_t* perm, Pts P, const float* scale,
                                                             _Float16* dst) {
+    __shared__ double cs[kColStage * D];
     const NearPair pr = pairs[blockIdx.y];
-    const uint32_t groups = static_cast<uint32_t>((pr.nb + 7) / 8);
-    const uint32_t tot = groups * static_cast<uint32_t>(pr.ld);
+    const int r = static_cast<int>(blockIdx.x) * kBlock + static_cast<int>(threadIdx.x);
+    if (static_cast<int>(blockIdx.x) * kBlock >= pr.ld) return;   // the whole workgroup
     const float inv = 1.0f / scale[blockIdx.y];
     const float nie = static_cast<float>(-1.0 / P.eps);
-    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += gridDim.x * blockDim.x) {
-        const int kg = static_cast<int>(e / static_cast<uint32_t>(pr.ld)), r = static_cast<int>(e % static_cast<uint32_t>(pr.ld));
-        double xr[D];
-        load_point<D>(P, perm[pr.a0 + min(r, pr.na - 1)], xr);
-        direct_h8 v;
+    double xr[D];
+    load_point<D>(P, perm[pr.a0 + min(r, pr.na - 1)], xr);
+    const int kc = (pr.nb + 7) / 8 * 8;
+    _Float16* out = dst + offp[blockIdx.y] + static_cast<int64_t>(r) * 8;
+    const int64_t gstride = static_cast<int64_t>(pr.ld) * 8;
+    for (int c0 = 0; c0 < kc; c0 += kColStage) {
+        __syncthreads();   // the previous chunk is read
+        stage_cols<D>(P, perm, pr.b0, c0, pr.nb, cs);
+        __syncthreads();
+        if (r >= pr.ld) continue;
+        const int cend = min(kc, c0 + kColStage);
+        for (int c = c0; c < cend; c += 8) {
+            direct_h8 v;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            double xc[D];
-            load_point<D>(P, perm[pr.b0 + min(kg * 8 + q, pr.nb - 1)], xc);
-            const bool in = r < pr.na && kg * 8 + q < pr.nb;
-            v[q] = static_cast<_Float16>(in ? kval_scaled_f32<D>(xr, xc, nie, inv) : 0.0f);
+            for (int q = 0; q < 8; ++q) {
+                double xc[D];
+#pragma unroll
+                for (int d = 0; d < D; ++d) xc[d] = cs[(c - c0 + q) * D + d];
+                const bool in = r < pr.na && c + q < pr.nb;
+                v[q] = static_cast<_Float16>(in ? kval_scaled_f32<D>(xr, xc, nie, inv) : 0.0f);
+            }
+            *reinterpret_cast<direct_h8*>(out + (c / 8) * gstride) = v;
         }
-        *reinterpret_cast<direct_h8*>(dst + offp[blockIdx.y] + static_cast<int64_t>(e) * 8) = v;
     }
 }
 
 // bfloat16 tiles (column-major ld x nb, padded rows zero): round-to-nearest-even
-// of K / scale in float32
+// of K / scale in float32; one thread per row as above, one column at a time
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_near_direct_bf16(const NearPair* pairs, const int32_t* perm, Pts P,
                                                              const float* scale, uint16_t* dst) {
+    __shared__ double cs[kColStage * D];
     const NearPair pr = pairs[blockIdx.y];
-    const uint32_t tot = static_cast<uint32_t>(pr.ld) * static_cast<uint32_t>(pr.nb);
+    const int r = static_cast<int>(blockIdx.x) * kBlock + static_cast<int>(threadIdx.x);
+    if (static_cast<int>(blockIdx.x) * kBlock >= pr.ld) return;   // the whole workgroup
     const float inv = 1.0f / scale[blockIdx.y];
     const float nie = static_cast<float>(-1.0 / P.eps);
-    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += gridDim.x * blockDim.x) {
-        const int i = static_cast<int>(e % static_cast<uint32_t>(pr.ld)), j = static_cast<int>(e / static_cast<uint32_t>(pr.ld));
-        double xr[D], xc[D];
-        load_point<D>(P, perm[pr.a0 + min(i, pr.na - 1)], xr);
-        load_point<D>(P, perm[pr.b0 + j], xc);
-        const float x = i < pr.na ? kval_scaled_f32<D>(xr, xc, nie, inv) : 0.0f;
-        const uint32_t u = __float_as_uint(x);
-        dst[pr.off + e] = static_cast<uint16_t>((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+    double xr[D];
+    load_point<D>(P, perm[pr.a0 + min(r, pr.na - 1)], xr);
+    uint16_t* out = dst + pr.off + r;
+    for (int c0 = 0; c0 < pr.nb; c0 += kColStage) {
+        __syncthreads();   // the previous chunk is read
+        stage_cols<D>(P, perm, pr.b0, c0, pr.nb, cs);
+        __syncthreads();
+        if (r >= pr.ld) continue;
+        const int cend = min(pr.nb, c0 + kColStage);
+        for (int c = c0; c < cend; ++c) {
+            double xc[D];
+#pragma unroll
+            for (int d = 0; d < D; ++d) xc[d] = cs[(c - c0) * D + d];
+            const float x = r < pr.na ? kval_scaled_f32<D>(xr, xc, nie, inv) : 0.0f;
+            const uint32_t u = __float_as_uint(x);
+            out[static_cast<int64_t>(c) * pr.ld] = static_cast<uint16_t>((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+        }
     }
 }
 
@@ -2244,16 +2295,23 @@ static void skeletonize_levels(Op& op, const Geo& G, hipStream_t s, SkelRun& R, 
         int dev = 0, max_shared = 0;
         HDM_HIP(hipGetDevice(&dev));
         HDM_HIP(hipDeviceGetAttribute(&max_shared, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-        hipFuncAttributes fa{};
-        HDM_HIP(hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(&k_pivoted_id)));
-        const int64_t avail = (static_cast<int64_t>(max_shared) - static_cast<int64_t>(fa.sharedSizeBytes)) /
+        // both workgroup sizes stage the same rows (the larger static part decides)
+        const void* id_fns[2] = {reinterpret_cast<const void*>(&k_pivoted_id<kBlock>),
+                                 reinterpret_cast<const void*>(&k_pivoted_id<kIdWide>)};
+        size_t stat = 0;
+        for (const void* f : id_fns) {
+            hipFuncAttributes fa{};
+            HDM_HIP(hipFuncGetAttributes(&fa, f));
+            stat = std::max(stat, fa.sharedSizeBytes);
+        }
+        const int64_t avail = (static_cast<int64_t>(max_shared) - static_cast<int64_t>(stat)) /
                               static_cast<int64_t>(sizeof(double));
         HDM_CHECK(avail >= rmax + cmax, HDM_EINTERNAL, "shared memory too small for the ID's vectors");
         id_lds = avail - rmax - cmax;
         id_shmem = sizeof(double) * static_cast<size_t>(rmax + cmax + id_lds);
         if (id_shmem > 65536)
-            HDM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pivoted_id),
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(id_shmem)));
+            for (const void* f : id_fns)
+                HDM_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(id_shmem)));
     }
     // row selection: the neighbour votes are counted through a bitmap over the
     // points in shared memory when it fits, else in a dense per-node array
@@ -2340,7 +2398,10 @@ static void skeletonize_levels(Op& op, const Geo& G, hipStream_t s, SkelRun& R, 
         const int per = lvl == op.depth ? std::min(kIdNodes, nodes) : nodes;
         for (int t0 = 0; t0 < nodes; t0 += per) {
             A.node0 = t0;
-            hipLaunchKernelGGL(k_pivoted_id, dim3(std::min(per, nodes - t0)), dim3(kBlock), id_shmem, s, A);
+            if (rmax > kIdWideRows)
+                hipLaunchKernelGGL(k_pivoted_id<kIdWide>, dim3(std::min(per, nodes - t0)), dim3(kIdWide), id_shmem, s, A);
+            else
+                hipLaunchKernelGGL(k_pivoted_id<kBlock>, dim3(std::min(per, nodes - t0)), dim3(kBlock), id_shmem, s, A);
         }
         A.node0 = 0;
         check_launch("skeletonisation");
@@ -2451,7 +2512,9 @@ static void build_near_tiles(Op& op, const Geo& G, hipStream_t s) {
             op.near_scale.alloc(static_cast<size_t>(np));
             HDM_DIM_DISPATCH(P.dim, k_near_scale, dim3(static_cast<unsigned>(np)), dim3(kBlock), 0, s, pairs_dev,
                              op.perm.get(), P, op.near_scale.get());
-            const unsigned gx = static_cast<unsigned>(std::min<int64_t>(ceil_div(maxe, 8 * kBlock), 64));
+            int32_t maxld = 0;
+            for (auto& p : pairs) maxld = std::max(maxld, p.ld);
+            const unsigned gx = static_cast<unsigned>(ceil_div(static_cast<int64_t>(maxld), kBlock));
             if (op.prm.near_prec == HDM_BF16) {
                 op.nearT.alloc(static_cast<size_t>(std::max<int64_t>(op.near_elems, 1)) * sizeof(uint16_t));
                 for (int64_t base = 0; base < np; base += 65535) {
