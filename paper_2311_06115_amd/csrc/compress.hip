@@ -2227,7 +2227,9 @@ struct SkelRun {
 // stream from the level with at most kSideGateNodes nodes on: the levels above
 // are latency-bound (a few workgroups each) and leave the device mostly idle,
 // while the leaf levels need its bandwidth (0: from the start).
-constexpr int kSideGateNodes = 8;   // N = 100000: 0 -> 17.1 ms, 64 -> 18.1, 16 -> 16.4, 8 -> 16.1, 4 -> 16.8, 2 -> 17.9
+// N = 100000, ms per compression: 0 -> 15.3, 32 -> 14.8, 8 -> 15.2, 2 -> 14.7 (with
+// the shared-memory tile kernels; the spread is near the run-to-run noise)
+constexpr int kSideGateNodes = 32;
 
 static void skeletonize_levels(Op& op, const Geo& G, hipStream_t s, SkelRun& R, hipEvent_t gate) {
     const Pts& P = G.P;

@@ -663,7 +663,7 @@ __global__ void __launch_bounds__(kCombBlock) k_combine(Batch b) {
 // complete: one workgroup per node, thread j owns column j of the parent's P
 // slice (consecutive threads read consecutive entries of a P row) and sums over
 // the parent's rows in increasing order, the arithmetic of the combine's walk.
-template <typename V, typename TP, bool kMulti>
+template <typename V, typename TP>
 __global__ void __launch_bounds__(kBlock) k_s2n(Batch b) {
     const int64_t u = blockIdx.x;
     const int o = batch_op(b, u);
@@ -675,34 +675,96 @@ __global__ void __launch_bounds__(kBlock) k_s2n(Batch b) {
     const int coff = (h & 1) ? D.rank[2 * p] : 0;
     const TP* Pp = static_cast<const TP*>(D.P) + D.poff[p] + coff;
     V* sku = static_cast<V*>(D.sku);
-    const int64_t ldsk = D.ldsk, sp = D.skoff[p], sh = D.skoff[h];
-    constexpr int NC = kMulti ? kMaxRhs : 1;
-    const int last = b.nrhs - 1;
-    constexpr int IB = kMulti ? 4 : 16;   // rows of P in flight per thread
+    const int64_t sp = D.skoff[p], sh = D.skoff[h];
+    constexpr int IB = 16;   // rows of P in flight per thread
     for (int j = threadIdx.x; j < rn; j += blockDim.x) {
-        V acc[NC];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) acc[c] = 0;
+        V acc = 0;
         // the last batch clamps its indexes and adds only the rows in range
         for (int i0 = 0; i0 < rp; i0 += IB) {
-            V pv[IB], uv[IB][NC];
+            V pv[IB], uv[IB];
 #pragma unroll
             for (int t = 0; t < IB; ++t) {
                 const int i = min(i0 + t, rp - 1);
                 pv[t] = static_cast<V>(Pp[static_cast<int64_t>(i) * ncp + j]);
-#pragma unroll
-                for (int c = 0; c < NC; ++c) uv[t][c] = sku[min(c, last) * ldsk + sp + i];
+                uv[t] = sku[sp + i];
             }
 #pragma unroll
             for (int t = 0; t < IB; ++t)
-                if (i0 + t < rp) {
-#pragma unroll
-                    for (int c = 0; c < NC; ++c) acc[c] += pv[t] * uv[t][c];
-                }
+                if (i0 + t < rp) acc += pv[t] * uv[t];
         }
+        sku[sh + j] = sku[sh + j] + acc;
+    }
+}
+
+// Several right-hand sides: workgroup (node h of level lvl, 64 of its rank
+// columns from 64 blockIdx.y on); lane l owns column j = 64 blockIdx.y + l.  The
+// parent's potentials are staged in shared memory kS2nRows rows at a time (one
+// row's kMaxRhs values together, read back as broadcasts); wave w adds the rows
+// w, w + 4, ... in increasing order, and the four waves' sums are added in wave
+// order.
+constexpr int kS2nRows = 256;
+
+template <typename V, typename TP>
+__global__ void __launch_bounds__(kBlock) k_s2n_m(Batch b) {
+    constexpr int NW = kBlock / kWave;
+    static_assert(NW * kWave <= kS2nRows, "the waves' sums reuse the staging rows");
+    __shared__ V st[kS2nRows * kMaxRhs];
+    const int64_t u = blockIdx.x;
+    const int o = batch_op(b, u);
+    const OpDev& D = *b.op[o];
+    const int lvl = b.arg[o];
+    const int64_t h = (int64_t(1) << lvl) + (u - b.pre[o]);
+    const int64_t p = h >> 1;
+    const int rn = D.rank[h];
+    const int j0 = static_cast<int>(blockIdx.y) * kWave;
+    if (j0 >= rn) return;   // the whole workgroup
+    const int rp = D.rank[p], ncp = D.ncand[p];
+    const int coff = (h & 1) ? D.rank[2 * p] : 0;
+    const TP* Pp = static_cast<const TP*>(D.P) + D.poff[p] + coff;
+    V* sku = static_cast<V*>(D.sku);
+    const int64_t ldsk = D.ldsk, sp = D.skoff[p], sh = D.skoff[h];
+    const int last = b.nrhs - 1;
+    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+    const int j = min(j0 + lane, rn - 1);
+    V acc[kMaxRhs];
 #pragma unroll
-        for (int c = 0; c < NC; ++c)
-            if (c <= last) sku[c * ldsk + sh + j] = sku[c * ldsk + sh + j] + acc[c];
+    for (int c = 0; c < kMaxRhs; ++c) acc[c] = 0;
+    constexpr int IB = 4;   // rows of P in flight per lane
+    for (int r0 = 0; r0 < rp; r0 += kS2nRows) {
+        const int nrow = min(kS2nRows, rp - r0);
+        __syncthreads();   // the previous rows are read
+        for (int e = threadIdx.x; e < nrow * kMaxRhs; e += kBlock) {
+            const int i = e / kMaxRhs, c = e % kMaxRhs;
+            st[e] = sku[min(c, last) * ldsk + sp + r0 + i];
+        }
+        __syncthreads();
+        for (int i = w; i < nrow; i += NW * IB) {
+            V pv[IB];
+#pragma unroll
+            for (int t = 0; t < IB; ++t)
+                pv[t] = static_cast<V>(Pp[static_cast<int64_t>(r0 + min(i + t * NW, nrow - 1)) * ncp + j]);
+#pragma unroll
+            for (int t = 0; t < IB; ++t) {
+                if (i + t * NW >= nrow) break;
+                V pot[kMaxRhs];
+                __builtin_memcpy(pot, st + (i + t * NW) * kMaxRhs, sizeof(pot));
+#pragma unroll
+                for (int c = 0; c < kMaxRhs; ++c) acc[c] += pv[t] * pot[c];
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < kMaxRhs; ++c) st[(w * kMaxRhs + c) * kWave + lane] = acc[c];
+    __syncthreads();
+    for (int e = threadIdx.x; e < kMaxRhs * kWave; e += kBlock) {
+        const int c = e / kWave, l = e % kWave;
+        if (c > last || j0 + l >= rn) continue;
+        V t = st[c * kWave + l];
+#pragma unroll
+        for (int q = 1; q < NW; ++q) t += st[(q * kMaxRhs + c) * kWave + l];
+        V* dst = sku + c * ldsk + sh + j0 + l;
+        *dst = *dst + t;
     }
 }
 
@@ -742,6 +804,54 @@ __global__ void k_n2s_m(Batch b) {
         if (lane == 0) skw[c * D.ldsk + D.skoff[T.h] + T.i] = t;
     }
 }
+
+// The same rows, one workgroup per node of level lvl (b.arg): the node's input
+// (its points' staged values at the leaves, its children's skeleton values
+// above) in shared memory, kMaxRhs columns of nc values, then wave w forms the
+// node's skeleton rows w, w + 4, ... with k_n2s_m's arithmetic (lane l: the
+// candidates l, l + 64, ... in increasing order, then the wave's butterfly).
+template <typename V, typename TP>
+__global__ void __launch_bounds__(kBlock) k_n2s_node_m(Batch b) {
+    extern __shared__ char n2s_dyn[];
+    V* xin = reinterpret_cast<V*>(n2s_dyn);
+    const int64_t u = blockIdx.x;
+    const int o = batch_op(b, u);
+    const OpDev& D = *b.op[o];
+    const int lvl = b.arg[o];
+    const int64_t h = (int64_t(1) << lvl) + (u - b.pre[o]);
+    const int nc = D.ncand[h], rk = D.rank[h];
+    const bool leaf = lvl == D.depth;
+    const V* in = leaf ? static_cast<const V*>(D.w) + D.start[h] : static_cast<const V*>(D.skw) + D.skoff[2 * h];
+    const int64_t ldin = leaf ? D.n : D.ldsk;
+    const int last = b.nrhs - 1;
+    for (int e = threadIdx.x; e < kMaxRhs * nc; e += kBlock) {
+        const int c = e / nc, j = e % nc;
+        xin[e] = in[min(c, last) * ldin + j];
+    }
+    __syncthreads();
+    const TP* P = static_cast<const TP*>(D.P) + D.poff[h];
+    V* skw = static_cast<V*>(D.skw);
+    const int lane = threadIdx.x % kWave;
+    for (int i = threadIdx.x / kWave; i < rk; i += kBlock / kWave) {
+        const TP* row = P + static_cast<int64_t>(i) * nc;
+        V acc[kMaxRhs];
+#pragma unroll
+        for (int c = 0; c < kMaxRhs; ++c) acc[c] = 0;
+        for (int j = lane; j < nc; j += kWave) {
+            const V p = val<V>(row[j]);
+#pragma unroll
+            for (int c = 0; c < kMaxRhs; ++c) acc[c] += p * xin[c * nc + j];
+        }
+#pragma unroll
+        for (int c = 0; c < kMaxRhs; ++c) {
+            if (c > last) break;
+            const V t = wave_sum(acc[c]);
+            if (lane == 0) skw[c * D.ldsk + D.skoff[h] + i] = t;
+        }
+    }
+}
+// largest shared-memory input of k_n2s_node_m (nodes with more candidates take k_n2s_m)
+constexpr int kN2sNodeBytes = 65536;
 
 template <typename V, typename TF>
 __global__ void k_s2s_m(Batch b) {
@@ -849,7 +959,7 @@ __global__ void __launch_bounds__(kCombBlock) k_combine_m(Batch b) {
     __syncthreads();
     // the walk starts at level 1, or at the leaf when a per-level downward pass
     // has completed every potential already
-    const int top = D.s2n_levels && depth >= 1 ? depth : 1;
+    const int top = D.s2n_multi && depth >= 1 ? depth : 1;
     if (depth >= 1) {
         const int r1 = m_rn[top];
         for (int e = tid; e < nr * r1; e += kCombBlock) {
@@ -1411,6 +1521,7 @@ static void publish_descriptors(Op& op, hipStream_t s) {
                               : nullptr;
         D.coff = op.d_coff;
         D.s2n_levels = op.s2n_levels ? 1 : 0;
+        D.s2n_multi = op.s2n_multi ? 1 : 0;
         if (!f64 && op.packed) {   // matrix-core plan of the packed half-precision tiles
             D.items = op.d_items_mma[1].get();
             D.nitems = static_cast<int64_t>(op.items_mma[1].size());
@@ -1740,6 +1851,18 @@ void build_eval_plan(Op& op, hipStream_t s) {
         int max_inner = 0;
         for (int64_t h = 2; h < op.L; ++h) max_inner = std::max(max_inner, static_cast<int>(op.rank[h]));
         if (max_inner > kMaxRank) op.s2n_levels = true;
+        // several right-hand sides: always level by level (one launch per level
+        // on the side stream, beside the near field, instead of a chain of
+        // dependent steps per leaf in the combine)
+        op.s2n_multi = op.s2n_levels || (nested && op.depth >= 2);
+        op.lvl_max_nc.assign(kMaxLevels + 1, 0);
+        op.lvl_max_rank.assign(kMaxLevels + 1, 0);
+        for (int64_t h = 2; h < 2 * op.L; ++h) {
+            int lvl = 0;
+            while ((int64_t(2) << lvl) <= h) ++lvl;
+            op.lvl_max_nc[lvl] = std::max(op.lvl_max_nc[lvl], static_cast<int32_t>(op.ncand[h]));
+            op.lvl_max_rank[lvl] = std::max(op.lvl_max_rank[lvl], static_cast<int32_t>(op.rank[h]));
+        }
         op.max_leaf_rank = 0;
         for (int64_t h = op.L; h < 2 * op.L; ++h) op.max_leaf_rank = std::max(op.max_leaf_rank, static_cast<int>(op.rank[h]));
     }
@@ -1797,6 +1920,11 @@ void build_eval_plan(Op& op, hipStream_t s) {
     op.lane.init(op.ctx ? &op.ctx->lanes : nullptr);
     ensure_ws(op, 1);
     publish_descriptors(op, s);
+}
+
+// shared memory of k_n2s_node_m at tree level lvl
+static size_t n2s_node_bytes(const Op& op, int lvl, size_t vsize) {
+    return static_cast<size_t>(kMaxRhs) * static_cast<size_t>(op.lvl_max_nc[lvl]) * vsize;
 }
 
 template <typename V, typename TN, typename TF, typename TP>
@@ -1912,6 +2040,23 @@ static void apply_t(const ApplyReq* reqs, int nops, bool f64, int normalised, in
             PhaseScope ph(cx, HDM_PHASE_N2S, ts);
             auto level_launch = [&](int k, bool with_comp) {
                 for (int o = 0; o < nops; ++o) b.arg[o] = reqs[o].op->depth - k;
+                auto active = [&](const Op& op) {
+                    const int lvl = op.depth - k;
+                    return lvl >= 1 && (with_comp || op.ncomp == 0);
+                };
+                if (multi) {   // one workgroup per node where the inputs fit shared memory
+                    size_t shm = 0;
+                    for (int o = 0; o < nops; ++o)
+                        if (active(*reqs[o].op)) shm = std::max(shm, n2s_node_bytes(*reqs[o].op, reqs[o].op->depth - k, sizeof(V)));
+                    if (shm <= static_cast<size_t>(kN2sNodeBytes)) {
+                        const int64_t nodes = prefix([&](const Op& op, int) {
+                            return active(op) ? int64_t(1) << (op.depth - k) : int64_t(0);
+                        });
+                        if (nodes > 0)
+                            hipLaunchKernelGGL((k_n2s_node_m<V, TP>), dim3(nodes), dim3(kBlock), shm, ts, b);
+                        return;
+                    }
+                }
                 const int64_t tot = prefix([&](const Op& op, int) {
                     const int lvl = op.depth - k;
                     return lvl >= 1 && (with_comp || op.ncomp == 0) ? op.row_count[lvl] : int64_t(0);
@@ -1946,20 +2091,27 @@ static void apply_t(const ApplyReq* reqs, int nops, bool f64, int normalised, in
                                           ev.stop, 0, b);
             }
         }
+        // S2N level by level for the operators that take it (large ranks; every
+        // product with several right-hand sides)
+        auto levels = [multi](const Op& op) { return multi ? op.s2n_multi : op.s2n_levels; };
         bool any_s2n = false;
-        for (int o = 0; o < nops; ++o) any_s2n = any_s2n || reqs[o].op->s2n_levels;
-        if (any_s2n) {   // S2N level by level for the operators that take it (large ranks)
+        for (int o = 0; o < nops; ++o) any_s2n = any_s2n || levels(*reqs[o].op);
+        if (any_s2n) {
             PhaseScope ph(cx, HDM_PHASE_S2N, ts);
             for (int lvl = 2; lvl <= maxdepth; ++lvl) {
                 for (int o = 0; o < nops; ++o) b.arg[o] = lvl;
-                const int64_t tot = prefix([lvl](const Op& op, int) {
-                    return op.s2n_levels && lvl <= op.depth ? int64_t(1) << lvl : int64_t(0);
+                const int64_t tot = prefix([&](const Op& op, int) {
+                    return levels(op) && lvl <= op.depth ? int64_t(1) << lvl : int64_t(0);
                 });
                 if (tot == 0) continue;
-                if (multi)
-                    hipLaunchKernelGGL((k_s2n<V, TP, true>), dim3(tot), dim3(kBlock), 0, ts, b);
-                else
-                    hipLaunchKernelGGL((k_s2n<V, TP, false>), dim3(tot), dim3(kBlock), 0, ts, b);
+                if (multi) {
+                    int rmax = 1;
+                    for (int o = 0; o < nops; ++o)
+                        if (lvl <= reqs[o].op->depth) rmax = std::max(rmax, reqs[o].op->lvl_max_rank[lvl]);
+                    hipLaunchKernelGGL((k_s2n_m<V, TP>), dim3(tot, ceil_div(rmax, kWave)), dim3(kBlock), 0, ts, b);
+                } else {
+                    hipLaunchKernelGGL((k_s2n<V, TP>), dim3(tot), dim3(kBlock), 0, ts, b);
+                }
             }
         }
     }
@@ -2066,13 +2218,13 @@ static void build_product_graph(Op& op, bool f64, int normalised, int nrhs, Prod
     base.op[0] = f64 ? op.dev64.get() : op.devT.get();
     base.pre[0] = 0;
     auto kernel = [&](void* func, dim3 grid, Batch bb, std::vector<hipGraphNode_t> deps, hipKernelNodeParams* keep,
-                      int threads = kBlock) {
+                      int threads = kBlock, size_t shm = 0) {
         hipKernelNodeParams p{};
         void* args[] = {&bb};
         p.func = func;
         p.gridDim = grid;
         p.blockDim = dim3(threads);
-        p.sharedMemBytes = 0;
+        p.sharedMemBytes = static_cast<unsigned>(shm);
         p.kernelParams = args;
         p.extra = nullptr;
         hipGraphNode_t n = nullptr;
@@ -2110,13 +2262,18 @@ static void build_product_graph(Op& op, bool f64, int normalised, int nrhs, Prod
     std::vector<hipGraphNode_t> comb_deps{near};
     // S2N by level after the far field, for operators with large ranks (as eager)
     auto s2n_levels = [&](hipGraphNode_t last) {
-        if (!op.s2n_levels) return last;
+        if (!(multi ? op.s2n_multi : op.s2n_levels)) return last;
         for (int lvl = 2; lvl <= op.depth; ++lvl) {
             Batch bn = base;
             bn.arg[0] = lvl;
             bn.pre[1] = int64_t(1) << lvl;
-            last = kernel(multi ? reinterpret_cast<void*>(&k_s2n<V, TP, true>) : reinterpret_cast<void*>(&k_s2n<V, TP, false>),
-                          dim3(static_cast<unsigned>(bn.pre[1])), bn, {last}, nullptr);
+            if (multi)
+                last = kernel(reinterpret_cast<void*>(&k_s2n_m<V, TP>),
+                              dim3(static_cast<unsigned>(bn.pre[1]), ceil_div(std::max(op.lvl_max_rank[lvl], 1), kWave)),
+                              bn, {last}, nullptr);
+            else
+                last = kernel(reinterpret_cast<void*>(&k_s2n<V, TP>), dim3(static_cast<unsigned>(bn.pre[1])), bn, {last},
+                              nullptr);
         }
         return last;
     };
@@ -2162,6 +2319,13 @@ static void build_product_graph(Op& op, bool f64, int normalised, int nrhs, Prod
             }
             Batch bn = base;
             bn.arg[0] = lvl;
+            const size_t shm = n2s_node_bytes(op, lvl, sizeof(V));
+            if (multi && shm <= static_cast<size_t>(kN2sNodeBytes)) {   // one workgroup per node (as eager)
+                bn.pre[1] = int64_t(1) << lvl;
+                last = kernel(reinterpret_cast<void*>(&k_n2s_node_m<V, TP>), dim3(static_cast<unsigned>(bn.pre[1])), bn,
+                              {last}, nullptr, kBlock, shm);
+                continue;
+            }
             bn.pre[1] = op.row_count[lvl];
             last = kernel(multi ? reinterpret_cast<void*>(&k_n2s_m<V, TP>) : reinterpret_cast<void*>(&k_n2s<V, TP>),
                           dim3(ceil_div(op.row_count[lvl], wpb)), bn, {last}, nullptr);

@@ -168,6 +168,7 @@ struct OpDev {
     int64_t ldw;
     const void* comp;             // composites of the nested bases (nullptr: level by level)
     int32_t s2n_levels;           // 1: the downward pass runs level by level before the combine
+    int32_t s2n_multi;            // the same for products with several right-hand sides
     const int64_t* coff;
 };
 
@@ -301,7 +302,9 @@ struct Op {
     std::vector<int64_t> coff;                 // per heap id
     int64_t ncomp = 0;
     bool s2n_levels = false;   // downward pass in per-level launches (large ranks) instead of per leaf path
+    bool s2n_multi = false;    // the same for several right-hand sides (every nested tree of depth >= 2)
     int max_leaf_rank = 0;
+    std::vector<int32_t> lvl_max_nc, lvl_max_rank;   // per tree level: largest candidate count and rank
     DevBuf<double> C64;
     DevBuf<float> C32;
     const int64_t* d_coff = nullptr;           // in plan_blob
