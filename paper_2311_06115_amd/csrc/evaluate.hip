@@ -805,11 +805,16 @@ __global__ void k_n2s_m(Batch b) {
     }
 }
 
-// The same rows, one workgroup per node of level lvl (b.arg): the node's input
-// (its points' staged values at the leaves, its children's skeleton values
-// above) in shared memory, kMaxRhs columns of nc values, then wave w forms the
-// node's skeleton rows w, w + 4, ... with k_n2s_m's arithmetic (lane l: the
-// candidates l, l + 64, ... in increasing order, then the wave's butterfly).
+// The same rows, workgroups per node of level lvl (b.arg), kN2sNodeRows rows
+// each (blockIdx.y: the chunk of rows): the node's input (its points' staged
+// values at the leaves, its children's skeleton values above) in shared memory,
+// kMaxRhs columns of nc values, then each wave forms four rows at once with
+// k_n2s_m's arithmetic per row (lane l: the candidates l, l + 64, ... in
+// increasing order, then the wave's butterfly); the input values read from
+// shared memory serve the four rows.
+constexpr int kN2sWaveRows = 4;
+constexpr int kN2sNodeRows = kN2sWaveRows * (kBlock / kWave);
+
 template <typename V, typename TP>
 __global__ void __launch_bounds__(kBlock) k_n2s_node_m(Batch b) {
     extern __shared__ char n2s_dyn[];
@@ -820,6 +825,8 @@ __global__ void __launch_bounds__(kBlock) k_n2s_node_m(Batch b) {
     const int lvl = b.arg[o];
     const int64_t h = (int64_t(1) << lvl) + (u - b.pre[o]);
     const int nc = D.ncand[h], rk = D.rank[h];
+    const int i0 = static_cast<int>(blockIdx.y) * kN2sNodeRows;
+    if (i0 >= rk) return;   // the whole workgroup
     const bool leaf = lvl == D.depth;
     const V* in = leaf ? static_cast<const V*>(D.w) + D.start[h] : static_cast<const V*>(D.skw) + D.skoff[2 * h];
     const int64_t ldin = leaf ? D.n : D.ldsk;
@@ -832,23 +839,35 @@ __global__ void __launch_bounds__(kBlock) k_n2s_node_m(Batch b) {
     const TP* P = static_cast<const TP*>(D.P) + D.poff[h];
     V* skw = static_cast<V*>(D.skw);
     const int lane = threadIdx.x % kWave;
-    for (int i = threadIdx.x / kWave; i < rk; i += kBlock / kWave) {
-        const TP* row = P + static_cast<int64_t>(i) * nc;
-        V acc[kMaxRhs];
+    const int ir = i0 + (static_cast<int>(threadIdx.x) / kWave) * kN2sWaveRows;   // the wave's first row
+    if (ir >= rk) return;
+    const TP* rows[kN2sWaveRows];
 #pragma unroll
-        for (int c = 0; c < kMaxRhs; ++c) acc[c] = 0;
-        for (int j = lane; j < nc; j += kWave) {
-            const V p = val<V>(row[j]);
+    for (int t = 0; t < kN2sWaveRows; ++t) rows[t] = P + static_cast<int64_t>(min(ir + t, rk - 1)) * nc;
+    V acc[kN2sWaveRows][kMaxRhs];
 #pragma unroll
-            for (int c = 0; c < kMaxRhs; ++c) acc[c] += p * xin[c * nc + j];
-        }
+    for (int t = 0; t < kN2sWaveRows; ++t)
+#pragma unroll
+        for (int c = 0; c < kMaxRhs; ++c) acc[t][c] = 0;
+    for (int j = lane; j < nc; j += kWave) {
+        V p[kN2sWaveRows];
+#pragma unroll
+        for (int t = 0; t < kN2sWaveRows; ++t) p[t] = val<V>(rows[t][j]);
 #pragma unroll
         for (int c = 0; c < kMaxRhs; ++c) {
-            if (c > last) break;
-            const V t = wave_sum(acc[c]);
-            if (lane == 0) skw[c * D.ldsk + D.skoff[h] + i] = t;
+            const V x = xin[c * nc + j];
+#pragma unroll
+            for (int t = 0; t < kN2sWaveRows; ++t) acc[t][c] += p[t] * x;
         }
     }
+#pragma unroll
+    for (int t = 0; t < kN2sWaveRows; ++t)
+#pragma unroll
+        for (int c = 0; c < kMaxRhs; ++c)
+            if (ir + t < rk && c <= last) {   // wave-uniform
+                const V s = wave_sum(acc[t][c]);
+                if (lane == 0) skw[c * D.ldsk + D.skoff[h] + ir + t] = s;
+            }
 }
 // largest shared-memory input of k_n2s_node_m (nodes with more candidates take k_n2s_m)
 constexpr int kN2sNodeBytes = 65536;
@@ -1133,35 +1152,48 @@ __global__ void __launch_bounds__(kBlock) k_prep_mma(Batch b) {
     if (threadIdx.x < kMaxRhs) smax[threadIdx.x] = 0u;
     __syncthreads();
     float* w = static_cast<float*>(D.w);
-    for (int e = threadIdx.x; e < nrhs * nr; e += blockDim.x) {
-        const int c = e / nr, p = e % nr;
-        const int64_t pos = lp.start + p;
-        const double sc = b.arg[o] ? D.c[pos] : 1.0;
-        const float v = static_cast<float>(sc * b.x[o][c * D.n + D.perm[pos]]);
-        w[c * D.n + pos] = v;
-        atomicMax(&smax[c], __float_as_uint(fabsf(v)));
-    }
-    __syncthreads();
-    _Float16* hi = static_cast<_Float16*>(D.wh);
-    _Float16* lo = hi + kMaxRhs * D.ldw;
-    for (int e = threadIdx.x; e < nrhs * kc; e += blockDim.x) {
-        const int c = e / kc, p = e % kc;
-        const float m = __uint_as_float(smax[c]);
-        const int ex = m > 0.0f ? ilogbf(m) : 0;
-        float h = 0.0f, l = 0.0f;
-        if (p < nr) {
-            // the same float32 value as in the first pass, recomputed from x
+    // w in float32, column by column, and each column's largest magnitude (a
+    // wave's maximum first, then one shared-memory atomic per wave)
+    for (int c = 0; c < nrhs; ++c) {
+        float m = 0.0f;
+        for (int p = threadIdx.x; p < nr; p += blockDim.x) {
             const int64_t pos = lp.start + p;
             const double sc = b.arg[o] ? D.c[pos] : 1.0;
-            const float v = ldexpf(static_cast<float>(sc * b.x[o][c * D.n + D.perm[pos]]), 13 - ex);   // |v| < 2^14
-            const _Float16 vh = static_cast<_Float16>(v);
-            h = static_cast<float>(vh);
-            l = v - h;
+            const float v = static_cast<float>(sc * b.x[o][c * D.n + D.perm[pos]]);
+            w[c * D.n + pos] = v;
+            m = fmaxf(m, fabsf(v));
         }
-        const int64_t at = (lp.wpad + (p & ~7)) * nrhs + c * 8 + (p & 7);
-        hi[at] = static_cast<_Float16>(h);
-        lo[at] = static_cast<_Float16>(l);
-        if (p == 0) D.wsc[a * kMaxRhs + c] = ldexpf(1.0f, ex - 13);
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, kWave));
+        if (threadIdx.x % kWave == 0) atomicMax(&smax[c], __float_as_uint(m));
+    }
+    __syncthreads();   // w and the maxima are complete (the workgroup's own stores)
+    _Float16* hi = static_cast<_Float16*>(D.wh);
+    _Float16* lo = hi + kMaxRhs * D.ldw;
+    // the halves of 8 consecutive points of one column per thread: two 16-byte stores
+    const int groups = kc / 8;
+    for (int e = threadIdx.x; e < nrhs * groups; e += blockDim.x) {
+        const int c = e / groups, g = e % groups;
+        const float m = __uint_as_float(smax[c]);
+        const int ex = m > 0.0f ? ilogbf(m) : 0;
+        h8_t hv, lv;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int p = g * 8 + q;
+            float h = 0.0f, l = 0.0f;
+            if (p < nr) {
+                const float v = ldexpf(w[c * D.n + lp.start + p], 13 - ex);   // |v| < 2^14
+                const _Float16 vh = static_cast<_Float16>(v);
+                h = static_cast<float>(vh);
+                l = v - h;
+            }
+            hv[q] = static_cast<_Float16>(h);
+            lv[q] = static_cast<_Float16>(l);
+        }
+        const int64_t at = (lp.wpad + g * 8) * nrhs + c * 8;
+        *reinterpret_cast<h8_t*>(hi + at) = hv;
+        *reinterpret_cast<h8_t*>(lo + at) = lv;
+        if (g == 0) D.wsc[a * kMaxRhs + c] = ldexpf(1.0f, ex - 13);
     }
     if (a == 0 && threadIdx.x < 8) hi[2 * kMaxRhs * D.ldw + threadIdx.x] = static_cast<_Float16>(0.0f);   // the zero block
 }
@@ -2052,8 +2084,12 @@ static void apply_t(const ApplyReq* reqs, int nops, bool f64, int normalised, in
                         const int64_t nodes = prefix([&](const Op& op, int) {
                             return active(op) ? int64_t(1) << (op.depth - k) : int64_t(0);
                         });
+                        int rmax = 1;
+                        for (int o = 0; o < nops; ++o)
+                            if (active(*reqs[o].op)) rmax = std::max(rmax, reqs[o].op->lvl_max_rank[reqs[o].op->depth - k]);
                         if (nodes > 0)
-                            hipLaunchKernelGGL((k_n2s_node_m<V, TP>), dim3(nodes), dim3(kBlock), shm, ts, b);
+                            hipLaunchKernelGGL((k_n2s_node_m<V, TP>), dim3(nodes, ceil_div(rmax, kN2sNodeRows)), dim3(kBlock),
+                                               shm, ts, b);
                         return;
                     }
                 }
@@ -2322,8 +2358,9 @@ static void build_product_graph(Op& op, bool f64, int normalised, int nrhs, Prod
             const size_t shm = n2s_node_bytes(op, lvl, sizeof(V));
             if (multi && shm <= static_cast<size_t>(kN2sNodeBytes)) {   // one workgroup per node (as eager)
                 bn.pre[1] = int64_t(1) << lvl;
-                last = kernel(reinterpret_cast<void*>(&k_n2s_node_m<V, TP>), dim3(static_cast<unsigned>(bn.pre[1])), bn,
-                              {last}, nullptr, kBlock, shm);
+                last = kernel(reinterpret_cast<void*>(&k_n2s_node_m<V, TP>),
+                              dim3(static_cast<unsigned>(bn.pre[1]), ceil_div(std::max(op.lvl_max_rank[lvl], 1), kN2sNodeRows)),
+                              bn, {last}, nullptr, kBlock, shm);
                 continue;
             }
             bn.pre[1] = op.row_count[lvl];
