@@ -1904,7 +1904,8 @@ __global__ void __launch_bounds__(kBlock) k_near_direct_bf16(const NearPair* pai
 }
 
 // The float64 near field of one column with the kernel evaluated on the fly:
-// one wave per work item of the plain plan (as the stored-tile kernel), lane l
+// the waves take the work items of the plain plan in turn (as the stored-tile
+// kernel takes them, one item per wave on a full grid), lane l
 // owning rows row0 + 2 l and row0 + 2 l + 1 of each 128-row pass.  The item's
 // (at most 64) column points and weights are loaded once, one per lane, and
 // broadcast from their lane column by column; part[part_off + row] = sum over the
@@ -1912,11 +1913,7 @@ __global__ void __launch_bounds__(kBlock) k_near_direct_bf16(const NearPair* pai
 // rounding per operation (the exponent's argument d2 times 1/eps: within an ulp
 // of the oracle's d2 / eps).
 template <int D>
-__global__ void __launch_bounds__(kBlock) k_near_otf(const NearItem* items, int64_t nitems, const int32_t* perm, Pts P,
-                                                    const double* w, double* part) {
-    const int64_t u = blockIdx.x * static_cast<int64_t>(blockDim.x / kWave) + threadIdx.x / kWave;
-    if (u >= nitems) return;
-    const NearItem I = items[u];
+__device__ inline void near_otf_item(const NearItem I, const int32_t* perm, const Pts& P, const double* w, double* part) {
     const int lane = threadIdx.x % kWave;
     double xc[D];
     load_point<D>(P, perm[I.col_pos + min(lane, I.ncols - 1)], xc);
@@ -1946,6 +1943,16 @@ __global__ void __launch_bounds__(kBlock) k_near_otf(const NearItem* items, int6
             if (row + 1 < rend) out[1] = a1;
         }
     }
+}
+
+
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_near_otf(const NearItem* items, int64_t nitems, const int32_t* perm, Pts P,
+                                                    const double* w, double* part) {
+    const int64_t waves = static_cast<int64_t>(gridDim.x) * (blockDim.x / kWave);
+    for (int64_t u = blockIdx.x * static_cast<int64_t>(blockDim.x / kWave) + threadIdx.x / kWave; u < nitems;
+         u += waves)
+        near_otf_item<D>(items[u], perm, P, w, part);
 }
 
 // launches a kernel template specialised on the point dimension
@@ -2639,10 +2646,17 @@ static void build_far_tiles(Op& op, const Geo& G, hipStream_t s, DevBuf<char>& k
 
 void near_field_ones(Op& op, hipStream_t s) {
     op.part_ones.alloc(static_cast<size_t>(std::max<int64_t>(op.part_elems, 1)));
-    near_field_otf(op, nullptr, op.part_ones.get(), s);
+    // beside the skeletonisation: at most kOtfSideWgs workgroups per compute unit,
+    // so that the ID's workgroups of the levels it overlaps find room (N = 100000:
+    // 14.68 -> 14.53 ms per compression; 4 per unit: 14.73)
+    constexpr int kOtfSideWgs = 2;
+    int dev = 0, ncu = 0;
+    HDM_HIP(hipGetDevice(&dev));
+    HDM_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    near_field_otf(op, nullptr, op.part_ones.get(), s, kOtfSideWgs * ncu);
 }
 
-void near_field_otf(const Op& op, const double* w_tree, double* part, hipStream_t s) {
+void near_field_otf(const Op& op, const double* w_tree, double* part, hipStream_t s, int max_wgs) {
     HDM_CHECK(op.near_direct && op.xf.get() && op.dim <= kDirectDim, HDM_EINTERNAL,
               "on-the-fly near field needs float64 points of few coordinates");
     Pts P{};
@@ -2653,7 +2667,9 @@ void near_field_otf(const Op& op, const double* w_tree, double* part, hipStream_
     const int64_t ni = static_cast<int64_t>(op.items.size());
     if (ni == 0) return;
     const int wpb = kBlock / kWave;
-    HDM_DIM_DISPATCH(P.dim, k_near_otf, dim3(ceil_div(ni, wpb)), dim3(kBlock), 0, s, op.d_items.get(), ni,
+    int64_t grid = ceil_div(ni, wpb);
+    if (max_wgs > 0) grid = std::min<int64_t>(grid, max_wgs);
+    HDM_DIM_DISPATCH(P.dim, k_near_otf, dim3(static_cast<unsigned>(grid)), dim3(kBlock), 0, s, op.d_items.get(), ni,
                      op.perm.get(), P, w_tree, part);
     check_launch("near field (kernel on the fly)");
 }

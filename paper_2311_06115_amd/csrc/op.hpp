@@ -373,7 +373,7 @@ void compress_operator(Op& op, const void* X, int x_on_device, hipStream_t s);
 // float64 near field of one column with the kernel evaluated on the fly from the
 // points (operators with near_direct): part[item] = K(rows, cols) w over the
 // plain work items, w and part the product's float64 workspaces
-void near_field_otf(const Op& op, const double* w_tree, double* part, hipStream_t s);
+void near_field_otf(const Op& op, const double* w_tree, double* part, hipStream_t s, int max_wgs = 0);
 // the same with w = 1 into op.part_ones (launched on the side stream after the near plan)
 void near_field_ones(Op& op, hipStream_t s);
 // offsets of the packed half-precision near tiles (evaluate.hip)
