@@ -657,6 +657,20 @@ __global__ void __launch_bounds__(kCombBlock) k_combine(Batch b) {
 }
 
 
+// cnt values into shared memory, dst[e] = load(e), the workgroup's kBlock threads
+// with eight loads in flight each (the loads of a batch are issued before its stores)
+template <typename V, typename Load>
+__device__ inline void stage_batched(int cnt, Load&& load, V* dst) {
+    for (int e0 = threadIdx.x; e0 < cnt; e0 += 8 * kBlock) {
+        V v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = load(min(e0 + q * kBlock, cnt - 1));
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (e0 + q * kBlock < cnt) dst[e0 + q * kBlock] = v[q];
+    }
+}
+
 // ---- S2N by level (operators with large ranks) ---------------------------------
 // u~_h = S2S(h) + (P_parent^T u~_parent)[h's columns] for every node h of level
 // lvl (b.arg), in place on the far-field potentials, parents' potentials already
@@ -733,10 +747,10 @@ __global__ void __launch_bounds__(kBlock) k_s2n_m(Batch b) {
     for (int r0 = 0; r0 < rp; r0 += kS2nRows) {
         const int nrow = min(kS2nRows, rp - r0);
         __syncthreads();   // the previous rows are read
-        for (int e = threadIdx.x; e < nrow * kMaxRhs; e += kBlock) {
+        stage_batched(nrow * kMaxRhs, [&](int e) {
             const int i = e / kMaxRhs, c = e % kMaxRhs;
-            st[e] = sku[min(c, last) * ldsk + sp + r0 + i];
-        }
+            return sku[min(c, last) * ldsk + sp + r0 + i];
+        }, st);
         __syncthreads();
         for (int i = w; i < nrow; i += NW * IB) {
             V pv[IB];
@@ -831,10 +845,10 @@ __global__ void __launch_bounds__(kBlock) k_n2s_node_m(Batch b) {
     const V* in = leaf ? static_cast<const V*>(D.w) + D.start[h] : static_cast<const V*>(D.skw) + D.skoff[2 * h];
     const int64_t ldin = leaf ? D.n : D.ldsk;
     const int last = b.nrhs - 1;
-    for (int e = threadIdx.x; e < kMaxRhs * nc; e += kBlock) {
+    stage_batched(kMaxRhs * nc, [&](int e) {
         const int c = e / nc, j = e % nc;
-        xin[e] = in[min(c, last) * ldin + j];
-    }
+        return in[min(c, last) * ldin + j];
+    }, xin);
     __syncthreads();
     const TP* P = static_cast<const TP*>(D.P) + D.poff[h];
     V* skw = static_cast<V*>(D.skw);
