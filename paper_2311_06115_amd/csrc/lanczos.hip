@@ -8,6 +8,8 @@
 // (a Ritz pair is exact when the residual vanishes, Sec. 2.2).
 #include <chrono>
 #include <cmath>
+#include <cstring>
+#include <initializer_list>
 
 #include "op.hpp"
 
@@ -1066,6 +1068,33 @@ __global__ void k_block_bounds(const double* Z, int m, int b, const double* Bj, 
 
 }  // namespace
 
+// Small results of a convergence check to the host with one wait: through pinned
+// staging inside a pool scope (the copies queue without a host round trip each;
+// pageable copies wait one by one), else directly.
+struct HostPart {
+    void* host;
+    const void* dev;
+    size_t bytes;
+};
+static void download_parts(std::initializer_list<HostPart> parts, hipStream_t s) {
+    size_t total = 0;
+    for (const HostPart& q : parts) total += (q.bytes + 15) / 16 * 16;
+    char* h = static_cast<char*>(host_stage(total));
+    size_t off = 0;
+    for (const HostPart& q : parts) {
+        if (!q.bytes) continue;
+        HDM_HIP(hipMemcpyAsync(h ? h + off : q.host, q.dev, q.bytes, hipMemcpyDeviceToHost, s));
+        off += (q.bytes + 15) / 16 * 16;
+    }
+    HDM_HIP(hipStreamSynchronize(s));
+    if (!h) return;
+    off = 0;
+    for (const HostPart& q : parts) {
+        if (q.bytes) std::memcpy(q.host, h + off, q.bytes);
+        off += (q.bytes + 15) / 16 * 16;
+    }
+}
+
 // restarts of one single-vector solve before it ends with HDM_ENOCONV (the
 // standalone solve and the serving loop alike, so their results agree)
 constexpr int kMaxRestarts = 100;
@@ -1142,9 +1171,8 @@ bool LanczosRun::after_product(hipStream_t s) {
             launch_tridiag(alpha.get(), beta.get(), m, r, theta.get(), Y.get(), bound.get(), s, ev.start, ev.stop);
         }
         check_launch("tridiagonal eigensolve");
-        theta.download(h_theta.data(), r, s);
-        bound.download(h_bound.data(), r, s);
-        HDM_HIP(hipStreamSynchronize(s));
+        download_parts({{h_theta.data(), theta.get(), r * sizeof(double)}, {h_bound.data(), bound.get(), r * sizeof(double)}},
+                       s);
         bool ok = true;
         for (int i = 0; i < r; ++i) ok = ok && (h_bound[i] <= tol * std::fabs(h_theta[i]));
         if (ok) {
@@ -1329,10 +1357,10 @@ static hdm_status block_lanczos_eigs(Op& op, int r, double tol, int b, int max_b
             hipLaunchKernelGGL(k_block_bounds, dim3(1), dim3(64), 0, s, Z.get(), m, b, Rtot.get(), r, bound.get());
             check_launch("block rayleigh-ritz");
             int st = 0;
-            status.download(&st, 1, s);
-            theta.download(h_theta.data(), r, s);
-            bound.download(h_bound.data(), r, s);
-            HDM_HIP(hipStreamSynchronize(s));
+            download_parts({{&st, status.get(), sizeof(int)},
+                            {h_theta.data(), theta.get(), r * sizeof(double)},
+                            {h_bound.data(), bound.get(), r * sizeof(double)}},
+                           s);
             HDM_CHECK(st == 0, HDM_ENUMERIC, "block Lanczos: the residual block lost rank (Cholesky QR failed)");
             bool ok = true;
             for (int i = 0; i < r; ++i) ok = ok && (h_bound[i] <= tol * std::fabs(h_theta[i]));
