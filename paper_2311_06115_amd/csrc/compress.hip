@@ -1903,6 +1903,31 @@ __global__ void __launch_bounds__(kBlock) k_near_direct_bf16(const NearPair* pai
     }
 }
 
+// exp(x) for x <= 0 by Tang's table-driven method (P. T. P. Tang, ACM TOMS 15(2),
+// 1989): x = (64 k + j) ln2/64 + r with |r| <= ln2/128, so exp(x) = 2^k 2^(j/64) e^r,
+// 2^(j/64) from a 64-entry table (each entry within an ulp) and e^r from its Taylor
+// polynomial of degree 5 (remainder below 4e-17 of the value); 0 below -745.2.  The
+// reduction splits ln2/64 as in det_exp (its head times the integer is exact).
+// Within a few ulp of exp: used for kernel values that only enter products (the
+// degree pass's near field), never for a decision of the compression.
+__device__ inline double exp_neg_tab(double x, const double* tab) {
+    constexpr double kInv64 = 0x1.71547652b82fep+6;         // 64 / ln 2
+    constexpr double kHi = 0x1.62e42fee00000p-7;            // ln2/64, head
+    constexpr double kLo = 0x1.a39ef35793c76p-39;           // ln2/64, tail
+    const bool live = x > -745.2;
+    x = live ? x : -745.2;   // branch-free: the value is dropped below
+    const double t = rint(x * kInv64);
+    const int n = static_cast<int>(t);
+    const double r = fma(-t, kLo, fma(-t, kHi, x));
+    double p = fma(r, 1.0 / 120.0, 1.0 / 24.0);
+    p = fma(p, r, 1.0 / 6.0);
+    p = fma(p, r, 0.5);
+    p = fma(p, r, 1.0);
+    p = fma(p, r, 1.0);
+    const double v = ldexp(tab[n & 63] * p, n >> 6);   // n = 64 k + j, j = n mod 64 in [0, 64)
+    return live ? v : 0.0;
+}
+
 // The float64 near field of one column with the kernel evaluated on the fly:
 // the waves take the work items of the plain plan in turn (as the stored-tile
 // kernel takes them, one item per wave on a full grid), lane l
@@ -1913,7 +1938,8 @@ __global__ void __launch_bounds__(kBlock) k_near_direct_bf16(const NearPair* pai
 // rounding per operation (the exponent's argument d2 times 1/eps: within an ulp
 // of the oracle's d2 / eps).
 template <int D>
-__device__ inline void near_otf_item(const NearItem I, const int32_t* perm, const Pts& P, const double* w, double* part) {
+__device__ inline void near_otf_item(const NearItem I, const int32_t* perm, const Pts& P, const double* w, double* part,
+                                     const double* tab) {
     const int lane = threadIdx.x % kWave;
     double xc[D];
     load_point<D>(P, perm[I.col_pos + min(lane, I.ncols - 1)], xc);
@@ -1932,8 +1958,8 @@ __device__ inline void near_otf_item(const NearItem I, const int32_t* perm, cons
 #pragma unroll
             for (int d = 0; d < D; ++d) y[d] = lane_value(xc[d], j);
             const double wj = lane_value(wl, j);
-            const double k0 = exp(-(sqd_regs<D>(x0, y) * ie));   // values only: the device's exp
-            const double k1 = exp(-(sqd_regs<D>(x1, y) * ie));
+            const double k0 = exp_neg_tab(-(sqd_regs<D>(x0, y) * ie), tab);   // values only
+            const double k1 = exp_neg_tab(-(sqd_regs<D>(x1, y) * ie), tab);
             a0 = a0 + (v0 ? k0 : 0.0) * wj;
             a1 = a1 + (v1 ? k1 : 0.0) * wj;
         }
@@ -1949,10 +1975,13 @@ __device__ inline void near_otf_item(const NearItem I, const int32_t* perm, cons
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_near_otf(const NearItem* items, int64_t nitems, const int32_t* perm, Pts P,
                                                     const double* w, double* part) {
+    __shared__ double tab[64];   // 2^(j/64)
+    if (threadIdx.x < 64) tab[threadIdx.x] = exp2(static_cast<double>(threadIdx.x) / 64.0);
+    __syncthreads();
     const int64_t waves = static_cast<int64_t>(gridDim.x) * (blockDim.x / kWave);
     for (int64_t u = blockIdx.x * static_cast<int64_t>(blockDim.x / kWave) + threadIdx.x / kWave; u < nitems;
          u += waves)
-        near_otf_item<D>(items[u], perm, P, w, part);
+        near_otf_item<D>(items[u], perm, P, w, part, tab);
 }
 
 // launches a kernel template specialised on the point dimension
