@@ -524,12 +524,21 @@ __global__ void __launch_bounds__(kSplitBlock) k_tree_split(int lvl, const int64
                 hist_add(hist, in && (u & mask) == prefix, static_cast<uint32_t>((u >> shift) & 255u));
             }
         } else {
-            // strided over the node (coalesced); every wave runs the same rounds
-            for (int q = 0; q < per; ++q) {
-                const int a = static_cast<int>(threadIdx.x) + q * static_cast<int>(blockDim.x);
-                const bool in = a < n;
-                const uint64_t u = in ? orderable(key[s0 + a]) : 0;
-                hist_add(hist, in && (u & mask) == prefix, static_cast<uint32_t>((u >> shift) & 255u));
+            // strided over the node (coalesced), eight loads in flight per thread;
+            // every wave runs the same rounds
+            for (int q0 = 0; q0 < per; q0 += 8) {
+                uint64_t u8[8];
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    const int a = static_cast<int>(threadIdx.x) + (q0 + t) * static_cast<int>(blockDim.x);
+                    u8[t] = orderable(key[s0 + min(a, n - 1)]);
+                }
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    const int a = static_cast<int>(threadIdx.x) + (q0 + t) * static_cast<int>(blockDim.x);
+                    const bool in = q0 + t < per && a < n;
+                    hist_add(hist, in && (u8[t] & mask) == prefix, static_cast<uint32_t>((u8[t] >> shift) & 255u));
+                }
             }
         }
         __syncthreads();
@@ -566,13 +575,22 @@ __global__ void __launch_bounds__(kSplitBlock) k_tree_split(int lvl, const int64
 #pragma unroll
     for (int r = 0; r < (kReg ? R : 1); ++r)
         if constexpr (kReg) neq += (r < cnt && img(r) == ustar);
-    if constexpr (!kReg)
-        for (int r = 0; r < cnt; ++r) neq += img(r) == ustar;
+    // (without registers: the thread's run read eight keys at a time, in order)
+    auto run8 = [&](auto&& body) {
+        for (int r0 = 0; r0 < cnt; r0 += 8) {
+            uint64_t u8[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) u8[t] = orderable(key[s0 + a0 + min(r0 + t, cnt - 1)]);
+#pragma unroll
+            for (int t = 0; t < 8; ++t)
+                if (r0 + t < cnt) body(r0 + t, u8[t]);
+        }
+    };
+    if constexpr (!kReg) run8([&](int, uint64_t u) { neq += u == ustar; });
     int tot = 0;
     const int eq_base = wg_scan_excl(neq, wsum, &tot);
     int nleft = 0, e = eq_base;
-    auto count_left = [&](int r) {
-        const uint64_t u = img(r);
+    auto count_left = [&](int, uint64_t u) {
         const bool eq = u == ustar;
         nleft += u < ustar || (eq && e < kstar);
         e += eq;
@@ -580,15 +598,14 @@ __global__ void __launch_bounds__(kSplitBlock) k_tree_split(int lvl, const int64
     if constexpr (kReg) {
 #pragma unroll
         for (int r = 0; r < R; ++r)
-            if (r < cnt) count_left(r);
+            if (r < cnt) count_left(r, img(r));
     } else {
-        for (int r = 0; r < cnt; ++r) count_left(r);
+        run8(count_left);
     }
     const int l_base = wg_scan_excl(nleft, wsum, &tot);
     int li = l_base, ri = a0 - l_base;
     e = eq_base;
-    auto place = [&](int r) {
-        const uint64_t u = img(r);
+    auto place = [&](int r, uint64_t u) {
         const bool eq = u == ustar;
         const bool left = u < ustar || (eq && e < kstar);
         e += eq;
@@ -597,9 +614,9 @@ __global__ void __launch_bounds__(kSplitBlock) k_tree_split(int lvl, const int64
     if constexpr (kReg) {
 #pragma unroll
         for (int r = 0; r < R; ++r)
-            if (r < cnt) place(r);
+            if (r < cnt) place(r, img(r));
     } else {
-        for (int r = 0; r < cnt; ++r) place(r);
+        run8(place);
     }
 }
 
