@@ -75,7 +75,8 @@ struct Batch {
     int up;                       // near field: leading workgroups that run the upward pass
     const OpDev* op[kMaxBatch];
     int64_t pre[kMaxBatch + 1];
-    int32_t arg[kMaxBatch];       // per operator: tree level (N2S) or normalised flag (prep, combine)
+    int32_t arg[kMaxBatch];       // per operator: tree level (N2S), or for prep and combine bit 0: normalised,
+                                  // bit 1: the vectors are in tree order (no gather or scatter)
     const double* x[kMaxBatch];
     double* y[kMaxBatch];
 };
@@ -94,8 +95,8 @@ __global__ void k_prep(Batch b) {
     const int o = batch_op(b, u);
     const OpDev& D = *b.op[o];
     const int64_t pos = u - b.pre[o];
-    const int32_t i = D.perm[pos];
-    const double sc = b.arg[o] ? D.c[pos] : 1.0;
+    const int64_t i = (b.arg[o] & 2) ? pos : D.perm[pos];
+    const double sc = (b.arg[o] & 1) ? D.c[pos] : 1.0;
     V* w = static_cast<V*>(D.w);
     for (int c = 0; c < b.nrhs; ++c) w[c * D.n + pos] = static_cast<V>(sc * b.x[o][c * D.n + i]);
 }
@@ -600,8 +601,8 @@ __global__ void __launch_bounds__(kCombBlock) k_combine(Batch b) {
     int64_t dst0 = 0;
     if (q == 0 && jq < lp.rows) {
         const int64_t pos = lp.start + jq;
-        sc0 = b.arg[o] ? D.c[pos] : 1.0;
-        dst0 = D.perm[pos];
+        sc0 = (b.arg[o] & 1) ? D.c[pos] : 1.0;
+        dst0 = (b.arg[o] & 2) ? pos : D.perm[pos];
     }
     __syncthreads();
 
@@ -647,8 +648,8 @@ __global__ void __launch_bounds__(kCombBlock) k_combine(Batch b) {
             int64_t dst = dst0;
             if (j0 > 0) {
                 const int64_t pos = lp.start + j;
-                sc = b.arg[o] ? D.c[pos] : 1.0;
-                dst = D.perm[pos];
+                sc = (b.arg[o] & 1) ? D.c[pos] : 1.0;
+                dst = (b.arg[o] & 2) ? pos : D.perm[pos];
             }
             b.y[o][dst] = sc * static_cast<double>(nsum + fsum);
         }
@@ -950,11 +951,12 @@ __global__ void __launch_bounds__(kBlock) k_part_reduce(Batch b) {
 // combine for several right-hand sides: the ancestor potentials of all columns
 // sit side by side in shared memory, so each P element is read once.  One
 // workgroup of kCombBlock threads per leaf, in the phases of k_combine: the
-// ranks and offsets along the path, the path's P slices staged in shared memory
-// in one batch (where they fit), the chain walk from there; then per row the
-// near partial sums (float32: two halves of the workgroup over half of the items
-// each, added in a fixed order, two items of every column in flight) and
-// P_leaf^T u~ with eight of its entries in flight.
+// ranks and offsets along the path, and (for operators whose downward pass has
+// not run level by level before it, s2n_multi = 0) the path's P slices staged in
+// shared memory in one batch (where they fit) and the chain walk from there;
+// then per row the near partial sums (float32: two halves of the workgroup over
+// half of the items each, added in a fixed order, two items of every column in
+// flight) and P_leaf^T u~ with eight of its entries in flight.
 template <typename V> constexpr int kStageM = sizeof(V) == 4 ? kMaxRhs * (kCombBlock / 2) : 1024;
 template <typename V> constexpr bool kSplitM = sizeof(V) == 4;
 template <typename V> constexpr int kItemBatchM = sizeof(V) == 4 ? 2 : 1;
@@ -1127,8 +1129,8 @@ __global__ void __launch_bounds__(kCombBlock) k_combine_m(Batch b) {
                     }
             }
             const int64_t pos = lp.start + j;
-            const double sc = b.arg[o] ? D.c[pos] : 1.0;
-            const int32_t dst = D.perm[pos];
+            const double sc = (b.arg[o] & 1) ? D.c[pos] : 1.0;
+            const int64_t dst = (b.arg[o] & 2) ? pos : D.perm[pos];
 #pragma unroll
             for (int c = 0; c < kMaxRhs; ++c)
                 if (c < nr) b.y[o][c * D.n + dst] = sc * static_cast<double>(f[c]);
@@ -1172,8 +1174,8 @@ __global__ void __launch_bounds__(kBlock) k_prep_mma(Batch b) {
         float m = 0.0f;
         for (int p = threadIdx.x; p < nr; p += blockDim.x) {
             const int64_t pos = lp.start + p;
-            const double sc = b.arg[o] ? D.c[pos] : 1.0;
-            const float v = static_cast<float>(sc * b.x[o][c * D.n + D.perm[pos]]);
+            const double sc = (b.arg[o] & 1) ? D.c[pos] : 1.0;
+            const float v = static_cast<float>(sc * b.x[o][c * D.n + ((b.arg[o] & 2) ? pos : D.perm[pos])]);
             w[c * D.n + pos] = v;
             m = fmaxf(m, fabsf(v));
         }
@@ -2011,11 +2013,11 @@ static void apply_t(const ApplyReq* reqs, int nops, bool f64, int normalised, in
         tree = tree || reqs[o].op->nskel > 0;
         maxdepth = std::max(maxdepth, reqs[o].op->depth);
     }
-    // Several right-hand sides: the upward pass and the far field run on the side
-    // stream while the near field streams on s.  One right-hand side: all on s,
-    // since the fork and join cost more than the overlap saves (4.8 against
-    // 5.2 ms per 25-step solve at N = 32768; 16.2 against 15.8 ms per block
-    // solve at N = 100000 with 16 columns).
+    // Several right-hand sides: the upward pass, the far field and the level-wise
+    // downward pass run on the side stream while the near field streams on s
+    // (100k, 16 columns: 545 against 586 us per product in sequence).  One
+    // right-hand side: all on s, since the fork and join cost more than the
+    // overlap saves (4.8 against 5.2 ms per 25-step solve at N = 32768).
     const bool overlap = tree && multi;
     hipStream_t ts = overlap ? lane.side : s;
     // The near field streams every tile once per product, more bytes than the
@@ -2457,7 +2459,8 @@ static bool apply_graph(Op& op, bool f64, int normalised, int nrhs, const double
     return true;
 }
 
-void apply(Op& op, int normalised, bool exact64, const double* x, double* y, int nrhs, hipStream_t s, bool graph_ok) {
+void apply(Op& op, int normalised, bool exact64, const double* x, double* y, int nrhs, hipStream_t s, bool graph_ok,
+           bool tree_order) {
     HDM_CHECK(op.max_leaf_rank <= kMaxRank, HDM_EINTERNAL, "leaf rank above the combine kernel's limit");
     HDM_CHECK(nrhs >= 1, HDM_EINVAL, "nrhs must be >= 1");
     const int per = std::min(nrhs, kMaxRhs);   // right-hand sides per pass
@@ -2474,8 +2477,8 @@ void apply(Op& op, int normalised, bool exact64, const double* x, double* y, int
     for (int c0 = 0; c0 < nrhs; c0 += per) {
         const ApplyReq r{&op, x + static_cast<int64_t>(c0) * op.n, y + static_cast<int64_t>(c0) * op.n};
         const int np = std::min(per, nrhs - c0);
-        if (graph_ok && !exact64 && apply_graph(op, f64, normalised, np, r.x, r.y, s)) continue;
-        apply_dispatch(&r, 1, f64, normalised, np, s, op.lane, cx);
+        if (graph_ok && !exact64 && !tree_order && apply_graph(op, f64, normalised, np, r.x, r.y, s)) continue;
+        apply_dispatch(&r, 1, f64, (normalised ? 1 : 0) | (tree_order ? 2 : 0), np, s, op.lane, cx);
     }
 }
 

@@ -491,8 +491,10 @@ static void launch_tridiag(const double* alpha, const double* beta, int m, int r
     hipExtLaunchKernelGGL(k_tridiag, dim3(r), dim3(64), shmem, s, start, stop, 0, alpha, beta, m, r, theta, Y, bound);
 }
 
-// Phi[:, k] = V Y[:, k] for k < r (rows per thread)
-__global__ void k_ritz(const double* V, int64_t ldv, int m, const double* Y, int r, double* Phi, int64_t n) {
+// Phi[:, k] = V Y[:, k] for k < r (rows per thread); with perm, row p of V is
+// point perm[p] of Phi (a basis kept in the tree's order)
+__global__ void k_ritz(const double* V, int64_t ldv, int m, const double* Y, int r, double* Phi, int64_t n,
+                       const int32_t* perm) {
     __shared__ double ys[4096];
     const int tot = m * r;
     for (int e = threadIdx.x; e < tot && e < 4096; e += blockDim.x) ys[e] = Y[e];
@@ -514,9 +516,10 @@ __global__ void k_ritz(const double* V, int64_t ldv, int m, const double* Y, int
                 acc[t] += v * (e < 4096 ? ys[e] : Y[e]);
             }
         }
+        const int64_t dst = perm ? perm[row] : row;
 #pragma unroll
         for (int t = 0; t < KB; ++t)
-            if (k0 + t < r) Phi[(k0 + t) * n + row] = acc[t];
+            if (k0 + t < r) Phi[(k0 + t) * n + dst] = acc[t];
     }
 }
 
@@ -574,11 +577,13 @@ __global__ void k_col_fix(double* Phi, int64_t n, const double* scale) {
 // ---------------------------------------------------------------------------
 constexpr int kMaxBlockBasis = 512;
 
-// the start block: column c of V takes the start-vector draws of column c
-__global__ void k_start_block(double* V, int64_t n, int b, uint64_t seed) {
+// the start block: column c of V takes the start-vector draws of column c (the
+// draw of point i, which sits at row p with perm[p] = i when V is in tree order)
+__global__ void k_start_block(double* V, int64_t n, int b, uint64_t seed, const int32_t* perm) {
     const int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
     if (e >= n * b) return;
-    const uint32_t c = static_cast<uint32_t>(e / n), i = static_cast<uint32_t>(e % n);
+    const uint32_t c = static_cast<uint32_t>(e / n), p = static_cast<uint32_t>(e % n);
+    const uint32_t i = perm ? static_cast<uint32_t>(perm[p]) : p;
     const uint32_t r = philox_draw(seed, kLanczosStart, c, 0, i);
     V[e] = (static_cast<double>(r) + 0.5) / 4294967296.0 - 0.5;
 }
@@ -1230,7 +1235,8 @@ void LanczosRun::restart(hipStream_t s) {
     const int kp = std::min(max_basis - 2, std::max(r + 1, (max_basis + r) / 2));
     solve_projected(kp, s);
     tmp.alloc(static_cast<size_t>(n) * kp);
-    hipLaunchKernelGGL(k_ritz, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, s, V.get(), n, m, Y.get(), kp, tmp.get(), n);
+    hipLaunchKernelGGL(k_ritz, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, s, V.get(), n, m, Y.get(), kp, tmp.get(), n,
+                       nullptr);
     HDM_HIP(hipMemcpyAsync(V.get(), tmp.get(), sizeof(double) * n * kp, hipMemcpyDeviceToDevice, s));
     HDM_HIP(hipMemcpyAsync(V.get() + static_cast<int64_t>(kp) * n, V.get() + static_cast<int64_t>(m) * n,
                            sizeof(double) * n, hipMemcpyDeviceToDevice, s));
@@ -1254,7 +1260,7 @@ hdm_status LanczosRun::result(double* evals, double* evecs, hdm_eig_info_t* info
     for (int i = 0; i < r; ++i) worst = std::max(worst, h_bound[i] / std::max(std::fabs(h_theta[i]), 1e-300));
     if (evecs) {
         const int gN = ceil_div(n, kBlock);
-        hipLaunchKernelGGL(k_ritz, dim3(gN), dim3(kBlock), 0, s, V.get(), n, m, Y.get(), r, evecs, n);
+        hipLaunchKernelGGL(k_ritz, dim3(gN), dim3(kBlock), 0, s, V.get(), n, m, Y.get(), r, evecs, n, nullptr);
         DevBuf<double> scale(r);
         hipLaunchKernelGGL(k_col_stats, dim3(r), dim3(kBlock), 0, s, evecs, n, scale.get());
         hipLaunchKernelGGL(k_col_fix, dim3(std::min(gN, 256), r), dim3(kBlock), 0, s, evecs, n, scale.get());
@@ -1319,7 +1325,10 @@ static hdm_status block_lanczos_eigs(Op& op, int r, double tol, int b, int max_b
             hipLaunchKernelGGL(k_trsm, dim3(gN), dim3(kBlock), 0, s, X, n, b, n, Rinv.get());
         }
     };
-    hipLaunchKernelGGL(k_start_block, dim3(ceil_div(n * b, kBlock)), dim3(kBlock), 0, s, V.get(), n, b, seed);
+    // the basis lives in the tree's point order: the products neither gather nor
+    // scatter, and the Ritz vectors are written back in the caller's order
+    const int32_t* perm = op.perm.get();
+    hipLaunchKernelGGL(k_start_block, dim3(ceil_div(n * b, kBlock)), dim3(kBlock), 0, s, V.get(), n, b, seed, perm);
     block_qr(V.get());
     check_launch("block lanczos start");
     std::vector<double> h_theta(r), h_bound(r);
@@ -1327,7 +1336,7 @@ static hdm_status block_lanczos_eigs(Op& op, int r, double tol, int b, int max_b
     bool converged = false;
     for (;; ++j) {
         const double* Q = V.get() + static_cast<int64_t>(j) * b * n;
-        apply(op, 1, false, Q, Y.get(), b, s);
+        apply(op, 1, false, Q, Y.get(), b, s, false, true);
         matvecs += b;
         const int nc = (j + 1) * b;
         {
@@ -1376,7 +1385,7 @@ static hdm_status block_lanczos_eigs(Op& op, int r, double tol, int b, int max_b
     double worst = 0.0;
     for (int i = 0; i < r; ++i) worst = std::max(worst, h_bound[i] / std::max(std::fabs(h_theta[i]), 1e-300));
     if (evecs) {
-        hipLaunchKernelGGL(k_ritz, dim3(gN), dim3(kBlock), 0, s, V.get(), n, m, Z.get(), r, evecs, n);
+        hipLaunchKernelGGL(k_ritz, dim3(gN), dim3(kBlock), 0, s, V.get(), n, m, Z.get(), r, evecs, n, perm);
         DevBuf<double> scale(r);
         hipLaunchKernelGGL(k_col_stats, dim3(r), dim3(kBlock), 0, s, evecs, n, scale.get());
         hipLaunchKernelGGL(k_col_fix, dim3(std::min(gN, 256), r), dim3(kBlock), 0, s, evecs, n, scale.get());

@@ -391,9 +391,11 @@ void finish_operator(Op& op, hipStream_t s);
 // on s without waiting (its index arrays live in conv_keep until finish_operator)
 void convert_near_tiles(Op& op, hipStream_t s);
 // graph_ok: the product may replay the operator's cached HIP graph (the caller's
-// one-off products); iterations that interleave other kernels launch eagerly
+// one-off products); iterations that interleave other kernels launch eagerly.
+// tree_order: x and y are in the tree's point order (no gather or scatter; the
+// block eigensolver keeps its basis that way)
 void apply(Op& op, int normalised, bool exact64, const double* x, double* y, int nrhs, hipStream_t s,
-           bool graph_ok = false);
+           bool graph_ok = false, bool tree_order = false);
 // One launch per phase for every operator of the batch (same tile precisions,
 // at most kMaxBatch operators, one nrhs); each operator's result is the one a
 // single-operator product gives.
