@@ -951,12 +951,13 @@ __global__ void __launch_bounds__(kBlock) k_part_reduce(Batch b) {
 // combine for several right-hand sides: the ancestor potentials of all columns
 // sit side by side in shared memory, so each P element is read once.  One
 // workgroup of kCombBlock threads per leaf, in the phases of k_combine: the
-// ranks and offsets along the path, and (for operators whose downward pass has
-// not run level by level before it, s2n_multi = 0) the path's P slices staged in
-// shared memory in one batch (where they fit) and the chain walk from there;
-// then per row the near partial sums (float32: two halves of the workgroup over
-// half of the items each, added in a fixed order, two items of every column in
-// flight) and P_leaf^T u~ with eight of its entries in flight.
+// ranks and offsets along the path; the leaf's potentials, either through the
+// composites of its ancestors (s2n_comp: one step, no chain), or already formed
+// by a per-level downward pass (s2n_multi), or else by the chain walk from level
+// 1 with the path's P slices staged in shared memory in one batch (where they
+// fit); then per row the near partial sums (float32: two halves of the workgroup
+// over half of the items each, added in a fixed order, two items of every column
+// in flight) and P_leaf^T u~ with eight of its entries in flight.
 template <typename V> constexpr int kStageM = sizeof(V) == 4 ? kMaxRhs * (kCombBlock / 2) : 1024;
 template <typename V> constexpr bool kSplitM = sizeof(V) == 4;
 template <typename V> constexpr int kItemBatchM = sizeof(V) == 4 ? 2 : 1;
@@ -967,12 +968,14 @@ __global__ void __launch_bounds__(kCombBlock) k_combine_m(Batch b) {
     constexpr int IB = kItemBatchM<V>;
     __shared__ V tot[2][kMaxRhs * kMaxRank];
     __shared__ V stage[kStageM<V>];   // the chain's P slices, then the second half's near sums
-    __shared__ int m_rn[kMaxLevels + 1], m_rp[kMaxLevels + 1], m_ncp[kMaxLevels + 1];
-    __shared__ int64_t m_pb[kMaxLevels + 1], m_sk[kMaxLevels + 1], m_pleaf;
+    __shared__ int m_rn[kMaxLevels + 1], m_rp[kMaxLevels + 1], m_ncp[kMaxLevels + 1], m_cs[kMaxLevels + 1],
+        m_so[kMaxLevels + 1];
+    __shared__ int64_t m_pb[kMaxLevels + 1], m_sk[kMaxLevels + 1], m_cb[kMaxLevels + 1], m_pleaf;
     const int64_t u = blockIdx.x;
     const int o = batch_op(b, u);
     const OpDev& D = *b.op[o];
     const LeafPlan lp = D.leaves[u - b.pre[o]];
+    const bool comp = D.s2n_comp && D.row_total > 0 && D.depth >= 2;
     const TP* P = static_cast<const TP*>(D.P);
     const V* sku = static_cast<const V*>(D.sku);
     const int depth = D.row_total > 0 ? D.depth : 0;
@@ -989,17 +992,65 @@ __global__ void __launch_bounds__(kCombBlock) k_combine_m(Batch b) {
             m_ncp[tid] = D.ncand[par];
             m_pb[tid] = D.poff[par] + ((node & 1) ? D.rank[2 * par] : 0);
         }
+        if (comp && tid < depth) {
+            // the leaf's block of columns in the composite of its ancestor at level tid
+            const LeafRun lr = leaf_run(D.skoff, D.rank, depth, node, tid);
+            m_cs[tid] = lr.nlk;
+            m_cb[tid] = D.coff[node] + (D.skoff[lp.heap] - lr.base);
+        }
     }
     if (tid == 0 && depth >= 1) m_pleaf = D.poff[lp.heap];
     __syncthreads();
     // the walk starts at level 1, or at the leaf when a per-level downward pass
-    // has completed every potential already
-    const int top = D.s2n_multi && depth >= 1 ? depth : 1;
+    // (or the composites below) completes every potential
+    const int top = (D.s2n_multi || comp) && depth >= 1 ? depth : 1;
     if (depth >= 1) {
         const int r1 = m_rn[top];
         for (int e = tid; e < nr * r1; e += kCombBlock) {
             const int c = e / r1, i = e % r1;
             tot[0][c * kMaxRank + i] = sku[c * ldsk + m_sk[top] + i];
+        }
+    }
+    // Through the composites: the leaf's potentials are its own far field plus,
+    // for each ancestor h (levels 1 .. depth - 1), the leaf's block of columns of
+    // C_h transposed times h's far field (the chain of P slices from h down to
+    // the leaf is that block).  The ancestors' far fields are staged in shared
+    // memory, every (level, column, row) sum is formed at once into the second
+    // potential buffer, and the levels are added in order.  The host enables this
+    // only where both fit (nr x the ancestors' ranks <= the staging, (depth - 1) x
+    // nr x the leaf's rank <= one potential buffer).
+    if (comp) {
+        const int rleaf = m_rn[depth], nl = depth - 1, per = nr * rleaf;
+        int so = 0;
+        for (int lvl = 1; lvl < depth; ++lvl) {
+            const int rn = m_rn[lvl];
+            if (tid == 0) m_so[lvl] = so;
+            for (int e = tid; e < nr * rn; e += kCombBlock) stage[so + e] = sku[(e / rn) * ldsk + m_sk[lvl] + e % rn];
+            so += nr * rn;
+        }
+        __syncthreads();
+        const V* Cm = static_cast<const V*>(D.comp);
+        for (int e = tid; e < nl * per; e += kCombBlock) {
+            const int lvl = 1 + e / per, r = e % per, c = r / rleaf, j = r % rleaf;
+            const int rn = m_rn[lvl], cs = m_cs[lvl];
+            const V* Sv = stage + m_so[lvl] + c * rn;
+            const V* Cp = Cm + m_cb[lvl] + j;
+            V acc = 0;
+            for (int i0 = 0; i0 < rn; i0 += 8) {
+                V cv[8];
+#pragma unroll
+                for (int t = 0; t < 8; ++t) cv[t] = Cp[static_cast<int64_t>(min(i0 + t, rn - 1)) * cs];
+#pragma unroll
+                for (int t = 0; t < 8; ++t)
+                    if (i0 + t < rn) acc += cv[t] * Sv[i0 + t];
+            }
+            tot[1][e] = acc;
+        }
+        __syncthreads();
+        for (int e = tid; e < per; e += kCombBlock) {
+            V s = tot[0][(e / rleaf) * kMaxRank + e % rleaf];
+            for (int l = 0; l < nl; ++l) s += tot[1][l * per + e];
+            tot[0][(e / rleaf) * kMaxRank + e % rleaf] = s;
         }
     }
     // the chain walk; as many consecutive levels' P slices as fit are staged in
@@ -1214,20 +1265,27 @@ __global__ void __launch_bounds__(kBlock) k_prep_mma(Batch b) {
     if (a == 0 && threadIdx.x < 8) hi[2 * kMaxRhs * D.ldw + threadIdx.x] = static_cast<_Float16>(0.0f);   // the zero block
 }
 
-// One wave per item: up to 8 row tiles of 16 rows of a run of near tiles of
-// one leaf against all their columns, 32 columns per step, hi and lo halves of
-// the vectors in turn.  Each tile's products are scaled by its tile and vector
-// scales and added to the run's sums in tile order; the run writes one
-// partial-sum slot.
+// Workgroups over segments of the packed near field.  A segment is a run of
+// tile steps (32 columns of one tile) of one leaf; it may start or end inside a
+// tile.  With several columns the plan gives each workgroup an equal share of
+// all steps (a list of segments), so every wave streams the same number of steps
+// and the launch ends with its waves busy (runs of whole tiles per wave, two
+// rounds of items over the wave slots, had left the last ~100 us of the launch
+// half empty); with one column each workgroup takes one tile.  The four waves of
+// a workgroup take the same segments, each for its own group of at most 8 row
+// tiles of 16 rows (wave g takes groups g, g + 4, ...).  A segment's products
+// are scaled by tile and vector scales at the end of each of its tiles' columns
+// and added in step order; the segment writes one partial-sum slot of its leaf,
+// so the result does not depend on when or where it runs.
 //
-// The steps of the whole run form one sequence, software-pipelined: the loads
-// of step s + 1 (8 A fragments, 2 B fragments, 16 bytes per lane each) are
-// issued before the matrix instructions of step s, so every wave keeps two
-// steps of tile data in flight.  No load is guarded: a row past the item (or
-// past the tile) reads the item's last row, whose products land in output rows
-// that are never stored, and a column group past the tile reads the tile's
-// last group against a zero B fragment; B lanes past nrhs or past the tile
-// read a block of zeros kept after the staged vectors.
+// The steps of a segment form one sequence, software-pipelined: the loads of
+// step s + 1 (8 A fragments, 2 B fragments, 16 bytes per lane each) are issued
+// before the matrix instructions of step s, so every wave keeps two steps of
+// tile data in flight.  No load is guarded: a row past the group (or past the
+// tile) reads the group's last row, whose products land in output rows that are
+// never stored, and a column group past the tile reads the tile's last group
+// against a zero B fragment; B lanes past nrhs or past the tile read a block of
+// zeros kept after the staged vectors.
 typedef const __attribute__((address_space(1))) h8_t gh8_t;
 
 // a 16-byte load through a global-memory pointer (not a flat one)
@@ -1238,26 +1296,26 @@ struct MmaStep {
     h8_t bh, bl;
 };
 
-// position in a run's step sequence, wave-uniform (scalar registers): tile q
-// of the run and its fields, columns k0 .. k0 + 31, the tile's scale and the
-// vector scales of its column leaf (one per right-hand side)
+// position in a segment's step sequence: tile q of the segment and its fields
+// (wave-uniform), columns k0 .. k0 + 31 up to kend (the tile's padded width, or
+// where the segment stops inside its last tile), the tile's scale and the vector
+// scale of this lane's column
 struct MmaPos {
-    int q, k0, kc, col_pos;
+    int q, k0, kc, kend, col_pos;
     int64_t tile_off;
     float ts;
-    float ws[kMaxRhs];
+    float wl;   // vector scale of this lane's column (column li of the B operand)
 };
 
 
-__device__ inline void mma_tile(const OpDev& D, int t, MmaPos& p) {
+__device__ inline void mma_tile(const OpDev& D, int t, int li, MmaPos& p) {
     cNearItem* T = (cNearItem*)D.tiles + t;
     p.kc = (T->ncols + 7) & ~7;
+    p.kend = p.kc;
     p.col_pos = T->col_pos;
     p.tile_off = T->tile_off;
     p.ts = D.nscale ? *((cfloat*)D.nscale + T->tile) : 1.0f;
-    cfloat* w = (cfloat*)D.wsc + static_cast<int64_t>(T->leaf_b) * kMaxRhs;
-#pragma unroll
-    for (int c = 0; c < kMaxRhs; ++c) p.ws[c] = w[c];
+    p.wl = D.wsc[static_cast<int64_t>(T->leaf_b) * kMaxRhs + li];
 }
 
 template <bool kUp>
@@ -1266,106 +1324,127 @@ __global__ void __launch_bounds__(kBlock) k_l2l_mma(Batch b) {
         leaf_n2s<float>(b, blockIdx.x);
         return;
     }
-    int64_t u = (blockIdx.x - b.up) * static_cast<int64_t>(blockDim.x / kWave) + threadIdx.x / kWave;
-    u = uni(static_cast<int>(u));   // wave-uniform: the descriptors load as scalars
-    if (u >= b.pre[b.nops]) return;
-    if (b.flip) u = b.pre[b.nops] - 1 - u;
-    const int o = batch_op(b, u);
+    int64_t wg = static_cast<int64_t>(blockIdx.x) - b.up;
+    if (wg >= b.pre[b.nops]) return;
+    if (b.flip) wg = b.pre[b.nops] - 1 - wg;
+    const int o = batch_op(b, wg);
     const OpDev& D = *b.op[o];
-    cNearItem* Ip = (cNearItem*)(b.nrhs > 1 ? D.items : D.items1) + (u - b.pre[o]);
-    const struct {
-        int64_t part_off;
-        int32_t ld, row0, nrows, tile, ntiles;
-    } I = {Ip->part_off, Ip->ld, Ip->row0, Ip->nrows, Ip->tile, Ip->ntiles};
+    const bool multi = b.nrhs > 1;
+    // no workgroup list: one segment per workgroup
+    const int32_t* wlist = multi ? D.wseg : D.wseg1;
+    const int64_t wi = wg - b.pre[o];
+    const int seg0 = wlist ? wlist[wi] : static_cast<int>(wi);
+    const int nseg = wlist ? wlist[wi + 1] - seg0 : 1;
+    cNearItem* segs = (cNearItem*)(multi ? D.items : D.items1);
     const int lane = threadIdx.x % kWave, li = lane % 16, g = lane / 16;
-    const int nrt = I.nrows / 16, nrhs = b.nrhs, ntiles = I.ntiles;
+    const int wave = uni(static_cast<int>(threadIdx.x) / kWave);
+    const int nrhs = b.nrhs;
     const bool jv = li < nrhs;   // B operand: column li of the vectors
-    // element offset (in halves) of this lane's row in each row tile, clamped to the item
-    int roff[kMmaRowTiles];
-#pragma unroll
-    for (int t = 0; t < kMmaRowTiles; ++t) roff[t] = min(I.row0 + 16 * min(t, nrt - 1) + li, I.ld - 1) * 8;
-    const int64_t ld8 = static_cast<int64_t>(I.ld) * 8;
     const int lc = min(li, nrhs - 1);
     const _Float16* whi = static_cast<const _Float16*>(D.wh) + 8 * lc;
     const int64_t lo_off = kMaxRhs * D.ldw;
     const _Float16* zero = static_cast<const _Float16*>(D.wh) + 2 * lo_off;   // 8 zero halves
     const _Float16* near = static_cast<const _Float16*>(D.near);
-    auto load = [&](const MmaPos& p, MmaStep& st) {
-        const int kg = p.k0 + 8 * g;               // this lane's 8 columns
-        const int kgc = min(kg, p.kc - 8);
-        const _Float16* tp = near + p.tile_off + (kgc / 8) * ld8;
+    float* part = static_cast<float*>(D.part) + static_cast<int64_t>(li) * (multi ? D.ldp : D.ldp1);
+    // flip (every other product): the workgroups, and each workgroup's segments,
+    // in reverse order, so that a product starts on the tiles the previous one
+    // read last (still cached); each segment keeps its own order and slot, so
+    // the sums do not change
+    for (int k = 0; k < nseg; ++k) {
+        cNearItem* Ip = segs + (b.flip ? seg0 + nseg - 1 - k : seg0 + k);
+        const struct {
+            int64_t part_off;
+            int32_t ld, tile, ntiles, kbeg, kend;
+        } I = {Ip->part_off, Ip->ld, Ip->tile, Ip->ntiles, Ip->kbeg, Ip->kend};
+        const int ntiles = I.ntiles;
+        const int rt = (I.ld + 15) / 16;   // row tiles of the leaf
+        const int groups = max((rt + kMmaRowTiles - 1) / kMmaRowTiles, min(kBlock / kWave, rt));
+        const int64_t ld8 = static_cast<int64_t>(I.ld) * 8;
+        for (int grp = wave; grp < groups; grp += kBlock / kWave) {
+            const int nrt = rt / groups + (grp < rt % groups ? 1 : 0);
+            const int row0 = 16 * (grp * (rt / groups) + min(grp, rt % groups));
+            // element offset (in halves) of this lane's row in each row tile, clamped to the group
+            int roff[kMmaRowTiles];
 #pragma unroll
-        for (int t = 0; t < kMmaRowTiles; ++t) st.a[t] = gload16(tp + roff[t]);
-        // B lanes past nrhs or past the tile read the zero block
-        const bool bv = jv && kg < p.kc;
-        const _Float16* wq = whi + (static_cast<int64_t>(p.col_pos) + kgc) * nrhs;
-        st.bh = gload16(bv ? wq : zero);
-        st.bl = gload16(bv ? wq + lo_off : zero);
-    };
-    // the next position; false past the run's last step
-    auto advance = [&](MmaPos& p) {
-        p.k0 += 32;
-        if (p.k0 < p.kc) return true;
-        p.k0 = 0;
-        ++p.q;
-        if (p.q >= ntiles) return false;
-        mma_tile(D, I.tile + p.q, p);
-        return true;
-    };
-    f4_t tot[kMmaRowTiles], acc[kMmaRowTiles];
+            for (int t = 0; t < kMmaRowTiles; ++t) roff[t] = min(row0 + 16 * min(t, nrt - 1) + li, I.ld - 1) * 8;
+            auto load = [&](const MmaPos& p, MmaStep& st) {
+                const int kg = p.k0 + 8 * g;               // this lane's 8 columns
+                const int kgc = min(kg, p.kc - 8);
+                const _Float16* tp = near + p.tile_off + (kgc / 8) * ld8;
 #pragma unroll
-    for (int t = 0; t < kMmaRowTiles; ++t) {
-        tot[t] = f4_t{0.0f, 0.0f, 0.0f, 0.0f};
-        acc[t] = f4_t{0.0f, 0.0f, 0.0f, 0.0f};
-    }
-    auto compute = [&](const MmaStep& st, const MmaPos& p) {
-#pragma unroll
-        for (int t = 0; t < kMmaRowTiles; ++t) {
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(st.a[t], st.bh, acc[t], 0, 0, 0);
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(st.a[t], st.bl, acc[t], 0, 0, 0);
-        }
-        if (p.k0 + 32 >= p.kc) {   // the tile's last step: scale and add in tile order
-            float w = 0.0f;
-#pragma unroll
-            for (int c = 0; c < kMaxRhs; ++c) w = li == c ? p.ws[c] : w;
-            const float sc = jv ? p.ts * w : 0.0f;
+                for (int t = 0; t < kMmaRowTiles; ++t) st.a[t] = gload16(tp + roff[t]);
+                // B lanes past nrhs or past the tile read the zero block
+                const bool bv = jv && kg < p.kc;
+                const _Float16* wq = whi + (static_cast<int64_t>(p.col_pos) + kgc) * nrhs;
+                st.bh = gload16(bv ? wq : zero);
+                st.bl = gload16(bv ? wq + lo_off : zero);
+            };
+            // the next position; false past the segment's last step
+            auto advance = [&](MmaPos& p) {
+                p.k0 += 32;
+                if (p.k0 < p.kend) return true;
+                p.k0 = 0;
+                ++p.q;
+                if (p.q >= ntiles) return false;
+                mma_tile(D, I.tile + p.q, li, p);
+                if (p.q == ntiles - 1) p.kend = I.kend;
+                return true;
+            };
+            f4_t tot[kMmaRowTiles], acc[kMmaRowTiles];
 #pragma unroll
             for (int t = 0; t < kMmaRowTiles; ++t) {
-                tot[t] += f4_t{acc[t][0] * sc, acc[t][1] * sc, acc[t][2] * sc, acc[t][3] * sc};
+                tot[t] = f4_t{0.0f, 0.0f, 0.0f, 0.0f};
                 acc[t] = f4_t{0.0f, 0.0f, 0.0f, 0.0f};
             }
-        }
-    };
-    // two step buffers in turn: the loads of one step are in flight while the
-    // matrix instructions of the previous one run
-    MmaStep s0, s1;
-    MmaPos p0{};
-    p0.q = 0;
-    p0.k0 = 0;
-    mma_tile(D, I.tile, p0);
-    load(p0, s0);
-    // (past the last step the loads repeat the current position: unconditional
-    // loads keep the loop free of branches around them, so each step waits only
-    // for its own loads)
-    for (;;) {
-        MmaPos p1 = p0;
-        const bool m1 = advance(p1);
-        load(m1 ? p1 : p0, s1);
-        compute(s0, p0);
-        if (!m1) break;
-        p0 = p1;
-        const bool m0 = advance(p0);
-        load(m0 ? p0 : p1, s0);
-        compute(s1, p1);
-        if (!m0) break;
-    }
-    // lane holds rows 4 g + q (q < 4) of column li of every row tile
-    if (!jv) return;
-    float* out = static_cast<float*>(D.part) + static_cast<int64_t>(li) * (nrhs > 1 ? D.ldp : D.ldp1) + I.part_off;
+            auto compute = [&](const MmaStep& st, const MmaPos& p) {
 #pragma unroll
-    for (int t = 0; t < kMmaRowTiles; ++t) {
-        const int r = I.row0 + 16 * t + 4 * g;
-        if (t < nrt && r < I.ld) *reinterpret_cast<f4_t*>(out + r) = tot[t];
+                for (int t = 0; t < kMmaRowTiles; ++t) {
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(st.a[t], st.bh, acc[t], 0, 0, 0);
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(st.a[t], st.bl, acc[t], 0, 0, 0);
+                }
+                if (p.k0 + 32 >= p.kend) {   // the tile's last step here: scale and add in tile order
+                    const float sc = jv ? p.ts * p.wl : 0.0f;
+#pragma unroll
+                    for (int t = 0; t < kMmaRowTiles; ++t) {
+                        tot[t] += f4_t{acc[t][0] * sc, acc[t][1] * sc, acc[t][2] * sc, acc[t][3] * sc};
+                        acc[t] = f4_t{0.0f, 0.0f, 0.0f, 0.0f};
+                    }
+                }
+            };
+            // two step buffers in turn: the loads of one step are in flight while the
+            // matrix instructions of the previous one run
+            MmaStep s0, s1;
+            MmaPos p0{};
+            p0.q = 0;
+            mma_tile(D, I.tile, li, p0);
+            p0.k0 = I.kbeg;
+            if (ntiles == 1) p0.kend = I.kend;
+            load(p0, s0);
+            // (past the last step the loads repeat the current position: unconditional
+            // loads keep the loop free of branches around them, so each step waits only
+            // for its own loads)
+            for (;;) {
+                MmaPos p1 = p0;
+                const bool m1 = advance(p1);
+                load(m1 ? p1 : p0, s1);
+                compute(s0, p0);
+                if (!m1) break;
+                p0 = p1;
+                const bool m0 = advance(p0);
+                load(m0 ? p0 : p1, s0);
+                compute(s1, p1);
+                if (!m0) break;
+            }
+            // lane holds rows 4 g + q (q < 4) of column li of every row tile
+            if (jv) {
+                float* out = part + I.part_off;
+#pragma unroll
+                for (int t = 0; t < kMmaRowTiles; ++t) {
+                    const int r = row0 + 16 * t + 4 * g;
+                    if (t < nrt && r < I.ld) *reinterpret_cast<f4_t*>(out + r) = tot[t];
+                }
+            }
+        }
     }
 }
 
@@ -1461,7 +1540,7 @@ size_t Op::footprint() const {
            far64.bytes() + farT.bytes() + far_scale.bytes() + far_colmap.bytes() + d_items.bytes() +
            d_leaves.bytes() + q.bytes() + d.bytes() + c.bytes() + w_tree.bytes() + skw.bytes() + sku.bytes() +
            part.bytes() + plan_blob.bytes() + wh.bytes() + wsc.bytes() + d_items_mma[0].bytes() + d_items_mma[1].bytes() + d_tiles_mma.bytes() +
-           d_leaves_mma[0].bytes() + d_leaves_mma[1].bytes();
+           d_leaves_mma[0].bytes() + d_leaves_mma[1].bytes() + d_wseg_mma[0].bytes() + d_wseg_mma[1].bytes();
 }
 
 void Lane::init(LanePool* from) {
@@ -1553,6 +1632,7 @@ static void publish_descriptors(Op& op, hipStream_t s) {
         D.items = D.items1 = op.d_items.get();
         D.nitems = D.nitems1 = static_cast<int64_t>(op.items.size());
         D.tiles = nullptr;
+        D.wseg = D.wseg1 = nullptr;
         D.near = f64 ? static_cast<const void*>(op.near64.get()) : static_cast<const void*>(op.nearT.get());
         D.nscale = (!f64 && op.near_scale.n) ? op.near_scale.get() : nullptr;
         D.leaves = D.leaves1 = op.d_leaves.get();
@@ -1569,7 +1649,8 @@ static void publish_descriptors(Op& op, hipStream_t s) {
                               : nullptr;
         D.coff = op.d_coff;
         D.s2n_levels = op.s2n_levels ? 1 : 0;
-        D.s2n_multi = op.s2n_multi ? 1 : 0;
+        D.s2n_multi = op.s2n_by_levels(true, f64) ? 1 : 0;
+        D.s2n_comp = op.s2n_comp && !f64 && op.ncomp > 0 ? 1 : 0;
         if (!f64 && op.packed) {   // matrix-core plan of the packed half-precision tiles
             D.items = op.d_items_mma[1].get();
             D.nitems = static_cast<int64_t>(op.items_mma[1].size());
@@ -1580,6 +1661,8 @@ static void publish_descriptors(Op& op, hipStream_t s) {
             D.leaves1 = op.d_leaves_mma[0].get();
             D.ldp1 = std::max<int64_t>(op.part_elems_mma[0], 1);
             D.tiles = op.d_tiles_mma.get();
+            D.wseg = op.wseg_one[1] ? nullptr : op.d_wseg_mma[1].get();
+            D.wseg1 = op.wseg_one[0] ? nullptr : op.d_wseg_mma[0].get();
             D.wh = op.wh.get();
             D.wsc = op.wsc.get();
             D.ldw = op.ldw;
@@ -1598,17 +1681,25 @@ static void publish_descriptors(Op& op, hipStream_t s) {
 static void check_near_plan(const Op& op);
 
 // Plan of the packed half-precision near field (k_l2l_mma): per near pair an
-// ld_a x kc_b packed tile, the tiles of one leaf consecutive in memory.  One
-// item is a run of consecutive tiles of leaf a times a group of at most 8 row
-// tiles; it accumulates the whole run in registers and writes one partial-sum
-// slot of ld_a rows per run.  Two plans over the same tiles: for one right-hand
-// side a run is one tile (more, shorter items: the single-column stream is
-// bound by how many loads are in flight), for several a run holds about
-// kMmaRunCols padded columns, the leaf's tiles split into runs of nearly equal
-// count (fewer partial sums to write and add; measured at N = 100000: 16
-// columns 372 -> 345 us, one column 266 -> 290 us).  Vectors are staged with
-// every leaf padded to a multiple of 8 points.
-constexpr int kMmaRunCols = 2048;
+// ld_a x kc_b packed tile, the tiles of one leaf consecutive in memory.  The
+// work is the sequence of tile steps (32 columns of one tile, all rows of its
+// leaf), leaf after leaf.
+// * Several columns: each workgroup takes a contiguous share of it, the shares
+//   equal to within one step, cut into segments at leaf boundaries (one
+//   partial-sum slot of ld_a rows per segment: few partial sums to write and
+//   add).  The workgroup count is 7/8 of what the device holds at once, fewer
+//   where a share would fall below kMmaMinSteps steps: the upward and far passes
+//   run on a side stream beside this launch and need the rest (N = 100000, 16
+//   columns: all slots 309 us for the near field but 534 us for the product, 7/8
+//   329 and 509 us, 6/8 344 and 489 us; runs of whole tiles, one wave each, had
+//   taken 349 and 575 us).
+// * One column: one workgroup per tile (many short items, which the hardware
+//   hands to whichever compute unit frees first; equal shares measured 275
+//   against 264 us).
+// Vectors are staged with every leaf padded to a multiple of 8 points.
+constexpr int kMmaMinSteps = 16;
+constexpr int kMmaShare8 = 7;        // eighths of the device's workgroups given to several columns
+constexpr bool kMmaTileWgs1 = true;  // one column: one workgroup per tile instead of equal shares
 
 static void build_mma_plan(Op& op, hipStream_t s) {
     const int64_t L = op.L;
@@ -1620,8 +1711,16 @@ static void build_mma_plan(Op& op, hipStream_t s) {
         op.ldw += (op.size[L + b] + 7) / 8 * 8;
     }
     packed_near_offsets(op);
+    // workgroups the device holds at once, per kernel ([0] one column, [1] several)
+    int dev = 0, ncu = 0;
+    HDM_HIP(hipGetDevice(&dev));
+    HDM_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    int occ[2] = {0, 0};
+    HDM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[0], k_l2l_mma<true>, kBlock, 0));
+    HDM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[1], k_l2l_mma<false>, kBlock, 0));
+    const int64_t wgs[2] = {static_cast<int64_t>(std::max(occ[0], 1)) * std::max(ncu, 1),
+                            static_cast<int64_t>(std::max(occ[1], 1)) * std::max(ncu, 1)};
     op.tiles_mma.clear();
-    std::vector<int64_t> leaf_cols(L, 0);
     int64_t off = 0;
     for (int64_t a = 0; a < L; ++a) {
         const int32_t ld = op.near_ld[a];
@@ -1638,54 +1737,102 @@ static void build_mma_plan(Op& op, hipStream_t s) {
             T.ntiles = 1;
             op.tiles_mma.push_back(T);
             off += static_cast<int64_t>(ld) * ((nb + 7) / 8 * 8);
-            leaf_cols[a] += (nb + 7) / 8 * 8;
         }
     }
     op.near_elems_mma = off;
+    // steps per tile and per leaf
+    std::vector<int64_t> leaf_steps(L, 0);
+    for (int64_t a = 0; a < L; ++a)
+        for (int32_t t = op.near_off[a]; t < op.near_off[a + 1]; ++t)
+            leaf_steps[a] += ceil_div((op.tiles_mma[t].ncols + 7) / 8 * 8, 32);
+    int64_t total = 0;
+    for (int64_t a = 0; a < L; ++a) total += leaf_steps[a];
     for (int k = 0; k < 2; ++k) {
         std::vector<NearItem>& items = op.items_mma[k];
         std::vector<LeafPlan>& leaves = op.leaves_mma[k];
+        std::vector<int32_t>& wseg = op.wseg_mma[k];
         items.clear();
         leaves.clear();
+        wseg.clear();
         op.red_groups_mma[k] = 0;
-        int64_t part = 0;
+        const bool per_tile = k == 0 && kMmaTileWgs1;
+        const int64_t cap = k == 0 ? wgs[0] : std::max<int64_t>(1, wgs[1] * kMmaShare8 / 8);
+        const int64_t P = std::max<int64_t>(1, std::min<int64_t>(cap, ceil_div(total, kMmaMinSteps)));
+        const int64_t Q = std::max<int64_t>(1, ceil_div(total, P));   // steps per workgroup
+        // every leaf's segments, in order: cut at each multiple of Q of the
+        // global step position
+        int64_t part = 0, pos = 0;
         for (int64_t a = 0; a < L; ++a) {
             const int64_t ha = L + a;
             const int32_t ld = op.near_ld[a];
-            const int32_t t_begin = op.near_off[a], ntiles = op.near_off[a + 1] - op.near_off[a];
-            const int nrun = k == 0 ? ntiles
-                                    : static_cast<int>(std::min<int64_t>(
-                                          ntiles, std::max<int64_t>(1, ceil_div(leaf_cols[a], kMmaRunCols))));
             LeafPlan lp{};
             lp.part_off = part;
-            lp.nitems = nrun;
             lp.ld = ld;
             lp.start = static_cast<int32_t>(op.start[ha]);
             lp.rows = static_cast<int32_t>(op.size[ha]);
             lp.heap = static_cast<int32_t>(ha);
-            const int rt = (ld + 15) / 16;                        // 16-row tiles covering ld rows
-            const int groups = (rt + kMmaRowTiles - 1) / kMmaRowTiles;
-            lp.ngroups = groups;
             lp.wpad = wpad[a];
-            lp.gstep = nrun > kReduceAbove ? kReduceGroup : 1;
-            if (lp.gstep > 1) op.red_groups_mma[k] = std::max(op.red_groups_mma[k], ceil_div(nrun, kReduceGroup));
-            for (int q = 0, t0 = t_begin; q < nrun; ++q) {
-                const int cnt_t = ntiles / nrun + (q < ntiles % nrun ? 1 : 0);
-                for (int g = 0, r0 = 0; g < groups; ++g) {
-                    const int cnt = rt / groups + (g < rt % groups ? 1 : 0);
-                    NearItem I = op.tiles_mma[t0];
-                    I.part_off = part + static_cast<int64_t>(q) * ld;
-                    I.row0 = 16 * r0;
-                    I.nrows = 16 * cnt;
-                    I.ntiles = cnt_t;
-                    items.push_back(I);
-                    r0 += cnt;
-                }
-                t0 += cnt_t;
+            int32_t nseg = 0;
+            // one workgroup per tile
+            for (int32_t t = op.near_off[a]; per_tile && t < op.near_off[a + 1]; ++t) {
+                wseg.push_back(static_cast<int32_t>(items.size()));
+                NearItem I = op.tiles_mma[t];
+                I.part_off = part + static_cast<int64_t>(nseg) * ld;
+                I.row0 = 0;
+                I.nrows = ld;
+                I.kbeg = 0;
+                I.kend = (I.ncols + 7) / 8 * 8;
+                items.push_back(I);
+                ++nseg;
             }
-            part += static_cast<int64_t>(nrun) * ld;
+            // leaf-local step range [lo, hi) of each segment
+            for (int64_t lo = 0; !per_tile && lo < leaf_steps[a];) {
+                const int64_t gpos = pos + lo;
+                if (gpos % Q == 0) wseg.push_back(static_cast<int32_t>(items.size()));
+                const int64_t hi = std::min(leaf_steps[a], lo + (Q - gpos % Q));
+                // tiles holding steps lo and hi - 1
+                NearItem I{};
+                int64_t acc = 0;
+                int32_t t0 = -1, t1 = -1;
+                for (int32_t t = op.near_off[a]; t < op.near_off[a + 1]; ++t) {
+                    const int64_t st = ceil_div((op.tiles_mma[t].ncols + 7) / 8 * 8, 32);
+                    if (t0 < 0 && lo < acc + st) {
+                        t0 = t;
+                        I.kbeg = static_cast<int32_t>(32 * (lo - acc));
+                    }
+                    if (hi <= acc + st) {
+                        t1 = t;
+                        const int32_t kc = (op.tiles_mma[t].ncols + 7) / 8 * 8;
+                        I.kend = static_cast<int32_t>(std::min<int64_t>(kc, 32 * (hi - acc)));
+                        break;
+                    }
+                    acc += st;
+                }
+                const NearItem& T0 = op.tiles_mma[t0];
+                I.tile_off = T0.tile_off;
+                I.part_off = part + static_cast<int64_t>(nseg) * ld;
+                I.ld = ld;
+                I.row0 = 0;
+                I.nrows = ld;
+                I.ncols = T0.ncols;
+                I.col_pos = T0.col_pos;
+                I.tile = t0;
+                I.leaf_b = T0.leaf_b;
+                I.ntiles = t1 - t0 + 1;
+                items.push_back(I);
+                ++nseg;
+                lo = hi;
+            }
+            pos += leaf_steps[a];
+            lp.nitems = nseg;
+            lp.ngroups = std::max(ceil_div((ld + 15) / 16, kMmaRowTiles), std::min<int>(kBlock / kWave, (ld + 15) / 16));
+            lp.gstep = nseg > kReduceAbove ? kReduceGroup : 1;
+            if (lp.gstep > 1) op.red_groups_mma[k] = std::max(op.red_groups_mma[k], ceil_div(nseg, kReduceGroup));
+            part += static_cast<int64_t>(nseg) * ld;
             leaves.push_back(lp);
         }
+        wseg.push_back(static_cast<int32_t>(items.size()));
+        op.wseg_one[k] = wseg.size() == items.size() + 1;
         op.part_elems_mma[k] = part;
     }
     op.ldw = std::max<int64_t>(op.ldw, 0);
@@ -1693,6 +1840,7 @@ static void build_mma_plan(Op& op, hipStream_t s) {
     for (int k = 0; k < 2; ++k) {
         op.d_items_mma[k] = to_device(op.items_mma[k], s);
         op.d_leaves_mma[k] = to_device(op.leaves_mma[k], s);
+        op.d_wseg_mma[k] = to_device(op.wseg_mma[k], s);
     }
     op.d_tiles_mma = to_device(op.tiles_mma, s);
     op.wh.alloc((static_cast<size_t>(std::max<int64_t>(op.ldw, 1)) * 2 * kMaxRhs + 8) * sizeof(_Float16));
@@ -1729,21 +1877,38 @@ static void check_near_plan(const Op& op) {
             if (T.tile_off < 0 || T.tile_off + kc * T.ld > op.near_elems_mma) bad("packed tile extent");
             if (T.col_pos < 0 || T.col_pos + kc > op.ldw) bad("staged vector extent");
         }
-        for (int k = 0; k < 2; ++k)
-        for (const NearItem& I : op.items_mma[k]) {
-            if (I.tile < 0 || I.ntiles < 1 || static_cast<int64_t>(I.tile) + I.ntiles > pairs) bad("packed item tiles");
-            // a run stays inside one leaf's near block
-            const int64_t a = std::upper_bound(op.near_off.begin(), op.near_off.end(), I.tile) - op.near_off.begin() - 1;
-            if (a < 0 || a >= L || static_cast<int64_t>(I.tile) + I.ntiles > op.near_off[a + 1]) bad("packed run across leaves");
-            if (I.tile_off != op.tiles_mma[I.tile].tile_off || I.ld != op.near_ld[a]) bad("packed run start");
-            if (I.row0 < 0 || I.row0 + I.nrows > (I.ld + 15) / 16 * 16) bad("packed rows");
-            if (I.part_off < 0 || I.part_off + I.ld > op.part_elems_mma[k]) bad("packed partial-sum extent");
-        }
-        for (int k = 0; k < 2; ++k)
-        for (const LeafPlan& lp : op.leaves_mma[k]) {
-            if (lp.part_off < 0 || lp.part_off + static_cast<int64_t>(lp.nitems) * lp.ld > op.part_elems_mma[k])
-                bad("packed leaf partials");
-            if (lp.wpad < 0 || lp.wpad + (lp.rows + 7) / 8 * 8 > op.ldw) bad("packed leaf vector");
+        for (int k = 0; k < 2; ++k) {
+            const std::vector<NearItem>& segs = op.items_mma[k];
+            const std::vector<LeafPlan>& leaves = op.leaves_mma[k];
+            if (static_cast<int64_t>(leaves.size()) != L) bad("packed leaf count");
+            // segments: leaf after leaf, each leaf's in slot order, inside the leaf's tiles
+            size_t si = 0;
+            for (int64_t a = 0; a < L; ++a) {
+                const LeafPlan& lp = leaves[a];
+                if (lp.nitems < 1 || lp.ld != op.near_ld[a]) bad("packed leaf plan");
+                if (lp.part_off < 0 || lp.part_off + static_cast<int64_t>(lp.nitems) * lp.ld > op.part_elems_mma[k])
+                    bad("packed leaf partials");
+                if (lp.wpad < 0 || lp.wpad + (lp.rows + 7) / 8 * 8 > op.ldw) bad("packed leaf vector");
+                for (int32_t q = 0; q < lp.nitems; ++q, ++si) {
+                    if (si >= segs.size()) bad("packed segment count");
+                    const NearItem& I = segs[si];
+                    if (I.tile < op.near_off[a] || I.ntiles < 1 || I.tile + I.ntiles > op.near_off[a + 1])
+                        bad("packed segment tiles");
+                    if (I.tile_off != op.tiles_mma[I.tile].tile_off || I.ld != lp.ld) bad("packed segment start");
+                    const int32_t kc0 = (op.tiles_mma[I.tile].ncols + 7) / 8 * 8;
+                    const int32_t kc1 = (op.tiles_mma[I.tile + I.ntiles - 1].ncols + 7) / 8 * 8;
+                    if (I.kbeg < 0 || I.kbeg % 32 != 0 || I.kbeg >= kc0) bad("packed segment first column");
+                    if (I.kend < 1 || I.kend > kc1 || (I.kend != kc1 && I.kend % 32 != 0)) bad("packed segment end column");
+                    if (I.ntiles == 1 && I.kbeg >= I.kend) bad("packed segment columns");
+                    if (I.part_off != lp.part_off + static_cast<int64_t>(q) * lp.ld) bad("packed segment slot");
+                }
+            }
+            if (si != segs.size()) bad("packed segment count");
+            const std::vector<int32_t>& wseg = op.wseg_mma[k];
+            if (wseg.size() < 2 || wseg.front() != 0 || wseg.back() != static_cast<int32_t>(segs.size()))
+                bad("packed workgroup segments");
+            for (size_t w = 0; w + 1 < wseg.size(); ++w)
+                if (wseg[w + 1] <= wseg[w]) bad("packed workgroup segments");
         }
     }
 }
@@ -1903,6 +2068,16 @@ void build_eval_plan(Op& op, hipStream_t s) {
         // on the side stream, beside the near field, instead of a chain of
         // dependent steps per leaf in the combine)
         op.s2n_multi = op.s2n_levels || (nested && op.depth >= 2);
+        // through the composites instead, where every leaf's ancestors' potentials
+        // (16 columns) fit the combine's staging and the per-level sums its second
+        // potential buffer
+        op.s2n_comp = op.ncomp > 0 && !op.s2n_levels && op.depth >= 2;
+        for (int64_t h = op.L; op.s2n_comp && h < 2 * op.L; ++h) {
+            int64_t anc = 0;
+            for (int64_t g = h >> 1; g >= 2; g >>= 1) anc += op.rank[g];
+            if (anc * kMaxRhs > kStageM<float> || int64_t(op.depth - 1) * op.rank[h] * kMaxRhs > kMaxRhs * kMaxRank)
+                op.s2n_comp = false;
+        }
         op.lvl_max_nc.assign(kMaxLevels + 1, 0);
         op.lvl_max_rank.assign(kMaxLevels + 1, 0);
         for (int64_t h = 2; h < 2 * op.L; ++h) {
@@ -2036,11 +2211,12 @@ static void apply_t(const ApplyReq* reqs, int nops, bool f64, int normalised, in
     const bool fuse_up = tree && !multi && nops == 1 && !otf;
     b.up = fuse_up ? static_cast<int>(reqs[0].op->L) : 0;
     auto near_field = [&] {
+        // matrix cores: one workgroup per share of the plan; plain tiles: one wave per item
         const int64_t tot = prefix([multi](const Op& op, int) {
-            return static_cast<int64_t>(mma ? op.items_mma[multi].size() : op.items.size());
+            return static_cast<int64_t>(mma ? op.wseg_mma[multi].size() - 1 : op.items.size());
         });
         b.flip = static_cast<int>(reqs[0].op->near_calls++ & 1u);
-        const int64_t grid = ceil_div(tot, wpb) + b.up;
+        const int64_t grid = (mma ? tot : ceil_div(tot, wpb)) + b.up;
         if (otf) {
             Op& o0 = *reqs[0].op;
             if (o0.near_ones_next && o0.part_ones.n) {   // K~ 1: its near field is already computed
@@ -2145,7 +2321,7 @@ static void apply_t(const ApplyReq* reqs, int nops, bool f64, int normalised, in
         }
         // S2N level by level for the operators that take it (large ranks; every
         // product with several right-hand sides)
-        auto levels = [multi](const Op& op) { return multi ? op.s2n_multi : op.s2n_levels; };
+        auto levels = [multi, f64](const Op& op) { return op.s2n_by_levels(multi, f64); };
         bool any_s2n = false;
         for (int o = 0; o < nops; ++o) any_s2n = any_s2n || levels(*reqs[o].op);
         if (any_s2n) {
@@ -2297,14 +2473,14 @@ static void build_product_graph(Op& op, bool f64, int normalised, int nrhs, Prod
     // near field (one column: with the leaf level of the upward pass, as in the
     // eager schedule, and the rest of the tree after it)
     Batch bl = base;
-    const int64_t nitems = static_cast<int64_t>(mma ? op.items_mma[nrhs > 1].size() : op.items.size());
+    const int64_t nitems = static_cast<int64_t>(mma ? op.wseg_mma[nrhs > 1].size() - 1 : op.items.size());
     bl.pre[1] = nitems;
     const bool fuse_up = op.nskel > 0 && !multi;
     bl.up = fuse_up ? op.L : 0;
     void* l2l_fn = mma ? (fuse_up ? reinterpret_cast<void*>(&k_l2l_mma<true>) : reinterpret_cast<void*>(&k_l2l_mma<false>))
                        : (fuse_up ? reinterpret_cast<void*>(&k_l2l<V, TN, true>)
                                   : reinterpret_cast<void*>(&k_l2l<V, TN, false>));
-    hipGraphNode_t near = kernel(l2l_fn, dim3(ceil_div(nitems, wpb) + bl.up), bl, {G.prep}, nullptr);
+    hipGraphNode_t near = kernel(l2l_fn, dim3((mma ? nitems : ceil_div(nitems, wpb)) + bl.up), bl, {G.prep}, nullptr);
     const int maxg = mma ? op.red_groups_mma[1] : op.red_groups;
     if (multi && maxg > 0) {
         Batch br = base;
@@ -2314,7 +2490,7 @@ static void build_product_graph(Op& op, bool f64, int normalised, int nrhs, Prod
     std::vector<hipGraphNode_t> comb_deps{near};
     // S2N by level after the far field, for operators with large ranks (as eager)
     auto s2n_levels = [&](hipGraphNode_t last) {
-        if (!(multi ? op.s2n_multi : op.s2n_levels)) return last;
+        if (!op.s2n_by_levels(multi, f64)) return last;
         for (int lvl = 2; lvl <= op.depth; ++lvl) {
             Batch bn = base;
             bn.arg[0] = lvl;

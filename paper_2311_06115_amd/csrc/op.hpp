@@ -92,6 +92,8 @@ struct NearItem {
     int32_t row_pos;    // tree position of the row leaf's first point (plain items)
     int32_t row_n;      // points in the row leaf (rows at or past it are padding)
     int32_t ntiles;     // matrix-core items: consecutive near tiles from `tile` on (one per tile record)
+    int32_t kbeg;       // matrix-core segments: first column taken of the first tile (a multiple of 32)
+    int32_t kend;       // matrix-core segments: end of the columns taken of the last tile
 };
 
 // Per leaf: where its partial sums live and how many items feed each row group.
@@ -153,6 +155,8 @@ struct OpDev {
     const LeafPlan* leaves1;
     int64_t ldp1;
     const NearItem* tiles;        // matrix-core plans: one record per near tile (items take runs of them)
+    const int32_t* wseg;          // matrix-core plans: first segment of each workgroup (several columns)
+    const int32_t* wseg1;         // the same for one column
     const void* near;
     const float* nscale;
     void* w;                      // workspaces (nrhs columns each)
@@ -169,6 +173,8 @@ struct OpDev {
     const void* comp;             // composites of the nested bases (nullptr: level by level)
     int32_t s2n_levels;           // 1: the downward pass runs level by level before the combine
     int32_t s2n_multi;            // the same for products with several right-hand sides
+    int32_t s2n_comp;             // several right-hand sides: the combine forms each leaf's potentials
+                                  // from its ancestors' far fields through the composites
     const int64_t* coff;
 };
 
@@ -244,14 +250,17 @@ struct Op {
     // their own tile offsets, items, leaf plans and partial-sum extent
     bool packed = false;
     std::vector<int64_t> near_tile_off_mma;
-    // packed (matrix-core) plans, [0] for one right-hand side (a run is one
-    // tile), [1] for several (runs of about kMmaRunCols columns)
+    // packed (matrix-core) plans, [0] for one right-hand side, [1] for several
+    // (each a list of segments, every workgroup an equal share of the tile steps)
     int64_t near_elems_mma = 0, part_elems_mma[2] = {0, 0};
     int red_groups = 0, red_groups_mma[2] = {0, 0};   // most pre-added groups of one leaf (plain, packed plans)
     std::vector<NearItem> items_mma[2], tiles_mma;
     DevBuf<NearItem> d_items_mma[2], d_tiles_mma;
     std::vector<LeafPlan> leaves_mma[2];
     DevBuf<LeafPlan> d_leaves_mma[2];
+    std::vector<int32_t> wseg_mma[2];   // per workgroup of the packed near field: its first segment (+ end)
+    DevBuf<int32_t> d_wseg_mma[2];
+    bool wseg_one[2] = {false, false};  // one segment per workgroup (the kernel takes no list)
     int64_t ldw = 0;
     DevBuf<char> wh;                           // 2 x 16 x ldw halves
     DevBuf<float> wsc;                         // L x 16
@@ -303,6 +312,11 @@ struct Op {
     int64_t ncomp = 0;
     bool s2n_levels = false;   // downward pass in per-level launches (large ranks) instead of per leaf path
     bool s2n_multi = false;    // the same for several right-hand sides (every nested tree of depth >= 2)
+    // several right-hand sides in evaluation precision: the leaf potentials through
+    // the composites inside the combine (no per-level launches), where they fit
+    bool s2n_comp = false;
+    // the downward pass of a product runs in per-level launches
+    bool s2n_by_levels(bool multi, bool f64) const { return multi ? s2n_multi && !(s2n_comp && !f64) : s2n_levels; }
     int max_leaf_rank = 0;
     std::vector<int32_t> lvl_max_nc, lvl_max_rank;   // per tree level: largest candidate count and rank
     DevBuf<double> C64;
