@@ -504,12 +504,13 @@ __global__ void __launch_bounds__(kCombBlock) k_combine(Batch b) {
     __shared__ V tot[2][kMaxRank];
     __shared__ V chain[kStage];
     __shared__ V quarter[2][4][kCombQ];
-    __shared__ int m_rn[kMaxLevels + 1], m_rp[kMaxLevels + 1], m_ncp[kMaxLevels + 1];
-    __shared__ int64_t m_pb[kMaxLevels + 1], m_sk[kMaxLevels + 1], m_pleaf;
+    __shared__ int m_rn[kMaxLevels + 1], m_rp[kMaxLevels + 1], m_ncp[kMaxLevels + 1], m_cs[kMaxLevels + 1];
+    __shared__ int64_t m_pb[kMaxLevels + 1], m_sk[kMaxLevels + 1], m_cb[kMaxLevels + 1], m_pleaf;
     const int64_t u = blockIdx.x;
     const int o = batch_op(b, u);
     const OpDev& D = *b.op[o];
     const LeafPlan lp = D.leaves1[u - b.pre[o]];   // one column
+    const bool comp = D.s2n_comp1 && D.row_total > 0 && D.depth >= 2;
     const TP* P = static_cast<const TP*>(D.P);
     const V* sku = static_cast<const V*>(D.sku);
     const V* pc = static_cast<const V*>(D.part) + lp.part_off;
@@ -526,23 +527,58 @@ __global__ void __launch_bounds__(kCombBlock) k_combine(Batch b) {
             m_ncp[tid] = D.ncand[par];
             m_pb[tid] = D.poff[par] + ((node & 1) ? D.rank[2 * par] : 0);
         }
+        if (comp && tid < depth) {
+            // the leaf's block of columns in the composite of its ancestor at level tid
+            const LeafRun lr = leaf_run(D.skoff, D.rank, depth, node, tid);
+            m_cs[tid] = lr.nlk;
+            m_cb[tid] = D.coff[node] + (D.skoff[lp.heap] - lr.base);
+        }
     }
     if (tid == 0 && depth >= 1) m_pleaf = D.poff[lp.heap];
     __syncthreads();
     // level lvl's slice of the chain buffer: rp x rn of P_parent (the node's
-    // columns), then the node's rn far-field values
+    // columns), then the node's rn far-field values; through the composites
+    // (comp): for each ancestor level, its rn far-field values, then the leaf's
+    // block of its composite (rn x rleaf), and after all levels the per-level sums
     // the walk starts at level 1, or at the leaf when a per-level downward pass
-    // has completed every potential already
-    const int top = D.s2n_levels && depth >= 1 ? depth : 1;
-    int64_t need = 0;
-    for (int lvl = top + 1; lvl <= depth; ++lvl) need += static_cast<int64_t>(m_rp[lvl] + 1) * m_rn[lvl];
-    const bool staged = need <= kStage;
+    // (or the composites) completes every potential
+    const int top = (D.s2n_levels || comp) && depth >= 1 ? depth : 1;
     const int rleaf = depth >= 1 ? m_rn[depth] : 0;
+    int64_t need = 0;
+    if (comp)
+        for (int lvl = 1; lvl < depth; ++lvl) need += static_cast<int64_t>(m_rn[lvl]) * (1 + rleaf);
+    else
+        for (int lvl = top + 1; lvl <= depth; ++lvl) need += static_cast<int64_t>(m_rp[lvl] + 1) * m_rn[lvl];
+    const bool staged = need <= kStage;
 
     // 2. independent loads
     if (depth >= 1)
         for (int i = tid; i < m_rn[top]; i += kCombBlock) tot[0][i] = sku[m_sk[top] + i];
-    if (staged && need > 0) {
+    if (comp) {
+        // need <= kStage (the host enables comp only where the whole staging fits);
+        // a leaf of rank 0 has no potentials to form
+        const int nd = rleaf > 0 ? static_cast<int>(need) : 0;
+        const V* Cm = static_cast<const V*>(D.comp);
+        int lvl = 1, lo = 0, sz = m_rn[1] * (1 + rleaf);
+        for (int g0 = tid; g0 < nd; g0 += 8 * kCombBlock) {
+            V x[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int g = min(g0 + t * kCombBlock, nd - 1);
+                while (g >= lo + sz) {
+                    lo += sz;
+                    ++lvl;
+                    sz = m_rn[lvl] * (1 + rleaf);
+                }
+                const int rn = m_rn[lvl], e = g - lo;
+                x[t] = e < rn ? sku[m_sk[lvl] + e]
+                              : Cm[m_cb[lvl] + static_cast<int64_t>((e - rn) / rleaf) * m_cs[lvl] + (e - rn) % rleaf];
+            }
+#pragma unroll
+            for (int t = 0; t < 8; ++t)
+                if (g0 + t * kCombBlock < nd) chain[g0 + t * kCombBlock] = x[t];
+        }
+    } else if (staged && need > 0) {
         // need <= kStage here, so the flat index fits in 32 bits; each thread's
         // elements come in increasing order, so its level only advances
         const int nd = static_cast<int>(need);
@@ -606,7 +642,31 @@ __global__ void __launch_bounds__(kCombBlock) k_combine(Batch b) {
     }
     __syncthreads();
 
-    // 3. downward chain: u~_child = S2S(child) + (P_parent^T u~_parent)[child's columns]
+    // 3. downward pass.  Through the composites: u~_leaf = S2S(leaf) + the sum
+    // over ancestors h of (the leaf's block of C_h)^T S2S(h), every (level, row)
+    // sum at once from shared memory, the levels added in order.
+    if (comp && rleaf > 0) {
+        const int nd = static_cast<int>(need);
+        for (int e = tid; e < (depth - 1) * rleaf; e += kCombBlock) {
+            const int lvl = 1 + e / rleaf, j = e % rleaf;
+            int off = 0;
+            for (int l = 1; l < lvl; ++l) off += m_rn[l] * (1 + rleaf);
+            const int rn = m_rn[lvl];
+            const V* S = chain + off;
+            const V* Cb = chain + off + rn + j;
+            V acc = 0;
+            for (int i = 0; i < rn; ++i) acc += Cb[i * rleaf] * S[i];
+            chain[nd + e] = acc;
+        }
+        __syncthreads();
+        for (int j = tid; j < rleaf; j += kCombBlock) {
+            V s = tot[0][j];
+            for (int l = 0; l < depth - 1; ++l) s += chain[nd + l * rleaf + j];
+            tot[0][j] = s;
+        }
+        __syncthreads();
+    }
+    // downward chain: u~_child = S2S(child) + (P_parent^T u~_parent)[child's columns]
     int cur = 0;
     int64_t off = 0;
     for (int lvl = top + 1; lvl <= depth; ++lvl) {
@@ -1651,6 +1711,10 @@ static void publish_descriptors(Op& op, hipStream_t s) {
         D.s2n_levels = op.s2n_levels ? 1 : 0;
         D.s2n_multi = op.s2n_by_levels(true, f64) ? 1 : 0;
         D.s2n_comp = op.s2n_comp && !f64 && op.ncomp > 0 ? 1 : 0;
+        D.s2n_comp1 = op.ncomp > 0 && !op.s2n_levels && op.depth >= 2 &&
+                              op.comp1_stage <= kChainStageBytes / static_cast<int64_t>(f64 ? sizeof(double) : sizeof(float))
+                          ? 1
+                          : 0;
         if (!f64 && op.packed) {   // matrix-core plan of the packed half-precision tiles
             D.items = op.d_items_mma[1].get();
             D.nitems = static_cast<int64_t>(op.items_mma[1].size());
@@ -2088,6 +2152,12 @@ void build_eval_plan(Op& op, hipStream_t s) {
         }
         op.max_leaf_rank = 0;
         for (int64_t h = op.L; h < 2 * op.L; ++h) op.max_leaf_rank = std::max(op.max_leaf_rank, static_cast<int>(op.rank[h]));
+        op.comp1_stage = 0;
+        for (int64_t h = op.L; h < 2 * op.L; ++h) {
+            int64_t anc = 0;
+            for (int64_t g = h >> 1; g >= 2; g >>= 1) anc += op.rank[g];
+            op.comp1_stage = std::max(op.comp1_stage, anc * (1 + op.rank[h]) + int64_t(op.depth - 1) * op.rank[h]);
+        }
     }
     check_eval_plan(op, tasks);
     // the skeleton-dependent arrays in one allocation and one copy

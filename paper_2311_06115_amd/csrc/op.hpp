@@ -175,6 +175,7 @@ struct OpDev {
     int32_t s2n_multi;            // the same for products with several right-hand sides
     int32_t s2n_comp;             // several right-hand sides: the combine forms each leaf's potentials
                                   // from its ancestors' far fields through the composites
+    int32_t s2n_comp1;            // the same for one right-hand side
     const int64_t* coff;
 };
 
@@ -318,6 +319,9 @@ struct Op {
     // the downward pass of a product runs in per-level launches
     bool s2n_by_levels(bool multi, bool f64) const { return multi ? s2n_multi && !(s2n_comp && !f64) : s2n_levels; }
     int max_leaf_rank = 0;
+    // one right-hand side through the composites: the largest shared-memory staging
+    // of any leaf (its ancestors' far fields and composite blocks, the per-level sums)
+    int64_t comp1_stage = 0;
     std::vector<int32_t> lvl_max_nc, lvl_max_rank;   // per tree level: largest candidate count and rank
     DevBuf<double> C64;
     DevBuf<float> C32;
