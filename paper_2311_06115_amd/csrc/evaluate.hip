@@ -1267,8 +1267,8 @@ constexpr int kMmaRowTiles = 8;   // 16-row tiles per work item
 // sit at (p / 8) 8 nrhs + 8 c + p % 8: the 8 consecutive points of one column
 // that a matrix-core lane takes are 16 contiguous bytes, and those of the
 // nrhs columns follow each other.
-__global__ void __launch_bounds__(kBlock) k_prep_mma(Batch b) {
-    __shared__ uint32_t smax[kMaxRhs];
+__global__ void __launch_bounds__(kCombBlock) k_prep_mma(Batch b) {
+    __shared__ float smax[kMaxRhs];
     const int64_t u = blockIdx.x;
     const int o = batch_op(b, u);
     const OpDev& D = *b.op[o];
@@ -1276,23 +1276,35 @@ __global__ void __launch_bounds__(kBlock) k_prep_mma(Batch b) {
     const LeafPlan lp = D.leaves[a];
     const int nr = lp.rows, nrhs = b.nrhs;
     const int kc = (nr + 7) & ~7;
-    if (threadIdx.x < kMaxRhs) smax[threadIdx.x] = 0u;
-    __syncthreads();
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    const bool norm = b.arg[o] & 1, gather = !(b.arg[o] & 2);
     float* w = static_cast<float*>(D.w);
-    // w in float32, column by column, and each column's largest magnitude (a
-    // wave's maximum first, then one shared-memory atomic per wave)
-    for (int c = 0; c < nrhs; ++c) {
+    // w in float32 and each column's largest magnitude: one wave per column, eight
+    // points per lane in flight (a column's values are loaded before any is stored)
+    for (int c = wave; c < nrhs; c += nw) {
+        const double* x = b.x[o] + static_cast<int64_t>(c) * D.n;
+        float* wc = w + static_cast<int64_t>(c) * D.n + lp.start;
         float m = 0.0f;
-        for (int p = threadIdx.x; p < nr; p += blockDim.x) {
-            const int64_t pos = lp.start + p;
-            const double sc = (b.arg[o] & 1) ? D.c[pos] : 1.0;
-            const float v = static_cast<float>(sc * b.x[o][c * D.n + ((b.arg[o] & 2) ? pos : D.perm[pos])]);
-            w[c * D.n + pos] = v;
-            m = fmaxf(m, fabsf(v));
+        for (int p0 = 0; p0 < nr; p0 += 8 * kWave) {
+            float v[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int64_t pos = lp.start + min(p0 + t * kWave + lane, nr - 1);
+                const double sc = norm ? D.c[pos] : 1.0;
+                v[t] = static_cast<float>(sc * x[gather ? D.perm[pos] : pos]);
+            }
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int p = p0 + t * kWave + lane;
+                if (p < nr) {
+                    wc[p] = v[t];
+                    m = fmaxf(m, fabsf(v[t]));
+                }
+            }
         }
 #pragma unroll
         for (int off = kWave / 2; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, kWave));
-        if (threadIdx.x % kWave == 0) atomicMax(&smax[c], __float_as_uint(m));
+        if (lane == 0) smax[c] = m;
     }
     __syncthreads();   // w and the maxima are complete (the workgroup's own stores)
     _Float16* hi = static_cast<_Float16*>(D.wh);
@@ -1301,7 +1313,7 @@ __global__ void __launch_bounds__(kBlock) k_prep_mma(Batch b) {
     const int groups = kc / 8;
     for (int e = threadIdx.x; e < nrhs * groups; e += blockDim.x) {
         const int c = e / groups, g = e % groups;
-        const float m = __uint_as_float(smax[c]);
+        const float m = smax[c];
         const int ex = m > 0.0f ? ilogbf(m) : 0;
         h8_t hv, lv;
 #pragma unroll
@@ -2245,7 +2257,7 @@ static void apply_t(const ApplyReq* reqs, int nops, bool f64, int normalised, in
         KernelEvents ev(cx, HDM_PHASE_PREP);
         if (mma) {
             const int64_t tot = prefix([](const Op& op, int) { return static_cast<int64_t>(op.L); });
-            hipExtLaunchKernelGGL(k_prep_mma, dim3(tot), dim3(kBlock), 0, s, ev.start, ev.stop, 0, b);
+            hipExtLaunchKernelGGL(k_prep_mma, dim3(tot), dim3(kCombBlock), 0, s, ev.start, ev.stop, 0, b);
         } else {
             const int64_t tot = prefix([](const Op& op, int) { return op.n; });
             hipExtLaunchKernelGGL((k_prep<V>), dim3(ceil_div(tot, kBlock)), dim3(kBlock), 0, s, ev.start, ev.stop, 0,
@@ -2538,7 +2550,7 @@ static void build_product_graph(Op& op, bool f64, int normalised, int nrhs, Prod
     bp.arg[0] = normalised;
     bp.pre[1] = mma ? op.L : op.n;
     G.prep = kernel(mma ? reinterpret_cast<void*>(&k_prep_mma) : reinterpret_cast<void*>(&k_prep<V>),
-                    mma ? dim3(op.L) : dim3(ceil_div(op.n, kBlock)), bp, {}, &G.prep_p);
+                    mma ? dim3(op.L) : dim3(ceil_div(op.n, kBlock)), bp, {}, &G.prep_p, mma ? kCombBlock : kBlock);
     G.prep_b = bp;
     // near field (one column: with the leaf level of the upward pass, as in the
     // eager schedule, and the rest of the tree after it)
