@@ -1954,34 +1954,41 @@ __device__ inline double exp_neg_tab(double x, const double* tab) {
 // columns in increasing order of K(row, col) w[col], K in float64 with one
 // rounding per operation (the exponent's argument d2 times 1/eps: within an ulp
 // of the oracle's d2 / eps).
+// one run of consecutive items of a leaf and row group: each lane takes two
+// rows at a time and accumulates them over every column of the run's items in
+// item order (w = nullptr: all ones); the run writes one partial-sum slot
 template <int D>
-__device__ inline void near_otf_item(const NearItem I, const int32_t* perm, const Pts& P, const double* w, double* part,
-                                     const double* tab) {
+__device__ inline void near_otf_run(const NearItem* items, const OtfRun R, const int32_t* perm, const Pts& P,
+                                    const double* w, double* part, const double* tab) {
     const int lane = threadIdx.x % kWave;
-    double xc[D];
-    load_point<D>(P, perm[I.col_pos + min(lane, I.ncols - 1)], xc);
-    const double wl = w ? w[I.col_pos + min(lane, I.ncols - 1)] : 1.0;   // w = nullptr: all ones
+    const NearItem I0 = items[R.item];
     const double ie = 1.0 / P.eps;
-    const int rend = min(I.ld, I.row0 + I.nrows);
-    for (int r0 = I.row0; r0 < rend; r0 += 2 * kWave) {
+    const int rend = min(I0.ld, I0.row0 + I0.nrows);
+    for (int r0 = I0.row0; r0 < rend; r0 += 2 * kWave) {
         const int row = r0 + 2 * lane;
         double x0[D], x1[D];
-        const bool v0 = row < I.row_n, v1 = row + 1 < I.row_n;
-        load_point<D>(P, perm[I.row_pos + min(row, I.row_n - 1)], x0);
-        load_point<D>(P, perm[I.row_pos + min(row + 1, I.row_n - 1)], x1);
+        const bool v0 = row < I0.row_n, v1 = row + 1 < I0.row_n;
+        load_point<D>(P, perm[I0.row_pos + min(row, I0.row_n - 1)], x0);
+        load_point<D>(P, perm[I0.row_pos + min(row + 1, I0.row_n - 1)], x1);
         double a0 = 0.0, a1 = 0.0;
-        for (int j = 0; j < I.ncols; ++j) {
-            double y[D];
+        for (int q = 0; q < R.count; ++q) {
+            const NearItem I = items[R.item + q];
+            double xc[D];
+            load_point<D>(P, perm[I.col_pos + min(lane, I.ncols - 1)], xc);
+            const double wl = w ? w[I.col_pos + min(lane, I.ncols - 1)] : 1.0;
+            for (int j = 0; j < I.ncols; ++j) {
+                double y[D];
 #pragma unroll
-            for (int d = 0; d < D; ++d) y[d] = lane_value(xc[d], j);
-            const double wj = lane_value(wl, j);
-            const double k0 = exp_neg_tab(-(sqd_regs<D>(x0, y) * ie), tab);   // values only
-            const double k1 = exp_neg_tab(-(sqd_regs<D>(x1, y) * ie), tab);
-            a0 = a0 + (v0 ? k0 : 0.0) * wj;
-            a1 = a1 + (v1 ? k1 : 0.0) * wj;
+                for (int d = 0; d < D; ++d) y[d] = lane_value(xc[d], j);
+                const double wj = lane_value(wl, j);
+                const double k0 = exp_neg_tab(-(sqd_regs<D>(x0, y) * ie), tab);   // values only
+                const double k1 = exp_neg_tab(-(sqd_regs<D>(x1, y) * ie), tab);
+                a0 = a0 + (v0 ? k0 : 0.0) * wj;
+                a1 = a1 + (v1 ? k1 : 0.0) * wj;
+            }
         }
         if (row < rend) {
-            double* out = part + I.part_off + row;
+            double* out = part + R.part_off + row;
             out[0] = a0;
             if (row + 1 < rend) out[1] = a1;
         }
@@ -1990,15 +1997,15 @@ __device__ inline void near_otf_item(const NearItem I, const int32_t* perm, cons
 
 
 template <int D>
-__global__ void __launch_bounds__(kBlock) k_near_otf(const NearItem* items, int64_t nitems, const int32_t* perm, Pts P,
-                                                    const double* w, double* part) {
+__global__ void __launch_bounds__(kBlock) k_near_otf(const NearItem* items, const OtfRun* runs, int64_t nruns,
+                                                    const int32_t* perm, Pts P, const double* w, double* part) {
     __shared__ double tab[64];   // 2^(j/64)
     if (threadIdx.x < 64) tab[threadIdx.x] = exp2(static_cast<double>(threadIdx.x) / 64.0);
     __syncthreads();
     const int64_t waves = static_cast<int64_t>(gridDim.x) * (blockDim.x / kWave);
-    for (int64_t u = blockIdx.x * static_cast<int64_t>(blockDim.x / kWave) + threadIdx.x / kWave; u < nitems;
+    for (int64_t u = blockIdx.x * static_cast<int64_t>(blockDim.x / kWave) + threadIdx.x / kWave; u < nruns;
          u += waves)
-        near_otf_item<D>(items[u], perm, P, w, part, tab);
+        near_otf_run<D>(items, runs[u], perm, P, w, part, tab);
 }
 
 // launches a kernel template specialised on the point dimension
@@ -2691,7 +2698,7 @@ static void build_far_tiles(Op& op, const Geo& G, hipStream_t s, DevBuf<char>& k
 }
 
 void near_field_ones(Op& op, hipStream_t s) {
-    op.part_ones.alloc(static_cast<size_t>(std::max<int64_t>(op.part_elems, 1)));
+    op.part_ones.alloc(static_cast<size_t>(std::max<int64_t>(op.part_elems_otf, 1)));
     // beside the skeletonisation: at most kOtfSideWgs workgroups per compute unit,
     // so that the ID's workgroups of the levels it overlaps find room (N = 100000:
     // 14.68 -> 14.53 ms per compression; 4 per unit: 14.73)
@@ -2710,13 +2717,13 @@ void near_field_otf(const Op& op, const double* w_tree, double* part, hipStream_
     P.dim = op.dim;
     P.is_u8 = 0;
     P.eps = op.prm.eps;
-    const int64_t ni = static_cast<int64_t>(op.items.size());
-    if (ni == 0) return;
+    const int64_t nr = static_cast<int64_t>(op.otf_runs.size());
+    if (nr == 0) return;
     const int wpb = kBlock / kWave;
-    int64_t grid = ceil_div(ni, wpb);
+    int64_t grid = ceil_div(nr, wpb);
     if (max_wgs > 0) grid = std::min<int64_t>(grid, max_wgs);
-    HDM_DIM_DISPATCH(P.dim, k_near_otf, dim3(static_cast<unsigned>(grid)), dim3(kBlock), 0, s, op.d_items.get(), ni,
-                     op.perm.get(), P, w_tree, part);
+    HDM_DIM_DISPATCH(P.dim, k_near_otf, dim3(static_cast<unsigned>(grid)), dim3(kBlock), 0, s, op.d_items.get(),
+                     op.d_otf_runs.get(), nr, op.perm.get(), P, w_tree, part);
     check_launch("near field (kernel on the fly)");
 }
 

@@ -23,6 +23,7 @@ namespace {
 constexpr int kWave = 64;
 constexpr int kBlock = 256;
 constexpr int kChunk = 64;    // columns per near-field work item
+constexpr int kOtfRunItems = 8;   // items per run of the on-the-fly float64 near field
 
 // ---- element types --------------------------------------------------------
 struct bf16_t { uint16_t v; };
@@ -1616,7 +1617,8 @@ size_t Op::footprint() const {
            far64.bytes() + farT.bytes() + far_scale.bytes() + far_colmap.bytes() + d_items.bytes() +
            d_leaves.bytes() + q.bytes() + d.bytes() + c.bytes() + w_tree.bytes() + skw.bytes() + sku.bytes() +
            part.bytes() + plan_blob.bytes() + wh.bytes() + wsc.bytes() + d_items_mma[0].bytes() + d_items_mma[1].bytes() + d_tiles_mma.bytes() +
-           d_leaves_mma[0].bytes() + d_leaves_mma[1].bytes() + d_wseg_mma[0].bytes() + d_wseg_mma[1].bytes();
+           d_leaves_mma[0].bytes() + d_leaves_mma[1].bytes() + d_wseg_mma[0].bytes() + d_wseg_mma[1].bytes() +
+           d_otf_runs.bytes() + d_leaves_otf.bytes();
 }
 
 void Lane::init(LanePool* from) {
@@ -1712,12 +1714,15 @@ static void publish_descriptors(Op& op, hipStream_t s) {
         D.near = f64 ? static_cast<const void*>(op.near64.get()) : static_cast<const void*>(op.nearT.get());
         D.nscale = (!f64 && op.near_scale.n) ? op.near_scale.get() : nullptr;
         D.leaves = D.leaves1 = op.d_leaves.get();
+        if (f64 && op.near_direct) {   // the on-the-fly near field's runs
+            D.leaves = D.leaves1 = op.d_leaves_otf.get();
+        }
         D.w = op.w_tree.get();
         D.skw = op.skw.get();
         D.sku = op.sku.get();
         D.part = op.part.get();
         D.ldsk = std::max<int64_t>(op.nskel, 1);
-        D.ldp = D.ldp1 = std::max<int64_t>(op.part_elems, 1);
+        D.ldp = D.ldp1 = std::max<int64_t>(f64 && op.near_direct ? op.part_elems_otf : op.part_elems, 1);
         D.wh = nullptr;
         D.wsc = nullptr;
         D.ldw = 0;
@@ -1948,6 +1953,19 @@ static void check_near_plan(const Op& op) {
         if (lp.rows < 1 || lp.rows > lp.ld || lp.start < 0 || lp.start + lp.rows > op.n) bad("leaf rows");
         if (lp.part_off < 0 || lp.part_off + static_cast<int64_t>(lp.nitems) * lp.ld > op.part_elems) bad("leaf partials");
     }
+    // on-the-fly runs: consecutive items of one leaf and row group, slots inside the leaf's
+    if (static_cast<int64_t>(op.leaves_otf.size()) != L) bad("on-the-fly leaf count");
+    for (const OtfRun& R : op.otf_runs) {
+        if (R.item < 0 || R.count < 1 || static_cast<int64_t>(R.item) + R.count > static_cast<int64_t>(op.items.size()))
+            bad("on-the-fly run items");
+        const NearItem& I0 = op.items[R.item];
+        const NearItem& I1 = op.items[R.item + R.count - 1];
+        if (I0.row0 != I1.row0 || I0.ld != I1.ld || I0.row_pos != I1.row_pos) bad("on-the-fly run across leaves");
+        if (R.part_off < 0 || R.part_off + I0.ld > op.part_elems_otf) bad("on-the-fly partial-sum extent");
+    }
+    for (const LeafPlan& lp : op.leaves_otf)
+        if (lp.part_off < 0 || lp.part_off + static_cast<int64_t>(lp.nitems) * lp.ld > op.part_elems_otf)
+            bad("on-the-fly leaf partials");
     if (op.packed) {
         if (static_cast<int64_t>(op.tiles_mma.size()) != pairs) bad("packed tile records");
         for (int64_t t = 0; t < pairs; ++t) {
@@ -2078,10 +2096,37 @@ void build_near_plan(Op& op, hipStream_t s) {
         op.leaves.push_back(lp);
     }
     op.part_elems = part;
+    // runs of the on-the-fly float64 near field: kOtfRunItems consecutive items of
+    // one leaf and row group (512 columns), one partial-sum slot per run
+    op.otf_runs.clear();
+    op.leaves_otf.clear();
+    int64_t opart = 0, it = 0;
+    for (int64_t a = 0; a < L; ++a) {
+        LeafPlan lp = op.leaves[a];
+        const int per_group = lp.nitems;
+        const int nrun = ceil_div(per_group, kOtfRunItems);
+        lp.part_off = opart;
+        lp.nitems = nrun;
+        lp.gstep = 1;
+        for (int g = 0; g < lp.ngroups; ++g)
+            for (int r = 0; r < nrun; ++r) {
+                OtfRun R{};
+                R.item = static_cast<int32_t>(it + static_cast<int64_t>(g) * per_group + r * kOtfRunItems);
+                R.count = std::min(kOtfRunItems, per_group - r * kOtfRunItems);
+                R.part_off = opart + static_cast<int64_t>(r) * lp.ld;
+                op.otf_runs.push_back(R);
+            }
+        it += static_cast<int64_t>(lp.ngroups) * per_group;
+        opart += static_cast<int64_t>(nrun) * lp.ld;
+        op.leaves_otf.push_back(lp);
+    }
+    op.part_elems_otf = opart;
     if (op.prm.near_prec == HDM_F16) build_mma_plan(op, s);
     check_near_plan(op);
     op.d_items = to_device(op.items, s);
     op.d_leaves = to_device(op.leaves, s);
+    op.d_otf_runs = to_device(op.otf_runs, s);
+    op.d_leaves_otf = to_device(op.leaves_otf, s);
 }
 
 // the rest of the plan, once the skeletons are known

@@ -96,6 +96,16 @@ struct NearItem {
     int32_t kend;       // matrix-core segments: end of the columns taken of the last tile
 };
 
+// float64 products of operators whose near tiles are made directly in the
+// evaluation precision evaluate the near field on the fly; each wave takes a
+// run of consecutive plain items of one leaf and row group and writes one
+// partial-sum slot for the run (fewer slots for the combine to add)
+struct OtfRun {
+    int64_t part_off;   // the run's partial-sum slot (ld rows of its leaf)
+    int32_t item;       // its first plain item
+    int32_t count;      // consecutive plain items of the same leaf and row group
+};
+
 // Per leaf: where its partial sums live and how many items feed each row group.
 struct LeafPlan {
     int64_t part_off;   // first partial of the leaf
@@ -246,6 +256,12 @@ struct Op {
     std::vector<LeafPlan> leaves;
     DevBuf<LeafPlan> d_leaves;
     int64_t part_elems = 0;
+    // runs of the on-the-fly float64 near field and their leaf plans
+    std::vector<OtfRun> otf_runs;
+    DevBuf<OtfRun> d_otf_runs;
+    std::vector<LeafPlan> leaves_otf;
+    DevBuf<LeafPlan> d_leaves_otf;
+    int64_t part_elems_otf = 0;
     int near_rows_per_group = 256;
     // half-precision near tiles are packed for the matrix cores (evaluate.hip):
     // their own tile offsets, items, leaf plans and partial-sum extent
