@@ -113,7 +113,7 @@ def serving_leg(hdm, pool, arrivals, near, far, max_slots=8):
 
 
 def serving(hdm, seconds, pool_size):
-    """Poisson 20/s, S-curve or MNIST-shaped, N log-uniform in [4096, 65536], r = 8 at
+    """The served stream: Poisson 20/s, S-curve or MNIST-shaped, N log-uniform in [4096, 65536], r = 8 at
     residual 1e-6, against mixed (bf16 near, f32 far) and plain float32 tiles on the same stream.  Where
     a path cannot keep up with the offered rate, it is replayed at 80% of its measured capacity."""
     import numpy as np
