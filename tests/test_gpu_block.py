@@ -38,6 +38,9 @@ def _case(name):
     if name == "scurve-4k-m390":   # leaves of 390/391 points, like the 100k workload's
         X, _ = synth.s_curve(3125, 13)
         return X, synth.median_sq_dist_eps(X, 13), 391, 128, 1e-5, 32, 13
+    if name == "scurve-4k-m1024":  # leaves of 1024 points: more row groups than waves per workgroup
+        X, _ = synth.s_curve(4096, 14)
+        return X, synth.median_sq_dist_eps(X, 14), 1024, 128, 1e-5, 32, 14
     raise KeyError(name)
 
 
@@ -94,7 +97,7 @@ F16_TOL = 2e-3
 
 
 @pytest.mark.parametrize("nrhs", [1, 3, 16, 20])
-@pytest.mark.parametrize("name", ["scurve-2k", "scurve-ragged-1537", "mnist-2k", "scurve-4k-m390"])
+@pytest.mark.parametrize("name", ["scurve-2k", "scurve-ragged-1537", "mnist-2k", "scurve-4k-m390", "scurve-4k-m1024"])
 def test_multi_rhs_float16_product(name, nrhs):
     X, eps, op, H = build(name, "f16", "f32")
     rng = np.random.default_rng(50 + nrhs)
